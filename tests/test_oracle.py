@@ -1,0 +1,514 @@
+"""Pins of the CPU oracle against facts that do not come from the oracle itself.
+
+Each test names what fixes the expected value: a closed form of the discrete operator (DST-I diagonalisation), an
+exactness property of the fourth-order scheme or of the quartic interpolation, a library routine (numpy dense solve,
+scipy DST), or a number printed in the paper (tests/golden/*, cited there).
+"""
+import os
+
+import numpy as np
+import pytest
+import scipy.fft
+
+import synth
+from conftest import GOLDEN
+
+RNG = np.random.default_rng(12345)
+
+
+def rand_nodes(n, rng=RNG):
+    return rng.standard_normal((n[2] + 1, n[1] + 1, n[0] + 1))
+
+
+def interior(a):
+    return a[1:-1, 1:-1, 1:-1]
+
+
+def zero_boundary(a):
+    b = np.zeros_like(a)
+    b[1:-1, 1:-1, 1:-1] = a[1:-1, 1:-1, 1:-1]
+    return b
+
+
+def symbol(n, box):
+    """Eigenvalues of M = -L_II on the sine modes, from the product form of the scheme's symbol:
+    lambda = 2a(1-cx)(4+cy+cz) + 2b(1-cy)(4+cx+cz) + 2c(1-cz)(4+cx+cy), with 1 - cos t = 2 sin^2(t/2)."""
+    (nx, ny, nz), (lx, ly, lz) = n, box
+    a, b, c = (nx / lx) ** 2, (ny / ly) ** 2, (nz / lz) ** 2
+    tx = np.arange(1, nx) * np.pi / nx
+    ty = np.arange(1, ny) * np.pi / ny
+    tz = np.arange(1, nz) * np.pi / nz
+    sx, sy, sz = 2 * np.sin(tx / 2) ** 2, 2 * np.sin(ty / 2) ** 2, 2 * np.sin(tz / 2) ** 2
+    cx, cy, cz = 1 - sx, 1 - sy, 1 - sz
+    X, Y, Z = sx[None, None, :], sy[None, :, None], sz[:, None, None]
+    CX, CY, CZ = cx[None, None, :], cy[None, :, None], cz[:, None, None]
+    return 2 * a * X * (4 + CY + CZ) + 2 * b * Y * (4 + CX + CZ) + 2 * c * Z * (4 + CX + CY)
+
+
+def dst_solve(b, n, box):
+    """Exact solution of M u = b by 3D DST-I (scipy) with the closed-form eigenvalues."""
+    lam = symbol(n, box)
+    bi = interior(b)
+    u = scipy.fft.idstn(scipy.fft.dstn(bi, type=1) / lam, type=1)
+    out = np.zeros_like(b)
+    out[1:-1, 1:-1, 1:-1] = u
+    return out
+
+
+# --------------------------------------------------------------------------------------------------------------
+# the operator
+# --------------------------------------------------------------------------------------------------------------
+
+def test_M_is_symmetric(orc):
+    n, box = (5, 4, 6), (1.0, 0.7, 1.3)
+    x, y = zero_boundary(rand_nodes(n)), zero_boundary(rand_nodes(n))
+    mx, my = orc.apply_M(x, box), orc.apply_M(y, box)
+    lhs, rhs = np.sum(mx * y), np.sum(x * my)
+    assert abs(lhs - rhs) <= 1e-13 * abs(lhs)
+
+
+@pytest.mark.parametrize("n,box", [((6, 5, 7), (1.0, 0.7, 1.3)), ((8, 4, 2), (1.0, 1.0, 1.0)),
+                                   ((5, 9, 4), (0.6, 1.9, 1.1))])
+def test_M_spectrum_matches_dst_closed_form(orc, n, box):
+    """The dense matrix of M (built column by column from the oracle) has exactly the DST-I closed-form spectrum,
+    and every sine mode is an eigenvector with its closed-form eigenvalue."""
+    nx, ny, nz = n
+    m = (nx - 1) * (ny - 1) * (nz - 1)
+    dense = np.zeros((m, m))
+    e = np.zeros((nz + 1, ny + 1, nx + 1))
+    col = 0
+    for k in range(1, nz):
+        for j in range(1, ny):
+            for i in range(1, nx):
+                e[:] = 0.0
+                e[k, j, i] = 1.0
+                dense[:, col] = interior(orc.apply_M(e, box)).ravel()
+                col += 1
+    ev = np.sort(np.linalg.eigvalsh(dense))
+    lam = symbol(n, box)
+    np.testing.assert_allclose(ev, np.sort(lam.ravel()), rtol=1e-12, atol=1e-12 * ev.max())
+    assert ev.min() > 0.0  # -L_II is positive definite
+    # eigenvectors: sine products
+    x, y, z = synth.mesh(n, (nx, ny, nz))  # integer node coordinates
+    for p, q, r in [(1, 1, 1), (2, 3, 1), (nx - 1, ny - 1, nz - 1)]:
+        s = np.sin(p * np.pi * x / nx) * np.sin(q * np.pi * y / ny) * np.sin(r * np.pi * z / nz)
+        s = zero_boundary(np.broadcast_to(s, e.shape).copy())
+        ms = orc.apply_M(s, box)
+        np.testing.assert_allclose(interior(ms), lam[r - 1, q - 1, p - 1] * interior(s), rtol=0,
+                                   atol=1e-12 * lam.max())
+
+
+def test_banded_assembly_equals_stencil(orc):
+    n, box = (7, 5, 6), (1.0, 0.5, 2.0)
+    x = rand_nodes(n)
+    np.testing.assert_allclose(orc.banded_M_apply(x, box), orc.apply_M(x, box), rtol=0, atol=1e-11 * 7 * 25)
+
+
+def test_R_symbol(orc):
+    """R applied to a sine mode gives (3 + cx + cy + cz) times the mode (DST-I, the 7-point average)."""
+    n = (8, 6, 10)
+    x, y, z = synth.mesh(n, n)
+    p, q, r = 3, 2, 5
+    s = np.sin(p * np.pi * x / n[0]) * np.sin(q * np.pi * y / n[1]) * np.sin(r * np.pi * z / n[2])
+    s = np.broadcast_to(s, (n[2] + 1, n[1] + 1, n[0] + 1)).copy()
+    rs = orc.apply_R(s)
+    fac = 3 + np.cos(p * np.pi / n[0]) + np.cos(q * np.pi / n[1]) + np.cos(r * np.pi / n[2])
+    np.testing.assert_allclose(interior(rs), fac * interior(s), atol=1e-14)
+
+
+# --------------------------------------------------------------------------------------------------------------
+# the scheme: exactness and order
+# --------------------------------------------------------------------------------------------------------------
+
+def random_poly(max_deg, total, rng):
+    coeffs = {}
+    for a in range(max_deg + 1):
+        for b in range(max_deg + 1):
+            for c in range(max_deg + 1):
+                if a + b + c <= total:
+                    coeffs[(a, b, c)] = rng.uniform(-1, 1)
+    return coeffs
+
+
+@pytest.mark.parametrize("n,box", [((6, 8, 5), (1.0, 1.3, 0.8)), ((4, 4, 4), (2.0, 1.0, 0.5))])
+def test_scheme_exact_for_quintic_polynomials(orc, n, box):
+    """The truncation error of the compact scheme is O(h^4) times sixth derivatives: degree <= 5 is reproduced."""
+    rng = np.random.default_rng(7)
+    p = synth.polynomial(random_poly(5, 5, rng), box)
+    f, g, u = synth.sample(p, n)
+    b = orc.rhs(f, g, box)
+    uh = orc.direct_solve(b, g, box)
+    assert np.max(np.abs(uh - u)) <= 1e-12 * np.max(np.abs(u))
+    # negative control: a sixth-degree term is not reproduced
+    p6 = synth.polynomial({(6, 0, 0): 1.0, (0, 2, 4): 1.0}, box)
+    f, g, u = synth.sample(p6, n)
+    uh = orc.direct_solve(orc.rhs(f, g, box), g, box)
+    assert np.max(np.abs(uh - u)) > 1e-6 * np.max(np.abs(u))
+
+
+def test_direct_solve_matches_numpy_dense(orc):
+    """DSOLVE on <= 6^3 interior points against numpy's dense solver on the same matrix."""
+    n, box = (7, 6, 5), (1.0, 0.9, 1.4)
+    nx, ny, nz = n
+    b = zero_boundary(rand_nodes(n))
+    m = (nx - 1) * (ny - 1) * (nz - 1)
+    dense = np.zeros((m, m))
+    e = np.zeros_like(b)
+    col = 0
+    for k in range(1, nz):
+        for j in range(1, ny):
+            for i in range(1, nx):
+                e[:] = 0.0
+                e[k, j, i] = 1.0
+                dense[:, col] = interior(orc.apply_M(e, box)).ravel()
+                col += 1
+    ref = np.linalg.solve(dense, interior(b).ravel())
+    u = orc.direct_solve(b, None, box)
+    np.testing.assert_allclose(interior(u).ravel(), ref, rtol=1e-12, atol=1e-13 * np.abs(ref).max())
+
+
+@pytest.mark.parametrize("box", [(1.0, 1.0, 1.0), (1.0, 0.5, 2.0)])
+def test_sine_mode_closed_form_and_order_four(orc, box):
+    """u = sin(p pi x/Lx) sin(q pi y/Ly) sin(r pi z/Lz): the discrete solution is rho * u with
+    rho = pi^2 K (3 + cx + cy + cz) / lambda (DST-I), and the error ratio per halving tends to 16."""
+    p, q, r = 1, 2, 1
+    K = (p / box[0]) ** 2 + (q / box[1]) ** 2 + (r / box[2]) ** 2
+    errs = []
+    for N in (16, 32, 64):
+        n = (N, N, N)
+        x, y, z = synth.mesh(n, box)
+        s = np.sin(p * np.pi * x / box[0]) * np.sin(q * np.pi * y / box[1]) * np.sin(r * np.pi * z / box[2])
+        s = np.broadcast_to(s, (N + 1, N + 1, N + 1)).copy()
+        f = -np.pi ** 2 * K * s
+        g = np.zeros_like(s)
+        b = orc.rhs(f, g, box)
+        uh, it, rr, _ = orc.cg(b, np.zeros_like(b), 1e-14, box)
+        cx, cy, cz = np.cos(p * np.pi / N), np.cos(q * np.pi / N), np.cos(r * np.pi / N)
+        lam = symbol(n, box)[r - 1, q - 1, p - 1]
+        rho = np.pi ** 2 * K * (3 + cx + cy + cz) / lam
+        np.testing.assert_allclose(uh, rho * s, atol=1e-12)
+        errs.append(abs(rho - 1.0))
+    assert 15.0 < errs[0] / errs[1] < 16.5
+    assert 15.7 < errs[1] / errs[2] < 16.3
+
+
+def test_cg_reaches_dst_exact_solution(orc):
+    """CG against the exact discrete solution from a 3D DST-I fast solve: the error obeys ||e||/||u*|| <= kappa*tol."""
+    n, box = (24, 20, 16), (1.0, 0.8, 0.6)
+    p = synth.smooth(0, box)
+    f, g, _ = synth.sample(p, n)
+    b = orc.rhs(f, g, box)
+    ustar = dst_solve(b, n, box)
+    tol = 1e-12
+    uh, it, rr, hist = orc.cg(b, g.copy(), tol, box)
+    lam = symbol(n, box)
+    kappa = lam.max() / lam.min()
+    err = np.linalg.norm(interior(uh) - interior(ustar)) / np.linalg.norm(interior(ustar))
+    assert rr <= 2 * tol
+    assert err <= kappa * 2 * tol
+    assert hist[-1] <= tol and hist[-2] > tol
+
+
+def test_cg_fixed_iterations_and_history(orc):
+    n, box = (12, 12, 12), (1.0, 1.0, 1.0)
+    f, g, _ = synth.sample(synth.example(1), n)
+    b = orc.rhs(f, g, box)
+    u5, it5, _, h5 = orc.cg(b, g.copy(), 0.0, box, fixed_iters=5)
+    assert it5 == 5 and len(h5) == 6
+    u_free, it, _, h = orc.cg(b, g.copy(), 1e-10, box)
+    # the first 5 iterates of the free run are the fixed run's
+    np.testing.assert_allclose(h[:6], h5, rtol=1e-12)
+    # energy-norm error is monotone in CG (a property of the method): check on the exact solution
+    ustar = dst_solve(b, n, box)
+    errs = []
+    for k in range(1, it + 1):
+        uk, _, _, _ = orc.cg(b, g.copy(), 0.0, box, fixed_iters=k)
+        e = zero_boundary(uk - ustar)
+        errs.append(np.sum(e * orc.apply_M(e, box)))
+    assert all(errs[i + 1] <= errs[i] * (1 + 1e-9) for i in range(len(errs) - 1))
+
+
+def test_cg_zero_rhs_gives_zero(orc):
+    n = (8, 8, 8)
+    b = np.zeros((9, 9, 9))
+    u, it, rr, _ = orc.cg(b, rand_nodes(n), 1e-10)
+    assert it == 0 and np.all(interior(u) == 0.0)
+
+
+# --------------------------------------------------------------------------------------------------------------
+# extrapolation and interpolation
+# --------------------------------------------------------------------------------------------------------------
+
+def test_quartic_weights_match_printed_rows(orc):
+    rows = [l.split() for l in open(os.path.join(GOLDEN, "quartic_weights.txt")) if l.strip() and l[0] != "#"]
+    for r in rows:
+        pos = float(r[0])  # in units of h0; the known values sit at 0, 1/2, 1, 3/2, 2
+        t = 2.0 * pos  # natural coordinate with the known nodes at t = 0..4
+        w = [orc.lagrange4(a, t) * 128.0 for a in range(5)]
+        np.testing.assert_allclose(w, [float(v) for v in r[1:]], atol=1e-12)
+    for t in np.linspace(0, 4, 17):
+        assert abs(sum(orc.lagrange4(a, t) for a in range(5)) - 1.0) < 1e-14
+
+
+def _triquartic(rng, box):
+    c = {}
+    for a in range(5):
+        for b in range(5):
+            for d in range(5):
+                c[(a, b, d)] = rng.uniform(-1, 1)
+    return synth.polynomial(c, box)
+
+
+def _trilinear(rng, box):
+    return synth.polynomial({(a, b, d): rng.uniform(-1, 1) for a in (0, 1) for b in (0, 1) for d in (0, 1)}, box)
+
+
+@pytest.mark.parametrize("n,box", [((16, 16, 16), (1.0, 1.0, 1.0)), ((32, 16, 8), (1.0, 1.0, 1.0)),
+                                   ((8, 24, 16), (0.7, 1.8, 1.1))])
+def test_exp_finite_exact_on_asymptotic_expansion(orc, n, box):
+    """If u^i = v + A h_i^4 with v tri-quartic and A trilinear (eq. asy without the O(h^6) term), EXP_finite
+    returns the fine solution v + A h^4 exactly: eqs. (jiedian)/(zhongdian) remove the h^4 term exactly where
+    A is linear along the averaged diagonals, and the tri-quartic interpolation reproduces v + A h^4."""
+    rng = np.random.default_rng(3)
+    v, A = _triquartic(rng, box), _trilinear(rng, box)
+
+    def field(m, h4):
+        x, y, z = synth.mesh(m, box)
+        return np.broadcast_to(v.u(x, y, z) + A.u(x, y, z) * h4, (m[2] + 1, m[1] + 1, m[0] + 1)).copy()
+
+    h = box[0] / n[0]
+    n2 = tuple(k // 2 for k in n)
+    n4 = tuple(k // 4 for k in n)
+    fine = field(n, h ** 4)
+    u2, u4 = field(n2, (2 * h) ** 4), field(n4, (4 * h) ** 4)
+    w = orc.exp_finite(u2, u4, fine)
+    assert np.max(np.abs(w - fine)) <= 1e-12 * np.max(np.abs(fine))
+    # a plain injection-plus-interpolation (no extrapolation) is off by O(h^4): the pin would catch a lost term
+    w0 = orc.exp_finite(u2, u2[::2, ::2, ::2].copy(), fine)  # delta = 0: no Richardson correction
+    assert np.max(np.abs(w0 - fine)) > 1e-3 * np.max(np.abs(A.u(*synth.mesh(n, box)))) * h ** 4
+
+
+def test_exp_finite_reproduces_triquartic(orc):
+    """With u_2h = u_4h (so every delta is 0) w is the tri-quartic interpolant of u_2h: exact for tri-quartic v."""
+    rng = np.random.default_rng(5)
+    box = (1.0, 1.0, 1.0)
+    v = _triquartic(rng, box)
+    n = (16, 8, 24)
+    _, _, fine = synth.sample(v, n)
+    _, _, u2 = synth.sample(v, tuple(k // 2 for k in n))
+    u4 = u2[::2, ::2, ::2].copy()
+    w = orc.exp_finite(u2, u4, fine)
+    assert np.max(np.abs(w - fine)) <= 1e-12 * np.max(np.abs(fine))
+    # a quintic term is not reproduced (negative control on the interpolation degree)
+    q = synth.polynomial({(5, 0, 0): 1.0}, box)
+    _, _, fine = synth.sample(q, n)
+    _, _, u2 = synth.sample(q, tuple(k // 2 for k in n))
+    w = orc.exp_finite(u2, u2[::2, ::2, ::2].copy(), fine)
+    assert np.max(np.abs(w - fine)) > 1e-8
+
+
+@pytest.mark.parametrize("n", [(16, 16, 16), (8, 12, 6)])
+def test_exp_true_exact_on_asymptotic_expansion(orc, n):
+    """u_h = v + A h^4 and u_2h = v + A (2h)^4 with A trilinear: eqs. (t1)/(chenlin) return v exactly, for any v."""
+    rng = np.random.default_rng(11)
+    box = (1.0, 1.0, 1.0)
+    A = _trilinear(rng, box)
+    h = 1.0 / n[0]
+    x, y, z = synth.mesh(n, box)
+    shape = (n[2] + 1, n[1] + 1, n[0] + 1)
+    v = np.broadcast_to(np.sin(3 * x + y) * np.exp(z) + x * y * z, shape).copy()
+    uh = v + np.broadcast_to(A.u(x, y, z), shape) * h ** 4
+    n2 = tuple(k // 2 for k in n)
+    x2, y2, z2 = synth.mesh(n2, box)
+    v2 = v[::2, ::2, ::2]
+    u2 = v2 + np.broadcast_to(A.u(x2, y2, z2), v2.shape) * (2 * h) ** 4
+    ut = orc.exp_true(uh, u2.copy())
+    assert np.max(np.abs(ut - v)) <= 1e-13
+
+
+def test_exp_shape_errors(orc):
+    a = np.zeros((13, 13, 13))
+    with pytest.raises(orc.OracleError):
+        orc.exp_finite(np.zeros((7, 7, 7)), np.zeros((4, 4, 4)), a)  # 12 is not a multiple of 8
+
+
+# --------------------------------------------------------------------------------------------------------------
+# gradient
+# --------------------------------------------------------------------------------------------------------------
+
+def test_gradient_exact_for_quartics(orc):
+    rng = np.random.default_rng(9)
+    box = (1.0, 0.6, 1.7)
+    p = synth.polynomial(random_poly(4, 4, rng), box)
+    n = (9, 6, 11)
+    _, _, u = synth.sample(p, n)
+    got = orc.gradient(u, box)
+    ref = synth.exact_gradient(p, n)
+    for g_, r_ in zip(got, ref):
+        assert np.max(np.abs(g_ - r_)) <= 1e-11 * max(1.0, np.max(np.abs(r_)))
+
+
+def test_gradient_order_four(orc):
+    p = synth.example(2)
+    e = []
+    for N in (8, 16, 32):
+        _, _, u = synth.sample(p, (N, N, N))
+        got = orc.gradient(u)
+        ref = synth.exact_gradient(p, (N, N, N))
+        e.append(max(np.max(np.abs(a - b)) for a, b in zip(got, ref)))
+    assert 3.7 < np.log2(e[1] / e[2]) < 4.3
+
+
+# --------------------------------------------------------------------------------------------------------------
+# the whole cascade against the paper's printed numbers
+# --------------------------------------------------------------------------------------------------------------
+
+def _table_rows():
+    rows = []
+    for line in open(os.path.join(GOLDEN, "paper_tables.txt")):
+        if not line.strip() or line.startswith("#"):
+            continue
+        ex, mesh, tol, norm, qty, val = line.split()
+        limited = val.endswith("*")
+        rows.append((int(ex), tuple(int(v) for v in mesh.split(",")), float(tol), norm, qty,
+                     float(val.rstrip("*")), limited))
+    return rows
+
+
+_CACHE = {}
+
+
+def _run(orc, ex, n, tol):
+    key = (ex, n, tol)
+    if key not in _CACHE:
+        p = synth.example(ex)
+        f, g, u = synth.sample(p, n)
+        nc = (8, 4, 2) if ex == 4 else (4, 4, 4)
+        r = orc.excmg(f, g, p.box, nc, tol, want_ext=True, want_w=True)
+        grad = orc.gradient(r["u"], p.box)
+        gex = synth.exact_gradient(p, n)
+        rms = lambda e: float(np.sqrt(np.mean(e * e)))
+        out = {
+            ("inf", "u"): np.max(np.abs(r["u"] - u)),
+            ("inf", "grad"): max(np.max(np.abs(a - b)) for a, b in zip(grad, gex)),
+            ("inf", "ext"): np.max(np.abs(r["ut"] - u)),
+            ("inf", "w"): np.max(np.abs(r["w"] - r["u"])),
+            ("l2", "u"): rms(r["u"] - u),
+            ("l2", "grad"): float(np.sqrt(sum(rms(a - b) ** 2 for a, b in zip(grad, gex)))),
+            ("l2", "ext"): rms(r["ut"] - u),
+            ("l2", "w"): rms(r["w"] - r["u"]),
+        }
+        _CACHE[key] = out
+    return _CACHE[key]
+
+
+@pytest.mark.parametrize("row", _table_rows(), ids=lambda r: f"ex{r[0]}-{'x'.join(map(str, r[1]))}-{r[3]}-{r[4]}")
+def test_paper_tables(orc, row):
+    """Printed errors of Tables 1-12 (three significant digits).  Max-norm columns are pinned to 2% (u, grad)
+    and 6% (ext, w); L2 columns of u, grad, ext to 2% with the L2 norm read as the RMS over all nodes; the paper's
+    L2 column of w_h - u_h follows no convention found (it is reported, not pinned, see the design notes)."""
+    ex, n, tol, norm, qty, val, limited = row
+    got = _run(orc, ex, n, tol)[(norm, qty)]
+    if limited:
+        pytest.skip("entry limited by the uniform CG tolerance (paper's own remark)")
+    if norm == "l2" and qty == "w":
+        assert 0.7 * val < got < 1.3 * val
+        return
+    rel = 0.02 if qty in ("u", "grad") else 0.06
+    assert abs(got - val) <= rel * val, (got, val)
+
+
+def test_paper_iteration_count_256(orc):
+    """Table 13: Example 1 with eps = 1e-14 needs 8 CG iterations on the finest 256^3 grid."""
+    p = synth.example(1)
+    f, g, u = synth.sample(p, (256, 256, 256))
+    r = orc.excmg(f, g, p.box, (4, 4, 4), 1e-14)
+    assert r["iters"][-1] == 8
+    assert np.max(np.abs(r["u"] - u)) < 2e-12
+
+
+def test_orders_on_smooth_workload(orc):
+    """Seeded smooth field: u_h fourth order, u~_h sixth order, w_h - u_h fifth order (the paper's claims, L2)."""
+    p = synth.smooth(0)
+    res = {}
+    for N in (16, 32, 64):
+        f, g, u = synth.sample(p, (N, N, N))
+        r = orc.excmg(f, g, p.box, (4, 4, 4), 1e-13, want_ext=True, want_w=True)
+        res[N] = (np.sqrt(np.mean((r["u"] - u) ** 2)), np.sqrt(np.mean((r["ut"] - u) ** 2)),
+                  np.sqrt(np.mean((r["w"] - r["u"]) ** 2)))
+    o = [np.log2(res[32][i] / res[64][i]) for i in range(3)]
+    assert 3.8 < o[0] < 4.2
+    assert 5.5 < o[1] < 6.5
+    assert 4.6 < o[2] < 5.4
+
+
+def test_cascade_argument_errors(orc):
+    f = np.zeros((17, 17, 17))
+    f12 = np.zeros((13, 13, 13))
+    with pytest.raises(orc.OracleError) as e:
+        orc.excmg(f12, f12, (1, 1, 1), (3, 3, 3), 1e-10)  # odd coarsest counts cannot feed EXP_finite
+    assert e.value.code == orc.ERR_SHAPE
+    with pytest.raises(ValueError):
+        orc.levels_for((16, 16, 16), (3, 3, 3))
+    with pytest.raises(orc.OracleError):
+        orc.excmg(f, f, (1, 1, 1), (4, 4, 4), -1.0)
+
+
+def test_single_and_two_level_cascades_are_direct(orc):
+    p = synth.example(1)
+    f, g, u = synth.sample(p, (8, 8, 8))
+    r1 = orc.excmg(f, g, p.box, (8, 8, 8), 1e-10)
+    r2 = orc.excmg(f, g, p.box, (4, 4, 4), 1e-10, want_ext=True)
+    ref = orc.direct_solve(orc.rhs(f, g), g)
+    np.testing.assert_allclose(r1["u"], ref, atol=1e-14)
+    np.testing.assert_allclose(r2["u"], ref, atol=1e-14)
+    assert list(r2["iters"]) == [0, 0]
+
+
+# --------------------------------------------------------------------------------------------------------------
+# adjoint
+# --------------------------------------------------------------------------------------------------------------
+
+def test_transposes_dot_product(orc):
+    n, box = (6, 5, 7), (1.0, 0.8, 1.5)
+    rng = np.random.default_rng(1)
+    x, y = rand_nodes(n, rng), zero_boundary(rand_nodes(n, rng))
+    # <R x, y> = <x, R^T y>
+    assert np.isclose(np.sum(orc.apply_R(x, box) * y), np.sum(x * orc.apply_RT(y)), rtol=1e-13)
+    # <L_IB g, y> = <g_B, L_IB^T y>: L_IB g is L applied to g restricted to the boundary
+    gb = np.where(synth.boundary_mask(n), x, 0.0)
+    lhs = np.sum(orc.apply_L(gb, box) * y)
+    rhs = np.sum(gb * orc.apply_LIBT(y, box))
+    assert np.isclose(lhs, rhs, rtol=1e-13)
+    assert np.all(orc.apply_LIBT(y, box)[~synth.boundary_mask(n)] == 0.0)
+
+
+def _loss_exact(orc, f, g, ut, box):
+    """L = ||u - u_t||^2 / 2 over all nodes, u the exact discrete solution (direct solve)."""
+    u = orc.direct_solve(orc.rhs(f, g, box), g, box)
+    u = np.where(synth.boundary_mask(_n(f)), g, u)
+    return 0.5 * np.sum((u - ut) ** 2), u
+
+
+def _n(a):
+    return (a.shape[2] - 1, a.shape[1] - 1, a.shape[0] - 1)
+
+
+def test_adjoint_against_central_differences(orc):
+    """L is quadratic in (f, g), so the central difference along any direction equals <grad L, d> to rounding."""
+    box = (1.0, 0.9, 1.2)
+    n = (8, 8, 8)
+    p = synth.smooth(0, box)
+    f, g, _ = synth.sample(p, n)
+    _, _, ut = synth.sample(synth.smooth(5, box), n)
+    L0, u = _loss_exact(orc, f, g, ut, box)
+    G = u - ut
+    adj = orc.adjoint(G, box, (2, 2, 2), 1e-15)
+    for seed in range(3):
+        df, dg = synth.direction(100 + seed, n)
+        eps = 1e-3
+        Lp, _ = _loss_exact(orc, f + eps * df, g + eps * dg, ut, box)
+        Lm, _ = _loss_exact(orc, f - eps * df, g - eps * dg, ut, box)
+        fd = (Lp - Lm) / (2 * eps)
+        an = np.sum(adj["dLdf"] * df) + np.sum(adj["dLdg"] * dg)
+        assert abs(fd - an) <= 1e-8 * max(abs(fd), 1e-12)
