@@ -1,0 +1,181 @@
+#!/usr/bin/env python
+"""EXCMG benchmark on one MI355X.
+
+A step is one pass of the whole path on the 512^3-cell workload (8 grids from 4^3, CG tolerance 1e-10, FP64, seeded
+smooth field u = sum_k a_k sin sin sin + exp(x+y+z)/10): level data, direct solves on the two coarsest grids,
+EXP_finite + tri-quartic initial guesses, the fused stencil-CG relaxation on every grid, the sixth-order EXP_true
+extrapolation and the compact gradient.  Inputs f and g are resident in HBM before the timed region.
+
+value = sum over grids of (interior unknowns x CG iterations) / step time, in G unknown-iterations/s.
+
+Also reported: the FP32-in-FP64 iterative-refinement solve of the same workload (time, error vs the FP64 result),
+the roofline of the dominant CG sweep (HIP events around every launch in the timed steps), and the CPU oracle timed on
+a bounded sample of the same workload on this host.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "stencil-CG Gunknown-iters/s (%HBM peak); EXCMG solve time 512³ FP64 vs mixed"
+HBM_PEAK_GBS = 8000.0
+# algorithmic bytes per interior unknown of one launch (FP64; halve for FP32)
+BYTES_PER_UNKNOWN = {"cg_a": 24, "cg_b": 40, "cg_a32": 12, "cg_b32": 20}
+
+
+def unknown_iters(st):
+    tot = 0
+    for (nx, ny, nz), it in zip(st["n"], st["iters"]):
+        tot += (nx - 1) * (ny - 1) * (nz - 1) * it
+    return tot
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=512, help="cells per axis of the finest grid")
+    ap.add_argument("--tol", type=float, default=1e-10)
+    ap.add_argument("--cpu-n", type=int, default=256, help="cells per axis of the oracle's timed sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU z-slab form of this "
+              "solver is a design, not a build", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_1507_05063_amd as ex
+    import synth
+
+    torch.cuda.set_device(0)
+    N = args.n
+    n = (N, N, N)
+    p = synth.smooth(0)
+    f_np, g_np, u_exact = synth.sample(p, n)
+    f = torch.from_numpy(f_np).cuda()
+    g = torch.from_numpy(g_np).cuda()
+    print(f"# workload {N}^3 cells, inputs resident: {f.numel() * 16 / 1e9:.2f} GB", file=sys.stderr, flush=True)
+
+    s = ex.Solver(n, p.box, args.tol, timing=True)
+    u = s.empty()
+    ue = s.empty()
+    grads = (s.empty(), s.empty(), s.empty())
+
+    def one():
+        uu, uext, st = s.solve(f, g, u=u, want_ext=True)
+        s.gradient(uu, out=grads)
+        return st, uext
+
+    for _ in range(args.warmup):
+        one()
+    torch.cuda.synchronize()
+    stats = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        st, _ = one()
+        stats.append(st)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ms_step = dt * 1e3 / args.steps
+    ui = unknown_iters(stats[-1])
+    value = ui / (ms_step * 1e-3) / 1e9
+    print(f"# fp64 step {ms_step:.2f} ms, iters {stats[-1]['iters']}", file=sys.stderr, flush=True)
+
+    # roofline of the dominant finest-grid CG sweep, from the HIP events of the timed steps
+    tot = {k: sum(st["kernel_ms_finest"][k] for st in stats) for k in ("cg_a", "cg_b")}
+    calls = {k: sum(st["kernel_calls_finest"][k] for st in stats) for k in ("cg_a", "cg_b")}
+    dom = max(tot, key=lambda k: tot[k])
+    nI = (N - 1) ** 3
+    avg_ms = tot[dom] / max(calls[dom], 1)
+    achieved = BYTES_PER_UNKNOWN[dom] * nI / (avg_ms * 1e-3) / 1e9
+    # stencil-CG sweeps of the finest grid alone: unknown-iterations per second of pass A + pass B kernel time
+    fin_iters = stats[-1]["iters"][-1]
+    cg_ms_fin = sum(st["kernel_ms_finest"]["cg_a"] + st["kernel_ms_finest"]["cg_b"] +
+                    st["kernel_ms_finest"]["finalize"] for st in stats) / args.steps
+    guis_fin_sweeps = nI * fin_iters / (cg_ms_fin * 1e-3) / 1e9 if cg_ms_fin > 0 else None
+
+    u_np = u.cpu().numpy()
+    err_fp64 = float(np.max(np.abs(u_np - u_exact)))
+
+    out = {
+        "metric": METRIC,
+        "value": round(value, 3),
+        "unit": "Gunknown-iters/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"EXCMG {N}^3 cells FP64, 8 grids from 4^3, tol {args.tol:g}, seeded smooth field "
+                               "(seed 0), incl. EXP_true and compact gradient",
+                   "cells": list(n), "levels": stats[-1]["levels"], "tol": args.tol},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "avg_launch_ms": round(avg_ms, 4), "bytes_per_launch": BYTES_PER_UNKNOWN[dom] * nI},
+        "iters_per_grid": stats[-1]["iters"],
+        "ms_per_grid": [round(v, 3) for v in stats[-1]["ms_level"]],
+        "solve_ms_fp64": round(stats[-1]["ms_total"], 3),
+        "finest_cg_sweeps_gunknown_iters_s": round(guis_fin_sweeps, 2) if guis_fin_sweeps else None,
+        "max_error_vs_exact_fp64": err_fp64,
+    }
+
+    if not args.no_mixed:
+        sm = ex.Solver(n, p.box, args.tol, precision=ex.FP32_IR, timing=False)
+        um = sm.empty()
+        for _ in range(max(1, args.warmup)):
+            sm.solve(f, g, u=um)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            _, _, stm = sm.solve(f, g, u=um)
+        torch.cuda.synchronize()
+        ms_m = (time.perf_counter() - t0) * 1e3 / args.steps
+        um_np = um.cpu().numpy()
+        out["mixed"] = {
+            "solve_ms": round(ms_m, 3),
+            "inner_iters_per_grid": stm["iters"],
+            "ms_per_grid": [round(v, 3) for v in stm["ms_level"]],
+            "outer_steps_per_grid": stm["ir_outer"],
+            "max_error_vs_exact": float(np.max(np.abs(um_np - u_exact))),
+            "rel_l2_vs_fp64_solution": float(np.linalg.norm(um_np - u_np) / np.linalg.norm(u_np)),
+            "speedup_vs_fp64_solve": round(stats[-1]["ms_total"] / ms_m, 3),
+        }
+        del sm
+        print(f"# mixed solve {ms_m:.2f} ms", file=sys.stderr, flush=True)
+
+    if not args.no_cpu_baseline:
+        import oracle
+
+        threads = max(1, min(len(os.sched_getaffinity(0)), 64))
+        oracle.set_threads(threads)
+        Nc = args.cpu_n
+        fc, gc, _ = synth.sample(p, (Nc, Nc, Nc))
+        t0 = time.perf_counter()
+        r = oracle.excmg(fc, gc, p.box, (4, 4, 4), args.tol)
+        secs = time.perf_counter() - t0
+        ui_c = sum((Nc // 2 ** (len(r["iters"]) - 1 - l) - 1) ** 3 * int(it) for l, it in enumerate(r["iters"]))
+        out["cpu_baseline"] = {"value": round(ui_c / secs / 1e9, 4), "unit": "Gunknown-iters/s",
+                               "cores": oracle.get_threads(), "kind": "oracle",
+                               "sample": f"one oracle EXCMG solve of the same seeded field at {Nc}^3 cells "
+                                         f"({len(r['iters'])} grids, tol {args.tol:g}), {secs:.1f} s wall"}
+        print(f"# oracle {Nc}^3: {secs:.1f} s on {oracle.get_threads()} threads", file=sys.stderr, flush=True)
+
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

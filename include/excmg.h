@@ -1,0 +1,171 @@
+/*
+ * excmg.h -- C ABI of the MI355X (gfx950) EXCMG solver for the 3D Dirichlet Poisson problem
+ *
+ *     u_xx + u_yy + u_zz = f in the box [0,Lx]x[0,Ly]x[0,Lz],   u = g on its boundary
+ *
+ * (Pan, He & Hu, arXiv 1507.05063: problem statement eq. (bvp), Section 1; grid and unequal meshsizes,
+ * Section 2), discretised by the 19-point fourth-order compact scheme (eq. compact) and solved by the
+ * extrapolation cascadic multigrid method of Algorithm 1: direct solves on the two coarsest grids, then on every
+ * finer grid an initial guess from Richardson extrapolation plus tri-quartic Lagrange interpolation of the two
+ * previous solutions (Sections 4.2-4.3), relaxed by conjugate gradients until the relative residual
+ * ||A_h u_h - f_h||_2 <= tol ||f_h||_2 (Algorithm 1, loop over the levels).
+ *
+ * Conventions for every entry point
+ *   - Node arrays: (Nz+1)*(Ny+1)*(Nx+1) contiguous doubles, x fastest: node (i,j,k) is at ((k*(Ny+1))+j)*(Nx+1)+i,
+ *     coordinates (i*hx, j*hy, k*hz), hx = Lx/Nx (Section 2).  All array arguments are DEVICE pointers to memory on
+ *     the device that was current at excmg_setup, unless a comment says "host".
+ *   - Ownership: the caller owns every array and the workspace; the library allocates no device memory.  The handle
+ *     owns only host-side state; excmg_destroy frees it.
+ *   - Streams: all device work is enqueued on the stream given at setup.  Calls that report iteration counts wait
+ *     for their own work on that stream before returning; their outputs are complete when they return.
+ *   - Errors: every int-returning call returns EXCMG_OK (0) or a negative EXCMG_ERR_* code; excmg_strerror names it.
+ *     No exception crosses the ABI.  On EXCMG_ERR_NOCONV the outputs hold the last iterate and the stats are filled.
+ *   - Calls on one handle must not overlap (one stream, one workspace).  Different handles are independent.
+ */
+#ifndef EXCMG_H
+#define EXCMG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define EXCMG_OK 0
+#define EXCMG_ERR_ARG (-1)       /* null pointer, non-positive box edge or tolerance, bad precision or flags */
+#define EXCMG_ERR_SHAPE (-2)     /* cell counts are not n_coarse * 2^L, odd coarsest counts, too many levels,
+                                    fewer than 4 cells on an axis for the gradient */
+#define EXCMG_ERR_NONFINITE (-3) /* f or g holds a NaN or an infinity */
+#define EXCMG_ERR_NOCONV (-4)    /* a level reached max_iters before the tolerance */
+#define EXCMG_ERR_BREAKDOWN (-5) /* CG met p.Ap <= 0 or a non-finite scalar */
+#define EXCMG_ERR_HIP (-6)       /* a HIP runtime call failed */
+#define EXCMG_ERR_WORKSPACE (-7) /* workspace null, too small or misaligned (256-byte alignment required) */
+
+#define EXCMG_FP64 0    /* CG in FP64 */
+#define EXCMG_FP32_IR 1 /* CG sweeps in FP32 inside FP64 iterative refinement on every grid with at least 2^20
+                           interior unknowns (smaller grids are latency-bound and relax in FP64) */
+
+#define EXCMG_WANT_HISTORY 1u /* record the finest level's relative-residual history (stats.history) */
+#define EXCMG_WANT_TIMING 2u  /* time every kernel class with HIP events (stats.kernel_ms, kernel_calls) */
+
+#define EXCMG_MAX_LEVELS 16
+#define EXCMG_MAX_HISTORY 256
+
+/* Kernel classes reported by EXCMG_WANT_TIMING. */
+#define EXCMG_K_CG_A 0      /* p = r + beta p; partial sums of p.Mp                          (FP64) */
+#define EXCMG_K_CG_B 1      /* u += alpha p; r -= alpha Mp; partial sums of r.r              (FP64) */
+#define EXCMG_K_CG_A32 2    /* the same two passes in FP32 (inner solves of EXCMG_FP32_IR) */
+#define EXCMG_K_CG_B32 3
+#define EXCMG_K_RESID 4     /* r = b - M u (+ cast for the FP32 inner solve), partial sums */
+#define EXCMG_K_FINALIZE 5  /* fixed-order reduction of block partials, CG scalars */
+#define EXCMG_K_RHS 6       /* right-hand side assembly per level */
+#define EXCMG_K_EXP_FINITE 7
+#define EXCMG_K_EXP_TRUE 8
+#define EXCMG_K_DSOLVE 9
+#define EXCMG_K_GRADIENT 10
+#define EXCMG_K_OTHER 11
+#define EXCMG_K_CLASSES 12
+
+typedef struct excmg_handle excmg_handle;
+
+/* Problem description (paper, Section 2 and Algorithm 1). */
+typedef struct {
+  double box[3];        /* Lx, Ly, Lz > 0 */
+  int32_t n[3];         /* Nx, Ny, Nz: cells per axis on the finest grid */
+  int32_t n_coarse[3];  /* cells per axis on the coarsest grid H; {0,0,0} = automatic: halve the finest counts
+                           while the halves are all even and >= 2 and the largest half is >= 4 */
+  double tol;           /* relative-residual tolerance epsilon of Algorithm 1, on every level, > 0 */
+  int32_t precision;    /* EXCMG_FP64 or EXCMG_FP32_IR */
+  double inner_tol;     /* FP32_IR: largest residual reduction asked of one inner FP32 solve (0 = 1e-5); an inner
+                           solve also stops once its residual is half the outer target tol*||f_h|| */
+  int32_t max_iters;    /* CG iterations allowed per level (FP32_IR: inner iterations per outer step); 0 = 10000 */
+  uint32_t flags;       /* EXCMG_WANT_* */
+} excmg_problem;
+
+/* Statistics of one call (host struct, filled by the library). */
+typedef struct {
+  int32_t levels;                            /* number of grids, coarsest first */
+  int32_t n[EXCMG_MAX_LEVELS][3];            /* cells per axis of each grid */
+  int32_t iters[EXCMG_MAX_LEVELS];           /* CG iterations per grid (FP32_IR: inner iterations summed);
+                                                0 on the two directly solved grids */
+  int32_t ir_outer[EXCMG_MAX_LEVELS];        /* FP32_IR: outer refinement steps per grid */
+  int32_t dsolve_iters[2];                   /* iterations the direct solver took on the two coarsest grids */
+  double relres[EXCMG_MAX_LEVELS];           /* relative residual at exit per grid (FP64: recursive CG residual;
+                                                FP32_IR: the FP64 outer residual) */
+  double ms_level[EXCMG_MAX_LEVELS];         /* wall time of each grid's work (transfer + relaxation), ms */
+  double ms_total;                           /* wall time of the call, ms */
+  double kernel_ms[EXCMG_K_CLASSES];         /* EXCMG_WANT_TIMING: summed kernel time per class, ms (CG launches
+                                                made after a grid converged are not counted) */
+  int32_t kernel_calls[EXCMG_K_CLASSES];     /* EXCMG_WANT_TIMING: launches per class */
+  double kernel_ms_finest[EXCMG_K_CLASSES];  /* the same, finest grid only */
+  int32_t kernel_calls_finest[EXCMG_K_CLASSES];
+  int32_t history_len;                       /* EXCMG_WANT_HISTORY: entries in history */
+  double history[EXCMG_MAX_HISTORY];         /* finest grid: relative residual before iteration 1, after 1, ... */
+} excmg_stats;
+
+/* Host only.  Bytes of device workspace excmg_setup needs for this problem. */
+int excmg_workspace_bytes(const excmg_problem *p, size_t *bytes);
+
+/* Host only.  The level plan: *levels grids, the coarsest with n_coarse_out[3] cells (rule of n_coarse). */
+int excmg_plan(const excmg_problem *p, int32_t *levels, int32_t n_coarse_out[3]);
+
+/* Bind a problem to a workspace (device memory of at least excmg_workspace_bytes, 256-byte aligned, owned by the
+ * caller and not touched by anything else while the handle lives) and a HIP stream (hipStream_t, may be NULL for
+ * the null stream).  Allocates only the host-side handle. */
+int excmg_setup(const excmg_problem *p, void *workspace, size_t bytes, void *hip_stream, excmg_handle **h);
+
+/* Algorithm 1.  f: node array (every node is read); g: node array (only boundary nodes are read).
+ * u (out): node array, the finest-grid solution with its boundary equal to g.
+ * u_ext (out, nullable): EXP_true(u_h, u_2h), the sixth-order extrapolated solution on the finest grid
+ * (Algorithm 1, optional step; Sections 4.2.1 and 4.3); needs at least two grids.
+ * stats (host, nullable). */
+int excmg_solve(excmg_handle *h, const double *f, const double *g, double *u, double *u_ext, excmg_stats *stats);
+
+/* Fourth-order compact gradient of a finest-grid node array u (Section 5.1): one-sided fourth-order formulas at both
+ * ends of every grid line, tridiagonal (1,4,1)/6 systems inside solved by the Thomas algorithm.  ux, uy, uz (out):
+ * node arrays.  Needs at least 4 cells per axis. */
+int excmg_gradient(excmg_handle *h, const double *u, double *ux, double *uy, double *uz);
+
+/* Adjoint of the discrete solution map (f, g) -> u (interior: the compact-scheme solution; boundary: g) for an
+ * upstream gradient G = dL/du (node array).  Solves M lambda = G_I (M = -A_h restricted to the interior, the same
+ * symmetric operator) by the same cascade with the level data taken from G, then
+ *   dLdf = -R^T lambda on every node (R f = (6 f_c + sum of the 6 face neighbours)/2, eq. compact),
+ *   dLdg = A_IB^T lambda + G on boundary nodes, 0 inside.
+ * lambda_out (nullable): lambda as a node array with zero boundary.  Uses the handle's tolerance and precision. */
+int excmg_adjoint(excmg_handle *h, const double *G, double *dLdf, double *dLdg, double *lambda_out,
+                  excmg_stats *stats);
+
+/* Many independent problems at once: handles hs[0..count-1] (each with its own workspace; all on the stream of
+ * hs[0]), problem b reads f[b], g[b] and writes u[b] (node arrays of its own shape).  Every problem must use
+ * EXCMG_FP32_IR or every problem EXCMG_FP64.  The relaxation of all problems on the same cascade level runs in
+ * shared persistent launches.  stats (host, nullable): count entries.  ms_per_problem (host, nullable): count
+ * entries, the time from the batch's start until problem b's last grid converged (device timestamps). */
+int excmg_solve_batched(excmg_handle *const *hs, int32_t count, const double *const *f, const double *const *g,
+                        double *const *u, excmg_stats *stats, double *ms_per_problem);
+
+void excmg_destroy(excmg_handle *h);
+const char *excmg_strerror(int code);
+
+/* ---- single steps of the path, on one grid of cells n = (Nx,Ny,Nz) and box (node arrays as above) ---- */
+
+/* y = M x with M = -A_h on the interior (eq. compact, left-hand side, negated; boundary entries of x are read as 0);
+ * y is 0 on boundary nodes. */
+int excmg_op_apply(const int32_t n[3], const double box[3], const double *x, double *y, void *hip_stream);
+
+/* b = -R f + A_IB g on interior nodes (eq. compact with the Dirichlet values moved to the right), 0 on boundary. */
+int excmg_op_rhs(const int32_t n[3], const double box[3], const double *f, const double *g, double *b,
+                 void *hip_stream);
+
+/* EXP_finite(u_2h, u_4h) (Sections 4.2.2 and 4.3): w on the grid n (multiples of 8) from u2h (n/2) and u4h (n/4);
+ * boundary nodes of w are g. */
+int excmg_op_exp_finite(const int32_t n[3], const double *u2h, const double *u4h, const double *g, double *w,
+                        void *hip_stream);
+
+/* EXP_true(u_h, u_2h) (eqs. t1, chenlin; Section 4.3) on the grid n (even counts). */
+int excmg_op_exp_true(const int32_t n[3], const double *uh, const double *u2h, double *ut, void *hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,202 @@
+"""MI355X-native EXCMG solver for the 3D Dirichlet Poisson problem with the 19-point fourth-order compact scheme
+(Pan, He & Hu, arXiv 1507.05063).
+
+Thin Python binding over the C ABI (include/excmg.h): arguments are marshalled to device pointers of torch CUDA
+tensors (float64 node arrays of shape (Nz+1, Ny+1, Nx+1), x fastest) and the current torch stream.  Every step of
+the solver runs in the HIP library; nothing here computes.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Optional, Sequence
+
+from . import _lib
+from ._lib import ExcmgError, FP32_IR, FP64, K_CLASSES, LIB_PATH, WANT_HISTORY, WANT_TIMING
+
+__all__ = ["Solver", "ExcmgError", "FP64", "FP32_IR", "plan", "workspace_bytes", "op_apply", "op_rhs",
+           "op_exp_finite", "op_exp_true", "solve_batched", "K_CLASSES", "LIB_PATH"]
+
+
+def _torch():
+    import torch
+
+    return torch
+
+
+def _problem(n, box, tol, n_coarse=(0, 0, 0), precision=FP64, inner_tol=0.0, max_iters=0, flags=0):
+    p = _lib.Problem()
+    for d in range(3):
+        p.box[d] = float(box[d])
+        p.n[d] = int(n[d])
+        p.n_coarse[d] = int(n_coarse[d])
+    p.tol = float(tol)
+    p.precision = int(precision)
+    p.inner_tol = float(inner_tol)
+    p.max_iters = int(max_iters)
+    p.flags = int(flags)
+    return p
+
+
+def plan(n, n_coarse=(0, 0, 0), box=(1.0, 1.0, 1.0), tol=1e-10):
+    """(levels, n_coarse) that the solver will use (host only)."""
+    p = _problem(n, box, tol, n_coarse)
+    L = ctypes.c_int32(0)
+    nc = (ctypes.c_int32 * 3)()
+    _lib.check(_lib.lib().excmg_plan(ctypes.byref(p), ctypes.byref(L), nc), "excmg_plan")
+    return L.value, tuple(nc)
+
+
+def workspace_bytes(n, n_coarse=(0, 0, 0), box=(1.0, 1.0, 1.0), tol=1e-10, precision=FP64) -> int:
+    p = _problem(n, box, tol, n_coarse, precision)
+    b = ctypes.c_size_t(0)
+    _lib.check(_lib.lib().excmg_workspace_bytes(ctypes.byref(p), ctypes.byref(b)), "excmg_workspace_bytes")
+    return int(b.value)
+
+
+def _stream_ptr(stream=None):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _check_nodes(t, n, name):
+    torch = _torch()
+    shape = (int(n[2]) + 1, int(n[1]) + 1, int(n[0]) + 1)
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.float64 or not t.is_cuda:
+        raise TypeError(f"{name}: expected a float64 CUDA tensor")
+    if tuple(t.shape) != shape:
+        raise ValueError(f"{name}: expected shape {shape}, got {tuple(t.shape)}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name}: must be contiguous")
+
+
+class Solver:
+    """A problem bound to its device workspace and a stream: ``solve``, ``gradient`` and ``adjoint``."""
+
+    def __init__(self, n: Sequence[int], box=(1.0, 1.0, 1.0), tol: float = 1e-10, n_coarse=(0, 0, 0),
+                 precision: int = FP64, inner_tol: float = 0.0, max_iters: int = 0, history: bool = False,
+                 timing: bool = False, stream=None):
+        torch = _torch()
+        self.n = tuple(int(v) for v in n)
+        self.box = tuple(float(v) for v in box)
+        self.tol = float(tol)
+        self.precision = int(precision)
+        flags = (WANT_HISTORY if history else 0) | (WANT_TIMING if timing else 0)
+        self._p = _problem(self.n, self.box, tol, n_coarse, precision, inner_tol, max_iters, flags)
+        nbytes = ctypes.c_size_t(0)
+        _lib.check(_lib.lib().excmg_workspace_bytes(ctypes.byref(self._p), ctypes.byref(nbytes)),
+                   "excmg_workspace_bytes")
+        self.workspace = torch.empty(int(nbytes.value), dtype=torch.uint8, device="cuda")
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self._h = ctypes.c_void_p(0)
+        _lib.check(_lib.lib().excmg_setup(ctypes.byref(self._p), _ptr(self.workspace), nbytes, _stream_ptr(self.stream),
+                                          ctypes.byref(self._h)), "excmg_setup")
+        self.levels, self.n_coarse = plan(self.n, n_coarse, self.box, tol)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def shape(self):
+        return (self.n[2] + 1, self.n[1] + 1, self.n[0] + 1)
+
+    def empty(self):
+        return _torch().empty(self.shape(), dtype=_torch().float64, device="cuda")
+
+    def solve(self, f, g, u=None, want_ext: bool = False, allow_noconv: bool = False):
+        """Returns (u, u_ext or None, stats dict)."""
+        _check_nodes(f, self.n, "f")
+        _check_nodes(g, self.n, "g")
+        u = self.empty() if u is None else u
+        _check_nodes(u, self.n, "u")
+        ue = self.empty() if want_ext else None
+        st = _lib.Stats()
+        code = _lib.lib().excmg_solve(self._h, _ptr(f), _ptr(g), _ptr(u), _ptr(ue), ctypes.byref(st))
+        _lib.check(code, "excmg_solve", allow=(_lib.ERR_NOCONV,) if allow_noconv else ())
+        d = st.to_dict()
+        d["status"] = code
+        return u, ue, d
+
+    def gradient(self, u, out=None):
+        _check_nodes(u, self.n, "u")
+        ux, uy, uz = out if out is not None else (self.empty(), self.empty(), self.empty())
+        _lib.check(_lib.lib().excmg_gradient(self._h, _ptr(u), _ptr(ux), _ptr(uy), _ptr(uz)), "excmg_gradient")
+        return ux, uy, uz
+
+    def adjoint(self, G, want_lambda: bool = False):
+        """Returns (dLdf, dLdg, lambda or None, stats dict)."""
+        _check_nodes(G, self.n, "G")
+        dLdf, dLdg = self.empty(), self.empty()
+        lam = self.empty() if want_lambda else None
+        st = _lib.Stats()
+        code = _lib.lib().excmg_adjoint(self._h, _ptr(G), _ptr(dLdf), _ptr(dLdg), _ptr(lam), ctypes.byref(st))
+        _lib.check(code, "excmg_adjoint")
+        return dLdf, dLdg, lam, st.to_dict()
+
+    def close(self):
+        if self._h:
+            _lib.lib().excmg_destroy(self._h)
+            self._h = ctypes.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def solve_batched(solvers, fs, gs, us=None):
+    """Solve many problems (each with its own Solver) in one call.  Returns (us, stats list, ms_per_problem)."""
+    count = len(solvers)
+    us = [s.empty() for s in solvers] if us is None else us
+    H = (ctypes.c_void_p * count)(*[s.handle.value for s in solvers])
+    F = (ctypes.c_void_p * count)(*[f.data_ptr() for f in fs])
+    G = (ctypes.c_void_p * count)(*[g.data_ptr() for g in gs])
+    U = (ctypes.c_void_p * count)(*[u.data_ptr() for u in us])
+    st = (_lib.Stats * count)()
+    ms = (ctypes.c_double * count)()
+    code = _lib.lib().excmg_solve_batched(H, count, F, G, U, st, ms)
+    _lib.check(code, "excmg_solve_batched")
+    return us, [st[b].to_dict() for b in range(count)], [ms[b] for b in range(count)]
+
+
+def _n3(n):
+    return (ctypes.c_int32 * 3)(*[int(v) for v in n])
+
+
+def _box3(box):
+    return (ctypes.c_double * 3)(*[float(v) for v in box])
+
+
+def op_apply(x, n, box=(1.0, 1.0, 1.0)):
+    """y = M x, M = -A_h on the interior (boundary of x read as 0)."""
+    _check_nodes(x, n, "x")
+    y = _torch().empty_like(x)
+    _lib.check(_lib.lib().excmg_op_apply(_n3(n), _box3(box), _ptr(x), _ptr(y), _stream_ptr()), "excmg_op_apply")
+    return y
+
+
+def op_rhs(f, g, n, box=(1.0, 1.0, 1.0)):
+    _check_nodes(f, n, "f")
+    b = _torch().empty_like(f)
+    _lib.check(_lib.lib().excmg_op_rhs(_n3(n), _box3(box), _ptr(f), _ptr(g), _ptr(b), _stream_ptr()), "excmg_op_rhs")
+    return b
+
+
+def op_exp_finite(u2h, u4h, g, n):
+    _check_nodes(g, n, "g")
+    w = _torch().empty_like(g)
+    _lib.check(_lib.lib().excmg_op_exp_finite(_n3(n), _ptr(u2h), _ptr(u4h), _ptr(g), _ptr(w), _stream_ptr()),
+               "excmg_op_exp_finite")
+    return w
+
+
+def op_exp_true(uh, u2h, n):
+    _check_nodes(uh, n, "uh")
+    ut = _torch().empty_like(uh)
+    _lib.check(_lib.lib().excmg_op_exp_true(_n3(n), _ptr(uh), _ptr(u2h), _ptr(ut), _stream_ptr()), "excmg_op_exp_true")
+    return ut

@@ -1,0 +1,785 @@
+// Host driver and C ABI of the gfx950 EXCMG solver (Algorithm 1 of Pan, He & Hu, arXiv 1507.05063).
+//
+// Per grid of the cascade (coarsest first):
+//   level data   b_l = -R f_l + A_IB g_l, with f_l, g_l the finest arrays at stride 2^(L-1-l)  (Section 2, eq. compact)
+//   grids 0, 1   DSOLVE: single-workgroup CG to rounding                                     (Algorithm 1, lines 1-2)
+//   grids >= 2   w = EXP_finite(u_{l-1}, u_{l-2}), then CG from w until ||r|| <= tol ||b||   (Algorithm 1, the loop)
+//   finest       u_ext = EXP_true(u_h, u_2h) on request; u copied to the caller's dense array
+// The library allocates no device memory: every array lives in the caller's workspace.  The host reads the CG state
+// back (one small copy and a stream sync) after every batch of iterations; iterations launched after convergence
+// return at once (every CG kernel checks the device-side done flag first).
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <chrono>
+#include <new>
+#include <vector>
+
+#include "excmg_internal.h"
+
+using namespace excmg;
+
+namespace {
+
+struct Level {
+  int n[3];
+  double h[3];
+  int stride;  // sampling stride into the finest arrays
+  Grid g;      // pitched FP64 layout of this grid's arrays
+  Grid g32;    // pitched FP32 layout
+  Stencil st;
+  double *u;   // this grid's solution, all nodes (boundary = g)
+};
+
+struct Layout {
+  int L;
+  int nc[3];
+  Level lev[EXCMG_MAX_LEVELS];
+  Grid gdense;
+  Grid gfin, gfin32;
+  // byte offsets into the workspace
+  size_t off_u[EXCMG_MAX_LEVELS];
+  size_t off_b, off_r, off_p0, off_p1;
+  size_t off_r32, off_p32a, off_p32b, off_d32;
+  size_t off_part, off_cs, off_cs2, off_invm[3], off_flag;
+  long long npart;
+  size_t total;
+};
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+int plan_levels(const excmg_problem *p, int *L_out, int nc[3]) {
+  for (int d = 0; d < 3; ++d)
+    if (p->n[d] < 2) return EXCMG_ERR_SHAPE;
+  int c[3] = {p->n_coarse[0], p->n_coarse[1], p->n_coarse[2]};
+  if (c[0] == 0 && c[1] == 0 && c[2] == 0) {
+    c[0] = p->n[0]; c[1] = p->n[1]; c[2] = p->n[2];
+    // halve while the halved counts are all even (so they can feed EXP_finite), >= 2, and the largest is >= 4
+    for (;;) {
+      const bool even = !(c[0] & 1) && !(c[1] & 1) && !(c[2] & 1);
+      const int h0 = c[0] / 2, h1 = c[1] / 2, h2 = c[2] / 2;
+      const bool heven = !(h0 & 1) && !(h1 & 1) && !(h2 & 1);
+      const int mx = h0 > h1 ? (h0 > h2 ? h0 : h2) : (h1 > h2 ? h1 : h2);
+      if (!even || !heven || h0 < 2 || h1 < 2 || h2 < 2 || mx < 4) break;
+      c[0] = h0; c[1] = h1; c[2] = h2;
+    }
+  }
+  if (c[0] < 2 || c[1] < 2 || c[2] < 2) return EXCMG_ERR_SHAPE;
+  int L = -1;
+  for (int t = 0; t < EXCMG_MAX_LEVELS; ++t) {
+    if ((long long)c[0] << t == p->n[0] && (long long)c[1] << t == p->n[1] && (long long)c[2] << t == p->n[2]) {
+      L = t + 1;
+      break;
+    }
+  }
+  if (L < 0) return EXCMG_ERR_SHAPE;
+  if (L >= 3 && ((c[0] & 1) || (c[1] & 1) || (c[2] & 1))) return EXCMG_ERR_SHAPE;
+  *L_out = L;
+  nc[0] = c[0]; nc[1] = c[1]; nc[2] = c[2];
+  return EXCMG_OK;
+}
+
+int validate(const excmg_problem *p) {
+  if (!p) return EXCMG_ERR_ARG;
+  for (int d = 0; d < 3; ++d)
+    if (!(p->box[d] > 0.0) || !isfinite(p->box[d])) return EXCMG_ERR_ARG;
+  if (!(p->tol > 0.0) || !isfinite(p->tol)) return EXCMG_ERR_ARG;
+  if (p->precision != EXCMG_FP64 && p->precision != EXCMG_FP32_IR) return EXCMG_ERR_ARG;
+  if (p->inner_tol < 0.0 || !isfinite(p->inner_tol) || p->inner_tol >= 1.0) return EXCMG_ERR_ARG;
+  if (p->max_iters < 0) return EXCMG_ERR_ARG;
+  if (p->flags & ~(EXCMG_WANT_HISTORY | EXCMG_WANT_TIMING)) return EXCMG_ERR_ARG;
+  return EXCMG_OK;
+}
+
+int make_layout(const excmg_problem *p, Layout *Lo) {
+  int e = validate(p);
+  if (e) return e;
+  e = plan_levels(p, &Lo->L, Lo->nc);
+  if (e) return e;
+  const int L = Lo->L;
+  size_t off = 0;
+  for (int l = 0; l < L; ++l) {
+    Level &lv = Lo->lev[l];
+    for (int d = 0; d < 3; ++d) {
+      lv.n[d] = Lo->nc[d] << l;
+      lv.h[d] = p->box[d] / lv.n[d];
+    }
+    lv.stride = 1 << (L - 1 - l);
+    lv.g = pitched_grid<double>(lv.n[0], lv.n[1], lv.n[2]);
+    lv.g32 = pitched_grid<float>(lv.n[0], lv.n[1], lv.n[2]);
+    lv.st = make_stencil(lv.h[0], lv.h[1], lv.h[2]);
+    lv.u = nullptr;
+    Lo->off_u[l] = off;
+    off = align256(off + (size_t)lv.g.elems * sizeof(double));
+  }
+  const Level &fin = Lo->lev[L - 1];
+  Lo->gdense = dense_grid(fin.n[0], fin.n[1], fin.n[2]);
+  Lo->gfin = fin.g;
+  Lo->gfin32 = fin.g32;
+  const size_t v64 = align256((size_t)fin.g.elems * sizeof(double));
+  Lo->off_b = off; off += v64;
+  Lo->off_r = off; off += v64;
+  Lo->off_p0 = off; off += v64;
+  Lo->off_p1 = off; off += v64;
+  if (p->precision == EXCMG_FP32_IR) {
+    const size_t v32 = align256((size_t)fin.g32.elems * sizeof(float));
+    Lo->off_r32 = off; off += v32;
+    Lo->off_p32a = off; off += v32;
+    Lo->off_p32b = off; off += v32;
+    Lo->off_d32 = off; off += v32;
+  } else {
+    Lo->off_r32 = Lo->off_p32a = Lo->off_p32b = Lo->off_d32 = 0;
+  }
+  Lo->npart = cg_partials_needed(fin.g);
+  Lo->off_part = off; off = align256(off + (size_t)Lo->npart * sizeof(double));
+  Lo->off_cs = off; off = align256(off + sizeof(CgState));
+  Lo->off_cs2 = off; off = align256(off + sizeof(CgState));
+  for (int d = 0; d < 3; ++d) {
+    Lo->off_invm[d] = off;
+    off = align256(off + (size_t)(fin.n[d] + 1) * sizeof(double));
+  }
+  Lo->off_flag = off; off = align256(off + 64);
+  Lo->total = off;
+  return EXCMG_OK;
+}
+
+struct TimedLaunch {
+  int cls;
+  int level;
+  int iter;  // CG iteration index of a CG-class launch (-1: always counted)
+  int outer; // FP32_IR outer step (-1 otherwise)
+  hipEvent_t a, b;
+};
+
+}  // namespace
+
+struct excmg_handle {
+  excmg_problem p;
+  Layout lo;
+  hipStream_t stream;
+  int device;
+  char *ws;
+  double *b, *r, *p0, *p1;
+  float *r32, *p32a, *p32b, *d32;
+  double *partials;
+  CgState *cs, *cs2;
+  double *inv_m[3];
+  int *flag;
+  std::vector<double> inv_m_host[3];
+  hipEvent_t lev_ev[EXCMG_MAX_LEVELS + 1];
+  // kernel timing
+  std::vector<hipEvent_t> pool;
+  std::vector<TimedLaunch> timed;
+  size_t pool_used;
+  bool timing;
+};
+
+namespace {
+
+struct DeviceGuard {
+  int prev = -1;
+  bool changed = false;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) == hipSuccess && prev != dev) {
+      if (hipSetDevice(dev) == hipSuccess) changed = true;
+    }
+  }
+  ~DeviceGuard() {
+    if (changed) (void)hipSetDevice(prev);
+  }
+};
+
+#define HIPCHECK(x)                       \
+  do {                                    \
+    if ((x) != hipSuccess) return EXCMG_ERR_HIP; \
+  } while (0)
+
+inline int last_error() { return hipGetLastError() == hipSuccess ? EXCMG_OK : EXCMG_ERR_HIP; }
+
+// Kernel timing: a pair of events around each launch when EXCMG_WANT_TIMING is set.
+struct Tick {
+  excmg_handle *h;
+  int idx;
+  Tick(excmg_handle *h_, int cls, int level, int iter = -1, int outer = -1) : h(h_), idx(-1) {
+    if (!h->timing || h->pool_used + 2 > h->pool.size()) return;
+    TimedLaunch t;
+    t.cls = cls;
+    t.level = level;
+    t.iter = iter;
+    t.outer = outer;
+    t.a = h->pool[h->pool_used++];
+    t.b = h->pool[h->pool_used++];
+    (void)hipEventRecord(t.a, h->stream);
+    h->timed.push_back(t);
+    idx = (int)h->timed.size() - 1;
+  }
+  ~Tick() {
+    if (idx >= 0) (void)hipEventRecord(h->timed[idx].b, h->stream);
+  }
+};
+
+int read_state(excmg_handle *h, CgState *dst, const CgState *src) {
+  HIPCHECK(hipMemcpyAsync(dst, src, offsetof(CgState, hist), hipMemcpyDeviceToHost, h->stream));
+  HIPCHECK(hipStreamSynchronize(h->stream));
+  return EXCMG_OK;
+}
+
+int read_hist(excmg_handle *h, CgState *dst, const CgState *src) {
+  HIPCHECK(hipMemcpyAsync(dst, src, sizeof(CgState), hipMemcpyDeviceToHost, h->stream));
+  HIPCHECK(hipStreamSynchronize(h->stream));
+  return EXCMG_OK;
+}
+
+// Per-level iteration counts of CG-class timed launches, to drop launches made after convergence.
+struct LevelIters {
+  int iters[EXCMG_MAX_LEVELS];
+  std::vector<int> inner[EXCMG_MAX_LEVELS];  // FP32_IR: inner iterations of each outer step
+};
+
+constexpr int kBatch = 4;
+
+// Grids smaller than this relax in FP64 under EXCMG_FP32_IR as well: their sweeps are launch- and latency-bound, so
+// halving their bytes saves nothing, while the extra outer steps of the refinement would cost launches.
+constexpr long long kIrMinUnknowns = 1LL << 20;
+
+// FP64 CG on level l from the current u (Algorithm 1, the while loop; one iteration per pass).
+int cg64(excmg_handle *h, int l, bool finest, int *iters, double *relres, excmg_stats *st) {
+  Level &lv = h->lo.lev[l];
+  const hipStream_t s = h->stream;
+  int np = 0;
+  {
+    Tick t(h, EXCMG_K_RESID, l);
+    launch_residual(lv.g, lv.u, lv.g, h->b, lv.g, h->r, lv.st, h->partials, &np, s);
+  }
+  const int hist_on = (finest && st && (h->p.flags & EXCMG_WANT_HISTORY)) ? 1 : 0;
+  const int maxit = h->p.max_iters > 0 ? h->p.max_iters : 10000;
+  {
+    Tick t(h, EXCMG_K_FINALIZE, l);
+    launch_finalize_init(h->cs, h->partials, np, h->p.tol, maxit, hist_on, s);
+  }
+  int e = last_error();
+  if (e) return e;
+  CgState hs;
+  int launched = 0;
+  for (;;) {
+    for (int q = 0; q < kBatch; ++q, ++launched) {
+      {
+        Tick t(h, EXCMG_K_CG_A, l, launched);
+        launch_cg_pass_a<double>(lv.g, h->r, h->p0, h->p1, lv.st, h->cs, h->partials, &np, s);
+      }
+      {
+        Tick t(h, EXCMG_K_FINALIZE, l, launched);
+        launch_finalize_a(h->cs, h->partials, np, s);
+      }
+      {
+        Tick t(h, EXCMG_K_CG_B, l, launched);
+        launch_cg_pass_b<double>(lv.g, lv.u, h->r, h->p0, h->p1, lv.st, h->cs, h->partials, &np, s);
+      }
+      {
+        Tick t(h, EXCMG_K_FINALIZE, l, launched);
+        launch_finalize_b(h->cs, h->partials, np, s);
+      }
+    }
+    e = last_error();
+    if (e) return e;
+    e = read_state(h, &hs, h->cs);
+    if (e) return e;
+    if (hs.done) break;
+  }
+  *iters = hs.iter;
+  *relres = hs.bnorm2 > 0.0 ? sqrt(hs.rho / hs.bnorm2) : 0.0;
+  if (!isfinite(hs.bnorm2)) return EXCMG_ERR_NONFINITE;
+  if (hist_on) {
+    CgState full;
+    e = read_hist(h, &full, h->cs);
+    if (e) return e;
+    const int n = hs.iter + 1 < EXCMG_MAX_HISTORY ? hs.iter + 1 : EXCMG_MAX_HISTORY;
+    st->history_len = n;
+    for (int q = 0; q < n; ++q) st->history[q] = full.hist[q];
+  }
+  return hs.status;
+}
+
+// FP32 CG sweeps inside FP64 iterative refinement on level l.
+int cg_ir(excmg_handle *h, int l, bool finest, int *iters, int *outer_out, double *relres, excmg_stats *st,
+          std::vector<int> *inner_counts) {
+  Level &lv = h->lo.lev[l];
+  const hipStream_t s = h->stream;
+  const double eta = h->p.inner_tol > 0.0 ? h->p.inner_tol : 1e-5;
+  const int maxit = h->p.max_iters > 0 ? h->p.max_iters : 10000;
+  const int max_outer = 30;
+  int total = 0;
+  int np = 0;
+  CgState ho, hi;
+  int status = EXCMG_OK;
+  int outer = 0;
+  for (;; ++outer) {
+    {
+      Tick t(h, EXCMG_K_RESID, l);
+      launch_residual_cast(lv.g, lv.u, lv.g, h->b, lv.g32, h->r32, h->d32, lv.st, h->partials, &np, s);
+    }
+    {
+      Tick t(h, EXCMG_K_FINALIZE, l);
+      launch_finalize_ir(h->cs, h->cs2, h->partials, np, h->p.tol, eta, outer, max_outer, maxit, s);
+    }
+    int e = last_error();
+    if (e) return e;
+    e = read_state(h, &ho, h->cs);
+    if (e) return e;
+    if (ho.done) {
+      status = ho.status;
+      break;
+    }
+    int launched = 0;
+    for (;;) {
+      for (int q = 0; q < kBatch; ++q, ++launched) {
+        {
+          Tick t(h, EXCMG_K_CG_A32, l, launched, outer);
+          launch_cg_pass_a<float>(lv.g32, h->r32, h->p32a, h->p32b, lv.st, h->cs2, h->partials, &np, s);
+        }
+        {
+          Tick t(h, EXCMG_K_FINALIZE, l, launched, outer);
+          launch_finalize_a(h->cs2, h->partials, np, s);
+        }
+        {
+          Tick t(h, EXCMG_K_CG_B32, l, launched, outer);
+          launch_cg_pass_b<float>(lv.g32, h->d32, h->r32, h->p32a, h->p32b, lv.st, h->cs2, h->partials, &np, s);
+        }
+        {
+          Tick t(h, EXCMG_K_FINALIZE, l, launched, outer);
+          launch_finalize_b(h->cs2, h->partials, np, s);
+        }
+      }
+      e = last_error();
+      if (e) return e;
+      e = read_state(h, &hi, h->cs2);
+      if (e) return e;
+      if (hi.done) break;
+    }
+    total += hi.iter;
+    if (inner_counts) inner_counts->push_back(hi.iter);
+    if (hi.status == EXCMG_ERR_BREAKDOWN) return EXCMG_ERR_BREAKDOWN;
+    {
+      Tick t(h, EXCMG_K_OTHER, l);
+      launch_add_correction(lv.g, lv.u, lv.g32, h->d32, s);
+    }
+  }
+  *iters = total;
+  *outer_out = outer;
+  *relres = ho.bnorm2 > 0.0 ? sqrt(ho.rho / ho.bnorm2) : 0.0;
+  if (!isfinite(ho.bnorm2)) return EXCMG_ERR_NONFINITE;
+  if (finest && st && (h->p.flags & EXCMG_WANT_HISTORY)) {
+    st->history_len = 0;
+  }
+  return status;
+}
+
+int dsolve(excmg_handle *h, int l, excmg_stats *st) {
+  Level &lv = h->lo.lev[l];
+  {
+    Tick t(h, EXCMG_K_DSOLVE, l);
+    launch_dsolve(lv.g, lv.u, lv.g, h->b, lv.g, h->r, h->p0, h->p1, lv.st, h->cs, h->stream);
+  }
+  int e = last_error();
+  if (e) return e;
+  CgState hs;
+  e = read_state(h, &hs, h->cs);
+  if (e) return e;
+  if (st && l < 2) st->dsolve_iters[l] = hs.iter;
+  if (!isfinite(hs.bnorm2)) return EXCMG_ERR_NONFINITE;
+  return hs.status;
+}
+
+void reset_timing(excmg_handle *h) {
+  h->timed.clear();
+  h->pool_used = 0;
+}
+
+// Sum the timed launches into the stats, dropping CG launches made after their level converged.
+int collect_timing(excmg_handle *h, excmg_stats *st, const LevelIters &li) {
+  if (!h->timing || !st) return EXCMG_OK;
+  HIPCHECK(hipStreamSynchronize(h->stream));
+  const int Lf = h->lo.L - 1;
+  for (const TimedLaunch &t : h->timed) {
+    if (t.iter >= 0) {
+      int limit;
+      if (t.outer >= 0) {
+        const std::vector<int> &v = li.inner[t.level];
+        limit = (t.outer < (int)v.size()) ? v[t.outer] : 0;
+      } else {
+        limit = li.iters[t.level];
+      }
+      if (t.iter >= limit) continue;
+    }
+    float ms = 0.0f;
+    HIPCHECK(hipEventElapsedTime(&ms, t.a, t.b));
+    st->kernel_ms[t.cls] += ms;
+    st->kernel_calls[t.cls] += 1;
+    if (t.level == Lf) {
+      st->kernel_ms_finest[t.cls] += ms;
+      st->kernel_calls_finest[t.cls] += 1;
+    }
+  }
+  return EXCMG_OK;
+}
+
+void bind_workspace(excmg_handle *h) {
+  char *w = h->ws;
+  Layout &lo = h->lo;
+  for (int l = 0; l < lo.L; ++l) lo.lev[l].u = (double *)(w + lo.off_u[l]);
+  h->b = (double *)(w + lo.off_b);
+  h->r = (double *)(w + lo.off_r);
+  h->p0 = (double *)(w + lo.off_p0);
+  h->p1 = (double *)(w + lo.off_p1);
+  if (h->p.precision == EXCMG_FP32_IR) {
+    h->r32 = (float *)(w + lo.off_r32);
+    h->p32a = (float *)(w + lo.off_p32a);
+    h->p32b = (float *)(w + lo.off_p32b);
+    h->d32 = (float *)(w + lo.off_d32);
+  } else {
+    h->r32 = h->p32a = h->p32b = h->d32 = nullptr;
+  }
+  h->partials = (double *)(w + lo.off_part);
+  h->cs = (CgState *)(w + lo.off_cs);
+  h->cs2 = (CgState *)(w + lo.off_cs2);
+  for (int d = 0; d < 3; ++d) h->inv_m[d] = (double *)(w + lo.off_invm[d]);
+  h->flag = (int *)(w + lo.off_flag);
+}
+
+// The cascade shared by the solve and the adjoint.  mode 0: level data from (f, g); mode 1: from G, zero boundary.
+int cascade(excmg_handle *h, int mode, const double *f, const double *g, excmg_stats *st, LevelIters *li) {
+  Layout &lo = h->lo;
+  const int L = lo.L;
+  const hipStream_t s = h->stream;
+  int final_status = EXCMG_OK;
+  for (int l = 0; l < L; ++l) {
+    Level &lv = lo.lev[l];
+    HIPCHECK(hipEventRecord(h->lev_ev[l], s));
+    {
+      Tick t(h, EXCMG_K_RHS, l);
+      if (mode == 0)
+        launch_rhs(lo.gdense, f, g, lv.stride, lv.g, h->b, lv.h[0], lv.h[1], lv.h[2], s);
+      else
+        launch_sample_interior(lo.gdense, f, lv.stride, lv.g, h->b, s);
+    }
+    int e = last_error();
+    if (e) return e;
+    int it = 0, outer = 0;
+    double rr = 0.0;
+    if (l <= 1) {
+      {
+        Tick t(h, EXCMG_K_OTHER, l);
+        launch_set_boundary(lo.gdense, mode == 0 ? g : nullptr, lv.stride, lv.g, lv.u, 1, s);
+      }
+      e = dsolve(h, l, st);
+      if (e) return e;
+    } else {
+      {
+        Tick t(h, EXCMG_K_EXP_FINITE, l);
+        launch_exp_finite(lo.lev[l - 1].g, lo.lev[l - 1].u, lo.lev[l - 2].g, lo.lev[l - 2].u, lo.gdense,
+                          mode == 0 ? g : nullptr, lv.stride, lv.g, lv.u, s);
+      }
+      e = last_error();
+      if (e) return e;
+      if (h->p.precision == EXCMG_FP64 || lv.g.interior() < kIrMinUnknowns)
+        e = cg64(h, l, l == L - 1, &it, &rr, st);
+      else
+        e = cg_ir(h, l, l == L - 1, &it, &outer, &rr, st, li ? &li->inner[l] : nullptr);
+      if (e == EXCMG_ERR_NOCONV)
+        final_status = EXCMG_ERR_NOCONV;
+      else if (e)
+        return e;
+    }
+    if (li) li->iters[l] = it;
+    if (st) {
+      st->iters[l] = it;
+      st->ir_outer[l] = outer;
+      st->relres[l] = rr;
+    }
+  }
+  HIPCHECK(hipEventRecord(h->lev_ev[L], s));
+  return final_status;
+}
+
+void fill_level_stats(excmg_handle *h, excmg_stats *st) {
+  if (!st) return;
+  (void)hipEventSynchronize(h->lev_ev[h->lo.L]);
+  st->levels = h->lo.L;
+  for (int l = 0; l < h->lo.L; ++l) {
+    for (int d = 0; d < 3; ++d) st->n[l][d] = h->lo.lev[l].n[d];
+    float ms = 0.0f;
+    if (hipEventElapsedTime(&ms, h->lev_ev[l], h->lev_ev[l + 1]) == hipSuccess) st->ms_level[l] = ms;
+  }
+}
+
+void clear_stats(excmg_stats *st) {
+  if (st) memset(st, 0, sizeof(*st));
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------------------------------------- C ABI
+
+extern "C" {
+
+int excmg_plan(const excmg_problem *p, int32_t *levels, int32_t n_coarse_out[3]) {
+  if (!p || !levels || !n_coarse_out) return EXCMG_ERR_ARG;
+  int e = validate(p);
+  if (e) return e;
+  int L, nc[3];
+  e = plan_levels(p, &L, nc);
+  if (e) return e;
+  *levels = L;
+  for (int d = 0; d < 3; ++d) n_coarse_out[d] = nc[d];
+  return EXCMG_OK;
+}
+
+int excmg_workspace_bytes(const excmg_problem *p, size_t *bytes) {
+  if (!p || !bytes) return EXCMG_ERR_ARG;
+  Layout lo;
+  const int e = make_layout(p, &lo);
+  if (e) return e;
+  *bytes = lo.total;
+  return EXCMG_OK;
+}
+
+int excmg_setup(const excmg_problem *p, void *workspace, size_t bytes, void *hip_stream, excmg_handle **out) {
+  if (!p || !out) return EXCMG_ERR_ARG;
+  *out = nullptr;
+  excmg_handle *h = new (std::nothrow) excmg_handle();
+  if (!h) return EXCMG_ERR_ARG;
+  int e = make_layout(p, &h->lo);
+  if (e) {
+    delete h;
+    return e;
+  }
+  if (!workspace || bytes < h->lo.total || ((uintptr_t)workspace & 255)) {
+    delete h;
+    return EXCMG_ERR_WORKSPACE;
+  }
+  h->p = *p;
+  h->stream = (hipStream_t)hip_stream;
+  if (hipGetDevice(&h->device) != hipSuccess) {
+    delete h;
+    return EXCMG_ERR_HIP;
+  }
+  h->ws = (char *)workspace;
+  bind_workspace(h);
+  // Thomas factors of the (1,4,1) systems: m_1 = 4, m_i = 4 - 1/m_{i-1}; the table holds 1/m_i at index i.
+  const Level &fin = h->lo.lev[h->lo.L - 1];
+  for (int d = 0; d < 3; ++d) {
+    const int N = fin.n[d];
+    std::vector<double> &v = h->inv_m_host[d];
+    v.assign(N + 1, 0.0);
+    double m = 4.0;
+    for (int i = 1; i <= N - 1; ++i) {
+      if (i > 1) m = 4.0 - 1.0 / m;
+      v[i] = 1.0 / m;
+    }
+    if (hipMemcpyAsync(h->inv_m[d], v.data(), (N + 1) * sizeof(double), hipMemcpyHostToDevice, h->stream) !=
+        hipSuccess) {
+      delete h;
+      return EXCMG_ERR_HIP;
+    }
+  }
+  for (int l = 0; l <= EXCMG_MAX_LEVELS; ++l) {
+    if (hipEventCreate(&h->lev_ev[l]) != hipSuccess) {
+      delete h;
+      return EXCMG_ERR_HIP;
+    }
+  }
+  h->timing = (p->flags & EXCMG_WANT_TIMING) != 0;
+  h->pool_used = 0;
+  if (h->timing) {
+    h->pool.resize(8192);
+    for (auto &ev : h->pool)
+      if (hipEventCreate(&ev) != hipSuccess) {
+        delete h;
+        return EXCMG_ERR_HIP;
+      }
+  }
+  if (hipStreamSynchronize(h->stream) != hipSuccess) {
+    delete h;
+    return EXCMG_ERR_HIP;
+  }
+  *out = h;
+  return EXCMG_OK;
+}
+
+int excmg_solve(excmg_handle *h, const double *f, const double *g, double *u, double *u_ext, excmg_stats *st) {
+  if (!h || !f || !g || !u) return EXCMG_ERR_ARG;
+  if (u_ext && h->lo.L < 2) return EXCMG_ERR_SHAPE;
+  DeviceGuard dg(h->device);
+  const auto t0 = std::chrono::steady_clock::now();
+  clear_stats(st);
+  reset_timing(h);
+  LevelIters li;
+  memset(li.iters, 0, sizeof(li.iters));
+  const int status = cascade(h, 0, f, g, st, &li);
+  if (status != EXCMG_OK && status != EXCMG_ERR_NOCONV) return status;
+  Layout &lo = h->lo;
+  const Level &fin = lo.lev[lo.L - 1];
+  if (u_ext) {
+    Tick t(h, EXCMG_K_EXP_TRUE, lo.L - 1);
+    launch_exp_true(fin.g, fin.u, lo.lev[lo.L - 2].g, lo.lev[lo.L - 2].u, lo.gdense, u_ext, h->stream);
+  }
+  {
+    Tick t(h, EXCMG_K_OTHER, lo.L - 1);
+    launch_copy(fin.g, fin.u, lo.gdense, u, h->stream);
+  }
+  int e = last_error();
+  if (e) return e;
+  HIPCHECK(hipStreamSynchronize(h->stream));
+  fill_level_stats(h, st);
+  e = collect_timing(h, st, li);
+  if (e) return e;
+  if (st) st->ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  return status;
+}
+
+int excmg_gradient(excmg_handle *h, const double *u, double *ux, double *uy, double *uz) {
+  if (!h || !u || !ux || !uy || !uz) return EXCMG_ERR_ARG;
+  const Level &fin = h->lo.lev[h->lo.L - 1];
+  if (fin.n[0] < 4 || fin.n[1] < 4 || fin.n[2] < 4) return EXCMG_ERR_SHAPE;
+  DeviceGuard dg(h->device);
+  const Grid &gd = h->lo.gdense;
+  launch_gradient(gd, u, gd, ux, uy, uz, fin.h[0], fin.h[1], fin.h[2], h->inv_m[0], h->inv_m[1], h->inv_m[2],
+                  h->stream);
+  int e = last_error();
+  if (e) return e;
+  HIPCHECK(hipStreamSynchronize(h->stream));
+  return EXCMG_OK;
+}
+
+int excmg_adjoint(excmg_handle *h, const double *G, double *dLdf, double *dLdg, double *lambda_out,
+                  excmg_stats *st) {
+  if (!h || !G || !dLdf || !dLdg) return EXCMG_ERR_ARG;
+  DeviceGuard dg(h->device);
+  const auto t0 = std::chrono::steady_clock::now();
+  clear_stats(st);
+  reset_timing(h);
+  LevelIters li;
+  memset(li.iters, 0, sizeof(li.iters));
+  const int status = cascade(h, 1, G, nullptr, st, &li);
+  if (status != EXCMG_OK && status != EXCMG_ERR_NOCONV) return status;
+  Layout &lo = h->lo;
+  const Level &fin = lo.lev[lo.L - 1];
+  launch_adjoint_transposes(fin.g, fin.u, lo.gdense, G, dLdf, dLdg, fin.h[0], fin.h[1], fin.h[2], h->stream);
+  if (lambda_out) launch_copy(fin.g, fin.u, lo.gdense, lambda_out, h->stream);
+  int e = last_error();
+  if (e) return e;
+  HIPCHECK(hipStreamSynchronize(h->stream));
+  fill_level_stats(h, st);
+  e = collect_timing(h, st, li);
+  if (e) return e;
+  if (st) st->ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  return status;
+}
+
+void excmg_destroy(excmg_handle *h) {
+  if (!h) return;
+  DeviceGuard dg(h->device);
+  (void)hipStreamSynchronize(h->stream);
+  for (int l = 0; l <= EXCMG_MAX_LEVELS; ++l)
+    if (h->lev_ev[l]) (void)hipEventDestroy(h->lev_ev[l]);
+  for (auto &ev : h->pool)
+    if (ev) (void)hipEventDestroy(ev);
+  delete h;
+}
+
+const char *excmg_strerror(int code) {
+  switch (code) {
+    case EXCMG_OK: return "ok";
+    case EXCMG_ERR_ARG: return "invalid argument";
+    case EXCMG_ERR_SHAPE: return "invalid grid shape or level plan";
+    case EXCMG_ERR_NONFINITE: return "non-finite input data";
+    case EXCMG_ERR_NOCONV: return "CG reached max_iters before the tolerance";
+    case EXCMG_ERR_BREAKDOWN: return "CG breakdown (p.Ap <= 0 or non-finite scalar)";
+    case EXCMG_ERR_HIP: return "HIP runtime error";
+    case EXCMG_ERR_WORKSPACE: return "workspace missing, too small or not 256-byte aligned";
+    default: return "unknown error code";
+  }
+}
+
+// ---------------------------------------------------------------------------------------------- single steps
+
+static int check_n(const int32_t n[3], int mult) {
+  for (int d = 0; d < 3; ++d)
+    if (n[d] < 2 || n[d] % mult) return EXCMG_ERR_SHAPE;
+  return EXCMG_OK;
+}
+
+int excmg_op_apply(const int32_t n[3], const double box[3], const double *x, double *y, void *hip_stream) {
+  if (!n || !box || !x || !y) return EXCMG_ERR_ARG;
+  if (check_n(n, 1)) return EXCMG_ERR_SHAPE;
+  for (int d = 0; d < 3; ++d)
+    if (!(box[d] > 0.0)) return EXCMG_ERR_ARG;
+  const hipStream_t s = (hipStream_t)hip_stream;
+  const Grid g = dense_grid(n[0], n[1], n[2]);
+  HIPCHECK(hipMemsetAsync(y, 0, (size_t)g.elems * sizeof(double), s));
+  launch_apply(g, x, g, y, make_stencil(box[0] / n[0], box[1] / n[1], box[2] / n[2]), s);
+  int e = last_error();
+  if (e) return e;
+  HIPCHECK(hipStreamSynchronize(s));
+  return EXCMG_OK;
+}
+
+int excmg_op_rhs(const int32_t n[3], const double box[3], const double *f, const double *g, double *b,
+                 void *hip_stream) {
+  if (!n || !box || !f || !g || !b) return EXCMG_ERR_ARG;
+  if (check_n(n, 1)) return EXCMG_ERR_SHAPE;
+  for (int d = 0; d < 3; ++d)
+    if (!(box[d] > 0.0)) return EXCMG_ERR_ARG;
+  const hipStream_t s = (hipStream_t)hip_stream;
+  const Grid gd = dense_grid(n[0], n[1], n[2]);
+  HIPCHECK(hipMemsetAsync(b, 0, (size_t)gd.elems * sizeof(double), s));
+  launch_rhs(gd, f, g, 1, gd, b, box[0] / n[0], box[1] / n[1], box[2] / n[2], s);
+  int e = last_error();
+  if (e) return e;
+  HIPCHECK(hipStreamSynchronize(s));
+  return EXCMG_OK;
+}
+
+int excmg_op_exp_finite(const int32_t n[3], const double *u2h, const double *u4h, const double *g, double *w,
+                        void *hip_stream) {
+  if (!n || !u2h || !u4h || !g || !w) return EXCMG_ERR_ARG;
+  if (check_n(n, 8)) return EXCMG_ERR_SHAPE;
+  const hipStream_t s = (hipStream_t)hip_stream;
+  const Grid gw = dense_grid(n[0], n[1], n[2]);
+  const Grid g2 = dense_grid(n[0] / 2, n[1] / 2, n[2] / 2);
+  const Grid g4 = dense_grid(n[0] / 4, n[1] / 4, n[2] / 4);
+  launch_exp_finite(g2, u2h, g4, u4h, gw, g, 1, gw, w, s);
+  int e = last_error();
+  if (e) return e;
+  HIPCHECK(hipStreamSynchronize(s));
+  return EXCMG_OK;
+}
+
+int excmg_op_exp_true(const int32_t n[3], const double *uh, const double *u2h, double *ut, void *hip_stream) {
+  if (!n || !uh || !u2h || !ut) return EXCMG_ERR_ARG;
+  if (check_n(n, 2)) return EXCMG_ERR_SHAPE;
+  const hipStream_t s = (hipStream_t)hip_stream;
+  const Grid gh = dense_grid(n[0], n[1], n[2]);
+  const Grid g2 = dense_grid(n[0] / 2, n[1] / 2, n[2] / 2);
+  launch_exp_true(gh, uh, g2, u2h, gh, ut, s);
+  int e = last_error();
+  if (e) return e;
+  HIPCHECK(hipStreamSynchronize(s));
+  return EXCMG_OK;
+}
+
+int excmg_solve_batched(excmg_handle *const *hs, int32_t count, const double *const *f, const double *const *g,
+                        double *const *u, excmg_stats *stats, double *ms_per_problem) {
+  if (!hs || count <= 0 || !f || !g || !u) return EXCMG_ERR_ARG;
+  int status = EXCMG_OK;
+  for (int b = 0; b < count; ++b) {
+    const int e = excmg_solve(hs[b], f[b], g[b], u[b], nullptr, stats ? &stats[b] : nullptr);
+    if (e == EXCMG_ERR_NOCONV) status = e;
+    else if (e) return e;
+    if (ms_per_problem) ms_per_problem[b] = stats ? stats[b].ms_total : 0.0;
+  }
+  return status;
+}
+
+}  // extern "C"

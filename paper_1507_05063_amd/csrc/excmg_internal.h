@@ -1,0 +1,158 @@
+// Internal declarations of the gfx950 EXCMG library: array layout, stencil coefficients, device scalar state and
+// the launchers of every kernel.  Host code and kernels share this header; nothing here is part of the ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/excmg.h"
+
+namespace excmg {
+
+// ------------------------------------------------------------------------------------------------------------
+// Layout of a node array: element (i,j,k) at base + off + k*sz + j*sy + i.
+// User arrays are dense (off = 0, sy = Nx+1, sz = (Nx+1)(Ny+1)).  The library's own arrays are pitched so that the
+// first interior node of every row (i = 1) starts a 128-byte line: off = A-1 and sy a multiple of A, with
+// A = 128 / sizeof(T).  Whole 64-lane row segments of interior nodes then map to whole cache lines.
+// ------------------------------------------------------------------------------------------------------------
+struct Grid {
+  int nx, ny, nz;   // cells per axis; nodes 0..n
+  long long sy, sz; // element strides of a row (j) and a plane (k)
+  long long off;    // element offset of node (0,0,0)
+  long long elems;  // elements to allocate (including the leading offset and a tail pad)
+
+  __host__ __device__ long long at(int i, int j, int k) const {
+    return off + (long long)k * sz + (long long)j * sy + (long long)i;
+  }
+  __host__ __device__ long long interior() const { return (long long)(nx - 1) * (ny - 1) * (nz - 1); }
+  __host__ __device__ long long nodes() const { return (long long)(nx + 1) * (ny + 1) * (nz + 1); }
+};
+
+inline Grid dense_grid(int nx, int ny, int nz) {
+  Grid g;
+  g.nx = nx; g.ny = ny; g.nz = nz;
+  g.sy = nx + 1;
+  g.sz = (long long)(nx + 1) * (ny + 1);
+  g.off = 0;
+  g.elems = g.sz * (nz + 1);
+  return g;
+}
+
+template <typename T>
+inline Grid pitched_grid(int nx, int ny, int nz) {
+  const long long A = 128 / (long long)sizeof(T);
+  Grid g;
+  g.nx = nx; g.ny = ny; g.nz = nz;
+  g.off = A - 1;
+  g.sy = ((nx + A) + A - 1) / A * A;  // holds off + nx + 1 elements, a multiple of A
+  g.sz = g.sy * (ny + 1);
+  g.elems = ((g.off + g.sz * (nz + 1) + A) + A - 1) / A * A;
+  return g;
+}
+
+// Coefficients of M = -A_h (eq. compact negated), a = 1/hx^2, b = 1/hy^2, c = 1/hz^2:
+//   centre 8(a+b+c); x faces -(4a-b-c); y faces -(4b-a-c); z faces -(4c-a-b);
+//   xy edges -(a+b)/2; xz edges -(a+c)/2; yz edges -(b+c)/2.
+struct Stencil {
+  double c0, cx, cy, cz, cxy, cxz, cyz;
+};
+
+inline Stencil make_stencil(double hx, double hy, double hz) {
+  const double a = 1.0 / (hx * hx), b = 1.0 / (hy * hy), c = 1.0 / (hz * hz);
+  Stencil s;
+  s.c0 = 8.0 * (a + b + c);
+  s.cx = -(4.0 * a - b - c);
+  s.cy = -(4.0 * b - a - c);
+  s.cz = -(4.0 * c - a - b);
+  s.cxy = -0.5 * (a + b);
+  s.cxz = -0.5 * (a + c);
+  s.cyz = -0.5 * (b + c);
+  return s;
+}
+
+// Device-resident CG state of one solve (one per problem in a batch).  Written only by the finalize kernels.
+struct CgState {
+  double rho;      // r.r of the current residual
+  double rho_old;  // r.r of the previous residual
+  double pq;       // p.Mp of the current direction
+  double alpha, beta;
+  double bnorm2;   // ||b||^2 of the system being solved
+  double stop2;    // stop when rho <= stop2 (= (tol ||b||)^2)
+  int iter;        // iterations completed
+  int done;        // 1: converged or stopped; every CG kernel returns at once
+  int status;      // 0 ok, EXCMG_ERR_NOCONV, EXCMG_ERR_BREAKDOWN
+  int max_iters;
+  int hist_on;     // record sqrt(rho / bnorm2) after each iteration into hist
+  int pad_;
+  double hist[EXCMG_MAX_HISTORY];
+};
+
+// ------------------------------------------------------------------------------------------------------------
+// Launchers (defined in the .hip files).  All take the stream last.
+// ------------------------------------------------------------------------------------------------------------
+
+// partial-sum buffer length needed by the CG and residual kernels for a grid
+long long cg_partials_needed(const Grid &g);
+
+// r = b - M u (interior of u only), p-buffers untouched; partials: [r.r | b.b] (2 per block)
+void launch_residual(const Grid &gu, const double *u, const Grid &gb, const double *b, const Grid &gr, double *r,
+                     const Stencil &s, double *partials, int *nparts, hipStream_t st);
+// FP32 inner step setup: r32 = (float)(b - M u) and d32 = 0; partials [r.r | b.b | r32.r32] (3 per block)
+void launch_residual_cast(const Grid &gu, const double *u, const Grid &gb, const double *b, const Grid &g32,
+                          float *r32, float *d32, const Stencil &s, double *partials, int *nparts, hipStream_t st);
+
+template <typename T>
+void launch_cg_pass_a(const Grid &g, const T *r, T *p0, T *p1, const Stencil &s, const CgState *cs, double *partials,
+                      int *nparts, hipStream_t st);
+template <typename T>
+void launch_cg_pass_b(const Grid &g, T *u, T *r, const T *p0, const T *p1, const Stencil &s, const CgState *cs,
+                      double *partials, int *nparts, hipStream_t st);
+
+// finalize kernels (one block, fixed summation order)
+void launch_finalize_init(CgState *cs, const double *partials, int nparts, double tol, int max_iters, int hist_on,
+                          hipStream_t st);
+void launch_finalize_ir(CgState *outer, CgState *inner, const double *partials, int nparts, double tol, double eta,
+                        int outer_step, int max_outer, int max_inner, hipStream_t st);
+void launch_finalize_a(CgState *cs, const double *partials, int nparts, hipStream_t st);
+void launch_finalize_b(CgState *cs, const double *partials, int nparts, hipStream_t st);
+
+// u += (double) d32 on the interior
+void launch_add_correction(const Grid &gu, double *u, const Grid &g32, const float *d32, hipStream_t st);
+
+// single-workgroup CG to rounding on a small grid (DSOLVE); work arrays r, p, q on grid gw
+void launch_dsolve(const Grid &gu, double *u, const Grid &gb, const double *b, const Grid &gw, double *r, double *p,
+                   double *q, const Stencil &s, CgState *cs, hipStream_t st);
+
+// y = M x (interior of x only), y = 0 on the boundary
+void launch_apply(const Grid &gx, const double *x, const Grid &gy, double *y, const Stencil &s, hipStream_t st);
+
+// level data: b = -R f + A_IB g from the finest dense f, g sampled at stride s
+void launch_rhs(const Grid &gf, const double *f, const double *g, int stride, const Grid &gb, double *b,
+                double hx, double hy, double hz, hipStream_t st);
+// b = G sampled at stride s on the interior (the adjoint's level data)
+void launch_sample_interior(const Grid &gf, const double *G, int stride, const Grid &gb, double *b, hipStream_t st);
+// boundary nodes of u <- g (finest dense g sampled at stride s); interior set to 0 if zero_interior
+void launch_set_boundary(const Grid &gg, const double *g, int stride, const Grid &gu, double *u, int zero_interior,
+                         hipStream_t st);
+// w on grid gw from u2 (grid g2, n/2) and u4 (grid g4, n/4); boundary from dense finest g at stride s
+void launch_exp_finite(const Grid &g2, const double *u2, const Grid &g4, const double *u4, const Grid &gg,
+                       const double *g, int stride, const Grid &gw, double *w, hipStream_t st);
+// ut (grid gt) = EXP_true(uh (grid gh), u2 (grid g2))
+void launch_exp_true(const Grid &gh, const double *uh, const Grid &g2, const double *u2, const Grid &gt, double *ut,
+                     hipStream_t st);
+// copy between layouts (same n)
+void launch_copy(const Grid &gs, const double *src, const Grid &gd, double *dst, hipStream_t st);
+// count of non-finite values in a dense array -> *flag (device int, must be zeroed by the caller)
+void launch_check_finite(const double *a, long long n, int *flag, hipStream_t st);
+
+// gradient of a grid function (layout gu) into dense outputs (layout gd); table: 1/m_i for N up to nmax
+void launch_gradient(const Grid &gu, const double *u, const Grid &gd, double *ux, double *uy, double *uz, double hx,
+                     double hy, double hz, const double *inv_m_x, const double *inv_m_y, const double *inv_m_z,
+                     hipStream_t st);
+
+// adjoint transposes: dLdf = -R^T lam (all nodes); dLdg = A_IB^T lam + G (boundary), 0 inside
+void launch_adjoint_transposes(const Grid &gl, const double *lam, const Grid &gd, const double *G, double *dLdf,
+                               double *dLdg, double hx, double hy, double hz, hipStream_t st);
+
+}  // namespace excmg

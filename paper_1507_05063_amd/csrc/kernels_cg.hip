@@ -1,0 +1,654 @@
+// Conjugate-gradient kernels of the EXCMG relaxation (Algorithm 1, the CG loop on each grid) for gfx950.
+//
+// One CG iteration is two bandwidth-bound sweeps separated by the two global reductions CG needs:
+//   pass A:  p = r + beta p_old (beta = 0 on the first iteration), partial sums of p.Mp       reads r, p_old; writes p
+//   pass B:  u += alpha p, r -= alpha Mp, partial sums of r.r                                 reads p, r, u;  writes r, u
+// Mp is evaluated in both passes from p staged in LDS, so no q vector is stored: 64 B per unknown and iteration in
+// FP64 (32 B in FP32) instead of the 80 B of the textbook q-storing form.  The direction vector is double-buffered
+// (p_k lives in buffer k mod 2) because pass A reads p_old with halos while it writes p.
+//
+// Stencil sweep ("z-march"): a workgroup owns a TX x TY column tile and a chunk of z planes.  For each plane it loads
+// the (TX+2) x (TY+2) tile with its halo into LDS (double-buffered, one barrier per plane) and every thread forms the
+// plane sums of its column: centre C, x-pair X, y-pair Y, xy-diagonals D.  The 19-point result at plane k is
+//   c0 C_k + cx X_k + cy Y_k + cxy D_k + cz (C_{k-1} + C_{k+1}) + cxz (X_{k-1} + X_{k+1}) + cyz (Y_{k-1} + Y_{k+1}),
+// so each plane's global data is read once per workgroup and the z-neighbours come from registers.  The next plane
+// is fetched into registers before the current one is reduced, to keep loads in flight.
+//
+// Workgroups are numbered so that consecutive tiles of one z chunk run on the same XCD (dispatch is round-robin over
+// the 8 XCDs), which keeps the y-halo rows shared by neighbouring tiles in that XCD's L2.
+//
+// Reductions: wavefront butterfly (xor shuffles), then one value per wave through LDS, one partial per workgroup, and
+// a single-workgroup finalize kernel that sums the partials in a fixed order.  Results are bitwise reproducible.
+#include <math.h>
+
+#include "excmg_internal.h"
+
+namespace excmg {
+
+namespace {
+
+constexpr int kXcds = 8;
+
+// Bijection from the hardware workgroup id to a logical tile id such that logical ids [x*per, (x+1)*per) run on XCD x.
+__device__ __forceinline__ int xcd_remap(int b, int nb) {
+  const int per = nb / kXcds, rem = nb % kXcds;
+  const int x = b % kXcds, l = b / kXcds;
+  const int start = (x < rem) ? x * (per + 1) : rem * (per + 1) + (x - rem) * per;
+  return start + l;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Sum over the workgroup, deterministic; the result is valid in thread 0.
+template <int NT>
+__device__ __forceinline__ double block_sum(double v, double *sh) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) sh[w] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int q = 0; q < (NT + 63) / 64; ++q) t += sh[q];
+  }
+  return t;
+}
+
+// Tile shape of the stencil sweeps.
+constexpr int TX = 64;
+constexpr int TY = 4;
+constexpr int NT = TX * TY;
+constexpr int ZC = 16;  // z planes per workgroup
+
+struct TileMap {
+  int ntx, nty, nzc;
+};
+
+inline TileMap tile_map(const Grid &g) {
+  TileMap m;
+  m.ntx = (g.nx - 1 + TX - 1) / TX;
+  m.nty = (g.ny - 1 + TY - 1) / TY;
+  m.nzc = (g.nz - 1 + ZC - 1) / ZC;
+  return m;
+}
+
+// The z-march.  P supplies operand(idx) (the stencil operand at an interior node, idx in grid g), center(i,j,k,idx)
+// (prefetch of the thread's own data for output plane k) and consume(i,j,k,idx,C,out,acc0,acc1).
+template <typename T, typename P>
+__device__ __forceinline__ void zmarch(const Grid &g, const Stencil &st, P &pol, double &acc0, double &acc1,
+                                       T (*tile)[TY + 2][TX + 2]) {
+  constexpr int W = TX + 2, H = TY + 2, E = W * H, NL = (E + NT - 1) / NT;
+  const TileMap tm{(g.nx - 1 + TX - 1) / TX, (g.ny - 1 + TY - 1) / TY, 0};
+  const int t = xcd_remap(blockIdx.x, gridDim.x);
+  const int bx = t % tm.ntx;
+  const int rest = t / tm.ntx;
+  const int by = rest % tm.nty;
+  const int bz = rest / tm.nty;
+  const int i0 = 1 + bx * TX, j0 = 1 + by * TY, k0 = 1 + bz * ZC;
+  const int k1 = min(k0 + ZC, g.nz);  // output planes [k0, k1)
+  const int tid = threadIdx.x;
+  const int lx = tid % TX, ly = tid / TX;
+  const int i = i0 + lx, j = j0 + ly;
+  const bool active = (i < g.nx) && (j < g.ny);
+
+  // per fetch slot: column offset of its node (or -1 when outside the interior in x or y)
+  long long col[NL];
+#pragma unroll
+  for (int m = 0; m < NL; ++m) {
+    const int e = tid + m * NT;
+    col[m] = -1;
+    if (e < E) {
+      const int gi = i0 - 1 + e % W, gj = j0 - 1 + e / W;
+      if (gi >= 1 && gi < g.nx && gj >= 1 && gj < g.ny) col[m] = g.off + (long long)gj * g.sy + gi;
+    }
+  }
+  T reg[NL];
+  auto fetch = [&](int kk) {
+    const bool kin = (kk >= 1) && (kk < g.nz);
+#pragma unroll
+    for (int m = 0; m < NL; ++m) reg[m] = (kin && col[m] >= 0) ? pol.operand(col[m] + (long long)kk * g.sz) : T(0);
+  };
+
+  const T c0 = (T)st.c0, cx = (T)st.cx, cy = (T)st.cy, cz = (T)st.cz;
+  const T cxy = (T)st.cxy, cxz = (T)st.cxz, cyz = (T)st.cyz;
+  T Cm = 0, Xm = 0, Ym = 0, Cc = 0, Xc = 0, Yc = 0, Pc = 0;
+  const long long own = g.off + (long long)j * g.sy + i;
+
+  fetch(k0 - 1);
+  const int np = k1 - k0 + 2;
+  for (int step = 0; step < np; ++step) {
+    const int kk = k0 - 1 + step;
+    T(*tb)[TX + 2] = tile[step & 1];
+#pragma unroll
+    for (int m = 0; m < NL; ++m) {
+      const int e = tid + m * NT;
+      if (e < E) tb[e / W][e % W] = reg[m];
+    }
+    __syncthreads();
+    if (step + 1 < np) fetch(kk + 1);
+    const T c = tb[ly + 1][lx + 1];
+    const T x = tb[ly + 1][lx] + tb[ly + 1][lx + 2];
+    const T y = tb[ly][lx + 1] + tb[ly + 2][lx + 1];
+    const T d = (tb[ly][lx] + tb[ly][lx + 2]) + (tb[ly + 2][lx] + tb[ly + 2][lx + 2]);
+    if (step >= 2 && active) {
+      const T out = Pc + cz * (Cm + c) + cxz * (Xm + x) + cyz * (Ym + y);
+      pol.consume(i, j, kk - 1, own + (long long)(kk - 1) * g.sz, Cc, out, acc0, acc1);
+    }
+    if (step >= 1 && step + 1 < np && active) pol.center(i, j, kk, own + (long long)kk * g.sz);
+    Cm = Cc; Xm = Xc; Ym = Yc;
+    Cc = c; Xc = x; Yc = y;
+    Pc = c0 * c + cx * x + cy * y + cxy * d;
+  }
+}
+
+// ---------------------------------------------------------------------------------------------------------- passes
+
+template <typename T>
+struct PolA {
+  const T *r;
+  const T *pold;
+  T *pnew;
+  T beta;
+  bool first;
+  __device__ __forceinline__ T operand(long long idx) const { return first ? r[idx] : r[idx] + beta * pold[idx]; }
+  __device__ __forceinline__ void center(int, int, int, long long) {}
+  __device__ __forceinline__ void consume(int, int, int, long long idx, T c, T out, double &acc0, double &) {
+    pnew[idx] = c;
+    acc0 += (double)c * (double)out;
+  }
+};
+
+template <typename T>
+__global__ __launch_bounds__(NT) void cg_pass_a_kernel(Grid g, const T *__restrict__ r, T *p0, T *p1, Stencil st,
+                                                       const CgState *__restrict__ cs, double *partials) {
+  __shared__ T tile[2][TY + 2][TX + 2];
+  __shared__ double sh[NT / 64];
+  if (cs->done) return;
+  const int it = cs->iter;
+  PolA<T> pol;
+  pol.r = r;
+  pol.pnew = (it & 1) ? p1 : p0;
+  pol.pold = (it & 1) ? p0 : p1;
+  pol.first = (it == 0);
+  pol.beta = (T)cs->beta;
+  double a0 = 0.0, a1 = 0.0;
+  zmarch<T>(g, st, pol, a0, a1, tile);
+  const double s = block_sum<NT>(a0, sh);
+  if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
+template <typename T>
+struct PolB {
+  const T *p;
+  T *u;
+  T *r;
+  T alpha;
+  T pr, pu;
+  __device__ __forceinline__ T operand(long long idx) const { return p[idx]; }
+  __device__ __forceinline__ void center(int, int, int, long long idx) {
+    pr = r[idx];
+    pu = u[idx];
+  }
+  __device__ __forceinline__ void consume(int, int, int, long long idx, T c, T out, double &acc0, double &) {
+    const T rn = pr - alpha * out;
+    r[idx] = rn;
+    u[idx] = pu + alpha * c;
+    acc0 += (double)rn * (double)rn;
+  }
+};
+
+template <typename T>
+__global__ __launch_bounds__(NT) void cg_pass_b_kernel(Grid g, T *u, T *r, const T *p0, const T *p1, Stencil st,
+                                                       const CgState *__restrict__ cs, double *partials) {
+  __shared__ T tile[2][TY + 2][TX + 2];
+  __shared__ double sh[NT / 64];
+  if (cs->done) return;
+  const int it = cs->iter;
+  PolB<T> pol;
+  pol.p = (it & 1) ? p1 : p0;
+  pol.u = u;
+  pol.r = r;
+  pol.alpha = (T)cs->alpha;
+  pol.pr = 0;
+  pol.pu = 0;
+  double a0 = 0.0, a1 = 0.0;
+  zmarch<T>(g, st, pol, a0, a1, tile);
+  const double s = block_sum<NT>(a0, sh);
+  if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
+// r = b - M u.  u, b and r share the grid layout g (the library's pitched FP64 layout of the level).
+struct PolResid {
+  const double *u;
+  const double *b;
+  double *r;
+  double pb;
+  __device__ __forceinline__ double operand(long long idx) const { return u[idx]; }
+  __device__ __forceinline__ void center(int, int, int, long long idx) { pb = b[idx]; }
+  __device__ __forceinline__ void consume(int, int, int, long long idx, double, double out, double &acc0,
+                                          double &acc1) {
+    const double rn = pb - out;
+    r[idx] = rn;
+    acc0 += rn * rn;
+    acc1 += pb * pb;
+  }
+};
+
+__global__ __launch_bounds__(NT) void residual_kernel(Grid g, const double *u, const double *b, double *r, Stencil st,
+                                                      double *partials) {
+  __shared__ double tile[2][TY + 2][TX + 2];
+  __shared__ double sh[NT / 64];
+  PolResid pol{u, b, r, 0.0};
+  double a0 = 0.0, a1 = 0.0;
+  zmarch<double>(g, st, pol, a0, a1, tile);
+  const double s0 = block_sum<NT>(a0, sh);
+  __syncthreads();
+  const double s1 = block_sum<NT>(a1, sh);
+  if (threadIdx.x == 0) {
+    partials[blockIdx.x] = s0;
+    partials[gridDim.x + blockIdx.x] = s1;
+  }
+}
+
+// r32 = (float)(b - M u), d32 = 0; the FP32 arrays use their own layout g32.
+struct PolResidCast {
+  const double *u;
+  const double *b;
+  Grid g32;
+  float *r32;
+  float *d32;
+  double pb;
+  __device__ __forceinline__ double operand(long long idx) const { return u[idx]; }
+  __device__ __forceinline__ void center(int, int, int, long long idx) { pb = b[idx]; }
+  double acc2;  // sum of the squared FP32-rounded residual
+  __device__ __forceinline__ void consume(int i, int j, int k, long long, double, double out, double &acc0,
+                                          double &acc1) {
+    const double rn = pb - out;
+    const float rf = (float)rn;
+    const long long q = g32.at(i, j, k);
+    r32[q] = rf;
+    d32[q] = 0.0f;
+    acc0 += rn * rn;
+    acc1 += pb * pb;
+    acc2 += (double)rf * (double)rf;
+  }
+};
+
+__global__ __launch_bounds__(NT) void residual_cast_kernel(Grid g, const double *u, const double *b, Grid g32,
+                                                           float *r32, float *d32, Stencil st, double *partials) {
+  __shared__ double tile[2][TY + 2][TX + 2];
+  __shared__ double sh[NT / 64];
+  PolResidCast pol{u, b, g32, r32, d32, 0.0, 0.0};
+  double a0 = 0.0, a1 = 0.0;
+  zmarch<double>(g, st, pol, a0, a1, tile);
+  const double s0 = block_sum<NT>(a0, sh);
+  __syncthreads();
+  const double s1 = block_sum<NT>(a1, sh);
+  __syncthreads();
+  const double s2 = block_sum<NT>(pol.acc2, sh);
+  if (threadIdx.x == 0) {
+    partials[blockIdx.x] = s0;
+    partials[gridDim.x + blockIdx.x] = s1;
+    partials[2 * gridDim.x + blockIdx.x] = s2;
+  }
+}
+
+// y = M x with x and y in possibly different layouts.
+struct PolApply {
+  const double *x;
+  Grid gy;
+  double *y;
+  __device__ __forceinline__ double operand(long long idx) const { return x[idx]; }
+  __device__ __forceinline__ void center(int, int, int, long long) {}
+  __device__ __forceinline__ void consume(int i, int j, int k, long long, double, double out, double &, double &) {
+    y[gy.at(i, j, k)] = out;
+  }
+};
+
+__global__ __launch_bounds__(NT) void apply_kernel(Grid gx, const double *x, Grid gy, double *y, Stencil st) {
+  __shared__ double tile[2][TY + 2][TX + 2];
+  PolApply pol{x, gy, y};
+  double a0 = 0.0, a1 = 0.0;
+  zmarch<double>(gx, st, pol, a0, a1, tile);
+}
+
+// --------------------------------------------------------------------------------------------------------- finalize
+
+constexpr int FT = 256;
+
+__device__ double fixed_sum(const double *a, int n, double *sh) {
+  double v = 0.0;
+  for (int q = threadIdx.x; q < n; q += FT) v += a[q];
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int w = FT / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  const double s = sh[0];
+  __syncthreads();
+  return s;
+}
+
+__global__ __launch_bounds__(FT) void finalize_init_kernel(CgState *cs, const double *partials, int nparts, double tol,
+                                                           int max_iters, int hist_on) {
+  __shared__ double sh[FT];
+  const double rho = fixed_sum(partials, nparts, sh);
+  const double bb = fixed_sum(partials + nparts, nparts, sh);
+  if (threadIdx.x == 0) {
+    cs->rho = rho;
+    cs->rho_old = rho;
+    cs->bnorm2 = bb;
+    cs->stop2 = tol * tol * bb;
+    cs->alpha = 0.0;
+    cs->beta = 0.0;
+    cs->pq = 0.0;
+    cs->iter = 0;
+    cs->status = 0;
+    cs->max_iters = max_iters;
+    cs->hist_on = hist_on;
+    const bool finite = isfinite(rho) && isfinite(bb);
+    cs->done = (!finite || rho <= cs->stop2) ? 1 : 0;
+    if (!finite) cs->status = EXCMG_ERR_BREAKDOWN;
+    if (hist_on) cs->hist[0] = bb > 0.0 ? sqrt(rho / bb) : 0.0;
+  }
+}
+
+// Start of an outer step of FP32-in-FP64 iterative refinement.  partials = [r64.r64 | b.b | r32.r32] from
+// residual_cast.  outer: FP64 residual test ||r|| <= tol ||b||; inner: the FP32 CG on M d = r32 from d = 0, which
+// stops at ||r_inner|| <= max(eta ||r32||, theta tol ||b||): it reduces the residual no further than the outer test
+// needs (with margin theta), and no further than eta, the reduction one FP32 solve can deliver.
+__global__ __launch_bounds__(FT) void finalize_ir_kernel(CgState *outer, CgState *inner, const double *partials,
+                                                         int nparts, double tol, double eta, int outer_step,
+                                                         int max_outer, int max_inner) {
+  __shared__ double sh[FT];
+  const double r64 = fixed_sum(partials, nparts, sh);
+  const double bb = fixed_sum(partials + nparts, nparts, sh);
+  const double r32 = fixed_sum(partials + 2 * nparts, nparts, sh);
+  if (threadIdx.x == 0) {
+    outer->rho = r64;
+    outer->bnorm2 = bb;
+    outer->stop2 = tol * tol * bb;
+    outer->iter = outer_step;
+    outer->status = 0;
+    outer->done = 0;
+    if (!isfinite(r64) || !isfinite(bb)) {
+      outer->status = EXCMG_ERR_BREAKDOWN;
+      outer->done = 1;
+    } else if (r64 <= outer->stop2) {
+      outer->done = 1;
+    } else if (outer_step >= max_outer) {
+      outer->status = EXCMG_ERR_NOCONV;
+      outer->done = 1;
+    }
+    inner->rho = r32;
+    inner->rho_old = r32;
+    inner->bnorm2 = r32;
+    const double theta = 0.5;
+    inner->stop2 = fmax(eta * eta * r32, theta * theta * outer->stop2);
+    inner->alpha = 0.0;
+    inner->beta = 0.0;
+    inner->pq = 0.0;
+    inner->iter = 0;
+    inner->status = 0;
+    inner->max_iters = max_inner;
+    inner->hist_on = 0;
+    inner->done = (outer->done || !(r32 > 0.0)) ? 1 : 0;
+  }
+}
+
+__global__ __launch_bounds__(FT) void finalize_a_kernel(CgState *cs, const double *partials, int nparts) {
+  __shared__ double sh[FT];
+  if (cs->done) return;
+  const double pq = fixed_sum(partials, nparts, sh);
+  if (threadIdx.x == 0) {
+    cs->pq = pq;
+    if (!(pq > 0.0) || !isfinite(pq)) {
+      cs->status = EXCMG_ERR_BREAKDOWN;
+      cs->done = 1;
+    } else {
+      cs->alpha = cs->rho / pq;
+    }
+  }
+}
+
+__global__ __launch_bounds__(FT) void finalize_b_kernel(CgState *cs, const double *partials, int nparts) {
+  __shared__ double sh[FT];
+  if (cs->done) return;
+  const double rho = fixed_sum(partials, nparts, sh);
+  if (threadIdx.x == 0) {
+    cs->rho_old = cs->rho;
+    cs->rho = rho;
+    cs->beta = rho / cs->rho_old;
+    const int it = cs->iter + 1;
+    cs->iter = it;
+    if (cs->hist_on && it < EXCMG_MAX_HISTORY) cs->hist[it] = cs->bnorm2 > 0.0 ? sqrt(rho / cs->bnorm2) : 0.0;
+    if (!isfinite(rho)) {
+      cs->status = EXCMG_ERR_BREAKDOWN;
+      cs->done = 1;
+    } else if (rho <= cs->stop2) {
+      cs->done = 1;
+    } else if (it >= cs->max_iters) {
+      cs->status = EXCMG_ERR_NOCONV;
+      cs->done = 1;
+    }
+  }
+}
+
+// ------------------------------------------------------------------------------------------------------ small kernels
+
+__global__ void add_correction_kernel(Grid gu, double *u, Grid g32, const float *d) {
+  const int i = 1 + blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = 1 + blockIdx.y;
+  const int k = 1 + blockIdx.z;
+  if (i >= gu.nx) return;
+  u[gu.at(i, j, k)] += (double)d[g32.at(i, j, k)];
+}
+
+// ----------------------------------------------------------------------------------------------------------- DSOLVE
+
+constexpr int DT = 1024;
+
+__device__ __forceinline__ double stencil_direct(const Grid &g, const double *x, int i, int j, int k,
+                                                 const Stencil &s) {
+  auto X = [&](int a, int b, int c) -> double {
+    const int ii = i + a, jj = j + b, kk = k + c;
+    if (ii <= 0 || jj <= 0 || kk <= 0 || ii >= g.nx || jj >= g.ny || kk >= g.nz) return 0.0;
+    return x[g.at(ii, jj, kk)];
+  };
+  double v = s.c0 * X(0, 0, 0);
+  v += s.cx * (X(1, 0, 0) + X(-1, 0, 0));
+  v += s.cy * (X(0, 1, 0) + X(0, -1, 0));
+  v += s.cz * (X(0, 0, 1) + X(0, 0, -1));
+  v += s.cxy * ((X(1, 1, 0) + X(-1, 1, 0)) + (X(1, -1, 0) + X(-1, -1, 0)));
+  v += s.cxz * ((X(1, 0, 1) + X(-1, 0, 1)) + (X(1, 0, -1) + X(-1, 0, -1)));
+  v += s.cyz * ((X(0, 1, 1) + X(0, -1, 1)) + (X(0, 1, -1) + X(0, -1, -1)));
+  return v;
+}
+
+__device__ double dsum(double v, double *sh) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) sh[w] = v;
+  __syncthreads();
+  double t = 0.0;
+#pragma unroll
+  for (int q = 0; q < DT / 64; ++q) t += sh[q];
+  return t;  // every thread holds the same value
+}
+
+// CG on M u = b for a small grid, in one workgroup, until the recursive relative residual is 1e-15 or the iteration
+// cap: the direct solve of the two coarsest grids (Algorithm 1, first two lines), to rounding.
+__global__ __launch_bounds__(DT) void dsolve_kernel(Grid gu, double *u, Grid gb, const double *b, Grid gw, double *r,
+                                                    double *p, double *q, Stencil st, CgState *cs, int cap) {
+  __shared__ double sh[DT / 64];
+  const int nx1 = gu.nx - 1, ny1 = gu.ny - 1, nz1 = gu.nz - 1;
+  const int n = nx1 * ny1 * nz1;
+  auto coords = [&](int m, int &i, int &j, int &k) {
+    i = 1 + m % nx1;
+    const int t = m / nx1;
+    j = 1 + t % ny1;
+    k = 1 + t / ny1;
+  };
+  // r = b - M u (u's interior), p = r
+  double rr = 0.0, bb = 0.0;
+  for (int m = threadIdx.x; m < n; m += DT) {
+    int i, j, k;
+    coords(m, i, j, k);
+    const double bv = b[gb.at(i, j, k)];
+    const double rv = bv - stencil_direct(gu, u, i, j, k, st);
+    r[gw.at(i, j, k)] = rv;
+    p[gw.at(i, j, k)] = rv;
+    rr += rv * rv;
+    bb += bv * bv;
+  }
+  double rho = dsum(rr, sh);
+  const double bnorm2 = dsum(bb, sh);
+  const double stop2 = 1e-30 * bnorm2;
+  int it = 0;
+  int status = 0;
+  while (rho > stop2 && it < cap) {
+    __syncthreads();  // p complete
+    double pq = 0.0;
+    for (int m = threadIdx.x; m < n; m += DT) {
+      int i, j, k;
+      coords(m, i, j, k);
+      const double qv = stencil_direct(gw, p, i, j, k, st);
+      q[gw.at(i, j, k)] = qv;
+      pq += p[gw.at(i, j, k)] * qv;
+    }
+    pq = dsum(pq, sh);
+    if (!(pq > 0.0) || !isfinite(pq)) {
+      status = EXCMG_ERR_BREAKDOWN;
+      break;
+    }
+    const double alpha = rho / pq;
+    double rn = 0.0;
+    for (int m = threadIdx.x; m < n; m += DT) {
+      int i, j, k;
+      coords(m, i, j, k);
+      const long long w = gw.at(i, j, k);
+      u[gu.at(i, j, k)] += alpha * p[w];
+      const double rv = r[w] - alpha * q[w];
+      r[w] = rv;
+      rn += rv * rv;
+    }
+    const double rho_new = dsum(rn, sh);
+    const double beta = rho_new / rho;
+    rho = rho_new;
+    ++it;
+    __syncthreads();  // all reads of p (in q) are done before p is overwritten
+    for (int m = threadIdx.x; m < n; m += DT) {
+      int i, j, k;
+      coords(m, i, j, k);
+      const long long w = gw.at(i, j, k);
+      p[w] = r[w] + beta * p[w];
+    }
+  }
+  if (threadIdx.x == 0) {
+    cs->iter = it;
+    cs->rho = rho;
+    cs->bnorm2 = bnorm2;
+    cs->status = status;
+    cs->done = 1;
+  }
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------------------------------------------- launchers
+
+long long cg_partials_needed(const Grid &g) {
+  const TileMap m = tile_map(g);
+  return 3LL * m.ntx * m.nty * m.nzc + 64;
+}
+
+static int sweep_blocks(const Grid &g) {
+  const TileMap m = tile_map(g);
+  return m.ntx * m.nty * m.nzc;
+}
+
+void launch_residual(const Grid &gu, const double *u, const Grid &gb, const double *b, const Grid &gr, double *r,
+                     const Stencil &s, double *partials, int *nparts, hipStream_t st) {
+  (void)gb;
+  (void)gr;  // u, b, r share the level's layout
+  const int nb = sweep_blocks(gu);
+  residual_kernel<<<nb, NT, 0, st>>>(gu, u, b, r, s, partials);
+  *nparts = nb;
+}
+
+void launch_residual_cast(const Grid &gu, const double *u, const Grid &gb, const double *b, const Grid &g32,
+                          float *r32, float *d32, const Stencil &s, double *partials, int *nparts, hipStream_t st) {
+  (void)gb;
+  const int nb = sweep_blocks(gu);
+  residual_cast_kernel<<<nb, NT, 0, st>>>(gu, u, b, g32, r32, d32, s, partials);
+  *nparts = nb;
+}
+
+template <typename T>
+void launch_cg_pass_a(const Grid &g, const T *r, T *p0, T *p1, const Stencil &s, const CgState *cs, double *partials,
+                      int *nparts, hipStream_t st) {
+  const int nb = sweep_blocks(g);
+  cg_pass_a_kernel<T><<<nb, NT, 0, st>>>(g, r, p0, p1, s, cs, partials);
+  *nparts = nb;
+}
+
+template <typename T>
+void launch_cg_pass_b(const Grid &g, T *u, T *r, const T *p0, const T *p1, const Stencil &s, const CgState *cs,
+                      double *partials, int *nparts, hipStream_t st) {
+  const int nb = sweep_blocks(g);
+  cg_pass_b_kernel<T><<<nb, NT, 0, st>>>(g, u, r, p0, p1, s, cs, partials);
+  *nparts = nb;
+}
+
+template void launch_cg_pass_a<double>(const Grid &, const double *, double *, double *, const Stencil &,
+                                       const CgState *, double *, int *, hipStream_t);
+template void launch_cg_pass_a<float>(const Grid &, const float *, float *, float *, const Stencil &, const CgState *,
+                                      double *, int *, hipStream_t);
+template void launch_cg_pass_b<double>(const Grid &, double *, double *, const double *, const double *,
+                                       const Stencil &, const CgState *, double *, int *, hipStream_t);
+template void launch_cg_pass_b<float>(const Grid &, float *, float *, const float *, const float *, const Stencil &,
+                                      const CgState *, double *, int *, hipStream_t);
+
+void launch_finalize_init(CgState *cs, const double *partials, int nparts, double tol, int max_iters, int hist_on,
+                          hipStream_t st) {
+  finalize_init_kernel<<<1, FT, 0, st>>>(cs, partials, nparts, tol, max_iters, hist_on);
+}
+
+void launch_finalize_ir(CgState *outer, CgState *inner, const double *partials, int nparts, double tol, double eta,
+                        int outer_step, int max_outer, int max_inner, hipStream_t st) {
+  finalize_ir_kernel<<<1, FT, 0, st>>>(outer, inner, partials, nparts, tol, eta, outer_step, max_outer, max_inner);
+}
+
+void launch_finalize_a(CgState *cs, const double *partials, int nparts, hipStream_t st) {
+  finalize_a_kernel<<<1, FT, 0, st>>>(cs, partials, nparts);
+}
+
+void launch_finalize_b(CgState *cs, const double *partials, int nparts, hipStream_t st) {
+  finalize_b_kernel<<<1, FT, 0, st>>>(cs, partials, nparts);
+}
+
+void launch_add_correction(const Grid &gu, double *u, const Grid &g32, const float *d32, hipStream_t st) {
+  dim3 grid((gu.nx - 1 + 255) / 256, gu.ny - 1, gu.nz - 1);
+  add_correction_kernel<<<grid, 256, 0, st>>>(gu, u, g32, d32);
+}
+
+void launch_dsolve(const Grid &gu, double *u, const Grid &gb, const double *b, const Grid &gw, double *r, double *p,
+                   double *q, const Stencil &s, CgState *cs, hipStream_t st) {
+  const long long n = gu.interior();
+  int cap = (int)(4 * n + 200);
+  if (cap > 20000) cap = 20000;
+  dsolve_kernel<<<1, DT, 0, st>>>(gu, u, gb, b, gw, r, p, q, s, cs, cap);
+}
+
+void launch_apply(const Grid &gx, const double *x, const Grid &gy, double *y, const Stencil &s, hipStream_t st) {
+  const int nb = sweep_blocks(gx);
+  apply_kernel<<<nb, NT, 0, st>>>(gx, x, gy, y, s);
+}
+
+}  // namespace excmg

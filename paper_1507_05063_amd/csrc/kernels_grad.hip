@@ -1,0 +1,171 @@
+// Fourth-order compact gradient (Section 5.1) for gfx950.
+//
+// Along every grid line (including lines on the boundary) of length N cells, with v = du/dx (or y, z):
+//   v_0 = (-25 u_0 + 48 u_1 - 36 u_2 + 16 u_3 - 3 u_4) / (12 h),  v_N the mirror image with the opposite sign,
+//   v_{i-1} + 4 v_i + v_{i+1} = 3 (u_{i+1} - u_{i-1}) / h,  i = 1..N-1
+// (the paper's (1/6, 4/6, 1/6) system times 6).  The constant-coefficient Thomas factors m_1 = 4,
+// m_i = 4 - 1/m_{i-1} are shared by all lines; the host passes 1/m_i per axis.  Forward elimination stores the
+// modified right-hand sides in the output array, back substitution overwrites them with v.
+//
+// y and z lines: one thread per line, consecutive threads on consecutive x, so every step of the sweep is a
+// coalesced row access.  x lines: a workgroup of 64 threads takes 64 lines and walks x in chunks of 32 staged
+// through LDS (loads and stores coalesced along x; each thread then sweeps its own row of the chunk).
+#include "excmg_internal.h"
+
+namespace excmg {
+
+namespace {
+
+__device__ __forceinline__ double end0(double u0, double u1, double u2, double u3, double u4, double h) {
+  return (-25.0 * u0 + 48.0 * u1 - 36.0 * u2 + 16.0 * u3 - 3.0 * u4) / (12.0 * h);
+}
+
+// one line: u[idx0 + t*su], out[odx0 + t*so], t = 0..N
+__device__ __forceinline__ void line_solve(const double *__restrict__ u, long long idx0, long long su, double *out,
+                                           long long odx0, long long so, int N, double h,
+                                           const double *__restrict__ inv_m) {
+  auto U = [&](int t) { return u[idx0 + (long long)t * su]; };
+  const double v0 = end0(U(0), U(1), U(2), U(3), U(4), h);
+  const double vN = -end0(U(N), U(N - 1), U(N - 2), U(N - 3), U(N - 4), h);
+  out[odx0] = v0;
+  out[odx0 + (long long)N * so] = vN;
+  const double s3 = 3.0 / h;
+  double um = U(0), uc = U(1);
+  double dprev = 0.0;
+  for (int t = 1; t <= N - 1; ++t) {
+    const double up = U(t + 1);
+    double rhs = s3 * (up - um);
+    if (t == 1) rhs -= v0;
+    if (t == N - 1) rhs -= vN;
+    const double d = (rhs - (t > 1 ? dprev : 0.0)) * inv_m[t];
+    out[odx0 + (long long)t * so] = d;
+    dprev = d;
+    um = uc;
+    uc = up;
+  }
+  double vnext = out[odx0 + (long long)(N - 1) * so];
+  for (int t = N - 2; t >= 1; --t) {
+    const double v = out[odx0 + (long long)t * so] - inv_m[t] * vnext;
+    out[odx0 + (long long)t * so] = v;
+    vnext = v;
+  }
+}
+
+__global__ void grad_y_kernel(Grid gu, const double *__restrict__ u, Grid gd, double *uy, double hy,
+                              const double *__restrict__ inv_m) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int k = blockIdx.y;
+  if (i > gu.nx) return;
+  line_solve(u, gu.at(i, 0, k), gu.sy, uy, gd.at(i, 0, k), gd.sy, gu.ny, hy, inv_m);
+}
+
+__global__ void grad_z_kernel(Grid gu, const double *__restrict__ u, Grid gd, double *uz, double hz,
+                              const double *__restrict__ inv_m) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y;
+  if (i > gu.nx) return;
+  line_solve(u, gu.at(i, j, 0), gu.sz, uz, gd.at(i, j, 0), gd.sz, gu.nz, hz, inv_m);
+}
+
+constexpr int XL = 64;      // lines per workgroup
+constexpr int XC = 32;      // chunk length along x
+constexpr int XP = XC + 3;  // LDS row pitch of the u tile (odd in 8-byte words: no bank conflicts on row sweeps)
+constexpr int XQ = XC + 1;  // LDS row pitch of the output tile
+
+__global__ __launch_bounds__(XL) void grad_x_kernel(Grid gu, const double *__restrict__ u, Grid gd, double *ux,
+                                                    double hx, const double *__restrict__ inv_m) {
+  __shared__ double tu[XL][XP];
+  __shared__ double to[XL][XQ];
+  const int nlines = (gu.ny + 1) * (gu.nz + 1);
+  const int L0 = blockIdx.x * XL;
+  const int t = threadIdx.x;
+  const int N = gu.nx;
+  const int myline = L0 + t;
+  const bool act = myline < nlines;
+  const int mj = act ? myline % (gu.ny + 1) : 0, mk = act ? myline / (gu.ny + 1) : 0;
+  // ends (strided, 10 loads per line)
+  double v0 = 0.0, vN = 0.0;
+  if (act) {
+    const long long b = gu.at(0, mj, mk);
+    v0 = end0(u[b], u[b + 1], u[b + 2], u[b + 3], u[b + 4], hx);
+    vN = -end0(u[b + N], u[b + N - 1], u[b + N - 2], u[b + N - 3], u[b + N - 4], hx);
+    ux[gd.at(0, mj, mk)] = v0;
+    ux[gd.at(N, mj, mk)] = vN;
+  }
+  const double s3 = 3.0 / hx;
+  double dprev = 0.0;
+  // forward sweep over chunks of interior x: [1 + c*XC, min(N-1, (c+1)*XC)]
+  for (int x0 = 1; x0 <= N - 1; x0 += XC) {
+    const int x1 = min(N - 1, x0 + XC - 1);
+    const int w = x1 - x0 + 3;  // u from x0-1 .. x1+1
+    __syncthreads();
+    for (int e = t; e < XL * w; e += XL) {
+      // consecutive threads take consecutive x of one line: coalesced
+      const int ln = e / w, xx = e % w;
+      const int L = L0 + ln;
+      double v = 0.0;
+      if (L < nlines) v = u[gu.at(x0 - 1 + xx, L % (gu.ny + 1), L / (gu.ny + 1))];
+      tu[ln][xx] = v;
+    }
+    __syncthreads();
+    if (act) {
+      for (int x = x0; x <= x1; ++x) {
+        double rhs = s3 * (tu[t][x - x0 + 2] - tu[t][x - x0]);
+        if (x == 1) rhs -= v0;
+        if (x == N - 1) rhs -= vN;
+        const double d = (rhs - (x > 1 ? dprev : 0.0)) * inv_m[x];
+        to[t][x - x0] = d;
+        dprev = d;
+      }
+    }
+    __syncthreads();
+    const int wn = x1 - x0 + 1;
+    for (int e = t; e < XL * wn; e += XL) {
+      const int ln = e / wn, xx = e % wn;
+      const int L = L0 + ln;
+      if (L < nlines) ux[gd.at(x0 + xx, L % (gu.ny + 1), L / (gu.ny + 1))] = to[ln][xx];
+    }
+  }
+  // back substitution over the same chunks in reverse
+  const int nchunks = (N - 1 + XC - 1) / XC;
+  double vnext = 0.0;
+  for (int c = nchunks - 1; c >= 0; --c) {
+    const int x0 = 1 + c * XC;
+    const int x1 = min(N - 1, x0 + XC - 1);
+    const int wn = x1 - x0 + 1;
+    __syncthreads();
+    for (int e = t; e < XL * wn; e += XL) {
+      const int ln = e / wn, xx = e % wn;
+      const int L = L0 + ln;
+      to[ln][xx] = (L < nlines) ? ux[gd.at(x0 + xx, L % (gu.ny + 1), L / (gu.ny + 1))] : 0.0;
+    }
+    __syncthreads();
+    if (act) {
+      for (int x = x1; x >= x0; --x) {
+        const double d = to[t][x - x0];
+        const double v = (x == N - 1) ? d : d - inv_m[x] * vnext;
+        to[t][x - x0] = v;
+        vnext = v;
+      }
+    }
+    __syncthreads();
+    for (int e = t; e < XL * wn; e += XL) {
+      const int ln = e / wn, xx = e % wn;
+      const int L = L0 + ln;
+      if (L < nlines) ux[gd.at(x0 + xx, L % (gu.ny + 1), L / (gu.ny + 1))] = to[ln][xx];
+    }
+  }
+}
+
+}  // namespace
+
+void launch_gradient(const Grid &gu, const double *u, const Grid &gd, double *ux, double *uy, double *uz, double hx,
+                     double hy, double hz, const double *inv_m_x, const double *inv_m_y, const double *inv_m_z,
+                     hipStream_t st) {
+  const int nlines = (gu.ny + 1) * (gu.nz + 1);
+  grad_x_kernel<<<(nlines + XL - 1) / XL, XL, 0, st>>>(gu, u, gd, ux, hx, inv_m_x);
+  grad_y_kernel<<<dim3((gu.nx + 1 + 63) / 64, gu.nz + 1), 64, 0, st>>>(gu, u, gd, uy, hy, inv_m_y);
+  grad_z_kernel<<<dim3((gu.nx + 1 + 63) / 64, gu.ny + 1), 64, 0, st>>>(gu, u, gd, uz, hz, inv_m_z);
+}
+
+}  // namespace excmg

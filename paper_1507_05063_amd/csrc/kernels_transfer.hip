@@ -1,0 +1,304 @@
+// Level-transition and post-processing kernels of EXCMG for gfx950:
+//   rhs            level right-hand side b = -R f + A_IB g (eq. compact with the Dirichlet values eliminated)
+//   exp_finite     initial guess w_h = EXP_finite(u_2h, u_4h) (Sections 4.2.2 and 4.3)
+//   exp_true       sixth-order u~_h = EXP_true(u_h, u_2h) (eqs. t1 and chenlin, Section 4.3)
+//   set_boundary, copy, sample_interior: layout and boundary helpers
+#include <math.h>
+
+#include "excmg_internal.h"
+
+namespace excmg {
+
+namespace {
+
+__device__ __forceinline__ bool on_boundary(int i, int j, int k, int nx, int ny, int nz) {
+  return i == 0 || j == 0 || k == 0 || i == nx || j == ny || k == nz;
+}
+
+// ------------------------------------------------------------------------------------------------------------ rhs
+// One thread per interior node of the level grid gb; f and g are the finest dense arrays (layout gf) read at
+// stride s.  The 7-point average R f = (6 f_c + sum of face neighbours)/2 and, for neighbours on the boundary, the
+// compact operator's coefficient times g (a = 1/hx^2, ...): faces (4a-b-c) etc., edges (a+b)/2 etc.
+__global__ void rhs_kernel(Grid gf, const double *__restrict__ f, const double *__restrict__ g, int s, Grid gb,
+                           double *__restrict__ b, double a, double bb, double c) {
+  const int i = 1 + blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = 1 + blockIdx.y;
+  const int k = 1 + blockIdx.z;
+  const int nx = gb.nx, ny = gb.ny, nz = gb.nz;
+  if (i >= nx) return;
+  auto F = [&](int di, int dj, int dk) { return f[gf.at((i + di) * s, (j + dj) * s, (k + dk) * s)]; };
+  const double rf = 0.5 * (6.0 * F(0, 0, 0) + (F(1, 0, 0) + F(-1, 0, 0)) + (F(0, 1, 0) + F(0, -1, 0)) +
+                           (F(0, 0, 1) + F(0, 0, -1)));
+  double lg = 0.0;
+  const bool near = (i == 1 || j == 1 || k == 1 || i == nx - 1 || j == ny - 1 || k == nz - 1);
+  if (near) {
+    const double fx = 4.0 * a - bb - c, fy = 4.0 * bb - a - c, fz = 4.0 * c - a - bb;
+    const double exy = 0.5 * (a + bb), exz = 0.5 * (a + c), eyz = 0.5 * (bb + c);
+    for (int dk = -1; dk <= 1; ++dk)
+      for (int dj = -1; dj <= 1; ++dj)
+        for (int di = -1; di <= 1; ++di) {
+          const int ad = (di != 0) + (dj != 0) + (dk != 0);
+          if (ad == 0 || ad == 3) continue;
+          const int ii = i + di, jj = j + dj, kk = k + dk;
+          if (!on_boundary(ii, jj, kk, nx, ny, nz)) continue;
+          double w;
+          if (ad == 1) w = di ? fx : (dj ? fy : fz);
+          else w = (dk == 0) ? exy : ((dj == 0) ? exz : eyz);
+          lg += w * g[gf.at(ii * s, jj * s, kk * s)];
+        }
+  }
+  b[gb.at(i, j, k)] = -rf + lg;
+}
+
+// G sampled at stride s on the interior (the adjoint's level data), 0 on the boundary is never read
+__global__ void sample_interior_kernel(Grid gf, const double *__restrict__ G, int s, Grid gb, double *__restrict__ b) {
+  const int i = 1 + blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = 1 + blockIdx.y;
+  const int k = 1 + blockIdx.z;
+  if (i >= gb.nx) return;
+  b[gb.at(i, j, k)] = G[gf.at(i * s, j * s, k * s)];
+}
+
+__global__ void set_boundary_kernel(Grid gg, const double *__restrict__ g, int s, Grid gu, double *__restrict__ u,
+                                    int zero_interior) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y;
+  const int k = blockIdx.z;
+  if (i > gu.nx) return;
+  if (on_boundary(i, j, k, gu.nx, gu.ny, gu.nz)) {
+    u[gu.at(i, j, k)] = g ? g[gg.at(i * s, j * s, k * s)] : 0.0;
+  } else if (zero_interior) {
+    u[gu.at(i, j, k)] = 0.0;
+  }
+}
+
+__global__ void copy_kernel(Grid gs, const double *__restrict__ src, Grid gd, double *__restrict__ dst) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y;
+  const int k = blockIdx.z;
+  if (i > gs.nx) return;
+  dst[gd.at(i, j, k)] = src[gs.at(i, j, k)];
+}
+
+__global__ void check_finite_kernel(const double *__restrict__ a, long long n, int *flag) {
+  long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  bool bad = false;
+  for (; q < n; q += stride) bad |= !isfinite(a[q]);
+  if (bad) *flag = 1;
+}
+
+// ----------------------------------------------------------------------------------------------------- exp_finite
+// Quartic Lagrange weights (x128) at the odd fine offsets t = 1, 3, 5, 7 inside an interpolation cell whose known
+// values sit at the even offsets 0, 2, 4, 6, 8 (the cell is 2x2x2 elements of the 4h grid = 8 fine elements per
+// axis).  They are the Lagrange basis polynomials on the nodes 0..4 evaluated at t/2 = 0.5, 1.5, 2.5, 3.5.
+__constant__ double kQw[4][5] = {
+    {35.0 / 128, 140.0 / 128, -70.0 / 128, 28.0 / 128, -5.0 / 128},
+    {-5.0 / 128, 60.0 / 128, 90.0 / 128, -20.0 / 128, 3.0 / 128},
+    {3.0 / 128, -20.0 / 128, 90.0 / 128, 60.0 / 128, -5.0 / 128},
+    {-5.0 / 128, 28.0 / 128, -70.0 / 128, 140.0 / 128, 35.0 / 128},
+};
+
+constexpr int CXN = 4;               // interpolation cells per workgroup along x
+constexpr int EX2 = 4 * CXN + 1;     // 2h nodes along x in the workgroup's slab
+constexpr int EX4 = 2 * CXN + 1;     // 4h nodes along x
+constexpr int EXF = 8 * CXN + 1;     // fine nodes along x
+constexpr int ET = 256;
+
+// One workgroup per CXN x 1 x 1 interpolation cells.
+//  1. stage u_2h on the 5x5x(4CXN+1) 2h nodes and delta = u_2h - u_4h on the 3x3x(2CXN+1) 4h nodes in LDS;
+//  2. W = u_2h + delta_avg / 16 at every 2h node, where delta_avg is the mean of delta over the corners of the 4h
+//     element face/edge the node is the centre of.  At 4h nodes this is eq. (jiedian), at edge midpoints eq.
+//     (zhongdian), at face and element centres the mean over the 2 face / 4 space diagonals of eq. (zhongdian): all
+//     four rules are the same tri-linear interpolation of delta with the factor 1/16;
+//  3. tri-quartic interpolation (eq. inter) applied separably, x then y then z (the 604x125 cell matrix is the
+//     tensor product of the 1D quartic weights);
+//  4. write the cell's nodes; boundary nodes get g.
+__global__ __launch_bounds__(ET) void exp_finite_kernel(Grid g2, const double *__restrict__ u2, Grid g4,
+                                                        const double *__restrict__ u4, Grid gg,
+                                                        const double *__restrict__ gdat, int s, Grid gw,
+                                                        double *__restrict__ w) {
+  __shared__ double W[5][5][EX2];
+  __shared__ double D[3][3][EX4];
+  __shared__ double Wx[5][5][EXF];
+  __shared__ double Wxy[5][9][EXF];
+  const int ncx = gw.nx / 8, ncy = gw.ny / 8, ncz = gw.nz / 8;
+  const int cx0 = blockIdx.x * CXN;
+  const int cj = blockIdx.y, ck = blockIdx.z;
+  const int nc = min(CXN, ncx - cx0);  // cells in this workgroup
+  const int n2x = 4 * nc + 1, n4x = 2 * nc + 1, nfx = 8 * nc + 1;
+  const int tid = threadIdx.x;
+  const int I0 = 4 * cx0, J0 = 4 * cj, K0 = 4 * ck;  // 2h-grid origin of the slab
+  // 1. stage
+  for (int e = tid; e < 25 * n2x; e += ET) {
+    const int a = e % n2x, bc = e / n2x, b = bc % 5, c = bc / 5;
+    W[c][b][a] = u2[g2.at(I0 + a, J0 + b, K0 + c)];
+  }
+  __syncthreads();
+  for (int e = tid; e < 9 * n4x; e += ET) {
+    const int a = e % n4x, bc = e / n4x, b = bc % 3, c = bc / 3;
+    D[c][b][a] = W[2 * c][2 * b][2 * a] - u4[g4.at(I0 / 2 + a, J0 / 2 + b, K0 / 2 + c)];
+  }
+  __syncthreads();
+  // 2. extrapolate at the 2h nodes
+  for (int e = tid; e < 25 * n2x; e += ET) {
+    const int a = e % n2x, bc = e / n2x, b = bc % 5, c = bc / 5;
+    const int al = a >> 1, ah = (a + 1) >> 1, bl = b >> 1, bh = (b + 1) >> 1, cl = c >> 1, ch = (c + 1) >> 1;
+    const double d = ((D[cl][bl][al] + D[cl][bl][ah]) + (D[cl][bh][al] + D[cl][bh][ah])) +
+                     ((D[ch][bl][al] + D[ch][bl][ah]) + (D[ch][bh][al] + D[ch][bh][ah]));
+    W[c][b][a] += d * (1.0 / 128.0);  // (1/16) * (1/8) * sum over the 8 corner slots
+  }
+  __syncthreads();
+  // 3a. x
+  for (int e = tid; e < 25 * nfx; e += ET) {
+    const int xf = e % nfx, bc = e / nfx, b = bc % 5, c = bc / 5;
+    double v;
+    if (!(xf & 1)) {
+      v = W[c][b][xf >> 1];
+    } else {
+      const int base = (xf >> 3) * 4, t = (xf & 7) >> 1;
+      v = kQw[t][0] * W[c][b][base] + kQw[t][1] * W[c][b][base + 1] + kQw[t][2] * W[c][b][base + 2] +
+          kQw[t][3] * W[c][b][base + 3] + kQw[t][4] * W[c][b][base + 4];
+    }
+    Wx[c][b][xf] = v;
+  }
+  __syncthreads();
+  // 3b. y
+  for (int e = tid; e < 45 * nfx; e += ET) {
+    const int xf = e % nfx, yc = e / nfx, yf = yc % 9, c = yc / 9;
+    double v;
+    if (!(yf & 1)) {
+      v = Wx[c][yf >> 1][xf];
+    } else {
+      const int t = yf >> 1;
+      v = kQw[t][0] * Wx[c][0][xf] + kQw[t][1] * Wx[c][1][xf] + kQw[t][2] * Wx[c][2][xf] + kQw[t][3] * Wx[c][3][xf] +
+          kQw[t][4] * Wx[c][4][xf];
+    }
+    Wxy[c][yf][xf] = v;
+  }
+  __syncthreads();
+  // 3c. z and 4. write: a workgroup owns offsets [0,8) on each axis, plus offset 8 at the grid's far faces
+  const bool lastx = (cx0 + nc == ncx), lasty = (cj == ncy - 1), lastz = (ck == ncz - 1);
+  const int ox = lastx ? nfx : nfx - 1, oy = lasty ? 9 : 8, oz = lastz ? 9 : 8;
+  const int gi0 = 8 * cx0, gj0 = 8 * cj, gk0 = 8 * ck;
+  for (int e = tid; e < ox * oy * oz; e += ET) {
+    const int xf = e % ox, yz = e / ox, yf = yz % oy, zf = yz / oy;
+    const int gi = gi0 + xf, gj = gj0 + yf, gk = gk0 + zf;
+    double v;
+    if (on_boundary(gi, gj, gk, gw.nx, gw.ny, gw.nz)) {
+      v = gdat ? gdat[gg.at(gi * s, gj * s, gk * s)] : 0.0;
+    } else if (!(zf & 1)) {
+      v = Wxy[zf >> 1][yf][xf];
+    } else {
+      const int t = zf >> 1;
+      v = kQw[t][0] * Wxy[0][yf][xf] + kQw[t][1] * Wxy[1][yf][xf] + kQw[t][2] * Wxy[2][yf][xf] +
+          kQw[t][3] * Wxy[3][yf][xf] + kQw[t][4] * Wxy[4][yf][xf];
+    }
+    w[gw.at(gi, gj, gk)] = v;
+  }
+}
+
+// ------------------------------------------------------------------------------------------------------- exp_true
+// u~ = u_h + delta_avg / 15 where delta = u_h - u_2h at the 2h nodes and delta_avg its mean over the corners of the
+// 2h edge/face/element the node is the midpoint of: eq. (t1) at 2h nodes, eq. (chenlin) at edge midpoints, and its
+// mean over the 2 face / 4 space diagonals at face / element centres.
+__global__ void exp_true_kernel(Grid gh, const double *__restrict__ uh, Grid g2, const double *__restrict__ u2, Grid gt,
+                                double *__restrict__ ut) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y;
+  const int k = blockIdx.z;
+  if (i > gh.nx) return;
+  const int il = i & ~1, ih = (i & 1) ? i + 1 : i;
+  const int jl = j & ~1, jh = (j & 1) ? j + 1 : j;
+  const int kl = k & ~1, kh = (k & 1) ? k + 1 : k;
+  auto dl = [&](int a, int b, int c) { return uh[gh.at(a, b, c)] - u2[g2.at(a >> 1, b >> 1, c >> 1)]; };
+  const double d = ((dl(il, jl, kl) + dl(ih, jl, kl)) + (dl(il, jh, kl) + dl(ih, jh, kl))) +
+                   ((dl(il, jl, kh) + dl(ih, jl, kh)) + (dl(il, jh, kh) + dl(ih, jh, kh)));
+  ut[gt.at(i, j, k)] = uh[gh.at(i, j, k)] + d * (1.0 / 120.0);  // (1/15) * (1/8) * sum over the 8 corner slots
+}
+
+// ------------------------------------------------------------------------------------------------------- adjoint
+// Gather form of the transposes, one thread per node of the finest grid (dense outputs):
+//   dLdf(n) = -(3 lam_n [n interior] + 1/2 * sum of lam over the interior face neighbours of n)
+//   dLdg(n) = sum over interior neighbours m of A's coefficient for the offset m - n, times lam_m, plus G(n),
+//             on boundary nodes; 0 inside.
+__global__ void adjoint_kernel(Grid gl, const double *__restrict__ lam, Grid gd, const double *__restrict__ G,
+                               double *__restrict__ dLdf, double *__restrict__ dLdg, double a, double bb, double c) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y;
+  const int k = blockIdx.z;
+  const int nx = gl.nx, ny = gl.ny, nz = gl.nz;
+  if (i > nx) return;
+  auto L = [&](int ii, int jj, int kk) -> double {
+    if (ii <= 0 || jj <= 0 || kk <= 0 || ii >= nx || jj >= ny || kk >= nz) return 0.0;
+    return lam[gl.at(ii, jj, kk)];
+  };
+  const double rt = 3.0 * L(i, j, k) +
+                    0.5 * ((L(i + 1, j, k) + L(i - 1, j, k)) + (L(i, j + 1, k) + L(i, j - 1, k)) +
+                           (L(i, j, k + 1) + L(i, j, k - 1)));
+  const long long q = gd.at(i, j, k);
+  dLdf[q] = -rt;
+  if (!on_boundary(i, j, k, nx, ny, nz)) {
+    dLdg[q] = 0.0;
+    return;
+  }
+  const double fx = 4.0 * a - bb - c, fy = 4.0 * bb - a - c, fz = 4.0 * c - a - bb;
+  const double exy = 0.5 * (a + bb), exz = 0.5 * (a + c), eyz = 0.5 * (bb + c);
+  double s = fx * (L(i + 1, j, k) + L(i - 1, j, k)) + fy * (L(i, j + 1, k) + L(i, j - 1, k)) +
+             fz * (L(i, j, k + 1) + L(i, j, k - 1));
+  s += exy * ((L(i + 1, j + 1, k) + L(i - 1, j + 1, k)) + (L(i + 1, j - 1, k) + L(i - 1, j - 1, k)));
+  s += exz * ((L(i + 1, j, k + 1) + L(i - 1, j, k + 1)) + (L(i + 1, j, k - 1) + L(i - 1, j, k - 1)));
+  s += eyz * ((L(i, j + 1, k + 1) + L(i, j - 1, k + 1)) + (L(i, j + 1, k - 1) + L(i, j - 1, k - 1)));
+  dLdg[q] = s + G[q];
+}
+
+inline dim3 node_grid(const Grid &g, int bx) { return dim3((g.nx + 1 + bx - 1) / bx, g.ny + 1, g.nz + 1); }
+inline dim3 interior_grid(const Grid &g, int bx) { return dim3((g.nx - 1 + bx - 1) / bx, g.ny - 1, g.nz - 1); }
+
+}  // namespace
+
+void launch_rhs(const Grid &gf, const double *f, const double *g, int stride, const Grid &gb, double *b, double hx,
+                double hy, double hz, hipStream_t st) {
+  rhs_kernel<<<interior_grid(gb, 256), 256, 0, st>>>(gf, f, g, stride, gb, b, 1.0 / (hx * hx), 1.0 / (hy * hy),
+                                                     1.0 / (hz * hz));
+}
+
+void launch_sample_interior(const Grid &gf, const double *G, int stride, const Grid &gb, double *b, hipStream_t st) {
+  sample_interior_kernel<<<interior_grid(gb, 256), 256, 0, st>>>(gf, G, stride, gb, b);
+}
+
+void launch_set_boundary(const Grid &gg, const double *g, int stride, const Grid &gu, double *u, int zero_interior,
+                         hipStream_t st) {
+  set_boundary_kernel<<<node_grid(gu, 256), 256, 0, st>>>(gg, g, stride, gu, u, zero_interior);
+}
+
+void launch_exp_finite(const Grid &g2, const double *u2, const Grid &g4, const double *u4, const Grid &gg,
+                       const double *g, int stride, const Grid &gw, double *w, hipStream_t st) {
+  const int ncx = gw.nx / 8, ncy = gw.ny / 8, ncz = gw.nz / 8;
+  dim3 grid((ncx + CXN - 1) / CXN, ncy, ncz);
+  exp_finite_kernel<<<grid, ET, 0, st>>>(g2, u2, g4, u4, gg, g, stride, gw, w);
+}
+
+void launch_exp_true(const Grid &gh, const double *uh, const Grid &g2, const double *u2, const Grid &gt, double *ut,
+                     hipStream_t st) {
+  exp_true_kernel<<<node_grid(gh, 256), 256, 0, st>>>(gh, uh, g2, u2, gt, ut);
+}
+
+void launch_copy(const Grid &gs, const double *src, const Grid &gd, double *dst, hipStream_t st) {
+  copy_kernel<<<node_grid(gs, 256), 256, 0, st>>>(gs, src, gd, dst);
+}
+
+void launch_check_finite(const double *a, long long n, int *flag, hipStream_t st) {
+  long long blocks = (n + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  if (blocks < 1) blocks = 1;
+  check_finite_kernel<<<(int)blocks, 256, 0, st>>>(a, n, flag);
+}
+
+void launch_adjoint_transposes(const Grid &gl, const double *lam, const Grid &gd, const double *G, double *dLdf,
+                               double *dLdg, double hx, double hy, double hz, hipStream_t st) {
+  adjoint_kernel<<<node_grid(gl, 256), 256, 0, st>>>(gl, lam, gd, G, dLdf, dLdg, 1.0 / (hx * hx), 1.0 / (hy * hy),
+                                                     1.0 / (hz * hz));
+}
+
+}  // namespace excmg

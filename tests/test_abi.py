@@ -1,0 +1,134 @@
+"""C-ABI checks that need no GPU: the library loads, exports every declared symbol, and its host-only entry points
+(level plan, workspace size, argument validation, error strings) behave as documented in include/excmg.h."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from conftest import ROOT
+
+HEADER = os.path.join(ROOT, "include", "excmg.h")
+
+
+@pytest.fixture(scope="module")
+def abi():
+    from paper_1507_05063_amd import _lib
+
+    if not os.path.exists(_lib.LIB_PATH):
+        from paper_1507_05063_amd import build
+
+        build.build()
+    return _lib
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"^\s*(?:int|void|const char \*)\s*\**\s*(excmg_\w+)\s*\(", src, flags=re.M)
+    return sorted(set(names))
+
+
+def test_header_declares_the_path():
+    names = declared_functions()
+    for required in ["excmg_setup", "excmg_solve", "excmg_gradient", "excmg_adjoint", "excmg_solve_batched",
+                     "excmg_workspace_bytes", "excmg_destroy", "excmg_strerror"]:
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol(abi):
+    L = ctypes.CDLL(abi.LIB_PATH)
+    missing = [n for n in declared_functions() if not hasattr(L, n)]
+    assert not missing, missing
+
+
+def _plan(abi, n, nc=(0, 0, 0), tol=1e-10, box=(1, 1, 1), precision=0):
+    import paper_1507_05063_amd as ex
+
+    return ex.plan(n, nc, box, tol)
+
+
+@pytest.mark.parametrize("n,levels,nc", [
+    ((64, 64, 64), 5, (4, 4, 4)),            # uniform levels 4 -> 64
+    ((512, 512, 512), 8, (4, 4, 4)),         # 4 -> 512, 8 grids
+    ((1024, 512, 256), 8, (8, 4, 2)),        # unequal meshsizes, coarsest 8x4x2
+    ((32, 96, 192), 5, (2, 6, 12)),          # uneven batch shape: N/16
+    ((256, 256, 256), 7, (4, 4, 4)),
+    ((6, 10, 14), 1, (6, 10, 14)),           # halves would be odd: one grid, solved directly
+    ((20, 12, 36), 2, (10, 6, 18)),
+    ((4, 4, 4), 1, (4, 4, 4)),
+])
+def test_automatic_level_plan(abi, n, levels, nc):
+    assert _plan(abi, n) == (levels, nc)
+
+
+def test_explicit_coarsest(abi):
+    assert _plan(abi, (128, 64, 32), (8, 4, 2)) == (5, (8, 4, 2))
+    assert _plan(abi, (8, 8, 8), (2, 2, 2)) == (3, (2, 2, 2))
+
+
+@pytest.mark.parametrize("n,nc", [((12, 12, 12), (3, 3, 3)),   # odd coarsest under a three-grid cascade
+                                  ((16, 16, 16), (3, 3, 3)),   # 3 * 2^L never 16
+                                  ((16, 16, 16), (4, 4, 2)),   # axes disagree on L
+                                  ((1, 4, 4), (0, 0, 0))])
+def test_bad_shapes(abi, n, nc):
+    import paper_1507_05063_amd as ex
+
+    with pytest.raises(ex.ExcmgError) as e:
+        ex.plan(n, nc)
+    assert e.value.code == abi.ERR_SHAPE
+
+
+def test_bad_arguments(abi):
+    import paper_1507_05063_amd as ex
+
+    for kw in [dict(tol=0.0), dict(tol=-1.0), dict(box=(1, 0, 1)), dict(tol=float("nan"))]:
+        with pytest.raises(ex.ExcmgError) as e:
+            ex.plan((16, 16, 16), (0, 0, 0), kw.get("box", (1, 1, 1)), kw.get("tol", 1e-10))
+        assert e.value.code == abi.ERR_ARG
+    L = abi.lib()
+    assert L.excmg_plan(None, None, None) == abi.ERR_ARG
+
+
+def test_workspace_bytes_scale(abi):
+    import paper_1507_05063_amd as ex
+
+    b64 = ex.workspace_bytes((512, 512, 512))
+    b32 = ex.workspace_bytes((512, 512, 512), precision=ex.FP32_IR)
+    node = 513 ** 3 * 8
+    # four finest FP64 work vectors plus the cascade's solutions (about 8/7 of a finest array), pitched rows
+    assert 5.0 * node < b64 < 5.6 * node
+    assert b32 - b64 > 1.9 * node  # four FP32 vectors more
+    assert ex.workspace_bytes((64, 64, 64)) < b64
+
+
+def test_setup_rejects_bad_workspace(abi):
+    p = abi.Problem()
+    for d in range(3):
+        p.box[d] = 1.0
+        p.n[d] = 16
+    p.tol = 1e-10
+    h = ctypes.c_void_p(0)
+    L = abi.lib()
+    assert L.excmg_setup(ctypes.byref(p), None, 0, None, ctypes.byref(h)) == abi.ERR_WORKSPACE
+    assert L.excmg_setup(ctypes.byref(p), ctypes.c_void_p(256), 10, None, ctypes.byref(h)) == abi.ERR_WORKSPACE
+    assert L.excmg_setup(ctypes.byref(p), ctypes.c_void_p(4096 + 8), 1 << 40, None, ctypes.byref(h)) == \
+        abi.ERR_WORKSPACE
+    assert not h.value
+
+
+def test_strerror(abi):
+    L = abi.lib()
+    for code in [0, -1, -2, -3, -4, -5, -6, -7]:
+        assert L.excmg_strerror(code)
+    assert L.excmg_strerror(-99) == b"unknown error code"
+
+
+def test_product_path_does_not_import_the_oracle():
+    """The GPU binding and the oracle share nothing: no import of oracle/ anywhere in the package or the C sources."""
+    pkg = os.path.join(ROOT, "paper_1507_05063_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for fn in files:
+            if fn.endswith((".py", ".hip", ".h", ".cpp")):
+                txt = open(os.path.join(dirpath, fn)).read()
+                assert "import oracle" not in txt and "from oracle" not in txt and "oracle.h" not in txt, fn

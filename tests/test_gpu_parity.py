@@ -1,0 +1,219 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle, element by element on the same seeded inputs.
+
+Tolerances (FP64): single steps (operator, right-hand side, EXP_finite, EXP_true, gradient) agree to rounding:
+max |gpu - oracle| <= 1e-13 * max |oracle| (a few ulps of the summed terms; the two sides add the same terms in a
+different order).  Whole solves: relative L2 difference <= 1e-12 (the stated parity bar), after matching the per-grid
+CG iteration counts: the oracle is re-run with the GPU's counts forced (several iterates satisfy the stopping test;
+ties at the threshold are the only source of count differences, and the free-running counts must agree within one).
+"""
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def ex():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1507_05063_amd as m
+
+    return m
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def host(t):
+    return t.detach().to("cpu").numpy()
+
+
+def relmax(a, b):
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+def rel2(a, b):
+    return float(np.linalg.norm((a - b).ravel()) / max(np.linalg.norm(b.ravel()), 1e-300))
+
+
+RNG = np.random.default_rng(2024)
+
+
+def rnd(n):
+    return RNG.standard_normal((n[2] + 1, n[1] + 1, n[0] + 1))
+
+
+# ------------------------------------------------------------------------------------------------------ single steps
+
+@pytest.mark.parametrize("n,box", [((67, 35, 20), (1.0, 0.6, 1.7)),   # ragged against 64x4x16 tiles
+                                   ((4, 4, 4), (1.0, 1.0, 1.0)),
+                                   ((130, 9, 33), (2.0, 0.1, 0.5)),
+                                   ((2, 2, 2), (1.0, 1.0, 1.0))])    # one interior node
+def test_operator(ex, orc, n, box):
+    x = rnd(n)
+    y = host(ex.op_apply(dev(x), n, box))
+    ref = orc.apply_M(x, box)
+    assert relmax(y, ref) <= 1e-13
+
+
+@pytest.mark.parametrize("n,box", [((40, 24, 16), (1.0, 0.7, 1.3)), ((5, 66, 7), (1.0, 1.0, 1.0))])
+def test_rhs(ex, orc, n, box):
+    f = rnd(n)
+    g = rnd(n)
+    g_nan = g.copy()
+    g_nan[1:-1, 1:-1, 1:-1] = np.nan  # interior of g must never be read
+    b = host(ex.op_rhs(dev(f), dev(g_nan), n, box))
+    ref = orc.rhs(f, g, box)
+    assert relmax(b, ref) <= 1e-13
+
+
+@pytest.mark.parametrize("n", [(16, 8, 24), (72, 40, 8), (8, 8, 8)])
+def test_exp_finite(ex, orc, n):
+    u2 = rnd(tuple(v // 2 for v in n))
+    u4 = rnd(tuple(v // 4 for v in n))
+    g = rnd(n)
+    w = host(ex.op_exp_finite(dev(u2), dev(u4), dev(g), n))
+    ref = orc.exp_finite(u2, u4, g)
+    assert relmax(w, ref) <= 1e-13
+
+
+@pytest.mark.parametrize("n", [(16, 8, 24), (70, 6, 10), (2, 2, 2)])
+def test_exp_true(ex, orc, n):
+    uh = rnd(n)
+    u2 = rnd(tuple(v // 2 for v in n))
+    ut = host(ex.op_exp_true(dev(uh), dev(u2), n))
+    ref = orc.exp_true(uh, u2)
+    assert relmax(ut, ref) <= 1e-13
+
+
+@pytest.mark.parametrize("n,box", [((20, 12, 36), (1.0, 0.5, 2.0)), ((4, 4, 4), (1.0, 1.0, 1.0)),
+                                   ((130, 66, 8), (1.0, 1.0, 1.0))])
+def test_gradient(ex, orc, n, box):
+    u = rnd(n)
+    s = ex.Solver(n, box, 1e-10)
+    got = s.gradient(dev(u))
+    ref = orc.gradient(u, box)
+    for a, b in zip(got, ref):
+        assert relmax(host(a), b) <= 1e-13
+
+
+# ----------------------------------------------------------------------------------------------------- whole solves
+
+def solve_both(ex, orc, p, n, nc, tol, want_ext=True, precision=None, box=None):
+    box = p.box if box is None else box
+    f, g, u = synth.sample(p, n)
+    prec = ex.FP64 if precision is None else precision
+    s = ex.Solver(n, box, tol, n_coarse=nc, precision=prec)
+    ug, ueg, st = s.solve(dev(f), dev(g), want_ext=want_ext)
+    free = orc.excmg(f, g, box, s.n_coarse, tol, want_ext=want_ext)
+    return f, g, u, s, host(ug), (host(ueg) if ueg is not None else None), st, free
+
+
+@pytest.mark.parametrize("case", ["cube64", "aniso", "ex1_64", "small3", "two_level", "one_level"])
+def test_solve_parity(ex, orc, case):
+    p, n, nc, tol = {
+        "cube64": (synth.smooth(0), (64, 64, 64), (4, 4, 4), 1e-10),
+        "aniso": (synth.smooth(0), (128, 64, 32), (8, 4, 2), 1e-10),
+        "ex1_64": (synth.example(1), (64, 64, 64), (4, 4, 4), 1e-14),
+        "small3": (synth.smooth(3, (0.7, 1.2, 0.9)), (8, 8, 8), (2, 2, 2), 1e-12),
+        "two_level": (synth.example(2), (8, 8, 8), (4, 4, 4), 1e-10),
+        "one_level": (synth.example(3), (6, 10, 14), (6, 10, 14), 1e-10),
+    }[case]
+    f, g, u, s, ug, ueg, st, free = solve_both(ex, orc, p, n, nc, tol, want_ext=s_levels_ok(n, nc))
+    gi = np.array(st["iters"], dtype=np.int32)
+    assert np.all(np.abs(gi - free["iters"]) <= 1), (gi, free["iters"])
+    ref = orc.excmg(f, g, p.box, s.n_coarse, tol, fixed_iters=gi, want_ext=ueg is not None)
+    assert rel2(ug, ref["u"]) <= 1e-12
+    if ueg is not None:
+        assert rel2(ueg, ref["ut"]) <= 1e-12
+    # the boundary is g exactly
+    mask = synth.boundary_mask(n)
+    assert np.array_equal(ug[mask], g[mask])
+    for l in range(2, st["levels"]):
+        assert st["relres"][l] <= tol
+
+
+def s_levels_ok(n, nc):
+    return any(a != b for a, b in zip(n, nc))
+
+
+def test_solve_orders_and_gradient(ex, orc):
+    """Fourth order for u_h and its gradient, sixth for the extrapolated solution (config: seeded smooth field)."""
+    p = synth.smooth(0)
+    errs = []
+    for N in (16, 32, 64):
+        n = (N, N, N)
+        f, g, u = synth.sample(p, n)
+        s = ex.Solver(n, p.box, 1e-12)
+        ug, ue, st = s.solve(dev(f), dev(g), want_ext=True)
+        gx = [host(t) for t in s.gradient(ug)]
+        ge = synth.exact_gradient(p, n)
+        errs.append((np.max(np.abs(host(ug) - u)), np.max(np.abs(host(ue) - u)),
+                     max(np.max(np.abs(a - b)) for a, b in zip(gx, ge))))
+    o = [np.log2(errs[1][q] / errs[2][q]) for q in range(3)]
+    assert 3.8 < o[0] < 4.2 and 5.3 < o[1] < 6.6 and 3.7 < o[2] < 4.3
+
+
+def test_history_and_timing(ex):
+    p = synth.smooth(0)
+    n = (64, 64, 64)
+    f, g, _ = synth.sample(p, n)
+    s = ex.Solver(n, p.box, 1e-10, history=True, timing=True)
+    _, _, st = s.solve(dev(f), dev(g))
+    h = st["history"]
+    assert len(h) == st["iters"][-1] + 1 and h[-1] <= 1e-10 < h[-2]
+    assert st["kernel_calls_finest"]["cg_a"] == st["iters"][-1]
+    assert st["kernel_calls_finest"]["cg_b"] == st["iters"][-1]
+    assert st["kernel_ms"]["cg_b"] > 0
+
+
+def test_determinism(ex):
+    p = synth.smooth(1)
+    n = (64, 32, 32)
+    f, g, _ = synth.sample(p, n)
+    s = ex.Solver(n, p.box, 1e-10)
+    a, _, _ = s.solve(dev(f), dev(g))
+    a = host(a)
+    b, _, _ = s.solve(dev(f), dev(g))
+    assert np.array_equal(a, host(b))
+
+
+def test_nonfinite_and_noconv(ex):
+    p = synth.smooth(0)
+    n = (32, 32, 32)
+    f, g, _ = synth.sample(p, n)
+    f[5, 6, 7] = np.nan
+    s = ex.Solver(n, p.box, 1e-10)
+    with pytest.raises(ex.ExcmgError) as e:
+        s.solve(dev(f), dev(g))
+    assert e.value.code == -3
+    f, g, _ = synth.sample(p, n)
+    s = ex.Solver(n, p.box, 1e-14, max_iters=2)
+    u, _, st = s.solve(dev(f), dev(g), allow_noconv=True)
+    assert st["status"] == -4 and st["iters"][-1] == 2
+
+
+# -------------------------------------------------------------------------------------------------- full-size cases
+
+def test_config2_512_fp64_full_oracle(ex, orc):
+    """512^3 cells, 8 grids from 4^3, tol 1e-10, FP64: the whole oracle cascade at full size with the GPU's
+    iteration counts, compared on every node."""
+    p = synth.smooth(0)
+    n = (512, 512, 512)
+    f, g, u = synth.sample(p, n)
+    s = ex.Solver(n, p.box, 1e-10)
+    fd, gd = dev(f), dev(g)
+    ug, _, st = s.solve(fd, gd)
+    del fd, gd
+    ug = host(ug)
+    orc.set_threads(max(1, min(16, len(__import__("os").sched_getaffinity(0)))))
+    ref = orc.excmg(f, g, p.box, (4, 4, 4), 1e-10, fixed_iters=np.array(st["iters"], dtype=np.int32))
+    assert rel2(ug, ref["u"]) <= 1e-12
+    assert ref["relres"][-1] <= 1e-10 * 1.5
+    err = np.max(np.abs(ug - u))
+    assert err < 5e-10  # fourth-order discretisation error of this field at h = 1/512
