@@ -67,6 +67,8 @@ def main():
     print(f"# workload {N}^3 cells, inputs resident: {f.numel() * 16 / 1e9:.2f} GB", file=sys.stderr, flush=True)
 
     s = ex.Solver(n, p.box, args.tol, timing=True)
+    zc64 = s.autotune()
+    print(f"# autotuned z chunks (A, B) per grid: {[z[:2] for z in zc64]}", file=sys.stderr, flush=True)
     u = s.empty()
     ue = s.empty()
     grads = (s.empty(), s.empty(), s.empty())
@@ -127,6 +129,7 @@ def main():
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
                      "avg_launch_ms": round(avg_ms, 4), "bytes_per_launch": BYTES_PER_UNKNOWN[dom] * nI},
         "iters_per_grid": stats[-1]["iters"],
+        "autotuned_z_chunks": [list(z[:2]) for z in zc64],
         "ms_per_grid": [round(v, 3) for v in stats[-1]["ms_level"]],
         "solve_ms_fp64": round(stats[-1]["ms_total"], 3),
         "finest_cg_sweeps_gunknown_iters_s": round(guis_fin_sweeps, 2) if guis_fin_sweeps else None,
@@ -135,6 +138,7 @@ def main():
 
     if not args.no_mixed:
         sm = ex.Solver(n, p.box, args.tol, precision=ex.FP32_IR, timing=False)
+        zc32 = sm.autotune()
         um = sm.empty()
         for _ in range(max(1, args.warmup)):
             sm.solve(f, g, u=um)

@@ -59,10 +59,10 @@ extern "C" {
 #define EXCMG_K_CG_B32 3
 #define EXCMG_K_RESID 4     /* r = b - M u (+ cast for the FP32 inner solve), partial sums */
 #define EXCMG_K_FINALIZE 5  /* fixed-order reduction of block partials, CG scalars */
-#define EXCMG_K_RHS 6       /* right-hand side assembly per level */
+#define EXCMG_K_RHS 6       /* right-hand side assembly (excmg_op_rhs; the solver forms b inside its kernels) */
 #define EXCMG_K_EXP_FINITE 7
 #define EXCMG_K_EXP_TRUE 8
-#define EXCMG_K_DSOLVE 9
+#define EXCMG_K_DSOLVE 9     /* single-workgroup CG: direct solves, and the relaxation of grids <= 8000 unknowns */
 #define EXCMG_K_GRADIENT 10
 #define EXCMG_K_OTHER 11
 #define EXCMG_K_CLASSES 12
@@ -143,6 +143,14 @@ int excmg_adjoint(excmg_handle *h, const double *G, double *dLdf, double *dLdg, 
  * entries, the time from the batch's start until problem b's last grid converged (device timestamps). */
 int excmg_solve_batched(excmg_handle *const *hs, int32_t count, const double *const *f, const double *const *g,
                         double *const *u, excmg_stats *stats, double *ms_per_problem);
+
+/* Autotuner (host call, device work on the handle's stream): times the two CG sweep kernels of every relaxed grid
+ * (FP64, and FP32 where EXCMG_FP32_IR relaxes in FP32) for each z-chunk length in {2, 4, ..., 64} planes per
+ * workgroup, on the handle's own work buffers (no caller array is read or written), and keeps the fastest chunk per
+ * grid and kernel for every later call on this handle.  zc_out (host, nullable, 4 * levels entries): per grid, the
+ * chunk of pass A and pass B in FP64, then in FP32 (0 where the grid is not relaxed that way).  Optional: without it
+ * the handle uses a fixed default (16 planes, fewer on small grids). */
+int excmg_autotune(excmg_handle *h, int32_t *zc_out);
 
 void excmg_destroy(excmg_handle *h);
 const char *excmg_strerror(int code);

@@ -137,6 +137,13 @@ class Solver:
         _lib.check(code, "excmg_adjoint")
         return dLdf, dLdg, lam, st.to_dict()
 
+    def autotune(self):
+        """Time the CG sweep variants of every relaxed grid and keep the fastest.  Returns, per grid, the z chunk of
+        (pass A, pass B) in FP64 and in FP32 (0 where unused)."""
+        zc = (ctypes.c_int32 * (4 * self.levels))()
+        _lib.check(_lib.lib().excmg_autotune(self._h, zc), "excmg_autotune")
+        return [tuple(zc[4 * l: 4 * l + 4]) for l in range(self.levels)]
+
     def close(self):
         if self._h:
             _lib.lib().excmg_destroy(self._h)

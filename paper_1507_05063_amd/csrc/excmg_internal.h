@@ -71,6 +71,56 @@ inline Stencil make_stencil(double hx, double hy, double hz) {
   return s;
 }
 
+// Level right-hand side at an interior node (i,j,k) of a grid with cells (nx,ny,nz), read from the finest dense
+// arrays at stride s (level data by injection, Section 2: every coarse node is a fine node).
+//   mode 0: b = -R f + A_IB g, R f = (6 f_c + sum of the 6 face neighbours)/2 and, for neighbours on the boundary,
+//           A's coefficient times g: faces (4a-b-c), (4b-a-c), (4c-a-b); edges (a+b)/2, (a+c)/2, (b+c)/2
+//           (eq. compact with the Dirichlet values moved to the right, negated so that M = -A_h is positive definite)
+//   mode 1: b = f(i s, j s, k s) (the adjoint's data, zero Dirichlet values)
+struct RhsSrc {
+  Grid gf;          // layout of the finest dense arrays
+  const double *f;  // f (mode 0) or the adjoint's G (mode 1)
+  const double *g;  // Dirichlet data (mode 0), only boundary nodes read
+  int s;            // stride into the finest arrays
+  int mode;
+  double a, b, c;   // 1/hx^2, 1/hy^2, 1/hz^2 of the level
+};
+
+// A's couplings to the Dirichlet values of the boundary neighbours of (i,j,k) (only nodes next to the boundary have any)
+__device__ __noinline__ inline double rhs_boundary_terms(const RhsSrc &rs, int nx, int ny, int nz, int i, int j,
+                                                         int k) {
+  const int s = rs.s;
+  const double a = rs.a, b = rs.b, c = rs.c;
+  const double fx = 4.0 * a - b - c, fy = 4.0 * b - a - c, fz = 4.0 * c - a - b;
+  const double exy = 0.5 * (a + b), exz = 0.5 * (a + c), eyz = 0.5 * (b + c);
+  double lg = 0.0;
+  for (int dk = -1; dk <= 1; ++dk)
+    for (int dj = -1; dj <= 1; ++dj)
+      for (int di = -1; di <= 1; ++di) {
+        const int ad = (di != 0) + (dj != 0) + (dk != 0);
+        if (ad == 0 || ad == 3) continue;
+        const int ii = i + di, jj = j + dj, kk = k + dk;
+        if (!(ii == 0 || jj == 0 || kk == 0 || ii == nx || jj == ny || kk == nz)) continue;
+        double w;
+        if (ad == 1) w = di ? fx : (dj ? fy : fz);
+        else w = (dk == 0) ? exy : ((dj == 0) ? exz : eyz);
+        lg += w * rs.g[rs.gf.at(ii * s, jj * s, kk * s)];
+      }
+  return lg;
+}
+
+__device__ __forceinline__ double rhs_at(const RhsSrc &rs, int nx, int ny, int nz, int i, int j, int k) {
+  const int s = rs.s;
+  auto F = [&](int di, int dj, int dk) { return rs.f[rs.gf.at((i + di) * s, (j + dj) * s, (k + dk) * s)]; };
+  if (rs.mode == 1) return F(0, 0, 0);
+  const double rf = 0.5 * (6.0 * F(0, 0, 0) + (F(1, 0, 0) + F(-1, 0, 0)) + (F(0, 1, 0) + F(0, -1, 0)) +
+                           (F(0, 0, 1) + F(0, 0, -1)));
+  double lg = 0.0;
+  if (i == 1 || j == 1 || k == 1 || i == nx - 1 || j == ny - 1 || k == nz - 1)
+    lg = rhs_boundary_terms(rs, nx, ny, nz, i, j, k);
+  return -rf + lg;
+}
+
 // Device-resident CG state of one solve (one per problem in a batch).  Written only by the finalize kernels.
 struct CgState {
   double rho;      // r.r of the current residual
@@ -92,46 +142,52 @@ struct CgState {
 // Launchers (defined in the .hip files).  All take the stream last.
 // ------------------------------------------------------------------------------------------------------------
 
+// A stencil sweep over one grid: layout, coefficients and the workgroup decomposition (64 x 4 column tiles, zc
+// planes per workgroup; chosen by make_sweep).
+struct Sweep {
+  Grid g;
+  Stencil st;
+  int zc, ntx, nty, nzc;
+};
+
+Sweep make_sweep(const Grid &g, const Stencil &s, int zc);  // zc <= 0: default chunk
+int sweep_blocks(const Sweep &sw);
 // partial-sum buffer length needed by the CG and residual kernels for a grid
 long long cg_partials_needed(const Grid &g);
 
-// r = b - M u (interior of u only), p-buffers untouched; partials: [r.r | b.b] (2 per block)
-void launch_residual(const Grid &gu, const double *u, const Grid &gb, const double *b, const Grid &gr, double *r,
-                     const Stencil &s, double *partials, int *nparts, hipStream_t st);
-// FP32 inner step setup: r32 = (float)(b - M u) and d32 = 0; partials [r.r | b.b | r32.r32] (3 per block)
-void launch_residual_cast(const Grid &gu, const double *u, const Grid &gb, const double *b, const Grid &g32,
-                          float *r32, float *d32, const Stencil &s, double *partials, int *nparts, hipStream_t st);
+// r = b - M u (interior of u only) on the level layout of sw, with b formed on the fly from the finest data (rs);
+// initialises the CG state (rho, ||b||^2, stop test)
+void launch_residual(const Sweep &sw, const double *u, const RhsSrc &rs, double *r, CgState *cs, double *partials,
+                     double tol, int max_iters, int hist_on, hipStream_t st);
+// FP32 inner step setup: r32 = (float)(b - M u), d32 = 0 (layout g32); sets the outer FP64 test and the inner state
+void launch_residual_cast(const Sweep &sw, const double *u, const RhsSrc &rs, const Grid &g32, float *r32,
+                          float *d32, CgState *outer, CgState *inner, double *partials, double tol, double eta,
+                          int outer_step, int max_outer, int max_inner, hipStream_t st);
 
+// one CG pass and its finalize kernel (a second, single-workgroup launch)
 template <typename T>
-void launch_cg_pass_a(const Grid &g, const T *r, T *p0, T *p1, const Stencil &s, const CgState *cs, double *partials,
-                      int *nparts, hipStream_t st);
+void launch_cg_pass_a(const Sweep &sw, const T *r, T *p0, T *p1, CgState *cs, double *partials, hipStream_t st);
 template <typename T>
-void launch_cg_pass_b(const Grid &g, T *u, T *r, const T *p0, const T *p1, const Stencil &s, const CgState *cs,
-                      double *partials, int *nparts, hipStream_t st);
+void launch_cg_pass_b(const Sweep &sw, T *u, T *r, const T *p0, const T *p1, CgState *cs, double *partials,
+                      hipStream_t st);
 
-// finalize kernels (one block, fixed summation order)
-void launch_finalize_init(CgState *cs, const double *partials, int nparts, double tol, int max_iters, int hist_on,
-                          hipStream_t st);
-void launch_finalize_ir(CgState *outer, CgState *inner, const double *partials, int nparts, double tol, double eta,
-                        int outer_step, int max_outer, int max_inner, hipStream_t st);
-void launch_finalize_a(CgState *cs, const double *partials, int nparts, hipStream_t st);
-void launch_finalize_b(CgState *cs, const double *partials, int nparts, hipStream_t st);
+// CG state for timing sweeps in isolation: iteration 0, alpha = beta = 0, never done
+void launch_tune_state(CgState *cs, hipStream_t st);
 
 // u += (double) d32 on the interior
 void launch_add_correction(const Grid &gu, double *u, const Grid &g32, const float *d32, hipStream_t st);
 
-// single-workgroup CG to rounding on a small grid (DSOLVE); work arrays r, p, q on grid gw
-void launch_dsolve(const Grid &gu, double *u, const Grid &gb, const double *b, const Grid &gw, double *r, double *p,
-                   double *q, const Stencil &s, CgState *cs, hipStream_t st);
+// single-workgroup CG on a small grid: exact = 1 to rounding (DSOLVE), exact = 0 to tol (relaxation); work arrays
+// r, p, q on grid gw
+void launch_small_cg(const Grid &gu, double *u, const RhsSrc &rs, const Grid &gw, double *r, double *p, double *q,
+                     const Stencil &s, CgState *cs, double tol, int max_iters, int exact, int hist_on,
+                     hipStream_t st);
 
 // y = M x (interior of x only), y = 0 on the boundary
 void launch_apply(const Grid &gx, const double *x, const Grid &gy, double *y, const Stencil &s, hipStream_t st);
 
-// level data: b = -R f + A_IB g from the finest dense f, g sampled at stride s
-void launch_rhs(const Grid &gf, const double *f, const double *g, int stride, const Grid &gb, double *b,
-                double hx, double hy, double hz, hipStream_t st);
-// b = G sampled at stride s on the interior (the adjoint's level data)
-void launch_sample_interior(const Grid &gf, const double *G, int stride, const Grid &gb, double *b, hipStream_t st);
+// level data b (layout gb) on the interior, from rhs_at
+void launch_rhs(const RhsSrc &rs, const Grid &gb, double *b, hipStream_t st);
 // boundary nodes of u <- g (finest dense g sampled at stride s); interior set to 0 if zero_interior
 void launch_set_boundary(const Grid &gg, const double *g, int stride, const Grid &gu, double *u, int zero_interior,
                          hipStream_t st);

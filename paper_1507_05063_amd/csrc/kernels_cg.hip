@@ -17,9 +17,12 @@
 // Workgroups are numbered so that consecutive tiles of one z chunk run on the same XCD (dispatch is round-robin over
 // the 8 XCDs), which keeps the y-halo rows shared by neighbouring tiles in that XCD's L2.
 //
-// Reductions: wavefront butterfly (xor shuffles), then one value per wave through LDS, one partial per workgroup, and
-// a single-workgroup finalize kernel that sums the partials in a fixed order.  Results are bitwise reproducible.
+// Reductions: wavefront butterfly (xor shuffles), then one value per wave through LDS, one partial per workgroup;
+// a single-workgroup finalize kernel sums the partials in a fixed order and updates the CG scalars (alpha, beta, the
+// stopping test) on the device.  Results are bitwise reproducible.
 #include <math.h>
+
+#include <type_traits>
 
 #include "excmg_internal.h"
 
@@ -58,38 +61,29 @@ __device__ __forceinline__ double block_sum(double v, double *sh) {
   return t;
 }
 
-// Tile shape of the stencil sweeps.
+// Tile shape of the stencil sweeps (x is the fast axis: one wavefront covers one 64-node row segment).
 constexpr int TX = 64;
 constexpr int TY = 4;
 constexpr int NT = TX * TY;
-constexpr int ZC = 16;  // z planes per workgroup
 
-struct TileMap {
-  int ntx, nty, nzc;
-};
-
-inline TileMap tile_map(const Grid &g) {
-  TileMap m;
-  m.ntx = (g.nx - 1 + TX - 1) / TX;
-  m.nty = (g.ny - 1 + TY - 1) / TY;
-  m.nzc = (g.nz - 1 + ZC - 1) / ZC;
-  return m;
-}
-
-// The z-march.  P supplies operand(idx) (the stencil operand at an interior node, idx in grid g), center(i,j,k,idx)
-// (prefetch of the thread's own data for output plane k) and consume(i,j,k,idx,C,out,acc0,acc1).
+// The z-march.  P supplies operand(idx) (the stencil operand at an interior node, idx in grid g),
+// center<S>(i,j,k,idx) (load of the thread's own data for output plane k into slot S) and
+// consume<S>(i,j,k,idx,C,out,acc0,acc1) (output plane k, data in slot S).  Both the stencil planes and the centre data
+// are requested two planes ahead of their use, so two planes' worth of loads are in flight per thread while a plane
+// is reduced.  Planes are stepped two at a time with compile-time parity: the register sets, the LDS buffer and the
+// centre slots all alternate by parity (zc is even, so the first output plane k0 = 1 + bz*zc is odd).
 template <typename T, typename P>
-__device__ __forceinline__ void zmarch(const Grid &g, const Stencil &st, P &pol, double &acc0, double &acc1,
+__device__ __forceinline__ void zmarch(const Sweep &sw, P &pol, double &acc0, double &acc1,
                                        T (*tile)[TY + 2][TX + 2]) {
   constexpr int W = TX + 2, H = TY + 2, E = W * H, NL = (E + NT - 1) / NT;
-  const TileMap tm{(g.nx - 1 + TX - 1) / TX, (g.ny - 1 + TY - 1) / TY, 0};
+  const Grid &g = sw.g;
   const int t = xcd_remap(blockIdx.x, gridDim.x);
-  const int bx = t % tm.ntx;
-  const int rest = t / tm.ntx;
-  const int by = rest % tm.nty;
-  const int bz = rest / tm.nty;
-  const int i0 = 1 + bx * TX, j0 = 1 + by * TY, k0 = 1 + bz * ZC;
-  const int k1 = min(k0 + ZC, g.nz);  // output planes [k0, k1)
+  const int bx = t % sw.ntx;
+  const int rest = t / sw.ntx;
+  const int by = rest % sw.nty;
+  const int bz = rest / sw.nty;
+  const int i0 = 1 + bx * TX, j0 = 1 + by * TY, k0 = 1 + bz * sw.zc;
+  const int k1 = min(k0 + sw.zc, g.nz);  // output planes [k0, k1)
   const int tid = threadIdx.x;
   const int lx = tid % TX, ly = tid / TX;
   const int i = i0 + lx, j = j0 + ly;
@@ -106,220 +100,79 @@ __device__ __forceinline__ void zmarch(const Grid &g, const Stencil &st, P &pol,
       if (gi >= 1 && gi < g.nx && gj >= 1 && gj < g.ny) col[m] = g.off + (long long)gj * g.sy + gi;
     }
   }
-  T reg[NL];
-  auto fetch = [&](int kk) {
+  T regA[NL], regB[NL];
+  auto fetch = [&](T(&reg)[NL], int kk) {
     const bool kin = (kk >= 1) && (kk < g.nz);
 #pragma unroll
     for (int m = 0; m < NL; ++m) reg[m] = (kin && col[m] >= 0) ? pol.operand(col[m] + (long long)kk * g.sz) : T(0);
   };
 
+  const Stencil &st = sw.st;
   const T c0 = (T)st.c0, cx = (T)st.cx, cy = (T)st.cy, cz = (T)st.cz;
   const T cxy = (T)st.cxy, cxz = (T)st.cxz, cyz = (T)st.cyz;
   T Cm = 0, Xm = 0, Ym = 0, Cc = 0, Xc = 0, Yc = 0, Pc = 0;
   const long long own = g.off + (long long)j * g.sy + i;
+  const int np = k1 - k0 + 2;  // planes k0-1 .. k1
 
-  fetch(k0 - 1);
-  const int np = k1 - k0 + 2;
-  for (int step = 0; step < np; ++step) {
+  fetch(regA, k0 - 1);
+  fetch(regB, k0);
+  if (active) {
+    pol.template center<1>(i, j, k0, own + (long long)k0 * g.sz);
+    if (k0 + 1 < k1) pol.template center<0>(i, j, k0 + 1, own + (long long)(k0 + 1) * g.sz);
+  }
+
+  auto body = [&](auto parity, int step) {
+    constexpr int PB = decltype(parity)::value;  // parity of the step
+    constexpr int SL = 1 - PB;                   // centre slot of the plane consumed / requested at this step
+    T(&reg)[NL] = PB ? regB : regA;
+    T(*tb)[TX + 2] = tile[PB];
     const int kk = k0 - 1 + step;
-    T(*tb)[TX + 2] = tile[step & 1];
 #pragma unroll
     for (int m = 0; m < NL; ++m) {
       const int e = tid + m * NT;
       if (e < E) tb[e / W][e % W] = reg[m];
     }
     __syncthreads();
-    if (step + 1 < np) fetch(kk + 1);
+    if (step + 2 < np) fetch(reg, kk + 2);
     const T c = tb[ly + 1][lx + 1];
     const T x = tb[ly + 1][lx] + tb[ly + 1][lx + 2];
     const T y = tb[ly][lx + 1] + tb[ly + 2][lx + 1];
     const T d = (tb[ly][lx] + tb[ly][lx + 2]) + (tb[ly + 2][lx] + tb[ly + 2][lx + 2]);
     if (step >= 2 && active) {
       const T out = Pc + cz * (Cm + c) + cxz * (Xm + x) + cyz * (Ym + y);
-      pol.consume(i, j, kk - 1, own + (long long)(kk - 1) * g.sz, Cc, out, acc0, acc1);
+      pol.template consume<SL>(i, j, kk - 1, own + (long long)(kk - 1) * g.sz, Cc, out, acc0, acc1);
+      if (kk + 1 < k1) pol.template center<SL>(i, j, kk + 1, own + (long long)(kk + 1) * g.sz);
     }
-    if (step >= 1 && step + 1 < np && active) pol.center(i, j, kk, own + (long long)kk * g.sz);
     Cm = Cc; Xm = Xc; Ym = Yc;
     Cc = c; Xc = x; Yc = y;
     Pc = c0 * c + cx * x + cy * y + cxy * d;
+  };
+  for (int step = 0; step < np; step += 2) {
+    body(std::integral_constant<int, 0>{}, step);
+    if (step + 1 < np) body(std::integral_constant<int, 1>{}, step + 1);
   }
 }
 
-// ---------------------------------------------------------------------------------------------------------- passes
-
-template <typename T>
-struct PolA {
-  const T *r;
-  const T *pold;
-  T *pnew;
-  T beta;
-  bool first;
-  __device__ __forceinline__ T operand(long long idx) const { return first ? r[idx] : r[idx] + beta * pold[idx]; }
-  __device__ __forceinline__ void center(int, int, int, long long) {}
-  __device__ __forceinline__ void consume(int, int, int, long long idx, T c, T out, double &acc0, double &) {
-    pnew[idx] = c;
-    acc0 += (double)c * (double)out;
-  }
-};
-
-template <typename T>
-__global__ __launch_bounds__(NT) void cg_pass_a_kernel(Grid g, const T *__restrict__ r, T *p0, T *p1, Stencil st,
-                                                       const CgState *__restrict__ cs, double *partials) {
-  __shared__ T tile[2][TY + 2][TX + 2];
-  __shared__ double sh[NT / 64];
-  if (cs->done) return;
-  const int it = cs->iter;
-  PolA<T> pol;
-  pol.r = r;
-  pol.pnew = (it & 1) ? p1 : p0;
-  pol.pold = (it & 1) ? p0 : p1;
-  pol.first = (it == 0);
-  pol.beta = (T)cs->beta;
-  double a0 = 0.0, a1 = 0.0;
-  zmarch<T>(g, st, pol, a0, a1, tile);
-  const double s = block_sum<NT>(a0, sh);
-  if (threadIdx.x == 0) partials[blockIdx.x] = s;
-}
-
-template <typename T>
-struct PolB {
-  const T *p;
-  T *u;
-  T *r;
-  T alpha;
-  T pr, pu;
-  __device__ __forceinline__ T operand(long long idx) const { return p[idx]; }
-  __device__ __forceinline__ void center(int, int, int, long long idx) {
-    pr = r[idx];
-    pu = u[idx];
-  }
-  __device__ __forceinline__ void consume(int, int, int, long long idx, T c, T out, double &acc0, double &) {
-    const T rn = pr - alpha * out;
-    r[idx] = rn;
-    u[idx] = pu + alpha * c;
-    acc0 += (double)rn * (double)rn;
-  }
-};
-
-template <typename T>
-__global__ __launch_bounds__(NT) void cg_pass_b_kernel(Grid g, T *u, T *r, const T *p0, const T *p1, Stencil st,
-                                                       const CgState *__restrict__ cs, double *partials) {
-  __shared__ T tile[2][TY + 2][TX + 2];
-  __shared__ double sh[NT / 64];
-  if (cs->done) return;
-  const int it = cs->iter;
-  PolB<T> pol;
-  pol.p = (it & 1) ? p1 : p0;
-  pol.u = u;
-  pol.r = r;
-  pol.alpha = (T)cs->alpha;
-  pol.pr = 0;
-  pol.pu = 0;
-  double a0 = 0.0, a1 = 0.0;
-  zmarch<T>(g, st, pol, a0, a1, tile);
-  const double s = block_sum<NT>(a0, sh);
-  if (threadIdx.x == 0) partials[blockIdx.x] = s;
-}
-
-// r = b - M u.  u, b and r share the grid layout g (the library's pitched FP64 layout of the level).
-struct PolResid {
-  const double *u;
-  const double *b;
-  double *r;
-  double pb;
-  __device__ __forceinline__ double operand(long long idx) const { return u[idx]; }
-  __device__ __forceinline__ void center(int, int, int, long long idx) { pb = b[idx]; }
-  __device__ __forceinline__ void consume(int, int, int, long long idx, double, double out, double &acc0,
-                                          double &acc1) {
-    const double rn = pb - out;
-    r[idx] = rn;
-    acc0 += rn * rn;
-    acc1 += pb * pb;
-  }
-};
-
-__global__ __launch_bounds__(NT) void residual_kernel(Grid g, const double *u, const double *b, double *r, Stencil st,
-                                                      double *partials) {
-  __shared__ double tile[2][TY + 2][TX + 2];
-  __shared__ double sh[NT / 64];
-  PolResid pol{u, b, r, 0.0};
-  double a0 = 0.0, a1 = 0.0;
-  zmarch<double>(g, st, pol, a0, a1, tile);
-  const double s0 = block_sum<NT>(a0, sh);
-  __syncthreads();
-  const double s1 = block_sum<NT>(a1, sh);
-  if (threadIdx.x == 0) {
-    partials[blockIdx.x] = s0;
-    partials[gridDim.x + blockIdx.x] = s1;
+// ---------------------------------------------------------------------------------------- grid-wide reductions
+//
+// Every workgroup writes its K partial sums to partials[k * nblocks + block]; a single-workgroup finalize kernel that
+// runs next on the stream sums them in block order and updates the CG state.  The kernel boundary orders the two;
+// no workgroup of a sweep fences or synchronises with another (on this GPU an agent-scope fence writes back and
+// invalidates the XCD's L2, far too costly to issue from every workgroup).
+template <int K>
+__device__ __forceinline__ void write_partials(const double (&v)[K], double *partials, double *sh) {
+  const int nb = gridDim.x;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const double s = block_sum<NT>(v[k], sh);
+    if (threadIdx.x == 0) partials[(long long)k * nb + blockIdx.x] = s;
+    __syncthreads();
   }
 }
-
-// r32 = (float)(b - M u), d32 = 0; the FP32 arrays use their own layout g32.
-struct PolResidCast {
-  const double *u;
-  const double *b;
-  Grid g32;
-  float *r32;
-  float *d32;
-  double pb;
-  __device__ __forceinline__ double operand(long long idx) const { return u[idx]; }
-  __device__ __forceinline__ void center(int, int, int, long long idx) { pb = b[idx]; }
-  double acc2;  // sum of the squared FP32-rounded residual
-  __device__ __forceinline__ void consume(int i, int j, int k, long long, double, double out, double &acc0,
-                                          double &acc1) {
-    const double rn = pb - out;
-    const float rf = (float)rn;
-    const long long q = g32.at(i, j, k);
-    r32[q] = rf;
-    d32[q] = 0.0f;
-    acc0 += rn * rn;
-    acc1 += pb * pb;
-    acc2 += (double)rf * (double)rf;
-  }
-};
-
-__global__ __launch_bounds__(NT) void residual_cast_kernel(Grid g, const double *u, const double *b, Grid g32,
-                                                           float *r32, float *d32, Stencil st, double *partials) {
-  __shared__ double tile[2][TY + 2][TX + 2];
-  __shared__ double sh[NT / 64];
-  PolResidCast pol{u, b, g32, r32, d32, 0.0, 0.0};
-  double a0 = 0.0, a1 = 0.0;
-  zmarch<double>(g, st, pol, a0, a1, tile);
-  const double s0 = block_sum<NT>(a0, sh);
-  __syncthreads();
-  const double s1 = block_sum<NT>(a1, sh);
-  __syncthreads();
-  const double s2 = block_sum<NT>(pol.acc2, sh);
-  if (threadIdx.x == 0) {
-    partials[blockIdx.x] = s0;
-    partials[gridDim.x + blockIdx.x] = s1;
-    partials[2 * gridDim.x + blockIdx.x] = s2;
-  }
-}
-
-// y = M x with x and y in possibly different layouts.
-struct PolApply {
-  const double *x;
-  Grid gy;
-  double *y;
-  __device__ __forceinline__ double operand(long long idx) const { return x[idx]; }
-  __device__ __forceinline__ void center(int, int, int, long long) {}
-  __device__ __forceinline__ void consume(int i, int j, int k, long long, double, double out, double &, double &) {
-    y[gy.at(i, j, k)] = out;
-  }
-};
-
-__global__ __launch_bounds__(NT) void apply_kernel(Grid gx, const double *x, Grid gy, double *y, Stencil st) {
-  __shared__ double tile[2][TY + 2][TX + 2];
-  PolApply pol{x, gy, y};
-  double a0 = 0.0, a1 = 0.0;
-  zmarch<double>(gx, st, pol, a0, a1, tile);
-}
-
-// --------------------------------------------------------------------------------------------------------- finalize
 
 constexpr int FT = 256;
 
+// fixed-order sum of n partials by one workgroup; the result is valid in every thread
 __device__ double fixed_sum(const double *a, int n, double *sh) {
   double v = 0.0;
   for (int q = threadIdx.x; q < n; q += FT) v += a[q];
@@ -334,34 +187,272 @@ __device__ double fixed_sum(const double *a, int n, double *sh) {
   return s;
 }
 
+// ------------------------------------------------------------------------------------------------ state updates
+
+__device__ void state_init(CgState *cs, double rho, double bb, double tol, int max_iters, int hist_on) {
+  cs->rho = rho;
+  cs->rho_old = rho;
+  cs->bnorm2 = bb;
+  cs->stop2 = tol * tol * bb;
+  cs->alpha = 0.0;
+  cs->beta = 0.0;
+  cs->pq = 0.0;
+  cs->iter = 0;
+  cs->status = 0;
+  cs->max_iters = max_iters;
+  cs->hist_on = hist_on;
+  const bool finite = isfinite(rho) && isfinite(bb);
+  cs->done = (!finite || rho <= cs->stop2) ? 1 : 0;
+  if (!finite) cs->status = EXCMG_ERR_BREAKDOWN;
+  if (hist_on) cs->hist[0] = bb > 0.0 ? sqrt(rho / bb) : 0.0;
+}
+
+// pass A: alpha = rho / p.Mp
+__device__ void state_after_a(CgState *cs, double pq) {
+  cs->pq = pq;
+  if (!(pq > 0.0) || !isfinite(pq)) {
+    cs->status = EXCMG_ERR_BREAKDOWN;
+    cs->done = 1;
+  } else {
+    cs->alpha = cs->rho / pq;
+  }
+}
+
+// pass B: beta = rho_new / rho, stopping test ||r|| <= tol ||b|| (Algorithm 1, the while condition)
+__device__ void state_after_b(CgState *cs, double rho) {
+  cs->rho_old = cs->rho;
+  cs->rho = rho;
+  cs->beta = rho / cs->rho_old;
+  const int it = cs->iter + 1;
+  cs->iter = it;
+  if (cs->hist_on && it < EXCMG_MAX_HISTORY) cs->hist[it] = cs->bnorm2 > 0.0 ? sqrt(rho / cs->bnorm2) : 0.0;
+  if (!isfinite(rho)) {
+    cs->status = EXCMG_ERR_BREAKDOWN;
+    cs->done = 1;
+  } else if (rho <= cs->stop2) {
+    cs->done = 1;
+  } else if (it >= cs->max_iters) {
+    cs->status = EXCMG_ERR_NOCONV;
+    cs->done = 1;
+  }
+}
+
+// Start of an outer step of FP32-in-FP64 iterative refinement.  outer: the FP64 residual test ||r|| <= tol ||b||;
+// inner: the FP32 CG on M d = r32 from d = 0, which stops at ||r_inner|| <= max(eta ||r32||, theta tol ||b||): it
+// reduces the residual no further than the outer test needs (with margin theta = 1/2), and no further than eta, the
+// reduction one FP32 solve is asked for.
+__device__ void state_ir(CgState *outer, CgState *inner, double r64, double bb, double r32, double tol, double eta,
+                         int outer_step, int max_outer, int max_inner) {
+  outer->rho = r64;
+  outer->bnorm2 = bb;
+  outer->stop2 = tol * tol * bb;
+  outer->iter = outer_step;
+  outer->status = 0;
+  outer->done = 0;
+  if (!isfinite(r64) || !isfinite(bb)) {
+    outer->status = EXCMG_ERR_BREAKDOWN;
+    outer->done = 1;
+  } else if (r64 <= outer->stop2) {
+    outer->done = 1;
+  } else if (outer_step >= max_outer) {
+    outer->status = EXCMG_ERR_NOCONV;
+    outer->done = 1;
+  }
+  inner->rho = r32;
+  inner->rho_old = r32;
+  inner->bnorm2 = r32;
+  const double theta = 0.5;
+  inner->stop2 = fmax(eta * eta * r32, theta * theta * outer->stop2);
+  inner->alpha = 0.0;
+  inner->beta = 0.0;
+  inner->pq = 0.0;
+  inner->iter = 0;
+  inner->status = 0;
+  inner->max_iters = max_inner;
+  inner->hist_on = 0;
+  inner->done = (outer->done || !(r32 > 0.0)) ? 1 : 0;
+}
+
+// ---------------------------------------------------------------------------------------------------------- passes
+
+template <typename T>
+struct PolA {
+  const T *r;
+  const T *pold;
+  T *pnew;
+  T beta;
+  bool first;
+  __device__ __forceinline__ T operand(long long idx) const { return first ? r[idx] : r[idx] + beta * pold[idx]; }
+  template <int S>
+  __device__ __forceinline__ void center(int, int, int, long long) {}
+  template <int S>
+  __device__ __forceinline__ void consume(int, int, int, long long idx, T c, T out, double &acc0, double &) {
+    pnew[idx] = c;
+    acc0 += (double)c * (double)out;
+  }
+};
+
+template <typename T>
+__global__ __launch_bounds__(NT) void cg_pass_a_kernel(Sweep sw, const T *__restrict__ r, T *p0, T *p1,
+                                                       const CgState *cs, double *partials) {
+  __shared__ T tile[2][TY + 2][TX + 2];
+  __shared__ double sh[NT / 64];
+  if (cs->done) return;
+  const int it = cs->iter;
+  PolA<T> pol;
+  pol.r = r;
+  pol.pnew = (it & 1) ? p1 : p0;
+  pol.pold = (it & 1) ? p0 : p1;
+  pol.first = (it == 0);
+  pol.beta = (T)cs->beta;
+  double a0 = 0.0, a1 = 0.0;
+  zmarch<T>(sw, pol, a0, a1, tile);
+  const double v[1] = {a0};
+  write_partials<1>(v, partials, sh);
+}
+
+template <typename T>
+struct PolB {
+  const T *p;
+  T *u;
+  T *r;
+  T alpha;
+  T pr[2], pu[2];
+  __device__ __forceinline__ T operand(long long idx) const { return p[idx]; }
+  template <int S>
+  __device__ __forceinline__ void center(int, int, int, long long idx) {
+    pr[S] = r[idx];
+    pu[S] = u[idx];
+  }
+  template <int S>
+  __device__ __forceinline__ void consume(int, int, int, long long idx, T c, T out, double &acc0, double &) {
+    const T rn = pr[S] - alpha * out;
+    r[idx] = rn;
+    u[idx] = pu[S] + alpha * c;
+    acc0 += (double)rn * (double)rn;
+  }
+};
+
+template <typename T>
+__global__ __launch_bounds__(NT) void cg_pass_b_kernel(Sweep sw, T *u, T *r, const T *p0, const T *p1,
+                                                       const CgState *cs, double *partials) {
+  __shared__ T tile[2][TY + 2][TX + 2];
+  __shared__ double sh[NT / 64];
+  if (cs->done) return;
+  const int it = cs->iter;
+  PolB<T> pol;
+  pol.p = (it & 1) ? p1 : p0;
+  pol.u = u;
+  pol.r = r;
+  pol.alpha = (T)cs->alpha;
+  pol.pr[0] = pol.pr[1] = 0;
+  pol.pu[0] = pol.pu[1] = 0;
+  double a0 = 0.0, a1 = 0.0;
+  zmarch<T>(sw, pol, a0, a1, tile);
+  const double v[1] = {a0};
+  write_partials<1>(v, partials, sh);
+}
+
+// r = b - M u with b formed on the fly from the finest f, g (rhs_at); u and r share the level layout.
+struct PolResid {
+  const double *u;
+  RhsSrc rs;
+  int nx, ny, nz;
+  double *r;
+  double pb[2];
+  __device__ __forceinline__ double operand(long long idx) const { return u[idx]; }
+  template <int S>
+  __device__ __forceinline__ void center(int i, int j, int k, long long) { pb[S] = rhs_at(rs, nx, ny, nz, i, j, k); }
+  template <int S>
+  __device__ __forceinline__ void consume(int, int, int, long long idx, double, double out, double &acc0,
+                                          double &acc1) {
+    const double rn = pb[S] - out;
+    r[idx] = rn;
+    acc0 += rn * rn;
+    acc1 += pb[S] * pb[S];
+  }
+};
+
+__global__ __launch_bounds__(NT) void residual_kernel(Sweep sw, const double *u, RhsSrc rs, double *r,
+                                                      double *partials) {
+  __shared__ double tile[2][TY + 2][TX + 2];
+  __shared__ double sh[NT / 64];
+  PolResid pol{u, rs, sw.g.nx, sw.g.ny, sw.g.nz, r, {0.0, 0.0}};
+  double a0 = 0.0, a1 = 0.0;
+  zmarch<double>(sw, pol, a0, a1, tile);
+  const double v[2] = {a0, a1};
+  write_partials<2>(v, partials, sh);
+}
+
+// r32 = (float)(b - M u), d32 = 0; the FP32 arrays use their own layout g32.
+struct PolResidCast {
+  const double *u;
+  RhsSrc rs;
+  int nx, ny, nz;
+  Grid g32;
+  float *r32;
+  float *d32;
+  double pb[2];
+  double acc2;  // sum of the squared FP32-rounded residual
+  __device__ __forceinline__ double operand(long long idx) const { return u[idx]; }
+  template <int S>
+  __device__ __forceinline__ void center(int i, int j, int k, long long) { pb[S] = rhs_at(rs, nx, ny, nz, i, j, k); }
+  template <int S>
+  __device__ __forceinline__ void consume(int i, int j, int k, long long, double, double out, double &acc0,
+                                          double &acc1) {
+    const double rn = pb[S] - out;
+    const float rf = (float)rn;
+    const long long q = g32.at(i, j, k);
+    r32[q] = rf;
+    d32[q] = 0.0f;
+    acc0 += rn * rn;
+    acc1 += pb[S] * pb[S];
+    acc2 += (double)rf * (double)rf;
+  }
+};
+
+__global__ __launch_bounds__(NT) void residual_cast_kernel(Sweep sw, const double *u, RhsSrc rs, Grid g32, float *r32,
+                                                           float *d32, double *partials) {
+  __shared__ double tile[2][TY + 2][TX + 2];
+  __shared__ double sh[NT / 64];
+  PolResidCast pol{u, rs, sw.g.nx, sw.g.ny, sw.g.nz, g32, r32, d32, {0.0, 0.0}, 0.0};
+  double a0 = 0.0, a1 = 0.0;
+  zmarch<double>(sw, pol, a0, a1, tile);
+  const double v[3] = {a0, a1, pol.acc2};
+  write_partials<3>(v, partials, sh);
+}
+
+// y = M x with x and y in possibly different layouts.
+struct PolApply {
+  const double *x;
+  Grid gy;
+  double *y;
+  __device__ __forceinline__ double operand(long long idx) const { return x[idx]; }
+  template <int S>
+  __device__ __forceinline__ void center(int, int, int, long long) {}
+  template <int S>
+  __device__ __forceinline__ void consume(int i, int j, int k, long long, double, double out, double &, double &) {
+    y[gy.at(i, j, k)] = out;
+  }
+};
+
+__global__ __launch_bounds__(NT) void apply_kernel(Sweep sw, const double *x, Grid gy, double *y) {
+  __shared__ double tile[2][TY + 2][TX + 2];
+  PolApply pol{x, gy, y};
+  double a0 = 0.0, a1 = 0.0;
+  zmarch<double>(sw, pol, a0, a1, tile);
+}
+
+// --------------------------------------------------------------------------------------------------------- finalize
+
 __global__ __launch_bounds__(FT) void finalize_init_kernel(CgState *cs, const double *partials, int nparts, double tol,
                                                            int max_iters, int hist_on) {
   __shared__ double sh[FT];
   const double rho = fixed_sum(partials, nparts, sh);
   const double bb = fixed_sum(partials + nparts, nparts, sh);
-  if (threadIdx.x == 0) {
-    cs->rho = rho;
-    cs->rho_old = rho;
-    cs->bnorm2 = bb;
-    cs->stop2 = tol * tol * bb;
-    cs->alpha = 0.0;
-    cs->beta = 0.0;
-    cs->pq = 0.0;
-    cs->iter = 0;
-    cs->status = 0;
-    cs->max_iters = max_iters;
-    cs->hist_on = hist_on;
-    const bool finite = isfinite(rho) && isfinite(bb);
-    cs->done = (!finite || rho <= cs->stop2) ? 1 : 0;
-    if (!finite) cs->status = EXCMG_ERR_BREAKDOWN;
-    if (hist_on) cs->hist[0] = bb > 0.0 ? sqrt(rho / bb) : 0.0;
-  }
+  if (threadIdx.x == 0) state_init(cs, rho, bb, tol, max_iters, hist_on);
 }
 
-// Start of an outer step of FP32-in-FP64 iterative refinement.  partials = [r64.r64 | b.b | r32.r32] from
-// residual_cast.  outer: FP64 residual test ||r|| <= tol ||b||; inner: the FP32 CG on M d = r32 from d = 0, which
-// stops at ||r_inner|| <= max(eta ||r32||, theta tol ||b||): it reduces the residual no further than the outer test
-// needs (with margin theta), and no further than eta, the reduction one FP32 solve can deliver.
 __global__ __launch_bounds__(FT) void finalize_ir_kernel(CgState *outer, CgState *inner, const double *partials,
                                                          int nparts, double tol, double eta, int outer_step,
                                                          int max_outer, int max_inner) {
@@ -369,77 +460,41 @@ __global__ __launch_bounds__(FT) void finalize_ir_kernel(CgState *outer, CgState
   const double r64 = fixed_sum(partials, nparts, sh);
   const double bb = fixed_sum(partials + nparts, nparts, sh);
   const double r32 = fixed_sum(partials + 2 * nparts, nparts, sh);
-  if (threadIdx.x == 0) {
-    outer->rho = r64;
-    outer->bnorm2 = bb;
-    outer->stop2 = tol * tol * bb;
-    outer->iter = outer_step;
-    outer->status = 0;
-    outer->done = 0;
-    if (!isfinite(r64) || !isfinite(bb)) {
-      outer->status = EXCMG_ERR_BREAKDOWN;
-      outer->done = 1;
-    } else if (r64 <= outer->stop2) {
-      outer->done = 1;
-    } else if (outer_step >= max_outer) {
-      outer->status = EXCMG_ERR_NOCONV;
-      outer->done = 1;
-    }
-    inner->rho = r32;
-    inner->rho_old = r32;
-    inner->bnorm2 = r32;
-    const double theta = 0.5;
-    inner->stop2 = fmax(eta * eta * r32, theta * theta * outer->stop2);
-    inner->alpha = 0.0;
-    inner->beta = 0.0;
-    inner->pq = 0.0;
-    inner->iter = 0;
-    inner->status = 0;
-    inner->max_iters = max_inner;
-    inner->hist_on = 0;
-    inner->done = (outer->done || !(r32 > 0.0)) ? 1 : 0;
-  }
+  if (threadIdx.x == 0) state_ir(outer, inner, r64, bb, r32, tol, eta, outer_step, max_outer, max_inner);
 }
 
 __global__ __launch_bounds__(FT) void finalize_a_kernel(CgState *cs, const double *partials, int nparts) {
   __shared__ double sh[FT];
   if (cs->done) return;
   const double pq = fixed_sum(partials, nparts, sh);
-  if (threadIdx.x == 0) {
-    cs->pq = pq;
-    if (!(pq > 0.0) || !isfinite(pq)) {
-      cs->status = EXCMG_ERR_BREAKDOWN;
-      cs->done = 1;
-    } else {
-      cs->alpha = cs->rho / pq;
-    }
-  }
+  if (threadIdx.x == 0) state_after_a(cs, pq);
 }
 
 __global__ __launch_bounds__(FT) void finalize_b_kernel(CgState *cs, const double *partials, int nparts) {
   __shared__ double sh[FT];
   if (cs->done) return;
   const double rho = fixed_sum(partials, nparts, sh);
-  if (threadIdx.x == 0) {
-    cs->rho_old = cs->rho;
-    cs->rho = rho;
-    cs->beta = rho / cs->rho_old;
-    const int it = cs->iter + 1;
-    cs->iter = it;
-    if (cs->hist_on && it < EXCMG_MAX_HISTORY) cs->hist[it] = cs->bnorm2 > 0.0 ? sqrt(rho / cs->bnorm2) : 0.0;
-    if (!isfinite(rho)) {
-      cs->status = EXCMG_ERR_BREAKDOWN;
-      cs->done = 1;
-    } else if (rho <= cs->stop2) {
-      cs->done = 1;
-    } else if (it >= cs->max_iters) {
-      cs->status = EXCMG_ERR_NOCONV;
-      cs->done = 1;
-    }
-  }
+  if (threadIdx.x == 0) state_after_b(cs, rho);
 }
 
 // ------------------------------------------------------------------------------------------------------ small kernels
+
+// A CG state in which the sweeps do their full work but change nothing that matters: iteration 0 (pass A reads only
+// r), alpha = 0 (pass B leaves u and r as they are), and a stopping test that never fires.
+__global__ void tune_state_kernel(CgState *cs) {
+  cs->rho = 1.0;
+  cs->rho_old = 1.0;
+  cs->pq = 1.0;
+  cs->alpha = 0.0;
+  cs->beta = 0.0;
+  cs->bnorm2 = 1.0;
+  cs->stop2 = -1.0;
+  cs->iter = 0;
+  cs->done = 0;
+  cs->status = 0;
+  cs->max_iters = 1 << 30;
+  cs->hist_on = 0;
+}
 
 __global__ void add_correction_kernel(Grid gu, double *u, Grid g32, const float *d) {
   const int i = 1 + blockIdx.x * blockDim.x + threadIdx.x;
@@ -482,10 +537,17 @@ __device__ double dsum(double v, double *sh) {
   return t;  // every thread holds the same value
 }
 
-// CG on M u = b for a small grid, in one workgroup, until the recursive relative residual is 1e-15 or the iteration
-// cap: the direct solve of the two coarsest grids (Algorithm 1, first two lines), to rounding.
-__global__ __launch_bounds__(DT) void dsolve_kernel(Grid gu, double *u, Grid gb, const double *b, Grid gw, double *r,
-                                                    double *p, double *q, Stencil st, CgState *cs, int cap) {
+// Conjugate gradients on M u = b for a small grid, in one workgroup of 1024 threads, all iterations in one launch
+// (b formed on the fly by rhs_at).  Two uses:
+//   exact = 1: the direct solve of the two coarsest grids (Algorithm 1, first two lines): iterate until the recursive
+//              relative residual is 1e-15 (rounding level) or the iteration cap;
+//   exact = 0: the relaxation of a small grid (Algorithm 1, the while loop): the same Hestenes-Stiefel iteration and
+//              stopping test as the multi-workgroup sweeps, ||r|| <= tol ||b|| checked before every iteration.
+// Small grids are latency-bound: one workgroup with every iteration in registers and L2 beats two sweep launches
+// plus two reductions per iteration.
+__global__ __launch_bounds__(DT) void small_cg_kernel(Grid gu, double *u, RhsSrc rs, Grid gw, double *r, double *p,
+                                                      double *q, Stencil st, CgState *cs, double tol, int cap,
+                                                      int exact, int hist_on) {
   __shared__ double sh[DT / 64];
   const int nx1 = gu.nx - 1, ny1 = gu.ny - 1, nz1 = gu.nz - 1;
   const int n = nx1 * ny1 * nz1;
@@ -500,7 +562,7 @@ __global__ __launch_bounds__(DT) void dsolve_kernel(Grid gu, double *u, Grid gb,
   for (int m = threadIdx.x; m < n; m += DT) {
     int i, j, k;
     coords(m, i, j, k);
-    const double bv = b[gb.at(i, j, k)];
+    const double bv = rhs_at(rs, gu.nx, gu.ny, gu.nz, i, j, k);
     const double rv = bv - stencil_direct(gu, u, i, j, k, st);
     r[gw.at(i, j, k)] = rv;
     p[gw.at(i, j, k)] = rv;
@@ -509,10 +571,16 @@ __global__ __launch_bounds__(DT) void dsolve_kernel(Grid gu, double *u, Grid gb,
   }
   double rho = dsum(rr, sh);
   const double bnorm2 = dsum(bb, sh);
-  const double stop2 = 1e-30 * bnorm2;
+  const double stop2 = (exact ? 1e-30 : tol * tol) * bnorm2;
+  if (hist_on && threadIdx.x == 0) cs->hist[0] = bnorm2 > 0.0 ? sqrt(rho / bnorm2) : 0.0;
   int it = 0;
   int status = 0;
-  while (rho > stop2 && it < cap) {
+  if (!isfinite(rho) || !isfinite(bnorm2)) status = EXCMG_ERR_BREAKDOWN;
+  while (status == 0 && rho > stop2) {
+    if (it >= cap) {
+      if (!exact) status = EXCMG_ERR_NOCONV;
+      break;
+    }
     __syncthreads();  // p complete
     double pq = 0.0;
     for (int m = threadIdx.x; m < n; m += DT) {
@@ -542,6 +610,11 @@ __global__ __launch_bounds__(DT) void dsolve_kernel(Grid gu, double *u, Grid gb,
     const double beta = rho_new / rho;
     rho = rho_new;
     ++it;
+    if (hist_on && threadIdx.x == 0 && it < EXCMG_MAX_HISTORY) cs->hist[it] = sqrt(rho / bnorm2);
+    if (!isfinite(rho)) {
+      status = EXCMG_ERR_BREAKDOWN;
+      break;
+    }
     __syncthreads();  // all reads of p (in q) are done before p is overwritten
     for (int m = threadIdx.x; m < n; m += DT) {
       int i, j, k;
@@ -563,92 +636,93 @@ __global__ __launch_bounds__(DT) void dsolve_kernel(Grid gu, double *u, Grid gb,
 
 // ------------------------------------------------------------------------------------------------------- launchers
 
+// z chunk per workgroup (even, so that the first output plane of every workgroup is odd).  Default: 16 planes, or
+// fewer while the grid has under 2048 workgroups (8 per CU).  The autotuner replaces it per grid and pass.
+Sweep make_sweep(const Grid &g, const Stencil &s, int zc) {
+  Sweep sw;
+  sw.g = g;
+  sw.st = s;
+  sw.ntx = (g.nx - 1 + TX - 1) / TX;
+  sw.nty = (g.ny - 1 + TY - 1) / TY;
+  const long long tiles = (long long)sw.ntx * sw.nty;
+  if (zc <= 0) {
+    zc = 16;
+    while (zc > 2 && tiles * ((g.nz - 1 + zc - 1) / zc) < 2048) zc /= 2;
+  }
+  zc = zc < 2 ? 2 : (zc & ~1);
+  sw.zc = zc;
+  sw.nzc = (g.nz - 1 + zc - 1) / zc;
+  return sw;
+}
+
+int sweep_blocks(const Sweep &sw) { return sw.ntx * sw.nty * sw.nzc; }
+
 long long cg_partials_needed(const Grid &g) {
-  const TileMap m = tile_map(g);
-  return 3LL * m.ntx * m.nty * m.nzc + 64;
+  const Sweep sw = make_sweep(g, Stencil{}, 2);  // the smallest chunk gives the most workgroups
+  return 3LL * sweep_blocks(sw) + 64;
 }
 
-static int sweep_blocks(const Grid &g) {
-  const TileMap m = tile_map(g);
-  return m.ntx * m.nty * m.nzc;
+void launch_residual(const Sweep &sw, const double *u, const RhsSrc &rs, double *r, CgState *cs, double *partials,
+                     double tol, int max_iters, int hist_on, hipStream_t st) {
+  const int nb = sweep_blocks(sw);
+  residual_kernel<<<nb, NT, 0, st>>>(sw, u, rs, r, partials);
+  finalize_init_kernel<<<1, FT, 0, st>>>(cs, partials, nb, tol, max_iters, hist_on);
 }
 
-void launch_residual(const Grid &gu, const double *u, const Grid &gb, const double *b, const Grid &gr, double *r,
-                     const Stencil &s, double *partials, int *nparts, hipStream_t st) {
-  (void)gb;
-  (void)gr;  // u, b, r share the level's layout
-  const int nb = sweep_blocks(gu);
-  residual_kernel<<<nb, NT, 0, st>>>(gu, u, b, r, s, partials);
-  *nparts = nb;
-}
-
-void launch_residual_cast(const Grid &gu, const double *u, const Grid &gb, const double *b, const Grid &g32,
-                          float *r32, float *d32, const Stencil &s, double *partials, int *nparts, hipStream_t st) {
-  (void)gb;
-  const int nb = sweep_blocks(gu);
-  residual_cast_kernel<<<nb, NT, 0, st>>>(gu, u, b, g32, r32, d32, s, partials);
-  *nparts = nb;
+void launch_residual_cast(const Sweep &sw, const double *u, const RhsSrc &rs, const Grid &g32, float *r32,
+                          float *d32, CgState *outer, CgState *inner, double *partials, double tol, double eta,
+                          int outer_step, int max_outer, int max_inner, hipStream_t st) {
+  const int nb = sweep_blocks(sw);
+  residual_cast_kernel<<<nb, NT, 0, st>>>(sw, u, rs, g32, r32, d32, partials);
+  finalize_ir_kernel<<<1, FT, 0, st>>>(outer, inner, partials, nb, tol, eta, outer_step, max_outer, max_inner);
 }
 
 template <typename T>
-void launch_cg_pass_a(const Grid &g, const T *r, T *p0, T *p1, const Stencil &s, const CgState *cs, double *partials,
-                      int *nparts, hipStream_t st) {
-  const int nb = sweep_blocks(g);
-  cg_pass_a_kernel<T><<<nb, NT, 0, st>>>(g, r, p0, p1, s, cs, partials);
-  *nparts = nb;
+void launch_cg_pass_a(const Sweep &sw, const T *r, T *p0, T *p1, CgState *cs, double *partials, hipStream_t st) {
+  const int nb = sweep_blocks(sw);
+  cg_pass_a_kernel<T><<<nb, NT, 0, st>>>(sw, r, p0, p1, cs, partials);
+  finalize_a_kernel<<<1, FT, 0, st>>>(cs, partials, nb);
 }
 
 template <typename T>
-void launch_cg_pass_b(const Grid &g, T *u, T *r, const T *p0, const T *p1, const Stencil &s, const CgState *cs,
-                      double *partials, int *nparts, hipStream_t st) {
-  const int nb = sweep_blocks(g);
-  cg_pass_b_kernel<T><<<nb, NT, 0, st>>>(g, u, r, p0, p1, s, cs, partials);
-  *nparts = nb;
+void launch_cg_pass_b(const Sweep &sw, T *u, T *r, const T *p0, const T *p1, CgState *cs, double *partials,
+                      hipStream_t st) {
+  const int nb = sweep_blocks(sw);
+  cg_pass_b_kernel<T><<<nb, NT, 0, st>>>(sw, u, r, p0, p1, cs, partials);
+  finalize_b_kernel<<<1, FT, 0, st>>>(cs, partials, nb);
 }
 
-template void launch_cg_pass_a<double>(const Grid &, const double *, double *, double *, const Stencil &,
-                                       const CgState *, double *, int *, hipStream_t);
-template void launch_cg_pass_a<float>(const Grid &, const float *, float *, float *, const Stencil &, const CgState *,
-                                      double *, int *, hipStream_t);
-template void launch_cg_pass_b<double>(const Grid &, double *, double *, const double *, const double *,
-                                       const Stencil &, const CgState *, double *, int *, hipStream_t);
-template void launch_cg_pass_b<float>(const Grid &, float *, float *, const float *, const float *, const Stencil &,
-                                      const CgState *, double *, int *, hipStream_t);
+template void launch_cg_pass_a<double>(const Sweep &, const double *, double *, double *, CgState *, double *,
+                                       hipStream_t);
+template void launch_cg_pass_a<float>(const Sweep &, const float *, float *, float *, CgState *, double *,
+                                      hipStream_t);
+template void launch_cg_pass_b<double>(const Sweep &, double *, double *, const double *, const double *, CgState *,
+                                       double *, hipStream_t);
+template void launch_cg_pass_b<float>(const Sweep &, float *, float *, const float *, const float *, CgState *,
+                                      double *, hipStream_t);
 
-void launch_finalize_init(CgState *cs, const double *partials, int nparts, double tol, int max_iters, int hist_on,
-                          hipStream_t st) {
-  finalize_init_kernel<<<1, FT, 0, st>>>(cs, partials, nparts, tol, max_iters, hist_on);
-}
-
-void launch_finalize_ir(CgState *outer, CgState *inner, const double *partials, int nparts, double tol, double eta,
-                        int outer_step, int max_outer, int max_inner, hipStream_t st) {
-  finalize_ir_kernel<<<1, FT, 0, st>>>(outer, inner, partials, nparts, tol, eta, outer_step, max_outer, max_inner);
-}
-
-void launch_finalize_a(CgState *cs, const double *partials, int nparts, hipStream_t st) {
-  finalize_a_kernel<<<1, FT, 0, st>>>(cs, partials, nparts);
-}
-
-void launch_finalize_b(CgState *cs, const double *partials, int nparts, hipStream_t st) {
-  finalize_b_kernel<<<1, FT, 0, st>>>(cs, partials, nparts);
-}
+void launch_tune_state(CgState *cs, hipStream_t st) { tune_state_kernel<<<1, 1, 0, st>>>(cs); }
 
 void launch_add_correction(const Grid &gu, double *u, const Grid &g32, const float *d32, hipStream_t st) {
   dim3 grid((gu.nx - 1 + 255) / 256, gu.ny - 1, gu.nz - 1);
   add_correction_kernel<<<grid, 256, 0, st>>>(gu, u, g32, d32);
 }
 
-void launch_dsolve(const Grid &gu, double *u, const Grid &gb, const double *b, const Grid &gw, double *r, double *p,
-                   double *q, const Stencil &s, CgState *cs, hipStream_t st) {
-  const long long n = gu.interior();
-  int cap = (int)(4 * n + 200);
-  if (cap > 20000) cap = 20000;
-  dsolve_kernel<<<1, DT, 0, st>>>(gu, u, gb, b, gw, r, p, q, s, cs, cap);
+void launch_small_cg(const Grid &gu, double *u, const RhsSrc &rs, const Grid &gw, double *r, double *p, double *q,
+                     const Stencil &s, CgState *cs, double tol, int max_iters, int exact, int hist_on,
+                     hipStream_t st) {
+  int cap = max_iters;
+  if (exact) {
+    const long long n = gu.interior();
+    cap = (int)(4 * n + 200);
+    if (cap > 20000) cap = 20000;
+  }
+  small_cg_kernel<<<1, DT, 0, st>>>(gu, u, rs, gw, r, p, q, s, cs, tol, cap, exact, hist_on);
 }
 
 void launch_apply(const Grid &gx, const double *x, const Grid &gy, double *y, const Stencil &s, hipStream_t st) {
-  const int nb = sweep_blocks(gx);
-  apply_kernel<<<nb, NT, 0, st>>>(gx, x, gy, y, s);
+  const Sweep sw = make_sweep(gx, s, 0);
+  apply_kernel<<<sweep_blocks(sw), NT, 0, st>>>(sw, x, gy, y);
 }
 
 }  // namespace excmg

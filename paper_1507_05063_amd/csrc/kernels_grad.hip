@@ -8,8 +8,8 @@
 // modified right-hand sides in the output array, back substitution overwrites them with v.
 //
 // y and z lines: one thread per line, consecutive threads on consecutive x, so every step of the sweep is a
-// coalesced row access.  x lines: a workgroup of 64 threads takes 64 lines and walks x in chunks of 32 staged
-// through LDS (loads and stores coalesced along x; each thread then sweeps its own row of the chunk).
+// coalesced row access.  x lines: a workgroup of 256 threads takes 256 lines and walks x in chunks of 8 staged
+// through LDS (loads and stores run along x; each thread then sweeps its own row of the chunk).
 #include "excmg_internal.h"
 
 namespace excmg {
@@ -67,8 +67,8 @@ __global__ void grad_z_kernel(Grid gu, const double *__restrict__ u, Grid gd, do
   line_solve(u, gu.at(i, j, 0), gu.sz, uz, gd.at(i, j, 0), gd.sz, gu.nz, hz, inv_m);
 }
 
-constexpr int XL = 64;      // lines per workgroup
-constexpr int XC = 32;      // chunk length along x
+constexpr int XL = 256;     // x lines per workgroup (one thread per line)
+constexpr int XC = 8;       // chunk length along x
 constexpr int XP = XC + 3;  // LDS row pitch of the u tile (odd in 8-byte words: no bank conflicts on row sweeps)
 constexpr int XQ = XC + 1;  // LDS row pitch of the output tile
 
@@ -76,84 +76,85 @@ __global__ __launch_bounds__(XL) void grad_x_kernel(Grid gu, const double *__res
                                                     double hx, const double *__restrict__ inv_m) {
   __shared__ double tu[XL][XP];
   __shared__ double to[XL][XQ];
+  __shared__ long long ub[XL], ob[XL];  // row start of each line in u and in ux
   const int nlines = (gu.ny + 1) * (gu.nz + 1);
   const int L0 = blockIdx.x * XL;
   const int t = threadIdx.x;
   const int N = gu.nx;
-  const int myline = L0 + t;
-  const bool act = myline < nlines;
-  const int mj = act ? myline % (gu.ny + 1) : 0, mk = act ? myline / (gu.ny + 1) : 0;
-  // ends (strided, 10 loads per line)
+  const int nl = min(XL, nlines - L0);  // lines in this workgroup
+  const bool act = t < nl;
+  {
+    const int L = L0 + (act ? t : 0);
+    const int j = L % (gu.ny + 1), k = L / (gu.ny + 1);
+    ub[t] = gu.at(0, j, k);
+    ob[t] = gd.at(0, j, k);
+  }
   double v0 = 0.0, vN = 0.0;
   if (act) {
-    const long long b = gu.at(0, mj, mk);
+    const long long b = ub[t];
     v0 = end0(u[b], u[b + 1], u[b + 2], u[b + 3], u[b + 4], hx);
     vN = -end0(u[b + N], u[b + N - 1], u[b + N - 2], u[b + N - 3], u[b + N - 4], hx);
-    ux[gd.at(0, mj, mk)] = v0;
-    ux[gd.at(N, mj, mk)] = vN;
+    ux[ob[t]] = v0;
+    ux[ob[t] + N] = vN;
   }
+  __syncthreads();
   const double s3 = 3.0 / hx;
   double dprev = 0.0;
-  // forward sweep over chunks of interior x: [1 + c*XC, min(N-1, (c+1)*XC)]
+  // forward elimination, chunk by chunk over the interior x = 1..N-1
   for (int x0 = 1; x0 <= N - 1; x0 += XC) {
-    const int x1 = min(N - 1, x0 + XC - 1);
-    const int w = x1 - x0 + 3;  // u from x0-1 .. x1+1
-    __syncthreads();
-    for (int e = t; e < XL * w; e += XL) {
-      // consecutive threads take consecutive x of one line: coalesced
-      const int ln = e / w, xx = e % w;
-      const int L = L0 + ln;
+    const int wn = min(XC, N - x0);  // interior values in this chunk
+    // stage u[x0-1 .. x0+XC] of every line; consecutive threads read consecutive x of a line
+    for (int e = t; e < XL * (XC + 2); e += XL) {
+      const int ln = e / (XC + 2), xx = e % (XC + 2);
       double v = 0.0;
-      if (L < nlines) v = u[gu.at(x0 - 1 + xx, L % (gu.ny + 1), L / (gu.ny + 1))];
+      if (ln < nl && x0 - 1 + xx <= N) v = u[ub[ln] + x0 - 1 + xx];
       tu[ln][xx] = v;
     }
     __syncthreads();
     if (act) {
-      for (int x = x0; x <= x1; ++x) {
-        double rhs = s3 * (tu[t][x - x0 + 2] - tu[t][x - x0]);
+      for (int q = 0; q < wn; ++q) {
+        const int x = x0 + q;
+        double rhs = s3 * (tu[t][q + 2] - tu[t][q]);
         if (x == 1) rhs -= v0;
         if (x == N - 1) rhs -= vN;
-        const double d = (rhs - (x > 1 ? dprev : 0.0)) * inv_m[x];
-        to[t][x - x0] = d;
+        const double d = (rhs - dprev) * inv_m[x];
+        to[t][q] = d;
         dprev = d;
       }
     }
     __syncthreads();
-    const int wn = x1 - x0 + 1;
-    for (int e = t; e < XL * wn; e += XL) {
-      const int ln = e / wn, xx = e % wn;
-      const int L = L0 + ln;
-      if (L < nlines) ux[gd.at(x0 + xx, L % (gu.ny + 1), L / (gu.ny + 1))] = to[ln][xx];
+    for (int e = t; e < XL * XC; e += XL) {
+      const int ln = e / XC, xx = e % XC;
+      if (ln < nl && xx < wn) ux[ob[ln] + x0 + xx] = to[ln][xx];
     }
+    __syncthreads();
   }
-  // back substitution over the same chunks in reverse
+  // back substitution over the same chunks in reverse order
   const int nchunks = (N - 1 + XC - 1) / XC;
   double vnext = 0.0;
   for (int c = nchunks - 1; c >= 0; --c) {
     const int x0 = 1 + c * XC;
-    const int x1 = min(N - 1, x0 + XC - 1);
-    const int wn = x1 - x0 + 1;
-    __syncthreads();
-    for (int e = t; e < XL * wn; e += XL) {
-      const int ln = e / wn, xx = e % wn;
-      const int L = L0 + ln;
-      to[ln][xx] = (L < nlines) ? ux[gd.at(x0 + xx, L % (gu.ny + 1), L / (gu.ny + 1))] : 0.0;
+    const int wn = min(XC, N - x0);
+    for (int e = t; e < XL * XC; e += XL) {
+      const int ln = e / XC, xx = e % XC;
+      to[ln][xx] = (ln < nl && xx < wn) ? ux[ob[ln] + x0 + xx] : 0.0;
     }
     __syncthreads();
     if (act) {
-      for (int x = x1; x >= x0; --x) {
-        const double d = to[t][x - x0];
+      for (int q = wn - 1; q >= 0; --q) {
+        const int x = x0 + q;
+        const double d = to[t][q];
         const double v = (x == N - 1) ? d : d - inv_m[x] * vnext;
-        to[t][x - x0] = v;
+        to[t][q] = v;
         vnext = v;
       }
     }
     __syncthreads();
-    for (int e = t; e < XL * wn; e += XL) {
-      const int ln = e / wn, xx = e % wn;
-      const int L = L0 + ln;
-      if (L < nlines) ux[gd.at(x0 + xx, L % (gu.ny + 1), L / (gu.ny + 1))] = to[ln][xx];
+    for (int e = t; e < XL * XC; e += XL) {
+      const int ln = e / XC, xx = e % XC;
+      if (ln < nl && xx < wn) ux[ob[ln] + x0 + xx] = to[ln][xx];
     }
+    __syncthreads();
   }
 }
 

@@ -2,7 +2,7 @@
 //   rhs            level right-hand side b = -R f + A_IB g (eq. compact with the Dirichlet values eliminated)
 //   exp_finite     initial guess w_h = EXP_finite(u_2h, u_4h) (Sections 4.2.2 and 4.3)
 //   exp_true       sixth-order u~_h = EXP_true(u_h, u_2h) (eqs. t1 and chenlin, Section 4.3)
-//   set_boundary, copy, sample_interior: layout and boundary helpers
+//   set_boundary, copy: layout and boundary helpers
 #include <math.h>
 
 #include "excmg_internal.h"
@@ -16,47 +16,13 @@ __device__ __forceinline__ bool on_boundary(int i, int j, int k, int nx, int ny,
 }
 
 // ------------------------------------------------------------------------------------------------------------ rhs
-// One thread per interior node of the level grid gb; f and g are the finest dense arrays (layout gf) read at
-// stride s.  The 7-point average R f = (6 f_c + sum of face neighbours)/2 and, for neighbours on the boundary, the
-// compact operator's coefficient times g (a = 1/hx^2, ...): faces (4a-b-c) etc., edges (a+b)/2 etc.
-__global__ void rhs_kernel(Grid gf, const double *__restrict__ f, const double *__restrict__ g, int s, Grid gb,
-                           double *__restrict__ b, double a, double bb, double c) {
-  const int i = 1 + blockIdx.x * blockDim.x + threadIdx.x;
-  const int j = 1 + blockIdx.y;
-  const int k = 1 + blockIdx.z;
-  const int nx = gb.nx, ny = gb.ny, nz = gb.nz;
-  if (i >= nx) return;
-  auto F = [&](int di, int dj, int dk) { return f[gf.at((i + di) * s, (j + dj) * s, (k + dk) * s)]; };
-  const double rf = 0.5 * (6.0 * F(0, 0, 0) + (F(1, 0, 0) + F(-1, 0, 0)) + (F(0, 1, 0) + F(0, -1, 0)) +
-                           (F(0, 0, 1) + F(0, 0, -1)));
-  double lg = 0.0;
-  const bool near = (i == 1 || j == 1 || k == 1 || i == nx - 1 || j == ny - 1 || k == nz - 1);
-  if (near) {
-    const double fx = 4.0 * a - bb - c, fy = 4.0 * bb - a - c, fz = 4.0 * c - a - bb;
-    const double exy = 0.5 * (a + bb), exz = 0.5 * (a + c), eyz = 0.5 * (bb + c);
-    for (int dk = -1; dk <= 1; ++dk)
-      for (int dj = -1; dj <= 1; ++dj)
-        for (int di = -1; di <= 1; ++di) {
-          const int ad = (di != 0) + (dj != 0) + (dk != 0);
-          if (ad == 0 || ad == 3) continue;
-          const int ii = i + di, jj = j + dj, kk = k + dk;
-          if (!on_boundary(ii, jj, kk, nx, ny, nz)) continue;
-          double w;
-          if (ad == 1) w = di ? fx : (dj ? fy : fz);
-          else w = (dk == 0) ? exy : ((dj == 0) ? exz : eyz);
-          lg += w * g[gf.at(ii * s, jj * s, kk * s)];
-        }
-  }
-  b[gb.at(i, j, k)] = -rf + lg;
-}
-
-// G sampled at stride s on the interior (the adjoint's level data), 0 on the boundary is never read
-__global__ void sample_interior_kernel(Grid gf, const double *__restrict__ G, int s, Grid gb, double *__restrict__ b) {
+// One thread per interior node of the level grid gb (rhs_at: eq. compact with the Dirichlet values eliminated).
+__global__ void rhs_kernel(RhsSrc rs, Grid gb, double *__restrict__ b) {
   const int i = 1 + blockIdx.x * blockDim.x + threadIdx.x;
   const int j = 1 + blockIdx.y;
   const int k = 1 + blockIdx.z;
   if (i >= gb.nx) return;
-  b[gb.at(i, j, k)] = G[gf.at(i * s, j * s, k * s)];
+  b[gb.at(i, j, k)] = rhs_at(rs, gb.nx, gb.ny, gb.nz, i, j, k);
 }
 
 __global__ void set_boundary_kernel(Grid gg, const double *__restrict__ g, int s, Grid gu, double *__restrict__ u,
@@ -125,24 +91,26 @@ __global__ __launch_bounds__(ET) void exp_finite_kernel(Grid g2, const double *_
   const int ncx = gw.nx / 8, ncy = gw.ny / 8, ncz = gw.nz / 8;
   const int cx0 = blockIdx.x * CXN;
   const int cj = blockIdx.y, ck = blockIdx.z;
-  const int nc = min(CXN, ncx - cx0);  // cells in this workgroup
+  const int nc = min(CXN, ncx - cx0);  // cells in this workgroup (fewer in the last one along x)
   const int n2x = 4 * nc + 1, n4x = 2 * nc + 1, nfx = 8 * nc + 1;
   const int tid = threadIdx.x;
   const int I0 = 4 * cx0, J0 = 4 * cj, K0 = 4 * ck;  // 2h-grid origin of the slab
+  // Index decompositions use the full-slab extents (compile-time divisors); entries past a short slab are skipped.
   // 1. stage
-  for (int e = tid; e < 25 * n2x; e += ET) {
-    const int a = e % n2x, bc = e / n2x, b = bc % 5, c = bc / 5;
-    W[c][b][a] = u2[g2.at(I0 + a, J0 + b, K0 + c)];
+  for (int e = tid; e < 25 * EX2; e += ET) {
+    const int a = e % EX2, bc = e / EX2, b = bc % 5, c = bc / 5;
+    if (a < n2x) W[c][b][a] = u2[g2.at(I0 + a, J0 + b, K0 + c)];
   }
   __syncthreads();
-  for (int e = tid; e < 9 * n4x; e += ET) {
-    const int a = e % n4x, bc = e / n4x, b = bc % 3, c = bc / 3;
-    D[c][b][a] = W[2 * c][2 * b][2 * a] - u4[g4.at(I0 / 2 + a, J0 / 2 + b, K0 / 2 + c)];
+  for (int e = tid; e < 9 * EX4; e += ET) {
+    const int a = e % EX4, bc = e / EX4, b = bc % 3, c = bc / 3;
+    if (a < n4x) D[c][b][a] = W[2 * c][2 * b][2 * a] - u4[g4.at(I0 / 2 + a, J0 / 2 + b, K0 / 2 + c)];
   }
   __syncthreads();
   // 2. extrapolate at the 2h nodes
-  for (int e = tid; e < 25 * n2x; e += ET) {
-    const int a = e % n2x, bc = e / n2x, b = bc % 5, c = bc / 5;
+  for (int e = tid; e < 25 * EX2; e += ET) {
+    const int a = e % EX2, bc = e / EX2, b = bc % 5, c = bc / 5;
+    if (a >= n2x) continue;
     const int al = a >> 1, ah = (a + 1) >> 1, bl = b >> 1, bh = (b + 1) >> 1, cl = c >> 1, ch = (c + 1) >> 1;
     const double d = ((D[cl][bl][al] + D[cl][bl][ah]) + (D[cl][bh][al] + D[cl][bh][ah])) +
                      ((D[ch][bl][al] + D[ch][bl][ah]) + (D[ch][bh][al] + D[ch][bh][ah]));
@@ -150,8 +118,9 @@ __global__ __launch_bounds__(ET) void exp_finite_kernel(Grid g2, const double *_
   }
   __syncthreads();
   // 3a. x
-  for (int e = tid; e < 25 * nfx; e += ET) {
-    const int xf = e % nfx, bc = e / nfx, b = bc % 5, c = bc / 5;
+  for (int e = tid; e < 25 * EXF; e += ET) {
+    const int xf = e % EXF, bc = e / EXF, b = bc % 5, c = bc / 5;
+    if (xf >= nfx) continue;
     double v;
     if (!(xf & 1)) {
       v = W[c][b][xf >> 1];
@@ -164,8 +133,9 @@ __global__ __launch_bounds__(ET) void exp_finite_kernel(Grid g2, const double *_
   }
   __syncthreads();
   // 3b. y
-  for (int e = tid; e < 45 * nfx; e += ET) {
-    const int xf = e % nfx, yc = e / nfx, yf = yc % 9, c = yc / 9;
+  for (int e = tid; e < 45 * EXF; e += ET) {
+    const int xf = e % EXF, yc = e / EXF, yf = yc % 9, c = yc / 9;
+    if (xf >= nfx) continue;
     double v;
     if (!(yf & 1)) {
       v = Wx[c][yf >> 1][xf];
@@ -181,8 +151,9 @@ __global__ __launch_bounds__(ET) void exp_finite_kernel(Grid g2, const double *_
   const bool lastx = (cx0 + nc == ncx), lasty = (cj == ncy - 1), lastz = (ck == ncz - 1);
   const int ox = lastx ? nfx : nfx - 1, oy = lasty ? 9 : 8, oz = lastz ? 9 : 8;
   const int gi0 = 8 * cx0, gj0 = 8 * cj, gk0 = 8 * ck;
-  for (int e = tid; e < ox * oy * oz; e += ET) {
-    const int xf = e % ox, yz = e / ox, yf = yz % oy, zf = yz / oy;
+  for (int e = tid; e < EXF * 81; e += ET) {
+    const int xf = e % EXF, yz = e / EXF, yf = yz % 9, zf = yz / 9;
+    if (xf >= ox || yf >= oy || zf >= oz) continue;
     const int gi = gi0 + xf, gj = gj0 + yf, gk = gk0 + zf;
     double v;
     if (on_boundary(gi, gj, gk, gw.nx, gw.ny, gw.nz)) {
@@ -202,19 +173,37 @@ __global__ __launch_bounds__(ET) void exp_finite_kernel(Grid g2, const double *_
 // u~ = u_h + delta_avg / 15 where delta = u_h - u_2h at the 2h nodes and delta_avg its mean over the corners of the
 // 2h edge/face/element the node is the midpoint of: eq. (t1) at 2h nodes, eq. (chenlin) at edge midpoints, and its
 // mean over the 2 face / 4 space diagonals at face / element centres.
-__global__ void exp_true_kernel(Grid gh, const double *__restrict__ uh, Grid g2, const double *__restrict__ u2, Grid gt,
-                                double *__restrict__ ut) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const int j = blockIdx.y;
-  const int k = blockIdx.z;
-  if (i > gh.nx) return;
-  const int il = i & ~1, ih = (i & 1) ? i + 1 : i;
-  const int jl = j & ~1, jh = (j & 1) ? j + 1 : j;
-  const int kl = k & ~1, kh = (k & 1) ? k + 1 : k;
-  auto dl = [&](int a, int b, int c) { return uh[gh.at(a, b, c)] - u2[g2.at(a >> 1, b >> 1, c >> 1)]; };
-  const double d = ((dl(il, jl, kl) + dl(ih, jl, kl)) + (dl(il, jh, kl) + dl(ih, jh, kl))) +
-                   ((dl(il, jl, kh) + dl(ih, jl, kh)) + (dl(il, jh, kh) + dl(ih, jh, kh)));
-  ut[gt.at(i, j, k)] = uh[gh.at(i, j, k)] + d * (1.0 / 120.0);  // (1/15) * (1/8) * sum over the 8 corner slots
+// A workgroup owns a 64 x 4 x 8 block of fine nodes (origin even on every axis): it first forms delta on the block's
+// 33 x 3 x 5 even nodes in LDS, then every thread writes 8 nodes of one (x, y) column.
+constexpr int TTX = 64, TTY = 4, TTZ = 8;
+constexpr int DTX = TTX / 2 + 1, DTY = TTY / 2 + 1, DTZ = TTZ / 2 + 1;
+
+__global__ __launch_bounds__(TTX *TTY) void exp_true_kernel(Grid gh, const double *__restrict__ uh, Grid g2,
+                                                           const double *__restrict__ u2, Grid gt,
+                                                           double *__restrict__ ut) {
+  __shared__ double D[DTZ][DTY][DTX];
+  const int x0 = blockIdx.x * TTX, y0 = blockIdx.y * TTY, z0 = blockIdx.z * TTZ;
+  const int tid = threadIdx.x;
+  for (int e = tid; e < DTX * DTY * DTZ; e += TTX * TTY) {
+    const int a = e % DTX, bc = e / DTX, b = bc % DTY, c = bc / DTY;
+    const int I = x0 / 2 + a, J = y0 / 2 + b, K = z0 / 2 + c;  // 2h-grid node
+    double d = 0.0;
+    if (2 * I <= gh.nx && 2 * J <= gh.ny && 2 * K <= gh.nz) d = uh[gh.at(2 * I, 2 * J, 2 * K)] - u2[g2.at(I, J, K)];
+    D[c][b][a] = d;
+  }
+  __syncthreads();
+  const int lx = tid % TTX, ly = tid / TTX;
+  const int i = x0 + lx, j = y0 + ly;
+  if (i > gh.nx || j > gh.ny) return;
+  const int al = lx >> 1, ah = (lx + 1) >> 1, bl = ly >> 1, bh = (ly + 1) >> 1;
+  const int zend = min(TTZ, gh.nz + 1 - z0);
+  for (int q = 0; q < zend; ++q) {
+    const int k = z0 + q;
+    const int cl = q >> 1, ch = (q + 1) >> 1;
+    const double d = ((D[cl][bl][al] + D[cl][bl][ah]) + (D[cl][bh][al] + D[cl][bh][ah])) +
+                     ((D[ch][bl][al] + D[ch][bl][ah]) + (D[ch][bh][al] + D[ch][bh][ah]));
+    ut[gt.at(i, j, k)] = uh[gh.at(i, j, k)] + d * (1.0 / 120.0);  // (1/15) * (1/8) * sum over the 8 corner slots
+  }
 }
 
 // ------------------------------------------------------------------------------------------------------- adjoint
@@ -257,14 +246,8 @@ inline dim3 interior_grid(const Grid &g, int bx) { return dim3((g.nx - 1 + bx - 
 
 }  // namespace
 
-void launch_rhs(const Grid &gf, const double *f, const double *g, int stride, const Grid &gb, double *b, double hx,
-                double hy, double hz, hipStream_t st) {
-  rhs_kernel<<<interior_grid(gb, 256), 256, 0, st>>>(gf, f, g, stride, gb, b, 1.0 / (hx * hx), 1.0 / (hy * hy),
-                                                     1.0 / (hz * hz));
-}
-
-void launch_sample_interior(const Grid &gf, const double *G, int stride, const Grid &gb, double *b, hipStream_t st) {
-  sample_interior_kernel<<<interior_grid(gb, 256), 256, 0, st>>>(gf, G, stride, gb, b);
+void launch_rhs(const RhsSrc &rs, const Grid &gb, double *b, hipStream_t st) {
+  rhs_kernel<<<interior_grid(gb, 256), 256, 0, st>>>(rs, gb, b);
 }
 
 void launch_set_boundary(const Grid &gg, const double *g, int stride, const Grid &gu, double *u, int zero_interior,
@@ -281,7 +264,8 @@ void launch_exp_finite(const Grid &g2, const double *u2, const Grid &g4, const d
 
 void launch_exp_true(const Grid &gh, const double *uh, const Grid &g2, const double *u2, const Grid &gt, double *ut,
                      hipStream_t st) {
-  exp_true_kernel<<<node_grid(gh, 256), 256, 0, st>>>(gh, uh, g2, u2, gt, ut);
+  dim3 grid((gh.nx + 1 + TTX - 1) / TTX, (gh.ny + 1 + TTY - 1) / TTY, (gh.nz + 1 + TTZ - 1) / TTZ);
+  exp_true_kernel<<<grid, TTX * TTY, 0, st>>>(gh, uh, g2, u2, gt, ut);
 }
 
 void launch_copy(const Grid &gs, const double *src, const Grid &gd, double *dst, hipStream_t st) {

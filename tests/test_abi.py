@@ -96,8 +96,8 @@ def test_workspace_bytes_scale(abi):
     b64 = ex.workspace_bytes((512, 512, 512))
     b32 = ex.workspace_bytes((512, 512, 512), precision=ex.FP32_IR)
     node = 513 ** 3 * 8
-    # four finest FP64 work vectors plus the cascade's solutions (about 8/7 of a finest array), pitched rows
-    assert 5.0 * node < b64 < 5.6 * node
+    # three finest FP64 work vectors plus the cascade's solutions (about 8/7 of a finest array), pitched rows
+    assert 4.0 * node < b64 < 4.6 * node
     assert b32 - b64 > 1.9 * node  # four FP32 vectors more
     assert ex.workspace_bytes((64, 64, 64)) < b64
 

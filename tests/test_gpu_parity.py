@@ -172,6 +172,21 @@ def test_history_and_timing(ex):
     assert st["kernel_ms"]["cg_b"] > 0
 
 
+def test_autotuned_solve_matches_oracle(ex, orc):
+    """After the autotuner picks other z chunks, the solve is still the oracle's (to the parity bar)."""
+    p = synth.smooth(2, (1.0, 0.8, 1.1))
+    n = (64, 32, 32)
+    f, g, _ = synth.sample(p, n)
+    s = ex.Solver(n, p.box, 1e-10)
+    zc = s.autotune()
+    # grids 0, 1 are solved directly and grids of <= 8000 unknowns by the single-workgroup kernel: no chunk
+    assert zc[0] == (0, 0, 0, 0) and zc[1] == (0, 0, 0, 0)
+    assert zc[-1][0] >= 2 and zc[-1][1] >= 2
+    ug, _, st = s.solve(dev(f), dev(g))
+    ref = orc.excmg(f, g, p.box, s.n_coarse, 1e-10, fixed_iters=np.array(st["iters"], dtype=np.int32))
+    assert rel2(host(ug), ref["u"]) <= 1e-12
+
+
 def test_determinism(ex):
     p = synth.smooth(1)
     n = (64, 32, 32)
