@@ -66,6 +66,8 @@ def main():
     g = torch.from_numpy(g_np).cuda()
     print(f"# workload {N}^3 cells, inputs resident: {f.numel() * 16 / 1e9:.2f} GB", file=sys.stderr, flush=True)
 
+    copy_gbs, read_gbs = ex.bandwidth_probe(2 << 30)
+    print(f"# streaming probe: copy {copy_gbs:.0f} GB/s, read {read_gbs:.0f} GB/s", file=sys.stderr, flush=True)
     s = ex.Solver(n, p.box, args.tol, timing=True)
     zc64 = s.autotune()
     print(f"# autotuned z chunks (A, B) per grid: {[z[:2] for z in zc64]}", file=sys.stderr, flush=True)
@@ -127,7 +129,9 @@ def main():
                    "cells": list(n), "levels": stats[-1]["levels"], "tol": args.tol},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "avg_launch_ms": round(avg_ms, 4), "bytes_per_launch": BYTES_PER_UNKNOWN[dom] * nI},
+                     "avg_launch_ms": round(avg_ms, 4), "bytes_per_launch": BYTES_PER_UNKNOWN[dom] * nI,
+                     "probe_copy_GBs": round(copy_gbs, 1), "probe_read_GBs": round(read_gbs, 1),
+                     "frac_of_probe_copy": round(achieved / copy_gbs, 4)},
         "iters_per_grid": stats[-1]["iters"],
         "autotuned_z_chunks": [list(z[:2]) for z in zc64],
         "ms_per_grid": [round(v, 3) for v in stats[-1]["ms_level"]],

@@ -155,6 +155,13 @@ int excmg_autotune(excmg_handle *h, int32_t *zc_out);
 void excmg_destroy(excmg_handle *h);
 const char *excmg_strerror(int code);
 
+/* Same-run bandwidth ceiling for the roofline: copies the first half of buf into the second half, and reads all of
+ * buf, reps times each (after one warm-up pass), with streaming kernels of 16-byte accesses; reports the best rates in
+ * GB/s (bytes read plus bytes written for the copy).  buf: device, at least 4096 bytes, 16-byte aligned; its contents
+ * are overwritten. */
+int excmg_bandwidth_probe(void *buf, size_t bytes, int32_t reps, void *hip_stream, double *copy_GBs,
+                          double *read_GBs);
+
 /* ---- single steps of the path, on one grid of cells n = (Nx,Ny,Nz) and box (node arrays as above) ---- */
 
 /* y = M x with M = -A_h on the interior (eq. compact, left-hand side, negated; boundary entries of x are read as 0);

@@ -14,7 +14,7 @@ from . import _lib
 from ._lib import ExcmgError, FP32_IR, FP64, K_CLASSES, LIB_PATH, WANT_HISTORY, WANT_TIMING
 
 __all__ = ["Solver", "ExcmgError", "FP64", "FP32_IR", "plan", "workspace_bytes", "op_apply", "op_rhs",
-           "op_exp_finite", "op_exp_true", "solve_batched", "K_CLASSES", "LIB_PATH"]
+           "op_exp_finite", "op_exp_true", "solve_batched", "bandwidth_probe", "K_CLASSES", "LIB_PATH"]
 
 
 def _torch():
@@ -169,6 +169,17 @@ def solve_batched(solvers, fs, gs, us=None):
     code = _lib.lib().excmg_solve_batched(H, count, F, G, U, st, ms)
     _lib.check(code, "excmg_solve_batched")
     return us, [st[b].to_dict() for b in range(count)], [ms[b] for b in range(count)]
+
+
+def bandwidth_probe(nbytes: int = 2 << 30, reps: int = 5):
+    """Achievable HBM bandwidth in this process: (copy GB/s, read GB/s) of streaming kernels over nbytes."""
+    torch = _torch()
+    buf = torch.empty(int(nbytes), dtype=torch.uint8, device="cuda")
+    c, r = ctypes.c_double(0.0), ctypes.c_double(0.0)
+    _lib.check(_lib.lib().excmg_bandwidth_probe(_ptr(buf), int(nbytes), int(reps), _stream_ptr(), ctypes.byref(c),
+                                                ctypes.byref(r)), "excmg_bandwidth_probe")
+    del buf
+    return c.value, r.value
 
 
 def _n3(n):

@@ -6,7 +6,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libexcmg.so")
-SOURCES = ["excmg.hip", "kernels_cg.hip", "kernels_transfer.hip", "kernels_grad.hip"]
+SOURCES = ["excmg.hip", "kernels_cg.hip", "kernels_transfer.hip", "kernels_grad.hip", "kernels_probe.hip"]
 ARCH = "gfx950"
 
 FLAGS = [

@@ -315,7 +315,7 @@ int cg_ir(excmg_handle *h, int l, const RhsSrc &rs, bool finest, int *iters, int
   for (;; ++outer) {
     {
       Tick t(h, EXCMG_K_RESID, l);
-      launch_residual_cast(lv.sw, lv.u, rs, lv.g32, h->r32, h->d32, h->cs, h->cs2, h->partials, h->p.tol, eta,
+      launch_residual_cast(lv.sw, lv.u, rs, h->r, lv.g32, h->r32, h->d32, h->cs, h->cs2, h->partials, h->p.tol, eta,
                            outer, max_outer, maxit, s);
     }
     int e = last_error();
@@ -844,6 +844,44 @@ int excmg_op_exp_true(const int32_t n[3], const double *uh, const double *u2h, d
   int e = last_error();
   if (e) return e;
   HIPCHECK(hipStreamSynchronize(s));
+  return EXCMG_OK;
+}
+
+int excmg_bandwidth_probe(void *buf, size_t bytes, int32_t reps, void *hip_stream, double *copy_GBs,
+                          double *read_GBs) {
+  if (!buf || bytes < 4096 || reps <= 0 || ((uintptr_t)buf & 15)) return EXCMG_ERR_ARG;
+  const hipStream_t s = (hipStream_t)hip_stream;
+  const long long n = (long long)(bytes / sizeof(double)) & ~3LL;  // doubles, a multiple of 4
+  double *a = (double *)buf;
+  hipEvent_t e0, e1;
+  HIPCHECK(hipEventCreate(&e0));
+  HIPCHECK(hipEventCreate(&e1));
+  HIPCHECK(hipMemsetAsync(buf, 0, (size_t)n * sizeof(double), s));
+  float best_c = 1e30f, best_r = 1e30f;
+  int rc = EXCMG_OK;
+  for (int rep = 0; rep <= reps && rc == EXCMG_OK; ++rep) {
+    float mc = 0.0f, mr = 0.0f;
+    if (hipEventRecord(e0, s) != hipSuccess) rc = EXCMG_ERR_HIP;
+    launch_probe_copy(a, a + n / 2, n / 2, s);
+    if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+        hipEventElapsedTime(&mc, e0, e1) != hipSuccess)
+      rc = EXCMG_ERR_HIP;
+    if (hipEventRecord(e0, s) != hipSuccess) rc = EXCMG_ERR_HIP;
+    launch_probe_read(a, n, a, s);
+    if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+        hipEventElapsedTime(&mr, e0, e1) != hipSuccess)
+      rc = EXCMG_ERR_HIP;
+    if (last_error() != EXCMG_OK) rc = EXCMG_ERR_HIP;
+    if (rep > 0) {  // the first pass warms up
+      if (mc < best_c) best_c = mc;
+      if (mr < best_r) best_r = mr;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc) return rc;
+  if (copy_GBs) *copy_GBs = (double)n * sizeof(double) / (best_c * 1e-3) / 1e9;  // n/2 read + n/2 written
+  if (read_GBs) *read_GBs = (double)n * sizeof(double) / (best_r * 1e-3) / 1e9;
   return EXCMG_OK;
 }
 

@@ -160,9 +160,14 @@ long long cg_partials_needed(const Grid &g);
 void launch_residual(const Sweep &sw, const double *u, const RhsSrc &rs, double *r, CgState *cs, double *partials,
                      double tol, int max_iters, int hist_on, hipStream_t st);
 // FP32 inner step setup: r32 = (float)(b - M u), d32 = 0 (layout g32); sets the outer FP64 test and the inner state
-void launch_residual_cast(const Sweep &sw, const double *u, const RhsSrc &rs, const Grid &g32, float *r32,
-                          float *d32, CgState *outer, CgState *inner, double *partials, double tol, double eta,
-                          int outer_step, int max_outer, int max_inner, hipStream_t st);
+// (bterm: FP64 scratch in the level layout for the boundary terms of b)
+void launch_residual_cast(const Sweep &sw, const double *u, const RhsSrc &rs, double *bterm, const Grid &g32,
+                          float *r32, float *d32, CgState *outer, CgState *inner, double *partials, double tol,
+                          double eta, int outer_step, int max_outer, int max_inner, hipStream_t st);
+
+// achievable-bandwidth probes over a caller buffer: copy of the first half into the second, and a read of the whole
+void launch_probe_copy(const double *src, double *dst, long long n, hipStream_t st);
+void launch_probe_read(const double *src, long long n, double *sink, hipStream_t st);
 
 // one CG pass and its finalize kernel (a second, single-workgroup launch)
 template <typename T>

@@ -68,14 +68,18 @@ constexpr int NT = TX * TY;
 
 // The z-march.  P supplies operand(idx) (the stencil operand at an interior node, idx in grid g),
 // center<S>(i,j,k,idx) (load of the thread's own data for output plane k into slot S) and
-// consume<S>(i,j,k,idx,C,out,acc0,acc1) (output plane k, data in slot S).  Both the stencil planes and the centre data
-// are requested two planes ahead of their use, so two planes' worth of loads are in flight per thread while a plane
-// is reduced.  Planes are stepped two at a time with compile-time parity: the register sets, the LDS buffer and the
-// centre slots all alternate by parity (zc is even, so the first output plane k0 = 1 + bz*zc is odd).
+// consume<S>(i,j,k,idx,C,out,cf,rf,acc0,acc1) (output plane k, data in slot S).  Both the stencil planes and the centre
+// data are requested two planes ahead of their use, so two planes' worth of loads are in flight per thread while a
+// plane is reduced.  Planes are stepped two at a time with compile-time parity: the register sets, the LDS buffers
+// and the centre slots all alternate by parity (zc is even, so the first output plane k0 = 1 + bz*zc is odd).
+// If P::kRhs, a second array (the finest f at the level's stride) is staged the same way in tileF and the 7-point
+// average R f = (6 f_c + sum of the 6 face neighbours)/2 of the output plane is handed to consume as rf (with the
+// centre value cf), so the right-hand side is formed with f read once.
 template <typename T, typename P>
-__device__ __forceinline__ void zmarch(const Sweep &sw, P &pol, double &acc0, double &acc1,
-                                       T (*tile)[TY + 2][TX + 2]) {
+__device__ __forceinline__ void zmarch(const Sweep &sw, P &pol, double &acc0, double &acc1, T (*tile)[TY + 2][TX + 2],
+                                       double (*tileF)[TY + 2][TX + 2]) {
   constexpr int W = TX + 2, H = TY + 2, E = W * H, NL = (E + NT - 1) / NT;
+  constexpr bool R = P::kRhs;
   const Grid &g = sw.g;
   const int t = xcd_remap(blockIdx.x, gridDim.x);
   const int bx = t % sw.ntx;
@@ -89,33 +93,42 @@ __device__ __forceinline__ void zmarch(const Sweep &sw, P &pol, double &acc0, do
   const int i = i0 + lx, j = j0 + ly;
   const bool active = (i < g.nx) && (j < g.ny);
 
-  // per fetch slot: column offset of its node (or -1 when outside the interior in x or y)
-  long long col[NL];
+  // per fetch slot: column offset of its node (or -1 when outside the interior in x or y); for f, any node of the grid
+  long long col[NL], colF[NL];
 #pragma unroll
   for (int m = 0; m < NL; ++m) {
     const int e = tid + m * NT;
     col[m] = -1;
+    colF[m] = -1;
     if (e < E) {
       const int gi = i0 - 1 + e % W, gj = j0 - 1 + e / W;
       if (gi >= 1 && gi < g.nx && gj >= 1 && gj < g.ny) col[m] = g.off + (long long)gj * g.sy + gi;
+      if (R && gi <= g.nx && gj <= g.ny) colF[m] = pol.fcol(gi, gj);
     }
   }
+  const long long fstride = R ? pol.fplane() : 0;
   T regA[NL], regB[NL];
-  auto fetch = [&](T(&reg)[NL], int kk) {
+  double fA[NL], fB[NL];
+  auto fetch = [&](T(&reg)[NL], double(&fr)[NL], int kk) {
     const bool kin = (kk >= 1) && (kk < g.nz);
 #pragma unroll
     for (int m = 0; m < NL; ++m) reg[m] = (kin && col[m] >= 0) ? pol.operand(col[m] + (long long)kk * g.sz) : T(0);
+    if constexpr (R) {
+#pragma unroll
+      for (int m = 0; m < NL; ++m) fr[m] = (colF[m] >= 0) ? pol.fval(colF[m] + (long long)kk * fstride) : 0.0;
+    }
   };
 
   const Stencil &st = sw.st;
   const T c0 = (T)st.c0, cx = (T)st.cx, cy = (T)st.cy, cz = (T)st.cz;
   const T cxy = (T)st.cxy, cxz = (T)st.cxz, cyz = (T)st.cyz;
   T Cm = 0, Xm = 0, Ym = 0, Cc = 0, Xc = 0, Yc = 0, Pc = 0;
+  double Fm = 0.0, Fc = 0.0, Gc = 0.0;  // f: centre of the previous and current plane, in-plane face sum
   const long long own = g.off + (long long)j * g.sy + i;
   const int np = k1 - k0 + 2;  // planes k0-1 .. k1
 
-  fetch(regA, k0 - 1);
-  fetch(regB, k0);
+  fetch(regA, fA, k0 - 1);
+  fetch(regB, fB, k0);
   if (active) {
     pol.template center<1>(i, j, k0, own + (long long)k0 * g.sz);
     if (k0 + 1 < k1) pol.template center<0>(i, j, k0 + 1, own + (long long)(k0 + 1) * g.sz);
@@ -125,6 +138,7 @@ __device__ __forceinline__ void zmarch(const Sweep &sw, P &pol, double &acc0, do
     constexpr int PB = decltype(parity)::value;  // parity of the step
     constexpr int SL = 1 - PB;                   // centre slot of the plane consumed / requested at this step
     T(&reg)[NL] = PB ? regB : regA;
+    double(&fr)[NL] = PB ? fB : fA;
     T(*tb)[TX + 2] = tile[PB];
     const int kk = k0 - 1 + step;
 #pragma unroll
@@ -132,20 +146,36 @@ __device__ __forceinline__ void zmarch(const Sweep &sw, P &pol, double &acc0, do
       const int e = tid + m * NT;
       if (e < E) tb[e / W][e % W] = reg[m];
     }
+    if constexpr (R) {
+      double(*tf)[TX + 2] = tileF[PB];
+#pragma unroll
+      for (int m = 0; m < NL; ++m) {
+        const int e = tid + m * NT;
+        if (e < E) tf[e / W][e % W] = fr[m];
+      }
+    }
     __syncthreads();
-    if (step + 2 < np) fetch(reg, kk + 2);
+    if (step + 2 < np) fetch(reg, fr, kk + 2);
     const T c = tb[ly + 1][lx + 1];
     const T x = tb[ly + 1][lx] + tb[ly + 1][lx + 2];
     const T y = tb[ly][lx + 1] + tb[ly + 2][lx + 1];
     const T d = (tb[ly][lx] + tb[ly][lx + 2]) + (tb[ly + 2][lx] + tb[ly + 2][lx + 2]);
+    double fc = 0.0, fg = 0.0;
+    if constexpr (R) {
+      double(*tf)[TX + 2] = tileF[PB];
+      fc = tf[ly + 1][lx + 1];
+      fg = (tf[ly + 1][lx] + tf[ly + 1][lx + 2]) + (tf[ly][lx + 1] + tf[ly + 2][lx + 1]);
+    }
     if (step >= 2 && active) {
       const T out = Pc + cz * (Cm + c) + cxz * (Xm + x) + cyz * (Ym + y);
-      pol.template consume<SL>(i, j, kk - 1, own + (long long)(kk - 1) * g.sz, Cc, out, acc0, acc1);
+      const double rf = 0.5 * (6.0 * Fc + (Gc + (Fm + fc)));
+      pol.template consume<SL>(i, j, kk - 1, own + (long long)(kk - 1) * g.sz, Cc, out, Fc, rf, acc0, acc1);
       if (kk + 1 < k1) pol.template center<SL>(i, j, kk + 1, own + (long long)(kk + 1) * g.sz);
     }
     Cm = Cc; Xm = Xc; Ym = Yc;
     Cc = c; Xc = x; Yc = y;
     Pc = c0 * c + cx * x + cy * y + cxy * d;
+    Fm = Fc; Fc = fc; Gc = fg;
   };
   for (int step = 0; step < np; step += 2) {
     body(std::integral_constant<int, 0>{}, step);
@@ -277,16 +307,21 @@ __device__ void state_ir(CgState *outer, CgState *inner, double r64, double bb, 
 
 template <typename T>
 struct PolA {
+  static constexpr bool kRhs = false;
   const T *r;
   const T *pold;
   T *pnew;
   T beta;
   bool first;
   __device__ __forceinline__ T operand(long long idx) const { return first ? r[idx] : r[idx] + beta * pold[idx]; }
+  __device__ __forceinline__ long long fcol(int, int) const { return -1; }
+  __device__ __forceinline__ long long fplane() const { return 0; }
+  __device__ __forceinline__ double fval(long long) const { return 0.0; }
   template <int S>
   __device__ __forceinline__ void center(int, int, int, long long) {}
   template <int S>
-  __device__ __forceinline__ void consume(int, int, int, long long idx, T c, T out, double &acc0, double &) {
+  __device__ __forceinline__ void consume(int, int, int, long long idx, T c, T out, double, double, double &acc0,
+                                          double &) {
     pnew[idx] = c;
     acc0 += (double)c * (double)out;
   }
@@ -306,26 +341,31 @@ __global__ __launch_bounds__(NT) void cg_pass_a_kernel(Sweep sw, const T *__rest
   pol.first = (it == 0);
   pol.beta = (T)cs->beta;
   double a0 = 0.0, a1 = 0.0;
-  zmarch<T>(sw, pol, a0, a1, tile);
+  zmarch<T>(sw, pol, a0, a1, tile, nullptr);
   const double v[1] = {a0};
   write_partials<1>(v, partials, sh);
 }
 
 template <typename T>
 struct PolB {
+  static constexpr bool kRhs = false;
   const T *p;
   T *u;
   T *r;
   T alpha;
   T pr[2], pu[2];
   __device__ __forceinline__ T operand(long long idx) const { return p[idx]; }
+  __device__ __forceinline__ long long fcol(int, int) const { return -1; }
+  __device__ __forceinline__ long long fplane() const { return 0; }
+  __device__ __forceinline__ double fval(long long) const { return 0.0; }
   template <int S>
   __device__ __forceinline__ void center(int, int, int, long long idx) {
     pr[S] = r[idx];
     pu[S] = u[idx];
   }
   template <int S>
-  __device__ __forceinline__ void consume(int, int, int, long long idx, T c, T out, double &acc0, double &) {
+  __device__ __forceinline__ void consume(int, int, int, long long idx, T c, T out, double, double, double &acc0,
+                                          double &) {
     const T rn = pr[S] - alpha * out;
     r[idx] = rn;
     u[idx] = pu[S] + alpha * c;
@@ -348,28 +388,53 @@ __global__ __launch_bounds__(NT) void cg_pass_b_kernel(Sweep sw, T *u, T *r, con
   pol.pr[0] = pol.pr[1] = 0;
   pol.pu[0] = pol.pu[1] = 0;
   double a0 = 0.0, a1 = 0.0;
-  zmarch<T>(sw, pol, a0, a1, tile);
+  zmarch<T>(sw, pol, a0, a1, tile, nullptr);
   const double v[1] = {a0};
   write_partials<1>(v, partials, sh);
 }
 
-// r = b - M u with b formed on the fly from the finest f, g (rhs_at); u and r share the level layout.
-struct PolResid {
-  const double *u;
+// The right-hand side inside the residual sweeps: f (or the adjoint's G) staged by the z-march (R f from LDS and
+// registers), plus A's couplings to the Dirichlet values for nodes next to the boundary, which a small kernel over
+// the six boundary-adjacent layers (boundary_terms_kernel) has written into r beforehand.
+struct RhsPart {
   RhsSrc rs;
   int nx, ny, nz;
+  const double *bterm;  // the boundary terms (in r's layout, read before r is overwritten at the same node)
+  double bt[2];         // boundary terms of the planes in flight
+  __device__ __forceinline__ long long fcol(int gi, int gj) const { return rs.gf.at(gi * rs.s, gj * rs.s, 0); }
+  __device__ __forceinline__ long long fplane() const { return (long long)rs.s * rs.gf.sz; }
+  __device__ __forceinline__ double fval(long long idx) const { return rs.f[idx]; }
+  template <int S>
+  __device__ __forceinline__ void boundary(int i, int j, int k, long long idx) {
+    const bool near = (i == 1 || j == 1 || k == 1 || i == nx - 1 || j == ny - 1 || k == nz - 1);
+    bt[S] = (rs.mode == 0 && near) ? bterm[idx] : 0.0;
+  }
+  template <int S>
+  __device__ __forceinline__ double b(double cf, double rf) const {
+    return rs.mode == 1 ? cf : -rf + bt[S];
+  }
+};
+
+// r = b - M u; u and r share the level layout.
+struct PolResid {
+  static constexpr bool kRhs = true;
+  const double *u;
   double *r;
-  double pb[2];
+  RhsPart rp;
   __device__ __forceinline__ double operand(long long idx) const { return u[idx]; }
+  __device__ __forceinline__ long long fcol(int gi, int gj) const { return rp.fcol(gi, gj); }
+  __device__ __forceinline__ long long fplane() const { return rp.fplane(); }
+  __device__ __forceinline__ double fval(long long idx) const { return rp.fval(idx); }
   template <int S>
-  __device__ __forceinline__ void center(int i, int j, int k, long long) { pb[S] = rhs_at(rs, nx, ny, nz, i, j, k); }
+  __device__ __forceinline__ void center(int i, int j, int k, long long idx) { rp.template boundary<S>(i, j, k, idx); }
   template <int S>
-  __device__ __forceinline__ void consume(int, int, int, long long idx, double, double out, double &acc0,
-                                          double &acc1) {
-    const double rn = pb[S] - out;
+  __device__ __forceinline__ void consume(int, int, int, long long idx, double, double out, double cf, double rf,
+                                          double &acc0, double &acc1) {
+    const double bv = rp.template b<S>(cf, rf);
+    const double rn = bv - out;
     r[idx] = rn;
     acc0 += rn * rn;
-    acc1 += pb[S] * pb[S];
+    acc1 += bv * bv;
   }
 };
 
@@ -377,61 +442,72 @@ __global__ __launch_bounds__(NT) void residual_kernel(Sweep sw, const double *u,
                                                       double *partials) {
   __shared__ double tile[2][TY + 2][TX + 2];
   __shared__ double sh[NT / 64];
-  PolResid pol{u, rs, sw.g.nx, sw.g.ny, sw.g.nz, r, {0.0, 0.0}};
+  __shared__ double tileF[2][TY + 2][TX + 2];
+  PolResid pol{u, r, RhsPart{rs, sw.g.nx, sw.g.ny, sw.g.nz, r, {0.0, 0.0}}};
   double a0 = 0.0, a1 = 0.0;
-  zmarch<double>(sw, pol, a0, a1, tile);
+  zmarch<double>(sw, pol, a0, a1, tile, tileF);
   const double v[2] = {a0, a1};
   write_partials<2>(v, partials, sh);
 }
 
 // r32 = (float)(b - M u), d32 = 0; the FP32 arrays use their own layout g32.
 struct PolResidCast {
+  static constexpr bool kRhs = true;
   const double *u;
-  RhsSrc rs;
-  int nx, ny, nz;
   Grid g32;
   float *r32;
   float *d32;
-  double pb[2];
+  RhsPart rp;
   double acc2;  // sum of the squared FP32-rounded residual
   __device__ __forceinline__ double operand(long long idx) const { return u[idx]; }
+  __device__ __forceinline__ long long fcol(int gi, int gj) const { return rp.fcol(gi, gj); }
+  __device__ __forceinline__ long long fplane() const { return rp.fplane(); }
+  __device__ __forceinline__ double fval(long long idx) const { return rp.fval(idx); }
   template <int S>
-  __device__ __forceinline__ void center(int i, int j, int k, long long) { pb[S] = rhs_at(rs, nx, ny, nz, i, j, k); }
+  __device__ __forceinline__ void center(int i, int j, int k, long long idx) { rp.template boundary<S>(i, j, k, idx); }
   template <int S>
-  __device__ __forceinline__ void consume(int i, int j, int k, long long, double, double out, double &acc0,
-                                          double &acc1) {
-    const double rn = pb[S] - out;
-    const float rf = (float)rn;
+  __device__ __forceinline__ void consume(int i, int j, int k, long long, double, double out, double cf, double rf,
+                                          double &acc0, double &acc1) {
+    const double bv = rp.template b<S>(cf, rf);
+    const double rn = bv - out;
+    const float rf32 = (float)rn;
     const long long q = g32.at(i, j, k);
-    r32[q] = rf;
+    r32[q] = rf32;
     d32[q] = 0.0f;
     acc0 += rn * rn;
-    acc1 += pb[S] * pb[S];
-    acc2 += (double)rf * (double)rf;
+    acc1 += bv * bv;
+    acc2 += (double)rf32 * (double)rf32;
   }
 };
 
-__global__ __launch_bounds__(NT) void residual_cast_kernel(Sweep sw, const double *u, RhsSrc rs, Grid g32, float *r32,
-                                                           float *d32, double *partials) {
+__global__ __launch_bounds__(NT) void residual_cast_kernel(Sweep sw, const double *u, RhsSrc rs,
+                                                           const double *bterm, Grid g32, float *r32, float *d32,
+                                                           double *partials) {
   __shared__ double tile[2][TY + 2][TX + 2];
   __shared__ double sh[NT / 64];
-  PolResidCast pol{u, rs, sw.g.nx, sw.g.ny, sw.g.nz, g32, r32, d32, {0.0, 0.0}, 0.0};
+  __shared__ double tileF[2][TY + 2][TX + 2];
+  PolResidCast pol{u, g32, r32, d32, RhsPart{rs, sw.g.nx, sw.g.ny, sw.g.nz, bterm, {0.0, 0.0}}, 0.0};
   double a0 = 0.0, a1 = 0.0;
-  zmarch<double>(sw, pol, a0, a1, tile);
+  zmarch<double>(sw, pol, a0, a1, tile, tileF);
   const double v[3] = {a0, a1, pol.acc2};
   write_partials<3>(v, partials, sh);
 }
 
 // y = M x with x and y in possibly different layouts.
 struct PolApply {
+  static constexpr bool kRhs = false;
   const double *x;
   Grid gy;
   double *y;
   __device__ __forceinline__ double operand(long long idx) const { return x[idx]; }
+  __device__ __forceinline__ long long fcol(int, int) const { return -1; }
+  __device__ __forceinline__ long long fplane() const { return 0; }
+  __device__ __forceinline__ double fval(long long) const { return 0.0; }
   template <int S>
   __device__ __forceinline__ void center(int, int, int, long long) {}
   template <int S>
-  __device__ __forceinline__ void consume(int i, int j, int k, long long, double, double out, double &, double &) {
+  __device__ __forceinline__ void consume(int i, int j, int k, long long, double, double out, double, double,
+                                          double &, double &) {
     y[gy.at(i, j, k)] = out;
   }
 };
@@ -440,7 +516,27 @@ __global__ __launch_bounds__(NT) void apply_kernel(Sweep sw, const double *x, Gr
   __shared__ double tile[2][TY + 2][TX + 2];
   PolApply pol{x, gy, y};
   double a0 = 0.0, a1 = 0.0;
-  zmarch<double>(sw, pol, a0, a1, tile);
+  zmarch<double>(sw, pol, a0, a1, tile, nullptr);
+}
+
+// A's couplings to the Dirichlet values, written at every interior node next to the boundary (the six layers
+// i = 1, i = nx-1, j = 1, ...; nodes on two layers are written twice with the same value).  blockIdx.z = layer.
+__global__ void boundary_terms_kernel(RhsSrc rs, Grid g, double *out) {
+  const int layer = blockIdx.z;  // 0,1: x layers; 2,3: y layers; 4,5: z layers
+  const int a = 1 + blockIdx.x * blockDim.x + threadIdx.x;
+  const int b = 1 + blockIdx.y;
+  int i, j, k;
+  if (layer < 2) {
+    if (a >= g.ny || b >= g.nz) return;
+    i = layer == 0 ? 1 : g.nx - 1; j = a; k = b;
+  } else if (layer < 4) {
+    if (a >= g.nx || b >= g.nz) return;
+    i = a; j = layer == 2 ? 1 : g.ny - 1; k = b;
+  } else {
+    if (a >= g.nx || b >= g.ny) return;
+    i = a; j = b; k = layer == 4 ? 1 : g.nz - 1;
+  }
+  out[g.at(i, j, k)] = rhs_boundary_terms(rs, g.nx, g.ny, g.nz, i, j, k);
 }
 
 // --------------------------------------------------------------------------------------------------------- finalize
@@ -662,18 +758,27 @@ long long cg_partials_needed(const Grid &g) {
   return 3LL * sweep_blocks(sw) + 64;
 }
 
+static void launch_boundary_terms(const RhsSrc &rs, const Grid &g, double *out, hipStream_t st) {
+  if (rs.mode != 0) return;
+  const int m = (g.nx > g.ny ? (g.nx > g.nz ? g.nx : g.nz) : (g.ny > g.nz ? g.ny : g.nz)) - 1;
+  dim3 grid((m + 255) / 256, m, 6);
+  boundary_terms_kernel<<<grid, 256, 0, st>>>(rs, g, out);
+}
+
 void launch_residual(const Sweep &sw, const double *u, const RhsSrc &rs, double *r, CgState *cs, double *partials,
                      double tol, int max_iters, int hist_on, hipStream_t st) {
   const int nb = sweep_blocks(sw);
+  launch_boundary_terms(rs, sw.g, r, st);
   residual_kernel<<<nb, NT, 0, st>>>(sw, u, rs, r, partials);
   finalize_init_kernel<<<1, FT, 0, st>>>(cs, partials, nb, tol, max_iters, hist_on);
 }
 
-void launch_residual_cast(const Sweep &sw, const double *u, const RhsSrc &rs, const Grid &g32, float *r32,
-                          float *d32, CgState *outer, CgState *inner, double *partials, double tol, double eta,
-                          int outer_step, int max_outer, int max_inner, hipStream_t st) {
+void launch_residual_cast(const Sweep &sw, const double *u, const RhsSrc &rs, double *bterm, const Grid &g32,
+                          float *r32, float *d32, CgState *outer, CgState *inner, double *partials, double tol,
+                          double eta, int outer_step, int max_outer, int max_inner, hipStream_t st) {
   const int nb = sweep_blocks(sw);
-  residual_cast_kernel<<<nb, NT, 0, st>>>(sw, u, rs, g32, r32, d32, partials);
+  launch_boundary_terms(rs, sw.g, bterm, st);
+  residual_cast_kernel<<<nb, NT, 0, st>>>(sw, u, rs, bterm, g32, r32, d32, partials);
   finalize_ir_kernel<<<1, FT, 0, st>>>(outer, inner, partials, nb, tol, eta, outer_step, max_outer, max_inner);
 }
 

@@ -32,21 +32,52 @@ __device__ __forceinline__ void line_solve(const double *__restrict__ u, long lo
   const double s3 = 3.0 / h;
   double um = U(0), uc = U(1);
   double dprev = 0.0;
-  for (int t = 1; t <= N - 1; ++t) {
+  constexpr int UN = 8;  // loads issued ahead of the dependent elimination chain
+  int t = 1;
+  for (; t + UN - 1 <= N - 1; t += UN) {
+    double up[UN];
+#pragma unroll
+    for (int q = 0; q < UN; ++q) up[q] = U(t + q + 1);
+#pragma unroll
+    for (int q = 0; q < UN; ++q) {
+      const int tt = t + q;
+      double rhs = s3 * (up[q] - um);
+      if (tt == 1) rhs -= v0;
+      if (tt == N - 1) rhs -= vN;
+      const double d = (rhs - dprev) * inv_m[tt];
+      out[odx0 + (long long)tt * so] = d;
+      dprev = d;
+      um = uc;
+      uc = up[q];
+    }
+  }
+  for (; t <= N - 1; ++t) {
     const double up = U(t + 1);
     double rhs = s3 * (up - um);
     if (t == 1) rhs -= v0;
     if (t == N - 1) rhs -= vN;
-    const double d = (rhs - (t > 1 ? dprev : 0.0)) * inv_m[t];
+    const double d = (rhs - dprev) * inv_m[t];
     out[odx0 + (long long)t * so] = d;
     dprev = d;
     um = uc;
     uc = up;
   }
   double vnext = out[odx0 + (long long)(N - 1) * so];
-  for (int t = N - 2; t >= 1; --t) {
-    const double v = out[odx0 + (long long)t * so] - inv_m[t] * vnext;
-    out[odx0 + (long long)t * so] = v;
+  int tb = N - 2;
+  for (; tb - UN + 1 >= 1; tb -= UN) {
+    double dd[UN];
+#pragma unroll
+    for (int q = 0; q < UN; ++q) dd[q] = out[odx0 + (long long)(tb - q) * so];
+#pragma unroll
+    for (int q = 0; q < UN; ++q) {
+      const double v = dd[q] - inv_m[tb - q] * vnext;
+      out[odx0 + (long long)(tb - q) * so] = v;
+      vnext = v;
+    }
+  }
+  for (; tb >= 1; --tb) {
+    const double v = out[odx0 + (long long)tb * so] - inv_m[tb] * vnext;
+    out[odx0 + (long long)tb * so] = v;
     vnext = v;
   }
 }
@@ -100,17 +131,30 @@ __global__ __launch_bounds__(XL) void grad_x_kernel(Grid gu, const double *__res
   __syncthreads();
   const double s3 = 3.0 / hx;
   double dprev = 0.0;
-  // forward elimination, chunk by chunk over the interior x = 1..N-1
-  for (int x0 = 1; x0 <= N - 1; x0 += XC) {
-    const int wn = min(XC, N - x0);  // interior values in this chunk
-    // stage u[x0-1 .. x0+XC] of every line; consecutive threads read consecutive x of a line
-    for (int e = t; e < XL * (XC + 2); e += XL) {
+  // forward elimination, chunk by chunk over the interior x = 1..N-1; the next chunk's u is loaded into registers
+  // while the current chunk is swept
+  constexpr int PER = (XL * (XC + 2) + XL - 1) / XL;  // staged values per thread and chunk
+  double nxt[PER];
+  auto load_chunk = [&](int x0) {
+#pragma unroll
+    for (int m = 0; m < PER; ++m) {
+      const int e = t + m * XL;
       const int ln = e / (XC + 2), xx = e % (XC + 2);
       double v = 0.0;
-      if (ln < nl && x0 - 1 + xx <= N) v = u[ub[ln] + x0 - 1 + xx];
-      tu[ln][xx] = v;
+      if (e < XL * (XC + 2) && ln < nl && x0 - 1 + xx <= N) v = u[ub[ln] + x0 - 1 + xx];
+      nxt[m] = v;
+    }
+  };
+  load_chunk(1);
+  for (int x0 = 1; x0 <= N - 1; x0 += XC) {
+    const int wn = min(XC, N - x0);  // interior values in this chunk
+#pragma unroll
+    for (int m = 0; m < PER; ++m) {
+      const int e = t + m * XL;
+      if (e < XL * (XC + 2)) tu[e / (XC + 2)][e % (XC + 2)] = nxt[m];
     }
     __syncthreads();
+    if (x0 + XC <= N - 1) load_chunk(x0 + XC);
     if (act) {
       for (int q = 0; q < wn; ++q) {
         const int x = x0 + q;

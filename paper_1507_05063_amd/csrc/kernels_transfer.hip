@@ -65,11 +65,16 @@ __constant__ double kQw[4][5] = {
     {-5.0 / 128, 28.0 / 128, -70.0 / 128, 140.0 / 128, 35.0 / 128},
 };
 
-constexpr int CXN = 4;               // interpolation cells per workgroup along x
+constexpr int CXN = 8;               // interpolation cells per workgroup along x
 constexpr int EX2 = 4 * CXN + 1;     // 2h nodes along x in the workgroup's slab
 constexpr int EX4 = 2 * CXN + 1;     // 4h nodes along x
 constexpr int EXF = 8 * CXN + 1;     // fine nodes along x
 constexpr int ET = 256;
+
+// quartic interpolation of five values at the odd offset t (0..3 for offsets 1, 3, 5, 7)
+__device__ __forceinline__ double quartic(int t, double a0, double a1, double a2, double a3, double a4) {
+  return kQw[t][0] * a0 + kQw[t][1] * a1 + kQw[t][2] * a2 + kQw[t][3] * a3 + kQw[t][4] * a4;
+}
 
 // One workgroup per CXN x 1 x 1 interpolation cells.
 //  1. stage u_2h on the 5x5x(4CXN+1) 2h nodes and delta = u_2h - u_4h on the 3x3x(2CXN+1) 4h nodes in LDS;
@@ -78,8 +83,10 @@ constexpr int ET = 256;
 //     (zhongdian), at face and element centres the mean over the 2 face / 4 space diagonals of eq. (zhongdian): all
 //     four rules are the same tri-linear interpolation of delta with the factor 1/16;
 //  3. tri-quartic interpolation (eq. inter) applied separably, x then y then z (the 604x125 cell matrix is the
-//     tensor product of the 1D quartic weights);
-//  4. write the cell's nodes; boundary nodes get g.
+//     tensor product of the 1D quartic weights): the x pass through LDS, then one thread per (x, z-layer) column
+//     for the y pass and one thread per (x, y) column for the z pass, each holding its five known values in
+//     registers and producing its nine outputs;
+//  4. boundary nodes get g.
 __global__ __launch_bounds__(ET) void exp_finite_kernel(Grid g2, const double *__restrict__ u2, Grid g4,
                                                         const double *__restrict__ u4, Grid gg,
                                                         const double *__restrict__ gdat, int s, Grid gw,
@@ -125,47 +132,53 @@ __global__ __launch_bounds__(ET) void exp_finite_kernel(Grid g2, const double *_
     if (!(xf & 1)) {
       v = W[c][b][xf >> 1];
     } else {
-      const int base = (xf >> 3) * 4, t = (xf & 7) >> 1;
-      v = kQw[t][0] * W[c][b][base] + kQw[t][1] * W[c][b][base + 1] + kQw[t][2] * W[c][b][base + 2] +
-          kQw[t][3] * W[c][b][base + 3] + kQw[t][4] * W[c][b][base + 4];
+      const int base = (xf >> 3) * 4;
+      v = quartic((xf & 7) >> 1, W[c][b][base], W[c][b][base + 1], W[c][b][base + 2], W[c][b][base + 3],
+                  W[c][b][base + 4]);
     }
     Wx[c][b][xf] = v;
   }
   __syncthreads();
-  // 3b. y
-  for (int e = tid; e < 45 * EXF; e += ET) {
-    const int xf = e % EXF, yc = e / EXF, yf = yc % 9, c = yc / 9;
+  // 3b. y: one thread per (xf, c) column
+  for (int e = tid; e < 5 * EXF; e += ET) {
+    const int xf = e % EXF, c = e / EXF;
     if (xf >= nfx) continue;
-    double v;
-    if (!(yf & 1)) {
-      v = Wx[c][yf >> 1][xf];
-    } else {
-      const int t = yf >> 1;
-      v = kQw[t][0] * Wx[c][0][xf] + kQw[t][1] * Wx[c][1][xf] + kQw[t][2] * Wx[c][2][xf] + kQw[t][3] * Wx[c][3][xf] +
-          kQw[t][4] * Wx[c][4][xf];
-    }
-    Wxy[c][yf][xf] = v;
+    const double a0 = Wx[c][0][xf], a1 = Wx[c][1][xf], a2 = Wx[c][2][xf], a3 = Wx[c][3][xf], a4 = Wx[c][4][xf];
+    Wxy[c][0][xf] = a0;
+    Wxy[c][1][xf] = quartic(0, a0, a1, a2, a3, a4);
+    Wxy[c][2][xf] = a1;
+    Wxy[c][3][xf] = quartic(1, a0, a1, a2, a3, a4);
+    Wxy[c][4][xf] = a2;
+    Wxy[c][5][xf] = quartic(2, a0, a1, a2, a3, a4);
+    Wxy[c][6][xf] = a3;
+    Wxy[c][7][xf] = quartic(3, a0, a1, a2, a3, a4);
+    Wxy[c][8][xf] = a4;
   }
   __syncthreads();
-  // 3c. z and 4. write: a workgroup owns offsets [0,8) on each axis, plus offset 8 at the grid's far faces
+  // 3c. z and 4. write, one thread per (xf, yf) column: a workgroup owns offsets [0,8) on each axis, plus offset 8 at
+  // the grid's far faces
   const bool lastx = (cx0 + nc == ncx), lasty = (cj == ncy - 1), lastz = (ck == ncz - 1);
   const int ox = lastx ? nfx : nfx - 1, oy = lasty ? 9 : 8, oz = lastz ? 9 : 8;
   const int gi0 = 8 * cx0, gj0 = 8 * cj, gk0 = 8 * ck;
-  for (int e = tid; e < EXF * 81; e += ET) {
-    const int xf = e % EXF, yz = e / EXF, yf = yz % 9, zf = yz / 9;
-    if (xf >= ox || yf >= oy || zf >= oz) continue;
-    const int gi = gi0 + xf, gj = gj0 + yf, gk = gk0 + zf;
-    double v;
-    if (on_boundary(gi, gj, gk, gw.nx, gw.ny, gw.nz)) {
-      v = gdat ? gdat[gg.at(gi * s, gj * s, gk * s)] : 0.0;
-    } else if (!(zf & 1)) {
-      v = Wxy[zf >> 1][yf][xf];
-    } else {
-      const int t = zf >> 1;
-      v = kQw[t][0] * Wxy[0][yf][xf] + kQw[t][1] * Wxy[1][yf][xf] + kQw[t][2] * Wxy[2][yf][xf] +
-          kQw[t][3] * Wxy[3][yf][xf] + kQw[t][4] * Wxy[4][yf][xf];
+  for (int e = tid; e < 9 * EXF; e += ET) {
+    const int xf = e % EXF, yf = e / EXF;
+    if (xf >= ox || yf >= oy) continue;
+    const int gi = gi0 + xf, gj = gj0 + yf;
+    const double a0 = Wxy[0][yf][xf], a1 = Wxy[1][yf][xf], a2 = Wxy[2][yf][xf], a3 = Wxy[3][yf][xf],
+                 a4 = Wxy[4][yf][xf];
+    const bool side = (gi == 0 || gj == 0 || gi == gw.nx || gj == gw.ny);
+    for (int zf = 0; zf < oz; ++zf) {
+      const int gk = gk0 + zf;
+      double v;
+      if (side || gk == 0 || gk == gw.nz) {
+        v = gdat ? gdat[gg.at(gi * s, gj * s, gk * s)] : 0.0;
+      } else if (!(zf & 1)) {
+        v = (zf == 0) ? a0 : (zf == 2) ? a1 : (zf == 4) ? a2 : (zf == 6) ? a3 : a4;
+      } else {
+        v = quartic(zf >> 1, a0, a1, a2, a3, a4);
+      }
+      w[gw.at(gi, gj, gk)] = v;
     }
-    w[gw.at(gi, gj, gk)] = v;
   }
 }
 
