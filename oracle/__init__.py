@@ -69,6 +69,8 @@ def lib():
         L.orc_lagrange4.restype = _D
         L.orc_set_threads.argtypes = [_I]
         L.orc_set_threads.restype = None
+        L.orc_set_progress.argtypes = [_I]
+        L.orc_set_progress.restype = None
         L.orc_get_threads.argtypes = []
         L.orc_get_threads.restype = _I
         _lib = L
@@ -105,6 +107,11 @@ def _c(a):
 
 def set_threads(n: int):
     lib().orc_set_threads(int(n))
+
+
+def set_progress(on: bool):
+    """Print a line on stderr after each grid of a cascade."""
+    lib().orc_set_progress(int(bool(on)))
 
 
 def get_threads() -> int:

