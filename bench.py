@@ -36,8 +36,126 @@ def unknown_iters(st):
     return tot
 
 
+def trace_summary(db, top=30):
+    """Per-kernel summary of a rocprofv3 database (kernel trace and/or counters), grouped by kernel and grid size.
+    A CG launch made after its grid converged returns at once; launches shorter than a fifth of the longest of their
+    group are counted as such early exits and left out of the 'working' average."""
+    import re
+    import sqlite3
+
+    c = sqlite3.connect(db)
+
+    def clean(nm):
+        nm = nm.replace("excmg::(anonymous namespace)::", "").replace("void ", "")
+        return re.sub(r"\(.*", "", nm)[:44]
+
+    rows = c.execute("select name, grid_x, workgroup_x, duration from kernels").fetchall()
+    if rows:
+        groups = {}
+        for nm, gx, wx, d in rows:
+            groups.setdefault((clean(nm), gx, wx), []).append(d)
+        tot = sum(d for _, _, _, d in rows)
+        print(f"kernel trace: {len(rows)} dispatches, {tot / 1e6:.3f} ms of kernel time")
+        print(f"{'kernel':44s} {'grid':>9s} {'wg':>5s} {'calls':>6s} {'total_ms':>9s} {'avg_us':>9s} "
+              f"{'working':>7s} {'work_avg_us':>11s}")
+        for (nm, gx, wx), ds in sorted(groups.items(), key=lambda kv: -sum(kv[1]))[:top]:
+            w = [d for d in ds if d >= 0.2 * max(ds)]
+            print(f"{nm:44s} {gx:9d} {wx:5d} {len(ds):6d} {sum(ds) / 1e6:9.3f} {sum(ds) / len(ds) / 1e3:9.2f} "
+                  f"{len(w):7d} {sum(w) / len(w) / 1e3:11.2f}")
+    pm = c.execute("select kernel_name, grid_size, counter_name, value from counters_collection").fetchall()
+    if pm:
+        groups = {}
+        for nm, gx, cn, v in pm:
+            groups.setdefault((clean(nm), gx, cn), []).append(v)
+        print("counters (per dispatch; 'working' = dispatches with at least a fifth of the group's largest value)")
+        print(f"{'kernel':44s} {'grid':>9s} {'counter':>12s} {'calls':>6s} {'working':>7s} {'work_avg':>14s}")
+        for (nm, gx, cn), vs in sorted(groups.items(), key=lambda kv: -max(kv[1]))[:top]:
+            w = [v for v in vs if v >= 0.2 * max(vs)]
+            print(f"{nm:44s} {gx:9d} {cn:>12s} {len(vs):6d} {len(w):7d} {sum(w) / max(len(w), 1):14.1f}")
+
+
+def _timed(torch, fn, reps):
+    """Median wall time (ms) of reps calls of fn after one warm-up call."""
+    fn()
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        r = fn()
+        torch.cuda.synchronize()
+        ts.append((time.perf_counter() - t0) * 1e3)
+    return float(np.median(ts)), r
+
+
+def bench_aniso(ex, synth, torch, args):
+    """1024 x 512 x 256 cells (hx : hy : hz = 1 : 2 : 4), 8 grids from 8 x 4 x 2, tol 1e-10: FP64 against the FP32
+    refinement, both against the exact field."""
+    n = (1024, 512, 256)
+    p = synth.smooth(0)
+    f_np, g_np, u_np = synth.sample(p, n)
+    f, g = torch.from_numpy(f_np).cuda(), torch.from_numpy(g_np).cuda()
+    del f_np, g_np
+    res = {"cells": list(n), "n_coarse": [8, 4, 2]}
+    sol = {}
+    for name, prec in (("fp64", ex.FP64), ("fp32_ir", ex.FP32_IR)):
+        s = ex.Solver(n, p.box, args.tol, n_coarse=(8, 4, 2), precision=prec)
+        s.autotune()
+        u = s.empty()
+        ms, (_, _, st) = _timed(torch, lambda: s.solve(f, g, u=u), max(2, args.steps // 2))
+        uh = u.cpu().numpy()
+        sol[name] = uh
+        res[name] = {"solve_ms": round(ms, 3), "iters": st["iters"], "ir_outer": st["ir_outer"],
+                     "max_error_vs_exact": float(np.max(np.abs(uh - u_np)))}
+        del s, u
+    res["rel_l2_fp32_ir_vs_fp64"] = float(np.linalg.norm(sol["fp32_ir"] - sol["fp64"]) / np.linalg.norm(sol["fp64"]))
+    res["speedup_fp32_ir"] = round(res["fp64"]["solve_ms"] / res["fp32_ir"]["solve_ms"], 3)
+    return res
+
+
+def bench_batch(ex, synth, torch, args):
+    """96 problems (master seed 4), cells per axis from {32, 64, 96, 128, 192}, box edges U(0.5, 2), coarsest N/16,
+    FP32 refinement, tol 1e-10, one batched call per step."""
+    cases = synth.batch(4, 96)
+    solvers, fs, gs = [], [], []
+    for n, p in cases:
+        f, g, _ = synth.sample(p, n)
+        solvers.append(ex.Solver(n, p.box, args.tol, n_coarse=tuple(v // 16 for v in n), precision=ex.FP32_IR))
+        fs.append(torch.from_numpy(f).cuda())
+        gs.append(torch.from_numpy(g).cuda())
+    us = [s.empty() for s in solvers]
+    ws = torch.empty(ex.batch_workspace_bytes(len(solvers)), dtype=torch.uint8, device="cuda")
+    ms, (_, stats, per) = _timed(torch, lambda: ex.solve_batched(solvers, fs, gs, us=us, workspace=ws), args.steps)
+    seq_ms, _ = _timed(torch, lambda: [s.solve(f, g, u=u) for s, f, g, u in zip(solvers, fs, gs, us)], 1)
+    unknowns = sum((n[0] - 1) * (n[1] - 1) * (n[2] - 1) for n, _ in cases)
+    ui = sum(sum((a - 1) * (b - 1) * (c - 1) * it for (a, b, c), it in zip(st["n"], st["iters"])) for st in stats)
+    per = np.array(per)
+    return {"problems": len(cases), "finest_unknowns": unknowns, "batch_ms": round(ms, 3),
+            "problems_per_s": round(len(cases) / (ms * 1e-3), 1),
+            "p50_ms": round(float(np.percentile(per, 50)), 3), "p99_ms": round(float(np.percentile(per, 99)), 3),
+            "gunknown_iters_per_s": round(ui / (ms * 1e-3) / 1e9, 3),
+            "one_at_a_time_ms": round(seq_ms, 3), "speedup_vs_one_at_a_time": round(seq_ms / ms, 2)}
+
+
+def bench_adjoint(ex, synth, torch, args):
+    """256^3 cells, FP64, tol 1e-10: forward solve and the adjoint (backward) solve with the two transposes."""
+    n = (256, 256, 256)
+    p = synth.smooth(0)
+    f_np, g_np, _ = synth.sample(p, n)
+    _, _, ut_np = synth.sample(synth.smooth(5), n)
+    f, g, ut = (torch.from_numpy(a).cuda() for a in (f_np, g_np, ut_np))
+    s = ex.Solver(n, p.box, args.tol)
+    s.autotune()
+    u = s.empty()
+    fwd_ms, _ = _timed(torch, lambda: s.solve(f, g, u=u), args.steps)
+    G = u - ut
+    bwd_ms, (_, _, _, st) = _timed(torch, lambda: s.adjoint(G), args.steps)
+    return {"cells": list(n), "forward_ms": round(fwd_ms, 3), "adjoint_ms": round(bwd_ms, 3),
+            "adjoint_iters": st["iters"]}
+
+
 def main():
     ap = argparse.ArgumentParser()
+    ap.add_argument("--trace-summary", metavar="DB", help="print a summary of a rocprofv3 database and exit")
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
@@ -46,7 +164,13 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=10.0, help="CPU work of the oracle's timed sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-aniso", action="store_true", help="skip the 1024x512x256 FP64 / FP32-refinement section")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 96-problem batched section")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the 256^3 adjoint section")
     args = ap.parse_args()
+    if args.trace_summary:
+        trace_summary(args.trace_summary)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU z-slab form of this "
               "solver is a design, not a build", file=sys.stderr)
@@ -164,6 +288,16 @@ def main():
         }
         del sm
         print(f"# mixed solve {ms_m:.2f} ms", file=sys.stderr, flush=True)
+
+    if not args.no_aniso:
+        out["aniso"] = bench_aniso(ex, synth, torch, args)
+        print(f"# aniso: {out['aniso']}", file=sys.stderr, flush=True)
+    if not args.no_batch:
+        out["batch"] = bench_batch(ex, synth, torch, args)
+        print(f"# batch: {out['batch']}", file=sys.stderr, flush=True)
+    if not args.no_adjoint:
+        out["adjoint"] = bench_adjoint(ex, synth, torch, args)
+        print(f"# adjoint: {out['adjoint']}", file=sys.stderr, flush=True)
 
     if not args.no_cpu_baseline:
         # the oracle timed on the same step (solve with EXP_true, then the gradient) of the same inputs, repeated

@@ -137,13 +137,25 @@ int excmg_gradient(excmg_handle *h, const double *u, double *ux, double *uy, dou
 int excmg_adjoint(excmg_handle *h, const double *G, double *dLdf, double *dLdg, double *lambda_out,
                   excmg_stats *stats);
 
-/* Many independent problems at once: handles hs[0..count-1] (each with its own workspace; all on the stream of
- * hs[0]), problem b reads f[b], g[b] and writes u[b] (node arrays of its own shape).  Every problem must use
- * EXCMG_FP32_IR or every problem EXCMG_FP64.  The relaxation of all problems on the same cascade level runs in
- * shared persistent launches.  stats (host, nullable): count entries.  ms_per_problem (host, nullable): count
- * entries, the time from the batch's start until problem b's last grid converged (device timestamps). */
+/* Host only.  Bytes of device workspace excmg_solve_batched needs for a batch of count problems (the per-step
+ * problem tables and the per-problem status words; about 20 KB per problem). */
+int excmg_batch_workspace_bytes(int32_t count, size_t *bytes);
+
+/* Many independent problems at once (Algorithm 1 for each): handles hs[0..count-1], each with its own workspace,
+ * all set up on the same device; problem b reads f[b], g[b] and writes u[b] (node arrays of its own shape, as for
+ * excmg_solve).  All work is enqueued on the stream of hs[0]; work the caller has queued for the other handles on
+ * other streams must be complete.  The cascades run in step, grid s of every problem in step s: each kernel launch
+ * covers every problem it concerns (the workgroups of one launch are split among the problems), so a batch costs
+ * about as many launches as its largest problem.  Each problem keeps its own precision, tolerance and iteration
+ * limits; the history and timing flags are ignored.
+ * batch_ws: device memory of at least excmg_batch_workspace_bytes(count), 256-byte aligned, owned by the caller.
+ * stats (host, nullable): count entries (ms_total = the host time of the whole call).  ms_per_problem (host,
+ * nullable): count entries, the device time from the start of the batch until problem b's finest grid converged.
+ * Returns the first error met (the batch stops), else EXCMG_ERR_NOCONV if a problem hit its iteration limit, else
+ * EXCMG_OK. */
 int excmg_solve_batched(excmg_handle *const *hs, int32_t count, const double *const *f, const double *const *g,
-                        double *const *u, excmg_stats *stats, double *ms_per_problem);
+                        double *const *u, void *batch_ws, size_t batch_bytes, excmg_stats *stats,
+                        double *ms_per_problem);
 
 /* Autotuner (host call, device work on the handle's stream): times the two CG sweep kernels of every relaxed grid
  * (FP64, and FP32 where EXCMG_FP32_IR relaxes in FP32) for each z-chunk length in {2, 4, ..., 64} planes per

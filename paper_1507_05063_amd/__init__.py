@@ -14,7 +14,8 @@ from . import _lib
 from ._lib import ExcmgError, FP32_IR, FP64, K_CLASSES, LIB_PATH, WANT_HISTORY, WANT_TIMING
 
 __all__ = ["Solver", "ExcmgError", "FP64", "FP32_IR", "plan", "workspace_bytes", "op_apply", "op_rhs",
-           "op_exp_finite", "op_exp_true", "solve_batched", "bandwidth_probe", "K_CLASSES", "LIB_PATH"]
+           "op_exp_finite", "op_exp_true", "solve_batched", "batch_workspace_bytes", "bandwidth_probe", "K_CLASSES",
+           "LIB_PATH"]
 
 
 def _torch():
@@ -156,18 +157,38 @@ class Solver:
             pass
 
 
-def solve_batched(solvers, fs, gs, us=None):
-    """Solve many problems (each with its own Solver) in one call.  Returns (us, stats list, ms_per_problem)."""
+def batch_workspace_bytes(count: int) -> int:
+    b = ctypes.c_size_t(0)
+    _lib.check(_lib.lib().excmg_batch_workspace_bytes(int(count), ctypes.byref(b)), "excmg_batch_workspace_bytes")
+    return int(b.value)
+
+
+def solve_batched(solvers, fs, gs, us=None, workspace=None, allow_noconv: bool = False):
+    """Solve many problems (each bound to its own Solver) in one batched call on the stream of solvers[0].
+    Returns (us, stats list, ms_per_problem list): ms_per_problem[b] is the device time from the start of the batch
+    until problem b's finest grid converged."""
+    torch = _torch()
     count = len(solvers)
+    if count == 0 or len(fs) != count or len(gs) != count:
+        raise ValueError("solvers, fs and gs must have the same nonzero length")
+    for s, f, g in zip(solvers, fs, gs):
+        _check_nodes(f, s.n, "f")
+        _check_nodes(g, s.n, "g")
     us = [s.empty() for s in solvers] if us is None else us
+    for s, u in zip(solvers, us):
+        _check_nodes(u, s.n, "u")
+    nbytes = batch_workspace_bytes(count)
+    if workspace is None or workspace.numel() < nbytes:
+        workspace = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
     H = (ctypes.c_void_p * count)(*[s.handle.value for s in solvers])
     F = (ctypes.c_void_p * count)(*[f.data_ptr() for f in fs])
     G = (ctypes.c_void_p * count)(*[g.data_ptr() for g in gs])
     U = (ctypes.c_void_p * count)(*[u.data_ptr() for u in us])
     st = (_lib.Stats * count)()
     ms = (ctypes.c_double * count)()
-    code = _lib.lib().excmg_solve_batched(H, count, F, G, U, st, ms)
-    _lib.check(code, "excmg_solve_batched")
+    code = _lib.lib().excmg_solve_batched(H, count, F, G, U, _ptr(workspace), ctypes.c_size_t(workspace.numel()), st,
+                                          ms)
+    _lib.check(code, "excmg_solve_batched", allow=(_lib.ERR_NOCONV,) if allow_noconv else ())
     return us, [st[b].to_dict() for b in range(count)], [ms[b] for b in range(count)]
 
 

@@ -101,8 +101,10 @@ def lib():
             "excmg_solve": ([_P, _P, _P, _P, _P, ctypes.POINTER(Stats)], _I),
             "excmg_gradient": ([_P, _P, _P, _P, _P], _I),
             "excmg_adjoint": ([_P, _P, _P, _P, _P, ctypes.POINTER(Stats)], _I),
+            "excmg_batch_workspace_bytes": ([ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)], _I),
             "excmg_solve_batched": ([ctypes.POINTER(_P), ctypes.c_int32, ctypes.POINTER(_P), ctypes.POINTER(_P),
-                                     ctypes.POINTER(_P), ctypes.POINTER(Stats), ctypes.POINTER(ctypes.c_double)], _I),
+                                     ctypes.POINTER(_P), _P, ctypes.c_size_t, ctypes.POINTER(Stats),
+                                     ctypes.POINTER(ctypes.c_double)], _I),
             "excmg_destroy": ([_P], None),
             "excmg_autotune": ([_P, _I32P], _I),
             "excmg_bandwidth_probe": ([_P, ctypes.c_size_t, ctypes.c_int32, _P, ctypes.POINTER(ctypes.c_double),

@@ -563,6 +563,235 @@ void clear_stats(excmg_stats *st) {
   if (st) memset(st, 0, sizeof(*st));
 }
 
+// ------------------------------------------------------------------------------------------------ batched solve
+//
+// All problems of a batch walk their cascades in step: step s treats grid s of every problem that has one.  Each
+// step is a table of entries (one per problem) in the batch workspace, built on the host and uploaded once; every
+// launch of the step covers all problems it concerns (flattened workgroup ranges, or one workgroup per problem),
+// so a step costs the same number of launches as one problem's grid.  Per step: boundary values (grids 0, 1) or
+// EXP_finite (grids >= 2); the single-workgroup CG of every small grid; then the FP64 CG of the grids relaxed in
+// FP64 and the refinement loop of those relaxed in FP32, each iterating until all its problems have converged
+// (converged problems' workgroups return at once); finally the copy of finished problems to the caller's arrays.
+
+size_t batch_table_bytes(int count) {
+  return align256(sizeof(BatchEntry) * (size_t)count) + align256(sizeof(int) * (size_t)kLaunchKinds * (count + 1));
+}
+
+size_t batch_ws_bytes(int count) {
+  return align256(sizeof(BatchStatus) * (size_t)count) + 256 + (size_t)EXCMG_MAX_LEVELS * batch_table_bytes(count);
+}
+
+int batch_kind(const excmg_handle *h, int l) {
+  if (l >= h->lo.L) return kBNone;
+  const Level &lv = h->lo.lev[l];
+  if (l <= 1 || lv.g.interior() <= kSmallCg) return kBSmall;
+  if (h->p.precision == EXCMG_FP64 || lv.g.interior() < kIrMinUnknowns) return kBCg64;
+  return kBIr;
+}
+
+void batch_entry(excmg_handle *h, int problem, int l, const double *f, const double *g, double *u, BatchEntry *E,
+                 int blocks[kLaunchKinds]) {
+  memset(E, 0, sizeof(*E));
+  for (int k = 0; k < kLaunchKinds; ++k) blocks[k] = 0;
+  E->kind = batch_kind(h, l);
+  E->problem = problem;
+  if (E->kind == kBNone) return;
+  const Layout &lo = h->lo;
+  const Level &lv = lo.lev[l];
+  E->finest = (l == lo.L - 1);
+  E->exact = (l <= 1);
+  E->level = l;
+  E->cap = h->p.max_iters > 0 ? h->p.max_iters : 10000;
+  E->max_outer = 30;
+  E->tol = h->p.tol;
+  E->eta = h->p.inner_tol > 0.0 ? h->p.inner_tol : 1e-5;
+  E->swA = lv.swA;
+  E->swB = lv.swB;
+  E->swR = lv.sw;
+  E->swA32 = lv.swA32;
+  E->swB32 = lv.swB32;
+  E->g = lv.g;
+  E->g32 = lv.g32;
+  E->gd = lo.gdense;
+  if (l >= 1) E->g2 = lo.lev[l - 1].g;
+  if (l >= 2) E->g4 = lo.lev[l - 2].g;
+  E->st = lv.st;
+  E->rs.gf = lo.gdense;
+  E->rs.f = f;
+  E->rs.g = g;
+  E->rs.s = lv.stride;
+  E->rs.mode = 0;
+  E->rs.a = 1.0 / (lv.h[0] * lv.h[0]);
+  E->rs.b = 1.0 / (lv.h[1] * lv.h[1]);
+  E->rs.c = 1.0 / (lv.h[2] * lv.h[2]);
+  E->u = lv.u;
+  E->r = h->r;
+  E->p0 = h->p0;
+  E->p1 = h->p1;
+  E->r32 = h->r32;
+  E->p32a = h->p32a;
+  E->p32b = h->p32b;
+  E->d32 = h->d32;
+  E->cs = h->cs;
+  E->cs2 = h->cs2;
+  E->parts = h->partials;
+  E->u2 = l >= 1 ? lo.lev[l - 1].u : nullptr;
+  E->u4 = l >= 2 ? lo.lev[l - 2].u : nullptr;
+  E->gb = g;
+  E->out = u;
+  if (E->kind == kBCg64) {
+    blocks[kLA64] = sweep_blocks(lv.swA);
+    blocks[kLB64] = sweep_blocks(lv.swB);
+    blocks[kLR64] = sweep_blocks(lv.sw);
+  }
+  if (E->kind == kBIr) {
+    blocks[kLA32] = sweep_blocks(lv.swA32);
+    blocks[kLB32] = sweep_blocks(lv.swB32);
+    blocks[kLRC] = sweep_blocks(lv.sw);
+    blocks[kLCorr] = b_blocks_interior(lv.g);
+  }
+  if (E->kind == kBCg64 || E->kind == kBIr) blocks[kLBterm] = b_blocks_bterms(lv.g);
+  if (l >= 2) blocks[kLExp] = b_blocks_exp_finite(lv.g);
+  if (l <= 1) blocks[kLSetB] = b_blocks_nodes(lv.g);
+  if (E->finest) blocks[kLCopy] = b_blocks_nodes(lv.g);
+}
+
+int batched_solve(excmg_handle *const *hs, int count, const double *const *f, const double *const *g,
+                  double *const *u, char *ws, excmg_stats *stats, double *ms_per_problem) {
+  const hipStream_t s = hs[0]->stream;
+  const auto t_host = std::chrono::steady_clock::now();
+  int S = 0;
+  for (int b = 0; b < count; ++b) S = hs[b]->lo.L > S ? hs[b]->lo.L : S;
+  BatchStatus *stat = (BatchStatus *)ws;
+  long long *t0 = (long long *)(ws + align256(sizeof(BatchStatus) * (size_t)count));
+  char *tables = ws + align256(sizeof(BatchStatus) * (size_t)count) + 256;
+  const size_t tb = batch_table_bytes(count);
+  const size_t pre_off = align256(sizeof(BatchEntry) * (size_t)count);
+  const int n1 = count + 1;
+
+  // host copy of every step's table, uploaded at once
+  std::vector<char> host((size_t)S * tb, 0);
+  std::vector<int> totals((size_t)S * kLaunchKinds, 0);
+  std::vector<int> kinds((size_t)S * count, kBNone);
+  int cap_max = 0;
+  for (int st = 0; st < S; ++st) {
+    BatchEntry *E = (BatchEntry *)(host.data() + st * tb);
+    int *pre = (int *)(host.data() + st * tb + pre_off);
+    for (int k = 0; k < kLaunchKinds; ++k) pre[k * n1] = 0;
+    for (int b = 0; b < count; ++b) {
+      int blocks[kLaunchKinds];
+      batch_entry(hs[b], b, st, f[b], g[b], u[b], &E[b], blocks);
+      kinds[(size_t)st * count + b] = E[b].kind;
+      if (E[b].cap > cap_max) cap_max = E[b].cap;
+      for (int k = 0; k < kLaunchKinds; ++k) pre[k * n1 + b + 1] = pre[k * n1 + b] + blocks[k];
+    }
+    for (int k = 0; k < kLaunchKinds; ++k) totals[(size_t)st * kLaunchKinds + k] = pre[k * n1 + count];
+  }
+  HIPCHECK(hipMemcpyAsync(tables, host.data(), host.size(), hipMemcpyHostToDevice, s));
+  HIPCHECK(hipStreamSynchronize(s));  // the host tables may go out of scope on any early return below
+  launch_b_init(stat, count, t0, s);
+  int e = last_error();
+  if (e) return e;
+
+  std::vector<BatchStatus> hstat(count);
+  auto read_stat = [&]() -> int {
+    HIPCHECK(hipMemcpyAsync(hstat.data(), stat, sizeof(BatchStatus) * (size_t)count, hipMemcpyDeviceToHost, s));
+    HIPCHECK(hipStreamSynchronize(s));
+    return EXCMG_OK;
+  };
+  if (stats)
+    for (int b = 0; b < count; ++b) {
+      memset(&stats[b], 0, sizeof(excmg_stats));
+      stats[b].levels = hs[b]->lo.L;
+      for (int l = 0; l < hs[b]->lo.L; ++l)
+        for (int d = 0; d < 3; ++d) stats[b].n[l][d] = hs[b]->lo.lev[l].n[d];
+    }
+  std::vector<int> inner_total(count), outer_done(count);
+  int final_status = EXCMG_OK;
+  for (int st = 0; st < S; ++st) {
+    const BatchEntry *T = (const BatchEntry *)(tables + st * tb);
+    const int *P = (const int *)(tables + st * tb + pre_off);
+    const int *tot = &totals[(size_t)st * kLaunchKinds];
+    const int *kd = &kinds[(size_t)st * count];
+    bool any[4] = {false, false, false, false};
+    for (int b = 0; b < count; ++b) any[kd[b]] = true;
+    launch_b_set_boundary(T, P, count, tot[kLSetB], s);
+    launch_b_exp_finite(T, P, count, tot[kLExp], s);
+    if (any[kBSmall]) launch_b_small_cg(T, count, stat, s);
+    launch_b_boundary_terms(T, P, count, tot[kLBterm], s);
+    if ((e = last_error())) return e;
+    if (any[kBCg64]) {
+      launch_b_residual(T, P, count, tot[kLR64], stat, s);
+      for (int launched = 0;;) {
+        for (int q = 0; q < kBatch; ++q, ++launched)
+          launch_b_iteration(0, T, P, count, tot[kLA64], tot[kLB64], stat, s);
+        if ((e = last_error()) || (e = read_stat())) return e;
+        bool all = true;
+        for (int b = 0; b < count; ++b)
+          if (kd[b] == kBCg64 && !hstat[b].m[0].done) all = false;
+        if (all) break;
+        if (launched > cap_max + kBatch) return EXCMG_ERR_NOCONV;  // the device caps every CG; not reached
+      }
+    }
+    if (any[kBIr]) {
+      for (int b = 0; b < count; ++b) inner_total[b] = 0;
+      for (int outer = 0;; ++outer) {
+        launch_b_residual_cast(T, P, count, tot[kLRC], outer, stat, s);
+        if ((e = last_error()) || (e = read_stat())) return e;
+        bool all = true;
+        for (int b = 0; b < count; ++b)
+          if (kd[b] == kBIr && !hstat[b].m[0].done) all = false;
+        if (all) break;
+        if (outer > 64) return EXCMG_ERR_NOCONV;  // the device caps the outer steps at 30; not reached
+        for (int launched = 0;;) {
+          for (int q = 0; q < kBatch; ++q, ++launched)
+            launch_b_iteration(1, T, P, count, tot[kLA32], tot[kLB32], stat, s);
+          if ((e = last_error()) || (e = read_stat())) return e;
+          bool idone = true;
+          for (int b = 0; b < count; ++b)
+            if (kd[b] == kBIr && !hstat[b].m[0].done && !hstat[b].m[1].done) idone = false;
+          if (idone) break;
+          if (launched > cap_max + kBatch) return EXCMG_ERR_NOCONV;
+        }
+        for (int b = 0; b < count; ++b)
+          if (kd[b] == kBIr && !hstat[b].m[0].done) {
+            inner_total[b] += hstat[b].m[1].iter;
+            if (hstat[b].m[1].status == EXCMG_ERR_BREAKDOWN) return EXCMG_ERR_BREAKDOWN;
+          }
+        launch_b_add_correction(T, P, count, tot[kLCorr], s);
+      }
+    }
+    launch_b_copy(T, P, count, tot[kLCopy], s);
+    if ((e = last_error()) || (e = read_stat())) return e;
+    for (int b = 0; b < count; ++b) {
+      if (kd[b] == kBNone) continue;
+      const BatchMirror &m = hstat[b].m[0];
+      if (!isfinite(m.bnorm2)) return EXCMG_ERR_NONFINITE;
+      if (m.status == EXCMG_ERR_BREAKDOWN) return EXCMG_ERR_BREAKDOWN;
+      if (m.status == EXCMG_ERR_NOCONV) final_status = EXCMG_ERR_NOCONV;
+      if (!stats) continue;
+      excmg_stats &o = stats[b];
+      const bool exact = (st <= 1);
+      o.iters[st] = kd[b] == kBIr ? inner_total[b] : (exact ? 0 : m.iter);
+      o.ir_outer[st] = kd[b] == kBIr ? m.iter : 0;
+      if (exact) o.dsolve_iters[st] = m.iter;
+      o.relres[st] = m.bnorm2 > 0.0 ? sqrt(m.rho / m.bnorm2) : 0.0;
+    }
+  }
+  long long t_start = 0;
+  HIPCHECK(hipMemcpyAsync(&t_start, t0, sizeof(long long), hipMemcpyDeviceToHost, s));
+  HIPCHECK(hipStreamSynchronize(s));
+  int rate_khz = 0;
+  HIPCHECK(hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, hs[0]->device));
+  const double host_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_host).count();
+  for (int b = 0; b < count; ++b) {
+    const double ms = (rate_khz > 0 && hstat[b].t_done > 0) ? (double)(hstat[b].t_done - t_start) / rate_khz : -1.0;
+    if (ms_per_problem) ms_per_problem[b] = ms;
+    if (stats) stats[b].ms_total = host_ms;
+  }
+  return final_status;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------------------------------------- C ABI
@@ -931,17 +1160,21 @@ int excmg_bandwidth_probe(void *buf, size_t bytes, int32_t reps, void *hip_strea
   return EXCMG_OK;
 }
 
+int excmg_batch_workspace_bytes(int32_t count, size_t *bytes) {
+  if (count <= 0 || !bytes) return EXCMG_ERR_ARG;
+  *bytes = batch_ws_bytes(count);
+  return EXCMG_OK;
+}
+
 int excmg_solve_batched(excmg_handle *const *hs, int32_t count, const double *const *f, const double *const *g,
-                        double *const *u, excmg_stats *stats, double *ms_per_problem) {
+                        double *const *u, void *batch_ws, size_t batch_bytes, excmg_stats *stats,
+                        double *ms_per_problem) {
   if (!hs || count <= 0 || !f || !g || !u) return EXCMG_ERR_ARG;
-  int status = EXCMG_OK;
-  for (int b = 0; b < count; ++b) {
-    const int e = excmg_solve(hs[b], f[b], g[b], u[b], nullptr, stats ? &stats[b] : nullptr);
-    if (e == EXCMG_ERR_NOCONV) status = e;
-    else if (e) return e;
-    if (ms_per_problem) ms_per_problem[b] = stats ? stats[b].ms_total : 0.0;
-  }
-  return status;
+  for (int b = 0; b < count; ++b)
+    if (!hs[b] || !f[b] || !g[b] || !u[b] || hs[b]->device != hs[0]->device) return EXCMG_ERR_ARG;
+  if (!batch_ws || ((uintptr_t)batch_ws & 255) || batch_bytes < batch_ws_bytes(count)) return EXCMG_ERR_WORKSPACE;
+  DeviceGuard dg(hs[0]->device);
+  return batched_solve(hs, count, f, g, u, (char *)batch_ws, stats, ms_per_problem);
 }
 
 }  // extern "C"

@@ -232,61 +232,78 @@ void launch_copy(const Grid &gs, const double *src, const Grid &gd, double *dst,
 void launch_check_finite(const double *a, long long n, int *flag, hipStream_t st);
 
 // ------------------------------------------------------------------------------------------------------------
-// Batched solves: one entry per problem taking part in a batched launch.  Flattened launches give every problem a
-// contiguous range [off, off + n) of workgroups; a workgroup finds its problem by binary search on off.  Launches
-// with one workgroup per problem use the entry index directly.
+// Batched solves.  One table per cascade step holds an entry for every problem of the batch on that step.  Launches
+// over several problems are flattened: launch kind K gives entry e the workgroups [pre[K][e], pre[K][e+1]) (zero
+// for entries the launch does not concern) and a workgroup finds its entry by binary search on pre[K].  Launches with
+// one workgroup per entry (reductions, small-grid CG) use blockIdx.x as the entry index.  Every problem keeps its own
+// arrays, partial sums and CG states in its own workspace, so the problems of one launch share nothing.
 // ------------------------------------------------------------------------------------------------------------
-struct BatchStatus {
-  int done, iter, status, inner_done;
-  int inner_iter, outer, pad0, pad1;
+enum BatchKind { kBSmall = 0, kBCg64 = 1, kBIr = 2, kBNone = 3 };
+enum BatchLaunch {
+  kLA64 = 0, kLB64, kLR64,   // FP64 CG passes and residual (kind kBCg64)
+  kLA32, kLB32, kLRC,        // FP32 inner passes and FP64 residual + cast (kind kBIr)
+  kLExp,                     // EXP_finite (grids >= 2)
+  kLSetB,                    // boundary values and zero interior (grids 0, 1)
+  kLCopy,                    // copy of the finest grid to the caller's dense array
+  kLCorr,                    // u += d (kind kBIr)
+  kLBterm,                   // boundary terms of the right-hand side (kinds kBCg64 and kBIr)
+  kLaunchKinds
+};
+
+struct BatchMirror {  // copy of one CG state's scalars, for the host
+  int done, iter, status, pad;
   double rho, bnorm2;
-  long long t_done;  // wall_clock64() when the problem's last grid converged
-  long long pad2;
+};
+
+struct BatchStatus {
+  BatchMirror m[2];  // [0]: the FP64 CG (or, under refinement, the outer loop); [1]: the FP32 inner solve
+  long long t_done;  // wall_clock64() when the problem's finest grid finished, 0 before
+  long long pad;
 };
 
 struct BatchEntry {
-  int off, n;          // workgroup range of this problem in the launch the table is built for
-  int problem;         // index into the status array
-  int finest;          // 1: this is the problem's finest grid
-  Sweep swA, swB, swR; // CG passes and residual sweep of this grid (FP64 or FP32 variants as used)
-  Grid g, g32;         // level layouts
+  int kind;       // BatchKind
+  int problem;    // index into the status array
+  int finest;     // this grid is the problem's finest
+  int exact;      // kBSmall: 1 = direct solve (grids 0, 1), 0 = relaxation to tol
+  int level;      // grid index in the problem's cascade
+  int cap;        // CG iteration cap (kBIr: per inner solve)
+  int max_outer;  // kBIr: outer refinement steps allowed
+  int pad;
+  double tol, eta;
+  Sweep swA, swB, swR, swA32, swB32;
+  Grid g, g32, gd, g2, g4;  // this grid (FP64, FP32 layouts), the problem's dense node layout, grids l-1 and l-2
   Stencil st;
-  RhsSrc rs;           // level data
-  double *u, *r, *p0, *p1;
+  RhsSrc rs;                // level data from the problem's finest f, g
+  double *u, *r, *p0, *p1;  // u: this grid's solution; r, p0, p1: the problem's work vectors
   float *r32, *p32a, *p32b, *d32;
   CgState *cs, *cs2;
-  double *parts;       // this problem's partial sums
-  // EXP_finite / boundary / copy
-  Grid g2, g4, gout;
-  const double *u2, *u4;
-  double *out;
-  int stride;
-  // CG parameters
-  double tol, eta;
-  int max_iters, exact, hist_on, pad;
+  double *parts;
+  const double *u2, *u4;    // solutions of grids l-1 and l-2 (EXP_finite)
+  const double *gb;         // the problem's finest g (boundary values)
+  double *out;              // the caller's u (finest grid)
 };
 
-// ---- batched launches (t: device table of n entries; total: sum of the entries' workgroup counts) ----
+// ---- batched launches (t: device table of n entries; pre: the table's prefix arrays, kLaunchKinds x (n + 1)) ----
+// total: pre[kind][n], the workgroups of the flattened launch (nothing is launched when it is 0)
+void launch_b_init(BatchStatus *stat, int count, long long *t0, hipStream_t st);
+void launch_b_set_boundary(const BatchEntry *t, const int *pre, int n, int total, hipStream_t st);
+void launch_b_exp_finite(const BatchEntry *t, const int *pre, int n, int total, hipStream_t st);
 void launch_b_small_cg(const BatchEntry *t, int n, BatchStatus *stat, hipStream_t st);
-void launch_b_residual(const BatchEntry *t, int n, int total, hipStream_t st);
-void launch_b_residual_cast(const BatchEntry *t, int n, int total, hipStream_t st);
-void launch_b_finalize_init(const BatchEntry *t, int n, BatchStatus *stat, hipStream_t st);
-void launch_b_finalize_ir(const BatchEntry *t, int n, int outer_step, int max_outer, BatchStatus *stat,
-                          hipStream_t st);
-template <typename T>
-void launch_b_pass(int pass, const BatchEntry *t, int n, int total, hipStream_t st);
-void launch_b_finalize(int pass, int inner, const BatchEntry *t, int n, BatchStatus *stat, hipStream_t st);
-void launch_b_boundary_terms(const BatchEntry *t, int n, int total, hipStream_t st);
-void launch_b_add_correction(const BatchEntry *t, int n, int total, hipStream_t st);
-void launch_b_exp_finite(const BatchEntry *t, int n, int total, hipStream_t st);
-void launch_b_set_boundary(const BatchEntry *t, int n, int total, hipStream_t st);
-void launch_b_copy(const BatchEntry *t, int n, int total, hipStream_t st);
-void launch_b_timestamp(long long *out, hipStream_t st);
-// workgroup counts of the flattened launches for one entry
+void launch_b_boundary_terms(const BatchEntry *t, const int *pre, int n, int total, hipStream_t st);
+void launch_b_residual(const BatchEntry *t, const int *pre, int n, int total, BatchStatus *stat, hipStream_t st);
+void launch_b_residual_cast(const BatchEntry *t, const int *pre, int n, int total, int outer_step,
+                            BatchStatus *stat, hipStream_t st);
+// one CG iteration (pass A, its reduction, pass B, its reduction) of every kBCg64 (fp32 = 0) or kBIr (fp32 = 1) entry
+void launch_b_iteration(int fp32, const BatchEntry *t, const int *pre, int n, int totalA, int totalB,
+                        BatchStatus *stat, hipStream_t st);
+void launch_b_add_correction(const BatchEntry *t, const int *pre, int n, int total, hipStream_t st);
+void launch_b_copy(const BatchEntry *t, const int *pre, int n, int total, hipStream_t st);
+// workgroup counts of the flattened launches for one grid
 int b_blocks_exp_finite(const Grid &gw);
-int b_blocks_nodes(const Grid &g);      // set_boundary and copy: 256 nodes per workgroup
-int b_blocks_interior(const Grid &g);   // add_correction: 256 interior nodes per workgroup
-int b_blocks_bterms(const Grid &g);     // boundary terms: the six boundary-adjacent layers, 256 nodes per workgroup
+int b_blocks_nodes(const Grid &g);     // set_boundary and copy
+int b_blocks_interior(const Grid &g);  // add_correction
+int b_blocks_bterms(const Grid &g);    // boundary terms
 
 // gradient of a grid function (layout gu) into dense outputs (layout gd); table: 1/m_i for N up to nmax
 void launch_gradient(const Grid &gu, const double *u, const Grid &gd, double *ux, double *uy, double *uz, double hx,

@@ -202,19 +202,32 @@ __device__ __forceinline__ void write_partials(const double (&v)[K], double *par
   }
 }
 
-constexpr int FT = 256;
+constexpr int FT = 1024;
 
-// fixed-order sum of n partials by one workgroup; the result is valid in every thread
-__device__ double fixed_sum(const double *a, int n, double *sh) {
+// Strided part of a fixed-order sum: thread t adds a[t], a[t + W], a[t + 2W], ... in that order.  Eight loads are
+// issued before their adds so that the loop is not one memory latency per element; the order of the adds, and so
+// the result, is that of the plain loop.
+template <int W>
+__device__ __forceinline__ double strided_sum(const double *a, int n) {
   double v = 0.0;
-  for (int q = threadIdx.x; q < n; q += FT) v += a[q];
-  sh[threadIdx.x] = v;
-  __syncthreads();
-  for (int w = FT / 2; w > 0; w >>= 1) {
-    if (threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
-    __syncthreads();
+  int q = threadIdx.x;
+  for (; q + 7 * W < n; q += 8 * W) {
+    double x[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) x[u] = a[q + u * W];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v += x[u];
   }
-  const double s = sh[0];
+  for (; q < n; q += W) v += a[q];
+  return v;
+}
+
+// fixed-order sum of n partials by one workgroup of FT threads; the result is valid in every thread
+__device__ double fixed_sum(const double *a, int n, double *sh) {
+  const double t = block_sum<FT>(strided_sum<FT>(a, n), sh);
+  if (threadIdx.x == 0) sh[FT / 64] = t;
+  __syncthreads();
+  const double s = sh[FT / 64];
   __syncthreads();
   return s;
 }
@@ -430,15 +443,10 @@ constexpr int kSelfRedMaxBlocks = 2048;
 
 // fixed-order sum by a whole workgroup of NT threads; valid in every thread
 __device__ double block_fixed_sum(const double *a, int n, double *sh) {
-  double v = 0.0;
-  for (int q = threadIdx.x; q < n; q += NT) v += a[q];
-  sh[threadIdx.x] = v;
+  const double t = block_sum<NT>(strided_sum<NT>(a, n), sh);
+  if (threadIdx.x == 0) sh[NT / 64] = t;
   __syncthreads();
-  for (int w = NT / 2; w > 0; w >>= 1) {
-    if (threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
-    __syncthreads();
-  }
-  const double s = sh[0];
+  const double s = sh[NT / 64];
   __syncthreads();
   return s;
 }
@@ -650,10 +658,11 @@ __global__ __launch_bounds__(NT) void apply_kernel(Sweep sw, const double *x, Gr
 
 // A's couplings to the Dirichlet values, written at every interior node next to the boundary (the six layers
 // i = 1, i = nx-1, j = 1, ...; nodes on two layers are written twice with the same value).  blockIdx.z = layer.
-__global__ void boundary_terms_kernel(RhsSrc rs, Grid g, double *out) {
-  const int layer = blockIdx.z;  // 0,1: x layers; 2,3: y layers; 4,5: z layers
-  const int a = 1 + blockIdx.x * blockDim.x + threadIdx.x;
-  const int b = 1 + blockIdx.y;
+__device__ __forceinline__ void boundary_terms_block(const RhsSrc &rs, const Grid &g, double *out, int bx, int by,
+                                                     int layer) {
+  // layer 0,1: x layers; 2,3: y layers; 4,5: z layers
+  const int a = 1 + bx * 256 + threadIdx.x;
+  const int b = 1 + by;
   int i, j, k;
   if (layer < 2) {
     if (a >= g.ny || b >= g.nz) return;
@@ -668,11 +677,15 @@ __global__ void boundary_terms_kernel(RhsSrc rs, Grid g, double *out) {
   out[g.at(i, j, k)] = rhs_boundary_terms(rs, g.nx, g.ny, g.nz, i, j, k);
 }
 
+__global__ __launch_bounds__(256) void boundary_terms_kernel(RhsSrc rs, Grid g, double *out) {
+  boundary_terms_block(rs, g, out, blockIdx.x, blockIdx.y, blockIdx.z);
+}
+
 // --------------------------------------------------------------------------------------------------------- finalize
 
 __global__ __launch_bounds__(FT) void finalize_init_kernel(CgState *cs, const double *partials, int nparts, double tol,
                                                            int max_iters, int hist_on) {
-  __shared__ double sh[FT];
+  __shared__ double sh[FT / 64 + 1];
   const double rho = fixed_sum(partials, nparts, sh);
   const double bb = fixed_sum(partials + nparts, nparts, sh);
   if (threadIdx.x == 0) state_init(cs, rho, bb, tol, max_iters, hist_on);
@@ -681,7 +694,7 @@ __global__ __launch_bounds__(FT) void finalize_init_kernel(CgState *cs, const do
 __global__ __launch_bounds__(FT) void finalize_ir_kernel(CgState *outer, CgState *inner, const double *partials,
                                                          int nparts, double tol, double eta, int outer_step,
                                                          int max_outer, int max_inner) {
-  __shared__ double sh[FT];
+  __shared__ double sh[FT / 64 + 1];
   const double r64 = fixed_sum(partials, nparts, sh);
   const double bb = fixed_sum(partials + nparts, nparts, sh);
   const double r32 = fixed_sum(partials + 2 * nparts, nparts, sh);
@@ -689,14 +702,14 @@ __global__ __launch_bounds__(FT) void finalize_ir_kernel(CgState *outer, CgState
 }
 
 __global__ __launch_bounds__(FT) void finalize_a_kernel(CgState *cs, const double *partials, int nparts) {
-  __shared__ double sh[FT];
+  __shared__ double sh[FT / 64 + 1];
   if (cs->done) return;
   const double pq = fixed_sum(partials, nparts, sh);
   if (threadIdx.x == 0) state_after_a(cs, pq);
 }
 
 __global__ __launch_bounds__(FT) void finalize_b_kernel(CgState *cs, const double *partials, int nparts) {
-  __shared__ double sh[FT];
+  __shared__ double sh[FT / 64 + 1];
   if (cs->done) return;
   const double rho = fixed_sum(partials, nparts, sh);
   if (threadIdx.x == 0) state_after_b(cs, rho);
@@ -721,12 +734,17 @@ __global__ void tune_state_kernel(CgState *cs) {
   cs->hist_on = 0;
 }
 
-__global__ void add_correction_kernel(Grid gu, double *u, Grid g32, const float *d) {
-  const int i = 1 + blockIdx.x * blockDim.x + threadIdx.x;
-  const int j = 1 + blockIdx.y;
-  const int k = 1 + blockIdx.z;
+__device__ __forceinline__ void add_correction_block(const Grid &gu, double *u, const Grid &g32, const float *d,
+                                                     int bx, int by, int bz) {
+  const int i = 1 + bx * 256 + threadIdx.x;
+  const int j = 1 + by;
+  const int k = 1 + bz;
   if (i >= gu.nx) return;
   u[gu.at(i, j, k)] += (double)d[g32.at(i, j, k)];
+}
+
+__global__ __launch_bounds__(256) void add_correction_kernel(Grid gu, double *u, Grid g32, const float *d) {
+  add_correction_block(gu, u, g32, d, blockIdx.x, blockIdx.y, blockIdx.z);
 }
 
 // ----------------------------------------------------------------------------------------------------------- DSOLVE
@@ -770,9 +788,8 @@ __device__ double dsum(double v, double *sh) {
 //              stopping test as the multi-workgroup sweeps, ||r|| <= tol ||b|| checked before every iteration.
 // Small grids are latency-bound: one workgroup with every iteration in registers and L2 beats two sweep launches
 // plus two reductions per iteration.
-__global__ __launch_bounds__(DT) void small_cg_kernel(Grid gu, double *u, RhsSrc rs, Grid gw, double *r, double *p,
-                                                      double *q, Stencil st, CgState *cs, double tol, int cap,
-                                                      int exact, int hist_on) {
+__device__ void small_cg_body(const Grid &gu, double *u, const RhsSrc &rs, const Grid &gw, double *r, double *p,
+                              double *q, const Stencil &st, CgState *cs, double tol, int cap, int exact, int hist_on) {
   __shared__ double sh[DT / 64];
   const int nx1 = gu.nx - 1, ny1 = gu.ny - 1, nz1 = gu.nz - 1;
   const int n = nx1 * ny1 * nz1;
@@ -855,6 +872,226 @@ __global__ __launch_bounds__(DT) void small_cg_kernel(Grid gu, double *u, RhsSrc
     cs->status = status;
     cs->done = 1;
   }
+}
+
+__global__ __launch_bounds__(DT) void small_cg_kernel(Grid gu, double *u, RhsSrc rs, Grid gw, double *r, double *p,
+                                                      double *q, Stencil st, CgState *cs, double tol, int cap,
+                                                      int exact, int hist_on) {
+  small_cg_body(gu, u, rs, gw, r, p, q, st, cs, tol, cap, exact, hist_on);
+}
+
+// ---------------------------------------------------------------------------------------------------- batched form
+//
+// The same sweeps, reductions and small-grid CG over a table of problems (one entry per problem; see BatchEntry).
+
+// entry of flattened workgroup b: the largest e with pre[e] <= b (entries with no workgroups have pre[e] = pre[e+1])
+__device__ __forceinline__ int find_entry(const int *pre, int n, int b) {
+  int lo = 0, hi = n;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (pre[mid] <= b) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// copy of a CG state's scalars for the host; the finest grid's completion time is stamped once
+__device__ void mirror(const BatchEntry &E, const CgState *cs, BatchStatus *stat, int slot, bool final_state) {
+  BatchMirror &m = stat[E.problem].m[slot];
+  m.done = cs->done;
+  m.iter = cs->iter;
+  m.status = cs->status;
+  m.rho = cs->rho;
+  m.bnorm2 = cs->bnorm2;
+  if (final_state && E.finest && cs->done && stat[E.problem].t_done == 0)
+    stat[E.problem].t_done = (long long)wall_clock64();
+}
+
+__global__ void b_init_kernel(BatchStatus *stat, int count, long long *t0) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q < count) {
+    BatchStatus z = {};
+    stat[q] = z;
+  }
+  if (q == 0) *t0 = (long long)wall_clock64();
+}
+
+__global__ __launch_bounds__(DT) void b_small_cg_kernel(const BatchEntry *t, BatchStatus *stat) {
+  const BatchEntry &E = t[blockIdx.x];
+  if (E.kind != kBSmall) return;
+  int cap = E.cap;
+  if (E.exact) {
+    const long long n = E.g.interior();
+    cap = (int)(4 * n + 200);
+    if (cap > 20000) cap = 20000;
+  }
+  small_cg_body(E.g, E.u, E.rs, E.g, E.r, E.p0, E.p1, E.st, E.cs, E.tol, cap, E.exact, 0);
+  if (threadIdx.x == 0) mirror(E, E.cs, stat, 0, true);
+}
+
+__global__ __launch_bounds__(256) void b_boundary_terms_kernel(const BatchEntry *t, const int *pre, int n) {
+  const int e = find_entry(pre, n, blockIdx.x);
+  const BatchEntry &E = t[e];
+  const Grid g = E.g;
+  const int m = max(g.nx, max(g.ny, g.nz)) - 1;
+  const int gx = (m + 255) / 256;
+  const int lb = blockIdx.x - pre[e];
+  boundary_terms_block(E.rs, g, E.r, lb % gx, (lb / gx) % m, lb / (gx * m));
+}
+
+__global__ __launch_bounds__(NT) void b_residual_kernel(const BatchEntry *t, const int *pre, int n) {
+  __shared__ double tile[2][TY + 2][TX + 2];
+  __shared__ double sh[NT / 64];
+  __shared__ double tileF[2][TY + 2][TX + 2];
+  const int e = find_entry(pre, n, blockIdx.x);
+  const BatchEntry &E = t[e];
+  const int bid = blockIdx.x - pre[e], nb = pre[e + 1] - pre[e];
+  const Sweep sw = E.swR;
+  PolResid pol{E.u, E.r, RhsPart{E.rs, sw.g.nx, sw.g.ny, sw.g.nz, E.r, {0.0, 0.0}}};
+  double a0 = 0.0, a1 = 0.0;
+  zmarch<double>(sw, pol, a0, a1, tile, tileF, bid, nb, false);
+  const double v[2] = {a0, a1};
+  write_partials<2>(v, E.parts, sh, bid, nb);
+}
+
+__global__ __launch_bounds__(FT) void b_finalize_init_kernel(const BatchEntry *t, const int *pre, int n,
+                                                             BatchStatus *stat) {
+  __shared__ double sh[FT / 64 + 1];
+  const BatchEntry &E = t[blockIdx.x];
+  if (E.kind != kBCg64) return;
+  const int nb = pre[blockIdx.x + 1] - pre[blockIdx.x];
+  const double rho = fixed_sum(E.parts, nb, sh);
+  const double bb = fixed_sum(E.parts + nb, nb, sh);
+  if (threadIdx.x == 0) {
+    state_init(E.cs, rho, bb, E.tol, E.cap, 0);
+    mirror(E, E.cs, stat, 0, true);
+  }
+}
+
+// FP64 residual and its FP32 copy for the outer step outer_step of the refinement; entries whose outer loop has
+// already finished (outer_step > 0 and done) are skipped
+__global__ __launch_bounds__(NT) void b_residual_cast_kernel(const BatchEntry *t, const int *pre, int n,
+                                                             int outer_step) {
+  __shared__ double tile[2][TY + 2][TX + 2];
+  __shared__ double sh[NT / 64];
+  __shared__ double tileF[2][TY + 2][TX + 2];
+  const int e = find_entry(pre, n, blockIdx.x);
+  const BatchEntry &E = t[e];
+  if (outer_step > 0 && E.cs->done) return;
+  const int bid = blockIdx.x - pre[e], nb = pre[e + 1] - pre[e];
+  const Sweep sw = E.swR;
+  PolResidCast pol{E.u, E.g32, E.r32, E.d32, RhsPart{E.rs, sw.g.nx, sw.g.ny, sw.g.nz, E.r, {0.0, 0.0}}, 0.0};
+  double a0 = 0.0, a1 = 0.0;
+  zmarch<double>(sw, pol, a0, a1, tile, tileF, bid, nb, false);
+  const double v[3] = {a0, a1, pol.acc2};
+  write_partials<3>(v, E.parts, sh, bid, nb);
+}
+
+__global__ __launch_bounds__(FT) void b_finalize_ir_kernel(const BatchEntry *t, const int *pre, int n,
+                                                           int outer_step, BatchStatus *stat) {
+  __shared__ double sh[FT / 64 + 1];
+  const BatchEntry &E = t[blockIdx.x];
+  if (E.kind != kBIr) return;
+  if (outer_step > 0 && E.cs->done) return;
+  const int nb = pre[blockIdx.x + 1] - pre[blockIdx.x];
+  const double r64 = fixed_sum(E.parts, nb, sh);
+  const double bb = fixed_sum(E.parts + nb, nb, sh);
+  const double r32 = fixed_sum(E.parts + 2 * nb, nb, sh);
+  if (threadIdx.x == 0) {
+    state_ir(E.cs, E.cs2, r64, bb, r32, E.tol, E.eta, outer_step, E.max_outer, E.cap);
+    mirror(E, E.cs, stat, 0, true);
+    mirror(E, E.cs2, stat, 1, false);
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(NT) void b_pass_a_kernel(const BatchEntry *t, const int *pre, int n) {
+  constexpr bool F = sizeof(T) == 4;
+  __shared__ T tile[2][TY + 2][TX + 2];
+  __shared__ double sh[NT / 64];
+  const int e = find_entry(pre, n, blockIdx.x);
+  const BatchEntry &E = t[e];
+  const CgState *cs = F ? E.cs2 : E.cs;
+  if (cs->done) return;
+  const int bid = blockIdx.x - pre[e], nb = pre[e + 1] - pre[e];
+  const int it = cs->iter;
+  T *p0, *p1;
+  const T *r;
+  if constexpr (F) {
+    r = E.r32; p0 = E.p32a; p1 = E.p32b;
+  } else {
+    r = E.r; p0 = E.p0; p1 = E.p1;
+  }
+  PolA<T> pol;
+  pol.r = r;
+  pol.pnew = (it & 1) ? p1 : p0;
+  pol.pold = (it & 1) ? p0 : p1;
+  pol.first = (it == 0);
+  pol.beta = (T)cs->beta;
+  const Sweep sw = F ? E.swA32 : E.swA;
+  double a0 = 0.0, a1 = 0.0;
+  zmarch<T>(sw, pol, a0, a1, tile, nullptr, bid, nb, false);
+  const double v[1] = {a0};
+  write_partials<1>(v, E.parts, sh, bid, nb);
+}
+
+template <typename T>
+__global__ __launch_bounds__(NT) void b_pass_b_kernel(const BatchEntry *t, const int *pre, int n) {
+  constexpr bool F = sizeof(T) == 4;
+  __shared__ T tile[2][TY + 2][TX + 2];
+  __shared__ double sh[NT / 64];
+  const int e = find_entry(pre, n, blockIdx.x);
+  const BatchEntry &E = t[e];
+  const CgState *cs = F ? E.cs2 : E.cs;
+  if (cs->done) return;
+  const int bid = blockIdx.x - pre[e], nb = pre[e + 1] - pre[e];
+  const int it = cs->iter;
+  PolB<T> pol;
+  if constexpr (F) {
+    pol.p = (it & 1) ? E.p32b : E.p32a;
+    pol.u = E.d32;
+    pol.r = E.r32;
+  } else {
+    pol.p = (it & 1) ? E.p1 : E.p0;
+    pol.u = E.u;
+    pol.r = E.r;
+  }
+  pol.alpha = (T)cs->alpha;
+  pol.pr[0] = pol.pr[1] = 0;
+  pol.pu[0] = pol.pu[1] = 0;
+  const Sweep sw = F ? E.swB32 : E.swB;
+  double a0 = 0.0, a1 = 0.0;
+  zmarch<T>(sw, pol, a0, a1, tile, nullptr, bid, nb, false);
+  const double v[1] = {a0};
+  write_partials<1>(v, E.parts, sh, bid, nb);
+}
+
+// reduction after pass A (PASS 0) or pass B (PASS 1) of the FP64 CG (F = 0) or the FP32 inner CG (F = 1)
+template <int PASS, int F>
+__global__ __launch_bounds__(FT) void b_finalize_pass_kernel(const BatchEntry *t, const int *pre, int n,
+                                                             BatchStatus *stat) {
+  __shared__ double sh[FT / 64 + 1];
+  const BatchEntry &E = t[blockIdx.x];
+  if (E.kind != (F ? kBIr : kBCg64)) return;
+  CgState *cs = F ? E.cs2 : E.cs;
+  if (cs->done) return;
+  const int nb = pre[blockIdx.x + 1] - pre[blockIdx.x];
+  const double v = fixed_sum(E.parts, nb, sh);
+  if (threadIdx.x == 0) {
+    if (PASS == 0) state_after_a(cs, v);
+    else state_after_b(cs, v);
+    mirror(E, cs, stat, F, F == 0);
+  }
+}
+
+__global__ __launch_bounds__(256) void b_add_correction_kernel(const BatchEntry *t, const int *pre, int n) {
+  const int e = find_entry(pre, n, blockIdx.x);
+  const BatchEntry &E = t[e];
+  if (E.cs->done) return;
+  const Grid g = E.g;
+  const int gx = (g.nx - 1 + 255) / 256, gy = g.ny - 1;
+  const int lb = blockIdx.x - pre[e];
+  add_correction_block(g, E.u, E.g32, E.d32, lb % gx, (lb / gx) % gy, lb / (gx * gy));
 }
 
 }  // namespace
@@ -990,6 +1227,65 @@ void launch_small_cg(const Grid &gu, double *u, const RhsSrc &rs, const Grid &gw
 void launch_apply(const Grid &gx, const double *x, const Grid &gy, double *y, const Stencil &s, hipStream_t st) {
   const Sweep sw = make_sweep(gx, s, 0);
   apply_kernel<<<sweep_blocks(sw), NT, 0, st>>>(sw, x, gy, y);
+}
+
+
+// ---------------------------------------------------------------------------------------------- batched launchers
+
+int b_blocks_interior(const Grid &g) { return ((g.nx - 1 + 255) / 256) * (g.ny - 1) * (g.nz - 1); }
+
+int b_blocks_bterms(const Grid &g) {
+  const int m = (g.nx > g.ny ? (g.nx > g.nz ? g.nx : g.nz) : (g.ny > g.nz ? g.ny : g.nz)) - 1;
+  return ((m + 255) / 256) * m * 6;
+}
+
+void launch_b_init(BatchStatus *stat, int count, long long *t0, hipStream_t st) {
+  b_init_kernel<<<(count + 255) / 256, 256, 0, st>>>(stat, count, t0);
+}
+
+void launch_b_small_cg(const BatchEntry *t, int n, BatchStatus *stat, hipStream_t st) {
+  b_small_cg_kernel<<<n, DT, 0, st>>>(t, stat);
+}
+
+void launch_b_boundary_terms(const BatchEntry *t, const int *pre, int n, int total, hipStream_t st) {
+  if (total > 0) b_boundary_terms_kernel<<<total, 256, 0, st>>>(t, pre + kLBterm * (n + 1), n);
+}
+
+void launch_b_residual(const BatchEntry *t, const int *pre, int n, int total, BatchStatus *stat, hipStream_t st) {
+  if (total <= 0) return;
+  const int *p = pre + kLR64 * (n + 1);
+  b_residual_kernel<<<total, NT, 0, st>>>(t, p, n);
+  b_finalize_init_kernel<<<n, FT, 0, st>>>(t, p, n, stat);
+}
+
+void launch_b_residual_cast(const BatchEntry *t, const int *pre, int n, int total, int outer_step,
+                            BatchStatus *stat, hipStream_t st) {
+  if (total <= 0) return;
+  const int *p = pre + kLRC * (n + 1);
+  b_residual_cast_kernel<<<total, NT, 0, st>>>(t, p, n, outer_step);
+  b_finalize_ir_kernel<<<n, FT, 0, st>>>(t, p, n, outer_step, stat);
+}
+
+void launch_b_iteration(int fp32, const BatchEntry *t, const int *pre, int n, int totalA, int totalB,
+                        BatchStatus *stat, hipStream_t st) {
+  if (totalA <= 0 || totalB <= 0) return;
+  if (fp32) {
+    const int *pa = pre + kLA32 * (n + 1), *pb = pre + kLB32 * (n + 1);
+    b_pass_a_kernel<float><<<totalA, NT, 0, st>>>(t, pa, n);
+    b_finalize_pass_kernel<0, 1><<<n, FT, 0, st>>>(t, pa, n, stat);
+    b_pass_b_kernel<float><<<totalB, NT, 0, st>>>(t, pb, n);
+    b_finalize_pass_kernel<1, 1><<<n, FT, 0, st>>>(t, pb, n, stat);
+  } else {
+    const int *pa = pre + kLA64 * (n + 1), *pb = pre + kLB64 * (n + 1);
+    b_pass_a_kernel<double><<<totalA, NT, 0, st>>>(t, pa, n);
+    b_finalize_pass_kernel<0, 0><<<n, FT, 0, st>>>(t, pa, n, stat);
+    b_pass_b_kernel<double><<<totalB, NT, 0, st>>>(t, pb, n);
+    b_finalize_pass_kernel<1, 0><<<n, FT, 0, st>>>(t, pb, n, stat);
+  }
+}
+
+void launch_b_add_correction(const BatchEntry *t, const int *pre, int n, int total, hipStream_t st) {
+  if (total > 0) b_add_correction_kernel<<<total, 256, 0, st>>>(t, pre + kLCorr * (n + 1), n);
 }
 
 }  // namespace excmg

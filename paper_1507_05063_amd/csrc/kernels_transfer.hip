@@ -25,11 +25,10 @@ __global__ void rhs_kernel(RhsSrc rs, Grid gb, double *__restrict__ b) {
   b[gb.at(i, j, k)] = rhs_at(rs, gb.nx, gb.ny, gb.nz, i, j, k);
 }
 
-__global__ void set_boundary_kernel(Grid gg, const double *__restrict__ g, int s, Grid gu, double *__restrict__ u,
-                                    int zero_interior) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const int j = blockIdx.y;
-  const int k = blockIdx.z;
+// Node-wise kernels run 256 threads per workgroup over (x segment, y, z) = (bx, j, k).
+__device__ __forceinline__ void set_boundary_block(const Grid &gg, const double *__restrict__ g, int s, const Grid &gu,
+                                                   double *__restrict__ u, int zero_interior, int bx, int j, int k) {
+  const int i = bx * 256 + threadIdx.x;
   if (i > gu.nx) return;
   if (on_boundary(i, j, k, gu.nx, gu.ny, gu.nz)) {
     u[gu.at(i, j, k)] = g ? g[gg.at(i * s, j * s, k * s)] : 0.0;
@@ -38,12 +37,21 @@ __global__ void set_boundary_kernel(Grid gg, const double *__restrict__ g, int s
   }
 }
 
-__global__ void copy_kernel(Grid gs, const double *__restrict__ src, Grid gd, double *__restrict__ dst) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const int j = blockIdx.y;
-  const int k = blockIdx.z;
+__global__ __launch_bounds__(256) void set_boundary_kernel(Grid gg, const double *__restrict__ g, int s, Grid gu,
+                                                           double *__restrict__ u, int zero_interior) {
+  set_boundary_block(gg, g, s, gu, u, zero_interior, blockIdx.x, blockIdx.y, blockIdx.z);
+}
+
+__device__ __forceinline__ void copy_block(const Grid &gs, const double *__restrict__ src, const Grid &gd,
+                                           double *__restrict__ dst, int bx, int j, int k) {
+  const int i = bx * 256 + threadIdx.x;
   if (i > gs.nx) return;
   dst[gd.at(i, j, k)] = src[gs.at(i, j, k)];
+}
+
+__global__ __launch_bounds__(256) void copy_kernel(Grid gs, const double *__restrict__ src, Grid gd,
+                                                   double *__restrict__ dst) {
+  copy_block(gs, src, gd, dst, blockIdx.x, blockIdx.y, blockIdx.z);
 }
 
 __global__ void check_finite_kernel(const double *__restrict__ a, long long n, int *flag) {
@@ -87,17 +95,15 @@ __device__ __forceinline__ double quartic(int t, double a0, double a1, double a2
 //     for the y pass and one thread per (x, y) column for the z pass, each holding its five known values in
 //     registers and producing its nine outputs;
 //  4. boundary nodes get g.
-__global__ __launch_bounds__(ET) void exp_finite_kernel(Grid g2, const double *__restrict__ u2, Grid g4,
-                                                        const double *__restrict__ u4, Grid gg,
-                                                        const double *__restrict__ gdat, int s, Grid gw,
-                                                        double *__restrict__ w) {
+__device__ void exp_finite_block(const Grid &g2, const double *__restrict__ u2, const Grid &g4,
+                                 const double *__restrict__ u4, const Grid &gg, const double *__restrict__ gdat, int s,
+                                 const Grid &gw, double *__restrict__ w, int bx, int cj, int ck) {
   __shared__ double W[5][5][EX2];
   __shared__ double D[3][3][EX4];
   __shared__ double Wx[5][5][EXF];
   __shared__ double Wxy[5][9][EXF];
   const int ncx = gw.nx / 8, ncy = gw.ny / 8, ncz = gw.nz / 8;
-  const int cx0 = blockIdx.x * CXN;
-  const int cj = blockIdx.y, ck = blockIdx.z;
+  const int cx0 = bx * CXN;
   const int nc = min(CXN, ncx - cx0);  // cells in this workgroup (fewer in the last one along x)
   const int n2x = 4 * nc + 1, n4x = 2 * nc + 1, nfx = 8 * nc + 1;
   const int tid = threadIdx.x;
@@ -182,6 +188,13 @@ __global__ __launch_bounds__(ET) void exp_finite_kernel(Grid g2, const double *_
   }
 }
 
+__global__ __launch_bounds__(ET) void exp_finite_kernel(Grid g2, const double *__restrict__ u2, Grid g4,
+                                                        const double *__restrict__ u4, Grid gg,
+                                                        const double *__restrict__ gdat, int s, Grid gw,
+                                                        double *__restrict__ w) {
+  exp_finite_block(g2, u2, g4, u4, gg, gdat, s, gw, w, blockIdx.x, blockIdx.y, blockIdx.z);
+}
+
 // ------------------------------------------------------------------------------------------------------- exp_true
 // u~ = u_h + delta_avg / 15 where delta = u_h - u_2h at the 2h nodes and delta_avg its mean over the corners of the
 // 2h edge/face/element the node is the midpoint of: eq. (t1) at 2h nodes, eq. (chenlin) at edge midpoints, and its
@@ -254,6 +267,45 @@ __global__ void adjoint_kernel(Grid gl, const double *__restrict__ lam, Grid gd,
   dLdg[q] = s + G[q];
 }
 
+// ---------------------------------------------------------------------------------------------------- batched form
+// Flattened over a table of problems (see BatchEntry): workgroup b belongs to the entry e with
+// pre[e] <= b < pre[e+1] and takes the local index b - pre[e] in that entry's launch.
+__device__ __forceinline__ int find_entry_t(const int *pre, int n, int b) {
+  int lo = 0, hi = n;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (pre[mid] <= b) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// boundary values and zero interior on grids 0 and 1
+__global__ __launch_bounds__(256) void b_set_boundary_kernel(const BatchEntry *t, const int *pre, int n) {
+  const int e = find_entry_t(pre, n, blockIdx.x);
+  const BatchEntry &E = t[e];
+  const int gx = (E.g.nx + 1 + 255) / 256, gy = E.g.ny + 1;
+  const int lb = blockIdx.x - pre[e];
+  set_boundary_block(E.gd, E.gb, E.rs.s, E.g, E.u, 1, lb % gx, (lb / gx) % gy, lb / (gx * gy));
+}
+
+__global__ __launch_bounds__(256) void b_copy_kernel(const BatchEntry *t, const int *pre, int n) {
+  const int e = find_entry_t(pre, n, blockIdx.x);
+  const BatchEntry &E = t[e];
+  const int gx = (E.g.nx + 1 + 255) / 256, gy = E.g.ny + 1;
+  const int lb = blockIdx.x - pre[e];
+  copy_block(E.g, E.u, E.gd, E.out, lb % gx, (lb / gx) % gy, lb / (gx * gy));
+}
+
+__global__ __launch_bounds__(ET) void b_exp_finite_kernel(const BatchEntry *t, const int *pre, int n) {
+  const int e = find_entry_t(pre, n, blockIdx.x);
+  const BatchEntry &E = t[e];
+  const int ncx = E.g.nx / 8, ncy = E.g.ny / 8;
+  const int gx = (ncx + CXN - 1) / CXN;
+  const int lb = blockIdx.x - pre[e];
+  exp_finite_block(E.g2, E.u2, E.g4, E.u4, E.gd, E.gb, E.rs.s, E.g, E.u, lb % gx, (lb / gx) % ncy, lb / (gx * ncy));
+}
+
 inline dim3 node_grid(const Grid &g, int bx) { return dim3((g.nx + 1 + bx - 1) / bx, g.ny + 1, g.nz + 1); }
 inline dim3 interior_grid(const Grid &g, int bx) { return dim3((g.nx - 1 + bx - 1) / bx, g.ny - 1, g.nz - 1); }
 
@@ -296,6 +348,25 @@ void launch_adjoint_transposes(const Grid &gl, const double *lam, const Grid &gd
                                double *dLdg, double hx, double hy, double hz, hipStream_t st) {
   adjoint_kernel<<<node_grid(gl, 256), 256, 0, st>>>(gl, lam, gd, G, dLdf, dLdg, 1.0 / (hx * hx), 1.0 / (hy * hy),
                                                      1.0 / (hz * hz));
+}
+
+int b_blocks_nodes(const Grid &g) { return ((g.nx + 1 + 255) / 256) * (g.ny + 1) * (g.nz + 1); }
+
+int b_blocks_exp_finite(const Grid &gw) {
+  const int ncx = gw.nx / 8, ncy = gw.ny / 8, ncz = gw.nz / 8;
+  return ((ncx + CXN - 1) / CXN) * ncy * ncz;
+}
+
+void launch_b_set_boundary(const BatchEntry *t, const int *pre, int n, int total, hipStream_t st) {
+  if (total > 0) b_set_boundary_kernel<<<total, 256, 0, st>>>(t, pre + kLSetB * (n + 1), n);
+}
+
+void launch_b_exp_finite(const BatchEntry *t, const int *pre, int n, int total, hipStream_t st) {
+  if (total > 0) b_exp_finite_kernel<<<total, ET, 0, st>>>(t, pre + kLExp * (n + 1), n);
+}
+
+void launch_b_copy(const BatchEntry *t, const int *pre, int n, int total, hipStream_t st) {
+  if (total > 0) b_copy_kernel<<<total, 256, 0, st>>>(t, pre + kLCopy * (n + 1), n);
 }
 
 }  // namespace excmg

@@ -132,3 +132,27 @@ def test_product_path_does_not_import_the_oracle():
             if fn.endswith((".py", ".hip", ".h", ".cpp")):
                 txt = open(os.path.join(dirpath, fn)).read()
                 assert "import oracle" not in txt and "from oracle" not in txt and "oracle.h" not in txt, fn
+
+
+def test_batch_workspace_bytes(abi):
+    import paper_1507_05063_amd as ex
+
+    one = ex.batch_workspace_bytes(1)
+    many = ex.batch_workspace_bytes(96)
+    assert 0 < one < many < 96 * 32 * 1024
+    with pytest.raises(ex.ExcmgError):
+        ex.batch_workspace_bytes(0)
+
+
+def test_batched_argument_errors(abi):
+    """Argument checks that return before any device call."""
+    import ctypes
+
+    from paper_1507_05063_amd import _lib
+
+    L = _lib.lib()
+    assert L.excmg_solve_batched(None, 1, None, None, None, None, 0, None, None) == _lib.ERR_ARG
+    H = (ctypes.c_void_p * 1)(None)
+    P = (ctypes.c_void_p * 1)(None)
+    assert L.excmg_solve_batched(H, 1, P, P, P, None, 0, None, None) == _lib.ERR_ARG
+    assert L.excmg_solve_batched(H, 0, P, P, P, None, 0, None, None) == _lib.ERR_ARG

@@ -1,0 +1,143 @@
+"""Batched solves (many independent problems in shared launches) against the oracle and against one-at-a-time solves.
+
+Bars: FP64 problems match the oracle run with the batch's per-grid iteration counts to a relative L2 of 1e-12 (the
+parity bar of the single solve), with free-running counts within one of the oracle's.  Problems relaxed in FP32 inside
+FP64 refinement take other iterates than any FP64 run, so they are held to what the refinement promises: the final
+FP64 residual meets the tolerance on every grid, and the difference from the FP64 oracle solution stays below that
+solution's own error against the exact field (max norm), with a factor 2 margin.  (Two iterates that both meet a
+relative residual of 1e-10 can differ by a sizeable part of the discretisation error on strongly anisotropic grids,
+where M is badly conditioned: on the 128 x 192 x 192 problem with hx about 5 hy the difference is 15% of it.)
+"""
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def ex():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1507_05063_amd as m
+
+    return m
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def host(t):
+    return t.detach().to("cpu").numpy()
+
+
+def rel2(a, b):
+    return float(np.linalg.norm((a - b).ravel()) / max(np.linalg.norm(b.ravel()), 1e-300))
+
+
+# Uneven shapes and boxes, different level counts (1 to 5 grids) and every relaxation kind: direct solves only, the
+# single-workgroup CG (grids of <= 8000 unknowns), multi-workgroup FP64 CG.
+MIXED = [
+    ((32, 64, 96), (2, 4, 6), synth.smooth(0, (0.7, 1.3, 1.9))),
+    ((64, 64, 64), (4, 4, 4), synth.smooth(1)),
+    ((16, 16, 16), (4, 4, 4), synth.smooth(2, (1.0, 0.5, 0.8))),
+    ((8, 8, 8), (4, 4, 4), synth.example(2)),
+    ((6, 10, 14), (6, 10, 14), synth.example(3)),
+    ((96, 32, 64), (6, 2, 4), synth.smooth(3, (1.5, 0.6, 1.1))),
+    ((128, 64, 32), (8, 4, 2), synth.smooth(4)),
+]
+
+
+def _run(ex, cases, tol, precision):
+    solvers, fs, gs, data = [], [], [], []
+    for n, nc, p in cases:
+        f, g, u = synth.sample(p, n)
+        solvers.append(ex.Solver(n, p.box, tol, n_coarse=nc, precision=precision))
+        fs.append(dev(f))
+        gs.append(dev(g))
+        data.append((f, g, u, p))
+    us, stats, ms = ex.solve_batched(solvers, fs, gs)
+    return solvers, fs, gs, data, us, stats, ms
+
+
+def test_batched_fp64_matches_oracle(ex, orc):
+    tol = 1e-10
+    solvers, fs, gs, data, us, stats, ms = _run(ex, MIXED, tol, ex.FP64)
+    for (n, nc, p), s, (f, g, u, _), ub, st, t in zip(MIXED, solvers, data, us, stats, ms):
+        free = orc.excmg(f, g, p.box, s.n_coarse, tol)
+        gi = np.array(st["iters"], dtype=np.int32)
+        assert np.all(np.abs(gi - free["iters"]) <= 1), (n, gi, free["iters"])
+        ref = orc.excmg(f, g, p.box, s.n_coarse, tol, fixed_iters=gi)
+        ub = host(ub)
+        assert rel2(ub, ref["u"]) <= 1e-12, n
+        mask = synth.boundary_mask(n)
+        assert np.array_equal(ub[mask], g[mask])
+        for l in range(2, st["levels"]):
+            assert st["relres"][l] <= tol
+        assert t > 0.0
+
+
+def test_batched_equals_single_solves(ex):
+    tol = 1e-10
+    solvers, fs, gs, data, us, stats, ms = _run(ex, MIXED, tol, ex.FP64)
+    for s, f, g, ub, st in zip(solvers, fs, gs, us, stats):
+        u1, _, st1 = s.solve(f, g)
+        assert all(abs(a - b) <= 1 for a, b in zip(st["iters"], st1["iters"])), (st["iters"], st1["iters"])
+        assert rel2(host(ub), host(u1)) <= 1e-11
+
+
+def test_batched_repeatable(ex):
+    solvers, fs, gs, data, us, stats, ms = _run(ex, MIXED[:3], 1e-10, ex.FP64)
+    us2, stats2, _ = ex.solve_batched(solvers, fs, gs)
+    for a, b in zip(us, us2):
+        assert torch.equal(a, b)
+    assert [s["iters"] for s in stats] == [s["iters"] for s in stats2]
+
+
+def test_batched_rejects_bad_workspace(ex):
+    solvers, fs, gs, data, us, stats, ms = _run(ex, MIXED[3:4], 1e-10, ex.FP64)
+    small = torch.empty(64, dtype=torch.uint8, device="cuda")
+    import ctypes
+
+    from paper_1507_05063_amd import _lib
+
+    H = (ctypes.c_void_p * 1)(solvers[0].handle.value)
+    P = (ctypes.c_void_p * 1)(fs[0].data_ptr())
+    Q = (ctypes.c_void_p * 1)(gs[0].data_ptr())
+    U = (ctypes.c_void_p * 1)(us[0].data_ptr())
+    code = _lib.lib().excmg_solve_batched(H, 1, P, Q, U, ctypes.c_void_p(small.data_ptr()), 64, None, None)
+    assert code == _lib.ERR_WORKSPACE
+
+
+# ------------------------------------------------------------------------- the 96-problem workload, FP32 refinement
+
+@pytest.fixture(scope="module")
+def batch96(ex):
+    """96 problems (master seed 4): cells per axis from {32, 64, 96, 128, 192}, box edges U(0.5, 2), coarsest grid
+    N/16 per axis (5 grids), FP32-in-FP64 refinement, tolerance 1e-10."""
+    cases = [(n, tuple(v // 16 for v in n), p) for n, p in synth.batch(4, 96)]
+    solvers, fs, gs, data, us, stats, ms = _run(ex, cases, 1e-10, ex.FP32_IR)
+    return cases, solvers, data, [host(u) for u in us], stats, ms
+
+
+@pytest.mark.parametrize("b", range(0, 96, 8))
+def test_batch96_fp32_ir_against_oracle(ex, orc, batch96, b):
+    cases, solvers, data, us, stats, ms = batch96
+    for q in range(b, b + 8):
+        n, nc, p = cases[q]
+        f, g, u, _ = data[q]
+        st = stats[q]
+        assert st["levels"] == 5
+        for l in range(2, 5):
+            assert st["relres"][l] <= 1e-10, (q, n, st["relres"])
+        ref = orc.excmg(f, g, p.box, nc, 1e-10)
+        disc = np.max(np.abs(ref["u"] - u))
+        diff = np.max(np.abs(us[q] - ref["u"]))
+        assert diff <= 0.5 * disc, (q, n, diff, disc)
+        mask = synth.boundary_mask(n)
+        assert np.array_equal(us[q][mask], g[mask])
+        assert ms[q] > 0.0
