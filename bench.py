@@ -153,9 +153,74 @@ def bench_adjoint(ex, synth, torch, args):
             "adjoint_iters": st["iters"]}
 
 
+PROBE_BYTES = 2 << 30  # buffer of the streaming probe: its copy kernel reads PROBE_BYTES/2 and writes PROBE_BYTES/2
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "excmg_512_fp64_hbm_counters.txt")
+KERNEL_SOURCES = ["paper_1507_05063_amd/csrc/kernels_cg.hip", "paper_1507_05063_amd/csrc/excmg_internal.h"]
+
+
+def kernel_source_hash():
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def counter_summary(fetch_db, write_db):
+    """HBM bytes per dispatch from a FETCH_SIZE run and a WRITE_SIZE run (KiB per dispatch), each scaled so that the
+    probe's copy kernel (PROBE_BYTES/2 read, PROBE_BYTES/2 written) reads its known size.  One JSON line per
+    (kernel, grid size), for the working dispatches (at least a fifth of the group's largest value)."""
+    import re
+    import sqlite3
+
+    def load(db, counter):
+        c = sqlite3.connect(db)
+        g = {}
+        for nm, gx, cn, v in c.execute("select kernel_name, grid_size, counter_name, value from counters_collection"):
+            if cn != counter:
+                continue
+            nm = re.sub(r"\(.*", "", nm.replace("excmg::(anonymous namespace)::", "").replace("void ", ""))
+            g.setdefault((nm, gx), []).append(v)
+        return {k: [x for x in v if x >= 0.2 * max(v)] for k, v in g.items() if max(v) > 0}
+
+    fetch, write = load(fetch_db, "FETCH_SIZE"), load(write_db, "WRITE_SIZE")
+    probe = [k for k in fetch if k[0] == "probe_copy_kernel"]
+    fk = (PROBE_BYTES / 2) / (np.mean(fetch[probe[0]]) * 1024)
+    wk = (PROBE_BYTES / 2) / (np.mean(write[probe[0]]) * 1024)
+    print(json.dumps({"calibration": "probe_copy_kernel", "known_read_bytes": PROBE_BYTES // 2,
+                      "known_write_bytes": PROBE_BYTES // 2, "fetch_KiB": float(np.mean(fetch[probe[0]])),
+                      "write_KiB": float(np.mean(write[probe[0]])), "fetch_scale": round(fk, 4),
+                      "write_scale": round(wk, 4), "kernel_source_hash": kernel_source_hash()}))
+    for k in sorted(set(fetch) & set(write)):
+        fb = float(np.mean(fetch[k])) * 1024 * fk
+        wb = float(np.mean(write[k])) * 1024 * wk
+        print(json.dumps({"kernel": k[0], "grid": k[1], "dispatches": len(fetch[k]), "read_bytes": round(fb),
+                          "write_bytes": round(wb), "hbm_bytes": round(fb + wb)}))
+
+
+def measured_traffic(kernel, grid):
+    """HBM bytes per launch of (kernel, grid) from the committed counter summary, if it was taken on the current
+    kernel sources; else None."""
+    try:
+        lines = [json.loads(x) for x in open(COUNTERS_FILE) if x.startswith("{")]
+    except OSError:
+        return None
+    cal = [x for x in lines if "calibration" in x]
+    if not cal or cal[0]["kernel_source_hash"] != kernel_source_hash():
+        return None
+    for x in lines:
+        if x.get("kernel") == kernel and x.get("grid") == grid:
+            return x["hbm_bytes"]
+    return None
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--trace-summary", metavar="DB", help="print a summary of a rocprofv3 database and exit")
+    ap.add_argument("--counter-summary", nargs=2, metavar=("FETCH_DB", "WRITE_DB"),
+                    help="print HBM bytes per dispatch from a FETCH_SIZE and a WRITE_SIZE rocprofv3 run and exit")
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
@@ -170,6 +235,9 @@ def main():
     args = ap.parse_args()
     if args.trace_summary:
         trace_summary(args.trace_summary)
+        return
+    if args.counter_summary:
+        counter_summary(*args.counter_summary)
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU z-slab form of this "
@@ -190,7 +258,7 @@ def main():
     g = torch.from_numpy(g_np).cuda()
     print(f"# workload {N}^3 cells, inputs resident: {f.numel() * 16 / 1e9:.2f} GB", file=sys.stderr, flush=True)
 
-    copy_gbs, read_gbs = ex.bandwidth_probe(2 << 30)
+    copy_gbs, read_gbs = ex.bandwidth_probe(PROBE_BYTES)
     print(f"# streaming probe: copy {copy_gbs:.0f} GB/s, read {read_gbs:.0f} GB/s", file=sys.stderr, flush=True)
     s = ex.Solver(n, p.box, args.tol, timing=True)
     zc64 = s.autotune()
@@ -226,6 +294,11 @@ def main():
     nI = (N - 1) ** 3
     avg_ms = tot[dom] / max(calls[dom], 1)
     achieved = BYTES_PER_UNKNOWN[dom] * nI / (avg_ms * 1e-3) / 1e9
+    # measured HBM bytes of the same kernel and launch shape (z chunk) from the committed counter runs
+    zc_dom = zc64[-1][0 if dom == "cg_a" else 1]
+    grid_threads = -(-(N - 1) // 64) * -(-(N - 1) // 4) * -(-(N - 1) // zc_dom) * 256
+    traffic = measured_traffic("cg_pass_a_kernel<double>" if dom == "cg_a" else "cg_pass_b_kernel<double>",
+                               grid_threads)
     # stencil-CG sweeps of the finest grid alone: unknown-iterations per second of pass A + pass B kernel time
     fin_iters = stats[-1]["iters"][-1]
     cg_ms_fin = sum(st["kernel_ms_finest"]["cg_a"] + st["kernel_ms_finest"]["cg_b"] +
@@ -252,7 +325,9 @@ def main():
                                "(seed 0), incl. EXP_true and compact gradient",
                    "cells": list(n), "levels": stats[-1]["levels"], "tol": args.tol},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": round(traffic / (avg_ms * 1e-3) / 1e9, 1) if traffic else None,
+                     "traffic_bytes_per_launch": traffic, "traffic_grid": grid_threads,
                      "avg_launch_ms": round(avg_ms, 4), "bytes_per_launch": BYTES_PER_UNKNOWN[dom] * nI,
                      "probe_copy_GBs": round(copy_gbs, 1), "probe_read_GBs": round(read_gbs, 1),
                      "frac_of_probe_copy": round(achieved / copy_gbs, 4)},

@@ -47,8 +47,10 @@ extern "C" {
                            interior unknowns (smaller grids are latency-bound and relax in FP64) */
 
 #define EXCMG_WANT_HISTORY 1u /* record the finest level's relative-residual history (stats.history) */
-#define EXCMG_WANT_TIMING 2u  /* time every kernel on grids of >= 2^20 interior unknowns with HIP events
-                                 (stats.kernel_ms, kernel_calls); smaller grids are not timed */
+#define EXCMG_WANT_TIMING 2u  /* time every kernel of the finest grid with HIP events (stats.kernel_ms,
+                                 kernel_calls); the coarser grids are not timed */
+#define EXCMG_NO_GRAPHS 4u    /* launch every CG iteration directly instead of replaying graphs of iteration batches on
+                                 the grids below the finest (same kernels in the same order: same results) */
 
 #define EXCMG_MAX_LEVELS 16
 #define EXCMG_MAX_HISTORY 256
@@ -96,8 +98,8 @@ typedef struct {
                                                 FP32_IR: the FP64 outer residual) */
   double ms_level[EXCMG_MAX_LEVELS];         /* wall time of each grid's work (transfer + relaxation), ms */
   double ms_total;                           /* wall time of the call, ms */
-  double kernel_ms[EXCMG_K_CLASSES];         /* EXCMG_WANT_TIMING: summed kernel time per class, ms (CG launches
-                                                made after a grid converged are not counted) */
+  double kernel_ms[EXCMG_K_CLASSES];         /* EXCMG_WANT_TIMING: summed kernel time per class on the finest
+                                                grid, ms (CG launches made after it converged are not counted) */
   int32_t kernel_calls[EXCMG_K_CLASSES];     /* EXCMG_WANT_TIMING: launches per class */
   double kernel_ms_finest[EXCMG_K_CLASSES];  /* the same, finest grid only */
   int32_t kernel_calls_finest[EXCMG_K_CLASSES];

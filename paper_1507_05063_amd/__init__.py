@@ -11,7 +11,7 @@ import ctypes
 from typing import Optional, Sequence
 
 from . import _lib
-from ._lib import ExcmgError, FP32_IR, FP64, K_CLASSES, LIB_PATH, WANT_HISTORY, WANT_TIMING
+from ._lib import ExcmgError, FP32_IR, FP64, K_CLASSES, LIB_PATH, NO_GRAPHS, WANT_HISTORY, WANT_TIMING
 
 __all__ = ["Solver", "ExcmgError", "FP64", "FP32_IR", "plan", "workspace_bytes", "op_apply", "op_rhs",
            "op_exp_finite", "op_exp_true", "solve_batched", "batch_workspace_bytes", "bandwidth_probe", "K_CLASSES",
@@ -80,13 +80,13 @@ class Solver:
 
     def __init__(self, n: Sequence[int], box=(1.0, 1.0, 1.0), tol: float = 1e-10, n_coarse=(0, 0, 0),
                  precision: int = FP64, inner_tol: float = 0.0, max_iters: int = 0, history: bool = False,
-                 timing: bool = False, stream=None):
+                 timing: bool = False, graphs: bool = True, stream=None):
         torch = _torch()
         self.n = tuple(int(v) for v in n)
         self.box = tuple(float(v) for v in box)
         self.tol = float(tol)
         self.precision = int(precision)
-        flags = (WANT_HISTORY if history else 0) | (WANT_TIMING if timing else 0)
+        flags = (WANT_HISTORY if history else 0) | (WANT_TIMING if timing else 0) | (0 if graphs else NO_GRAPHS)
         self._p = _problem(self.n, self.box, tol, n_coarse, precision, inner_tol, max_iters, flags)
         nbytes = ctypes.c_size_t(0)
         _lib.check(_lib.lib().excmg_workspace_bytes(ctypes.byref(self._p), ctypes.byref(nbytes)),

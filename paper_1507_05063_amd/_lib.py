@@ -14,7 +14,7 @@ LIB_PATH = os.path.join(HERE, "libexcmg.so")
 OK = 0
 ERR_ARG, ERR_SHAPE, ERR_NONFINITE, ERR_NOCONV, ERR_BREAKDOWN, ERR_HIP, ERR_WORKSPACE = -1, -2, -3, -4, -5, -6, -7
 FP64, FP32_IR = 0, 1
-WANT_HISTORY, WANT_TIMING = 1, 2
+WANT_HISTORY, WANT_TIMING, NO_GRAPHS = 1, 2, 4
 MAX_LEVELS, MAX_HISTORY = 16, 256
 
 K_CLASSES = ["cg_a", "cg_b", "cg_a32", "cg_b32", "resid", "finalize", "rhs", "exp_finite", "exp_true", "dsolve",

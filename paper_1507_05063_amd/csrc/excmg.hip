@@ -93,7 +93,7 @@ int validate(const excmg_problem *p) {
   if (p->precision != EXCMG_FP64 && p->precision != EXCMG_FP32_IR) return EXCMG_ERR_ARG;
   if (p->inner_tol < 0.0 || !isfinite(p->inner_tol) || p->inner_tol >= 1.0) return EXCMG_ERR_ARG;
   if (p->max_iters < 0) return EXCMG_ERR_ARG;
-  if (p->flags & ~(EXCMG_WANT_HISTORY | EXCMG_WANT_TIMING)) return EXCMG_ERR_ARG;
+  if (p->flags & ~(EXCMG_WANT_HISTORY | EXCMG_WANT_TIMING | EXCMG_NO_GRAPHS)) return EXCMG_ERR_ARG;
   return EXCMG_OK;
 }
 
@@ -182,6 +182,31 @@ struct excmg_handle {
   std::vector<TimedLaunch> timed;
   size_t pool_used;
   bool timing;
+  // pinned host memory the device writes CG states (and batch status words) into; pin_dev is its device address
+  void *pin_host = nullptr, *pin_dev = nullptr;
+  size_t pin_bytes = 0;
+  // graphs of kBatch CG iterations per grid (FP64, FP32 inner), captured on first use on a private stream
+  hipStream_t cap = nullptr;
+  hipGraphExec_t gexec[EXCMG_MAX_LEVELS][2] = {};
+
+  void drop_graphs() {
+    for (auto &row : gexec)
+      for (auto &ex : row)
+        if (ex) {
+          (void)hipGraphExecDestroy(ex);
+          ex = nullptr;
+        }
+  }
+
+  ~excmg_handle() {
+    drop_graphs();
+    if (cap) (void)hipStreamDestroy(cap);
+    for (int l = 0; l <= EXCMG_MAX_LEVELS; ++l)
+      if (lev_ev[l]) (void)hipEventDestroy(lev_ev[l]);
+    for (auto &ev : pool)
+      if (ev) (void)hipEventDestroy(ev);
+    if (pin_host) (void)hipHostFree(pin_host);
+  }
 };
 
 namespace {
@@ -206,9 +231,8 @@ struct DeviceGuard {
 
 inline int last_error() { return hipGetLastError() == hipSuccess ? EXCMG_OK : EXCMG_ERR_HIP; }
 
-// Kernel timing: a pair of events around each launch on grids of at least 2^20 interior unknowns when
-// EXCMG_WANT_TIMING is set (on smaller grids the event records would cost as much as the kernels they time).
-constexpr long long kTimedMinUnknowns = 1LL << 20;
+// Kernel timing: a pair of events around each launch on the finest grid when EXCMG_WANT_TIMING is set (the coarser
+// grids' launches are replayed from graphs, and their event records would cost as much as the kernels they time).
 
 struct Tick {
   excmg_handle *h;
@@ -221,7 +245,7 @@ struct Tick {
 
 Tick::Tick(excmg_handle *h_, int cls, int level, int iter, int outer) : h(h_), idx(-1) {
     if (!h->timing || h->pool_used + 2 > h->pool.size()) return;
-    if (h->lo.lev[level].g.interior() < kTimedMinUnknowns) return;
+    if (level != h->lo.L - 1) return;
     TimedLaunch t;
     t.cls = cls;
     t.level = level;
@@ -234,17 +258,39 @@ Tick::Tick(excmg_handle *h_, int cls, int level, int iter, int outer) : h(h_), i
     idx = (int)h->timed.size() - 1;
 }
 
-int read_state(excmg_handle *h, CgState *dst, const CgState *src) {
-  HIPCHECK(hipMemcpyAsync(dst, src, offsetof(CgState, hist), hipMemcpyDeviceToHost, h->stream));
-  HIPCHECK(hipStreamSynchronize(h->stream));
+// Pinned host memory of at least bytes for the handle's published records (grown on demand).
+int ensure_pinned(excmg_handle *h, size_t bytes) {
+  if (h->pin_bytes >= bytes) return EXCMG_OK;
+  if (h->pin_host) {
+    HIPCHECK(hipStreamSynchronize(h->stream));
+    (void)hipHostFree(h->pin_host);
+    h->pin_host = h->pin_dev = nullptr;
+    h->pin_bytes = 0;
+  }
+  bytes = (bytes + 4095) & ~(size_t)4095;
+  HIPCHECK(hipHostMalloc(&h->pin_host, bytes, hipHostMallocMapped | hipHostMallocCoherent));
+  HIPCHECK(hipHostGetDevicePointer(&h->pin_dev, h->pin_host, 0));
+  h->pin_bytes = bytes;
   return EXCMG_OK;
 }
 
-int read_hist(excmg_handle *h, CgState *dst, const CgState *src) {
-  HIPCHECK(hipMemcpyAsync(dst, src, sizeof(CgState), hipMemcpyDeviceToHost, h->stream));
+// Copy `bytes` of a device record to the host: a one-workgroup kernel writes it into the pinned buffer, then the host
+// waits for the stream and reads it there.
+int read_record(excmg_handle *h, void *dst, const void *src, size_t bytes) {
+  int e = ensure_pinned(h, bytes);
+  if (e) return e;
+  launch_publish(src, h->pin_dev, bytes, h->stream);
+  HIPCHECK(hipGetLastError());
   HIPCHECK(hipStreamSynchronize(h->stream));
+  memcpy(dst, h->pin_host, bytes);
   return EXCMG_OK;
 }
+
+int read_state(excmg_handle *h, CgState *dst, const CgState *src) {
+  return read_record(h, dst, src, offsetof(CgState, hist));
+}
+
+int read_hist(excmg_handle *h, CgState *dst, const CgState *src) { return read_record(h, dst, src, sizeof(CgState)); }
 
 // Per-level iteration counts of CG-class timed launches, to drop launches made after convergence.
 struct LevelIters {
@@ -253,6 +299,21 @@ struct LevelIters {
 };
 
 constexpr int kBatch = 4;
+constexpr int kBatchMax = 16;
+
+// CG iterations to launch before the next look at the state: from the residual decay since the start (rho0 -> rho over
+// `done` iterations), the geometric rate predicts how many remain; a few more are launched than predicted, since
+// iterations launched after convergence cost a near-empty launch each while a look costs a round trip.
+int next_batch(double rho, double rho0, int done, double stop2) {
+  if (done <= 0 || !(rho > 0.0) || !(rho0 > rho) || !(stop2 > 0.0)) return kBatch;
+  if (rho <= stop2) return 1;
+  const double rate = log(rho / rho0) / done;  // < 0
+  const double need = log(stop2 / rho) / rate;
+  int n = (int)ceil(1.15 * need) + 1;
+  if (n < 2) n = 2;
+  if (n > kBatchMax) n = kBatchMax;
+  return n;
+}
 
 // Grids smaller than this relax in FP64 under EXCMG_FP32_IR as well: their sweeps are launch- and latency-bound, so
 // halving their bytes saves nothing, while the extra outer steps of the refinement would cost launches.
@@ -261,12 +322,103 @@ constexpr long long kIrMinUnknowns = 1LL << 20;
 // Grids with at most this many interior unknowns (16^3 cells and below) relax in one single-workgroup launch.
 constexpr long long kSmallCg = 8000;
 
-// FP64 CG on level l from the current u (Algorithm 1, the while loop; one iteration per pass).
 bool self_finalizing(const Level &lv, bool fp32) {
   const int m = selfred_max_blocks();
   const Sweep &a = fp32 ? lv.swA32 : lv.swA, &b = fp32 ? lv.swB32 : lv.swB;
   return sweep_blocks(a) <= m && sweep_blocks(b) <= m && sweep_blocks(lv.sw) <= m;
 }
+
+// One CG iteration of grid l on stream s: FP64 (fp32 = 0) on u, r, p, or the FP32 inner solve (fp32 = 1) on d32, r32,
+// p32.  first: the first FP64 iteration of a self-finalizing grid, whose pass A sums the residual sweep's partials.
+// launched: iteration index for the kernel timing.
+void launch_iteration(excmg_handle *h, int l, int fp32, bool first, hipStream_t s, int launched, int outer) {
+  Level &lv = h->lo.lev[l];
+  double *pa = h->partials, *pb = h->partials + h->lo.npart;
+  if (fp32) {
+    if (self_finalizing(lv, true)) {
+      {
+        Tick t(h, EXCMG_K_CG_A32, l, launched, outer);
+        launch_selfred_a<float>(lv.swA32, h->r32, h->p32a, h->p32b, h->cs2, pb, sweep_blocks(lv.swB32), h->p.tol,
+                                pa, s);
+      }
+      Tick t(h, EXCMG_K_CG_B32, l, launched, outer);
+      launch_selfred_b<float>(lv.swB32, h->d32, h->r32, h->p32a, h->p32b, h->cs2, pa, sweep_blocks(lv.swA32), pb, s);
+    } else {
+      {
+        Tick t(h, EXCMG_K_CG_A32, l, launched, outer);
+        launch_cg_pass_a<float>(lv.swA32, h->r32, h->p32a, h->p32b, h->cs2, h->partials, s);
+      }
+      Tick t(h, EXCMG_K_CG_B32, l, launched, outer);
+      launch_cg_pass_b<float>(lv.swB32, h->d32, h->r32, h->p32a, h->p32b, h->cs2, h->partials, s);
+    }
+    return;
+  }
+  if (self_finalizing(lv, false)) {
+    {
+      Tick t(h, EXCMG_K_CG_A, l, launched);
+      launch_selfred_a<double>(lv.swA, h->r, h->p0, h->p1, h->cs, pb,
+                               first ? sweep_blocks(lv.sw) : sweep_blocks(lv.swB), h->p.tol, pa, s);
+    }
+    Tick t(h, EXCMG_K_CG_B, l, launched);
+    launch_selfred_b<double>(lv.swB, lv.u, h->r, h->p0, h->p1, h->cs, pa, sweep_blocks(lv.swA), pb, s);
+  } else {
+    {
+      Tick t(h, EXCMG_K_CG_A, l, launched);
+      launch_cg_pass_a<double>(lv.swA, h->r, h->p0, h->p1, h->cs, h->partials, s);
+    }
+    Tick t(h, EXCMG_K_CG_B, l, launched);
+    launch_cg_pass_b<double>(lv.swB, lv.u, h->r, h->p0, h->p1, h->cs, h->partials, s);
+  }
+}
+
+// Graphs replace the iteration launches on every grid but the finest (where launches are long and may be timed),
+// unless EXCMG_NO_GRAPHS is set.
+bool use_graphs(const excmg_handle *h, int l) { return !(h->p.flags & EXCMG_NO_GRAPHS) && l < h->lo.L - 1; }
+
+// kBatch CG iterations of grid l (not the first of a self-finalizing FP64 solve) as one graph launch on the handle's
+// stream.  The graph holds kernel launches only; it is captured on first use and kept until the sweeps change.
+int launch_iteration_graph(excmg_handle *h, int l, int fp32) {
+  hipGraphExec_t &ex = h->gexec[l][fp32];
+  if (!ex) {
+    hipGraph_t g = nullptr;
+    HIPCHECK(hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal));
+    for (int q = 0; q < kBatch; ++q) launch_iteration(h, l, fp32, false, h->cap, -1, -1);
+    const hipError_t ec = hipStreamEndCapture(h->cap, &g);
+    if (ec != hipSuccess) return EXCMG_ERR_HIP;
+    const hipError_t ei = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ei != hipSuccess) {
+      ex = nullptr;
+      return EXCMG_ERR_HIP;
+    }
+  }
+  HIPCHECK(hipGraphLaunch(ex, h->stream));
+  return EXCMG_OK;
+}
+
+// Launch nb iterations (rounded up to whole graphs where graphs are used); returns the new launched count.
+int launch_iterations(excmg_handle *h, int l, int fp32, int nb, int launched, int outer, int *err) {
+  *err = EXCMG_OK;
+  const bool selfred64 = !fp32 && self_finalizing(h->lo.lev[l], false);
+  if (!use_graphs(h, l)) {
+    for (int q = 0; q < nb; ++q, ++launched)
+      launch_iteration(h, l, fp32, selfred64 && launched == 0, h->stream, launched, outer);
+    return launched;
+  }
+  int q = 0;
+  if (selfred64 && launched == 0) {
+    launch_iteration(h, l, fp32, true, h->stream, launched, outer);
+    ++q;
+    ++launched;
+  }
+  for (; q < nb; q += kBatch, launched += kBatch) {
+    *err = launch_iteration_graph(h, l, fp32);
+    if (*err) return launched;
+  }
+  return launched;
+}
+
+// FP64 CG on level l from the current u (Algorithm 1, the while loop; one iteration per pass).
 
 int cg64(excmg_handle *h, int l, const RhsSrc &rs, bool finest, int *iters, double *relres, excmg_stats *st) {
   Level &lv = h->lo.lev[l];
@@ -274,7 +426,7 @@ int cg64(excmg_handle *h, int l, const RhsSrc &rs, bool finest, int *iters, doub
   const int hist_on = (finest && st && (h->p.flags & EXCMG_WANT_HISTORY)) ? 1 : 0;
   const int maxit = h->p.max_iters > 0 ? h->p.max_iters : 10000;
   const bool selfred = self_finalizing(lv, false);
-  double *partsA = h->partials, *partsB = h->partials + h->lo.npart;
+  double *partsB = h->partials + h->lo.npart;
   {
     Tick t(h, EXCMG_K_RESID, l);
     if (selfred) {
@@ -288,34 +440,15 @@ int cg64(excmg_handle *h, int l, const RhsSrc &rs, bool finest, int *iters, doub
   if (e) return e;
   CgState hs;
   int launched = 0;
-  for (;;) {
-    for (int q = 0; q < kBatch; ++q, ++launched) {
-      if (selfred) {
-        {
-          Tick t(h, EXCMG_K_CG_A, l, launched);
-          launch_selfred_a<double>(lv.swA, h->r, h->p0, h->p1, h->cs, partsB,
-                                   launched == 0 ? sweep_blocks(lv.sw) : sweep_blocks(lv.swB), h->p.tol, partsA, s);
-        }
-        {
-          Tick t(h, EXCMG_K_CG_B, l, launched);
-          launch_selfred_b<double>(lv.swB, lv.u, h->r, h->p0, h->p1, h->cs, partsA, sweep_blocks(lv.swA), partsB, s);
-        }
-        continue;
-      }
-      {
-        Tick t(h, EXCMG_K_CG_A, l, launched);
-        launch_cg_pass_a<double>(lv.swA, h->r, h->p0, h->p1, h->cs, h->partials, s);
-      }
-      {
-        Tick t(h, EXCMG_K_CG_B, l, launched);
-        launch_cg_pass_b<double>(lv.swB, lv.u, h->r, h->p0, h->p1, h->cs, h->partials, s);
-      }
-    }
+  for (int nb = kBatch;;) {
+    launched = launch_iterations(h, l, 0, nb, launched, -1, &e);
+    if (e) return e;
     e = last_error();
     if (e) return e;
     e = read_state(h, &hs, h->cs);
     if (e) return e;
     if (hs.done) break;
+    nb = next_batch(hs.rho, hs.rho0, hs.iter, hs.stop2);
   }
   *iters = hs.iter;
   *relres = hs.bnorm2 > 0.0 ? sqrt(hs.rho / hs.bnorm2) : 0.0;
@@ -358,37 +491,15 @@ int cg_ir(excmg_handle *h, int l, const RhsSrc &rs, bool finest, int *iters, int
       break;
     }
     int launched = 0;
-    const bool selfred = self_finalizing(lv, true);
-    for (;;) {
-      for (int q = 0; q < kBatch; ++q, ++launched) {
-        if (selfred) {
-          double *pa = h->partials, *pb = h->partials + h->lo.npart;
-          {
-            Tick t(h, EXCMG_K_CG_A32, l, launched, outer);
-            launch_selfred_a<float>(lv.swA32, h->r32, h->p32a, h->p32b, h->cs2, pb, sweep_blocks(lv.swB32), h->p.tol,
-                                    pa, s);
-          }
-          {
-            Tick t(h, EXCMG_K_CG_B32, l, launched, outer);
-            launch_selfred_b<float>(lv.swB32, h->d32, h->r32, h->p32a, h->p32b, h->cs2, pa, sweep_blocks(lv.swA32),
-                                    pb, s);
-          }
-          continue;
-        }
-        {
-          Tick t(h, EXCMG_K_CG_A32, l, launched, outer);
-          launch_cg_pass_a<float>(lv.swA32, h->r32, h->p32a, h->p32b, h->cs2, h->partials, s);
-        }
-        {
-          Tick t(h, EXCMG_K_CG_B32, l, launched, outer);
-          launch_cg_pass_b<float>(lv.swB32, h->d32, h->r32, h->p32a, h->p32b, h->cs2, h->partials, s);
-        }
-      }
+    for (int nb = kBatch;;) {
+      launched = launch_iterations(h, l, 1, nb, launched, outer, &e);
+      if (e) return e;
       e = last_error();
       if (e) return e;
       e = read_state(h, &hi, h->cs2);
       if (e) return e;
       if (hi.done) break;
+      nb = next_batch(hi.rho, hi.rho0, hi.iter, hi.stop2);
     }
     total += hi.iter;
     if (inner_counts) inner_counts->push_back(hi.iter);
@@ -577,8 +688,11 @@ size_t batch_table_bytes(int count) {
   return align256(sizeof(BatchEntry) * (size_t)count) + align256(sizeof(int) * (size_t)kLaunchKinds * (count + 1));
 }
 
+size_t batch_dyn_bytes(int count) { return align256(sizeof(int) * (size_t)kLaunchKinds * (count + 1)); }
+
 size_t batch_ws_bytes(int count) {
-  return align256(sizeof(BatchStatus) * (size_t)count) + 256 + (size_t)EXCMG_MAX_LEVELS * batch_table_bytes(count);
+  return align256(sizeof(BatchStatus) * (size_t)count) + 256 + (size_t)EXCMG_MAX_LEVELS * batch_table_bytes(count) +
+         batch_dyn_bytes(count);
 }
 
 int batch_kind(const excmg_handle *h, int l) {
@@ -695,8 +809,30 @@ int batched_solve(excmg_handle *const *hs, int count, const double *const *f, co
 
   std::vector<BatchStatus> hstat(count);
   auto read_stat = [&]() -> int {
-    HIPCHECK(hipMemcpyAsync(hstat.data(), stat, sizeof(BatchStatus) * (size_t)count, hipMemcpyDeviceToHost, s));
-    HIPCHECK(hipStreamSynchronize(s));
+    return read_record(hs[0], hstat.data(), stat, sizeof(BatchStatus) * (size_t)count);
+  };
+  // Prefix arrays of the iteration launches restricted to the problems still iterating, rebuilt after every look at
+  // the status words (converged problems get no workgroups).  Written into pinned host memory behind the status
+  // words and copied to the dynamic block of the batch workspace; every copy is complete before the next rebuild,
+  // which follows a stream synchronisation.
+  int *dynP = (int *)(tables + (size_t)EXCMG_MAX_LEVELS * tb);
+  const size_t stat_bytes = align256(sizeof(BatchStatus) * (size_t)count);
+  if ((e = ensure_pinned(hs[0], stat_bytes + batch_dyn_bytes(count)))) return e;
+  int *dynH = (int *)((char *)hs[0]->pin_host + stat_bytes);
+  auto active_prefix = [&](const int *P_host, int kA, int slot, int kind, const int *kd, int *totA, int *totB) -> int {
+    for (int k = kA; k <= kA + 1; ++k) {
+      int *o = dynH + (size_t)k * n1;
+      const int *src = P_host + (size_t)k * n1;
+      o[0] = 0;
+      for (int b = 0; b < count; ++b) {
+        const bool on = kd[b] == kind && !hstat[b].m[slot].done && !(slot == 1 && hstat[b].m[0].done);
+        o[b + 1] = o[b] + (on ? src[b + 1] - src[b] : 0);
+      }
+    }
+    *totA = dynH[(size_t)kA * n1 + count];
+    *totB = dynH[(size_t)(kA + 1) * n1 + count];
+    HIPCHECK(hipMemcpyAsync(dynP + (size_t)kA * n1, dynH + (size_t)kA * n1, sizeof(int) * 2 * (size_t)n1,
+                            hipMemcpyHostToDevice, s));
     return EXCMG_OK;
   };
   if (stats)
@@ -711,29 +847,48 @@ int batched_solve(excmg_handle *const *hs, int count, const double *const *f, co
   for (int st = 0; st < S; ++st) {
     const BatchEntry *T = (const BatchEntry *)(tables + st * tb);
     const int *P = (const int *)(tables + st * tb + pre_off);
+    const int *P_host = (const int *)(host.data() + st * tb + pre_off);
     const int *tot = &totals[(size_t)st * kLaunchKinds];
     const int *kd = &kinds[(size_t)st * count];
     bool any[4] = {false, false, false, false};
     for (int b = 0; b < count; ++b) any[kd[b]] = true;
     launch_b_set_boundary(T, P, count, tot[kLSetB], s);
     launch_b_exp_finite(T, P, count, tot[kLExp], s);
-    if (any[kBSmall]) launch_b_small_cg(T, count, stat, s);
+    if (any[kBSmall]) {
+      int lds = 0;
+      for (int b = 0; b < count; ++b)
+        if (kd[b] == kBSmall) {
+          const int v = b_small_lds_nodes(hs[b]->lo.lev[st].g);
+          lds = v > lds ? v : lds;
+        }
+      launch_b_small_cg(T, count, lds, stat, s);
+    }
     launch_b_boundary_terms(T, P, count, tot[kLBterm], s);
     if ((e = last_error())) return e;
     if (any[kBCg64]) {
       launch_b_residual(T, P, count, tot[kLR64], stat, s);
-      for (int launched = 0;;) {
-        for (int q = 0; q < kBatch; ++q, ++launched)
-          launch_b_iteration(0, T, P, count, tot[kLA64], tot[kLB64], stat, s);
+      const int *PI = P;  // the step's prefix arrays until the first look, then the active ones
+      int tA = tot[kLA64], tB = tot[kLB64];
+      for (int launched = 0, nb = kBatch;;) {
+        for (int q = 0; q < nb; ++q, ++launched) launch_b_iteration(0, T, PI, count, tA, tB, stat, s);
         if ((e = last_error()) || (e = read_stat())) return e;
         bool all = true;
+        nb = 1;
         for (int b = 0; b < count; ++b)
-          if (kd[b] == kBCg64 && !hstat[b].m[0].done) all = false;
+          if (kd[b] == kBCg64 && !hstat[b].m[0].done) {
+            all = false;
+            const BatchMirror &m = hstat[b].m[0];
+            const int want = next_batch(m.rho, m.rho0, m.iter, m.stop2);
+            nb = want > nb ? want : nb;
+          }
         if (all) break;
-        if (launched > cap_max + kBatch) return EXCMG_ERR_NOCONV;  // the device caps every CG; not reached
+        if (launched > cap_max + kBatchMax) return EXCMG_ERR_NOCONV;  // the device caps every CG; not reached
+        if ((e = active_prefix(P_host, kLA64, 0, kBCg64, kd, &tA, &tB))) return e;
+        PI = dynP;
       }
     }
     if (any[kBIr]) {
+      int tA32 = 0, tB32 = 0;
       for (int b = 0; b < count; ++b) inner_total[b] = 0;
       for (int outer = 0;; ++outer) {
         launch_b_residual_cast(T, P, count, tot[kLRC], outer, stat, s);
@@ -743,15 +898,22 @@ int batched_solve(excmg_handle *const *hs, int count, const double *const *f, co
           if (kd[b] == kBIr && !hstat[b].m[0].done) all = false;
         if (all) break;
         if (outer > 64) return EXCMG_ERR_NOCONV;  // the device caps the outer steps at 30; not reached
-        for (int launched = 0;;) {
-          for (int q = 0; q < kBatch; ++q, ++launched)
-            launch_b_iteration(1, T, P, count, tot[kLA32], tot[kLB32], stat, s);
+        if ((e = active_prefix(P_host, kLA32, 1, kBIr, kd, &tA32, &tB32))) return e;
+        for (int launched = 0, nb = kBatch;;) {
+          for (int q = 0; q < nb; ++q, ++launched) launch_b_iteration(1, T, dynP, count, tA32, tB32, stat, s);
           if ((e = last_error()) || (e = read_stat())) return e;
           bool idone = true;
+          nb = 1;
           for (int b = 0; b < count; ++b)
-            if (kd[b] == kBIr && !hstat[b].m[0].done && !hstat[b].m[1].done) idone = false;
+            if (kd[b] == kBIr && !hstat[b].m[0].done && !hstat[b].m[1].done) {
+              idone = false;
+              const BatchMirror &m = hstat[b].m[1];
+              const int want = next_batch(m.rho, m.rho0, m.iter, m.stop2);
+              nb = want > nb ? want : nb;
+            }
           if (idone) break;
-          if (launched > cap_max + kBatch) return EXCMG_ERR_NOCONV;
+          if (launched > cap_max + kBatchMax) return EXCMG_ERR_NOCONV;
+          if ((e = active_prefix(P_host, kLA32, 1, kBIr, kd, &tA32, &tB32))) return e;
         }
         for (int b = 0; b < count; ++b)
           if (kd[b] == kBIr && !hstat[b].m[0].done) {
@@ -779,8 +941,7 @@ int batched_solve(excmg_handle *const *hs, int count, const double *const *f, co
     }
   }
   long long t_start = 0;
-  HIPCHECK(hipMemcpyAsync(&t_start, t0, sizeof(long long), hipMemcpyDeviceToHost, s));
-  HIPCHECK(hipStreamSynchronize(s));
+  if ((e = read_record(hs[0], &t_start, t0, sizeof(long long)))) return e;
   int rate_khz = 0;
   HIPCHECK(hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, hs[0]->device));
   const double host_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_host).count();
@@ -864,6 +1025,11 @@ int excmg_setup(const excmg_problem *p, void *workspace, size_t bytes, void *hip
       return EXCMG_ERR_HIP;
     }
   }
+  if (ensure_pinned(h, sizeof(CgState)) != EXCMG_OK ||
+      hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking) != hipSuccess) {
+    delete h;
+    return EXCMG_ERR_HIP;
+  }
   h->timing = (p->flags & EXCMG_WANT_TIMING) != 0;
   h->pool_used = 0;
   if (h->timing) {
@@ -895,11 +1061,10 @@ int excmg_solve(excmg_handle *h, const double *f, const double *g, double *u, do
   if (status != EXCMG_OK && status != EXCMG_ERR_NOCONV) return status;
   Layout &lo = h->lo;
   const Level &fin = lo.lev[lo.L - 1];
-  if (u_ext) {
+  if (u_ext) {  // EXP_true also writes u to the caller's array from the same read of u_h
     Tick t(h, EXCMG_K_EXP_TRUE, lo.L - 1);
-    launch_exp_true(fin.g, fin.u, lo.lev[lo.L - 2].g, lo.lev[lo.L - 2].u, lo.gdense, u_ext, h->stream);
-  }
-  {
+    launch_exp_true(fin.g, fin.u, lo.lev[lo.L - 2].g, lo.lev[lo.L - 2].u, lo.gdense, u_ext, u, h->stream);
+  } else {
     Tick t(h, EXCMG_K_OTHER, lo.L - 1);
     launch_copy(fin.g, fin.u, lo.gdense, u, h->stream);
   }
@@ -955,6 +1120,7 @@ int excmg_adjoint(excmg_handle *h, const double *G, double *dLdf, double *dLdg, 
 int excmg_autotune(excmg_handle *h, int32_t *zc_out) {
   if (!h) return EXCMG_ERR_ARG;
   DeviceGuard dg(h->device);
+  h->drop_graphs();  // captured with the old sweep shapes
   const hipStream_t s = h->stream;
   Layout &lo = h->lo;
   static const int cand[] = {2, 4, 8, 16, 32, 64};
@@ -1025,11 +1191,7 @@ void excmg_destroy(excmg_handle *h) {
   if (!h) return;
   DeviceGuard dg(h->device);
   (void)hipStreamSynchronize(h->stream);
-  for (int l = 0; l <= EXCMG_MAX_LEVELS; ++l)
-    if (h->lev_ev[l]) (void)hipEventDestroy(h->lev_ev[l]);
-  for (auto &ev : h->pool)
-    if (ev) (void)hipEventDestroy(ev);
-  delete h;
+  delete h;  // events and the pinned buffer are released by the handle's destructor
 }
 
 const char *excmg_strerror(int code) {
@@ -1115,7 +1277,7 @@ int excmg_op_exp_true(const int32_t n[3], const double *uh, const double *u2h, d
   const hipStream_t s = (hipStream_t)hip_stream;
   const Grid gh = dense_grid(n[0], n[1], n[2]);
   const Grid g2 = dense_grid(n[0] / 2, n[1] / 2, n[2] / 2);
-  launch_exp_true(gh, uh, g2, u2h, gh, ut, s);
+  launch_exp_true(gh, uh, g2, u2h, gh, ut, nullptr, s);
   int e = last_error();
   if (e) return e;
   HIPCHECK(hipStreamSynchronize(s));

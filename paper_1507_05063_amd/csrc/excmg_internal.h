@@ -87,7 +87,7 @@ struct RhsSrc {
 };
 
 // A's couplings to the Dirichlet values of the boundary neighbours of (i,j,k) (only nodes next to the boundary have any)
-__device__ __noinline__ inline double rhs_boundary_terms(const RhsSrc &rs, int nx, int ny, int nz, int i, int j,
+__device__ __forceinline__ double rhs_boundary_terms_inl(const RhsSrc &rs, int nx, int ny, int nz, int i, int j,
                                                          int k) {
   const int s = rs.s;
   const double a = rs.a, b = rs.b, c = rs.c;
@@ -109,6 +109,13 @@ __device__ __noinline__ inline double rhs_boundary_terms(const RhsSrc &rs, int n
   return lg;
 }
 
+// The same as a call (kept out of line in the large sweep kernels, where it runs only for nodes next to the boundary).
+__device__ __noinline__ inline double rhs_boundary_terms(const RhsSrc &rs, int nx, int ny, int nz, int i, int j,
+                                                         int k) {
+  return rhs_boundary_terms_inl(rs, nx, ny, nz, i, j, k);
+}
+
+template <bool kInline = false>
 __device__ __forceinline__ double rhs_at(const RhsSrc &rs, int nx, int ny, int nz, int i, int j, int k) {
   const int s = rs.s;
   auto F = [&](int di, int dj, int dk) { return rs.f[rs.gf.at((i + di) * s, (j + dj) * s, (k + dk) * s)]; };
@@ -117,7 +124,7 @@ __device__ __forceinline__ double rhs_at(const RhsSrc &rs, int nx, int ny, int n
                            (F(0, 0, 1) + F(0, 0, -1)));
   double lg = 0.0;
   if (i == 1 || j == 1 || k == 1 || i == nx - 1 || j == ny - 1 || k == nz - 1)
-    lg = rhs_boundary_terms(rs, nx, ny, nz, i, j, k);
+    lg = kInline ? rhs_boundary_terms_inl(rs, nx, ny, nz, i, j, k) : rhs_boundary_terms(rs, nx, ny, nz, i, j, k);
   return -rf + lg;
 }
 
@@ -129,6 +136,7 @@ struct CgState {
   double alpha, beta;
   double bnorm2;   // ||b||^2 of the system being solved
   double stop2;    // stop when rho <= stop2 (= (tol ||b||)^2)
+  double rho0;     // rho of the starting residual (the host predicts how many iterations remain from it)
   int iter;        // iterations completed
   int done;        // 1: converged or stopped; every CG kernel returns at once
   int status;      // 0 ok, EXCMG_ERR_NOCONV, EXCMG_ERR_BREAKDOWN
@@ -202,6 +210,8 @@ void launch_cg_pass_b(const Sweep &sw, T *u, T *r, const T *p0, const T *p1, CgS
 
 // CG state for timing sweeps in isolation: iteration 0, alpha = beta = 0, never done
 void launch_tune_state(CgState *cs, hipStream_t st);
+// copy bytes (a multiple of 8) from device memory to host memory mapped for the device
+void launch_publish(const void *src, void *dst, size_t bytes, hipStream_t st);
 
 // u += (double) d32 on the interior
 void launch_add_correction(const Grid &gu, double *u, const Grid &g32, const float *d32, hipStream_t st);
@@ -225,7 +235,7 @@ void launch_exp_finite(const Grid &g2, const double *u2, const Grid &g4, const d
                        const double *g, int stride, const Grid &gw, double *w, hipStream_t st);
 // ut (grid gt) = EXP_true(uh (grid gh), u2 (grid g2))
 void launch_exp_true(const Grid &gh, const double *uh, const Grid &g2, const double *u2, const Grid &gt, double *ut,
-                     hipStream_t st);
+                     double *ucopy, hipStream_t st);
 // copy between layouts (same n)
 void launch_copy(const Grid &gs, const double *src, const Grid &gd, double *dst, hipStream_t st);
 // count of non-finite values in a dense array -> *flag (device int, must be zeroed by the caller)
@@ -252,7 +262,7 @@ enum BatchLaunch {
 
 struct BatchMirror {  // copy of one CG state's scalars, for the host
   int done, iter, status, pad;
-  double rho, bnorm2;
+  double rho, bnorm2, rho0, stop2;
 };
 
 struct BatchStatus {
@@ -289,7 +299,8 @@ struct BatchEntry {
 void launch_b_init(BatchStatus *stat, int count, long long *t0, hipStream_t st);
 void launch_b_set_boundary(const BatchEntry *t, const int *pre, int n, int total, hipStream_t st);
 void launch_b_exp_finite(const BatchEntry *t, const int *pre, int n, int total, hipStream_t st);
-void launch_b_small_cg(const BatchEntry *t, int n, BatchStatus *stat, hipStream_t st);
+void launch_b_small_cg(const BatchEntry *t, int n, int lds_nodes, BatchStatus *stat, hipStream_t st);
+int b_small_lds_nodes(const Grid &g);  // LDS (doubles) the small-grid CG of this grid uses, 0 if it does not fit
 void launch_b_boundary_terms(const BatchEntry *t, const int *pre, int n, int total, hipStream_t st);
 void launch_b_residual(const BatchEntry *t, const int *pre, int n, int total, BatchStatus *stat, hipStream_t st);
 void launch_b_residual_cast(const BatchEntry *t, const int *pre, int n, int total, int outer_step,

@@ -237,6 +237,7 @@ __device__ double fixed_sum(const double *a, int n, double *sh) {
 __device__ void state_init(CgState *cs, double rho, double bb, double tol, int max_iters, int hist_on) {
   cs->rho = rho;
   cs->rho_old = rho;
+  cs->rho0 = rho;
   cs->bnorm2 = bb;
   cs->stop2 = tol * tol * bb;
   cs->alpha = 0.0;
@@ -305,6 +306,7 @@ __device__ void state_ir(CgState *outer, CgState *inner, double r64, double bb, 
   }
   inner->rho = r32;
   inner->rho_old = r32;
+  inner->rho0 = r32;
   inner->bnorm2 = r32;
   const double theta = 0.5;
   inner->stop2 = fmax(eta * eta * r32, theta * theta * outer->stop2);
@@ -483,6 +485,7 @@ __global__ __launch_bounds__(NT) void cg_selfred_a_kernel(Sweep sw, const T *__r
     if (k == 0) {
       cs->bnorm2 = bb;
       cs->stop2 = stop2;
+      cs->rho0 = rho;
     }
     if (cs->hist_on && k < EXCMG_MAX_HISTORY) cs->hist[k] = bb > 0.0 ? sqrt(rho / bb) : 0.0;
     cs->rhoA[k & 1] = rho;
@@ -674,7 +677,7 @@ __device__ __forceinline__ void boundary_terms_block(const RhsSrc &rs, const Gri
     if (a >= g.nx || b >= g.ny) return;
     i = a; j = b; k = layer == 4 ? 1 : g.nz - 1;
   }
-  out[g.at(i, j, k)] = rhs_boundary_terms(rs, g.nx, g.ny, g.nz, i, j, k);
+  out[g.at(i, j, k)] = rhs_boundary_terms_inl(rs, g.nx, g.ny, g.nz, i, j, k);
 }
 
 __global__ __launch_bounds__(256) void boundary_terms_kernel(RhsSrc rs, Grid g, double *out) {
@@ -732,6 +735,12 @@ __global__ void tune_state_kernel(CgState *cs) {
   cs->status = 0;
   cs->max_iters = 1 << 30;
   cs->hist_on = 0;
+}
+
+// copy of a small device record (n 8-byte words) into host memory the device can write (the host reads it after a
+// stream synchronisation; no staged copy)
+__global__ void publish_kernel(const unsigned long long *src, unsigned long long *dst, int n) {
+  for (int q = threadIdx.x; q < n; q += blockDim.x) dst[q] = src[q];
 }
 
 __device__ __forceinline__ void add_correction_block(const Grid &gu, double *u, const Grid &g32, const float *d,
@@ -804,7 +813,7 @@ __device__ void small_cg_body(const Grid &gu, double *u, const RhsSrc &rs, const
   for (int m = threadIdx.x; m < n; m += DT) {
     int i, j, k;
     coords(m, i, j, k);
-    const double bv = rhs_at(rs, gu.nx, gu.ny, gu.nz, i, j, k);
+    const double bv = rhs_at<true>(rs, gu.nx, gu.ny, gu.nz, i, j, k);
     const double rv = bv - stencil_direct(gu, u, i, j, k, st);
     r[gw.at(i, j, k)] = rv;
     p[gw.at(i, j, k)] = rv;
@@ -874,10 +883,152 @@ __device__ void small_cg_body(const Grid &gu, double *u, const RhsSrc &rs, const
   }
 }
 
+// The same CG with the search direction p in LDS: the grid's node array (boundary nodes held at 0, which is the halo
+// of the stencil) and every thread's own unknowns (node m = threadIdx.x + q*DT, q < SK) with their u, r, p and M p in
+// registers.  An iteration is then one stencil evaluation from LDS and two workgroup reductions.
+constexpr int SK = 4;  // unknowns per thread: up to SK * DT = 4096 unknowns
+
+__host__ __device__ inline long long small_lds_nodes(const Grid &g) {
+  return (long long)(g.nx + 1) * (g.ny + 1) * (g.nz + 1);
+}
+constexpr long long kSmallLdsMax = 8192;  // nodes that fit the LDS path (64 KB)
+
+__device__ void small_cg_lds_body(const Grid &gu, double *u, const RhsSrc &rs, const Grid &gw, double *r,
+                                  const Stencil &st, CgState *cs, double tol, int cap, int exact, int hist_on,
+                                  double *P) {
+  __shared__ double sh[DT / 64];
+  const int nx1 = gu.nx - 1, ny1 = gu.ny - 1, nz1 = gu.nz - 1;
+  const int n = nx1 * ny1 * nz1;
+  const int sy = gu.nx + 1, sz = (gu.nx + 1) * (gu.ny + 1);
+  const int nodes = sz * (gu.nz + 1);
+  const double c0 = st.c0, cx = st.cx, cy = st.cy, cz = st.cz, cxy = st.cxy, cxz = st.cxz, cyz = st.cyz;
+  auto apply = [&](int c) {  // (M x)(node c) from LDS
+    const double *x = P + c;
+    double v = c0 * x[0];
+    v += cx * (x[1] + x[-1]);
+    v += cy * (x[sy] + x[-sy]);
+    v += cz * (x[sz] + x[-sz]);
+    v += cxy * ((x[1 + sy] + x[-1 + sy]) + (x[1 - sy] + x[-1 - sy]));
+    v += cxz * ((x[1 + sz] + x[-1 + sz]) + (x[1 - sz] + x[-1 - sz]));
+    v += cyz * ((x[sy + sz] + x[-sy + sz]) + (x[sy - sz] + x[-sy - sz]));
+    return v;
+  };
+  auto coords = [&](int m, int &i, int &j, int &k) {
+    i = 1 + m % nx1;
+    const int t = m / nx1;
+    j = 1 + t % ny1;
+    k = 1 + t / ny1;
+  };
+  // 1. r = b - M u into the global work array (b formed on the fly; nothing else is live across its calls)
+  double r2 = 0.0, b2 = 0.0;
+  for (int m = threadIdx.x; m < n; m += DT) {
+    int i, j, k;
+    coords(m, i, j, k);
+    const double bv = rhs_at<true>(rs, gu.nx, gu.ny, gu.nz, i, j, k);
+    const double rv = bv - stencil_direct(gu, u, i, j, k, st);
+    r[gw.at(i, j, k)] = rv;
+    r2 += rv * rv;
+    b2 += bv * bv;
+  }
+  double rho = dsum(r2, sh);  // its barriers also make r visible to the whole workgroup
+  const double bnorm2 = dsum(b2, sh);
+  const double rho_start = rho;
+  // 2. own unknowns into registers, p = r into LDS (boundary nodes 0)
+  for (int c = threadIdx.x; c < nodes; c += DT) P[c] = 0.0;
+  __syncthreads();
+  int li[SK];
+  double uu[SK], rr[SK], pp[SK], qq[SK];
+#pragma unroll
+  for (int q = 0; q < SK; ++q) {
+    const int m = threadIdx.x + q * DT;
+    li[q] = -1;
+    uu[q] = rr[q] = pp[q] = qq[q] = 0.0;
+    if (m < n) {
+      int i, j, k;
+      coords(m, i, j, k);
+      li[q] = i + j * sy + k * sz;
+      uu[q] = u[gu.at(i, j, k)];
+      rr[q] = r[gw.at(i, j, k)];
+      pp[q] = rr[q];
+      P[li[q]] = pp[q];
+    }
+  }
+  const double stop2 = (exact ? 1e-30 : tol * tol) * bnorm2;
+  if (hist_on && threadIdx.x == 0) cs->hist[0] = bnorm2 > 0.0 ? sqrt(rho / bnorm2) : 0.0;
+  int it = 0, status = 0;
+  if (!isfinite(rho) || !isfinite(bnorm2)) status = EXCMG_ERR_BREAKDOWN;
+  while (status == 0 && rho > stop2) {
+    if (it >= cap) {
+      if (!exact) status = EXCMG_ERR_NOCONV;
+      break;
+    }
+    __syncthreads();  // p complete in LDS
+    double pq = 0.0;
+#pragma unroll
+    for (int q = 0; q < SK; ++q) {
+      if (li[q] < 0) continue;
+      qq[q] = apply(li[q]);
+      pq += pp[q] * qq[q];
+    }
+    pq = dsum(pq, sh);  // its barriers order every read of p above before the writes of p below
+    if (!(pq > 0.0) || !isfinite(pq)) {
+      status = EXCMG_ERR_BREAKDOWN;
+      break;
+    }
+    const double alpha = rho / pq;
+    double rn = 0.0;
+#pragma unroll
+    for (int q = 0; q < SK; ++q) {
+      if (li[q] < 0) continue;
+      uu[q] += alpha * pp[q];
+      rr[q] -= alpha * qq[q];
+      rn += rr[q] * rr[q];
+    }
+    const double rho_new = dsum(rn, sh);
+    const double beta = rho_new / rho;
+    rho = rho_new;
+    ++it;
+    if (hist_on && threadIdx.x == 0 && it < EXCMG_MAX_HISTORY) cs->hist[it] = sqrt(rho / bnorm2);
+    if (!isfinite(rho)) {
+      status = EXCMG_ERR_BREAKDOWN;
+      break;
+    }
+#pragma unroll
+    for (int q = 0; q < SK; ++q) {
+      if (li[q] < 0) continue;
+      pp[q] = rr[q] + beta * pp[q];
+      P[li[q]] = pp[q];
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < SK; ++q) {
+    if (li[q] < 0) continue;
+    int i, j, k;
+    coords(threadIdx.x + q * DT, i, j, k);
+    u[gu.at(i, j, k)] = uu[q];
+  }
+  if (threadIdx.x == 0) {
+    cs->iter = it;
+    cs->rho = rho;
+    cs->rho0 = rho_start;
+    cs->bnorm2 = bnorm2;
+    cs->status = status;
+    cs->done = 1;
+  }
+}
+
+__host__ __device__ inline bool small_fits_lds(const Grid &g) {
+  return small_lds_nodes(g) <= kSmallLdsMax && g.interior() <= (long long)SK * DT;
+}
+
 __global__ __launch_bounds__(DT) void small_cg_kernel(Grid gu, double *u, RhsSrc rs, Grid gw, double *r, double *p,
                                                       double *q, Stencil st, CgState *cs, double tol, int cap,
                                                       int exact, int hist_on) {
-  small_cg_body(gu, u, rs, gw, r, p, q, st, cs, tol, cap, exact, hist_on);
+  extern __shared__ double lds_p[];
+  if (small_fits_lds(gu))
+    small_cg_lds_body(gu, u, rs, gw, r, st, cs, tol, cap, exact, hist_on, lds_p);
+  else
+    small_cg_body(gu, u, rs, gw, r, p, q, st, cs, tol, cap, exact, hist_on);
 }
 
 // ---------------------------------------------------------------------------------------------------- batched form
@@ -903,6 +1054,8 @@ __device__ void mirror(const BatchEntry &E, const CgState *cs, BatchStatus *stat
   m.status = cs->status;
   m.rho = cs->rho;
   m.bnorm2 = cs->bnorm2;
+  m.rho0 = cs->rho0;
+  m.stop2 = cs->stop2;
   if (final_state && E.finest && cs->done && stat[E.problem].t_done == 0)
     stat[E.problem].t_done = (long long)wall_clock64();
 }
@@ -916,7 +1069,9 @@ __global__ void b_init_kernel(BatchStatus *stat, int count, long long *t0) {
   if (q == 0) *t0 = (long long)wall_clock64();
 }
 
-__global__ __launch_bounds__(DT) void b_small_cg_kernel(const BatchEntry *t, BatchStatus *stat) {
+// lds_nodes: the dynamic LDS of the launch, in doubles (entries whose grid does not fit use the global-memory form)
+__global__ __launch_bounds__(DT) void b_small_cg_kernel(const BatchEntry *t, BatchStatus *stat, int lds_nodes) {
+  extern __shared__ double lds_p[];
   const BatchEntry &E = t[blockIdx.x];
   if (E.kind != kBSmall) return;
   int cap = E.cap;
@@ -925,7 +1080,10 @@ __global__ __launch_bounds__(DT) void b_small_cg_kernel(const BatchEntry *t, Bat
     cap = (int)(4 * n + 200);
     if (cap > 20000) cap = 20000;
   }
-  small_cg_body(E.g, E.u, E.rs, E.g, E.r, E.p0, E.p1, E.st, E.cs, E.tol, cap, E.exact, 0);
+  if (small_fits_lds(E.g) && small_lds_nodes(E.g) <= lds_nodes)
+    small_cg_lds_body(E.g, E.u, E.rs, E.g, E.r, E.st, E.cs, E.tol, cap, E.exact, 0, lds_p);
+  else
+    small_cg_body(E.g, E.u, E.rs, E.g, E.r, E.p0, E.p1, E.st, E.cs, E.tol, cap, E.exact, 0);
   if (threadIdx.x == 0) mirror(E, E.cs, stat, 0, true);
 }
 
@@ -1221,7 +1379,8 @@ void launch_small_cg(const Grid &gu, double *u, const RhsSrc &rs, const Grid &gw
     cap = (int)(4 * n + 200);
     if (cap > 20000) cap = 20000;
   }
-  small_cg_kernel<<<1, DT, 0, st>>>(gu, u, rs, gw, r, p, q, s, cs, tol, cap, exact, hist_on);
+  const size_t lds = small_fits_lds(gu) ? (size_t)small_lds_nodes(gu) * sizeof(double) : 0;
+  small_cg_kernel<<<1, DT, lds, st>>>(gu, u, rs, gw, r, p, q, s, cs, tol, cap, exact, hist_on);
 }
 
 void launch_apply(const Grid &gx, const double *x, const Grid &gy, double *y, const Stencil &s, hipStream_t st) {
@@ -1243,9 +1402,11 @@ void launch_b_init(BatchStatus *stat, int count, long long *t0, hipStream_t st) 
   b_init_kernel<<<(count + 255) / 256, 256, 0, st>>>(stat, count, t0);
 }
 
-void launch_b_small_cg(const BatchEntry *t, int n, BatchStatus *stat, hipStream_t st) {
-  b_small_cg_kernel<<<n, DT, 0, st>>>(t, stat);
+void launch_b_small_cg(const BatchEntry *t, int n, int lds_nodes, BatchStatus *stat, hipStream_t st) {
+  b_small_cg_kernel<<<n, DT, (size_t)lds_nodes * sizeof(double), st>>>(t, stat, lds_nodes);
 }
+
+int b_small_lds_nodes(const Grid &g) { return small_fits_lds(g) ? (int)small_lds_nodes(g) : 0; }
 
 void launch_b_boundary_terms(const BatchEntry *t, const int *pre, int n, int total, hipStream_t st) {
   if (total > 0) b_boundary_terms_kernel<<<total, 256, 0, st>>>(t, pre + kLBterm * (n + 1), n);
@@ -1286,6 +1447,10 @@ void launch_b_iteration(int fp32, const BatchEntry *t, const int *pre, int n, in
 
 void launch_b_add_correction(const BatchEntry *t, const int *pre, int n, int total, hipStream_t st) {
   if (total > 0) b_add_correction_kernel<<<total, 256, 0, st>>>(t, pre + kLCorr * (n + 1), n);
+}
+
+void launch_publish(const void *src, void *dst, size_t bytes, hipStream_t st) {
+  publish_kernel<<<1, 256, 0, st>>>((const unsigned long long *)src, (unsigned long long *)dst, (int)(bytes / 8));
 }
 
 }  // namespace excmg

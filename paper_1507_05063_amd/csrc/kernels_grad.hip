@@ -4,12 +4,7 @@
 //   v_0 = (-25 u_0 + 48 u_1 - 36 u_2 + 16 u_3 - 3 u_4) / (12 h),  v_N the mirror image with the opposite sign,
 //   v_{i-1} + 4 v_i + v_{i+1} = 3 (u_{i+1} - u_{i-1}) / h,  i = 1..N-1
 // (the paper's (1/6, 4/6, 1/6) system times 6).  The constant-coefficient Thomas factors m_1 = 4,
-// m_i = 4 - 1/m_{i-1} are shared by all lines; the host passes 1/m_i per axis.  Forward elimination stores the
-// modified right-hand sides in the output array, back substitution overwrites them with v.
-//
-// y and z lines: one thread per line, consecutive threads on consecutive x, so every step of the sweep is a
-// coalesced row access.  x lines: a workgroup of 256 threads takes 256 lines and walks x in chunks of 8 staged
-// through LDS (loads and stores run along x; each thread then sweeps its own row of the chunk).
+// m_i = 4 - 1/m_{i-1} are shared by all lines; the host passes 1/m_i per axis.
 #include "excmg_internal.h"
 
 namespace excmg {
@@ -20,7 +15,14 @@ __device__ __forceinline__ double end0(double u0, double u1, double u2, double u
   return (-25.0 * u0 + 48.0 * u1 - 36.0 * u2 + 16.0 * u3 - 3.0 * u4) / (12.0 * h);
 }
 
-// one line: u[idx0 + t*su], out[odx0 + t*so], t = 0..N
+// One line per thread: u[idx0 + t*su] and out[odx0 + t*so], t = 0..N.  The Thomas sweeps run chunk by chunk, GC
+// unknowns at a time, with the forward-eliminated values d of two chunks in registers: once the forward sweep has
+// finished chunk c+1, the back substitution starts at the top of chunk c+1 with v = d there (as if the unknown above
+// were 0) and runs down through chunk c, whose values are then final and stored.  The starting error is damped by
+// 1/m_t < 2 - sqrt(3) per step, so after the GC = 32 steps of chunk c+1 it is below 0.268^32 = 5e-19 of |v|: the
+// result is the exact Thomas solution to rounding, while u is read once and each output written once.
+constexpr int GC = 32;
+
 __device__ __forceinline__ void line_solve(const double *__restrict__ u, long long idx0, long long su, double *out,
                                            long long odx0, long long so, int N, double h,
                                            const double *__restrict__ inv_m) {
@@ -30,176 +32,178 @@ __device__ __forceinline__ void line_solve(const double *__restrict__ u, long lo
   out[odx0] = v0;
   out[odx0 + (long long)N * so] = vN;
   const double s3 = 3.0 / h;
-  double um = U(0), uc = U(1);
-  double dprev = 0.0;
-  constexpr int UN = 8;  // loads issued ahead of the dependent elimination chain
-  int t = 1;
-  for (; t + UN - 1 <= N - 1; t += UN) {
-    double up[UN];
+  const int M = N - 1;  // interior unknowns t = 1..M
+  double um = U(0), uc = U(1), dprev = 0.0;
+  // forward elimination of the chunk starting at t0 into d[]
+  auto forward = [&](double (&d)[GC], int t0) {
+    constexpr int G = 8;  // loads issued ahead of the dependent elimination chain
 #pragma unroll
-    for (int q = 0; q < UN; ++q) up[q] = U(t + q + 1);
+    for (int q0 = 0; q0 < GC; q0 += G) {
+      double up[G];
 #pragma unroll
-    for (int q = 0; q < UN; ++q) {
-      const int tt = t + q;
-      double rhs = s3 * (up[q] - um);
-      if (tt == 1) rhs -= v0;
-      if (tt == N - 1) rhs -= vN;
-      const double d = (rhs - dprev) * inv_m[tt];
-      out[odx0 + (long long)tt * so] = d;
-      dprev = d;
-      um = uc;
-      uc = up[q];
+      for (int q = 0; q < G; ++q) {
+        const int t = t0 + q0 + q;
+        up[q] = (t <= M) ? U(t + 1) : 0.0;
+      }
+#pragma unroll
+      for (int q = 0; q < G; ++q) {
+        const int t = t0 + q0 + q;
+        if (t <= M) {
+          double rhs = s3 * (up[q] - um);
+          if (t == 1) rhs -= v0;
+          if (t == M) rhs -= vN;
+          const double dd = (rhs - dprev) * inv_m[t];
+          d[q0 + q] = dd;
+          dprev = dd;
+          um = uc;
+          uc = up[q];
+        }
+      }
     }
-  }
-  for (; t <= N - 1; ++t) {
-    const double up = U(t + 1);
-    double rhs = s3 * (up - um);
-    if (t == 1) rhs -= v0;
-    if (t == N - 1) rhs -= vN;
-    const double d = (rhs - dprev) * inv_m[t];
-    out[odx0 + (long long)t * so] = d;
-    dprev = d;
-    um = uc;
-    uc = up;
-  }
-  double vnext = out[odx0 + (long long)(N - 1) * so];
-  int tb = N - 2;
-  for (; tb - UN + 1 >= 1; tb -= UN) {
-    double dd[UN];
+  };
+  double dA[GC], dB[GC];
+  forward(dA, 1);
+  for (int t0 = 1; t0 <= M; t0 += GC) {
+    const int t1 = t0 + GC;  // first unknown of the next chunk
+    double v = 0.0;          // v_{t+1} during the back substitution
+    if (t1 <= M) {
+      forward(dB, t1);
 #pragma unroll
-    for (int q = 0; q < UN; ++q) dd[q] = out[odx0 + (long long)(tb - q) * so];
-#pragma unroll
-    for (int q = 0; q < UN; ++q) {
-      const double v = dd[q] - inv_m[tb - q] * vnext;
-      out[odx0 + (long long)(tb - q) * so] = v;
-      vnext = v;
+      for (int q = GC - 1; q >= 0; --q) {
+        const int t = t1 + q;
+        if (t <= M) v = (t == M) ? dB[q] : dB[q] - inv_m[t] * v;
+      }
     }
-  }
-  for (; tb >= 1; --tb) {
-    const double v = out[odx0 + (long long)tb * so] - inv_m[tb] * vnext;
-    out[odx0 + (long long)tb * so] = v;
-    vnext = v;
+#pragma unroll
+    for (int q = GC - 1; q >= 0; --q) {
+      const int t = t0 + q;
+      if (t <= M) {
+        v = (t == M) ? dA[q] : dA[q] - inv_m[t] * v;
+        out[odx0 + (long long)t * so] = v;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < GC; ++q) dA[q] = dB[q];
   }
 }
 
-__global__ void grad_y_kernel(Grid gu, const double *__restrict__ u, Grid gd, double *uy, double hy,
-                              const double *__restrict__ inv_m) {
+// x lines: one thread per line, 64 lines per workgroup.  The rows are contiguous in memory, so the chunk of GC values
+// every line needs next is staged through an LDS tile with coalesced loads (each 32-value row segment read by 32
+// consecutive threads), and the finished chunk goes back out through the same tile with coalesced stores.  The
+// Thomas sweeps are those of line_solve, with u taken from the tile.
+constexpr int XW = 64;
+
+__global__ __launch_bounds__(XW) void grad_x_kernel(Grid gu, const double *__restrict__ u, Grid gd, double *ux,
+                                                    double hx, const double *__restrict__ inv_m) {
+  __shared__ double tile[XW][GC + 1];
+  __shared__ long long rb[XW], ob[XW];  // row starts of the workgroup's lines in u and in ux
+  const int nlines = (gu.ny + 1) * (gu.nz + 1);
+  const int L0 = blockIdx.x * XW;
+  const int tid = threadIdx.x;
+  const int nl = min(XW, nlines - L0);
+  const int N = gu.nx, M = N - 1;
+  {
+    const int L = L0 + (tid < nl ? tid : 0);
+    const int j = L % (gu.ny + 1), k = L / (gu.ny + 1);
+    rb[tid] = gu.at(0, j, k);
+    ob[tid] = gd.at(0, j, k);
+  }
+  __syncthreads();
+  const bool act = tid < nl;
+  const long long b = rb[tid];
+  double v0 = 0.0, vN = 0.0, um = 0.0, uc = 0.0;
+  if (act) {
+    v0 = end0(u[b], u[b + 1], u[b + 2], u[b + 3], u[b + 4], hx);
+    vN = -end0(u[b + N], u[b + N - 1], u[b + N - 2], u[b + N - 3], u[b + N - 4], hx);
+    ux[ob[tid]] = v0;
+    ux[ob[tid] + N] = vN;
+    um = u[b];
+    uc = u[b + 1];
+  }
+  const double s3 = 3.0 / hx;
+  double dprev = 0.0;
+  // tile <- u at x = t0+1 .. t0+GC of every line (the values the forward sweep over t0 .. t0+GC-1 needs)
+  auto load = [&](int t0) {
+#pragma unroll 8
+    for (int m = 0; m < GC; ++m) {
+      const int e = tid + m * XW;
+      const int ln = e / GC, xx = e % GC, x = t0 + 1 + xx;
+      tile[ln][xx] = (ln < nl && x <= N) ? u[rb[ln] + x] : 0.0;
+    }
+  };
+  auto forward = [&](double (&d)[GC], int t0) {
+#pragma unroll
+    for (int q = 0; q < GC; ++q) {
+      const int t = t0 + q;
+      if (t <= M) {
+        const double up = tile[tid][q];
+        double rhs = s3 * (up - um);
+        if (t == 1) rhs -= v0;
+        if (t == M) rhs -= vN;
+        const double dd = (rhs - dprev) * inv_m[t];
+        d[q] = dd;
+        dprev = dd;
+        um = uc;
+        uc = up;
+      }
+    }
+  };
+  double dA[GC], dB[GC];
+  load(1);
+  __syncthreads();
+  forward(dA, 1);
+  __syncthreads();
+  for (int t0 = 1; t0 <= M; t0 += GC) {
+    const int t1 = t0 + GC;
+    double v = 0.0;
+    if (t1 <= M) {
+      load(t1);
+      __syncthreads();
+      forward(dB, t1);
+      __syncthreads();  // every line has consumed the tile
+#pragma unroll
+      for (int q = GC - 1; q >= 0; --q) {
+        const int t = t1 + q;
+        if (t <= M) v = (t == M) ? dB[q] : dB[q] - inv_m[t] * v;
+      }
+    }
+#pragma unroll
+    for (int q = GC - 1; q >= 0; --q) {
+      const int t = t0 + q;
+      if (t <= M) {
+        v = (t == M) ? dA[q] : dA[q] - inv_m[t] * v;
+        tile[tid][q] = v;
+      }
+    }
+    __syncthreads();
+#pragma unroll 8
+    for (int m = 0; m < GC; ++m) {
+      const int e = tid + m * XW;
+      const int ln = e / GC, xx = e % GC, t = t0 + xx;
+      if (ln < nl && t <= M) ux[ob[ln] + t] = tile[ln][xx];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < GC; ++q) dA[q] = dB[q];
+  }
+}
+
+// y and z lines: one thread per line, consecutive threads on consecutive x, so every step of the sweeps is a
+// coalesced row access.
+__global__ __launch_bounds__(64) void grad_y_kernel(Grid gu, const double *__restrict__ u, Grid gd, double *uy,
+                                                    double hy, const double *__restrict__ inv_m) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int k = blockIdx.y;
   if (i > gu.nx) return;
   line_solve(u, gu.at(i, 0, k), gu.sy, uy, gd.at(i, 0, k), gd.sy, gu.ny, hy, inv_m);
 }
 
-__global__ void grad_z_kernel(Grid gu, const double *__restrict__ u, Grid gd, double *uz, double hz,
-                              const double *__restrict__ inv_m) {
+__global__ __launch_bounds__(64) void grad_z_kernel(Grid gu, const double *__restrict__ u, Grid gd, double *uz,
+                                                    double hz, const double *__restrict__ inv_m) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int j = blockIdx.y;
   if (i > gu.nx) return;
   line_solve(u, gu.at(i, j, 0), gu.sz, uz, gd.at(i, j, 0), gd.sz, gu.nz, hz, inv_m);
-}
-
-constexpr int XL = 256;     // x lines per workgroup (one thread per line)
-constexpr int XC = 8;       // chunk length along x
-constexpr int XP = XC + 3;  // LDS row pitch of the u tile (odd in 8-byte words: no bank conflicts on row sweeps)
-constexpr int XQ = XC + 1;  // LDS row pitch of the output tile
-
-__global__ __launch_bounds__(XL) void grad_x_kernel(Grid gu, const double *__restrict__ u, Grid gd, double *ux,
-                                                    double hx, const double *__restrict__ inv_m) {
-  __shared__ double tu[XL][XP];
-  __shared__ double to[XL][XQ];
-  __shared__ long long ub[XL], ob[XL];  // row start of each line in u and in ux
-  const int nlines = (gu.ny + 1) * (gu.nz + 1);
-  const int L0 = blockIdx.x * XL;
-  const int t = threadIdx.x;
-  const int N = gu.nx;
-  const int nl = min(XL, nlines - L0);  // lines in this workgroup
-  const bool act = t < nl;
-  {
-    const int L = L0 + (act ? t : 0);
-    const int j = L % (gu.ny + 1), k = L / (gu.ny + 1);
-    ub[t] = gu.at(0, j, k);
-    ob[t] = gd.at(0, j, k);
-  }
-  double v0 = 0.0, vN = 0.0;
-  if (act) {
-    const long long b = ub[t];
-    v0 = end0(u[b], u[b + 1], u[b + 2], u[b + 3], u[b + 4], hx);
-    vN = -end0(u[b + N], u[b + N - 1], u[b + N - 2], u[b + N - 3], u[b + N - 4], hx);
-    ux[ob[t]] = v0;
-    ux[ob[t] + N] = vN;
-  }
-  __syncthreads();
-  const double s3 = 3.0 / hx;
-  double dprev = 0.0;
-  // forward elimination, chunk by chunk over the interior x = 1..N-1; the next chunk's u is loaded into registers
-  // while the current chunk is swept
-  constexpr int PER = (XL * (XC + 2) + XL - 1) / XL;  // staged values per thread and chunk
-  double nxt[PER];
-  auto load_chunk = [&](int x0) {
-#pragma unroll
-    for (int m = 0; m < PER; ++m) {
-      const int e = t + m * XL;
-      const int ln = e / (XC + 2), xx = e % (XC + 2);
-      double v = 0.0;
-      if (e < XL * (XC + 2) && ln < nl && x0 - 1 + xx <= N) v = u[ub[ln] + x0 - 1 + xx];
-      nxt[m] = v;
-    }
-  };
-  load_chunk(1);
-  for (int x0 = 1; x0 <= N - 1; x0 += XC) {
-    const int wn = min(XC, N - x0);  // interior values in this chunk
-#pragma unroll
-    for (int m = 0; m < PER; ++m) {
-      const int e = t + m * XL;
-      if (e < XL * (XC + 2)) tu[e / (XC + 2)][e % (XC + 2)] = nxt[m];
-    }
-    __syncthreads();
-    if (x0 + XC <= N - 1) load_chunk(x0 + XC);
-    if (act) {
-      for (int q = 0; q < wn; ++q) {
-        const int x = x0 + q;
-        double rhs = s3 * (tu[t][q + 2] - tu[t][q]);
-        if (x == 1) rhs -= v0;
-        if (x == N - 1) rhs -= vN;
-        const double d = (rhs - dprev) * inv_m[x];
-        to[t][q] = d;
-        dprev = d;
-      }
-    }
-    __syncthreads();
-    for (int e = t; e < XL * XC; e += XL) {
-      const int ln = e / XC, xx = e % XC;
-      if (ln < nl && xx < wn) ux[ob[ln] + x0 + xx] = to[ln][xx];
-    }
-    __syncthreads();
-  }
-  // back substitution over the same chunks in reverse order
-  const int nchunks = (N - 1 + XC - 1) / XC;
-  double vnext = 0.0;
-  for (int c = nchunks - 1; c >= 0; --c) {
-    const int x0 = 1 + c * XC;
-    const int wn = min(XC, N - x0);
-    for (int e = t; e < XL * XC; e += XL) {
-      const int ln = e / XC, xx = e % XC;
-      to[ln][xx] = (ln < nl && xx < wn) ? ux[ob[ln] + x0 + xx] : 0.0;
-    }
-    __syncthreads();
-    if (act) {
-      for (int q = wn - 1; q >= 0; --q) {
-        const int x = x0 + q;
-        const double d = to[t][q];
-        const double v = (x == N - 1) ? d : d - inv_m[x] * vnext;
-        to[t][q] = v;
-        vnext = v;
-      }
-    }
-    __syncthreads();
-    for (int e = t; e < XL * XC; e += XL) {
-      const int ln = e / XC, xx = e % XC;
-      if (ln < nl && xx < wn) ux[ob[ln] + x0 + xx] = to[ln][xx];
-    }
-    __syncthreads();
-  }
 }
 
 }  // namespace
@@ -208,7 +212,7 @@ void launch_gradient(const Grid &gu, const double *u, const Grid &gd, double *ux
                      double hy, double hz, const double *inv_m_x, const double *inv_m_y, const double *inv_m_z,
                      hipStream_t st) {
   const int nlines = (gu.ny + 1) * (gu.nz + 1);
-  grad_x_kernel<<<(nlines + XL - 1) / XL, XL, 0, st>>>(gu, u, gd, ux, hx, inv_m_x);
+  grad_x_kernel<<<(nlines + XW - 1) / XW, XW, 0, st>>>(gu, u, gd, ux, hx, inv_m_x);
   grad_y_kernel<<<dim3((gu.nx + 1 + 63) / 64, gu.nz + 1), 64, 0, st>>>(gu, u, gd, uy, hy, inv_m_y);
   grad_z_kernel<<<dim3((gu.nx + 1 + 63) / 64, gu.ny + 1), 64, 0, st>>>(gu, u, gd, uz, hz, inv_m_z);
 }

@@ -91,9 +91,8 @@ __device__ __forceinline__ double quartic(int t, double a0, double a1, double a2
 //     (zhongdian), at face and element centres the mean over the 2 face / 4 space diagonals of eq. (zhongdian): all
 //     four rules are the same tri-linear interpolation of delta with the factor 1/16;
 //  3. tri-quartic interpolation (eq. inter) applied separably, x then y then z (the 604x125 cell matrix is the
-//     tensor product of the 1D quartic weights): the x pass through LDS, then one thread per (x, z-layer) column
-//     for the y pass and one thread per (x, y) column for the z pass, each holding its five known values in
-//     registers and producing its nine outputs;
+//     tensor product of the 1D quartic weights): the x pass through LDS, then one thread per (x, y) column that
+//     interpolates its five z layers in y from the x-pass values and then produces its nine z outputs;
 //  4. boundary nodes get g.
 __device__ void exp_finite_block(const Grid &g2, const double *__restrict__ u2, const Grid &g4,
                                  const double *__restrict__ u4, const Grid &gg, const double *__restrict__ gdat, int s,
@@ -101,7 +100,6 @@ __device__ void exp_finite_block(const Grid &g2, const double *__restrict__ u2, 
   __shared__ double W[5][5][EX2];
   __shared__ double D[3][3][EX4];
   __shared__ double Wx[5][5][EXF];
-  __shared__ double Wxy[5][9][EXF];
   const int ncx = gw.nx / 8, ncy = gw.ny / 8, ncz = gw.nz / 8;
   const int cx0 = bx * CXN;
   const int nc = min(CXN, ncx - cx0);  // cells in this workgroup (fewer in the last one along x)
@@ -145,22 +143,6 @@ __device__ void exp_finite_block(const Grid &g2, const double *__restrict__ u2, 
     Wx[c][b][xf] = v;
   }
   __syncthreads();
-  // 3b. y: one thread per (xf, c) column
-  for (int e = tid; e < 5 * EXF; e += ET) {
-    const int xf = e % EXF, c = e / EXF;
-    if (xf >= nfx) continue;
-    const double a0 = Wx[c][0][xf], a1 = Wx[c][1][xf], a2 = Wx[c][2][xf], a3 = Wx[c][3][xf], a4 = Wx[c][4][xf];
-    Wxy[c][0][xf] = a0;
-    Wxy[c][1][xf] = quartic(0, a0, a1, a2, a3, a4);
-    Wxy[c][2][xf] = a1;
-    Wxy[c][3][xf] = quartic(1, a0, a1, a2, a3, a4);
-    Wxy[c][4][xf] = a2;
-    Wxy[c][5][xf] = quartic(2, a0, a1, a2, a3, a4);
-    Wxy[c][6][xf] = a3;
-    Wxy[c][7][xf] = quartic(3, a0, a1, a2, a3, a4);
-    Wxy[c][8][xf] = a4;
-  }
-  __syncthreads();
   // 3c. z and 4. write, one thread per (xf, yf) column: a workgroup owns offsets [0,8) on each axis, plus offset 8 at
   // the grid's far faces
   const bool lastx = (cx0 + nc == ncx), lasty = (cj == ncy - 1), lastz = (ck == ncz - 1);
@@ -170,8 +152,13 @@ __device__ void exp_finite_block(const Grid &g2, const double *__restrict__ u2, 
     const int xf = e % EXF, yf = e / EXF;
     if (xf >= ox || yf >= oy) continue;
     const int gi = gi0 + xf, gj = gj0 + yf;
-    const double a0 = Wxy[0][yf][xf], a1 = Wxy[1][yf][xf], a2 = Wxy[2][yf][xf], a3 = Wxy[3][yf][xf],
-                 a4 = Wxy[4][yf][xf];
+    // y: the five z layers of this column, from the x-interpolated values (known at even yf, quartic at odd yf)
+    double a[5];
+#pragma unroll
+    for (int c = 0; c < 5; ++c)
+      a[c] = (yf & 1) ? quartic(yf >> 1, Wx[c][0][xf], Wx[c][1][xf], Wx[c][2][xf], Wx[c][3][xf], Wx[c][4][xf])
+                      : Wx[c][yf >> 1][xf];
+    const double a0 = a[0], a1 = a[1], a2 = a[2], a3 = a[3], a4 = a[4];
     const bool side = (gi == 0 || gj == 0 || gi == gw.nx || gj == gw.ny);
     for (int zf = 0; zf < oz; ++zf) {
       const int gk = gk0 + zf;
@@ -204,9 +191,11 @@ __global__ __launch_bounds__(ET) void exp_finite_kernel(Grid g2, const double *_
 constexpr int TTX = 64, TTY = 4, TTZ = 8;
 constexpr int DTX = TTX / 2 + 1, DTY = TTY / 2 + 1, DTZ = TTZ / 2 + 1;
 
+// ucopy (nullable): u_h itself is also written there, in the layout gt (the solution's copy to the caller's array,
+// made from the same read of u_h).
 __global__ __launch_bounds__(TTX *TTY) void exp_true_kernel(Grid gh, const double *__restrict__ uh, Grid g2,
                                                            const double *__restrict__ u2, Grid gt,
-                                                           double *__restrict__ ut) {
+                                                           double *__restrict__ ut, double *__restrict__ ucopy) {
   __shared__ double D[DTZ][DTY][DTX];
   const int x0 = blockIdx.x * TTX, y0 = blockIdx.y * TTY, z0 = blockIdx.z * TTZ;
   const int tid = threadIdx.x;
@@ -228,7 +217,9 @@ __global__ __launch_bounds__(TTX *TTY) void exp_true_kernel(Grid gh, const doubl
     const int cl = q >> 1, ch = (q + 1) >> 1;
     const double d = ((D[cl][bl][al] + D[cl][bl][ah]) + (D[cl][bh][al] + D[cl][bh][ah])) +
                      ((D[ch][bl][al] + D[ch][bl][ah]) + (D[ch][bh][al] + D[ch][bh][ah]));
-    ut[gt.at(i, j, k)] = uh[gh.at(i, j, k)] + d * (1.0 / 120.0);  // (1/15) * (1/8) * sum over the 8 corner slots
+    const double v = uh[gh.at(i, j, k)];
+    ut[gt.at(i, j, k)] = v + d * (1.0 / 120.0);  // (1/15) * (1/8) * sum over the 8 corner slots
+    if (ucopy) ucopy[gt.at(i, j, k)] = v;
   }
 }
 
@@ -328,9 +319,9 @@ void launch_exp_finite(const Grid &g2, const double *u2, const Grid &g4, const d
 }
 
 void launch_exp_true(const Grid &gh, const double *uh, const Grid &g2, const double *u2, const Grid &gt, double *ut,
-                     hipStream_t st) {
+                     double *ucopy, hipStream_t st) {
   dim3 grid((gh.nx + 1 + TTX - 1) / TTX, (gh.ny + 1 + TTY - 1) / TTY, (gh.nz + 1 + TTZ - 1) / TTZ);
-  exp_true_kernel<<<grid, TTX * TTY, 0, st>>>(gh, uh, g2, u2, gt, ut);
+  exp_true_kernel<<<grid, TTX * TTY, 0, st>>>(gh, uh, g2, u2, gt, ut, ucopy);
 }
 
 void launch_copy(const Grid &gs, const double *src, const Grid &gd, double *dst, hipStream_t st) {

@@ -198,6 +198,30 @@ def test_determinism(ex):
     assert np.array_equal(a, host(b))
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32_ir"])
+def test_graph_replays_match_direct_launches(ex, precision):
+    """The coarser grids replay captured graphs of CG iterations; the same solve with every launch made directly must
+    agree bit for bit, on every one of several replays with other device work in between."""
+    p = synth.smooth(1, (1.0, 0.7, 1.3))
+    n = (128, 128, 128)  # IR on the 128^3 grid (>= 2^20 unknowns) is below the finest only on a 256^3 problem,
+    if precision == "fp32_ir":  # so the FP32 case runs that size
+        n = (256, 256, 256)
+    prec = ex.FP64 if precision == "fp64" else ex.FP32_IR
+    f, g, _ = synth.sample(p, n)
+    fd, gd = dev(f), dev(g)
+    eager = ex.Solver(n, p.box, 1e-10, precision=prec, graphs=False)
+    ref, _, st_ref = eager.solve(fd, gd)
+    ref = ref.clone()
+    s = ex.Solver(n, p.box, 1e-10, precision=prec)
+    x = dev(rnd((16, 16, 16)))
+    for rep in range(3):
+        u, _, st = s.solve(fd, gd)
+        assert st["iters"] == st_ref["iters"], (rep, st["iters"], st_ref["iters"])
+        assert torch.equal(u, ref), rep
+        ex.op_apply(x, (16, 16, 16))  # unrelated eager work between the replays
+        torch.cuda.synchronize()
+
+
 def test_nonfinite_and_noconv(ex):
     p = synth.smooth(0)
     n = (32, 32, 32)
