@@ -261,8 +261,9 @@ def main():
     copy_gbs, read_gbs = ex.bandwidth_probe(PROBE_BYTES)
     print(f"# streaming probe: copy {copy_gbs:.0f} GB/s, read {read_gbs:.0f} GB/s", file=sys.stderr, flush=True)
     s = ex.Solver(n, p.box, args.tol, timing=True)
-    zc64 = s.autotune()
-    print(f"# autotuned z chunks (A, B) per grid: {[z[:2] for z in zc64]}", file=sys.stderr, flush=True)
+    zc64, dp64 = s.autotune(with_depth=True)
+    print(f"# autotuned z chunks (A, B) per grid: {[z[:2] for z in zc64]}, depths {[d[:2] for d in dp64]}",
+          file=sys.stderr, flush=True)
     u = s.empty()
     ue = s.empty()
     grads = (s.empty(), s.empty(), s.empty())
@@ -333,6 +334,7 @@ def main():
                      "frac_of_probe_copy": round(achieved / copy_gbs, 4)},
         "iters_per_grid": stats[-1]["iters"],
         "autotuned_z_chunks": [list(z[:2]) for z in zc64],
+        "autotuned_depths": [list(d[:2]) for d in dp64],
         "ms_per_grid": [round(v, 3) for v in stats[-1]["ms_level"]],
         "solve_ms_fp64": round(stats[-1]["ms_total"], 3),
         "finest_cg_sweeps_gunknown_iters_s": round(guis_fin_sweeps, 2) if guis_fin_sweeps else None,

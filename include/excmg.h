@@ -65,7 +65,7 @@ extern "C" {
 #define EXCMG_K_RHS 6       /* right-hand side assembly (excmg_op_rhs; the solver forms b inside its kernels) */
 #define EXCMG_K_EXP_FINITE 7
 #define EXCMG_K_EXP_TRUE 8
-#define EXCMG_K_DSOLVE 9     /* single-workgroup CG: direct solves, and the relaxation of grids <= 8000 unknowns */
+#define EXCMG_K_DSOLVE 9     /* single-workgroup kernels: the direct solves, and the CG of grids <= 8000 unknowns */
 #define EXCMG_K_GRADIENT 10
 #define EXCMG_K_OTHER 11
 #define EXCMG_K_CLASSES 12
@@ -93,7 +93,9 @@ typedef struct {
   int32_t iters[EXCMG_MAX_LEVELS];           /* CG iterations per grid (FP32_IR: inner iterations summed);
                                                 0 on the two directly solved grids */
   int32_t ir_outer[EXCMG_MAX_LEVELS];        /* FP32_IR: outer refinement steps per grid */
-  int32_t dsolve_iters[2];                   /* iterations the direct solver took on the two coarsest grids */
+  int32_t dsolve_iters[2];                   /* the two coarsest grids are solved exactly: by sine transforms
+                                                (0 here) up to 64 cells per axis, else by CG to a relative
+                                                residual of 1e-15 (its iteration count here) */
   double relres[EXCMG_MAX_LEVELS];           /* relative residual at exit per grid (FP64: recursive CG residual;
                                                 FP32_IR: the FP64 outer residual) */
   double ms_level[EXCMG_MAX_LEVELS];         /* wall time of each grid's work (transfer + relaxation), ms */
@@ -161,11 +163,12 @@ int excmg_solve_batched(excmg_handle *const *hs, int32_t count, const double *co
 
 /* Autotuner (host call, device work on the handle's stream): times the two CG sweep kernels of every relaxed grid
  * (FP64, and FP32 where EXCMG_FP32_IR relaxes in FP32) for each z-chunk length in {2, 4, ..., 64} planes per
- * workgroup, on the handle's own work buffers (no caller array is read or written), and keeps the fastest chunk per
- * grid and kernel for every later call on this handle.  zc_out (host, nullable, 4 * levels entries): per grid, the
- * chunk of pass A and pass B in FP64, then in FP32 (0 where the grid is not relaxed that way).  Optional: without it
- * the handle uses a fixed default (16 planes, fewer on small grids). */
-int excmg_autotune(excmg_handle *h, int32_t *zc_out);
+ * workgroup and each prefetch depth (2 or 3 planes of loads in flight per thread), on the handle's own work buffers
+ * (no caller array is read or written), and keeps the fastest shape per grid and kernel for every later call on this
+ * handle.  zc_out, depth_out (host, nullable, 4 * levels entries each): per grid, the chunk and depth of pass A and
+ * pass B in FP64, then in FP32 (0 where the grid is not relaxed that way).  Optional: without it the handle uses a
+ * fixed default (16 planes, fewer on small grids; depth 2). */
+int excmg_autotune(excmg_handle *h, int32_t *zc_out, int32_t *depth_out);
 
 void excmg_destroy(excmg_handle *h);
 const char *excmg_strerror(int code);

@@ -138,12 +138,17 @@ class Solver:
         _lib.check(code, "excmg_adjoint")
         return dLdf, dLdg, lam, st.to_dict()
 
-    def autotune(self):
+    def autotune(self, with_depth: bool = False):
         """Time the CG sweep variants of every relaxed grid and keep the fastest.  Returns, per grid, the z chunk of
-        (pass A, pass B) in FP64 and in FP32 (0 where unused)."""
+        (pass A, pass B) in FP64 and in FP32 (0 where unused); with_depth: also the prefetch depths, as a second
+        list of the same form."""
         zc = (ctypes.c_int32 * (4 * self.levels))()
-        _lib.check(_lib.lib().excmg_autotune(self._h, zc), "excmg_autotune")
-        return [tuple(zc[4 * l: 4 * l + 4]) for l in range(self.levels)]
+        dp = (ctypes.c_int32 * (4 * self.levels))()
+        _lib.check(_lib.lib().excmg_autotune(self._h, zc, dp), "excmg_autotune")
+        z = [tuple(zc[4 * l: 4 * l + 4]) for l in range(self.levels)]
+        if with_depth:
+            return z, [tuple(dp[4 * l: 4 * l + 4]) for l in range(self.levels)]
+        return z
 
     def close(self):
         if self._h:

@@ -1117,7 +1117,7 @@ int excmg_adjoint(excmg_handle *h, const double *G, double *dLdf, double *dLdg, 
   return status;
 }
 
-int excmg_autotune(excmg_handle *h, int32_t *zc_out) {
+int excmg_autotune(excmg_handle *h, int32_t *zc_out, int32_t *depth_out) {
   if (!h) return EXCMG_ERR_ARG;
   DeviceGuard dg(h->device);
   h->drop_graphs();  // captured with the old sweep shapes
@@ -1137,9 +1137,10 @@ int excmg_autotune(excmg_handle *h, int32_t *zc_out) {
       for (int pass = 0; pass < 2 && rc == EXCMG_OK; ++pass) {
         float best = 1e30f;
         Sweep bsw = prec ? (pass ? lv.swB32 : lv.swA32) : (pass ? lv.swB : lv.swA);
-        for (int zc : cand) {
+        for (int ci = 0; ci < 2 * (int)(sizeof(cand) / sizeof(cand[0])); ++ci) {
+          const int zc = cand[ci / 2], depth = 2 + ci % 2;
           if (zc > 2 * (g.nz - 1) + 2) break;
-          const Sweep sw = make_sweep(g, lv.st, zc);
+          const Sweep sw = make_sweep(g, lv.st, zc, depth);
           if (3LL * sweep_blocks(sw) > lo.npart) continue;
           float tmin = 1e30f;
           for (int rep = 0; rep < 4; ++rep) {
@@ -1182,6 +1183,17 @@ int excmg_autotune(excmg_handle *h, int32_t *zc_out) {
       zc_out[4 * l + 1] = relaxed ? lv.swB.zc : 0;
       zc_out[4 * l + 2] = ir ? lv.swA32.zc : 0;
       zc_out[4 * l + 3] = ir ? lv.swB32.zc : 0;
+    }
+  }
+  if (depth_out) {
+    for (int l = 0; l < lo.L; ++l) {
+      const Level &lv = lo.lev[l];
+      const bool relaxed = l >= 2 && lv.g.interior() > kSmallCg;
+      const bool ir = relaxed && (h->p.precision == EXCMG_FP32_IR) && lv.g.interior() >= kIrMinUnknowns;
+      depth_out[4 * l + 0] = relaxed ? lv.swA.depth : 0;
+      depth_out[4 * l + 1] = relaxed ? lv.swB.depth : 0;
+      depth_out[4 * l + 2] = ir ? lv.swA32.depth : 0;
+      depth_out[4 * l + 3] = ir ? lv.swB32.depth : 0;
     }
   }
   return EXCMG_OK;

@@ -78,10 +78,12 @@ constexpr int NT = TX * TY;
 // bid, nb: this workgroup's index among the nb workgroups of the sweep (the grid of a single-problem launch, or one
 // problem's range of a batched launch); remap: number the tiles XCD by XCD (single-problem launches only, where the
 // hardware's round-robin dispatch over the XCDs follows bid).
-template <typename T, typename P>
+template <typename T, int D = 2, typename P>
 __device__ __forceinline__ void zmarch(const Sweep &sw, P &pol, double &acc0, double &acc1, T (*tile)[TY + 2][TX + 2],
                                        double (*tileF)[TY + 2][TX + 2], int bid, int nb, bool remap) {
+  static_assert(D == 2 || D == 3, "prefetch depth");
   constexpr int W = TX + 2, H = TY + 2, E = W * H, NL = (E + NT - 1) / NT;
+  constexpr int U = D == 2 ? 2 : 6;  // steps per unrolled round: a multiple of both 2 (LDS buffers) and D
   constexpr bool R = P::kRhs;
   const Grid &g = sw.g;
   const int t = remap ? xcd_remap(bid, nb) : bid;
@@ -110,12 +112,12 @@ __device__ __forceinline__ void zmarch(const Sweep &sw, P &pol, double &acc0, do
     }
   }
   const long long fstride = R ? pol.fplane() : 0;
-  T regA[NL], regB[NL];
-  double fA[NL], fB[NL];
-  auto fetch = [&](T(&reg)[NL], double(&fr)[NL], int kk) {
+  T reg[D][NL];
+  double fre[D][NL];
+  auto fetch = [&](T(&rg)[NL], double(&fr)[NL], int kk) {
     const bool kin = (kk >= 1) && (kk < g.nz);
 #pragma unroll
-    for (int m = 0; m < NL; ++m) reg[m] = (kin && col[m] >= 0) ? pol.operand(col[m] + (long long)kk * g.sz) : T(0);
+    for (int m = 0; m < NL; ++m) rg[m] = (kin && col[m] >= 0) ? pol.operand(col[m] + (long long)kk * g.sz) : T(0);
     if constexpr (R) {
 #pragma unroll
       for (int m = 0; m < NL; ++m) fr[m] = (colF[m] >= 0) ? pol.fval(colF[m] + (long long)kk * fstride) : 0.0;
@@ -130,35 +132,37 @@ __device__ __forceinline__ void zmarch(const Sweep &sw, P &pol, double &acc0, do
   const long long own = g.off + (long long)j * g.sy + i;
   const int np = k1 - k0 + 2;  // planes k0-1 .. k1
 
-  fetch(regA, fA, k0 - 1);
-  fetch(regB, fB, k0);
+  // Step s (plane kk = k0-1+s) takes the operand from register set s%D, stages it in LDS buffer s%2, refills the set
+  // with plane kk+D, and (s >= 2) produces output plane kk-1 from the centre data in slot s%D, which it then refills
+  // for output plane kk-1+D.
+#pragma unroll
+  for (int d = 0; d < D; ++d) fetch(reg[d], fre[d], k0 - 1 + d);
   if (active) {
-    pol.template center<1>(i, j, k0, own + (long long)k0 * g.sz);
-    if (k0 + 1 < k1) pol.template center<0>(i, j, k0 + 1, own + (long long)(k0 + 1) * g.sz);
+    if (k0 < k1) pol.template center<2 % D>(i, j, k0, own + (long long)k0 * g.sz);
+    if (k0 + 1 < k1) pol.template center<3 % D>(i, j, k0 + 1, own + (long long)(k0 + 1) * g.sz);
+    if (D == 3 && k0 + 2 < k1) pol.template center<4 % D>(i, j, k0 + 2, own + (long long)(k0 + 2) * g.sz);
   }
 
-  auto body = [&](auto parity, int step) {
-    constexpr int PB = decltype(parity)::value;  // parity of the step
-    constexpr int SL = 1 - PB;                   // centre slot of the plane consumed / requested at this step
-    T(&reg)[NL] = PB ? regB : regA;
-    double(&fr)[NL] = PB ? fB : fA;
+  auto body = [&](auto pb, auto pr, int step) {
+    constexpr int PB = decltype(pb)::value;  // LDS buffer of the step: step % 2
+    constexpr int PR = decltype(pr)::value;  // register set and centre slot of the step: step % D
     T(*tb)[TX + 2] = tile[PB];
     const int kk = k0 - 1 + step;
 #pragma unroll
     for (int m = 0; m < NL; ++m) {
       const int e = tid + m * NT;
-      if (e < E) tb[e / W][e % W] = reg[m];
+      if (e < E) tb[e / W][e % W] = reg[PR][m];
     }
     if constexpr (R) {
       double(*tf)[TX + 2] = tileF[PB];
 #pragma unroll
       for (int m = 0; m < NL; ++m) {
         const int e = tid + m * NT;
-        if (e < E) tf[e / W][e % W] = fr[m];
+        if (e < E) tf[e / W][e % W] = fre[PR][m];
       }
     }
     __syncthreads();
-    if (step + 2 < np) fetch(reg, fr, kk + 2);
+    if (step + D < np) fetch(reg[PR], fre[PR], kk + D);
     const T c = tb[ly + 1][lx + 1];
     const T x = tb[ly + 1][lx] + tb[ly + 1][lx + 2];
     const T y = tb[ly][lx + 1] + tb[ly + 2][lx + 1];
@@ -172,17 +176,29 @@ __device__ __forceinline__ void zmarch(const Sweep &sw, P &pol, double &acc0, do
     if (step >= 2 && active) {
       const T out = Pc + cz * (Cm + c) + cxz * (Xm + x) + cyz * (Ym + y);
       const double rf = 0.5 * (6.0 * Fc + (Gc + (Fm + fc)));
-      pol.template consume<SL>(i, j, kk - 1, own + (long long)(kk - 1) * g.sz, Cc, out, Fc, rf, acc0, acc1);
-      if (kk + 1 < k1) pol.template center<SL>(i, j, kk + 1, own + (long long)(kk + 1) * g.sz);
+      pol.template consume<PR>(i, j, kk - 1, own + (long long)(kk - 1) * g.sz, Cc, out, Fc, rf, acc0, acc1);
+      if (kk - 1 + D < k1) pol.template center<PR>(i, j, kk - 1 + D, own + (long long)(kk - 1 + D) * g.sz);
     }
     Cm = Cc; Xm = Xc; Ym = Yc;
     Cc = c; Xc = x; Yc = y;
     Pc = c0 * c + cx * x + cy * y + cxy * d;
     Fm = Fc; Fc = fc; Gc = fg;
   };
-  for (int step = 0; step < np; step += 2) {
-    body(std::integral_constant<int, 0>{}, step);
-    if (step + 1 < np) body(std::integral_constant<int, 1>{}, step + 1);
+  using I0 = std::integral_constant<int, 0>;
+  using I1 = std::integral_constant<int, 1>;
+  using I2 = std::integral_constant<int, 2>;
+  for (int step = 0; step < np; step += U) {
+    if constexpr (D == 2) {
+      body(I0{}, I0{}, step);
+      if (step + 1 < np) body(I1{}, I1{}, step + 1);
+    } else {
+      body(I0{}, I0{}, step);
+      if (step + 1 < np) body(I1{}, I1{}, step + 1);
+      if (step + 2 < np) body(I0{}, I2{}, step + 2);
+      if (step + 3 < np) body(I1{}, I0{}, step + 3);
+      if (step + 4 < np) body(I0{}, I1{}, step + 4);
+      if (step + 5 < np) body(I1{}, I2{}, step + 5);
+    }
   }
 }
 
@@ -347,7 +363,7 @@ struct PolA {
   }
 };
 
-template <typename T>
+template <typename T, int D>
 __global__ __launch_bounds__(NT) void cg_pass_a_kernel(Sweep sw, const T *__restrict__ r, T *p0, T *p1,
                                                        const CgState *cs, double *partials) {
   __shared__ T tile[2][TY + 2][TX + 2];
@@ -361,7 +377,7 @@ __global__ __launch_bounds__(NT) void cg_pass_a_kernel(Sweep sw, const T *__rest
   pol.first = (it == 0);
   pol.beta = (T)cs->beta;
   double a0 = 0.0, a1 = 0.0;
-  zmarch<T>(sw, pol, a0, a1, tile, nullptr, blockIdx.x, gridDim.x, true);
+  zmarch<T, D>(sw, pol, a0, a1, tile, nullptr, blockIdx.x, gridDim.x, true);
   const double v[1] = {a0};
   write_partials<1>(v, partials, sh, blockIdx.x, gridDim.x);
 }
@@ -373,7 +389,7 @@ struct PolB {
   T *u;
   T *r;
   T alpha;
-  T pr[2], pu[2];
+  T pr[3], pu[3];
   __device__ __forceinline__ T operand(long long idx) const { return p[idx]; }
   __device__ __forceinline__ long long fcol(int, int) const { return -1; }
   __device__ __forceinline__ long long fplane() const { return 0; }
@@ -393,7 +409,7 @@ struct PolB {
   }
 };
 
-template <typename T>
+template <typename T, int D>
 __global__ __launch_bounds__(NT) void cg_pass_b_kernel(Sweep sw, T *u, T *r, const T *p0, const T *p1,
                                                        const CgState *cs, double *partials) {
   __shared__ T tile[2][TY + 2][TX + 2];
@@ -405,10 +421,10 @@ __global__ __launch_bounds__(NT) void cg_pass_b_kernel(Sweep sw, T *u, T *r, con
   pol.u = u;
   pol.r = r;
   pol.alpha = (T)cs->alpha;
-  pol.pr[0] = pol.pr[1] = 0;
-  pol.pu[0] = pol.pu[1] = 0;
+  pol.pr[0] = pol.pr[1] = pol.pr[2] = 0;
+  pol.pu[0] = pol.pu[1] = pol.pu[2] = 0;
   double a0 = 0.0, a1 = 0.0;
-  zmarch<T>(sw, pol, a0, a1, tile, nullptr, blockIdx.x, gridDim.x, true);
+  zmarch<T, D>(sw, pol, a0, a1, tile, nullptr, blockIdx.x, gridDim.x, true);
   const double v[1] = {a0};
   write_partials<1>(v, partials, sh, blockIdx.x, gridDim.x);
 }
@@ -420,7 +436,7 @@ struct RhsPart {
   RhsSrc rs;
   int nx, ny, nz;
   const double *bterm;  // the boundary terms (in r's layout, read before r is overwritten at the same node)
-  double bt[2];         // boundary terms of the planes in flight
+  double bt[3];         // boundary terms of the planes in flight
   __device__ __forceinline__ long long fcol(int gi, int gj) const { return rs.gf.at(gi * rs.s, gj * rs.s, 0); }
   __device__ __forceinline__ long long fplane() const { return (long long)rs.s * rs.gf.sz; }
   __device__ __forceinline__ double fval(long long idx) const { return rs.f[idx]; }
@@ -536,8 +552,8 @@ __global__ __launch_bounds__(NT) void cg_selfred_b_kernel(Sweep sw, T *u, T *r, 
   pol.u = u;
   pol.r = r;
   pol.alpha = (T)(cs->rhoA[k & 1] / pq);
-  pol.pr[0] = pol.pr[1] = 0;
-  pol.pu[0] = pol.pu[1] = 0;
+  pol.pr[0] = pol.pr[1] = pol.pr[2] = 0;
+  pol.pu[0] = pol.pu[1] = pol.pu[2] = 0;
   double a0 = 0.0, a1 = 0.0;
   zmarch<T>(sw, pol, a0, a1, tile, nullptr, blockIdx.x, gridDim.x, true);
   const double v[1] = {a0};
@@ -578,14 +594,15 @@ struct PolResid {
   }
 };
 
+template <int D>
 __global__ __launch_bounds__(NT) void residual_kernel(Sweep sw, const double *u, RhsSrc rs, double *r,
                                                       double *partials) {
   __shared__ double tile[2][TY + 2][TX + 2];
   __shared__ double sh[NT / 64];
   __shared__ double tileF[2][TY + 2][TX + 2];
-  PolResid pol{u, r, RhsPart{rs, sw.g.nx, sw.g.ny, sw.g.nz, r, {0.0, 0.0}}};
+  PolResid pol{u, r, RhsPart{rs, sw.g.nx, sw.g.ny, sw.g.nz, r, {0.0, 0.0, 0.0}}};
   double a0 = 0.0, a1 = 0.0;
-  zmarch<double>(sw, pol, a0, a1, tile, tileF, blockIdx.x, gridDim.x, true);
+  zmarch<double, D>(sw, pol, a0, a1, tile, tileF, blockIdx.x, gridDim.x, true);
   const double v[2] = {a0, a1};
   write_partials<2>(v, partials, sh, blockIdx.x, gridDim.x);
 }
@@ -620,15 +637,16 @@ struct PolResidCast {
   }
 };
 
+template <int D>
 __global__ __launch_bounds__(NT) void residual_cast_kernel(Sweep sw, const double *u, RhsSrc rs,
                                                            const double *bterm, Grid g32, float *r32, float *d32,
                                                            double *partials) {
   __shared__ double tile[2][TY + 2][TX + 2];
   __shared__ double sh[NT / 64];
   __shared__ double tileF[2][TY + 2][TX + 2];
-  PolResidCast pol{u, g32, r32, d32, RhsPart{rs, sw.g.nx, sw.g.ny, sw.g.nz, bterm, {0.0, 0.0}}, 0.0};
+  PolResidCast pol{u, g32, r32, d32, RhsPart{rs, sw.g.nx, sw.g.ny, sw.g.nz, bterm, {0.0, 0.0, 0.0}}, 0.0};
   double a0 = 0.0, a1 = 0.0;
-  zmarch<double>(sw, pol, a0, a1, tile, tileF, blockIdx.x, gridDim.x, true);
+  zmarch<double, D>(sw, pol, a0, a1, tile, tileF, blockIdx.x, gridDim.x, true);
   const double v[3] = {a0, a1, pol.acc2};
   write_partials<3>(v, partials, sh, blockIdx.x, gridDim.x);
 }
@@ -1017,6 +1035,114 @@ __device__ void small_cg_lds_body(const Grid &gu, double *u, const RhsSrc &rs, c
   }
 }
 
+// ----------------------------------------------------------------------------------------- direct solve by sines
+//
+// With zero Dirichlet data, M (the 19-point operator on the interior) is diagonalised by the products of DST-I
+// vectors s_p(i) = sin(pi p i / N), p, i = 1..N-1 per axis: M S = S diag(lambda) with
+//   lambda_pqr = c0 + 2 cx Cx + 2 cy Cy + 2 cz Cz + 4 cxy Cx Cy + 4 cxz Cx Cz + 4 cyz Cy Cz,  Cx = cos(pi p / Nx), ...
+// (c* the stencil's coefficients), and S^2 = (Nx Ny Nz / 8) I.  So M^-1 b = (8 / (Nx Ny Nz)) S diag(1/lambda) S b: three
+// one-dimensional sine transforms, a division, three more.  This is DSOLVE of Algorithm 1 as an exact direct solve
+// (to rounding), in one workgroup, for grids of at most kDstMax cells per axis; the transforms are dense
+// (N-1) x (N-1) products along each axis through the work arrays A and B (the grid's layout), with the sine table of
+// the current axis in LDS.
+constexpr int kDstMax = 64;
+
+__host__ __device__ inline bool dst_fits(const Grid &g) {
+  return g.nx <= kDstMax && g.ny <= kDstMax && g.nz <= kDstMax;
+}
+
+__device__ void dst_solve_body(const Grid &gu, double *u, const RhsSrc &rs, const Stencil &st, CgState *cs,
+                               double *A, double *B) {
+  __shared__ double tab[(kDstMax - 1) * (kDstMax - 1)];
+  __shared__ double cosv[3][kDstMax];
+  __shared__ double sh[DT / 64];
+  const int n1[3] = {gu.nx - 1, gu.ny - 1, gu.nz - 1};
+  const int N[3] = {gu.nx, gu.ny, gu.nz};
+  const int n = n1[0] * n1[1] * n1[2];
+  auto coords = [&](int m, int &i, int &j, int &k) {
+    i = 1 + m % n1[0];
+    const int t = m / n1[0];
+    j = 1 + t % n1[1];
+    k = 1 + t / n1[1];
+  };
+  // A = b (formed from the level data), and the cosines of every axis
+  double b2 = 0.0;
+  for (int m = threadIdx.x; m < n; m += DT) {
+    int i, j, k;
+    coords(m, i, j, k);
+    const double bv = rhs_at<true>(rs, gu.nx, gu.ny, gu.nz, i, j, k);
+    A[gu.at(i, j, k)] = bv;
+    b2 += bv * bv;
+  }
+  for (int e = threadIdx.x; e < 3 * kDstMax; e += DT) {
+    const int d = e / kDstMax, p = e % kDstMax;
+    cosv[d][p] = (p >= 1 && p < N[d]) ? cospi((double)p / N[d]) : 0.0;
+  }
+  // one transform along axis d: dst(.., i, ..) = sum_i' sin(pi i i' / N_d) src(.., i', ..)
+  auto transform = [&](int d, const double *src, double *dst) {
+    const int L = n1[d];
+    __syncthreads();  // src complete; the previous table no longer read
+    for (int e = threadIdx.x; e < L * L; e += DT) {
+      const int p = e / L + 1, q = e % L + 1;
+      tab[e] = sinpi((double)((p * q) % (2 * N[d])) / N[d]);
+    }
+    __syncthreads();
+    const long long stride = d == 0 ? 1 : (d == 1 ? gu.sy : gu.sz);
+    for (int m = threadIdx.x; m < n; m += DT) {
+      int i, j, k;
+      coords(m, i, j, k);
+      const int t = d == 0 ? i : (d == 1 ? j : k);
+      const long long base = gu.at(i, j, k) - (long long)t * stride;  // the line's node 0
+      const double *row = tab + (t - 1) * L;
+      double v = 0.0;
+      for (int q = 1; q <= L; ++q) v += row[q - 1] * src[base + (long long)q * stride];
+      dst[gu.at(i, j, k)] = v;
+    }
+  };
+  transform(0, A, B);
+  transform(1, B, A);
+  transform(2, A, B);
+  // divide by the eigenvalues (with the scale of the inverse transform)
+  __syncthreads();
+  const double scale = 8.0 / ((double)N[0] * N[1] * N[2]);
+  for (int m = threadIdx.x; m < n; m += DT) {
+    int i, j, k;
+    coords(m, i, j, k);
+    const double Cx = cosv[0][i], Cy = cosv[1][j], Cz = cosv[2][k];
+    const double lam = st.c0 + 2.0 * (st.cx * Cx + st.cy * Cy + st.cz * Cz) +
+                       4.0 * (st.cxy * Cx * Cy + st.cxz * Cx * Cz + st.cyz * Cy * Cz);
+    B[gu.at(i, j, k)] *= scale / lam;
+  }
+  transform(0, B, A);
+  transform(1, A, B);
+  transform(2, B, A);
+  __syncthreads();
+  for (int m = threadIdx.x; m < n; m += DT) {
+    int i, j, k;
+    coords(m, i, j, k);
+    u[gu.at(i, j, k)] = A[gu.at(i, j, k)];
+  }
+  __syncthreads();
+  // residual of the solve, for the record
+  double r2 = 0.0;
+  for (int m = threadIdx.x; m < n; m += DT) {
+    int i, j, k;
+    coords(m, i, j, k);
+    const double rv = rhs_at<true>(rs, gu.nx, gu.ny, gu.nz, i, j, k) - stencil_direct(gu, u, i, j, k, st);
+    r2 += rv * rv;
+  }
+  const double rho = dsum(r2, sh);
+  const double bnorm2 = dsum(b2, sh);
+  if (threadIdx.x == 0) {
+    cs->iter = 0;
+    cs->rho = rho;
+    cs->rho0 = rho;
+    cs->bnorm2 = bnorm2;
+    cs->status = (isfinite(rho) && isfinite(bnorm2)) ? 0 : EXCMG_ERR_BREAKDOWN;
+    cs->done = 1;
+  }
+}
+
 __host__ __device__ inline bool small_fits_lds(const Grid &g) {
   return small_lds_nodes(g) <= kSmallLdsMax && g.interior() <= (long long)SK * DT;
 }
@@ -1025,7 +1151,9 @@ __global__ __launch_bounds__(DT) void small_cg_kernel(Grid gu, double *u, RhsSrc
                                                       double *q, Stencil st, CgState *cs, double tol, int cap,
                                                       int exact, int hist_on) {
   extern __shared__ double lds_p[];
-  if (small_fits_lds(gu))
+  if (exact && dst_fits(gu))
+    dst_solve_body(gu, u, rs, st, cs, r, p);
+  else if (small_fits_lds(gu))
     small_cg_lds_body(gu, u, rs, gw, r, st, cs, tol, cap, exact, hist_on, lds_p);
   else
     small_cg_body(gu, u, rs, gw, r, p, q, st, cs, tol, cap, exact, hist_on);
@@ -1080,7 +1208,9 @@ __global__ __launch_bounds__(DT) void b_small_cg_kernel(const BatchEntry *t, Bat
     cap = (int)(4 * n + 200);
     if (cap > 20000) cap = 20000;
   }
-  if (small_fits_lds(E.g) && small_lds_nodes(E.g) <= lds_nodes)
+  if (E.exact && dst_fits(E.g))
+    dst_solve_body(E.g, E.u, E.rs, E.st, E.cs, E.r, E.p0);
+  else if (small_fits_lds(E.g) && small_lds_nodes(E.g) <= lds_nodes)
     small_cg_lds_body(E.g, E.u, E.rs, E.g, E.r, E.st, E.cs, E.tol, cap, E.exact, 0, lds_p);
   else
     small_cg_body(E.g, E.u, E.rs, E.g, E.r, E.p0, E.p1, E.st, E.cs, E.tol, cap, E.exact, 0);
@@ -1105,7 +1235,7 @@ __global__ __launch_bounds__(NT) void b_residual_kernel(const BatchEntry *t, con
   const BatchEntry &E = t[e];
   const int bid = blockIdx.x - pre[e], nb = pre[e + 1] - pre[e];
   const Sweep sw = E.swR;
-  PolResid pol{E.u, E.r, RhsPart{E.rs, sw.g.nx, sw.g.ny, sw.g.nz, E.r, {0.0, 0.0}}};
+  PolResid pol{E.u, E.r, RhsPart{E.rs, sw.g.nx, sw.g.ny, sw.g.nz, E.r, {0.0, 0.0, 0.0}}};
   double a0 = 0.0, a1 = 0.0;
   zmarch<double>(sw, pol, a0, a1, tile, tileF, bid, nb, false);
   const double v[2] = {a0, a1};
@@ -1138,7 +1268,7 @@ __global__ __launch_bounds__(NT) void b_residual_cast_kernel(const BatchEntry *t
   if (outer_step > 0 && E.cs->done) return;
   const int bid = blockIdx.x - pre[e], nb = pre[e + 1] - pre[e];
   const Sweep sw = E.swR;
-  PolResidCast pol{E.u, E.g32, E.r32, E.d32, RhsPart{E.rs, sw.g.nx, sw.g.ny, sw.g.nz, E.r, {0.0, 0.0}}, 0.0};
+  PolResidCast pol{E.u, E.g32, E.r32, E.d32, RhsPart{E.rs, sw.g.nx, sw.g.ny, sw.g.nz, E.r, {0.0, 0.0, 0.0}}, 0.0};
   double a0 = 0.0, a1 = 0.0;
   zmarch<double>(sw, pol, a0, a1, tile, tileF, bid, nb, false);
   const double v[3] = {a0, a1, pol.acc2};
@@ -1215,8 +1345,8 @@ __global__ __launch_bounds__(NT) void b_pass_b_kernel(const BatchEntry *t, const
     pol.r = E.r;
   }
   pol.alpha = (T)cs->alpha;
-  pol.pr[0] = pol.pr[1] = 0;
-  pol.pu[0] = pol.pu[1] = 0;
+  pol.pr[0] = pol.pr[1] = pol.pr[2] = 0;
+  pol.pu[0] = pol.pu[1] = pol.pu[2] = 0;
   const Sweep sw = F ? E.swB32 : E.swB;
   double a0 = 0.0, a1 = 0.0;
   zmarch<T>(sw, pol, a0, a1, tile, nullptr, bid, nb, false);
@@ -1258,8 +1388,9 @@ __global__ __launch_bounds__(256) void b_add_correction_kernel(const BatchEntry 
 
 // z chunk per workgroup (even, so that the first output plane of every workgroup is odd).  Default: 16 planes, or
 // fewer while the grid has under 2048 workgroups (8 per CU).  The autotuner replaces it per grid and pass.
-Sweep make_sweep(const Grid &g, const Stencil &s, int zc) {
+Sweep make_sweep(const Grid &g, const Stencil &s, int zc, int depth) {
   Sweep sw;
+  sw.depth = depth == 3 ? 3 : 2;
   sw.g = g;
   sw.st = s;
   sw.ntx = (g.nx - 1 + TX - 1) / TX;
@@ -1292,7 +1423,8 @@ static void launch_boundary_terms(const RhsSrc &rs, const Grid &g, double *out, 
 void launch_residual_partials(const Sweep &sw, const double *u, const RhsSrc &rs, double *r, double *parts,
                               hipStream_t st) {
   launch_boundary_terms(rs, sw.g, r, st);
-  residual_kernel<<<sweep_blocks(sw), NT, 0, st>>>(sw, u, rs, r, parts);
+  if (sw.depth == 3) residual_kernel<3><<<sweep_blocks(sw), NT, 0, st>>>(sw, u, rs, r, parts);
+  else residual_kernel<2><<<sweep_blocks(sw), NT, 0, st>>>(sw, u, rs, r, parts);
 }
 
 void launch_selfred_init(CgState *cs, int max_iters, int hist_on, int preset, hipStream_t st) {
@@ -1326,7 +1458,8 @@ void launch_residual(const Sweep &sw, const double *u, const RhsSrc &rs, double 
                      double tol, int max_iters, int hist_on, hipStream_t st) {
   const int nb = sweep_blocks(sw);
   launch_boundary_terms(rs, sw.g, r, st);
-  residual_kernel<<<nb, NT, 0, st>>>(sw, u, rs, r, partials);
+  if (sw.depth == 3) residual_kernel<3><<<nb, NT, 0, st>>>(sw, u, rs, r, partials);
+  else residual_kernel<2><<<nb, NT, 0, st>>>(sw, u, rs, r, partials);
   finalize_init_kernel<<<1, FT, 0, st>>>(cs, partials, nb, tol, max_iters, hist_on);
 }
 
@@ -1335,14 +1468,16 @@ void launch_residual_cast(const Sweep &sw, const double *u, const RhsSrc &rs, do
                           double eta, int outer_step, int max_outer, int max_inner, hipStream_t st) {
   const int nb = sweep_blocks(sw);
   launch_boundary_terms(rs, sw.g, bterm, st);
-  residual_cast_kernel<<<nb, NT, 0, st>>>(sw, u, rs, bterm, g32, r32, d32, partials);
+  if (sw.depth == 3) residual_cast_kernel<3><<<nb, NT, 0, st>>>(sw, u, rs, bterm, g32, r32, d32, partials);
+  else residual_cast_kernel<2><<<nb, NT, 0, st>>>(sw, u, rs, bterm, g32, r32, d32, partials);
   finalize_ir_kernel<<<1, FT, 0, st>>>(outer, inner, partials, nb, tol, eta, outer_step, max_outer, max_inner);
 }
 
 template <typename T>
 void launch_cg_pass_a(const Sweep &sw, const T *r, T *p0, T *p1, CgState *cs, double *partials, hipStream_t st) {
   const int nb = sweep_blocks(sw);
-  cg_pass_a_kernel<T><<<nb, NT, 0, st>>>(sw, r, p0, p1, cs, partials);
+  if (sw.depth == 3) cg_pass_a_kernel<T, 3><<<nb, NT, 0, st>>>(sw, r, p0, p1, cs, partials);
+  else cg_pass_a_kernel<T, 2><<<nb, NT, 0, st>>>(sw, r, p0, p1, cs, partials);
   finalize_a_kernel<<<1, FT, 0, st>>>(cs, partials, nb);
 }
 
@@ -1350,7 +1485,8 @@ template <typename T>
 void launch_cg_pass_b(const Sweep &sw, T *u, T *r, const T *p0, const T *p1, CgState *cs, double *partials,
                       hipStream_t st) {
   const int nb = sweep_blocks(sw);
-  cg_pass_b_kernel<T><<<nb, NT, 0, st>>>(sw, u, r, p0, p1, cs, partials);
+  if (sw.depth == 3) cg_pass_b_kernel<T, 3><<<nb, NT, 0, st>>>(sw, u, r, p0, p1, cs, partials);
+  else cg_pass_b_kernel<T, 2><<<nb, NT, 0, st>>>(sw, u, r, p0, p1, cs, partials);
   finalize_b_kernel<<<1, FT, 0, st>>>(cs, partials, nb);
 }
 
@@ -1379,7 +1515,8 @@ void launch_small_cg(const Grid &gu, double *u, const RhsSrc &rs, const Grid &gw
     cap = (int)(4 * n + 200);
     if (cap > 20000) cap = 20000;
   }
-  const size_t lds = small_fits_lds(gu) ? (size_t)small_lds_nodes(gu) * sizeof(double) : 0;
+  const size_t lds = (!(exact && dst_fits(gu)) && small_fits_lds(gu)) ? (size_t)small_lds_nodes(gu) * sizeof(double)
+                                                                        : 0;
   small_cg_kernel<<<1, DT, lds, st>>>(gu, u, rs, gw, r, p, q, s, cs, tol, cap, exact, hist_on);
 }
 
