@@ -114,7 +114,8 @@ int make_layout(const excmg_problem *p, Layout *Lo) {
     lv.g = pitched_grid<double>(lv.n[0], lv.n[1], lv.n[2]);
     lv.g32 = pitched_grid<float>(lv.n[0], lv.n[1], lv.n[2]);
     lv.st = make_stencil(lv.h[0], lv.h[1], lv.h[2]);
-    lv.sw = make_sweep(lv.g, lv.st, 0);
+    // the residual sweep runs once per grid: streaming stores when the grid is far larger than the caches
+    lv.sw = make_sweep(lv.g, lv.st, 0, 2, lv.g.interior() >= (1LL << 23) ? 1 : 0);
     lv.sw32 = make_sweep(lv.g32, lv.st, 0);
     lv.swA = lv.swB = lv.sw;
     lv.swA32 = lv.swB32 = lv.sw32;
@@ -1137,10 +1138,10 @@ int excmg_autotune(excmg_handle *h, int32_t *zc_out, int32_t *depth_out) {
       for (int pass = 0; pass < 2 && rc == EXCMG_OK; ++pass) {
         float best = 1e30f;
         Sweep bsw = prec ? (pass ? lv.swB32 : lv.swA32) : (pass ? lv.swB : lv.swA);
-        for (int ci = 0; ci < 2 * (int)(sizeof(cand) / sizeof(cand[0])); ++ci) {
-          const int zc = cand[ci / 2], depth = 2 + ci % 2;
+        for (int ci = 0; ci < 4 * (int)(sizeof(cand) / sizeof(cand[0])); ++ci) {
+          const int zc = cand[ci / 4], depth = 2 + ci % 2, nt = (ci / 2) % 2;
           if (zc > 2 * (g.nz - 1) + 2) break;
-          const Sweep sw = make_sweep(g, lv.st, zc, depth);
+          const Sweep sw = make_sweep(g, lv.st, zc, depth, nt);
           if (3LL * sweep_blocks(sw) > lo.npart) continue;
           float tmin = 1e30f;
           for (int rep = 0; rep < 4; ++rep) {
@@ -1190,10 +1191,10 @@ int excmg_autotune(excmg_handle *h, int32_t *zc_out, int32_t *depth_out) {
       const Level &lv = lo.lev[l];
       const bool relaxed = l >= 2 && lv.g.interior() > kSmallCg;
       const bool ir = relaxed && (h->p.precision == EXCMG_FP32_IR) && lv.g.interior() >= kIrMinUnknowns;
-      depth_out[4 * l + 0] = relaxed ? lv.swA.depth : 0;
-      depth_out[4 * l + 1] = relaxed ? lv.swB.depth : 0;
-      depth_out[4 * l + 2] = ir ? lv.swA32.depth : 0;
-      depth_out[4 * l + 3] = ir ? lv.swB32.depth : 0;
+      depth_out[4 * l + 0] = relaxed ? lv.swA.depth + 10 * lv.swA.nt : 0;
+      depth_out[4 * l + 1] = relaxed ? lv.swB.depth + 10 * lv.swB.nt : 0;
+      depth_out[4 * l + 2] = ir ? lv.swA32.depth + 10 * lv.swA32.nt : 0;
+      depth_out[4 * l + 3] = ir ? lv.swB32.depth + 10 * lv.swB32.nt : 0;
     }
   }
   return EXCMG_OK;

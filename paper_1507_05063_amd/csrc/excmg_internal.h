@@ -164,9 +164,10 @@ struct Sweep {
   Stencil st;
   int zc, ntx, nty, nzc;
   int depth;  // planes of loads in flight per thread in the z-march (2 or 3; the pass and residual sweeps)
+  int nt;     // 1: data read or written once per sweep uses non-temporal (streaming) loads and stores
 };
 
-Sweep make_sweep(const Grid &g, const Stencil &s, int zc, int depth = 2);  // zc <= 0: default chunk
+Sweep make_sweep(const Grid &g, const Stencil &s, int zc, int depth = 2, int nt = 0);  // zc <= 0: default chunk
 int sweep_blocks(const Sweep &sw);
 // partial-sum buffer length needed by the CG and residual kernels for a grid
 long long cg_partials_needed(const Grid &g);

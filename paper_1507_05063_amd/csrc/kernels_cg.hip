@@ -66,6 +66,19 @@ constexpr int TX = 64;
 constexpr int TY = 4;
 constexpr int NT = TX * TY;
 
+// Loads and stores of data a sweep touches once: non-temporal (streaming) when NTP, so that they do not displace the
+// operand's halo lines, which neighbouring tiles read again, from the caches.
+template <bool NTP, typename T>
+__device__ __forceinline__ T ld1(const T *p) {
+  if constexpr (NTP) return __builtin_nontemporal_load(p);
+  else return *p;
+}
+template <bool NTP, typename T>
+__device__ __forceinline__ void st1(T v, T *p) {
+  if constexpr (NTP) __builtin_nontemporal_store(v, p);
+  else *p = v;
+}
+
 // The z-march.  P supplies operand(idx) (the stencil operand at an interior node, idx in grid g),
 // center<S>(i,j,k,idx) (load of the thread's own data for output plane k into slot S) and
 // consume<S>(i,j,k,idx,C,out,cf,rf,acc0,acc1) (output plane k, data in slot S).  Both the stencil planes and the centre
@@ -341,7 +354,7 @@ __device__ void state_ir(CgState *outer, CgState *inner, double r64, double bb, 
 
 // ---------------------------------------------------------------------------------------------------------- passes
 
-template <typename T>
+template <typename T, bool NTP = false>
 struct PolA {
   static constexpr bool kRhs = false;
   const T *r;
@@ -358,19 +371,19 @@ struct PolA {
   template <int S>
   __device__ __forceinline__ void consume(int, int, int, long long idx, T c, T out, double, double, double &acc0,
                                           double &) {
-    pnew[idx] = c;
+    st1<NTP>(c, &pnew[idx]);
     acc0 += (double)c * (double)out;
   }
 };
 
-template <typename T, int D>
+template <typename T, int D, bool NTP>
 __global__ __launch_bounds__(NT) void cg_pass_a_kernel(Sweep sw, const T *__restrict__ r, T *p0, T *p1,
                                                        const CgState *cs, double *partials) {
   __shared__ T tile[2][TY + 2][TX + 2];
   __shared__ double sh[NT / 64];
   if (cs->done) return;
   const int it = cs->iter;
-  PolA<T> pol;
+  PolA<T, NTP> pol;
   pol.r = r;
   pol.pnew = (it & 1) ? p1 : p0;
   pol.pold = (it & 1) ? p0 : p1;
@@ -382,7 +395,7 @@ __global__ __launch_bounds__(NT) void cg_pass_a_kernel(Sweep sw, const T *__rest
   write_partials<1>(v, partials, sh, blockIdx.x, gridDim.x);
 }
 
-template <typename T>
+template <typename T, bool NTP = false>
 struct PolB {
   static constexpr bool kRhs = false;
   const T *p;
@@ -396,27 +409,27 @@ struct PolB {
   __device__ __forceinline__ double fval(long long) const { return 0.0; }
   template <int S>
   __device__ __forceinline__ void center(int, int, int, long long idx) {
-    pr[S] = r[idx];
-    pu[S] = u[idx];
+    pr[S] = ld1<NTP>(&r[idx]);
+    pu[S] = ld1<NTP>(&u[idx]);
   }
   template <int S>
   __device__ __forceinline__ void consume(int, int, int, long long idx, T c, T out, double, double, double &acc0,
                                           double &) {
     const T rn = pr[S] - alpha * out;
-    r[idx] = rn;
-    u[idx] = pu[S] + alpha * c;
+    st1<NTP>(rn, &r[idx]);
+    st1<NTP>(pu[S] + alpha * c, &u[idx]);
     acc0 += (double)rn * (double)rn;
   }
 };
 
-template <typename T, int D>
+template <typename T, int D, bool NTP>
 __global__ __launch_bounds__(NT) void cg_pass_b_kernel(Sweep sw, T *u, T *r, const T *p0, const T *p1,
                                                        const CgState *cs, double *partials) {
   __shared__ T tile[2][TY + 2][TX + 2];
   __shared__ double sh[NT / 64];
   if (cs->done) return;
   const int it = cs->iter;
-  PolB<T> pol;
+  PolB<T, NTP> pol;
   pol.p = (it & 1) ? p1 : p0;
   pol.u = u;
   pol.r = r;
@@ -572,6 +585,7 @@ __global__ void selfred_init_kernel(CgState *cs, int max_iters, int hist_on, int
 }
 
 // r = b - M u; u and r share the level layout.
+template <bool NTP = false>
 struct PolResid {
   static constexpr bool kRhs = true;
   const double *u;
@@ -588,19 +602,19 @@ struct PolResid {
                                           double &acc0, double &acc1) {
     const double bv = rp.template b<S>(cf, rf);
     const double rn = bv - out;
-    r[idx] = rn;
+    st1<NTP>(rn, &r[idx]);
     acc0 += rn * rn;
     acc1 += bv * bv;
   }
 };
 
-template <int D>
+template <int D, bool NTP>
 __global__ __launch_bounds__(NT) void residual_kernel(Sweep sw, const double *u, RhsSrc rs, double *r,
                                                       double *partials) {
   __shared__ double tile[2][TY + 2][TX + 2];
   __shared__ double sh[NT / 64];
   __shared__ double tileF[2][TY + 2][TX + 2];
-  PolResid pol{u, r, RhsPart{rs, sw.g.nx, sw.g.ny, sw.g.nz, r, {0.0, 0.0, 0.0}}};
+  PolResid<NTP> pol{u, r, RhsPart{rs, sw.g.nx, sw.g.ny, sw.g.nz, r, {0.0, 0.0, 0.0}}};
   double a0 = 0.0, a1 = 0.0;
   zmarch<double, D>(sw, pol, a0, a1, tile, tileF, blockIdx.x, gridDim.x, true);
   const double v[2] = {a0, a1};
@@ -608,6 +622,7 @@ __global__ __launch_bounds__(NT) void residual_kernel(Sweep sw, const double *u,
 }
 
 // r32 = (float)(b - M u), d32 = 0; the FP32 arrays use their own layout g32.
+template <bool NTP = false>
 struct PolResidCast {
   static constexpr bool kRhs = true;
   const double *u;
@@ -629,22 +644,22 @@ struct PolResidCast {
     const double rn = bv - out;
     const float rf32 = (float)rn;
     const long long q = g32.at(i, j, k);
-    r32[q] = rf32;
-    d32[q] = 0.0f;
+    st1<NTP>(rf32, &r32[q]);
+    st1<NTP>(0.0f, &d32[q]);
     acc0 += rn * rn;
     acc1 += bv * bv;
     acc2 += (double)rf32 * (double)rf32;
   }
 };
 
-template <int D>
+template <int D, bool NTP>
 __global__ __launch_bounds__(NT) void residual_cast_kernel(Sweep sw, const double *u, RhsSrc rs,
                                                            const double *bterm, Grid g32, float *r32, float *d32,
                                                            double *partials) {
   __shared__ double tile[2][TY + 2][TX + 2];
   __shared__ double sh[NT / 64];
   __shared__ double tileF[2][TY + 2][TX + 2];
-  PolResidCast pol{u, g32, r32, d32, RhsPart{rs, sw.g.nx, sw.g.ny, sw.g.nz, bterm, {0.0, 0.0, 0.0}}, 0.0};
+  PolResidCast<NTP> pol{u, g32, r32, d32, RhsPart{rs, sw.g.nx, sw.g.ny, sw.g.nz, bterm, {0.0, 0.0, 0.0}}, 0.0};
   double a0 = 0.0, a1 = 0.0;
   zmarch<double, D>(sw, pol, a0, a1, tile, tileF, blockIdx.x, gridDim.x, true);
   const double v[3] = {a0, a1, pol.acc2};
@@ -1235,7 +1250,7 @@ __global__ __launch_bounds__(NT) void b_residual_kernel(const BatchEntry *t, con
   const BatchEntry &E = t[e];
   const int bid = blockIdx.x - pre[e], nb = pre[e + 1] - pre[e];
   const Sweep sw = E.swR;
-  PolResid pol{E.u, E.r, RhsPart{E.rs, sw.g.nx, sw.g.ny, sw.g.nz, E.r, {0.0, 0.0, 0.0}}};
+  PolResid<> pol{E.u, E.r, RhsPart{E.rs, sw.g.nx, sw.g.ny, sw.g.nz, E.r, {0.0, 0.0, 0.0}}};
   double a0 = 0.0, a1 = 0.0;
   zmarch<double>(sw, pol, a0, a1, tile, tileF, bid, nb, false);
   const double v[2] = {a0, a1};
@@ -1268,7 +1283,7 @@ __global__ __launch_bounds__(NT) void b_residual_cast_kernel(const BatchEntry *t
   if (outer_step > 0 && E.cs->done) return;
   const int bid = blockIdx.x - pre[e], nb = pre[e + 1] - pre[e];
   const Sweep sw = E.swR;
-  PolResidCast pol{E.u, E.g32, E.r32, E.d32, RhsPart{E.rs, sw.g.nx, sw.g.ny, sw.g.nz, E.r, {0.0, 0.0, 0.0}}, 0.0};
+  PolResidCast<> pol{E.u, E.g32, E.r32, E.d32, RhsPart{E.rs, sw.g.nx, sw.g.ny, sw.g.nz, E.r, {0.0, 0.0, 0.0}}, 0.0};
   double a0 = 0.0, a1 = 0.0;
   zmarch<double>(sw, pol, a0, a1, tile, tileF, bid, nb, false);
   const double v[3] = {a0, a1, pol.acc2};
@@ -1388,9 +1403,10 @@ __global__ __launch_bounds__(256) void b_add_correction_kernel(const BatchEntry 
 
 // z chunk per workgroup (even, so that the first output plane of every workgroup is odd).  Default: 16 planes, or
 // fewer while the grid has under 2048 workgroups (8 per CU).  The autotuner replaces it per grid and pass.
-Sweep make_sweep(const Grid &g, const Stencil &s, int zc, int depth) {
+Sweep make_sweep(const Grid &g, const Stencil &s, int zc, int depth, int nt) {
   Sweep sw;
   sw.depth = depth == 3 ? 3 : 2;
+  sw.nt = nt ? 1 : 0;
   sw.g = g;
   sw.st = s;
   sw.ntx = (g.nx - 1 + TX - 1) / TX;
@@ -1420,11 +1436,20 @@ static void launch_boundary_terms(const RhsSrc &rs, const Grid &g, double *out, 
   boundary_terms_kernel<<<grid, 256, 0, st>>>(rs, g, out);
 }
 
+static void launch_resid(const Sweep &sw, const double *u, const RhsSrc &rs, double *r, double *parts,
+                         hipStream_t st) {
+  const int nb = sweep_blocks(sw);
+  const int v = (sw.depth == 3 ? 2 : 0) + sw.nt;
+  if (v == 0) residual_kernel<2, false><<<nb, NT, 0, st>>>(sw, u, rs, r, parts);
+  else if (v == 1) residual_kernel<2, true><<<nb, NT, 0, st>>>(sw, u, rs, r, parts);
+  else if (v == 2) residual_kernel<3, false><<<nb, NT, 0, st>>>(sw, u, rs, r, parts);
+  else residual_kernel<3, true><<<nb, NT, 0, st>>>(sw, u, rs, r, parts);
+}
+
 void launch_residual_partials(const Sweep &sw, const double *u, const RhsSrc &rs, double *r, double *parts,
                               hipStream_t st) {
   launch_boundary_terms(rs, sw.g, r, st);
-  if (sw.depth == 3) residual_kernel<3><<<sweep_blocks(sw), NT, 0, st>>>(sw, u, rs, r, parts);
-  else residual_kernel<2><<<sweep_blocks(sw), NT, 0, st>>>(sw, u, rs, r, parts);
+  launch_resid(sw, u, rs, r, parts, st);
 }
 
 void launch_selfred_init(CgState *cs, int max_iters, int hist_on, int preset, hipStream_t st) {
@@ -1458,8 +1483,7 @@ void launch_residual(const Sweep &sw, const double *u, const RhsSrc &rs, double 
                      double tol, int max_iters, int hist_on, hipStream_t st) {
   const int nb = sweep_blocks(sw);
   launch_boundary_terms(rs, sw.g, r, st);
-  if (sw.depth == 3) residual_kernel<3><<<nb, NT, 0, st>>>(sw, u, rs, r, partials);
-  else residual_kernel<2><<<nb, NT, 0, st>>>(sw, u, rs, r, partials);
+  launch_resid(sw, u, rs, r, partials, st);
   finalize_init_kernel<<<1, FT, 0, st>>>(cs, partials, nb, tol, max_iters, hist_on);
 }
 
@@ -1468,16 +1492,22 @@ void launch_residual_cast(const Sweep &sw, const double *u, const RhsSrc &rs, do
                           double eta, int outer_step, int max_outer, int max_inner, hipStream_t st) {
   const int nb = sweep_blocks(sw);
   launch_boundary_terms(rs, sw.g, bterm, st);
-  if (sw.depth == 3) residual_cast_kernel<3><<<nb, NT, 0, st>>>(sw, u, rs, bterm, g32, r32, d32, partials);
-  else residual_cast_kernel<2><<<nb, NT, 0, st>>>(sw, u, rs, bterm, g32, r32, d32, partials);
+  const int v = (sw.depth == 3 ? 2 : 0) + sw.nt;
+  if (v == 0) residual_cast_kernel<2, false><<<nb, NT, 0, st>>>(sw, u, rs, bterm, g32, r32, d32, partials);
+  else if (v == 1) residual_cast_kernel<2, true><<<nb, NT, 0, st>>>(sw, u, rs, bterm, g32, r32, d32, partials);
+  else if (v == 2) residual_cast_kernel<3, false><<<nb, NT, 0, st>>>(sw, u, rs, bterm, g32, r32, d32, partials);
+  else residual_cast_kernel<3, true><<<nb, NT, 0, st>>>(sw, u, rs, bterm, g32, r32, d32, partials);
   finalize_ir_kernel<<<1, FT, 0, st>>>(outer, inner, partials, nb, tol, eta, outer_step, max_outer, max_inner);
 }
 
 template <typename T>
 void launch_cg_pass_a(const Sweep &sw, const T *r, T *p0, T *p1, CgState *cs, double *partials, hipStream_t st) {
   const int nb = sweep_blocks(sw);
-  if (sw.depth == 3) cg_pass_a_kernel<T, 3><<<nb, NT, 0, st>>>(sw, r, p0, p1, cs, partials);
-  else cg_pass_a_kernel<T, 2><<<nb, NT, 0, st>>>(sw, r, p0, p1, cs, partials);
+  const int v = (sw.depth == 3 ? 2 : 0) + sw.nt;
+  if (v == 0) cg_pass_a_kernel<T, 2, false><<<nb, NT, 0, st>>>(sw, r, p0, p1, cs, partials);
+  else if (v == 1) cg_pass_a_kernel<T, 2, true><<<nb, NT, 0, st>>>(sw, r, p0, p1, cs, partials);
+  else if (v == 2) cg_pass_a_kernel<T, 3, false><<<nb, NT, 0, st>>>(sw, r, p0, p1, cs, partials);
+  else cg_pass_a_kernel<T, 3, true><<<nb, NT, 0, st>>>(sw, r, p0, p1, cs, partials);
   finalize_a_kernel<<<1, FT, 0, st>>>(cs, partials, nb);
 }
 
@@ -1485,8 +1515,11 @@ template <typename T>
 void launch_cg_pass_b(const Sweep &sw, T *u, T *r, const T *p0, const T *p1, CgState *cs, double *partials,
                       hipStream_t st) {
   const int nb = sweep_blocks(sw);
-  if (sw.depth == 3) cg_pass_b_kernel<T, 3><<<nb, NT, 0, st>>>(sw, u, r, p0, p1, cs, partials);
-  else cg_pass_b_kernel<T, 2><<<nb, NT, 0, st>>>(sw, u, r, p0, p1, cs, partials);
+  const int v = (sw.depth == 3 ? 2 : 0) + sw.nt;
+  if (v == 0) cg_pass_b_kernel<T, 2, false><<<nb, NT, 0, st>>>(sw, u, r, p0, p1, cs, partials);
+  else if (v == 1) cg_pass_b_kernel<T, 2, true><<<nb, NT, 0, st>>>(sw, u, r, p0, p1, cs, partials);
+  else if (v == 2) cg_pass_b_kernel<T, 3, false><<<nb, NT, 0, st>>>(sw, u, r, p0, p1, cs, partials);
+  else cg_pass_b_kernel<T, 3, true><<<nb, NT, 0, st>>>(sw, u, r, p0, p1, cs, partials);
   finalize_b_kernel<<<1, FT, 0, st>>>(cs, partials, nb);
 }
 

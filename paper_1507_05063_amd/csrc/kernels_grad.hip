@@ -79,7 +79,7 @@ __device__ __forceinline__ void line_solve(const double *__restrict__ u, long lo
       const int t = t0 + q;
       if (t <= M) {
         v = (t == M) ? dA[q] : dA[q] - inv_m[t] * v;
-        out[odx0 + (long long)t * so] = v;
+        __builtin_nontemporal_store(v, &out[odx0 + (long long)t * so]);  // the caller's output
       }
     }
 #pragma unroll
@@ -180,7 +180,7 @@ __global__ __launch_bounds__(XW) void grad_x_kernel(Grid gu, const double *__res
     for (int m = 0; m < GC; ++m) {
       const int e = tid + m * XW;
       const int ln = e / GC, xx = e % GC, t = t0 + xx;
-      if (ln < nl && t <= M) ux[ob[ln] + t] = tile[ln][xx];
+      if (ln < nl && t <= M) __builtin_nontemporal_store(tile[ln][xx], &ux[ob[ln] + t]);
     }
     __syncthreads();
 #pragma unroll

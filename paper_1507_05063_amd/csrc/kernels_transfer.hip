@@ -46,7 +46,7 @@ __device__ __forceinline__ void copy_block(const Grid &gs, const double *__restr
                                            double *__restrict__ dst, int bx, int j, int k) {
   const int i = bx * 256 + threadIdx.x;
   if (i > gs.nx) return;
-  dst[gd.at(i, j, k)] = src[gs.at(i, j, k)];
+  __builtin_nontemporal_store(__builtin_nontemporal_load(&src[gs.at(i, j, k)]), &dst[gd.at(i, j, k)]);
 }
 
 __global__ __launch_bounds__(256) void copy_kernel(Grid gs, const double *__restrict__ src, Grid gd,
@@ -96,7 +96,7 @@ __device__ __forceinline__ double quartic(int t, double a0, double a1, double a2
 //  4. boundary nodes get g.
 __device__ void exp_finite_block(const Grid &g2, const double *__restrict__ u2, const Grid &g4,
                                  const double *__restrict__ u4, const Grid &gg, const double *__restrict__ gdat, int s,
-                                 const Grid &gw, double *__restrict__ w, int bx, int cj, int ck) {
+                                 const Grid &gw, double *__restrict__ w, int bx, int cj, int ck, bool nt) {
   __shared__ double W[5][5][EX2];
   __shared__ double D[3][3][EX4];
   __shared__ double Wx[5][5][EXF];
@@ -170,7 +170,8 @@ __device__ void exp_finite_block(const Grid &g2, const double *__restrict__ u2, 
       } else {
         v = quartic(zf >> 1, a0, a1, a2, a3, a4);
       }
-      w[gw.at(gi, gj, gk)] = v;
+      if (nt) __builtin_nontemporal_store(v, &w[gw.at(gi, gj, gk)]);
+      else w[gw.at(gi, gj, gk)] = v;
     }
   }
 }
@@ -179,7 +180,9 @@ __global__ __launch_bounds__(ET) void exp_finite_kernel(Grid g2, const double *_
                                                         const double *__restrict__ u4, Grid gg,
                                                         const double *__restrict__ gdat, int s, Grid gw,
                                                         double *__restrict__ w) {
-  exp_finite_block(g2, u2, g4, u4, gg, gdat, s, gw, w, blockIdx.x, blockIdx.y, blockIdx.z);
+  // w is read again right away by the residual sweep: streaming stores only where it cannot stay in the caches
+  exp_finite_block(g2, u2, g4, u4, gg, gdat, s, gw, w, blockIdx.x, blockIdx.y, blockIdx.z,
+                   gw.interior() >= (1LL << 23));
 }
 
 // ------------------------------------------------------------------------------------------------------- exp_true
@@ -218,8 +221,9 @@ __global__ __launch_bounds__(TTX *TTY) void exp_true_kernel(Grid gh, const doubl
     const double d = ((D[cl][bl][al] + D[cl][bl][ah]) + (D[cl][bh][al] + D[cl][bh][ah])) +
                      ((D[ch][bl][al] + D[ch][bl][ah]) + (D[ch][bh][al] + D[ch][bh][ah]));
     const double v = uh[gh.at(i, j, k)];
-    ut[gt.at(i, j, k)] = v + d * (1.0 / 120.0);  // (1/15) * (1/8) * sum over the 8 corner slots
-    if (ucopy) ucopy[gt.at(i, j, k)] = v;
+    // the outputs are the caller's: streaming stores
+    __builtin_nontemporal_store(v + d * (1.0 / 120.0), &ut[gt.at(i, j, k)]);  // (1/15) (1/8) sum of the 8 slots
+    if (ucopy) __builtin_nontemporal_store(v, &ucopy[gt.at(i, j, k)]);
   }
 }
 
@@ -294,7 +298,8 @@ __global__ __launch_bounds__(ET) void b_exp_finite_kernel(const BatchEntry *t, c
   const int ncx = E.g.nx / 8, ncy = E.g.ny / 8;
   const int gx = (ncx + CXN - 1) / CXN;
   const int lb = blockIdx.x - pre[e];
-  exp_finite_block(E.g2, E.u2, E.g4, E.u4, E.gd, E.gb, E.rs.s, E.g, E.u, lb % gx, (lb / gx) % ncy, lb / (gx * ncy));
+  exp_finite_block(E.g2, E.u2, E.g4, E.u4, E.gd, E.gb, E.rs.s, E.g, E.u, lb % gx, (lb / gx) % ncy, lb / (gx * ncy),
+                   false);
 }
 
 inline dim3 node_grid(const Grid &g, int bx) { return dim3((g.nx + 1 + bx - 1) / bx, g.ny + 1, g.nz + 1); }
