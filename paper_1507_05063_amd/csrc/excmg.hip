@@ -677,23 +677,29 @@ void clear_stats(excmg_stats *st) {
 
 // ------------------------------------------------------------------------------------------------ batched solve
 //
-// All problems of a batch walk their cascades in step: step s treats grid s of every problem that has one.  Each
-// step is a table of entries (one per problem) in the batch workspace, built on the host and uploaded once; every
-// launch of the step covers all problems it concerns (flattened workgroup ranges, or one workgroup per problem),
-// so a step costs the same number of launches as one problem's grid.  Per step: boundary values (grids 0, 1) or
-// EXP_finite (grids >= 2); the single-workgroup CG of every small grid; then the FP64 CG of the grids relaxed in
-// FP64 and the refinement loop of those relaxed in FP32, each iterating until all its problems have converged
-// (converged problems' workgroups return at once); finally the copy of finished problems to the caller's arrays.
+// Every problem of a batch walks its own cascade; the host keeps each problem's grid and phase and, in rounds, issues
+// one launch per kind of work for all problems that need it (flattened workgroup ranges, or one workgroup per
+// problem), whatever grid each is on: grid starts (boundary values, or EXP_finite), direct and small-grid solves,
+// residuals, refinement corrections, then a batch of CG iterations for every problem that is iterating.  After each
+// round one look at the problems' status words (pinned host memory) moves them on.  Fast problems thus reach their
+// finest grids while slow ones are still relaxing coarse ones, and a problem that has converged takes no workgroups.
+//
+// Per (problem, grid) the device tables hold an entry (layouts, arrays in the problem's own workspace, level data,
+// tolerances), built on the host and uploaded once; each round uploads only the launch lists (entry pointers and
+// workgroup prefixes).
 
-size_t batch_table_bytes(int count) {
-  return align256(sizeof(BatchEntry) * (size_t)count) + align256(sizeof(int) * (size_t)kLaunchKinds * (count + 1));
+enum BatchListKind { kListSetB, kListExp, kListSmall, kListBterm, kListR64, kListRC, kListCorr, kListI64, kListI32,
+                     kListCopy, kListKinds };
+
+size_t batch_table_bytes(int count) { return align256(sizeof(BatchEntry) * (size_t)count); }
+
+size_t batch_list_bytes(int count) {
+  return align256(sizeof(void *) * (size_t)count + sizeof(int) * (2 * (size_t)(count + 1) + (size_t)count));
 }
-
-size_t batch_dyn_bytes(int count) { return align256(sizeof(int) * (size_t)kLaunchKinds * (count + 1)); }
 
 size_t batch_ws_bytes(int count) {
   return align256(sizeof(BatchStatus) * (size_t)count) + 256 + (size_t)EXCMG_MAX_LEVELS * batch_table_bytes(count) +
-         batch_dyn_bytes(count);
+         (size_t)kListKinds * batch_list_bytes(count);
 }
 
 int batch_kind(const excmg_handle *h, int l) {
@@ -771,71 +777,74 @@ void batch_entry(excmg_handle *h, int problem, int l, const double *f, const dou
   if (E->finest) blocks[kLCopy] = b_blocks_nodes(lv.g);
 }
 
+// a problem's place in its cascade
+enum BatchPhase { kPhStart, kPhSmall, kPhIter64, kPhIter32, kPhOuter, kPhCopy, kPhDone };
+
 int batched_solve(excmg_handle *const *hs, int count, const double *const *f, const double *const *g,
                   double *const *u, char *ws, excmg_stats *stats, double *ms_per_problem) {
   const hipStream_t s = hs[0]->stream;
   const auto t_host = std::chrono::steady_clock::now();
   int S = 0;
   for (int b = 0; b < count; ++b) S = hs[b]->lo.L > S ? hs[b]->lo.L : S;
+  const size_t stat_bytes = align256(sizeof(BatchStatus) * (size_t)count);
   BatchStatus *stat = (BatchStatus *)ws;
-  long long *t0 = (long long *)(ws + align256(sizeof(BatchStatus) * (size_t)count));
-  char *tables = ws + align256(sizeof(BatchStatus) * (size_t)count) + 256;
+  long long *t0 = (long long *)(ws + stat_bytes);
+  char *tables = ws + stat_bytes + 256;
   const size_t tb = batch_table_bytes(count);
-  const size_t pre_off = align256(sizeof(BatchEntry) * (size_t)count);
+  char *lists_dev = tables + (size_t)EXCMG_MAX_LEVELS * tb;
+  const size_t lb = batch_list_bytes(count);
   const int n1 = count + 1;
 
-  // host copy of every step's table, uploaded at once
+  // the entry of every (grid, problem), and its workgroup counts per launch kind
   std::vector<char> host((size_t)S * tb, 0);
-  std::vector<int> totals((size_t)S * kLaunchKinds, 0);
-  std::vector<int> kinds((size_t)S * count, kBNone);
-  int cap_max = 0;
-  for (int st = 0; st < S; ++st) {
-    BatchEntry *E = (BatchEntry *)(host.data() + st * tb);
-    int *pre = (int *)(host.data() + st * tb + pre_off);
-    for (int k = 0; k < kLaunchKinds; ++k) pre[k * n1] = 0;
-    for (int b = 0; b < count; ++b) {
-      int blocks[kLaunchKinds];
-      batch_entry(hs[b], b, st, f[b], g[b], u[b], &E[b], blocks);
-      kinds[(size_t)st * count + b] = E[b].kind;
-      if (E[b].cap > cap_max) cap_max = E[b].cap;
-      for (int k = 0; k < kLaunchKinds; ++k) pre[k * n1 + b + 1] = pre[k * n1 + b] + blocks[k];
-    }
-    for (int k = 0; k < kLaunchKinds; ++k) totals[(size_t)st * kLaunchKinds + k] = pre[k * n1 + count];
-  }
+  std::vector<int> blocks((size_t)S * count * kLaunchKinds, 0);
+  for (int l = 0; l < S; ++l)
+    for (int b = 0; b < count; ++b)
+      batch_entry(hs[b], b, l, f[b], g[b], u[b], (BatchEntry *)(host.data() + l * tb) + b,
+                  &blocks[((size_t)l * count + b) * kLaunchKinds]);
+  int e;
   HIPCHECK(hipMemcpyAsync(tables, host.data(), host.size(), hipMemcpyHostToDevice, s));
   HIPCHECK(hipStreamSynchronize(s));  // the host tables may go out of scope on any early return below
   launch_b_init(stat, count, t0, s);
-  int e = last_error();
-  if (e) return e;
+  if ((e = last_error())) return e;
+  auto entry = [&](int l, int b) { return (const BatchEntry *)(tables + l * tb) + b; };
+  auto nblk = [&](int l, int b, int k) { return blocks[((size_t)l * count + b) * kLaunchKinds + k]; };
 
+  // pinned host memory: the status words, then the launch lists of a round (copied to lists_dev in one piece)
+  if ((e = ensure_pinned(hs[0], stat_bytes + (size_t)kListKinds * lb))) return e;
+  char *lists_host = (char *)hs[0]->pin_host + stat_bytes;
   std::vector<BatchStatus> hstat(count);
   auto read_stat = [&]() -> int {
     return read_record(hs[0], hstat.data(), stat, sizeof(BatchStatus) * (size_t)count);
   };
-  // Prefix arrays of the iteration launches restricted to the problems still iterating, rebuilt after every look at
-  // the status words (converged problems get no workgroups).  Written into pinned host memory behind the status
-  // words and copied to the dynamic block of the batch workspace; every copy is complete before the next rebuild,
-  // which follows a stream synchronisation.
-  int *dynP = (int *)(tables + (size_t)EXCMG_MAX_LEVELS * tb);
-  const size_t stat_bytes = align256(sizeof(BatchStatus) * (size_t)count);
-  if ((e = ensure_pinned(hs[0], stat_bytes + batch_dyn_bytes(count)))) return e;
-  int *dynH = (int *)((char *)hs[0]->pin_host + stat_bytes);
-  auto active_prefix = [&](const int *P_host, int kA, int slot, int kind, const int *kd, int *totA, int *totB) -> int {
-    for (int k = kA; k <= kA + 1; ++k) {
-      int *o = dynH + (size_t)k * n1;
-      const int *src = P_host + (size_t)k * n1;
-      o[0] = 0;
-      for (int b = 0; b < count; ++b) {
-        const bool on = kd[b] == kind && !hstat[b].m[slot].done && !(slot == 1 && hstat[b].m[0].done);
-        o[b + 1] = o[b] + (on ? src[b + 1] - src[b] : 0);
-      }
-    }
-    *totA = dynH[(size_t)kA * n1 + count];
-    *totB = dynH[(size_t)(kA + 1) * n1 + count];
-    HIPCHECK(hipMemcpyAsync(dynP + (size_t)kA * n1, dynH + (size_t)kA * n1, sizeof(int) * 2 * (size_t)n1,
-                            hipMemcpyHostToDevice, s));
-    return EXCMG_OK;
+  struct HostList {
+    const BatchEntry **ent;
+    int *preA, *preB, *aux;
+    int n;
   };
+  HostList hl[kListKinds];
+  BatchList dl[kListKinds][2];
+  for (int k = 0; k < kListKinds; ++k) {
+    char *hb = lists_host + k * lb, *db = lists_dev + k * lb;
+    hl[k].ent = (const BatchEntry **)hb;
+    hl[k].preA = (int *)(hb + sizeof(void *) * count);
+    hl[k].preB = hl[k].preA + n1;
+    hl[k].aux = hl[k].preB + n1;
+    for (int q = 0; q < 2; ++q) {
+      dl[k][q].ent = (const BatchEntry *const *)db;
+      dl[k][q].pre = (const int *)(db + sizeof(void *) * count) + q * n1;
+      dl[k][q].aux = (const int *)(db + sizeof(void *) * count) + 2 * n1;
+    }
+  }
+  auto add = [&](int k, int l, int b, int wa, int wb, int aux) {
+    HostList &L = hl[k];
+    L.ent[L.n] = entry(l, b);
+    L.preA[L.n + 1] = L.preA[L.n] + wa;
+    L.preB[L.n + 1] = L.preB[L.n] + wb;
+    L.aux[L.n] = aux;
+    ++L.n;
+  };
+
   if (stats)
     for (int b = 0; b < count; ++b) {
       memset(&stats[b], 0, sizeof(excmg_stats));
@@ -843,103 +852,153 @@ int batched_solve(excmg_handle *const *hs, int count, const double *const *f, co
       for (int l = 0; l < hs[b]->lo.L; ++l)
         for (int d = 0; d < 3; ++d) stats[b].n[l][d] = hs[b]->lo.lev[l].n[d];
     }
-  std::vector<int> inner_total(count), outer_done(count);
-  int final_status = EXCMG_OK;
-  for (int st = 0; st < S; ++st) {
-    const BatchEntry *T = (const BatchEntry *)(tables + st * tb);
-    const int *P = (const int *)(tables + st * tb + pre_off);
-    const int *P_host = (const int *)(host.data() + st * tb + pre_off);
-    const int *tot = &totals[(size_t)st * kLaunchKinds];
-    const int *kd = &kinds[(size_t)st * count];
-    bool any[4] = {false, false, false, false};
-    for (int b = 0; b < count; ++b) any[kd[b]] = true;
-    launch_b_set_boundary(T, P, count, tot[kLSetB], s);
-    launch_b_exp_finite(T, P, count, tot[kLExp], s);
-    if (any[kBSmall]) {
-      int lds = 0;
-      for (int b = 0; b < count; ++b)
-        if (kd[b] == kBSmall) {
-          const int v = b_small_lds_nodes(hs[b]->lo.lev[st].g);
-          lds = v > lds ? v : lds;
-        }
-      launch_b_small_cg(T, count, lds, stat, s);
-    }
-    launch_b_boundary_terms(T, P, count, tot[kLBterm], s);
-    if ((e = last_error())) return e;
-    if (any[kBCg64]) {
-      launch_b_residual(T, P, count, tot[kLR64], stat, s);
-      const int *PI = P;  // the step's prefix arrays until the first look, then the active ones
-      int tA = tot[kLA64], tB = tot[kLB64];
-      for (int launched = 0, nb = kBatch;;) {
-        for (int q = 0; q < nb; ++q, ++launched) launch_b_iteration(0, T, PI, count, tA, tB, stat, s);
-        if ((e = last_error()) || (e = read_stat())) return e;
-        bool all = true;
-        nb = 1;
-        for (int b = 0; b < count; ++b)
-          if (kd[b] == kBCg64 && !hstat[b].m[0].done) {
-            all = false;
-            const BatchMirror &m = hstat[b].m[0];
-            const int want = next_batch(m.rho, m.rho0, m.iter, m.stop2);
-            nb = want > nb ? want : nb;
-          }
-        if (all) break;
-        if (launched > cap_max + kBatchMax) return EXCMG_ERR_NOCONV;  // the device caps every CG; not reached
-        if ((e = active_prefix(P_host, kLA64, 0, kBCg64, kd, &tA, &tB))) return e;
-        PI = dynP;
-      }
-    }
-    if (any[kBIr]) {
-      int tA32 = 0, tB32 = 0;
-      for (int b = 0; b < count; ++b) inner_total[b] = 0;
-      for (int outer = 0;; ++outer) {
-        launch_b_residual_cast(T, P, count, tot[kLRC], outer, stat, s);
-        if ((e = last_error()) || (e = read_stat())) return e;
-        bool all = true;
-        for (int b = 0; b < count; ++b)
-          if (kd[b] == kBIr && !hstat[b].m[0].done) all = false;
-        if (all) break;
-        if (outer > 64) return EXCMG_ERR_NOCONV;  // the device caps the outer steps at 30; not reached
-        if ((e = active_prefix(P_host, kLA32, 1, kBIr, kd, &tA32, &tB32))) return e;
-        for (int launched = 0, nb = kBatch;;) {
-          for (int q = 0; q < nb; ++q, ++launched) launch_b_iteration(1, T, dynP, count, tA32, tB32, stat, s);
-          if ((e = last_error()) || (e = read_stat())) return e;
-          bool idone = true;
-          nb = 1;
-          for (int b = 0; b < count; ++b)
-            if (kd[b] == kBIr && !hstat[b].m[0].done && !hstat[b].m[1].done) {
-              idone = false;
-              const BatchMirror &m = hstat[b].m[1];
-              const int want = next_batch(m.rho, m.rho0, m.iter, m.stop2);
-              nb = want > nb ? want : nb;
-            }
-          if (idone) break;
-          if (launched > cap_max + kBatchMax) return EXCMG_ERR_NOCONV;
-          if ((e = active_prefix(P_host, kLA32, 1, kBIr, kd, &tA32, &tB32))) return e;
-        }
-        for (int b = 0; b < count; ++b)
-          if (kd[b] == kBIr && !hstat[b].m[0].done) {
-            inner_total[b] += hstat[b].m[1].iter;
-            if (hstat[b].m[1].status == EXCMG_ERR_BREAKDOWN) return EXCMG_ERR_BREAKDOWN;
-          }
-        launch_b_add_correction(T, P, count, tot[kLCorr], s);
-      }
-    }
-    launch_b_copy(T, P, count, tot[kLCopy], s);
-    if ((e = last_error()) || (e = read_stat())) return e;
-    for (int b = 0; b < count; ++b) {
-      if (kd[b] == kBNone) continue;
-      const BatchMirror &m = hstat[b].m[0];
-      if (!isfinite(m.bnorm2)) return EXCMG_ERR_NONFINITE;
-      if (m.status == EXCMG_ERR_BREAKDOWN) return EXCMG_ERR_BREAKDOWN;
-      if (m.status == EXCMG_ERR_NOCONV) final_status = EXCMG_ERR_NOCONV;
-      if (!stats) continue;
+  std::vector<int> lev(count, 0), ph(count, kPhStart), outer(count, 0), inner(count, 0), fresh(count, 0);
+  int final_status = EXCMG_OK, remaining = count;
+  // a problem's grid is finished: record it, then start its next grid (or copy it out)
+  auto finish_grid = [&](int b) -> int {
+    const int l = lev[b];
+    const int kind = batch_kind(hs[b], l);
+    const BatchMirror &m = hstat[b].m[0];
+    if (!isfinite(m.bnorm2)) return EXCMG_ERR_NONFINITE;
+    if (m.status == EXCMG_ERR_BREAKDOWN) return EXCMG_ERR_BREAKDOWN;
+    if (m.status == EXCMG_ERR_NOCONV) final_status = EXCMG_ERR_NOCONV;
+    if (stats) {
       excmg_stats &o = stats[b];
-      const bool exact = (st <= 1);
-      o.iters[st] = kd[b] == kBIr ? inner_total[b] : (exact ? 0 : m.iter);
-      o.ir_outer[st] = kd[b] == kBIr ? m.iter : 0;
-      if (exact) o.dsolve_iters[st] = m.iter;
-      o.relres[st] = m.bnorm2 > 0.0 ? sqrt(m.rho / m.bnorm2) : 0.0;
+      o.iters[l] = kind == kBIr ? inner[b] : (l <= 1 ? 0 : m.iter);
+      o.ir_outer[l] = kind == kBIr ? m.iter : 0;
+      if (l <= 1) o.dsolve_iters[l] = m.iter;
+      o.relres[l] = m.bnorm2 > 0.0 ? sqrt(m.rho / m.bnorm2) : 0.0;
     }
+    if (l == hs[b]->lo.L - 1) {
+      ph[b] = kPhCopy;
+    } else {
+      lev[b] = l + 1;
+      ph[b] = kPhStart;
+    }
+    return EXCMG_OK;
+  };
+
+  int nb64 = kBatch, nb32 = kBatch;
+  for (int round = 0; remaining > 0; ++round) {
+    if (round > 4 * 1000 * 1000) return EXCMG_ERR_NOCONV;  // every device loop is capped; not reached
+    for (int k = 0; k < kListKinds; ++k) {
+      hl[k].n = 0;
+      hl[k].preA[0] = hl[k].preB[0] = 0;
+    }
+    int lds = 0;
+    for (int b = 0; b < count; ++b) {
+      const int l = lev[b];
+      fresh[b] = 0;
+      switch (ph[b]) {
+        case kPhStart: {
+          const int kind = batch_kind(hs[b], l);
+          if (l <= 1) add(kListSetB, l, b, nblk(l, b, kLSetB), 0, 0);
+          else add(kListExp, l, b, nblk(l, b, kLExp), 0, 0);
+          if (kind == kBSmall) {
+            add(kListSmall, l, b, 0, 0, 0);
+            const int v = b_small_lds_nodes(hs[b]->lo.lev[l].g);
+            lds = v > lds ? v : lds;
+            ph[b] = kPhSmall;
+          } else if (kind == kBCg64) {
+            add(kListBterm, l, b, nblk(l, b, kLBterm), 0, 0);
+            add(kListR64, l, b, nblk(l, b, kLR64), 0, 0);
+            add(kListI64, l, b, nblk(l, b, kLA64), nblk(l, b, kLB64), 0);
+            ph[b] = kPhIter64;
+            fresh[b] = 1;
+          } else {
+            add(kListBterm, l, b, nblk(l, b, kLBterm), 0, 0);
+            outer[b] = 0;
+            inner[b] = 0;
+            add(kListRC, l, b, nblk(l, b, kLRC), 0, 0);
+            add(kListI32, l, b, nblk(l, b, kLA32), nblk(l, b, kLB32), 0);
+            ph[b] = kPhIter32;
+            fresh[b] = 1;
+          }
+          break;
+        }
+        case kPhIter64:
+          add(kListI64, l, b, nblk(l, b, kLA64), nblk(l, b, kLB64), 0);
+          break;
+        case kPhIter32:
+          add(kListI32, l, b, nblk(l, b, kLA32), nblk(l, b, kLB32), 0);
+          break;
+        case kPhOuter:  // the inner solve finished: u += d, then the next outer residual and inner solve
+          add(kListCorr, l, b, nblk(l, b, kLCorr), 0, 0);
+          add(kListRC, l, b, nblk(l, b, kLRC), 0, outer[b]);
+          add(kListI32, l, b, nblk(l, b, kLA32), nblk(l, b, kLB32), 0);
+          ph[b] = kPhIter32;
+          fresh[b] = 1;
+          break;
+        case kPhCopy:
+          add(kListCopy, l, b, nblk(l, b, kLCopy), 0, 0);
+          ph[b] = kPhDone;
+          --remaining;
+          break;
+        default:
+          break;
+      }
+    }
+    HIPCHECK(hipMemcpyAsync(lists_dev, lists_host, (size_t)kListKinds * lb, hipMemcpyHostToDevice, s));
+    for (int k = 0; k < kListKinds; ++k)
+      for (int q = 0; q < 2; ++q) {
+        dl[k][q].n = hl[k].n;
+        dl[k][q].total = q ? hl[k].preB[hl[k].n] : hl[k].preA[hl[k].n];
+      }
+    launch_b_copy(dl[kListCopy][0], s);
+    launch_b_set_boundary(dl[kListSetB][0], s);
+    launch_b_exp_finite(dl[kListExp][0], s);
+    launch_b_small_cg(dl[kListSmall][0], lds, stat, s);
+    launch_b_boundary_terms(dl[kListBterm][0], s);
+    launch_b_residual(dl[kListR64][0], stat, s);
+    launch_b_add_correction(dl[kListCorr][0], s);
+    launch_b_residual_cast(dl[kListRC][0], stat, s);
+    const int it = hl[kListI64].n || hl[kListI32].n ? (nb64 > nb32 ? nb64 : nb32) : 0;
+    for (int q = 0; q < it; ++q) {
+      if (q < nb64) launch_b_iteration(0, dl[kListI64][0], dl[kListI64][1], stat, s);
+      if (q < nb32) launch_b_iteration(1, dl[kListI32][0], dl[kListI32][1], stat, s);
+    }
+    if ((e = last_error()) || (e = read_stat())) return e;
+    // move every problem on, and size the next round's iteration batches from the residual decay seen so far
+    nb64 = nb32 = 1;
+    bool any64 = false, any32 = false;
+    for (int b = 0; b < count; ++b) {
+      switch (ph[b]) {
+        case kPhSmall:
+          if ((e = finish_grid(b))) return e;
+          break;
+        case kPhIter64: {
+          const BatchMirror &m = hstat[b].m[0];
+          if (m.done) {
+            if ((e = finish_grid(b))) return e;
+          } else {
+            const int want = fresh[b] ? kBatch : next_batch(m.rho, m.rho0, m.iter, m.stop2);
+            nb64 = want > nb64 ? want : nb64;
+            any64 = true;
+          }
+          break;
+        }
+        case kPhIter32: {
+          const BatchMirror &mo = hstat[b].m[0], &mi = hstat[b].m[1];
+          if (mo.done) {  // the outer residual met the tolerance (or the outer steps ran out)
+            if ((e = finish_grid(b))) return e;
+          } else if (mi.done) {
+            inner[b] += mi.iter;
+            if (mi.status == EXCMG_ERR_BREAKDOWN) return EXCMG_ERR_BREAKDOWN;
+            ++outer[b];
+            ph[b] = kPhOuter;
+          } else {
+            const int want = fresh[b] ? kBatch : next_batch(mi.rho, mi.rho0, mi.iter, mi.stop2);
+            nb32 = want > nb32 ? want : nb32;
+            any32 = true;
+          }
+          break;
+        }
+        default:
+          break;
+      }
+    }
+    if (!any64) nb64 = kBatch;
+    if (!any32) nb32 = kBatch;
   }
   long long t_start = 0;
   if ((e = read_record(hs[0], &t_start, t0, sizeof(long long)))) return e;

@@ -296,22 +296,31 @@ struct BatchEntry {
   double *out;              // the caller's u (finest grid)
 };
 
-// ---- batched launches (t: device table of n entries; pre: the table's prefix arrays, kLaunchKinds x (n + 1)) ----
-// total: pre[kind][n], the workgroups of the flattened launch (nothing is launched when it is 0)
+// ---- batched launches ----
+// A list of entries for one launch: ent[0..n) point into the device tables; flattened launches give entry e the
+// workgroups [pre[e], pre[e+1]) (total = pre[n] workgroups); aux[e] is a per-entry argument (the refinement's outer
+// step for the residual-and-cast launch).  Launches with one workgroup per entry use n workgroups.
+struct BatchList {
+  const BatchEntry *const *ent;
+  const int *pre;
+  const int *aux;
+  int n;
+  int total;
+};
+
 void launch_b_init(BatchStatus *stat, int count, long long *t0, hipStream_t st);
-void launch_b_set_boundary(const BatchEntry *t, const int *pre, int n, int total, hipStream_t st);
-void launch_b_exp_finite(const BatchEntry *t, const int *pre, int n, int total, hipStream_t st);
-void launch_b_small_cg(const BatchEntry *t, int n, int lds_nodes, BatchStatus *stat, hipStream_t st);
+void launch_b_set_boundary(const BatchList &L, hipStream_t st);
+void launch_b_exp_finite(const BatchList &L, hipStream_t st);
+void launch_b_small_cg(const BatchList &L, int lds_nodes, BatchStatus *stat, hipStream_t st);
 int b_small_lds_nodes(const Grid &g);  // LDS (doubles) the small-grid CG of this grid uses, 0 if it does not fit
-void launch_b_boundary_terms(const BatchEntry *t, const int *pre, int n, int total, hipStream_t st);
-void launch_b_residual(const BatchEntry *t, const int *pre, int n, int total, BatchStatus *stat, hipStream_t st);
-void launch_b_residual_cast(const BatchEntry *t, const int *pre, int n, int total, int outer_step,
-                            BatchStatus *stat, hipStream_t st);
-// one CG iteration (pass A, its reduction, pass B, its reduction) of every kBCg64 (fp32 = 0) or kBIr (fp32 = 1) entry
-void launch_b_iteration(int fp32, const BatchEntry *t, const int *pre, int n, int totalA, int totalB,
-                        BatchStatus *stat, hipStream_t st);
-void launch_b_add_correction(const BatchEntry *t, const int *pre, int n, int total, hipStream_t st);
-void launch_b_copy(const BatchEntry *t, const int *pre, int n, int total, hipStream_t st);
+void launch_b_boundary_terms(const BatchList &L, hipStream_t st);
+void launch_b_residual(const BatchList &L, BatchStatus *stat, hipStream_t st);       // + the reduction
+void launch_b_residual_cast(const BatchList &L, BatchStatus *stat, hipStream_t st);  // + the reduction
+// one CG iteration (pass A, its reduction, pass B, its reduction) of the entries of A and B (the same entries, with the
+// workgroup prefixes of pass A and pass B); fp32: the inner FP32 solves of the refinement
+void launch_b_iteration(int fp32, const BatchList &A, const BatchList &B, BatchStatus *stat, hipStream_t st);
+void launch_b_add_correction(const BatchList &L, hipStream_t st);
+void launch_b_copy(const BatchList &L, hipStream_t st);
 // workgroup counts of the flattened launches for one grid
 int b_blocks_exp_finite(const Grid &gw);
 int b_blocks_nodes(const Grid &g);     // set_boundary and copy

@@ -1213,10 +1213,9 @@ __global__ void b_init_kernel(BatchStatus *stat, int count, long long *t0) {
 }
 
 // lds_nodes: the dynamic LDS of the launch, in doubles (entries whose grid does not fit use the global-memory form)
-__global__ __launch_bounds__(DT) void b_small_cg_kernel(const BatchEntry *t, BatchStatus *stat, int lds_nodes) {
+__global__ __launch_bounds__(DT) void b_small_cg_kernel(BatchList L, BatchStatus *stat, int lds_nodes) {
   extern __shared__ double lds_p[];
-  const BatchEntry &E = t[blockIdx.x];
-  if (E.kind != kBSmall) return;
+  const BatchEntry &E = *L.ent[blockIdx.x];
   int cap = E.cap;
   if (E.exact) {
     const long long n = E.g.interior();
@@ -1232,37 +1231,35 @@ __global__ __launch_bounds__(DT) void b_small_cg_kernel(const BatchEntry *t, Bat
   if (threadIdx.x == 0) mirror(E, E.cs, stat, 0, true);
 }
 
-__global__ __launch_bounds__(256) void b_boundary_terms_kernel(const BatchEntry *t, const int *pre, int n) {
-  const int e = find_entry(pre, n, blockIdx.x);
-  const BatchEntry &E = t[e];
+__global__ __launch_bounds__(256) void b_boundary_terms_kernel(BatchList L) {
+  const int e = find_entry(L.pre, L.n, blockIdx.x);
+  const BatchEntry &E = *L.ent[e];
   const Grid g = E.g;
   const int m = max(g.nx, max(g.ny, g.nz)) - 1;
   const int gx = (m + 255) / 256;
-  const int lb = blockIdx.x - pre[e];
+  const int lb = blockIdx.x - L.pre[e];
   boundary_terms_block(E.rs, g, E.r, lb % gx, (lb / gx) % m, lb / (gx * m));
 }
 
-__global__ __launch_bounds__(NT) void b_residual_kernel(const BatchEntry *t, const int *pre, int n) {
+__global__ __launch_bounds__(NT) void b_residual_kernel(BatchList L) {
   __shared__ double tile[2][TY + 2][TX + 2];
   __shared__ double sh[NT / 64];
   __shared__ double tileF[2][TY + 2][TX + 2];
-  const int e = find_entry(pre, n, blockIdx.x);
-  const BatchEntry &E = t[e];
-  const int bid = blockIdx.x - pre[e], nb = pre[e + 1] - pre[e];
+  const int e = find_entry(L.pre, L.n, blockIdx.x);
+  const BatchEntry &E = *L.ent[e];
+  const int bid = blockIdx.x - L.pre[e], nb = L.pre[e + 1] - L.pre[e];
   const Sweep sw = E.swR;
-  PolResid<> pol{E.u, E.r, RhsPart{E.rs, sw.g.nx, sw.g.ny, sw.g.nz, E.r, {0.0, 0.0, 0.0}}};
+  PolResid<true> pol{E.u, E.r, RhsPart{E.rs, sw.g.nx, sw.g.ny, sw.g.nz, E.r, {0.0, 0.0, 0.0}}};
   double a0 = 0.0, a1 = 0.0;
   zmarch<double>(sw, pol, a0, a1, tile, tileF, bid, nb, false);
   const double v[2] = {a0, a1};
   write_partials<2>(v, E.parts, sh, bid, nb);
 }
 
-__global__ __launch_bounds__(FT) void b_finalize_init_kernel(const BatchEntry *t, const int *pre, int n,
-                                                             BatchStatus *stat) {
+__global__ __launch_bounds__(FT) void b_finalize_init_kernel(BatchList L, BatchStatus *stat) {
   __shared__ double sh[FT / 64 + 1];
-  const BatchEntry &E = t[blockIdx.x];
-  if (E.kind != kBCg64) return;
-  const int nb = pre[blockIdx.x + 1] - pre[blockIdx.x];
+  const BatchEntry &E = *L.ent[blockIdx.x];
+  const int nb = L.pre[blockIdx.x + 1] - L.pre[blockIdx.x];
   const double rho = fixed_sum(E.parts, nb, sh);
   const double bb = fixed_sum(E.parts + nb, nb, sh);
   if (threadIdx.x == 0) {
@@ -1271,52 +1268,46 @@ __global__ __launch_bounds__(FT) void b_finalize_init_kernel(const BatchEntry *t
   }
 }
 
-// FP64 residual and its FP32 copy for the outer step outer_step of the refinement; entries whose outer loop has
-// already finished (outer_step > 0 and done) are skipped
-__global__ __launch_bounds__(NT) void b_residual_cast_kernel(const BatchEntry *t, const int *pre, int n,
-                                                             int outer_step) {
+// FP64 residual and its FP32 copy for outer step aux[e] of the refinement
+__global__ __launch_bounds__(NT) void b_residual_cast_kernel(BatchList L) {
   __shared__ double tile[2][TY + 2][TX + 2];
   __shared__ double sh[NT / 64];
   __shared__ double tileF[2][TY + 2][TX + 2];
-  const int e = find_entry(pre, n, blockIdx.x);
-  const BatchEntry &E = t[e];
-  if (outer_step > 0 && E.cs->done) return;
-  const int bid = blockIdx.x - pre[e], nb = pre[e + 1] - pre[e];
+  const int e = find_entry(L.pre, L.n, blockIdx.x);
+  const BatchEntry &E = *L.ent[e];
+  const int bid = blockIdx.x - L.pre[e], nb = L.pre[e + 1] - L.pre[e];
   const Sweep sw = E.swR;
-  PolResidCast<> pol{E.u, E.g32, E.r32, E.d32, RhsPart{E.rs, sw.g.nx, sw.g.ny, sw.g.nz, E.r, {0.0, 0.0, 0.0}}, 0.0};
+  PolResidCast<true> pol{E.u, E.g32, E.r32, E.d32, RhsPart{E.rs, sw.g.nx, sw.g.ny, sw.g.nz, E.r, {0.0, 0.0, 0.0}}, 0.0};
   double a0 = 0.0, a1 = 0.0;
   zmarch<double>(sw, pol, a0, a1, tile, tileF, bid, nb, false);
   const double v[3] = {a0, a1, pol.acc2};
   write_partials<3>(v, E.parts, sh, bid, nb);
 }
 
-__global__ __launch_bounds__(FT) void b_finalize_ir_kernel(const BatchEntry *t, const int *pre, int n,
-                                                           int outer_step, BatchStatus *stat) {
+__global__ __launch_bounds__(FT) void b_finalize_ir_kernel(BatchList L, BatchStatus *stat) {
   __shared__ double sh[FT / 64 + 1];
-  const BatchEntry &E = t[blockIdx.x];
-  if (E.kind != kBIr) return;
-  if (outer_step > 0 && E.cs->done) return;
-  const int nb = pre[blockIdx.x + 1] - pre[blockIdx.x];
+  const BatchEntry &E = *L.ent[blockIdx.x];
+  const int nb = L.pre[blockIdx.x + 1] - L.pre[blockIdx.x];
   const double r64 = fixed_sum(E.parts, nb, sh);
   const double bb = fixed_sum(E.parts + nb, nb, sh);
   const double r32 = fixed_sum(E.parts + 2 * nb, nb, sh);
   if (threadIdx.x == 0) {
-    state_ir(E.cs, E.cs2, r64, bb, r32, E.tol, E.eta, outer_step, E.max_outer, E.cap);
+    state_ir(E.cs, E.cs2, r64, bb, r32, E.tol, E.eta, L.aux[blockIdx.x], E.max_outer, E.cap);
     mirror(E, E.cs, stat, 0, true);
     mirror(E, E.cs2, stat, 1, false);
   }
 }
 
 template <typename T>
-__global__ __launch_bounds__(NT) void b_pass_a_kernel(const BatchEntry *t, const int *pre, int n) {
+__global__ __launch_bounds__(NT) void b_pass_a_kernel(BatchList L) {
   constexpr bool F = sizeof(T) == 4;
   __shared__ T tile[2][TY + 2][TX + 2];
   __shared__ double sh[NT / 64];
-  const int e = find_entry(pre, n, blockIdx.x);
-  const BatchEntry &E = t[e];
+  const int e = find_entry(L.pre, L.n, blockIdx.x);
+  const BatchEntry &E = *L.ent[e];
   const CgState *cs = F ? E.cs2 : E.cs;
   if (cs->done) return;
-  const int bid = blockIdx.x - pre[e], nb = pre[e + 1] - pre[e];
+  const int bid = blockIdx.x - L.pre[e], nb = L.pre[e + 1] - L.pre[e];
   const int it = cs->iter;
   T *p0, *p1;
   const T *r;
@@ -1325,7 +1316,7 @@ __global__ __launch_bounds__(NT) void b_pass_a_kernel(const BatchEntry *t, const
   } else {
     r = E.r; p0 = E.p0; p1 = E.p1;
   }
-  PolA<T> pol;
+  PolA<T, true> pol;  // the batch's working set is far larger than the caches: streaming policy
   pol.r = r;
   pol.pnew = (it & 1) ? p1 : p0;
   pol.pold = (it & 1) ? p0 : p1;
@@ -1339,17 +1330,17 @@ __global__ __launch_bounds__(NT) void b_pass_a_kernel(const BatchEntry *t, const
 }
 
 template <typename T>
-__global__ __launch_bounds__(NT) void b_pass_b_kernel(const BatchEntry *t, const int *pre, int n) {
+__global__ __launch_bounds__(NT) void b_pass_b_kernel(BatchList L) {
   constexpr bool F = sizeof(T) == 4;
   __shared__ T tile[2][TY + 2][TX + 2];
   __shared__ double sh[NT / 64];
-  const int e = find_entry(pre, n, blockIdx.x);
-  const BatchEntry &E = t[e];
+  const int e = find_entry(L.pre, L.n, blockIdx.x);
+  const BatchEntry &E = *L.ent[e];
   const CgState *cs = F ? E.cs2 : E.cs;
   if (cs->done) return;
-  const int bid = blockIdx.x - pre[e], nb = pre[e + 1] - pre[e];
+  const int bid = blockIdx.x - L.pre[e], nb = L.pre[e + 1] - L.pre[e];
   const int it = cs->iter;
-  PolB<T> pol;
+  PolB<T, true> pol;
   if constexpr (F) {
     pol.p = (it & 1) ? E.p32b : E.p32a;
     pol.u = E.d32;
@@ -1371,14 +1362,12 @@ __global__ __launch_bounds__(NT) void b_pass_b_kernel(const BatchEntry *t, const
 
 // reduction after pass A (PASS 0) or pass B (PASS 1) of the FP64 CG (F = 0) or the FP32 inner CG (F = 1)
 template <int PASS, int F>
-__global__ __launch_bounds__(FT) void b_finalize_pass_kernel(const BatchEntry *t, const int *pre, int n,
-                                                             BatchStatus *stat) {
+__global__ __launch_bounds__(FT) void b_finalize_pass_kernel(BatchList L, BatchStatus *stat) {
   __shared__ double sh[FT / 64 + 1];
-  const BatchEntry &E = t[blockIdx.x];
-  if (E.kind != (F ? kBIr : kBCg64)) return;
+  const BatchEntry &E = *L.ent[blockIdx.x];
   CgState *cs = F ? E.cs2 : E.cs;
   if (cs->done) return;
-  const int nb = pre[blockIdx.x + 1] - pre[blockIdx.x];
+  const int nb = L.pre[blockIdx.x + 1] - L.pre[blockIdx.x];
   const double v = fixed_sum(E.parts, nb, sh);
   if (threadIdx.x == 0) {
     if (PASS == 0) state_after_a(cs, v);
@@ -1387,13 +1376,12 @@ __global__ __launch_bounds__(FT) void b_finalize_pass_kernel(const BatchEntry *t
   }
 }
 
-__global__ __launch_bounds__(256) void b_add_correction_kernel(const BatchEntry *t, const int *pre, int n) {
-  const int e = find_entry(pre, n, blockIdx.x);
-  const BatchEntry &E = t[e];
-  if (E.cs->done) return;
+__global__ __launch_bounds__(256) void b_add_correction_kernel(BatchList L) {
+  const int e = find_entry(L.pre, L.n, blockIdx.x);
+  const BatchEntry &E = *L.ent[e];
   const Grid g = E.g;
   const int gx = (g.nx - 1 + 255) / 256, gy = g.ny - 1;
-  const int lb = blockIdx.x - pre[e];
+  const int lb = blockIdx.x - L.pre[e];
   add_correction_block(g, E.u, E.g32, E.d32, lb % gx, (lb / gx) % gy, lb / (gx * gy));
 }
 
@@ -1572,51 +1560,45 @@ void launch_b_init(BatchStatus *stat, int count, long long *t0, hipStream_t st) 
   b_init_kernel<<<(count + 255) / 256, 256, 0, st>>>(stat, count, t0);
 }
 
-void launch_b_small_cg(const BatchEntry *t, int n, int lds_nodes, BatchStatus *stat, hipStream_t st) {
-  b_small_cg_kernel<<<n, DT, (size_t)lds_nodes * sizeof(double), st>>>(t, stat, lds_nodes);
+void launch_b_small_cg(const BatchList &L, int lds_nodes, BatchStatus *stat, hipStream_t st) {
+  if (L.n > 0) b_small_cg_kernel<<<L.n, DT, (size_t)lds_nodes * sizeof(double), st>>>(L, stat, lds_nodes);
 }
 
 int b_small_lds_nodes(const Grid &g) { return small_fits_lds(g) ? (int)small_lds_nodes(g) : 0; }
 
-void launch_b_boundary_terms(const BatchEntry *t, const int *pre, int n, int total, hipStream_t st) {
-  if (total > 0) b_boundary_terms_kernel<<<total, 256, 0, st>>>(t, pre + kLBterm * (n + 1), n);
+void launch_b_boundary_terms(const BatchList &L, hipStream_t st) {
+  if (L.total > 0) b_boundary_terms_kernel<<<L.total, 256, 0, st>>>(L);
 }
 
-void launch_b_residual(const BatchEntry *t, const int *pre, int n, int total, BatchStatus *stat, hipStream_t st) {
-  if (total <= 0) return;
-  const int *p = pre + kLR64 * (n + 1);
-  b_residual_kernel<<<total, NT, 0, st>>>(t, p, n);
-  b_finalize_init_kernel<<<n, FT, 0, st>>>(t, p, n, stat);
+void launch_b_residual(const BatchList &L, BatchStatus *stat, hipStream_t st) {
+  if (L.total <= 0) return;
+  b_residual_kernel<<<L.total, NT, 0, st>>>(L);
+  b_finalize_init_kernel<<<L.n, FT, 0, st>>>(L, stat);
 }
 
-void launch_b_residual_cast(const BatchEntry *t, const int *pre, int n, int total, int outer_step,
-                            BatchStatus *stat, hipStream_t st) {
-  if (total <= 0) return;
-  const int *p = pre + kLRC * (n + 1);
-  b_residual_cast_kernel<<<total, NT, 0, st>>>(t, p, n, outer_step);
-  b_finalize_ir_kernel<<<n, FT, 0, st>>>(t, p, n, outer_step, stat);
+void launch_b_residual_cast(const BatchList &L, BatchStatus *stat, hipStream_t st) {
+  if (L.total <= 0) return;
+  b_residual_cast_kernel<<<L.total, NT, 0, st>>>(L);
+  b_finalize_ir_kernel<<<L.n, FT, 0, st>>>(L, stat);
 }
 
-void launch_b_iteration(int fp32, const BatchEntry *t, const int *pre, int n, int totalA, int totalB,
-                        BatchStatus *stat, hipStream_t st) {
-  if (totalA <= 0 || totalB <= 0) return;
+void launch_b_iteration(int fp32, const BatchList &A, const BatchList &B, BatchStatus *stat, hipStream_t st) {
+  if (A.total <= 0 || B.total <= 0) return;
   if (fp32) {
-    const int *pa = pre + kLA32 * (n + 1), *pb = pre + kLB32 * (n + 1);
-    b_pass_a_kernel<float><<<totalA, NT, 0, st>>>(t, pa, n);
-    b_finalize_pass_kernel<0, 1><<<n, FT, 0, st>>>(t, pa, n, stat);
-    b_pass_b_kernel<float><<<totalB, NT, 0, st>>>(t, pb, n);
-    b_finalize_pass_kernel<1, 1><<<n, FT, 0, st>>>(t, pb, n, stat);
+    b_pass_a_kernel<float><<<A.total, NT, 0, st>>>(A);
+    b_finalize_pass_kernel<0, 1><<<A.n, FT, 0, st>>>(A, stat);
+    b_pass_b_kernel<float><<<B.total, NT, 0, st>>>(B);
+    b_finalize_pass_kernel<1, 1><<<B.n, FT, 0, st>>>(B, stat);
   } else {
-    const int *pa = pre + kLA64 * (n + 1), *pb = pre + kLB64 * (n + 1);
-    b_pass_a_kernel<double><<<totalA, NT, 0, st>>>(t, pa, n);
-    b_finalize_pass_kernel<0, 0><<<n, FT, 0, st>>>(t, pa, n, stat);
-    b_pass_b_kernel<double><<<totalB, NT, 0, st>>>(t, pb, n);
-    b_finalize_pass_kernel<1, 0><<<n, FT, 0, st>>>(t, pb, n, stat);
+    b_pass_a_kernel<double><<<A.total, NT, 0, st>>>(A);
+    b_finalize_pass_kernel<0, 0><<<A.n, FT, 0, st>>>(A, stat);
+    b_pass_b_kernel<double><<<B.total, NT, 0, st>>>(B);
+    b_finalize_pass_kernel<1, 0><<<B.n, FT, 0, st>>>(B, stat);
   }
 }
 
-void launch_b_add_correction(const BatchEntry *t, const int *pre, int n, int total, hipStream_t st) {
-  if (total > 0) b_add_correction_kernel<<<total, 256, 0, st>>>(t, pre + kLCorr * (n + 1), n);
+void launch_b_add_correction(const BatchList &L, hipStream_t st) {
+  if (L.total > 0) b_add_correction_kernel<<<L.total, 256, 0, st>>>(L);
 }
 
 void launch_publish(const void *src, void *dst, size_t bytes, hipStream_t st) {

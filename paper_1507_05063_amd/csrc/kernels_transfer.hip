@@ -276,28 +276,28 @@ __device__ __forceinline__ int find_entry_t(const int *pre, int n, int b) {
 }
 
 // boundary values and zero interior on grids 0 and 1
-__global__ __launch_bounds__(256) void b_set_boundary_kernel(const BatchEntry *t, const int *pre, int n) {
-  const int e = find_entry_t(pre, n, blockIdx.x);
-  const BatchEntry &E = t[e];
+__global__ __launch_bounds__(256) void b_set_boundary_kernel(BatchList L) {
+  const int e = find_entry_t(L.pre, L.n, blockIdx.x);
+  const BatchEntry &E = *L.ent[e];
   const int gx = (E.g.nx + 1 + 255) / 256, gy = E.g.ny + 1;
-  const int lb = blockIdx.x - pre[e];
+  const int lb = blockIdx.x - L.pre[e];
   set_boundary_block(E.gd, E.gb, E.rs.s, E.g, E.u, 1, lb % gx, (lb / gx) % gy, lb / (gx * gy));
 }
 
-__global__ __launch_bounds__(256) void b_copy_kernel(const BatchEntry *t, const int *pre, int n) {
-  const int e = find_entry_t(pre, n, blockIdx.x);
-  const BatchEntry &E = t[e];
+__global__ __launch_bounds__(256) void b_copy_kernel(BatchList L) {
+  const int e = find_entry_t(L.pre, L.n, blockIdx.x);
+  const BatchEntry &E = *L.ent[e];
   const int gx = (E.g.nx + 1 + 255) / 256, gy = E.g.ny + 1;
-  const int lb = blockIdx.x - pre[e];
+  const int lb = blockIdx.x - L.pre[e];
   copy_block(E.g, E.u, E.gd, E.out, lb % gx, (lb / gx) % gy, lb / (gx * gy));
 }
 
-__global__ __launch_bounds__(ET) void b_exp_finite_kernel(const BatchEntry *t, const int *pre, int n) {
-  const int e = find_entry_t(pre, n, blockIdx.x);
-  const BatchEntry &E = t[e];
+__global__ __launch_bounds__(ET) void b_exp_finite_kernel(BatchList L) {
+  const int e = find_entry_t(L.pre, L.n, blockIdx.x);
+  const BatchEntry &E = *L.ent[e];
   const int ncx = E.g.nx / 8, ncy = E.g.ny / 8;
   const int gx = (ncx + CXN - 1) / CXN;
-  const int lb = blockIdx.x - pre[e];
+  const int lb = blockIdx.x - L.pre[e];
   exp_finite_block(E.g2, E.u2, E.g4, E.u4, E.gd, E.gb, E.rs.s, E.g, E.u, lb % gx, (lb / gx) % ncy, lb / (gx * ncy),
                    false);
 }
@@ -353,16 +353,16 @@ int b_blocks_exp_finite(const Grid &gw) {
   return ((ncx + CXN - 1) / CXN) * ncy * ncz;
 }
 
-void launch_b_set_boundary(const BatchEntry *t, const int *pre, int n, int total, hipStream_t st) {
-  if (total > 0) b_set_boundary_kernel<<<total, 256, 0, st>>>(t, pre + kLSetB * (n + 1), n);
+void launch_b_set_boundary(const BatchList &L, hipStream_t st) {
+  if (L.total > 0) b_set_boundary_kernel<<<L.total, 256, 0, st>>>(L);
 }
 
-void launch_b_exp_finite(const BatchEntry *t, const int *pre, int n, int total, hipStream_t st) {
-  if (total > 0) b_exp_finite_kernel<<<total, ET, 0, st>>>(t, pre + kLExp * (n + 1), n);
+void launch_b_exp_finite(const BatchList &L, hipStream_t st) {
+  if (L.total > 0) b_exp_finite_kernel<<<L.total, ET, 0, st>>>(L);
 }
 
-void launch_b_copy(const BatchEntry *t, const int *pre, int n, int total, hipStream_t st) {
-  if (total > 0) b_copy_kernel<<<total, 256, 0, st>>>(t, pre + kLCopy * (n + 1), n);
+void launch_b_copy(const BatchList &L, hipStream_t st) {
+  if (L.total > 0) b_copy_kernel<<<L.total, 256, 0, st>>>(L);
 }
 
 }  // namespace excmg
