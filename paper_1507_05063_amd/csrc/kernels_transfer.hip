@@ -143,14 +143,16 @@ __device__ void exp_finite_block(const Grid &g2, const double *__restrict__ u2, 
     Wx[c][b][xf] = v;
   }
   __syncthreads();
-  // 3c. z and 4. write, one thread per (xf, yf) column: a workgroup owns offsets [0,8) on each axis, plus offset 8 at
-  // the grid's far faces
-  const bool lastx = (cx0 + nc == ncx), lasty = (cj == ncy - 1), lastz = (ck == ncz - 1);
-  const int ox = lastx ? nfx : nfx - 1, oy = lasty ? 9 : 8, oz = lastz ? 9 : 8;
+  // 3c. z and 4. write, one thread per (xf, yf) column.  Along x a workgroup writes offsets 1..8nc of its slab (the
+  // slab's first node, offset 0, is the previous workgroup's last), so that with the grid's interior aligned to
+  // 128-byte lines every row segment it stores is whole lines: 64 consecutive lanes take offsets 1..64.  The first
+  // workgroup also writes offset 0 (the boundary).  Along y and z it owns offsets [0, 8), plus offset 8 at the far
+  // faces.
+  const bool lasty = (cj == ncy - 1), lastz = (ck == ncz - 1);
+  const int oy = lasty ? 9 : 8, oz = lastz ? 9 : 8;
   const int gi0 = 8 * cx0, gj0 = 8 * cj, gk0 = 8 * ck;
-  for (int e = tid; e < 9 * EXF; e += ET) {
-    const int xf = e % EXF, yf = e / EXF;
-    if (xf >= ox || yf >= oy) continue;
+  const int xhi = 8 * nc;
+  auto column = [&](int xf, int yf) {
     const int gi = gi0 + xf, gj = gj0 + yf;
     // y: the five z layers of this column, from the x-interpolated values (known at even yf, quartic at odd yf)
     double a[5];
@@ -173,7 +175,13 @@ __device__ void exp_finite_block(const Grid &g2, const double *__restrict__ u2, 
       if (nt) __builtin_nontemporal_store(v, &w[gw.at(gi, gj, gk)]);
       else w[gw.at(gi, gj, gk)] = v;
     }
+  };
+  for (int e = tid; e < 64 * 9; e += ET) {
+    const int xf = 1 + (e & 63), yf = e >> 6;
+    if (xf <= xhi && yf < oy) column(xf, yf);
   }
+  if (gi0 == 0)
+    for (int yf = tid; yf < oy; yf += ET) column(0, yf);
 }
 
 __global__ __launch_bounds__(ET) void exp_finite_kernel(Grid g2, const double *__restrict__ u2, Grid g4,
