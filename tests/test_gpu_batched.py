@@ -141,3 +141,46 @@ def test_batch96_fp32_ir_against_oracle(ex, orc, batch96, b):
         mask = synth.boundary_mask(n)
         assert np.array_equal(us[q][mask], g[mask])
         assert ms[q] > 0.0
+
+
+def test_batched_single_and_mixed_precision(ex, orc):
+    """A batch of one, and a batch mixing FP64 and FP32-refinement problems of different level counts."""
+    n, nc, p = MIXED[1]
+    solvers, fs, gs, data, us, stats, ms = _run(ex, [MIXED[1]], 1e-10, ex.FP64)
+    f, g, _, _ = data[0]
+    ref = orc.excmg(f, g, p.box, nc, 1e-10, fixed_iters=np.array(stats[0]["iters"], dtype=np.int32))
+    assert rel2(host(us[0]), ref["u"]) <= 1e-12
+    cases = [(n, nc, p), ((128, 128, 128), (4, 4, 4), synth.smooth(2)), MIXED[3]]
+    precs = [ex.FP64, ex.FP32_IR, ex.FP32_IR]
+    solvers, fs, gs, data = [], [], [], []
+    for (n_, nc_, p_), pr in zip(cases, precs):
+        f_, g_, u_ = synth.sample(p_, n_)
+        solvers.append(ex.Solver(n_, p_.box, 1e-10, n_coarse=nc_, precision=pr))
+        fs.append(dev(f_))
+        gs.append(dev(g_))
+        data.append((f_, g_, u_, p_))
+    us, stats, ms = ex.solve_batched(solvers, fs, gs)
+    # the 128^3 FP32-refinement problem refines in FP32 on its finest grid only (the coarser ones are < 2^20 unknowns)
+    assert stats[1]["ir_outer"][-1] >= 1 and all(o == 0 for o in stats[1]["ir_outer"][:-1])
+    for (n_, nc_, p_), s_, (f_, g_, u_, _), ub, st in zip(cases, solvers, data, us, stats):
+        for l in range(2, st["levels"]):
+            assert st["relres"][l] <= 1e-10
+        ref = orc.excmg(f_, g_, p_.box, s_.n_coarse, 1e-10)
+        disc = max(np.max(np.abs(ref["u"] - u_)), 1e-14)
+        assert np.max(np.abs(host(ub) - ref["u"])) <= 0.5 * disc
+
+
+def test_batched_errors(ex):
+    """An iteration cap is reported as EXCMG_ERR_NOCONV with every output written; a NaN in one problem's data stops
+    the batch with EXCMG_ERR_NONFINITE."""
+    n, nc, p = MIXED[1]
+    f, g, _ = synth.sample(p, n)
+    s1 = ex.Solver(n, p.box, 1e-14, n_coarse=nc, max_iters=3)
+    s2 = ex.Solver(n, p.box, 1e-10, n_coarse=nc)
+    us, stats, ms = ex.solve_batched([s1, s2], [dev(f), dev(f)], [dev(g), dev(g)], allow_noconv=True)
+    assert stats[0]["iters"][-1] == 3 and stats[1]["relres"][-1] <= 1e-10
+    bad = f.copy()
+    bad[3, 4, 5] = np.nan
+    with pytest.raises(ex.ExcmgError) as e:
+        ex.solve_batched([s2, s2.__class__(n, p.box, 1e-10, n_coarse=nc)], [dev(f), dev(bad)], [dev(g), dev(g)])
+    assert e.value.code == -3
