@@ -188,6 +188,79 @@ __global__ __launch_bounds__(XW) void grad_x_kernel(Grid gu, const double *__res
   }
 }
 
+// x lines, one wavefront per line (grids of at most kXWaveMax cells along x): the line is read into LDS with
+// contiguous loads, and lane l produces the XS unknowns t0 = 1 + XS l (+ 64 XS per pass) from its own windows: the
+// forward elimination starts XWIN unknowns before t0 with d = 0 in place of the true d there, the back substitution
+// starts XWIN unknowns after the lane's last one with v = d there; both starting errors are damped below
+// 0.268^32 = 5e-19 of the values by the time they reach the lane's unknowns, so the result is the Thomas solution to
+// rounding (as in line_solve).  The factors 1/m_t reach their limit 1/(2 + sqrt 3) to the last bit by t = 14, so the
+// first kInvM of them sit in LDS and the rest equal the last of those.  The results go back through LDS and out with
+// contiguous stores.
+constexpr int XS = 8, XWIN = 32, kInvM = 32;
+constexpr int kXWaveMax = 4095;
+
+__global__ __launch_bounds__(64) void grad_x_wave_kernel(Grid gu, const double *__restrict__ u, Grid gd, double *ux,
+                                                         double hx, const double *__restrict__ inv_m) {
+  extern __shared__ double lds[];
+  __shared__ double im[kInvM + 1];
+  const int N = gu.nx, M = N - 1;
+  // LDS position of unknown t: one pad word per XS, so that the lanes (XS apart) hit different banks
+  auto P = [](int t) { return t + (t >> 3); };
+  double *lu = lds, *lo = lds + P(N) + 1;
+  const int L = blockIdx.x;
+  const int j = L % (gu.ny + 1), k = L / (gu.ny + 1);
+  const long long b = gu.at(0, j, k), ob = gd.at(0, j, k);
+  for (int t = threadIdx.x; t <= N; t += 64) lu[P(t)] = u[b + t];
+  for (int t = threadIdx.x; t <= kInvM; t += 64) im[t] = (t >= 1 && t <= M) ? inv_m[t] : (t > M ? inv_m[M] : 0.0);
+  __syncthreads();
+  const double v0 = end0(lu[P(0)], lu[P(1)], lu[P(2)], lu[P(3)], lu[P(4)], hx);
+  const double vN = -end0(lu[P(N)], lu[P(N - 1)], lu[P(N - 2)], lu[P(N - 3)], lu[P(N - 4)], hx);
+  const double s3 = 3.0 / hx;
+  auto rhs = [&](int t) {
+    double r = s3 * (lu[P(t + 1)] - lu[P(t - 1)]);
+    if (t == 1) r -= v0;
+    if (t == M) r -= vN;
+    return r;
+  };
+  auto invm = [&](int t) { return im[t < kInvM ? t : kInvM]; };
+  if (threadIdx.x == 0) {
+    lo[P(0)] = v0;
+    lo[P(N)] = vN;
+  }
+  for (int base = 1; base <= M; base += 64 * XS) {
+    const int t0 = base + threadIdx.x * XS;
+    if (t0 <= M) {
+      const int te = t0 + XS - 1 + XWIN > M ? M : t0 + XS - 1 + XWIN;
+      double d = 0.0;
+#pragma unroll
+      for (int q = -XWIN; q < 0; ++q) {
+        const int t = t0 + q;
+        if (t >= 1) d = (rhs(t) - d) * invm(t);
+      }
+      double dk[XS + XWIN];
+#pragma unroll
+      for (int q = 0; q < XS + XWIN; ++q) {
+        const int t = t0 + q;
+        if (t <= te) {
+          d = (rhs(t) - d) * invm(t);
+          dk[q] = d;
+        }
+      }
+      double v = 0.0;
+#pragma unroll
+      for (int q = XS + XWIN - 1; q >= 0; --q) {
+        const int t = t0 + q;
+        if (t <= te) {
+          v = (t == M) ? dk[q] : dk[q] - invm(t) * v;
+          if (q < XS) lo[P(t)] = v;
+        }
+      }
+    }
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t <= N; t += 64) __builtin_nontemporal_store(lo[P(t)], &ux[ob + t]);
+}
+
 // y and z lines: one thread per line, consecutive threads on consecutive x, so every step of the sweeps is a
 // coalesced row access.
 __global__ __launch_bounds__(64) void grad_y_kernel(Grid gu, const double *__restrict__ u, Grid gd, double *uy,
@@ -212,7 +285,11 @@ void launch_gradient(const Grid &gu, const double *u, const Grid &gd, double *ux
                      double hy, double hz, const double *inv_m_x, const double *inv_m_y, const double *inv_m_z,
                      hipStream_t st) {
   const int nlines = (gu.ny + 1) * (gu.nz + 1);
-  grad_x_kernel<<<(nlines + XW - 1) / XW, XW, 0, st>>>(gu, u, gd, ux, hx, inv_m_x);
+  if (gu.nx <= kXWaveMax)
+    grad_x_wave_kernel<<<nlines, 64, 2 * (size_t)(gu.nx + gu.nx / 8 + 2) * sizeof(double), st>>>(gu, u, gd, ux, hx,
+                                                                                                inv_m_x);
+  else
+    grad_x_kernel<<<(nlines + XW - 1) / XW, XW, 0, st>>>(gu, u, gd, ux, hx, inv_m_x);
   grad_y_kernel<<<dim3((gu.nx + 1 + 63) / 64, gu.nz + 1), 64, 0, st>>>(gu, u, gd, uy, hy, inv_m_y);
   grad_z_kernel<<<dim3((gu.nx + 1 + 63) / 64, gu.ny + 1), 64, 0, st>>>(gu, u, gd, uz, hz, inv_m_z);
 }
