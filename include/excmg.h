@@ -163,8 +163,8 @@ int excmg_solve_batched(excmg_handle *const *hs, int32_t count, const double *co
 
 /* Autotuner (host call, device work on the handle's stream): times the two CG sweep kernels of every relaxed grid
  * (FP64, and FP32 where EXCMG_FP32_IR relaxes in FP32) for each z-chunk length in {2, 4, ..., 64} planes per
- * workgroup, each prefetch depth (2 or 3 planes of loads in flight per thread) and each cache policy (ordinary or
- * non-temporal loads and stores of the data a sweep touches once), on the handle's own work buffers (no caller array
+ * workgroup, each prefetch depth (2, 3, 4 or 6 planes of loads in flight per thread) and each cache policy
+ * (ordinary or non-temporal loads and stores of the data a sweep touches once), on the handle's own work buffers (no caller array
  * is read or written), and keeps the fastest per grid and kernel for every later call on this handle.
  * zc_out, depth_out (host, nullable, 4 * levels entries each): per grid, pass A and pass B in FP64, then in FP32 (0
  * where the grid is not relaxed that way): the chunk, and the depth plus 10 if the non-temporal policy won.

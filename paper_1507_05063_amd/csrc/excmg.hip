@@ -1184,6 +1184,8 @@ int excmg_autotune(excmg_handle *h, int32_t *zc_out, int32_t *depth_out) {
   const hipStream_t s = h->stream;
   Layout &lo = h->lo;
   static const int cand[] = {2, 4, 8, 16, 32, 64};
+  static const int depths[] = {2, 3, 4, 6};
+  constexpr int kVar = 2 * (int)(sizeof(depths) / sizeof(depths[0]));  // depth x cache policy
   hipEvent_t ea, eb;
   HIPCHECK(hipEventCreate(&ea));
   HIPCHECK(hipEventCreate(&eb));
@@ -1197,8 +1199,8 @@ int excmg_autotune(excmg_handle *h, int32_t *zc_out, int32_t *depth_out) {
       for (int pass = 0; pass < 2 && rc == EXCMG_OK; ++pass) {
         float best = 1e30f;
         Sweep bsw = prec ? (pass ? lv.swB32 : lv.swA32) : (pass ? lv.swB : lv.swA);
-        for (int ci = 0; ci < 4 * (int)(sizeof(cand) / sizeof(cand[0])); ++ci) {
-          const int zc = cand[ci / 4], depth = 2 + ci % 2, nt = (ci / 2) % 2;
+        for (int ci = 0; ci < kVar * (int)(sizeof(cand) / sizeof(cand[0])); ++ci) {
+          const int zc = cand[ci / kVar], depth = depths[(ci % kVar) / 2], nt = ci % 2;
           if (zc > 2 * (g.nz - 1) + 2) break;
           const Sweep sw = make_sweep(g, lv.st, zc, depth, nt);
           if (3LL * sweep_blocks(sw) > lo.npart) continue;

@@ -163,7 +163,8 @@ struct Sweep {
   Grid g;
   Stencil st;
   int zc, ntx, nty, nzc;
-  int depth;  // planes of loads in flight per thread in the z-march (2 or 3; the pass and residual sweeps)
+  int depth;  // planes of loads in flight per thread in the z-march (2, 3, 4 or 6 in the CG passes; 2 or 3 in
+              // the residual sweeps)
   int nt;     // 1: data read or written once per sweep uses non-temporal (streaming) loads and stores
 };
 

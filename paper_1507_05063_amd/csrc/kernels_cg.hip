@@ -23,6 +23,7 @@
 #include <math.h>
 
 #include <type_traits>
+#include <utility>
 
 #include "excmg_internal.h"
 
@@ -65,6 +66,11 @@ __device__ __forceinline__ double block_sum(double v, double *sh) {
 constexpr int TX = 64;
 constexpr int TY = 4;
 constexpr int NT = TX * TY;
+// Rows of one LDS plane buffer: the (TX+2) x (TY+2) tile with its halo, padded so that every fetch slot of the
+// workgroup (a whole number of slots per thread) has an entry and the staging stores need no bounds test.
+constexpr int kTileRows = ((TX + 2) * (TY + 2) + NT - 1) / NT * NT / (TX + 2) + 1;
+
+__device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
 // Loads and stores of data a sweep touches once: non-temporal (streaming) when NTP, so that they do not displace the
 // operand's halo lines, which neighbouring tiles read again, from the caches.
@@ -79,12 +85,30 @@ __device__ __forceinline__ void st1(T v, T *p) {
   else *p = v;
 }
 
-// The z-march.  P supplies operand(idx) (the stencil operand at an interior node, idx in grid g),
+// f(integral_constant<int, 0>), ..., f(integral_constant<int, N - 1>), in that order
+template <typename F, int... Q>
+__device__ __forceinline__ void static_for_impl(F &&f, std::integer_sequence<int, Q...>) {
+  (f(std::integral_constant<int, Q>{}), ...);
+}
+template <int N, typename F>
+__device__ __forceinline__ void static_for(F &&f) {
+  static_for_impl(f, std::make_integer_sequence<int, N>{});
+}
+
+// Prefetch depths the z-march is built for.  Deeper prefetch keeps more bytes in flight per thread, which the FP32
+// sweeps need (half the bytes per load of FP64 at the same latency); it costs registers.
+constexpr int kMaxDepth = 6;
+template <int D>
+constexpr bool depth_ok() { return D == 2 || D == 3 || D == 4 || D == 6; }
+
+// The z-march.  P supplies operand(idx) (the raw loads of the stencil operand at an interior node, idx in grid g, of
+// type P::Raw) and value(raw) (the operand formed from them when the plane is staged in LDS, so that no arithmetic
+// waits on a load while later planes are being fetched),
 // center<S>(i,j,k,idx) (load of the thread's own data for output plane k into slot S) and
 // consume<S>(i,j,k,idx,C,out,cf,rf,acc0,acc1) (output plane k, data in slot S).  Both the stencil planes and the centre
-// data are requested two planes ahead of their use, so two planes' worth of loads are in flight per thread while a
-// plane is reduced.  Planes are stepped two at a time with compile-time parity: the register sets, the LDS buffers
-// and the centre slots all alternate by parity (zc is even, so the first output plane k0 = 1 + bz*zc is odd).
+// data are requested D planes ahead of their use, so D planes' worth of loads are in flight per thread while a
+// plane is reduced.  The steps are unrolled in rounds of lcm(2, D) so that the LDS buffer (step parity), the
+// register set and the centre slot (step mod D) of every step are compile-time constants.
 // If P::kRhs, a second array (the finest f at the level's stride) is staged the same way in tileF and the 7-point
 // average R f = (6 f_c + sum of the 6 face neighbours)/2 of the output plane is handed to consume as rf (with the
 // centre value cf), so the right-hand side is formed with f read once.
@@ -92,11 +116,12 @@ __device__ __forceinline__ void st1(T v, T *p) {
 // problem's range of a batched launch); remap: number the tiles XCD by XCD (single-problem launches only, where the
 // hardware's round-robin dispatch over the XCDs follows bid).
 template <typename T, int D = 2, typename P>
-__device__ __forceinline__ void zmarch(const Sweep &sw, P &pol, double &acc0, double &acc1, T (*tile)[TY + 2][TX + 2],
-                                       double (*tileF)[TY + 2][TX + 2], int bid, int nb, bool remap) {
-  static_assert(D == 2 || D == 3, "prefetch depth");
+__device__ __forceinline__ void zmarch(const Sweep &sw, P &pol, double &acc0, double &acc1, T (*tile)[kTileRows][TX + 2],
+                                       double (*tileF)[kTileRows][TX + 2], int bid, int nb, bool remap) {
+  static_assert(depth_ok<D>(), "prefetch depth");
   constexpr int W = TX + 2, H = TY + 2, E = W * H, NL = (E + NT - 1) / NT;
-  constexpr int U = D == 2 ? 2 : 6;  // steps per unrolled round: a multiple of both 2 (LDS buffers) and D
+  static_assert(NL * NT <= kTileRows * W, "every fetch slot has an LDS entry");
+  constexpr int U = D % 2 == 0 ? D : 2 * D;  // steps per unrolled round: a multiple of both 2 (LDS buffers) and D
   constexpr bool R = P::kRhs;
   const Grid &g = sw.g;
   const int t = remap ? xcd_remap(bid, nb) : bid;
@@ -111,29 +136,34 @@ __device__ __forceinline__ void zmarch(const Sweep &sw, P &pol, double &acc0, do
   const int i = i0 + lx, j = j0 + ly;
   const bool active = (i < g.nx) && (j < g.ny);
 
-  // per fetch slot: column offset of its node (or -1 when outside the interior in x or y); for f, any node of the grid
+  // Every load is issued unconditionally, from an address clamped into the interior (or, for f, into the grid), and
+  // what lies outside is zeroed by a select when the plane is staged: with no branch around a load the compiler can
+  // wait for each plane's loads alone instead of draining all of them.  Per fetch slot: column offset of its
+  // (clamped) node and whether the node is interior in x and y; for f, any node of the grid.
   long long col[NL], colF[NL];
+  bool cin[NL], fin[NL];
 #pragma unroll
   for (int m = 0; m < NL; ++m) {
     const int e = tid + m * NT;
-    col[m] = -1;
-    colF[m] = -1;
-    if (e < E) {
-      const int gi = i0 - 1 + e % W, gj = j0 - 1 + e / W;
-      if (gi >= 1 && gi < g.nx && gj >= 1 && gj < g.ny) col[m] = g.off + (long long)gj * g.sy + gi;
-      if (R && gi <= g.nx && gj <= g.ny) colF[m] = pol.fcol(gi, gj);
-    }
+    const int ee = e < E ? e : E - 1;
+    const int gi = i0 - 1 + ee % W, gj = j0 - 1 + ee / W;
+    cin[m] = e < E && gi >= 1 && gi < g.nx && gj >= 1 && gj < g.ny;
+    col[m] = g.off + (long long)clampi(gj, 1, g.ny - 1) * g.sy + clampi(gi, 1, g.nx - 1);
+    fin[m] = e < E && gi <= g.nx && gj <= g.ny;
+    colF[m] = R ? pol.fcol(min(gi, g.nx), min(gj, g.ny)) : 0;
   }
   const long long fstride = R ? pol.fplane() : 0;
-  T reg[D][NL];
+  using Raw = typename P::Raw;
+  Raw reg[D][NL];
   double fre[D][NL];
-  auto fetch = [&](T(&rg)[NL], double(&fr)[NL], int kk) {
-    const bool kin = (kk >= 1) && (kk < g.nz);
+  auto fetch = [&](Raw(&rg)[NL], double(&fr)[NL], int kk) {  // planes past the chunk load a clamped, unused plane
+    const long long pk = (long long)clampi(kk, 1, g.nz - 1) * g.sz;
 #pragma unroll
-    for (int m = 0; m < NL; ++m) rg[m] = (kin && col[m] >= 0) ? pol.operand(col[m] + (long long)kk * g.sz) : T(0);
+    for (int m = 0; m < NL; ++m) rg[m] = pol.operand(col[m] + pk);
     if constexpr (R) {
+      const long long pf = (long long)min(kk, g.nz) * fstride;
 #pragma unroll
-      for (int m = 0; m < NL; ++m) fr[m] = (colF[m] >= 0) ? pol.fval(colF[m] + (long long)kk * fstride) : 0.0;
+      for (int m = 0; m < NL; ++m) fr[m] = pol.fval(colF[m] + pf);
     }
   };
 
@@ -142,40 +172,41 @@ __device__ __forceinline__ void zmarch(const Sweep &sw, P &pol, double &acc0, do
   const T cxy = (T)st.cxy, cxz = (T)st.cxz, cyz = (T)st.cyz;
   T Cm = 0, Xm = 0, Ym = 0, Cc = 0, Xc = 0, Yc = 0, Pc = 0;
   double Fm = 0.0, Fc = 0.0, Gc = 0.0;  // f: centre of the previous and current plane, in-plane face sum
-  const long long own = g.off + (long long)j * g.sy + i;
+  // the thread's own column, clamped into the interior (inactive threads load but never consume)
+  const long long own = g.off + (long long)min(j, g.ny - 1) * g.sy + min(i, g.nx - 1);
   const int np = k1 - k0 + 2;  // planes k0-1 .. k1
+  auto center_at = [&](auto sc, int k) {  // centre data of output plane k (clamped to the chunk) into slot sc
+    pol.template center<decltype(sc)::value>(i, j, k, own + (long long)min(k, k1 - 1) * g.sz);
+  };
 
   // Step s (plane kk = k0-1+s) takes the operand from register set s%D, stages it in LDS buffer s%2, refills the set
   // with plane kk+D, and (s >= 2) produces output plane kk-1 from the centre data in slot s%D, which it then refills
   // for output plane kk-1+D.
 #pragma unroll
   for (int d = 0; d < D; ++d) fetch(reg[d], fre[d], k0 - 1 + d);
-  if (active) {
-    if (k0 < k1) pol.template center<2 % D>(i, j, k0, own + (long long)k0 * g.sz);
-    if (k0 + 1 < k1) pol.template center<3 % D>(i, j, k0 + 1, own + (long long)(k0 + 1) * g.sz);
-    if (D == 3 && k0 + 2 < k1) pol.template center<4 % D>(i, j, k0 + 2, own + (long long)(k0 + 2) * g.sz);
-  }
+  // output plane k0 + m is produced at step m + 2, from centre slot (m + 2) mod D
+  static_for<D>([&](auto mc) {
+    constexpr int m = decltype(mc)::value;
+    center_at(std::integral_constant<int, (m + 2) % D>{}, k0 + m);
+  });
 
-  auto body = [&](auto pb, auto pr, int step) {
+  // produce: compile-time step >= 2 (false only in the first round)
+  auto body = [&](auto pb, auto pr, auto produce, int step) {
     constexpr int PB = decltype(pb)::value;  // LDS buffer of the step: step % 2
     constexpr int PR = decltype(pr)::value;  // register set and centre slot of the step: step % D
     T(*tb)[TX + 2] = tile[PB];
+    T *tl = &tile[PB][0][0];
     const int kk = k0 - 1 + step;
+    const bool kin = (kk >= 1) && (kk < g.nz);
 #pragma unroll
-    for (int m = 0; m < NL; ++m) {
-      const int e = tid + m * NT;
-      if (e < E) tb[e / W][e % W] = reg[PR][m];
-    }
+    for (int m = 0; m < NL; ++m) tl[tid + m * NT] = (kin && cin[m]) ? pol.value(reg[PR][m]) : T(0);
     if constexpr (R) {
-      double(*tf)[TX + 2] = tileF[PB];
+      double *tfl = &tileF[PB][0][0];
 #pragma unroll
-      for (int m = 0; m < NL; ++m) {
-        const int e = tid + m * NT;
-        if (e < E) tf[e / W][e % W] = fre[PR][m];
-      }
+      for (int m = 0; m < NL; ++m) tfl[tid + m * NT] = fin[m] ? fre[PR][m] : 0.0;
     }
     __syncthreads();
-    if (step + D < np) fetch(reg[PR], fre[PR], kk + D);
+    fetch(reg[PR], fre[PR], kk + D);
     const T c = tb[ly + 1][lx + 1];
     const T x = tb[ly + 1][lx] + tb[ly + 1][lx + 2];
     const T y = tb[ly][lx + 1] + tb[ly + 2][lx + 1];
@@ -186,33 +217,35 @@ __device__ __forceinline__ void zmarch(const Sweep &sw, P &pol, double &acc0, do
       fc = tf[ly + 1][lx + 1];
       fg = (tf[ly + 1][lx] + tf[ly + 1][lx + 2]) + (tf[ly][lx + 1] + tf[ly + 2][lx + 1]);
     }
-    if (step >= 2 && active) {
-      const T out = Pc + cz * (Cm + c) + cxz * (Xm + x) + cyz * (Ym + y);
-      const double rf = 0.5 * (6.0 * Fc + (Gc + (Fm + fc)));
-      pol.template consume<PR>(i, j, kk - 1, own + (long long)(kk - 1) * g.sz, Cc, out, Fc, rf, acc0, acc1);
-      if (kk - 1 + D < k1) pol.template center<PR>(i, j, kk - 1 + D, own + (long long)(kk - 1 + D) * g.sz);
+    if constexpr (decltype(produce)::value) {
+      if (active) {
+        const T out = Pc + cz * (Cm + c) + cxz * (Xm + x) + cyz * (Ym + y);
+        const double rf = 0.5 * (6.0 * Fc + (Gc + (Fm + fc)));
+        pol.template consume<PR>(i, j, kk - 1, own + (long long)(kk - 1) * g.sz, Cc, out, Fc, rf, acc0, acc1);
+      }
+      center_at(pr, kk - 1 + D);  // past the chunk: a clamped, unused load
     }
     Cm = Cc; Xm = Xc; Ym = Yc;
     Cc = c; Xc = x; Yc = y;
     Pc = c0 * c + cx * x + cy * y + cxy * d;
     Fm = Fc; Fc = fc; Gc = fg;
   };
-  using I0 = std::integral_constant<int, 0>;
-  using I1 = std::integral_constant<int, 1>;
-  using I2 = std::integral_constant<int, 2>;
-  for (int step = 0; step < np; step += U) {
-    if constexpr (D == 2) {
-      body(I0{}, I0{}, step);
-      if (step + 1 < np) body(I1{}, I1{}, step + 1);
-    } else {
-      body(I0{}, I0{}, step);
-      if (step + 1 < np) body(I1{}, I1{}, step + 1);
-      if (step + 2 < np) body(I0{}, I2{}, step + 2);
-      if (step + 3 < np) body(I1{}, I0{}, step + 3);
-      if (step + 4 < np) body(I0{}, I1{}, step + 4);
-      if (step + 5 < np) body(I1{}, I2{}, step + 5);
-    }
+  // First round (steps 0 and 1 only stage), whole rounds without bounds tests, then the tail.
+  static_for<U>([&](auto sc) {
+    constexpr int q = decltype(sc)::value;
+    if (q < np) body(std::integral_constant<int, q % 2>{}, std::integral_constant<int, q % D>{}, std::bool_constant<(q >= 2)>{}, q);
+  });
+  int step = U;
+  for (; step + U <= np; step += U) {
+    static_for<U>([&](auto sc) {
+      constexpr int q = decltype(sc)::value;
+      body(std::integral_constant<int, q % 2>{}, std::integral_constant<int, q % D>{}, std::true_type{}, step + q);
+    });
   }
+  static_for<U>([&](auto sc) {
+    constexpr int q = decltype(sc)::value;
+    if (step + q < np) body(std::integral_constant<int, q % 2>{}, std::integral_constant<int, q % D>{}, std::true_type{}, step + q);
+  });
 }
 
 // ---------------------------------------------------------------------------------------- grid-wide reductions
@@ -361,8 +394,17 @@ struct PolA {
   const T *pold;
   T *pnew;
   T beta;
-  bool first;
-  __device__ __forceinline__ T operand(long long idx) const { return first ? r[idx] : r[idx] + beta * pold[idx]; }
+  bool first;  // p = r; pold then points at r (a cache hit, and no branch around the load)
+  struct Raw {
+    T r, p;
+  };
+  __device__ __forceinline__ Raw operand(long long idx) const {
+    Raw v;
+    v.r = r[idx];
+    v.p = pold[idx];
+    return v;
+  }
+  __device__ __forceinline__ T value(const Raw &v) const { return first ? v.r : v.r + beta * v.p; }
   __device__ __forceinline__ long long fcol(int, int) const { return -1; }
   __device__ __forceinline__ long long fplane() const { return 0; }
   __device__ __forceinline__ double fval(long long) const { return 0.0; }
@@ -379,15 +421,15 @@ struct PolA {
 template <typename T, int D, bool NTP>
 __global__ __launch_bounds__(NT) void cg_pass_a_kernel(Sweep sw, const T *__restrict__ r, T *p0, T *p1,
                                                        const CgState *cs, double *partials) {
-  __shared__ T tile[2][TY + 2][TX + 2];
+  __shared__ T tile[2][kTileRows][TX + 2];
   __shared__ double sh[NT / 64];
   if (cs->done) return;
   const int it = cs->iter;
   PolA<T, NTP> pol;
   pol.r = r;
   pol.pnew = (it & 1) ? p1 : p0;
-  pol.pold = (it & 1) ? p0 : p1;
   pol.first = (it == 0);
+  pol.pold = pol.first ? r : ((it & 1) ? p0 : p1);
   pol.beta = (T)cs->beta;
   double a0 = 0.0, a1 = 0.0;
   zmarch<T, D>(sw, pol, a0, a1, tile, nullptr, blockIdx.x, gridDim.x, true);
@@ -402,13 +444,16 @@ struct PolB {
   T *u;
   T *r;
   T alpha;
-  T pr[3], pu[3];
+  T pr[kMaxDepth], pu[kMaxDepth];
+  using Raw = T;
   __device__ __forceinline__ T operand(long long idx) const { return p[idx]; }
+  __device__ __forceinline__ T value(T v) const { return v; }
   __device__ __forceinline__ long long fcol(int, int) const { return -1; }
   __device__ __forceinline__ long long fplane() const { return 0; }
   __device__ __forceinline__ double fval(long long) const { return 0.0; }
   template <int S>
   __device__ __forceinline__ void center(int, int, int, long long idx) {
+    static_assert(S < kMaxDepth, "centre slot");
     pr[S] = ld1<NTP>(&r[idx]);
     pu[S] = ld1<NTP>(&u[idx]);
   }
@@ -425,7 +470,7 @@ struct PolB {
 template <typename T, int D, bool NTP>
 __global__ __launch_bounds__(NT) void cg_pass_b_kernel(Sweep sw, T *u, T *r, const T *p0, const T *p1,
                                                        const CgState *cs, double *partials) {
-  __shared__ T tile[2][TY + 2][TX + 2];
+  __shared__ T tile[2][kTileRows][TX + 2];
   __shared__ double sh[NT / 64];
   if (cs->done) return;
   const int it = cs->iter;
@@ -434,8 +479,7 @@ __global__ __launch_bounds__(NT) void cg_pass_b_kernel(Sweep sw, T *u, T *r, con
   pol.u = u;
   pol.r = r;
   pol.alpha = (T)cs->alpha;
-  pol.pr[0] = pol.pr[1] = pol.pr[2] = 0;
-  pol.pu[0] = pol.pu[1] = pol.pu[2] = 0;
+  for (int q = 0; q < kMaxDepth; ++q) pol.pr[q] = pol.pu[q] = 0;
   double a0 = 0.0, a1 = 0.0;
   zmarch<T, D>(sw, pol, a0, a1, tile, nullptr, blockIdx.x, gridDim.x, true);
   const double v[1] = {a0};
@@ -455,6 +499,7 @@ struct RhsPart {
   __device__ __forceinline__ double fval(long long idx) const { return rs.f[idx]; }
   template <int S>
   __device__ __forceinline__ void boundary(int i, int j, int k, long long idx) {
+    static_assert(S < 3, "residual sweeps prefetch at most 3 planes");
     const bool near = (i == 1 || j == 1 || k == 1 || i == nx - 1 || j == ny - 1 || k == nz - 1);
     bt[S] = (rs.mode == 0 && near) ? bterm[idx] : 0.0;
   }
@@ -488,7 +533,7 @@ template <typename T>
 __global__ __launch_bounds__(NT) void cg_selfred_a_kernel(Sweep sw, const T *__restrict__ r, T *p0, T *p1,
                                                           CgState *cs, const double *partsB, int nbB, double tol,
                                                           double *partsA) {
-  __shared__ T tile[2][TY + 2][TX + 2];
+  __shared__ T tile[2][kTileRows][TX + 2];
   __shared__ double sh[NT / 64];
   __shared__ double shf[NT];
   if (cs->done) return;
@@ -529,8 +574,8 @@ __global__ __launch_bounds__(NT) void cg_selfred_a_kernel(Sweep sw, const T *__r
   PolA<T> pol;
   pol.r = r;
   pol.pnew = (k & 1) ? p1 : p0;
-  pol.pold = (k & 1) ? p0 : p1;
   pol.first = (k == 0);
+  pol.pold = pol.first ? r : ((k & 1) ? p0 : p1);
   pol.beta = (k == 0) ? T(0) : (T)(rho / cs->rhoA[(k - 1) & 1]);
   double a0 = 0.0, a1 = 0.0;
   zmarch<T>(sw, pol, a0, a1, tile, nullptr, blockIdx.x, gridDim.x, true);
@@ -544,7 +589,7 @@ template <typename T>
 __global__ __launch_bounds__(NT) void cg_selfred_b_kernel(Sweep sw, T *u, T *r, const T *p0, const T *p1,
                                                           CgState *cs, const double *partsA, int nbA,
                                                           double *partsB) {
-  __shared__ T tile[2][TY + 2][TX + 2];
+  __shared__ T tile[2][kTileRows][TX + 2];
   __shared__ double sh[NT / 64];
   __shared__ double shf[NT];
   if (cs->done) return;
@@ -565,8 +610,7 @@ __global__ __launch_bounds__(NT) void cg_selfred_b_kernel(Sweep sw, T *u, T *r, 
   pol.u = u;
   pol.r = r;
   pol.alpha = (T)(cs->rhoA[k & 1] / pq);
-  pol.pr[0] = pol.pr[1] = pol.pr[2] = 0;
-  pol.pu[0] = pol.pu[1] = pol.pu[2] = 0;
+  for (int q = 0; q < kMaxDepth; ++q) pol.pr[q] = pol.pu[q] = 0;
   double a0 = 0.0, a1 = 0.0;
   zmarch<T>(sw, pol, a0, a1, tile, nullptr, blockIdx.x, gridDim.x, true);
   const double v[1] = {a0};
@@ -591,7 +635,9 @@ struct PolResid {
   const double *u;
   double *r;
   RhsPart rp;
+  using Raw = double;
   __device__ __forceinline__ double operand(long long idx) const { return u[idx]; }
+  __device__ __forceinline__ double value(double v) const { return v; }
   __device__ __forceinline__ long long fcol(int gi, int gj) const { return rp.fcol(gi, gj); }
   __device__ __forceinline__ long long fplane() const { return rp.fplane(); }
   __device__ __forceinline__ double fval(long long idx) const { return rp.fval(idx); }
@@ -611,9 +657,9 @@ struct PolResid {
 template <int D, bool NTP>
 __global__ __launch_bounds__(NT) void residual_kernel(Sweep sw, const double *u, RhsSrc rs, double *r,
                                                       double *partials) {
-  __shared__ double tile[2][TY + 2][TX + 2];
+  __shared__ double tile[2][kTileRows][TX + 2];
   __shared__ double sh[NT / 64];
-  __shared__ double tileF[2][TY + 2][TX + 2];
+  __shared__ double tileF[2][kTileRows][TX + 2];
   PolResid<NTP> pol{u, r, RhsPart{rs, sw.g.nx, sw.g.ny, sw.g.nz, r, {0.0, 0.0, 0.0}}};
   double a0 = 0.0, a1 = 0.0;
   zmarch<double, D>(sw, pol, a0, a1, tile, tileF, blockIdx.x, gridDim.x, true);
@@ -631,7 +677,9 @@ struct PolResidCast {
   float *d32;
   RhsPart rp;
   double acc2;  // sum of the squared FP32-rounded residual
+  using Raw = double;
   __device__ __forceinline__ double operand(long long idx) const { return u[idx]; }
+  __device__ __forceinline__ double value(double v) const { return v; }
   __device__ __forceinline__ long long fcol(int gi, int gj) const { return rp.fcol(gi, gj); }
   __device__ __forceinline__ long long fplane() const { return rp.fplane(); }
   __device__ __forceinline__ double fval(long long idx) const { return rp.fval(idx); }
@@ -656,9 +704,9 @@ template <int D, bool NTP>
 __global__ __launch_bounds__(NT) void residual_cast_kernel(Sweep sw, const double *u, RhsSrc rs,
                                                            const double *bterm, Grid g32, float *r32, float *d32,
                                                            double *partials) {
-  __shared__ double tile[2][TY + 2][TX + 2];
+  __shared__ double tile[2][kTileRows][TX + 2];
   __shared__ double sh[NT / 64];
-  __shared__ double tileF[2][TY + 2][TX + 2];
+  __shared__ double tileF[2][kTileRows][TX + 2];
   PolResidCast<NTP> pol{u, g32, r32, d32, RhsPart{rs, sw.g.nx, sw.g.ny, sw.g.nz, bterm, {0.0, 0.0, 0.0}}, 0.0};
   double a0 = 0.0, a1 = 0.0;
   zmarch<double, D>(sw, pol, a0, a1, tile, tileF, blockIdx.x, gridDim.x, true);
@@ -672,7 +720,9 @@ struct PolApply {
   const double *x;
   Grid gy;
   double *y;
+  using Raw = double;
   __device__ __forceinline__ double operand(long long idx) const { return x[idx]; }
+  __device__ __forceinline__ double value(double v) const { return v; }
   __device__ __forceinline__ long long fcol(int, int) const { return -1; }
   __device__ __forceinline__ long long fplane() const { return 0; }
   __device__ __forceinline__ double fval(long long) const { return 0.0; }
@@ -686,7 +736,7 @@ struct PolApply {
 };
 
 __global__ __launch_bounds__(NT) void apply_kernel(Sweep sw, const double *x, Grid gy, double *y) {
-  __shared__ double tile[2][TY + 2][TX + 2];
+  __shared__ double tile[2][kTileRows][TX + 2];
   PolApply pol{x, gy, y};
   double a0 = 0.0, a1 = 0.0;
   zmarch<double>(sw, pol, a0, a1, tile, nullptr, blockIdx.x, gridDim.x, true);
@@ -1242,9 +1292,9 @@ __global__ __launch_bounds__(256) void b_boundary_terms_kernel(BatchList L) {
 }
 
 __global__ __launch_bounds__(NT) void b_residual_kernel(BatchList L) {
-  __shared__ double tile[2][TY + 2][TX + 2];
+  __shared__ double tile[2][kTileRows][TX + 2];
   __shared__ double sh[NT / 64];
-  __shared__ double tileF[2][TY + 2][TX + 2];
+  __shared__ double tileF[2][kTileRows][TX + 2];
   const int e = find_entry(L.pre, L.n, blockIdx.x);
   const BatchEntry &E = *L.ent[e];
   const int bid = blockIdx.x - L.pre[e], nb = L.pre[e + 1] - L.pre[e];
@@ -1270,9 +1320,9 @@ __global__ __launch_bounds__(FT) void b_finalize_init_kernel(BatchList L, BatchS
 
 // FP64 residual and its FP32 copy for outer step aux[e] of the refinement
 __global__ __launch_bounds__(NT) void b_residual_cast_kernel(BatchList L) {
-  __shared__ double tile[2][TY + 2][TX + 2];
+  __shared__ double tile[2][kTileRows][TX + 2];
   __shared__ double sh[NT / 64];
-  __shared__ double tileF[2][TY + 2][TX + 2];
+  __shared__ double tileF[2][kTileRows][TX + 2];
   const int e = find_entry(L.pre, L.n, blockIdx.x);
   const BatchEntry &E = *L.ent[e];
   const int bid = blockIdx.x - L.pre[e], nb = L.pre[e + 1] - L.pre[e];
@@ -1301,7 +1351,7 @@ __global__ __launch_bounds__(FT) void b_finalize_ir_kernel(BatchList L, BatchSta
 template <typename T>
 __global__ __launch_bounds__(NT) void b_pass_a_kernel(BatchList L) {
   constexpr bool F = sizeof(T) == 4;
-  __shared__ T tile[2][TY + 2][TX + 2];
+  __shared__ T tile[2][kTileRows][TX + 2];
   __shared__ double sh[NT / 64];
   const int e = find_entry(L.pre, L.n, blockIdx.x);
   const BatchEntry &E = *L.ent[e];
@@ -1319,8 +1369,8 @@ __global__ __launch_bounds__(NT) void b_pass_a_kernel(BatchList L) {
   PolA<T, true> pol;  // the batch's working set is far larger than the caches: streaming policy
   pol.r = r;
   pol.pnew = (it & 1) ? p1 : p0;
-  pol.pold = (it & 1) ? p0 : p1;
   pol.first = (it == 0);
+  pol.pold = pol.first ? r : ((it & 1) ? p0 : p1);
   pol.beta = (T)cs->beta;
   const Sweep sw = F ? E.swA32 : E.swA;
   double a0 = 0.0, a1 = 0.0;
@@ -1332,7 +1382,7 @@ __global__ __launch_bounds__(NT) void b_pass_a_kernel(BatchList L) {
 template <typename T>
 __global__ __launch_bounds__(NT) void b_pass_b_kernel(BatchList L) {
   constexpr bool F = sizeof(T) == 4;
-  __shared__ T tile[2][TY + 2][TX + 2];
+  __shared__ T tile[2][kTileRows][TX + 2];
   __shared__ double sh[NT / 64];
   const int e = find_entry(L.pre, L.n, blockIdx.x);
   const BatchEntry &E = *L.ent[e];
@@ -1351,8 +1401,7 @@ __global__ __launch_bounds__(NT) void b_pass_b_kernel(BatchList L) {
     pol.r = E.r;
   }
   pol.alpha = (T)cs->alpha;
-  pol.pr[0] = pol.pr[1] = pol.pr[2] = 0;
-  pol.pu[0] = pol.pu[1] = pol.pu[2] = 0;
+  for (int q = 0; q < kMaxDepth; ++q) pol.pr[q] = pol.pu[q] = 0;
   const Sweep sw = F ? E.swB32 : E.swB;
   double a0 = 0.0, a1 = 0.0;
   zmarch<T>(sw, pol, a0, a1, tile, nullptr, bid, nb, false);
@@ -1393,7 +1442,7 @@ __global__ __launch_bounds__(256) void b_add_correction_kernel(BatchList L) {
 // fewer while the grid has under 2048 workgroups (8 per CU).  The autotuner replaces it per grid and pass.
 Sweep make_sweep(const Grid &g, const Stencil &s, int zc, int depth, int nt) {
   Sweep sw;
-  sw.depth = depth == 3 ? 3 : 2;
+  sw.depth = (depth == 3 || depth == 4 || depth == 6) ? depth : 2;
   sw.nt = nt ? 1 : 0;
   sw.g = g;
   sw.st = s;
@@ -1488,14 +1537,27 @@ void launch_residual_cast(const Sweep &sw, const double *u, const RhsSrc &rs, do
   finalize_ir_kernel<<<1, FT, 0, st>>>(outer, inner, partials, nb, tol, eta, outer_step, max_outer, max_inner);
 }
 
+// f(depth, policy) with the sweep's prefetch depth and cache policy as compile-time constants.
+template <typename F>
+static void with_depth_policy(const Sweep &sw, F &&f) {
+  auto pol = [&](auto d) {
+    if (sw.nt) f(d, std::true_type{});
+    else f(d, std::false_type{});
+  };
+  switch (sw.depth) {
+    case 3: pol(std::integral_constant<int, 3>{}); break;
+    case 4: pol(std::integral_constant<int, 4>{}); break;
+    case 6: pol(std::integral_constant<int, 6>{}); break;
+    default: pol(std::integral_constant<int, 2>{}); break;
+  }
+}
+
 template <typename T>
 void launch_cg_pass_a(const Sweep &sw, const T *r, T *p0, T *p1, CgState *cs, double *partials, hipStream_t st) {
   const int nb = sweep_blocks(sw);
-  const int v = (sw.depth == 3 ? 2 : 0) + sw.nt;
-  if (v == 0) cg_pass_a_kernel<T, 2, false><<<nb, NT, 0, st>>>(sw, r, p0, p1, cs, partials);
-  else if (v == 1) cg_pass_a_kernel<T, 2, true><<<nb, NT, 0, st>>>(sw, r, p0, p1, cs, partials);
-  else if (v == 2) cg_pass_a_kernel<T, 3, false><<<nb, NT, 0, st>>>(sw, r, p0, p1, cs, partials);
-  else cg_pass_a_kernel<T, 3, true><<<nb, NT, 0, st>>>(sw, r, p0, p1, cs, partials);
+  with_depth_policy(sw, [&](auto d, auto n) {
+    cg_pass_a_kernel<T, decltype(d)::value, decltype(n)::value><<<nb, NT, 0, st>>>(sw, r, p0, p1, cs, partials);
+  });
   finalize_a_kernel<<<1, FT, 0, st>>>(cs, partials, nb);
 }
 
@@ -1503,11 +1565,9 @@ template <typename T>
 void launch_cg_pass_b(const Sweep &sw, T *u, T *r, const T *p0, const T *p1, CgState *cs, double *partials,
                       hipStream_t st) {
   const int nb = sweep_blocks(sw);
-  const int v = (sw.depth == 3 ? 2 : 0) + sw.nt;
-  if (v == 0) cg_pass_b_kernel<T, 2, false><<<nb, NT, 0, st>>>(sw, u, r, p0, p1, cs, partials);
-  else if (v == 1) cg_pass_b_kernel<T, 2, true><<<nb, NT, 0, st>>>(sw, u, r, p0, p1, cs, partials);
-  else if (v == 2) cg_pass_b_kernel<T, 3, false><<<nb, NT, 0, st>>>(sw, u, r, p0, p1, cs, partials);
-  else cg_pass_b_kernel<T, 3, true><<<nb, NT, 0, st>>>(sw, u, r, p0, p1, cs, partials);
+  with_depth_policy(sw, [&](auto d, auto n) {
+    cg_pass_b_kernel<T, decltype(d)::value, decltype(n)::value><<<nb, NT, 0, st>>>(sw, u, r, p0, p1, cs, partials);
+  });
   finalize_b_kernel<<<1, FT, 0, st>>>(cs, partials, nb);
 }
 
