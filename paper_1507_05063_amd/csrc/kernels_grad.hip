@@ -5,6 +5,8 @@
 //   v_{i-1} + 4 v_i + v_{i+1} = 3 (u_{i+1} - u_{i-1}) / h,  i = 1..N-1
 // (the paper's (1/6, 4/6, 1/6) system times 6).  The constant-coefficient Thomas factors m_1 = 4,
 // m_i = 4 - 1/m_{i-1} are shared by all lines; the host passes 1/m_i per axis.
+#include <algorithm>
+
 #include "excmg_internal.h"
 
 namespace excmg {
@@ -87,178 +89,274 @@ __device__ __forceinline__ void line_solve(const double *__restrict__ u, long lo
   }
 }
 
-// x lines: one thread per line, 64 lines per workgroup.  The rows are contiguous in memory, so the chunk of GC values
-// every line needs next is staged through an LDS tile with coalesced loads (each 32-value row segment read by 32
-// consecutive threads), and the finished chunk goes back out through the same tile with coalesced stores.  The
-// Thomas sweeps are those of line_solve, with u taken from the tile.
-constexpr int XW = 64;
+// x lines, one wavefront per line, by prefix scans.  Both Thomas recursions are first-order linear recurrences,
+//   forward  d_t = w_t rhs_t - w_t d_{t-1}   (d_0 = 0),        back  v_t = d_t - w_t v_{t+1}   (v_{M+1} = 0),
+// with w_t = 1/m_t, i.e. compositions of affine maps x -> A + B x.  The line is cut into segments of 64 XL unknowns
+// and lane l of the wavefront owns unknowns t = 1 + 64 XL s + XL l + q (q < XL) of segment s: it composes the maps of
+// its XL steps (running them from 0 gives A, the product of the B's gives B), a Kogge-Stone scan over the 64 lanes
+// (shuffles, in lane order for the forward sweep and in reverse for the back substitution) composes the lanes' maps,
+// and each lane then has the exact value entering its first step; its XL results follow as A_q + B_q x_in.  Segments
+// are chained through the value leaving the last (forward) or first (back) lane.  The back substitution runs over
+// the segments from the last to the first and redoes the forward sweep of every segment but the last (whose d stay
+// in registers) from its stored entering value.  This is the Thomas solution, summed in another order.
+// Past the last unknown the maps are x -> 0, which makes d and v vanish there.  A segment of u goes into LDS with
+// contiguous loads and the lanes read their XL + 2 values from there; the results go out the same way.  LDS slots
+// are padded by 2 words per 8 so that the lanes' blocks (XL apart) start on different banks.
+constexpr int XL = 8;
+constexpr int XSEG = 64 * XL;
+constexpr int kInvM = 32;  // 1/m_t has reached its limit 1/(2 + sqrt 3) to the last bit well before t = 32
 
-__global__ __launch_bounds__(XW) void grad_x_kernel(Grid gu, const double *__restrict__ u, Grid gd, double *ux,
-                                                    double hx, const double *__restrict__ inv_m) {
-  __shared__ double tile[XW][GC + 1];
-  __shared__ long long rb[XW], ob[XW];  // row starts of the workgroup's lines in u and in ux
-  const int nlines = (gu.ny + 1) * (gu.nz + 1);
-  const int L0 = blockIdx.x * XW;
-  const int tid = threadIdx.x;
-  const int nl = min(XW, nlines - L0);
-  const int N = gu.nx, M = N - 1;
-  {
-    const int L = L0 + (tid < nl ? tid : 0);
-    const int j = L % (gu.ny + 1), k = L / (gu.ny + 1);
-    rb[tid] = gu.at(0, j, k);
-    ob[tid] = gd.at(0, j, k);
+__device__ __forceinline__ void scan_lanes_up(double &A, double &B, int lane) {  // maps of lanes 0..lane
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const double Ap = __shfl_up(A, off, 64), Bp = __shfl_up(B, off, 64);
+    const bool take = lane >= off;
+    A = take ? A + B * Ap : A;
+    B = take ? B * Bp : B;
   }
-  __syncthreads();
-  const bool act = tid < nl;
-  const long long b = rb[tid];
-  double v0 = 0.0, vN = 0.0, um = 0.0, uc = 0.0;
-  if (act) {
-    v0 = end0(u[b], u[b + 1], u[b + 2], u[b + 3], u[b + 4], hx);
-    vN = -end0(u[b + N], u[b + N - 1], u[b + N - 2], u[b + N - 3], u[b + N - 4], hx);
-    ux[ob[tid]] = v0;
-    ux[ob[tid] + N] = vN;
-    um = u[b];
-    uc = u[b + 1];
+}
+
+__device__ __forceinline__ void scan_lanes_down(double &A, double &B, int lane) {  // maps of lanes lane..63
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const double An = __shfl_down(A, off, 64), Bn = __shfl_down(B, off, 64);
+    const bool take = lane + off < 64;
+    A = take ? A + B * An : A;
+    B = take ? B * Bn : B;
+  }
+}
+
+__device__ __forceinline__ int xslot(int e) { return e + 2 * (e >> 3); }
+constexpr int kXBuf = XSEG + 2 + 2 * ((XSEG + 2) >> 3) + 2;  // slots of u at t0-1 .. t0+XSEG
+
+__global__ __launch_bounds__(64) void grad_x_scan_kernel(Grid gu, const double *__restrict__ u, Grid gd, double *ux,
+                                                         double hx, const double *__restrict__ inv_m) {
+  __shared__ double buf[kXBuf];
+  __shared__ double wt[kInvM + 1];
+  extern __shared__ double seg_in[];  // d entering each segment
+  const int N = gu.nx, M = N - 1;
+  const int lane = threadIdx.x;
+  const int L = blockIdx.x;
+  const int j = L % (gu.ny + 1), k = L / (gu.ny + 1);
+  const long long b = gu.at(0, j, k), ob = gd.at(0, j, k);
+  const int wlast = min(M, kInvM);
+  if (lane <= kInvM) wt[lane] = inv_m[min(max(lane, 1), wlast)];
+  const double v0 = end0(u[b], u[b + 1], u[b + 2], u[b + 3], u[b + 4], hx);
+  const double vN = -end0(u[b + N], u[b + N - 1], u[b + N - 2], u[b + N - 3], u[b + N - 4], hx);
+  if (lane == 0) {
+    ux[ob] = v0;
+    ux[ob + N] = vN;
   }
   const double s3 = 3.0 / hx;
-  double dprev = 0.0;
-  // tile <- u at x = t0+1 .. t0+GC of every line (the values the forward sweep over t0 .. t0+GC-1 needs)
-  auto load = [&](int t0) {
-#pragma unroll 8
-    for (int m = 0; m < GC; ++m) {
-      const int e = tid + m * XW;
-      const int ln = e / GC, xx = e % GC, x = t0 + 1 + xx;
-      tile[ln][xx] = (ln < nl && x <= N) ? u[rb[ln] + x] : 0.0;
-    }
-  };
-  auto forward = [&](double (&d)[GC], int t0) {
+  const int nseg = (M + XSEG - 1) / XSEG;
+  auto W = [&](int t) { return wt[min(t, kInvM)]; };  // 1/m_t (t >= 1; entries past wlast repeat it)
+
+  // u of segment s into buf (slot e: x = 64 XL s + e), then the lane's composite forward map (A, B)
+  auto forward_map = [&](int s, double &A, double &B) {
+    const int base = s * XSEG;
+    __syncthreads();  // earlier reads of buf are done
 #pragma unroll
-    for (int q = 0; q < GC; ++q) {
-      const int t = t0 + q;
-      if (t <= M) {
-        const double up = tile[tid][q];
+    for (int m = 0; m < (XSEG + 2 + 63) / 64; ++m) {
+      const int e = lane + 64 * m;
+      if (e < XSEG + 2) buf[xslot(e)] = u[b + min(base + e, N)];
+    }
+    __syncthreads();
+    const int tb = 1 + base + lane * XL;
+    double d = 0.0, pr = 1.0, um = buf[xslot(lane * XL)], uc = buf[xslot(lane * XL + 1)];
+#pragma unroll
+    for (int q = 0; q < XL; ++q) {
+      const int t = tb + q;
+      const double up = buf[xslot(lane * XL + q + 2)];
+      double rhs = s3 * (up - um);
+      rhs = (t == 1) ? rhs - v0 : rhs;
+      rhs = (t == M) ? rhs - vN : rhs;
+      const double w = W(t);
+      const bool ok = t <= M;
+      d = ok ? w * (rhs - d) : 0.0;
+      pr = ok ? -w * pr : 0.0;
+      um = uc;
+      uc = up;
+    }
+    A = d;
+    B = pr;
+  };
+  // the exact d of the lane's unknowns (replayed from the scanned entering value); returns d leaving the segment
+  double dd[XL];
+  auto forward_fix = [&](int s, double A, double B, double din_seg) {
+    scan_lanes_up(A, B, lane);
+    const double dend = A + B * din_seg;
+    double d = __shfl_up(dend, 1, 64);
+    d = lane == 0 ? din_seg : d;
+    const int tb = 1 + s * XSEG + lane * XL;
+    double um = buf[xslot(lane * XL)], uc = buf[xslot(lane * XL + 1)];
+#pragma unroll
+    for (int q = 0; q < XL; ++q) {
+      const int t = tb + q;
+      const double up = buf[xslot(lane * XL + q + 2)];
+      double rhs = s3 * (up - um);
+      rhs = (t == 1) ? rhs - v0 : rhs;
+      rhs = (t == M) ? rhs - vN : rhs;
+      d = (t <= M) ? W(t) * (rhs - d) : 0.0;
+      dd[q] = d;
+      um = uc;
+      uc = up;
+    }
+    return __shfl(dend, 63, 64);
+  };
+
+  double carry = 0.0;
+  for (int s = 0; s < nseg; ++s) {
+    if (lane == 0) seg_in[s] = carry;
+    double A, B;
+    forward_map(s, A, B);
+    carry = forward_fix(s, A, B, carry);
+  }
+  double vcarry = 0.0;  // v just past the segment
+  for (int s = nseg - 1; s >= 0; --s) {
+    if (s < nseg - 1) {
+      double A, B;
+      forward_map(s, A, B);
+      forward_fix(s, A, B, seg_in[s]);
+    }
+    const int tb = 1 + s * XSEG + lane * XL;
+    double v = 0.0, pr = 1.0;
+#pragma unroll
+    for (int q = XL - 1; q >= 0; --q) {
+      const int t = tb + q;
+      const bool ok = t <= M;
+      const double w = W(t);
+      v = ok ? dd[q] - w * v : 0.0;
+      pr = ok ? -w * pr : 0.0;
+    }
+    double A = v, B = pr;
+    scan_lanes_down(A, B, lane);
+    const double vfirst = A + B * vcarry;
+    v = __shfl_down(vfirst, 1, 64);
+    v = lane == 63 ? vcarry : v;
+    __syncthreads();  // the lanes' reads of buf are done
+#pragma unroll
+    for (int q = XL - 1; q >= 0; --q) {
+      const int t = tb + q;
+      v = (t <= M) ? dd[q] - W(t) * v : 0.0;
+      buf[xslot(lane * XL + q)] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < XL; ++m) {
+      const int e = lane + 64 * m, t = 1 + s * XSEG + e;
+      if (t <= M) __builtin_nontemporal_store(buf[xslot(e)], &ux[ob + t]);
+    }
+    vcarry = __shfl(vfirst, 0, 64);
+  }
+}
+
+// x lines of at most 64 XL unknowns (one segment), several lines per wavefront: the lanes load the next line's u
+// into registers while the current line is solved, so the read latency of one line overlaps the work of the last.
+// Every global access is unconditional (clamped indices; lanes past the last unknown store its value again), which
+// lets the compiler wait for just the loads it needs instead of draining all of them.
+constexpr int kXFetch = (XSEG + 2 + 63) / 64;  // u values per lane and line
+
+__global__ __launch_bounds__(64) void grad_x_short_kernel(Grid gu, const double *__restrict__ u, Grid gd, double *ux,
+                                                          double hx, const double *__restrict__ inv_m) {
+  __shared__ double buf[kXBuf];
+  __shared__ double wt[kInvM + 1];
+  const int N = gu.nx, M = N - 1;
+  const int lane = threadIdx.x;
+  const int nlines = (gu.ny + 1) * (gu.nz + 1);
+  const int wlast = min(M, kInvM);
+  if (lane <= kInvM) wt[lane] = inv_m[min(max(lane, 1), wlast)];
+  const double s3 = 3.0 / hx;
+  auto W = [&](int t) { return wt[min(t, kInvM)]; };
+  double pf[kXFetch];
+  auto fetch = [&](int L) {  // u of line L (clamped to the last line) at x = min(lane + 64 m, N)
+    L = min(L, nlines - 1);
+    const long long bb = gu.at(0, L % (gu.ny + 1), L / (gu.ny + 1));
+#pragma unroll
+    for (int m = 0; m < kXFetch; ++m) pf[m] = u[bb + min(lane + 64 * m, N)];
+  };
+  fetch(blockIdx.x);
+  for (int L = blockIdx.x; L < nlines; L += gridDim.x) {
+    const long long ob = gd.at(0, L % (gu.ny + 1), L / (gu.ny + 1));
+    __syncthreads();  // the previous line's reads of buf are done
+#pragma unroll
+    for (int m = 0; m < kXFetch; ++m) buf[xslot(min(lane + 64 * m, XSEG + 1))] = pf[m];  // slot x: u at min(x, N)
+    fetch(L + gridDim.x);
+    __syncthreads();
+    const double v0 = end0(buf[xslot(0)], buf[xslot(1)], buf[xslot(2)], buf[xslot(3)], buf[xslot(4)], hx);
+    const double vN = -end0(buf[xslot(N)], buf[xslot(N - 1)], buf[xslot(N - 2)], buf[xslot(N - 3)],
+                            buf[xslot(N - 4)], hx);
+    const int tb = 1 + lane * XL;
+    // forward: the lane's composite map, the scan, then the replay from the exact entering d
+    double d = 0.0, pr = 1.0;
+    {
+      double um = buf[xslot(lane * XL)], uc = buf[xslot(lane * XL + 1)];
+#pragma unroll
+      for (int q = 0; q < XL; ++q) {
+        const int t = tb + q;
+        const double up = buf[xslot(lane * XL + q + 2)];
         double rhs = s3 * (up - um);
-        if (t == 1) rhs -= v0;
-        if (t == M) rhs -= vN;
-        const double dd = (rhs - dprev) * inv_m[t];
-        d[q] = dd;
-        dprev = dd;
+        rhs = (t == 1) ? rhs - v0 : rhs;
+        rhs = (t == M) ? rhs - vN : rhs;
+        const double w = W(t);
+        const bool ok = t <= M;
+        d = ok ? w * (rhs - d) : 0.0;
+        pr = ok ? -w * pr : 0.0;
         um = uc;
         uc = up;
       }
     }
-  };
-  double dA[GC], dB[GC];
-  load(1);
-  __syncthreads();
-  forward(dA, 1);
-  __syncthreads();
-  for (int t0 = 1; t0 <= M; t0 += GC) {
-    const int t1 = t0 + GC;
+    double A = d, B = pr;
+    scan_lanes_up(A, B, lane);
+    d = __shfl_up(A, 1, 64);  // d entering the lane (the segment starts from d_0 = 0)
+    d = lane == 0 ? 0.0 : d;
+    double dd[XL];
+    {
+      double um = buf[xslot(lane * XL)], uc = buf[xslot(lane * XL + 1)];
+#pragma unroll
+      for (int q = 0; q < XL; ++q) {
+        const int t = tb + q;
+        const double up = buf[xslot(lane * XL + q + 2)];
+        double rhs = s3 * (up - um);
+        rhs = (t == 1) ? rhs - v0 : rhs;
+        rhs = (t == M) ? rhs - vN : rhs;
+        d = (t <= M) ? W(t) * (rhs - d) : 0.0;
+        dd[q] = d;
+        um = uc;
+        uc = up;
+      }
+    }
+    // back substitution: the same with the maps of v_t = d_t - w_t v_{t+1}, lanes in reverse
     double v = 0.0;
-    if (t1 <= M) {
-      load(t1);
-      __syncthreads();
-      forward(dB, t1);
-      __syncthreads();  // every line has consumed the tile
+    pr = 1.0;
 #pragma unroll
-      for (int q = GC - 1; q >= 0; --q) {
-        const int t = t1 + q;
-        if (t <= M) v = (t == M) ? dB[q] : dB[q] - inv_m[t] * v;
-      }
+    for (int q = XL - 1; q >= 0; --q) {
+      const int t = tb + q;
+      const bool ok = t <= M;
+      const double w = W(t);
+      v = ok ? dd[q] - w * v : 0.0;
+      pr = ok ? -w * pr : 0.0;
     }
+    A = v;
+    B = pr;
+    scan_lanes_down(A, B, lane);
+    v = __shfl_down(A, 1, 64);  // v entering the lane from above (v_{M+1} = 0)
+    v = lane == 63 ? 0.0 : v;
+    __syncthreads();  // the lanes' reads of buf are done
 #pragma unroll
-    for (int q = GC - 1; q >= 0; --q) {
-      const int t = t0 + q;
-      if (t <= M) {
-        v = (t == M) ? dA[q] : dA[q] - inv_m[t] * v;
-        tile[tid][q] = v;
-      }
-    }
-    __syncthreads();
-#pragma unroll 8
-    for (int m = 0; m < GC; ++m) {
-      const int e = tid + m * XW;
-      const int ln = e / GC, xx = e % GC, t = t0 + xx;
-      if (ln < nl && t <= M) __builtin_nontemporal_store(tile[ln][xx], &ux[ob[ln] + t]);
+    for (int q = XL - 1; q >= 0; --q) {
+      const int t = tb + q;
+      v = (t <= M) ? dd[q] - W(t) * v : 0.0;
+      buf[xslot(lane * XL + q)] = v;
     }
     __syncthreads();
 #pragma unroll
-    for (int q = 0; q < GC; ++q) dA[q] = dB[q];
-  }
-}
-
-// x lines, one wavefront per line (grids of at most kXWaveMax cells along x): the line is read into LDS with
-// contiguous loads, and lane l produces the XS unknowns t0 = 1 + XS l (+ 64 XS per pass) from its own windows: the
-// forward elimination starts XWIN unknowns before t0 with d = 0 in place of the true d there, the back substitution
-// starts XWIN unknowns after the lane's last one with v = d there; both starting errors are damped below
-// 0.268^32 = 5e-19 of the values by the time they reach the lane's unknowns, so the result is the Thomas solution to
-// rounding (as in line_solve).  The factors 1/m_t reach their limit 1/(2 + sqrt 3) to the last bit by t = 14, so the
-// first kInvM of them sit in LDS and the rest equal the last of those.  The results go back through LDS and out with
-// contiguous stores.
-constexpr int XS = 8, XWIN = 32, kInvM = 32;
-constexpr int kXWaveMax = 4095;
-
-__global__ __launch_bounds__(64) void grad_x_wave_kernel(Grid gu, const double *__restrict__ u, Grid gd, double *ux,
-                                                         double hx, const double *__restrict__ inv_m) {
-  extern __shared__ double lds[];
-  __shared__ double im[kInvM + 1];
-  const int N = gu.nx, M = N - 1;
-  // LDS position of unknown t: one pad word per XS, so that the lanes (XS apart) hit different banks
-  auto P = [](int t) { return t + (t >> 3); };
-  double *lu = lds, *lo = lds + P(N) + 1;
-  const int L = blockIdx.x;
-  const int j = L % (gu.ny + 1), k = L / (gu.ny + 1);
-  const long long b = gu.at(0, j, k), ob = gd.at(0, j, k);
-  for (int t = threadIdx.x; t <= N; t += 64) lu[P(t)] = u[b + t];
-  for (int t = threadIdx.x; t <= kInvM; t += 64) im[t] = (t >= 1 && t <= M) ? inv_m[t] : (t > M ? inv_m[M] : 0.0);
-  __syncthreads();
-  const double v0 = end0(lu[P(0)], lu[P(1)], lu[P(2)], lu[P(3)], lu[P(4)], hx);
-  const double vN = -end0(lu[P(N)], lu[P(N - 1)], lu[P(N - 2)], lu[P(N - 3)], lu[P(N - 4)], hx);
-  const double s3 = 3.0 / hx;
-  auto rhs = [&](int t) {
-    double r = s3 * (lu[P(t + 1)] - lu[P(t - 1)]);
-    if (t == 1) r -= v0;
-    if (t == M) r -= vN;
-    return r;
-  };
-  auto invm = [&](int t) { return im[t < kInvM ? t : kInvM]; };
-  if (threadIdx.x == 0) {
-    lo[P(0)] = v0;
-    lo[P(N)] = vN;
-  }
-  for (int base = 1; base <= M; base += 64 * XS) {
-    const int t0 = base + threadIdx.x * XS;
-    if (t0 <= M) {
-      const int te = t0 + XS - 1 + XWIN > M ? M : t0 + XS - 1 + XWIN;
-      double d = 0.0;
-#pragma unroll
-      for (int q = -XWIN; q < 0; ++q) {
-        const int t = t0 + q;
-        if (t >= 1) d = (rhs(t) - d) * invm(t);
-      }
-      double dk[XS + XWIN];
-#pragma unroll
-      for (int q = 0; q < XS + XWIN; ++q) {
-        const int t = t0 + q;
-        if (t <= te) {
-          d = (rhs(t) - d) * invm(t);
-          dk[q] = d;
-        }
-      }
-      double v = 0.0;
-#pragma unroll
-      for (int q = XS + XWIN - 1; q >= 0; --q) {
-        const int t = t0 + q;
-        if (t <= te) {
-          v = (t == M) ? dk[q] : dk[q] - invm(t) * v;
-          if (q < XS) lo[P(t)] = v;
-        }
-      }
+    for (int m = 0; m < XL; ++m) {
+      const int t = min(1 + lane + 64 * m, M);
+      __builtin_nontemporal_store(buf[xslot(t - 1)], &ux[ob + t]);
     }
+    __builtin_nontemporal_store(v0, &ux[ob]);
+    __builtin_nontemporal_store(vN, &ux[ob + N]);
   }
-  __syncthreads();
-  for (int t = threadIdx.x; t <= N; t += 64) __builtin_nontemporal_store(lo[P(t)], &ux[ob + t]);
 }
 
 // y and z lines: one thread per line, consecutive threads on consecutive x, so every step of the sweeps is a
@@ -285,11 +383,11 @@ void launch_gradient(const Grid &gu, const double *u, const Grid &gd, double *ux
                      double hy, double hz, const double *inv_m_x, const double *inv_m_y, const double *inv_m_z,
                      hipStream_t st) {
   const int nlines = (gu.ny + 1) * (gu.nz + 1);
-  if (gu.nx <= kXWaveMax)
-    grad_x_wave_kernel<<<nlines, 64, 2 * (size_t)(gu.nx + gu.nx / 8 + 2) * sizeof(double), st>>>(gu, u, gd, ux, hx,
-                                                                                                inv_m_x);
+  const int nseg = (gu.nx - 1 + XSEG - 1) / XSEG;
+  if (nseg == 1)  // about 8 lines per wavefront, 32 wavefronts per CU at most
+    grad_x_short_kernel<<<std::min(nlines, 8192), 64, 0, st>>>(gu, u, gd, ux, hx, inv_m_x);
   else
-    grad_x_kernel<<<(nlines + XW - 1) / XW, XW, 0, st>>>(gu, u, gd, ux, hx, inv_m_x);
+    grad_x_scan_kernel<<<nlines, 64, (size_t)nseg * sizeof(double), st>>>(gu, u, gd, ux, hx, inv_m_x);
   grad_y_kernel<<<dim3((gu.nx + 1 + 63) / 64, gu.nz + 1), 64, 0, st>>>(gu, u, gd, uy, hy, inv_m_y);
   grad_z_kernel<<<dim3((gu.nx + 1 + 63) / 64, gu.ny + 1), 64, 0, st>>>(gu, u, gd, uz, hz, inv_m_z);
 }

@@ -92,7 +92,8 @@ def test_exp_true(ex, orc, n):
 
 
 @pytest.mark.parametrize("n,box", [((20, 12, 36), (1.0, 0.5, 2.0)), ((4, 4, 4), (1.0, 1.0, 1.0)),
-                                   ((130, 66, 8), (1.0, 1.0, 1.0))])
+                                   ((130, 66, 8), (1.0, 1.0, 1.0)),
+                                   ((1100, 6, 4), (2.0, 1.0, 1.0))])  # x lines of three 512-unknown segments
 def test_gradient(ex, orc, n, box):
     u = rnd(n)
     s = ex.Solver(n, box, 1e-10)
