@@ -360,18 +360,33 @@ __global__ __launch_bounds__(64) void grad_x_short_kernel(Grid gu, const double 
 }
 
 // y and z lines: one thread per line, consecutive threads on consecutive x, so every step of the sweeps is a
-// coalesced row access.
-__global__ __launch_bounds__(64) void grad_y_kernel(Grid gu, const double *__restrict__ u, Grid gd, double *uy,
-                                                    double hy, const double *__restrict__ inv_m) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const int k = blockIdx.y;
+// coalesced row access.  A workgroup takes 64 lines of one plane (k for y lines, j for z lines).  The y-line
+// workgroups are numbered so that all x blocks of a plane run on the same XCD (the hardware deals consecutive
+// workgroups to the 8 XCDs in turn): the row segments they write meet inside cache lines of the caller's unpadded
+// rows, and a line written from two XCDs goes out to memory in pieces.  (The z lines write a different plane at
+// every step, and measured no better for it.)
+constexpr int kXcd = 8;
+constexpr int kLineWg = 64;
+
+__device__ __forceinline__ bool plane_block(int nbx, int nplanes, int &bx, int &plane) {
+  const int x = blockIdx.x % kXcd, rest = blockIdx.x / kXcd;
+  bx = rest % nbx;
+  plane = (rest / nbx) * kXcd + x;
+  return plane < nplanes;
+}
+
+__global__ __launch_bounds__(kLineWg) void grad_y_kernel(Grid gu, const double *__restrict__ u, Grid gd, double *uy,
+                                                         double hy, const double *__restrict__ inv_m) {
+  int bx, k;
+  if (!plane_block((gu.nx + kLineWg) / kLineWg, gu.nz + 1, bx, k)) return;
+  const int i = bx * kLineWg + threadIdx.x;
   if (i > gu.nx) return;
   line_solve(u, gu.at(i, 0, k), gu.sy, uy, gd.at(i, 0, k), gd.sy, gu.ny, hy, inv_m);
 }
 
-__global__ __launch_bounds__(64) void grad_z_kernel(Grid gu, const double *__restrict__ u, Grid gd, double *uz,
-                                                    double hz, const double *__restrict__ inv_m) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(kLineWg) void grad_z_kernel(Grid gu, const double *__restrict__ u, Grid gd, double *uz,
+                                                         double hz, const double *__restrict__ inv_m) {
+  const int i = blockIdx.x * kLineWg + threadIdx.x;
   const int j = blockIdx.y;
   if (i > gu.nx) return;
   line_solve(u, gu.at(i, j, 0), gu.sz, uz, gd.at(i, j, 0), gd.sz, gu.nz, hz, inv_m);
@@ -388,8 +403,9 @@ void launch_gradient(const Grid &gu, const double *u, const Grid &gd, double *ux
     grad_x_short_kernel<<<std::min(nlines, 8192), 64, 0, st>>>(gu, u, gd, ux, hx, inv_m_x);
   else
     grad_x_scan_kernel<<<nlines, 64, (size_t)nseg * sizeof(double), st>>>(gu, u, gd, ux, hx, inv_m_x);
-  grad_y_kernel<<<dim3((gu.nx + 1 + 63) / 64, gu.nz + 1), 64, 0, st>>>(gu, u, gd, uy, hy, inv_m_y);
-  grad_z_kernel<<<dim3((gu.nx + 1 + 63) / 64, gu.ny + 1), 64, 0, st>>>(gu, u, gd, uz, hz, inv_m_z);
+  const int nbx = (gu.nx + kLineWg) / kLineWg;  // x blocks of nx + 1 nodes
+  grad_y_kernel<<<nbx * ((gu.nz + 1 + kXcd - 1) / kXcd) * kXcd, kLineWg, 0, st>>>(gu, u, gd, uy, hy, inv_m_y);
+  grad_z_kernel<<<dim3(nbx, gu.ny + 1), kLineWg, 0, st>>>(gu, u, gd, uz, hz, inv_m_z);
 }
 
 }  // namespace excmg

@@ -66,7 +66,7 @@ __global__ void check_finite_kernel(const double *__restrict__ a, long long n, i
 // Quartic Lagrange weights (x128) at the odd fine offsets t = 1, 3, 5, 7 inside an interpolation cell whose known
 // values sit at the even offsets 0, 2, 4, 6, 8 (the cell is 2x2x2 elements of the 4h grid = 8 fine elements per
 // axis).  They are the Lagrange basis polynomials on the nodes 0..4 evaluated at t/2 = 0.5, 1.5, 2.5, 3.5.
-__constant__ double kQw[4][5] = {
+constexpr double kQw[4][5] = {
     {35.0 / 128, 140.0 / 128, -70.0 / 128, 28.0 / 128, -5.0 / 128},
     {-5.0 / 128, 60.0 / 128, 90.0 / 128, -20.0 / 128, 3.0 / 128},
     {3.0 / 128, -20.0 / 128, 90.0 / 128, 60.0 / 128, -5.0 / 128},
@@ -79,9 +79,16 @@ constexpr int EX4 = 2 * CXN + 1;     // 4h nodes along x
 constexpr int EXF = 8 * CXN + 1;     // fine nodes along x
 constexpr int ET = 256;
 
-// quartic interpolation of five values at the odd offset t (0..3 for offsets 1, 3, 5, 7)
-__device__ __forceinline__ double quartic(int t, double a0, double a1, double a2, double a3, double a4) {
-  return kQw[t][0] * a0 + kQw[t][1] * a1 + kQw[t][2] * a2 + kQw[t][3] * a3 + kQw[t][4] * a4;
+// quartic interpolation of five values at the odd offset T (0..3 for offsets 1, 3, 5, 7): the weights are
+// compile-time constants
+template <int T>
+__device__ __forceinline__ double quartic(double a0, double a1, double a2, double a3, double a4) {
+  return kQw[T][0] * a0 + kQw[T][1] * a1 + kQw[T][2] * a2 + kQw[T][3] * a3 + kQw[T][4] * a4;
+}
+// the same with a run-time offset t, from a copy of the weights in LDS
+__device__ __forceinline__ double quartic(const double (*q)[5], int t, double a0, double a1, double a2, double a3,
+                                          double a4) {
+  return q[t][0] * a0 + q[t][1] * a1 + q[t][2] * a2 + q[t][3] * a3 + q[t][4] * a4;
 }
 
 // One workgroup per CXN x 1 x 1 interpolation cells.
@@ -91,8 +98,9 @@ __device__ __forceinline__ double quartic(int t, double a0, double a1, double a2
 //     (zhongdian), at face and element centres the mean over the 2 face / 4 space diagonals of eq. (zhongdian): all
 //     four rules are the same tri-linear interpolation of delta with the factor 1/16;
 //  3. tri-quartic interpolation (eq. inter) applied separably, x then y then z (the 604x125 cell matrix is the
-//     tensor product of the 1D quartic weights): the x pass through LDS, then one thread per (x, y) column that
-//     interpolates its five z layers in y from the x-pass values and then produces its nine z outputs;
+//     tensor product of the 1D quartic weights): the x pass through LDS (one thread per cell, row and layer, so
+//     that the four odd offsets have constant weights), then one thread per (x, y) column that interpolates its five
+//     z layers in y from the x-pass values and then produces its nine z outputs;
 //  4. boundary nodes get g.
 __device__ void exp_finite_block(const Grid &g2, const double *__restrict__ u2, const Grid &g4,
                                  const double *__restrict__ u4, const Grid &gg, const double *__restrict__ gdat, int s,
@@ -100,10 +108,12 @@ __device__ void exp_finite_block(const Grid &g2, const double *__restrict__ u2, 
   __shared__ double W[5][5][EX2];
   __shared__ double D[3][3][EX4];
   __shared__ double Wx[5][5][EXF];
+  __shared__ double Q[4][5];
+  if (threadIdx.x < 20) Q[threadIdx.x / 5][threadIdx.x % 5] = kQw[threadIdx.x / 5][threadIdx.x % 5];
   const int ncx = gw.nx / 8, ncy = gw.ny / 8, ncz = gw.nz / 8;
   const int cx0 = bx * CXN;
   const int nc = min(CXN, ncx - cx0);  // cells in this workgroup (fewer in the last one along x)
-  const int n2x = 4 * nc + 1, n4x = 2 * nc + 1, nfx = 8 * nc + 1;
+  const int n2x = 4 * nc + 1, n4x = 2 * nc + 1;
   const int tid = threadIdx.x;
   const int I0 = 4 * cx0, J0 = 4 * cj, K0 = 4 * ck;  // 2h-grid origin of the slab
   // Index decompositions use the full-slab extents (compile-time divisors); entries past a short slab are skipped.
@@ -128,19 +138,24 @@ __device__ void exp_finite_block(const Grid &g2, const double *__restrict__ u2, 
     W[c][b][a] += d * (1.0 / 128.0);  // (1/16) * (1/8) * sum over the 8 corner slots
   }
   __syncthreads();
-  // 3a. x
-  for (int e = tid; e < 25 * EXF; e += ET) {
-    const int xf = e % EXF, bc = e / EXF, b = bc % 5, c = bc / 5;
-    if (xf >= nfx) continue;
-    double v;
-    if (!(xf & 1)) {
-      v = W[c][b][xf >> 1];
-    } else {
-      const int base = (xf >> 3) * 4;
-      v = quartic((xf & 7) >> 1, W[c][b][base], W[c][b][base + 1], W[c][b][base + 2], W[c][b][base + 3],
-                  W[c][b][base + 4]);
+  // 3a. x: one thread per (cell, row b, layer c) writes the cell's fine offsets 0..7 (the last cell also 8)
+  static_assert(CXN * 25 <= ET, "one x-pass item per thread");
+  if (tid < 25 * CXN) {
+    const int cx = tid % CXN, bc = tid / CXN, b = bc % 5, c = bc / 5;
+    if (cx < nc) {
+      const double *wr = &W[c][b][4 * cx];
+      const double a0 = wr[0], a1 = wr[1], a2 = wr[2], a3 = wr[3], a4 = wr[4];
+      double *o = &Wx[c][b][8 * cx];
+      o[0] = a0;
+      o[1] = quartic<0>(a0, a1, a2, a3, a4);
+      o[2] = a1;
+      o[3] = quartic<1>(a0, a1, a2, a3, a4);
+      o[4] = a2;
+      o[5] = quartic<2>(a0, a1, a2, a3, a4);
+      o[6] = a3;
+      o[7] = quartic<3>(a0, a1, a2, a3, a4);
+      if (cx == nc - 1) o[8] = a4;
     }
-    Wx[c][b][xf] = v;
   }
   __syncthreads();
   // 3c. z and 4. write, one thread per (xf, yf) column.  Along x a workgroup writes offsets 1..8nc of its slab (the
@@ -158,22 +173,21 @@ __device__ void exp_finite_block(const Grid &g2, const double *__restrict__ u2, 
     double a[5];
 #pragma unroll
     for (int c = 0; c < 5; ++c)
-      a[c] = (yf & 1) ? quartic(yf >> 1, Wx[c][0][xf], Wx[c][1][xf], Wx[c][2][xf], Wx[c][3][xf], Wx[c][4][xf])
+      a[c] = (yf & 1) ? quartic(Q, yf >> 1, Wx[c][0][xf], Wx[c][1][xf], Wx[c][2][xf], Wx[c][3][xf], Wx[c][4][xf])
                       : Wx[c][yf >> 1][xf];
     const double a0 = a[0], a1 = a[1], a2 = a[2], a3 = a[3], a4 = a[4];
     const bool side = (gi == 0 || gj == 0 || gi == gw.nx || gj == gw.ny);
-    for (int zf = 0; zf < oz; ++zf) {
-      const int gk = gk0 + zf;
-      double v;
-      if (side || gk == 0 || gk == gw.nz) {
-        v = gdat ? gdat[gg.at(gi * s, gj * s, gk * s)] : 0.0;
-      } else if (!(zf & 1)) {
-        v = (zf == 0) ? a0 : (zf == 2) ? a1 : (zf == 4) ? a2 : (zf == 6) ? a3 : a4;
-      } else {
-        v = quartic(zf >> 1, a0, a1, a2, a3, a4);
+    const double zv[9] = {a0, quartic<0>(a0, a1, a2, a3, a4), a1, quartic<1>(a0, a1, a2, a3, a4), a2,
+                          quartic<2>(a0, a1, a2, a3, a4), a3, quartic<3>(a0, a1, a2, a3, a4), a4};
+#pragma unroll
+    for (int zf = 0; zf < 9; ++zf) {
+      if (zf < oz) {
+        const int gk = gk0 + zf;
+        double v = zv[zf];
+        if (side || gk == 0 || gk == gw.nz) v = gdat ? gdat[gg.at(gi * s, gj * s, gk * s)] : 0.0;
+        if (nt) __builtin_nontemporal_store(v, &w[gw.at(gi, gj, gk)]);
+        else w[gw.at(gi, gj, gk)] = v;
       }
-      if (nt) __builtin_nontemporal_store(v, &w[gw.at(gi, gj, gk)]);
-      else w[gw.at(gi, gj, gk)] = v;
     }
   };
   for (int e = tid; e < 64 * 9; e += ET) {
@@ -197,8 +211,11 @@ __global__ __launch_bounds__(ET) void exp_finite_kernel(Grid g2, const double *_
 // u~ = u_h + delta_avg / 15 where delta = u_h - u_2h at the 2h nodes and delta_avg its mean over the corners of the
 // 2h edge/face/element the node is the midpoint of: eq. (t1) at 2h nodes, eq. (chenlin) at edge midpoints, and its
 // mean over the 2 face / 4 space diagonals at face / element centres.
-// A workgroup owns a 64 x 4 x 8 block of fine nodes (origin even on every axis): it first forms delta on the block's
-// 33 x 3 x 5 even nodes in LDS, then every thread writes 8 nodes of one (x, y) column.
+// A workgroup owns the fine nodes x0+1 .. x0+64, y0+1 .. y0+4, z0+1 .. z0+8 (x0, y0, z0 multiples of the block
+// size; the first block along an axis also takes node 0): it first forms delta on the 33 x 3 x 5 even nodes
+// x0 .. x0+64, ... in LDS, then every thread writes the 8 (or 9) nodes of its (x, y) column.  Starting the blocks at
+// offset 1 keeps the row segments of u_h on whole 128-byte lines and leaves no block with a single node along an
+// axis.
 constexpr int TTX = 64, TTY = 4, TTZ = 8;
 constexpr int DTX = TTX / 2 + 1, DTY = TTY / 2 + 1, DTZ = TTZ / 2 + 1;
 
@@ -208,7 +225,10 @@ __global__ __launch_bounds__(TTX *TTY) void exp_true_kernel(Grid gh, const doubl
                                                            const double *__restrict__ u2, Grid gt,
                                                            double *__restrict__ ut, double *__restrict__ ucopy) {
   __shared__ double D[DTZ][DTY][DTX];
-  const int x0 = blockIdx.x * TTX, y0 = blockIdx.y * TTY, z0 = blockIdx.z * TTZ;
+  // blockIdx.x runs along y: consecutive workgroups (which the hardware deals out to the XCDs in turn) take
+  // different rows, so all the blocks of one row segment run on one XCD and no cache line is written from two
+  const int bx = blockIdx.y, by = blockIdx.x;
+  const int x0 = bx * TTX, y0 = by * TTY, z0 = blockIdx.z * TTZ;
   const int tid = threadIdx.x;
   for (int e = tid; e < DTX * DTY * DTZ; e += TTX * TTY) {
     const int a = e % DTX, bc = e / DTX, b = bc % DTY, c = bc / DTY;
@@ -219,20 +239,34 @@ __global__ __launch_bounds__(TTX *TTY) void exp_true_kernel(Grid gh, const doubl
   }
   __syncthreads();
   const int lx = tid % TTX, ly = tid / TTX;
-  const int i = x0 + lx, j = y0 + ly;
-  if (i > gh.nx || j > gh.ny) return;
-  const int al = lx >> 1, ah = (lx + 1) >> 1, bl = ly >> 1, bh = (ly + 1) >> 1;
-  const int zend = min(TTZ, gh.nz + 1 - z0);
-  for (int q = 0; q < zend; ++q) {
-    const int k = z0 + q;
-    const int cl = q >> 1, ch = (q + 1) >> 1;
-    const double d = ((D[cl][bl][al] + D[cl][bl][ah]) + (D[cl][bh][al] + D[cl][bh][ah])) +
-                     ((D[ch][bl][al] + D[ch][bl][ah]) + (D[ch][bh][al] + D[ch][bh][ah]));
-    const double v = uh[gh.at(i, j, k)];
-    // the outputs are the caller's: streaming stores
-    __builtin_nontemporal_store(v + d * (1.0 / 120.0), &ut[gt.at(i, j, k)]);  // (1/15) (1/8) sum of the 8 slots
-    if (ucopy) __builtin_nontemporal_store(v, &ucopy[gt.at(i, j, k)]);
-  }
+  const bool z_first = (blockIdx.z == 0);
+  // column (x0 + ox, y0 + oy), local offsets ox in 0..64, oy in 0..4
+  auto column = [&](int ox, int oy) {
+    const int i = x0 + ox, j = y0 + oy;
+    if (i > gh.nx || j > gh.ny) return;
+    const int al = ox >> 1, ah = (ox + 1) >> 1, bl = oy >> 1, bh = (oy + 1) >> 1;
+    double dxy[DTZ];  // the four corner slots in x and y of every even z layer of the block
+#pragma unroll
+    for (int c = 0; c < DTZ; ++c) dxy[c] = (D[c][bl][al] + D[c][bl][ah]) + (D[c][bh][al] + D[c][bh][ah]);
+    auto put = [&](int q, double v) {  // z offset q in 0..8, u_h there
+      const int k = z0 + q;
+      const double d = dxy[q >> 1] + dxy[(q + 1) >> 1];
+      // the outputs are the caller's: streaming stores
+      __builtin_nontemporal_store(v + d * (1.0 / 120.0), &ut[gt.at(i, j, k)]);  // (1/15) (1/8) sum of the 8 slots
+      if (ucopy) __builtin_nontemporal_store(v, &ucopy[gt.at(i, j, k)]);
+    };
+    if (z_first) put(0, uh[gh.at(i, j, z0)]);
+    double v[TTZ];  // all of the column's loads first (planes past the grid read its last plane and are not stored)
+#pragma unroll
+    for (int q = 1; q <= TTZ; ++q) v[q - 1] = uh[gh.at(i, j, min(z0 + q, gh.nz))];
+#pragma unroll
+    for (int q = 1; q <= TTZ; ++q)
+      if (z0 + q <= gh.nz) put(q, v[q - 1]);
+  };
+  column(1 + lx, 1 + ly);
+  if (bx == 0 && lx == 0) column(0, 1 + ly);
+  if (by == 0 && ly == 0) column(1 + lx, 0);
+  if (bx == 0 && by == 0 && tid == 0) column(0, 0);
 }
 
 // ------------------------------------------------------------------------------------------------------- adjoint
@@ -333,7 +367,7 @@ void launch_exp_finite(const Grid &g2, const double *u2, const Grid &g4, const d
 
 void launch_exp_true(const Grid &gh, const double *uh, const Grid &g2, const double *u2, const Grid &gt, double *ut,
                      double *ucopy, hipStream_t st) {
-  dim3 grid((gh.nx + 1 + TTX - 1) / TTX, (gh.ny + 1 + TTY - 1) / TTY, (gh.nz + 1 + TTZ - 1) / TTZ);
+  dim3 grid((gh.ny + TTY - 1) / TTY, (gh.nx + TTX - 1) / TTX, (gh.nz + TTZ - 1) / TTZ);
   exp_true_kernel<<<grid, TTX * TTY, 0, st>>>(gh, uh, g2, u2, gt, ut, ucopy);
 }
 
