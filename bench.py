@@ -38,8 +38,8 @@ def unknown_iters(st):
 
 def trace_summary(db, top=30):
     """Per-kernel summary of a rocprofv3 database (kernel trace and/or counters), grouped by kernel and grid size.
-    A CG launch made after its grid converged returns at once; launches shorter than a fifth of the longest of their
-    group are counted as such early exits and left out of the 'working' average."""
+    A CG launch made after its grid converged returns at once; launches shorter than half the longest of their group
+    (early exits, or a coarser grid's launches of the same shape) are left out of the 'working' average."""
     import re
     import sqlite3
 
@@ -59,7 +59,7 @@ def trace_summary(db, top=30):
         print(f"{'kernel':44s} {'grid':>9s} {'wg':>5s} {'calls':>6s} {'total_ms':>9s} {'avg_us':>9s} "
               f"{'working':>7s} {'work_avg_us':>11s}")
         for (nm, gx, wx), ds in sorted(groups.items(), key=lambda kv: -sum(kv[1]))[:top]:
-            w = [d for d in ds if d >= 0.2 * max(ds)]
+            w = [d for d in ds if d >= 0.5 * max(ds)]
             print(f"{nm:44s} {gx:9d} {wx:5d} {len(ds):6d} {sum(ds) / 1e6:9.3f} {sum(ds) / len(ds) / 1e3:9.2f} "
                   f"{len(w):7d} {sum(w) / len(w) / 1e3:11.2f}")
     pm = c.execute("select kernel_name, grid_size, counter_name, value from counters_collection").fetchall()
@@ -67,10 +67,10 @@ def trace_summary(db, top=30):
         groups = {}
         for nm, gx, cn, v in pm:
             groups.setdefault((clean(nm), gx, cn), []).append(v)
-        print("counters (per dispatch; 'working' = dispatches with at least a fifth of the group's largest value)")
+        print("counters (per dispatch; 'working' = dispatches with at least half of the group's largest value)")
         print(f"{'kernel':44s} {'grid':>9s} {'counter':>12s} {'calls':>6s} {'working':>7s} {'work_avg':>14s}")
         for (nm, gx, cn), vs in sorted(groups.items(), key=lambda kv: -max(kv[1]))[:top]:
-            w = [v for v in vs if v >= 0.2 * max(vs)]
+            w = [v for v in vs if v >= 0.5 * max(vs)]
             print(f"{nm:44s} {gx:9d} {cn:>12s} {len(vs):6d} {len(w):7d} {sum(w) / max(len(w), 1):14.1f}")
 
 
@@ -168,10 +168,11 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def counter_summary(fetch_db, write_db):
+def counter_summary(fetch_db, write_db, min_bytes=512 << 20):
     """HBM bytes per dispatch from a FETCH_SIZE run and a WRITE_SIZE run (KiB per dispatch), each scaled so that the
     probe's copy kernel (PROBE_BYTES/2 read, PROBE_BYTES/2 written) reads its known size.  One JSON line per
-    (kernel, grid size), for the working dispatches (at least a fifth of the group's largest value)."""
+    (kernel, grid size) that moves at least min_bytes, for the working dispatches (at least half of the group's
+    largest value: this drops launches that return at once and a coarser grid's launches of the same shape)."""
     import re
     import sqlite3
 
@@ -183,7 +184,7 @@ def counter_summary(fetch_db, write_db):
                 continue
             nm = re.sub(r"\(.*", "", nm.replace("excmg::(anonymous namespace)::", "").replace("void ", ""))
             g.setdefault((nm, gx), []).append(v)
-        return {k: [x for x in v if x >= 0.2 * max(v)] for k, v in g.items() if max(v) > 0}
+        return {k: [x for x in v if x >= 0.5 * max(v)] for k, v in g.items() if max(v) > 0}
 
     fetch, write = load(fetch_db, "FETCH_SIZE"), load(write_db, "WRITE_SIZE")
     probe = [k for k in fetch if k[0] == "probe_copy_kernel"]
@@ -196,8 +197,10 @@ def counter_summary(fetch_db, write_db):
     for k in sorted(set(fetch) & set(write)):
         fb = float(np.mean(fetch[k])) * 1024 * fk
         wb = float(np.mean(write[k])) * 1024 * wk
-        print(json.dumps({"kernel": k[0], "grid": k[1], "dispatches": len(fetch[k]), "read_bytes": round(fb),
-                          "write_bytes": round(wb), "hbm_bytes": round(fb + wb)}))
+        if fb + wb < min_bytes:
+            continue
+        print(json.dumps({"kernel": k[0], "grid": k[1], "n": len(fetch[k]), "read": round(fb), "write": round(wb),
+                          "hbm_bytes": round(fb + wb)}))
 
 
 def measured_traffic(kernel, grid):
@@ -298,8 +301,9 @@ def main():
     # measured HBM bytes of the same kernel and launch shape (z chunk) from the committed counter runs
     zc_dom = zc64[-1][0 if dom == "cg_a" else 1]
     grid_threads = -(-(N - 1) // 64) * -(-(N - 1) // 4) * -(-(N - 1) // zc_dom) * 256
-    traffic = measured_traffic("cg_pass_a_kernel<double>" if dom == "cg_a" else "cg_pass_b_kernel<double>",
-                               grid_threads)
+    dvar = dp64[-1][0 if dom == "cg_a" else 1]  # prefetch depth, plus 10 for the non-temporal policy
+    kname = f"cg_pass_{dom[-1]}_kernel<double, {dvar % 10}, {'true' if dvar >= 10 else 'false'}>"
+    traffic = measured_traffic(kname, grid_threads)
     # stencil-CG sweeps of the finest grid alone: unknown-iterations per second of pass A + pass B kernel time
     fin_iters = stats[-1]["iters"][-1]
     cg_ms_fin = sum(st["kernel_ms_finest"]["cg_a"] + st["kernel_ms_finest"]["cg_b"] +
@@ -328,7 +332,7 @@ def main():
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": round(traffic / (avg_ms * 1e-3) / 1e9, 1) if traffic else None,
-                     "traffic_bytes_per_launch": traffic, "traffic_grid": grid_threads,
+                     "traffic_bytes_per_launch": traffic, "traffic_kernel": kname, "traffic_grid": grid_threads,
                      "avg_launch_ms": round(avg_ms, 4), "bytes_per_launch": BYTES_PER_UNKNOWN[dom] * nI,
                      "probe_copy_GBs": round(copy_gbs, 1), "probe_read_GBs": round(read_gbs, 1),
                      "frac_of_probe_copy": round(achieved / copy_gbs, 4)},

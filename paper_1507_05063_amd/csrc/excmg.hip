@@ -97,6 +97,9 @@ int validate(const excmg_problem *p) {
   return EXCMG_OK;
 }
 
+// z planes per workgroup of the residual sweeps on large grids
+constexpr int kResidChunk = 64;
+
 int make_layout(const excmg_problem *p, Layout *Lo) {
   int e = validate(p);
   if (e) return e;
@@ -114,10 +117,12 @@ int make_layout(const excmg_problem *p, Layout *Lo) {
     lv.g = pitched_grid<double>(lv.n[0], lv.n[1], lv.n[2]);
     lv.g32 = pitched_grid<float>(lv.n[0], lv.n[1], lv.n[2]);
     lv.st = make_stencil(lv.h[0], lv.h[1], lv.h[2]);
-    // the residual sweep runs once per grid: streaming stores when the grid is far larger than the caches
-    lv.sw = make_sweep(lv.g, lv.st, 0, 2, lv.g.interior() >= (1LL << 23) ? 1 : 0);
+    // The residual sweep runs once or twice per grid.  On grids far larger than the caches: streaming stores, and
+    // long z chunks, since every chunk reads two extra planes of u and of f.
+    const bool big = lv.g.interior() >= (1LL << 23);
+    lv.sw = make_sweep(lv.g, lv.st, big ? kResidChunk : 0, 2, big ? 1 : 0);
     lv.sw32 = make_sweep(lv.g32, lv.st, 0);
-    lv.swA = lv.swB = lv.sw;
+    lv.swA = lv.swB = make_sweep(lv.g, lv.st, 0, 2, big ? 1 : 0);
     lv.swA32 = lv.swB32 = lv.sw32;
     lv.u = nullptr;
     Lo->off_u[l] = off;

@@ -805,6 +805,9 @@ __global__ __launch_bounds__(FT) void finalize_b_kernel(CgState *cs, const doubl
 
 // A CG state in which the sweeps do their full work but change nothing that matters: iteration 0 (pass A reads only
 // r), alpha = 0 (pass B leaves u and r as they are), and a stopping test that never fires.
+// CG state for the autotuner's trial launches: a later iteration (pass A then reads r and p_old, as it does in
+// every iteration but the first), never converged, alpha = beta = 0.  The trials' results are discarded: a solve
+// writes these work buffers before it reads them.
 __global__ void tune_state_kernel(CgState *cs) {
   cs->rho = 1.0;
   cs->rho_old = 1.0;
@@ -813,7 +816,7 @@ __global__ void tune_state_kernel(CgState *cs) {
   cs->beta = 0.0;
   cs->bnorm2 = 1.0;
   cs->stop2 = -1.0;
-  cs->iter = 0;
+  cs->iter = 1;
   cs->done = 0;
   cs->status = 0;
   cs->max_iters = 1 << 30;
