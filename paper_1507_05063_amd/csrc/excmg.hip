@@ -100,6 +100,10 @@ int validate(const excmg_problem *p) {
 // z planes per workgroup of the residual sweeps on large grids
 constexpr int kResidChunk = 64;
 
+// Events that only take timestamps: no system-scope fence at record (the cache write-back and invalidation it
+// costs would sit between the timed kernels).  Results are read on the host only after a stream synchronization.
+constexpr unsigned kTimingEvent = hipEventDisableSystemFence;
+
 int make_layout(const excmg_problem *p, Layout *Lo) {
   int e = validate(p);
   if (e) return e;
@@ -1085,7 +1089,7 @@ int excmg_setup(const excmg_problem *p, void *workspace, size_t bytes, void *hip
     }
   }
   for (int l = 0; l <= EXCMG_MAX_LEVELS; ++l) {
-    if (hipEventCreate(&h->lev_ev[l]) != hipSuccess) {
+    if (hipEventCreateWithFlags(&h->lev_ev[l], kTimingEvent) != hipSuccess) {
       delete h;
       return EXCMG_ERR_HIP;
     }
@@ -1100,7 +1104,7 @@ int excmg_setup(const excmg_problem *p, void *workspace, size_t bytes, void *hip
   if (h->timing) {
     h->pool.resize(8192);
     for (auto &ev : h->pool)
-      if (hipEventCreate(&ev) != hipSuccess) {
+      if (hipEventCreateWithFlags(&ev, kTimingEvent) != hipSuccess) {
         delete h;
         return EXCMG_ERR_HIP;
       }
@@ -1192,8 +1196,8 @@ int excmg_autotune(excmg_handle *h, int32_t *zc_out, int32_t *depth_out) {
   static const int depths[] = {2, 3, 4, 6};
   constexpr int kVar = 2 * (int)(sizeof(depths) / sizeof(depths[0]));  // depth x cache policy
   hipEvent_t ea, eb;
-  HIPCHECK(hipEventCreate(&ea));
-  HIPCHECK(hipEventCreate(&eb));
+  HIPCHECK(hipEventCreateWithFlags(&ea, kTimingEvent));
+  HIPCHECK(hipEventCreateWithFlags(&eb, kTimingEvent));
   int rc = EXCMG_OK;
   for (int l = 2; l < lo.L && rc == EXCMG_OK; ++l) {
     Level &lv = lo.lev[l];
@@ -1370,8 +1374,8 @@ int excmg_bandwidth_probe(void *buf, size_t bytes, int32_t reps, void *hip_strea
   const long long n = (long long)(bytes / sizeof(double)) & ~3LL;  // doubles, a multiple of 4
   double *a = (double *)buf;
   hipEvent_t e0, e1;
-  HIPCHECK(hipEventCreate(&e0));
-  HIPCHECK(hipEventCreate(&e1));
+  HIPCHECK(hipEventCreateWithFlags(&e0, kTimingEvent));
+  HIPCHECK(hipEventCreateWithFlags(&e1, kTimingEvent));
   HIPCHECK(hipMemsetAsync(buf, 0, (size_t)n * sizeof(double), s));
   float best_c = 1e30f, best_r = 1e30f;
   int rc = EXCMG_OK;
