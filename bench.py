@@ -261,8 +261,10 @@ def main():
     g = torch.from_numpy(g_np).cuda()
     print(f"# workload {N}^3 cells, inputs resident: {f.numel() * 16 / 1e9:.2f} GB", file=sys.stderr, flush=True)
 
-    copy_gbs, read_gbs = ex.bandwidth_probe(PROBE_BYTES)
-    print(f"# streaming probe: copy {copy_gbs:.0f} GB/s, read {read_gbs:.0f} GB/s", file=sys.stderr, flush=True)
+    probe = ex.bandwidth_probe(PROBE_BYTES)
+    copy_gbs = probe["copy"]
+    print("# streaming probe (GB/s): " + ", ".join(f"{k} {v:.0f}" for k, v in probe.items()), file=sys.stderr,
+          flush=True)
     s = ex.Solver(n, p.box, args.tol, timing=True)
     zc64, dp64 = s.autotune(with_depth=True)
     print(f"# autotuned z chunks (A, B) per grid: {[z[:2] for z in zc64]}, depths {[d[:2] for d in dp64]}",
@@ -334,8 +336,8 @@ def main():
                      "traffic": round(traffic / (avg_ms * 1e-3) / 1e9, 1) if traffic else None,
                      "traffic_bytes_per_launch": traffic, "traffic_kernel": kname, "traffic_grid": grid_threads,
                      "avg_launch_ms": round(avg_ms, 4), "bytes_per_launch": BYTES_PER_UNKNOWN[dom] * nI,
-                     "probe_copy_GBs": round(copy_gbs, 1), "probe_read_GBs": round(read_gbs, 1),
-                     "frac_of_probe_copy": round(achieved / copy_gbs, 4)},
+                     "probe_GBs": {k: round(v, 1) for k, v in probe.items()},
+                     "frac_of_probe_mix_nt": round(achieved / probe["mix_nt"], 4)},
         "iters_per_grid": stats[-1]["iters"],
         "autotuned_z_chunks": [list(z[:2]) for z in zc64],
         "autotuned_depths": [list(d[:2]) for d in dp64],

@@ -174,12 +174,21 @@ int excmg_autotune(excmg_handle *h, int32_t *zc_out, int32_t *depth_out);
 void excmg_destroy(excmg_handle *h);
 const char *excmg_strerror(int code);
 
-/* Same-run bandwidth ceiling for the roofline: copies the first half of buf into the second half, and reads all of
- * buf, reps times each (after one warm-up pass), with streaming kernels of 16-byte accesses; reports the best rates in
- * GB/s (bytes read plus bytes written for the copy).  buf: device, at least 4096 bytes, 16-byte aligned; its contents
- * are overwritten. */
-int excmg_bandwidth_probe(void *buf, size_t bytes, int32_t reps, void *hip_stream, double *copy_GBs,
-                          double *read_GBs);
+/* Kinds of the bandwidth probe, in the order of its rates. */
+enum {
+  EXCMG_PROBE_COPY = 0,    /* first half of buf into the second half, ordinary loads and stores */
+  EXCMG_PROBE_READ = 1,    /* all of buf read, ordinary loads */
+  EXCMG_PROBE_COPY_NT = 2, /* the copy with non-temporal loads and stores */
+  EXCMG_PROBE_READ_NT = 3, /* the read with non-temporal loads */
+  EXCMG_PROBE_MIX_NT = 4,  /* buf as three arrays a, b, c: b += a/2, c -= a/2, non-temporal (pass B's 3 reads, 2 writes) */
+  EXCMG_PROBE_KINDS = 5
+};
+
+/* Same-run bandwidth ceilings for the roofline: each kind above reps times (after one warm-up pass), with streaming
+ * kernels of 16-byte accesses; GBs[kind] = the best rate in GB/s (bytes read plus bytes written).  buf: device, at
+ * least 4096 bytes, 16-byte aligned; its contents are overwritten.  GBs: host, EXCMG_PROBE_KINDS entries.
+ * Errors: EXCMG_ERR_ARG for a null or misaligned pointer, too few bytes or reps <= 0. */
+int excmg_bandwidth_probe(void *buf, size_t bytes, int32_t reps, void *hip_stream, double *GBs);
 
 /* ---- single steps of the path, on one grid of cells n = (Nx,Ny,Nz) and box (node arrays as above) ---- */
 

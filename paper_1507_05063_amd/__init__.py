@@ -14,7 +14,7 @@ from . import _lib
 from ._lib import ExcmgError, FP32_IR, FP64, K_CLASSES, LIB_PATH, NO_GRAPHS, WANT_HISTORY, WANT_TIMING
 
 __all__ = ["Solver", "ExcmgError", "FP64", "FP32_IR", "plan", "workspace_bytes", "op_apply", "op_rhs",
-           "op_exp_finite", "op_exp_true", "solve_batched", "batch_workspace_bytes", "bandwidth_probe", "K_CLASSES",
+           "op_exp_finite", "op_exp_true", "solve_batched", "batch_workspace_bytes", "bandwidth_probe", "PROBE_KINDS", "K_CLASSES",
            "LIB_PATH"]
 
 
@@ -197,15 +197,19 @@ def solve_batched(solvers, fs, gs, us=None, workspace=None, allow_noconv: bool =
     return us, [st[b].to_dict() for b in range(count)], [ms[b] for b in range(count)]
 
 
+PROBE_KINDS = ("copy", "read", "copy_nt", "read_nt", "mix_nt")
+
+
 def bandwidth_probe(nbytes: int = 2 << 30, reps: int = 5):
-    """Achievable HBM bandwidth in this process: (copy GB/s, read GB/s) of streaming kernels over nbytes."""
+    """Achievable HBM bandwidth in this process: GB/s of streaming kernels over nbytes, by kind: copy and read with
+    ordinary and with non-temporal accesses, and pass B's mix (three arrays read, two written, non-temporal)."""
     torch = _torch()
     buf = torch.empty(int(nbytes), dtype=torch.uint8, device="cuda")
-    c, r = ctypes.c_double(0.0), ctypes.c_double(0.0)
-    _lib.check(_lib.lib().excmg_bandwidth_probe(_ptr(buf), int(nbytes), int(reps), _stream_ptr(), ctypes.byref(c),
-                                                ctypes.byref(r)), "excmg_bandwidth_probe")
+    rates = (ctypes.c_double * len(PROBE_KINDS))()
+    _lib.check(_lib.lib().excmg_bandwidth_probe(_ptr(buf), int(nbytes), int(reps), _stream_ptr(), rates),
+               "excmg_bandwidth_probe")
     del buf
-    return c.value, r.value
+    return {k: rates[i] for i, k in enumerate(PROBE_KINDS)}
 
 
 def _n3(n):

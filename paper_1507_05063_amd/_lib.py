@@ -107,8 +107,7 @@ def lib():
                                      ctypes.POINTER(ctypes.c_double)], _I),
             "excmg_destroy": ([_P], None),
             "excmg_autotune": ([_P, _I32P, _I32P], _I),
-            "excmg_bandwidth_probe": ([_P, ctypes.c_size_t, ctypes.c_int32, _P, ctypes.POINTER(ctypes.c_double),
-                                       ctypes.POINTER(ctypes.c_double)], _I),
+            "excmg_bandwidth_probe": ([_P, ctypes.c_size_t, ctypes.c_int32, _P, ctypes.POINTER(ctypes.c_double)], _I),
             "excmg_strerror": ([_I], ctypes.c_char_p),
             "excmg_op_apply": ([_I32P, _D3, _P, _P, _P], _I),
             "excmg_op_rhs": ([_I32P, _D3, _P, _P, _P, _P], _I),

@@ -1367,41 +1367,44 @@ int excmg_op_exp_true(const int32_t n[3], const double *uh, const double *u2h, d
   return EXCMG_OK;
 }
 
-int excmg_bandwidth_probe(void *buf, size_t bytes, int32_t reps, void *hip_stream, double *copy_GBs,
-                          double *read_GBs) {
-  if (!buf || bytes < 4096 || reps <= 0 || ((uintptr_t)buf & 15)) return EXCMG_ERR_ARG;
+int excmg_bandwidth_probe(void *buf, size_t bytes, int32_t reps, void *hip_stream, double *GBs) {
+  if (!buf || bytes < 4096 || reps <= 0 || ((uintptr_t)buf & 15) || !GBs) return EXCMG_ERR_ARG;
   const hipStream_t s = (hipStream_t)hip_stream;
-  const long long n = (long long)(bytes / sizeof(double)) & ~3LL;  // doubles, a multiple of 4
+  const long long n = (long long)(bytes / sizeof(double)) & ~7LL;  // doubles, a multiple of 8
+  const long long m = (n / 3) & ~1LL;                              // doubles per array of the mix, even
   double *a = (double *)buf;
   hipEvent_t e0, e1;
   HIPCHECK(hipEventCreateWithFlags(&e0, kTimingEvent));
   HIPCHECK(hipEventCreateWithFlags(&e1, kTimingEvent));
   HIPCHECK(hipMemsetAsync(buf, 0, (size_t)n * sizeof(double), s));
-  float best_c = 1e30f, best_r = 1e30f;
+  // bytes each kind moves (read plus written)
+  const double moved[EXCMG_PROBE_KINDS] = {(double)n * 8, (double)n * 8, (double)n * 8, (double)n * 8,
+                                           5.0 * (double)m * 8};
+  float best[EXCMG_PROBE_KINDS];
+  for (float &v : best) v = 1e30f;
   int rc = EXCMG_OK;
   for (int rep = 0; rep <= reps && rc == EXCMG_OK; ++rep) {
-    float mc = 0.0f, mr = 0.0f;
-    if (hipEventRecord(e0, s) != hipSuccess) rc = EXCMG_ERR_HIP;
-    launch_probe_copy(a, a + n / 2, n / 2, s);
-    if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
-        hipEventElapsedTime(&mc, e0, e1) != hipSuccess)
-      rc = EXCMG_ERR_HIP;
-    if (hipEventRecord(e0, s) != hipSuccess) rc = EXCMG_ERR_HIP;
-    launch_probe_read(a, n, a, s);
-    if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
-        hipEventElapsedTime(&mr, e0, e1) != hipSuccess)
-      rc = EXCMG_ERR_HIP;
-    if (last_error() != EXCMG_OK) rc = EXCMG_ERR_HIP;
-    if (rep > 0) {  // the first pass warms up
-      if (mc < best_c) best_c = mc;
-      if (mr < best_r) best_r = mr;
+    for (int kind = 0; kind < EXCMG_PROBE_KINDS && rc == EXCMG_OK; ++kind) {
+      if (hipEventRecord(e0, s) != hipSuccess) rc = EXCMG_ERR_HIP;
+      switch (kind) {
+        case EXCMG_PROBE_COPY: launch_probe_copy(a, a + n / 2, n / 2, s); break;
+        case EXCMG_PROBE_READ: launch_probe_read(a, n, a, s); break;
+        case EXCMG_PROBE_COPY_NT: launch_probe_copy_nt(a, a + n / 2, n / 2, s); break;
+        case EXCMG_PROBE_READ_NT: launch_probe_read_nt(a, n, a, s); break;
+        default: launch_probe_mix_nt(a, a + m, a + 2 * m, m, s); break;
+      }
+      float ms = 0.0f;
+      if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+          hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+        rc = EXCMG_ERR_HIP;
+      if (last_error() != EXCMG_OK) rc = EXCMG_ERR_HIP;
+      if (rep > 0 && ms < best[kind]) best[kind] = ms;  // the first pass warms up
     }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (rc) return rc;
-  if (copy_GBs) *copy_GBs = (double)n * sizeof(double) / (best_c * 1e-3) / 1e9;  // n/2 read + n/2 written
-  if (read_GBs) *read_GBs = (double)n * sizeof(double) / (best_r * 1e-3) / 1e9;
+  for (int kind = 0; kind < EXCMG_PROBE_KINDS; ++kind) GBs[kind] = moved[kind] / (best[kind] * 1e-3) / 1e9;
   return EXCMG_OK;
 }
 

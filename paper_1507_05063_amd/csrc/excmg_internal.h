@@ -186,6 +186,9 @@ void launch_residual_cast(const Sweep &sw, const double *u, const RhsSrc &rs, do
 // achievable-bandwidth probes over a caller buffer: copy of the first half into the second, and a read of the whole
 void launch_probe_copy(const double *src, double *dst, long long n, hipStream_t st);
 void launch_probe_read(const double *src, long long n, double *sink, hipStream_t st);
+void launch_probe_copy_nt(const double *src, double *dst, long long n, hipStream_t st);
+void launch_probe_read_nt(const double *src, long long n, double *sink, hipStream_t st);
+void launch_probe_mix_nt(const double *a, double *b, double *c, long long n, hipStream_t st);
 
 // one CG iteration with the reductions finalized inside the sweeps: pass A reads nb_prev partial sums from partsB
 // (the residual's [r.r | b.b] before iteration 0, pass B's r.r afterwards) and writes partsA; pass B reads nbA from

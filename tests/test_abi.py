@@ -156,3 +156,18 @@ def test_batched_argument_errors(abi):
     P = (ctypes.c_void_p * 1)(None)
     assert L.excmg_solve_batched(H, 1, P, P, P, None, 0, None, None) == _lib.ERR_ARG
     assert L.excmg_solve_batched(H, 0, P, P, P, None, 0, None, None) == _lib.ERR_ARG
+
+
+def test_bandwidth_probe_argument_errors(abi):
+    """Argument checks of the probe return before any device call; the kinds match the header's enum."""
+    import paper_1507_05063_amd as ex
+
+    L = abi.lib()
+    rates = (ctypes.c_double * len(ex.PROBE_KINDS))()
+    assert L.excmg_bandwidth_probe(None, 1 << 20, 1, None, rates) == abi.ERR_ARG
+    assert L.excmg_bandwidth_probe(ctypes.c_void_p(16), 1024, 1, None, rates) == abi.ERR_ARG  # too few bytes
+    assert L.excmg_bandwidth_probe(ctypes.c_void_p(8), 1 << 20, 1, None, rates) == abi.ERR_ARG  # misaligned
+    assert L.excmg_bandwidth_probe(ctypes.c_void_p(16), 1 << 20, 0, None, rates) == abi.ERR_ARG  # no reps
+    assert L.excmg_bandwidth_probe(ctypes.c_void_p(16), 1 << 20, 1, None, None) == abi.ERR_ARG  # no output
+    src = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    assert int(re.search(r"EXCMG_PROBE_KINDS\s*=\s*(\d+)", src).group(1)) == len(ex.PROBE_KINDS)

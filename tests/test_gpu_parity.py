@@ -265,3 +265,12 @@ def test_config2_512_fp64_full_oracle(ex, orc):
     # error (about 1e-11), so the bound is on that tolerance-limited level, not on h^4.
     err = np.max(np.abs(ug - u))
     assert err < 5e-9
+
+
+def test_bandwidth_probe(ex):
+    """Every probe kind reports a plausible rate over a buffer 4x the last-level cache: above 0.1 TB/s, and not above
+    the part's 8 TB/s by more than what the cache can add."""
+    rates = ex.bandwidth_probe(1 << 30, reps=2)
+    assert set(rates) == set(ex.PROBE_KINDS)
+    for k, v in rates.items():
+        assert 100.0 < v < 12000.0, (k, v)
