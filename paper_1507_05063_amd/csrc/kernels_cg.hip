@@ -529,7 +529,7 @@ __device__ double block_fixed_sum(const double *a, int n, double *sh) {
 
 // Pass A of iteration k = iterA: the stopping test on rho_k (Algorithm 1, the while condition), then
 // p = r + beta p with beta = rho_k / rho_{k-1}, partial sums of p.Mp into partsA.
-template <typename T>
+template <typename T, int D, bool NTP>
 __global__ __launch_bounds__(NT) void cg_selfred_a_kernel(Sweep sw, const T *__restrict__ r, T *p0, T *p1,
                                                           CgState *cs, const double *partsB, int nbB, double tol,
                                                           double *partsA) {
@@ -571,21 +571,21 @@ __global__ __launch_bounds__(NT) void cg_selfred_a_kernel(Sweep sw, const T *__r
     if (!finite || conv || cap) cs->done = 1;
   }
   if (!finite || conv || cap) return;
-  PolA<T> pol;
+  PolA<T, NTP> pol;
   pol.r = r;
   pol.pnew = (k & 1) ? p1 : p0;
   pol.first = (k == 0);
   pol.pold = pol.first ? r : ((k & 1) ? p0 : p1);
   pol.beta = (k == 0) ? T(0) : (T)(rho / cs->rhoA[(k - 1) & 1]);
   double a0 = 0.0, a1 = 0.0;
-  zmarch<T>(sw, pol, a0, a1, tile, nullptr, blockIdx.x, gridDim.x, true);
+  zmarch<T, D>(sw, pol, a0, a1, tile, nullptr, blockIdx.x, gridDim.x, true);
   const double v[1] = {a0};
   write_partials<1>(v, partsA, sh, blockIdx.x, gridDim.x);
 }
 
 // Pass B of iteration k = iterB: alpha = rho_k / p.Mp (from partsA), u += alpha p, r -= alpha Mp, partial sums of
 // r.r into partsB.
-template <typename T>
+template <typename T, int D, bool NTP>
 __global__ __launch_bounds__(NT) void cg_selfred_b_kernel(Sweep sw, T *u, T *r, const T *p0, const T *p1,
                                                           CgState *cs, const double *partsA, int nbA,
                                                           double *partsB) {
@@ -605,14 +605,14 @@ __global__ __launch_bounds__(NT) void cg_selfred_b_kernel(Sweep sw, T *u, T *r, 
     cs->iterA = k + 1;
   }
   if (bad) return;
-  PolB<T> pol;
+  PolB<T, NTP> pol;
   pol.p = (k & 1) ? p1 : p0;
   pol.u = u;
   pol.r = r;
   pol.alpha = (T)(cs->rhoA[k & 1] / pq);
   for (int q = 0; q < kMaxDepth; ++q) pol.pr[q] = pol.pu[q] = 0;
   double a0 = 0.0, a1 = 0.0;
-  zmarch<T>(sw, pol, a0, a1, tile, nullptr, blockIdx.x, gridDim.x, true);
+  zmarch<T, D>(sw, pol, a0, a1, tile, nullptr, blockIdx.x, gridDim.x, true);
   const double v[1] = {a0};
   write_partials<1>(v, partsB, sh, blockIdx.x, gridDim.x);
 }
@@ -1469,6 +1469,21 @@ long long cg_partials_needed(const Grid &g) {
   return 3LL * sweep_blocks(sw) + 64;
 }
 
+// f(depth, policy) with the sweep's prefetch depth and cache policy as compile-time constants.
+template <typename F>
+static void with_depth_policy(const Sweep &sw, F &&f) {
+  auto pol = [&](auto d) {
+    if (sw.nt) f(d, std::true_type{});
+    else f(d, std::false_type{});
+  };
+  switch (sw.depth) {
+    case 3: pol(std::integral_constant<int, 3>{}); break;
+    case 4: pol(std::integral_constant<int, 4>{}); break;
+    case 6: pol(std::integral_constant<int, 6>{}); break;
+    default: pol(std::integral_constant<int, 2>{}); break;
+  }
+}
+
 static void launch_boundary_terms(const RhsSrc &rs, const Grid &g, double *out, hipStream_t st) {
   if (rs.mode != 0) return;
   const int m = (g.nx > g.ny ? (g.nx > g.nz ? g.nx : g.nz) : (g.ny > g.nz ? g.ny : g.nz)) - 1;
@@ -1499,13 +1514,19 @@ void launch_selfred_init(CgState *cs, int max_iters, int hist_on, int preset, hi
 template <typename T>
 void launch_selfred_a(const Sweep &swA, const T *r, T *p0, T *p1, CgState *cs, const double *partsB, int nb_prev,
                       double tol, double *partsA, hipStream_t st) {
-  cg_selfred_a_kernel<T><<<sweep_blocks(swA), NT, 0, st>>>(swA, r, p0, p1, cs, partsB, nb_prev, tol, partsA);
+  with_depth_policy(swA, [&](auto d, auto n) {
+    cg_selfred_a_kernel<T, decltype(d)::value, decltype(n)::value>
+        <<<sweep_blocks(swA), NT, 0, st>>>(swA, r, p0, p1, cs, partsB, nb_prev, tol, partsA);
+  });
 }
 
 template <typename T>
 void launch_selfred_b(const Sweep &swB, T *u, T *r, const T *p0, const T *p1, CgState *cs, const double *partsA,
                       int nbA, double *partsB, hipStream_t st) {
-  cg_selfred_b_kernel<T><<<sweep_blocks(swB), NT, 0, st>>>(swB, u, r, p0, p1, cs, partsA, nbA, partsB);
+  with_depth_policy(swB, [&](auto d, auto n) {
+    cg_selfred_b_kernel<T, decltype(d)::value, decltype(n)::value>
+        <<<sweep_blocks(swB), NT, 0, st>>>(swB, u, r, p0, p1, cs, partsA, nbA, partsB);
+  });
 }
 
 template void launch_selfred_a<double>(const Sweep &, const double *, double *, double *, CgState *, const double *,
@@ -1538,21 +1559,6 @@ void launch_residual_cast(const Sweep &sw, const double *u, const RhsSrc &rs, do
   else if (v == 2) residual_cast_kernel<3, false><<<nb, NT, 0, st>>>(sw, u, rs, bterm, g32, r32, d32, partials);
   else residual_cast_kernel<3, true><<<nb, NT, 0, st>>>(sw, u, rs, bterm, g32, r32, d32, partials);
   finalize_ir_kernel<<<1, FT, 0, st>>>(outer, inner, partials, nb, tol, eta, outer_step, max_outer, max_inner);
-}
-
-// f(depth, policy) with the sweep's prefetch depth and cache policy as compile-time constants.
-template <typename F>
-static void with_depth_policy(const Sweep &sw, F &&f) {
-  auto pol = [&](auto d) {
-    if (sw.nt) f(d, std::true_type{});
-    else f(d, std::false_type{});
-  };
-  switch (sw.depth) {
-    case 3: pol(std::integral_constant<int, 3>{}); break;
-    case 4: pol(std::integral_constant<int, 4>{}); break;
-    case 6: pol(std::integral_constant<int, 6>{}); break;
-    default: pol(std::integral_constant<int, 2>{}); break;
-  }
 }
 
 template <typename T>
