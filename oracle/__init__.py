@@ -61,12 +61,16 @@ def lib():
             ("orc_adjoint", [_I, _I, _I, _D, _D, _D, _I, _I, _I, _P, _D, _I, _P, _P, _P, _P, _P, _P]),
             ("orc_apply_RT", [_I, _I, _I, _P, _P]),
             ("orc_apply_LIBT", g6 + [_P, _P]),
+            ("orc_initial_guess", [_I, _I, _I, _I, _P, _P, _P, _P]),
+            ("orc_excmg_guess", [_I, _I, _I, _I, _D, _D, _D, _I, _I, _I, _P, _P, _D, _I, _P, _P, _P, _P, _P]),
         ]:
             fn = getattr(L, name)
             fn.argtypes = args
             fn.restype = _I
         L.orc_lagrange4.argtypes = [_I, _D]
         L.orc_lagrange4.restype = _D
+        L.orc_lagrange2.argtypes = [_I, _D]
+        L.orc_lagrange2.restype = _D
         L.orc_set_threads.argtypes = [_I]
         L.orc_set_threads.restype = None
         L.orc_set_progress.argtypes = [_I]
@@ -194,6 +198,42 @@ def exp_finite(u2h, u4h, g):
     w = np.empty_like(g)
     _check(lib().orc_exp_finite(*n, _ptr(u2h), _ptr(u4h), _ptr(g), _ptr(w)), "exp_finite")
     return w
+
+
+GUESS_QUARTIC, GUESS_QUADRATIC, GUESS_LINEAR = 0, 1, 2
+GUESS_KINDS = {"quartic": GUESS_QUARTIC, "quadratic": GUESS_QUADRATIC, "linear": GUESS_LINEAR}
+
+
+def lagrange2(a: int, t: float) -> float:
+    return float(lib().orc_lagrange2(int(a), float(t)))
+
+
+def initial_guess(kind, u2h, u4h, g):
+    """The initial guess of the given kind ('quartic' = EXP_finite, 'quadratic', 'linear') on g's grid."""
+    k = GUESS_KINDS[kind] if isinstance(kind, str) else int(kind)
+    u2h, g = _c(u2h), _c(g)
+    u4h = None if u4h is None else _c(u4h)
+    n = _dims(g)
+    w = np.empty_like(g)
+    _check(lib().orc_initial_guess(k, *n, _ptr(u2h), _ptr(u4h), _ptr(g), _ptr(w)), "initial_guess")
+    return w
+
+
+def excmg_guess(kind, f, g, box, n_coarse, tol, max_iters=100000):
+    """Algorithm 1 with the initial guess of the given kind on every level from 2 on.
+    Returns dict(u, w, iters, relres): w is the finest level's initial guess."""
+    k = GUESS_KINDS[kind] if isinstance(kind, str) else int(kind)
+    f, g = _c(f), _c(g)
+    n = _dims(f)
+    nl = levels_for(n, n_coarse)
+    u, w = np.empty_like(f), np.empty_like(f)
+    iters = np.zeros(nl, dtype=np.int32)
+    relres = np.zeros(nl, dtype=np.float64)
+    code = lib().orc_excmg_guess(k, *n, *(float(v) for v in box), *(int(v) for v in n_coarse), _ptr(f), _ptr(g),
+                                 float(tol), int(max_iters), None, _ptr(u), _ptr(w) if nl >= 3 else None,
+                                 iters.ctypes.data, relres.ctypes.data)
+    _check(code, "excmg_guess")
+    return dict(u=u, w=w if nl >= 3 else None, iters=iters, relres=relres)
 
 
 def exp_true(uh, u2h):

@@ -466,9 +466,9 @@ static double delta_at(const void *vctx, int I, int J, int K) {
   return c->fine[fi] - c->coarse[ci];
 }
 
-int orc_exp_finite(int nx, int ny, int nz, const double *u2h, const double *u4h, const double *g, double *w) {
-  if (!u2h || !u4h || !g || !w) return ORC_ERR_ARG;
-  if (nx % 8 || ny % 8 || nz % 8 || nx < 8 || ny < 8 || nz < 8) return ORC_ERR_SHAPE;
+/* The known values of the fine grid's interpolation: the extrapolated value at every node of the 2h grid (which is a
+ * fine node with all offsets even), written into w there.  nx, ny, nz multiples of 4. */
+static void extrapolate_2h_nodes(int nx, int ny, int nz, const double *u2h, const double *u4h, double *w) {
   const int mx = nx / 2, my = ny / 2, mz = nz / 2; /* 2h grid */
   delta_ctx ctx;
   ctx.fine = u2h;
@@ -497,6 +497,12 @@ int orc_exp_finite(int nx, int ny, int nz, const double *u2h, const double *u4h,
         }
         w[NID(2 * I, 2 * J, 2 * K)] = v;
       }
+}
+
+int orc_exp_finite(int nx, int ny, int nz, const double *u2h, const double *u4h, const double *g, double *w) {
+  if (!u2h || !u4h || !g || !w) return ORC_ERR_ARG;
+  if (nx % 8 || ny % 8 || nz % 8 || nx < 8 || ny < 8 || nz < 8) return ORC_ERR_SHAPE;
+  extrapolate_2h_nodes(nx, ny, nz, u2h, u4h, w);
 
   /* 2. tri-quartic Lagrange interpolation (eq. inter) on each cell of 2x2x2 elements of the 4h grid (8x8x8 fine
    *    elements): the 604 remaining nodes of the cell from its 125 known nodes, natural coordinate t = offset/2. */
@@ -521,6 +527,86 @@ int orc_exp_finite(int nx, int ny, int nz, const double *u2h, const double *u4h,
             }
 
   /* 3. Dirichlet values on the boundary */
+  for (int k = 0; k <= nz; ++k)
+    for (int j = 0; j <= ny; ++j)
+      for (int i = 0; i <= nx; ++i)
+        if (is_bnd(nx, ny, nz, i, j, k)) w[NID(i, j, k)] = g[NID(i, j, k)];
+  return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------------------------------------------ */
+/* the other initial guesses the paper compares with (its remark on the interpolation order, Section 4.3, and the   */
+/* CMG method of Section 3)                                                                                     */
+/* ------------------------------------------------------------------------------------------------------------ */
+
+double orc_lagrange2(int a, double t) {
+  double v = 1.0;
+  for (int m = 0; m <= 2; ++m) {
+    if (m == a) continue;
+    v *= (t - (double)m) / ((double)a - (double)m);
+  }
+  return v;
+}
+
+int orc_initial_guess(int kind, int nx, int ny, int nz, const double *u2h, const double *u4h, const double *g,
+                      double *w) {
+  if (!u2h || !g || !w) return ORC_ERR_ARG;
+  if (kind == ORC_GUESS_QUARTIC) {
+    if (!u4h) return ORC_ERR_ARG;
+    return orc_exp_finite(nx, ny, nz, u2h, u4h, g, w);
+  }
+  if (kind == ORC_GUESS_QUADRATIC) {
+    if (!u4h) return ORC_ERR_ARG;
+    if (nx % 4 || ny % 4 || nz % 4 || nx < 4 || ny < 4 || nz < 4) return ORC_ERR_SHAPE;
+    extrapolate_2h_nodes(nx, ny, nz, u2h, u4h, w);
+    /* tri-quadratic Lagrange interpolation on each cell of 2x2x2 elements of the 2h grid (4x4x4 fine elements):
+     * the nodes of the cell with an odd offset from its 27 known nodes, natural coordinate t = offset/2 */
+    double lw[5][3];
+    for (int o = 0; o <= 4; ++o)
+      for (int a = 0; a <= 2; ++a) lw[o][a] = orc_lagrange2(a, 0.5 * (double)o);
+    const int cx = nx / 4, cy = ny / 4, cz = nz / 4;
+#pragma omp parallel for schedule(static)
+    for (int ck = 0; ck < cz; ++ck)
+      for (int cj = 0; cj < cy; ++cj)
+        for (int ci = 0; ci < cx; ++ci)
+          for (int ok = 0; ok <= 4; ++ok)
+            for (int oj = 0; oj <= 4; ++oj)
+              for (int oi = 0; oi <= 4; ++oi) {
+                if (!(oi & 1) && !(oj & 1) && !(ok & 1)) continue; /* a known node */
+                double s = 0.0;
+                for (int c = 0; c <= 2; ++c)
+                  for (int b = 0; b <= 2; ++b)
+                    for (int a = 0; a <= 2; ++a)
+                      s += lw[oi][a] * lw[oj][b] * lw[ok][c] * w[NID(4 * ci + 2 * a, 4 * cj + 2 * b, 4 * ck + 2 * c)];
+                w[NID(4 * ci + oi, 4 * cj + oj, 4 * ck + ok)] = s;
+              }
+  } else if (kind == ORC_GUESS_LINEAR) {
+    if (nx % 2 || ny % 2 || nz % 2 || nx < 2 || ny < 2 || nz < 2) return ORC_ERR_SHAPE;
+    /* trilinear interpolation of u_2h itself (no extrapolation): a fine node at 2h coordinates (i/2, j/2, k/2) is the
+     * weighted sum over the corners of the 2h element that holds it */
+    const int mx = nx / 2, my = ny / 2;
+#pragma omp parallel for schedule(static)
+    for (int k = 0; k <= nz; ++k)
+      for (int j = 0; j <= ny; ++j)
+        for (int i = 0; i <= nx; ++i) {
+          const int I0 = i / 2, J0 = j / 2, K0 = k / 2;
+          const double fx = 0.5 * (i % 2), fy = 0.5 * (j % 2), fz = 0.5 * (k % 2);
+          double s = 0.0;
+          for (int dk = 0; dk <= 1; ++dk)
+            for (int dj = 0; dj <= 1; ++dj)
+              for (int di = 0; di <= 1; ++di) {
+                const double wgt = (di ? fx : 1.0 - fx) * (dj ? fy : 1.0 - fy) * (dk ? fz : 1.0 - fz);
+                if (wgt == 0.0) continue; /* the corner past the grid's last node carries no weight */
+                const size_t ci = (((size_t)(K0 + dk)) * (size_t)(my + 1) + (size_t)(J0 + dj)) * (size_t)(mx + 1) +
+                                  (size_t)(I0 + di);
+                s += wgt * u2h[ci];
+              }
+          w[NID(i, j, k)] = s;
+        }
+  } else {
+    return ORC_ERR_ARG;
+  }
+  /* Dirichlet values on the boundary */
   for (int k = 0; k <= nz; ++k)
     for (int j = 0; j <= ny; ++j)
       for (int i = 0; i <= nx; ++i)
@@ -645,9 +731,9 @@ static void sample_stride(int nx, int ny, int nz, const double *fine, int s, int
 }
 
 /* shared cascade; mode 0: b_l from (f, g); mode 1: b_l = G on the interior, zero Dirichlet data */
-static int cascade(int mode, int nx, int ny, int nz, double lx, double ly, double lz, int ncx, int ncy, int ncz,
-                   const double *f, const double *g, double tol, int max_iters, const int *fixed_iters, double *u,
-                   double *ut, double *w_out, int *iters, double *relres, double *seconds) {
+static int cascade(int mode, int guess, int nx, int ny, int nz, double lx, double ly, double lz, int ncx, int ncy,
+                   int ncz, const double *f, const double *g, double tol, int max_iters, const int *fixed_iters,
+                   double *u, double *ut, double *w_out, int *iters, double *relres, double *seconds) {
   if (!f || !u || !iters || !relres) return ORC_ERR_ARG;
   if (mode == 0 && !g) return ORC_ERR_ARG;
   if (!(lx > 0) || !(ly > 0) || !(lz > 0) || !(tol > 0) || max_iters < 0) return ORC_ERR_ARG;
@@ -717,9 +803,9 @@ static int cascade(int mode, int nx, int ny, int nz, double lx, double ly, doubl
       free(tmp);
       free(rr);
     } else {
-      /* w_h = EXP_finite(u_2h, u_4h), then CG from w_h */
+      /* w_h = EXP_finite(u_2h, u_4h) (or the compared initial guess), then CG from w_h */
       const double *u2 = lev[l - 1], *u4 = lev[l - 2];
-      int e = orc_exp_finite(mx, my, mz, u2, u4, gl, ul);
+      int e = orc_initial_guess(guess, mx, my, mz, u2, u4, gl, ul);
       if (e) {
         status = e;
         goto done;
@@ -762,8 +848,16 @@ done:
 int orc_excmg(int nx, int ny, int nz, double lx, double ly, double lz, int ncx, int ncy, int ncz,
               const double *f, const double *g, double tol, int max_iters, const int *fixed_iters, double *u,
               double *ut, double *w_out, int *iters, double *relres, double *seconds) {
-  return cascade(0, nx, ny, nz, lx, ly, lz, ncx, ncy, ncz, f, g, tol, max_iters, fixed_iters, u, ut, w_out, iters,
-                 relres, seconds);
+  return cascade(0, ORC_GUESS_QUARTIC, nx, ny, nz, lx, ly, lz, ncx, ncy, ncz, f, g, tol, max_iters, fixed_iters, u,
+                 ut, w_out, iters, relres, seconds);
+}
+
+int orc_excmg_guess(int guess, int nx, int ny, int nz, double lx, double ly, double lz, int ncx, int ncy, int ncz,
+                    const double *f, const double *g, double tol, int max_iters, const int *fixed_iters, double *u,
+                    double *w_out, int *iters, double *relres) {
+  if (guess != ORC_GUESS_QUARTIC && guess != ORC_GUESS_QUADRATIC && guess != ORC_GUESS_LINEAR) return ORC_ERR_ARG;
+  return cascade(0, guess, nx, ny, nz, lx, ly, lz, ncx, ncy, ncz, f, g, tol, max_iters, fixed_iters, u, NULL, w_out,
+                 iters, relres, NULL);
 }
 
 /* ------------------------------------------------------------------------------------------------------------ */
@@ -818,7 +912,7 @@ int orc_adjoint(int nx, int ny, int nz, double lx, double ly, double lz, int ncx
   const size_t n = node_count(nx, ny, nz);
   double *lam = (double *)calloc(n, sizeof(double));
   if (!lam) return ORC_ERR_NOMEM;
-  int status = cascade(1, nx, ny, nz, lx, ly, lz, ncx, ncy, ncz, G, NULL, tol, max_iters, fixed_iters, lam, NULL,
+  int status = cascade(1, ORC_GUESS_QUARTIC, nx, ny, nz, lx, ly, lz, ncx, ncy, ncz, G, NULL, tol, max_iters, fixed_iters, lam, NULL,
                        NULL, iters, relres, NULL);
   if (status && status != ORC_ERR_NOCONV) {
     free(lam);

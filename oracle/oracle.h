@@ -76,6 +76,19 @@ double orc_lagrange4(int a, double t);
  * every interpolation cell of 2x2x2 elements of the 4h grid, then boundary nodes set to g. */
 int orc_exp_finite(int nx, int ny, int nz, const double *u2h, const double *u4h, const double *g, double *w);
 
+/* The initial guesses the paper compares: its own (ORC_GUESS_QUARTIC, = orc_exp_finite), the same extrapolation at
+ * the 2h nodes followed by tri-quadratic Lagrange interpolation on every cell of 2x2x2 elements of the 2h grid
+ * (ORC_GUESS_QUADRATIC: the interpolation of the earlier EXCMG for linear elements, which the remark in Section 4.3
+ * finds too inaccurate for a fourth-order solution), and trilinear interpolation of u_2h without extrapolation
+ * (ORC_GUESS_LINEAR: the CMG prolongation of Section 3).  Shapes: multiples of 8, 4 and 2.  u4h is not read by
+ * ORC_GUESS_LINEAR (may be NULL).  Boundary nodes of w are g. */
+#define ORC_GUESS_QUARTIC 0
+#define ORC_GUESS_QUADRATIC 1
+#define ORC_GUESS_LINEAR 2
+double orc_lagrange2(int a, double t);
+int orc_initial_guess(int kind, int nx, int ny, int nz, const double *u2h, const double *u4h, const double *g,
+                      double *w);
+
 /* EXP_true (Sections 4.2.1 and 4.3): sixth-order extrapolated solution on the fine grid from u_h (fine) and
  * u_2h (nx/2,...): eq. (t1) at coarse nodes, eq. (chenlin) and its diagonal means elsewhere.  nx, ny, nz even. */
 int orc_exp_true(int nx, int ny, int nz, const double *uh, const double *u2h, double *ut);
@@ -97,6 +110,11 @@ int orc_gradient(int nx, int ny, int nz, double hx, double hy, double hz, const 
 int orc_excmg(int nx, int ny, int nz, double lx, double ly, double lz, int ncx, int ncy, int ncz,
               const double *f, const double *g, double tol, int max_iters, const int *fixed_iters, double *u,
               double *ut, double *w_out, int *iters, double *relres, double *seconds);
+
+/* orc_excmg with the initial guess of kind guess (ORC_GUESS_*) on every level from 2 on; no EXP_true, no timing. */
+int orc_excmg_guess(int guess, int nx, int ny, int nz, double lx, double ly, double lz, int ncx, int ncy, int ncz,
+                    const double *f, const double *g, double tol, int max_iters, const int *fixed_iters, double *u,
+                    double *w_out, int *iters, double *relres);
 
 /* Adjoint of the exact discrete map u = (interior: M^-1 b(f, g); boundary: g) for an upstream gradient G
  * (node array, dL/du).  lambda solves M lambda = G_I by the same cascade (level data: G sampled on the interior),

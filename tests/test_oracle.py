@@ -307,6 +307,114 @@ def test_exp_finite_reproduces_triquartic(orc):
     assert np.max(np.abs(w - fine)) > 1e-8
 
 
+def _triquadratic(rng, box):
+    return synth.polynomial({(a, b, d): rng.uniform(-1, 1) for a in range(3) for b in range(3) for d in range(3)}, box)
+
+
+def test_quadratic_weights_at_the_midpoints(orc):
+    """Quadratic Lagrange basis on the nodes 0, 1, 2 at t = 1/2 and 3/2 (the odd fine offsets of a tri-quadratic
+    cell): (3, 6, -1)/8 and (-1, 6, 3)/8, and a partition of unity everywhere."""
+    np.testing.assert_allclose([orc.lagrange2(a, 0.5) for a in range(3)], [3 / 8, 6 / 8, -1 / 8], atol=1e-15)
+    np.testing.assert_allclose([orc.lagrange2(a, 1.5) for a in range(3)], [-1 / 8, 6 / 8, 3 / 8], atol=1e-15)
+    for t in np.linspace(0, 2, 9):
+        assert abs(sum(orc.lagrange2(a, t) for a in range(3)) - 1.0) < 1e-15
+
+
+@pytest.mark.parametrize("n,box", [((16, 16, 16), (1.0, 1.0, 1.0)), ((12, 8, 20), (0.7, 1.8, 1.1))])
+def test_quadratic_guess_exact_on_asymptotic_expansion(orc, n, box):
+    """The tri-quadratic guess shares EXP_finite's extrapolation at the 2h nodes: with u^i = v + A h_i^4, v
+    tri-quadratic and A trilinear, it returns the fine solution v + A h^4 exactly (the interpolation reproduces a
+    tri-quadratic field); with the 4h solution equal to the 2h one (no Richardson correction) it is off by O(h^4)."""
+    rng = np.random.default_rng(7)
+    v, A = _triquadratic(rng, box), _trilinear(rng, box)
+
+    def field(m, h4):
+        x, y, z = synth.mesh(m, box)
+        return np.broadcast_to(v.u(x, y, z) + A.u(x, y, z) * h4, (m[2] + 1, m[1] + 1, m[0] + 1)).copy()
+
+    h = box[0] / n[0]
+    fine = field(n, h ** 4)
+    u2 = field(tuple(k // 2 for k in n), (2 * h) ** 4)
+    u4 = field(tuple(k // 4 for k in n), (4 * h) ** 4)
+    w = orc.initial_guess("quadratic", u2, u4, fine)
+    assert np.max(np.abs(w - fine)) <= 1e-12 * np.max(np.abs(fine))
+    w0 = orc.initial_guess("quadratic", u2, u2[::2, ::2, ::2].copy(), fine)
+    assert np.max(np.abs(w0 - fine)) > 1e-3 * np.max(np.abs(A.u(*synth.mesh(n, box)))) * h ** 4
+
+
+def test_quadratic_guess_degree(orc):
+    """With delta = 0 the tri-quadratic guess is exact for tri-quadratic fields and not for a cubic term (negative
+    control on the interpolation degree); the tri-quartic guess is exact for both."""
+    rng = np.random.default_rng(8)
+    box = (1.0, 1.0, 1.0)
+    n = (16, 8, 12)
+    v = _triquadratic(rng, box)
+    _, _, fine = synth.sample(v, n)
+    _, _, u2 = synth.sample(v, tuple(k // 2 for k in n))
+    w = orc.initial_guess("quadratic", u2, u2[::2, ::2, ::2].copy(), fine)
+    assert np.max(np.abs(w - fine)) <= 1e-12 * np.max(np.abs(fine))
+    q = synth.polynomial({(0, 3, 0): 1.0}, box)
+    n8 = (16, 8, 16)
+    _, _, fine = synth.sample(q, n8)
+    _, _, u2 = synth.sample(q, tuple(k // 2 for k in n8))
+    wq = orc.initial_guess("quadratic", u2, u2[::2, ::2, ::2].copy(), fine)
+    w4 = orc.initial_guess("quartic", u2, u2[::2, ::2, ::2].copy(), fine)
+    assert np.max(np.abs(wq - fine)) > 1e-6
+    assert np.max(np.abs(w4 - fine)) <= 1e-12
+
+
+def test_linear_guess_is_trilinear_interpolation(orc):
+    """The CMG guess interpolates u_2h trilinearly and ignores u_4h: exact for trilinear fields, takes u_2h as is at
+    the 2h nodes, and is not exact for x^2 (negative control)."""
+    rng = np.random.default_rng(9)
+    box = (1.0, 2.0, 0.5)
+    n = (8, 6, 10)
+    v = _trilinear(rng, box)
+    _, _, fine = synth.sample(v, n)
+    _, _, u2 = synth.sample(v, tuple(k // 2 for k in n))
+    w = orc.initial_guess("linear", u2, None, fine)
+    assert np.max(np.abs(w - fine)) <= 1e-13 * np.max(np.abs(fine))
+    u2r = rand_nodes(tuple(k // 2 for k in n))
+    g = rand_nodes(n)
+    w = orc.initial_guess("linear", u2r, None, g)
+    np.testing.assert_array_equal(w[2:-2:2, 2:-2:2, 2:-2:2], u2r[1:-1, 1:-1, 1:-1])
+    q = synth.polynomial({(2, 0, 0): 1.0}, box)
+    _, _, fine = synth.sample(q, n)
+    _, _, u2 = synth.sample(q, tuple(k // 2 for k in n))
+    assert np.max(np.abs(orc.initial_guess("linear", u2, None, fine) - fine)) > 1e-4
+
+
+def test_initial_guess_orders(orc):
+    """How well each initial guess approximates the finest solution u_h, on the seeded smooth field at 16^3, 32^3,
+    64^3 (from 4^3): ||w_h - u_h|| falls like h^5 for the paper's tri-quartic guess (the remark after eq. (inter) in
+    Section 4.3: one order above the fourth-order solution), like h^3 for the tri-quadratic one (the interpolation
+    error of quadratics dominates) and like h^2 for CMG's trilinear interpolation of u_2h; the finest grid's CG
+    iterations grow in the same order."""
+    p = synth.smooth(0)
+    got = {}
+    for kind in ("quartic", "quadratic", "linear"):
+        errs, its = [], None
+        for N in (16, 32, 64):
+            f, g, _ = synth.sample(p, (N, N, N))
+            r = orc.excmg_guess(kind, f, g, p.box, (4, 4, 4), 1e-12)
+            errs.append(orc.norms(r["w"] - r["u"], p.box)[0])
+            its = int(r["iters"][-1])
+        got[kind] = (np.log2(errs[1] / errs[2]), its)
+    assert 4.6 < got["quartic"][0] < 5.4, got
+    assert 2.7 < got["quadratic"][0] < 3.3, got
+    assert 1.7 < got["linear"][0] < 2.3, got
+    assert got["quartic"][1] < got["quadratic"][1] < got["linear"][1], got
+
+
+def test_initial_guess_argument_errors(orc):
+    g = np.zeros((9, 9, 9))
+    u2 = np.zeros((5, 5, 5))
+    with pytest.raises(orc.OracleError):
+        orc.initial_guess(7, u2, u2, g)  # unknown kind
+    with pytest.raises(orc.OracleError):
+        orc.initial_guess("quadratic", np.zeros((4, 4, 4)), np.zeros((2, 2, 2)), np.zeros((7, 7, 7)))  # 6 cells
+
+
 @pytest.mark.parametrize("n", [(16, 16, 16), (8, 12, 6)])
 def test_exp_true_exact_on_asymptotic_expansion(orc, n):
     """u_h = v + A h^4 and u_2h = v + A (2h)^4 with A trilinear: eqs. (t1)/(chenlin) return v exactly, for any v."""
