@@ -153,6 +153,43 @@ def bench_adjoint(ex, synth, torch, args):
             "adjoint_iters": st["iters"]}
 
 
+def bench_guess(ex, synth, torch, args, f, g, u_ref):
+    """The paper's initial guess against the two it compares with (tri-quadratic after the same extrapolation; CMG's
+    trilinear interpolation of u_2h), FP64 on the benchmark's workload: finest-grid CG iterations and solve time per
+    guess, and ||w_h - u_h|| (the guess against the converged solution) at N and N/2.  The grids N/2, N/4, N/8 of the
+    cascade are the finest data sampled at strides 2, 4, 8 and are solved here as problems of their own."""
+    N = args.n
+    p = synth.smooth(0)
+    h3 = (1.0 / N) ** 3
+    sub = {}
+    for m in (N // 2, N // 4, N // 8):
+        st_ = N // m
+        s_ = ex.Solver((m, m, m), p.box, args.tol)
+        sub[m], _, _ = s_.solve(f[::st_, ::st_, ::st_].contiguous(), g[::st_, ::st_, ::st_].contiguous())
+        del s_
+    sub[N] = u_ref
+
+    def werr(kind, m):  # the guess on grid m from the solutions on m/2 and m/4, against the solution on m
+        st_ = N // m
+        gm = g[::st_, ::st_, ::st_].contiguous()
+        w = ex.op_initial_guess(kind, sub[m // 2], sub[m // 4] if kind != "linear" else None, gm, (m, m, m))
+        e = w - sub[m]
+        return (float(torch.sqrt(torch.sum(e * e) * h3 * (N // m) ** 3)), float(torch.max(torch.abs(e))))
+
+    res = {}
+    for kind in ("quartic", "quadratic", "linear"):
+        s = ex.Solver((N, N, N), p.box, args.tol, guess=kind)
+        s.autotune()
+        u = s.empty()
+        ms, (_, _, st) = _timed(torch, lambda: s.solve(f, g, u=u), 3)
+        eN, eH = werr(kind, N), werr(kind, N // 2)
+        res[kind] = {"solve_ms": round(ms, 3), "iters": st["iters"], "w_minus_u_L2": [eH[0], eN[0]],
+                     "w_minus_u_max": [eH[1], eN[1]], "order_L2": round(float(np.log2(eH[0] / eN[0])), 2)}
+        del s, u
+    res["grids_of_w_minus_u"] = [N // 2, N]
+    return res
+
+
 PROBE_BYTES = 2 << 30  # buffer of the streaming probe: its copy kernel reads PROBE_BYTES/2 and writes PROBE_BYTES/2
 COUNTERS_FILE = os.path.join(ROOT, "profiles", "excmg_512_fp64_hbm_counters.txt")
 KERNEL_SOURCES = ["paper_1507_05063_amd/csrc/kernels_cg.hip", "paper_1507_05063_amd/csrc/excmg_internal.h"]
@@ -235,6 +272,7 @@ def main():
     ap.add_argument("--no-aniso", action="store_true", help="skip the 1024x512x256 FP64 / FP32-refinement section")
     ap.add_argument("--no-batch", action="store_true", help="skip the 96-problem batched section")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the 256^3 adjoint section")
+    ap.add_argument("--no-guess", action="store_true", help="skip the initial-guess ablation (three 512^3 solves)")
     args = ap.parse_args()
     if args.trace_summary:
         trace_summary(args.trace_summary)
@@ -381,6 +419,9 @@ def main():
     if not args.no_adjoint:
         out["adjoint"] = bench_adjoint(ex, synth, torch, args)
         print(f"# adjoint: {out['adjoint']}", file=sys.stderr, flush=True)
+    if not args.no_guess:
+        out["guess_ablation"] = bench_guess(ex, synth, torch, args, f, g, u)
+        print(f"# guess ablation: {out['guess_ablation']}", file=sys.stderr, flush=True)
 
     if not args.no_cpu_baseline:
         # the oracle timed on the same step (solve with EXP_true, then the gradient) of the same inputs, repeated

@@ -51,6 +51,12 @@ extern "C" {
                                  kernel_calls); the coarser grids are not timed */
 #define EXCMG_NO_GRAPHS 4u    /* launch every CG iteration directly instead of replaying graphs of iteration batches on
                                  the grids below the finest (same kernels in the same order: same results) */
+/* The initial guesses the paper compares its own with (at most one of the two; neither = EXP_finite, Algorithm 1):
+ * on every grid from the third on, the CG starts from */
+#define EXCMG_GUESS_QUADRATIC 8u /* the extrapolation of EXP_finite at the 2h nodes, then tri-quadratic Lagrange
+                                    interpolation on cells of 2x2x2 2h elements (the earlier EXCMG's interpolation,
+                                    which the remark after eq. (inter) in Section 4.3 finds too weak here) */
+#define EXCMG_GUESS_LINEAR 16u   /* trilinear interpolation of u_2h, no extrapolation (the CMG method, Section 3) */
 
 #define EXCMG_MAX_LEVELS 16
 #define EXCMG_MAX_HISTORY 256
@@ -151,7 +157,8 @@ int excmg_batch_workspace_bytes(int32_t count, size_t *bytes);
  * other streams must be complete.  The cascades run in step, grid s of every problem in step s: each kernel launch
  * covers every problem it concerns (the workgroups of one launch are split among the problems), so a batch costs
  * about as many launches as its largest problem.  Each problem keeps its own precision, tolerance and iteration
- * limits; the history and timing flags are ignored.
+ * limits; the history and timing flags are ignored.  Handles set up with an EXCMG_GUESS_* flag are rejected
+ * (EXCMG_ERR_ARG): batched solves start every grid from EXP_finite.
  * batch_ws: device memory of at least excmg_batch_workspace_bytes(count), 256-byte aligned, owned by the caller.
  * stats (host, nullable): count entries (ms_total = the host time of the whole call).  ms_per_problem (host,
  * nullable): count entries, the device time from the start of the batch until problem b's finest grid converged.
@@ -204,6 +211,13 @@ int excmg_op_rhs(const int32_t n[3], const double box[3], const double *f, const
  * boundary nodes of w are g. */
 int excmg_op_exp_finite(const int32_t n[3], const double *u2h, const double *u4h, const double *g, double *w,
                         void *hip_stream);
+
+/* The initial guess of a kind: 0 = EXP_finite (as excmg_op_exp_finite), 1 = tri-quadratic after the same
+ * extrapolation, 2 = trilinear interpolation of u2h (u4h not read, may be NULL); see EXCMG_GUESS_*.  n: multiples of 8
+ * for kinds 0 and 1, even for kind 2.  Errors: EXCMG_ERR_ARG for an unknown kind or a null pointer,
+ * EXCMG_ERR_SHAPE for counts that do not fit. */
+int excmg_op_initial_guess(int32_t kind, const int32_t n[3], const double *u2h, const double *u4h, const double *g,
+                           double *w, void *hip_stream);
 
 /* EXP_true(u_h, u_2h) (eqs. t1, chenlin; Section 4.3) on the grid n (even counts). */
 int excmg_op_exp_true(const int32_t n[3], const double *uh, const double *u2h, double *ut, void *hip_stream);

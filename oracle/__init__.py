@@ -219,7 +219,7 @@ def initial_guess(kind, u2h, u4h, g):
     return w
 
 
-def excmg_guess(kind, f, g, box, n_coarse, tol, max_iters=100000):
+def excmg_guess(kind, f, g, box, n_coarse, tol, max_iters=100000, fixed_iters=None):
     """Algorithm 1 with the initial guess of the given kind on every level from 2 on.
     Returns dict(u, w, iters, relres): w is the finest level's initial guess."""
     k = GUESS_KINDS[kind] if isinstance(kind, str) else int(kind)
@@ -229,9 +229,13 @@ def excmg_guess(kind, f, g, box, n_coarse, tol, max_iters=100000):
     u, w = np.empty_like(f), np.empty_like(f)
     iters = np.zeros(nl, dtype=np.int32)
     relres = np.zeros(nl, dtype=np.float64)
+    fx = None
+    if fixed_iters is not None:
+        fx = np.ascontiguousarray(fixed_iters, dtype=np.int32)
+        assert fx.size == nl
     code = lib().orc_excmg_guess(k, *n, *(float(v) for v in box), *(int(v) for v in n_coarse), _ptr(f), _ptr(g),
-                                 float(tol), int(max_iters), None, _ptr(u), _ptr(w) if nl >= 3 else None,
-                                 iters.ctypes.data, relres.ctypes.data)
+                                 float(tol), int(max_iters), None if fx is None else fx.ctypes.data, _ptr(u),
+                                 _ptr(w) if nl >= 3 else None, iters.ctypes.data, relres.ctypes.data)
     _check(code, "excmg_guess")
     return dict(u=u, w=w if nl >= 3 else None, iters=iters, relres=relres)
 

@@ -14,8 +14,8 @@ from . import _lib
 from ._lib import ExcmgError, FP32_IR, FP64, K_CLASSES, LIB_PATH, NO_GRAPHS, WANT_HISTORY, WANT_TIMING
 
 __all__ = ["Solver", "ExcmgError", "FP64", "FP32_IR", "plan", "workspace_bytes", "op_apply", "op_rhs",
-           "op_exp_finite", "op_exp_true", "solve_batched", "batch_workspace_bytes", "bandwidth_probe", "PROBE_KINDS", "K_CLASSES",
-           "LIB_PATH"]
+           "op_exp_finite", "op_initial_guess", "op_exp_true", "solve_batched", "batch_workspace_bytes",
+           "bandwidth_probe", "PROBE_KINDS", "K_CLASSES", "LIB_PATH"]
 
 
 def _torch():
@@ -80,13 +80,19 @@ class Solver:
 
     def __init__(self, n: Sequence[int], box=(1.0, 1.0, 1.0), tol: float = 1e-10, n_coarse=(0, 0, 0),
                  precision: int = FP64, inner_tol: float = 0.0, max_iters: int = 0, history: bool = False,
-                 timing: bool = False, graphs: bool = True, stream=None):
+                 timing: bool = False, graphs: bool = True, guess: str = "quartic", stream=None):
+        """guess: the initial guess of every grid from the third on: "quartic" (EXP_finite, the paper's method),
+        "quadratic" (the same extrapolation, tri-quadratic interpolation) or "linear" (CMG: trilinear u_2h)."""
         torch = _torch()
         self.n = tuple(int(v) for v in n)
         self.box = tuple(float(v) for v in box)
         self.tol = float(tol)
         self.precision = int(precision)
+        if guess not in _lib.GUESS_FLAGS:
+            raise ValueError(f"guess must be one of {sorted(_lib.GUESS_FLAGS)}, not {guess!r}")
+        self.guess = guess
         flags = (WANT_HISTORY if history else 0) | (WANT_TIMING if timing else 0) | (0 if graphs else NO_GRAPHS)
+        flags |= _lib.GUESS_FLAGS[guess]
         self._p = _problem(self.n, self.box, tol, n_coarse, precision, inner_tol, max_iters, flags)
         nbytes = ctypes.c_size_t(0)
         _lib.check(_lib.lib().excmg_workspace_bytes(ctypes.byref(self._p), ctypes.byref(nbytes)),
@@ -240,6 +246,17 @@ def op_exp_finite(u2h, u4h, g, n):
     w = _torch().empty_like(g)
     _lib.check(_lib.lib().excmg_op_exp_finite(_n3(n), _ptr(u2h), _ptr(u4h), _ptr(g), _ptr(w), _stream_ptr()),
                "excmg_op_exp_finite")
+    return w
+
+
+def op_initial_guess(kind: str, u2h, u4h, g, n):
+    """The initial guess of a kind ("quartic" = op_exp_finite, "quadratic", "linear"; u4h unused, may be None for
+    "linear") on the grid n, with g on the boundary."""
+    _check_nodes(g, n, "g")
+    w = _torch().empty_like(g)
+    _lib.check(_lib.lib().excmg_op_initial_guess(_lib.GUESS_KINDS[kind], _n3(n), _ptr(u2h),
+                                                 None if u4h is None else _ptr(u4h), _ptr(g), _ptr(w), _stream_ptr()),
+               "excmg_op_initial_guess")
     return w
 
 

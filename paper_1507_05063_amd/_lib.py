@@ -14,7 +14,9 @@ LIB_PATH = os.path.join(HERE, "libexcmg.so")
 OK = 0
 ERR_ARG, ERR_SHAPE, ERR_NONFINITE, ERR_NOCONV, ERR_BREAKDOWN, ERR_HIP, ERR_WORKSPACE = -1, -2, -3, -4, -5, -6, -7
 FP64, FP32_IR = 0, 1
-WANT_HISTORY, WANT_TIMING, NO_GRAPHS = 1, 2, 4
+WANT_HISTORY, WANT_TIMING, NO_GRAPHS, GUESS_QUADRATIC, GUESS_LINEAR = 1, 2, 4, 8, 16
+GUESS_KINDS = {"quartic": 0, "quadratic": 1, "linear": 2}
+GUESS_FLAGS = {"quartic": 0, "quadratic": GUESS_QUADRATIC, "linear": GUESS_LINEAR}
 MAX_LEVELS, MAX_HISTORY = 16, 256
 
 K_CLASSES = ["cg_a", "cg_b", "cg_a32", "cg_b32", "resid", "finalize", "rhs", "exp_finite", "exp_true", "dsolve",
@@ -113,6 +115,7 @@ def lib():
             "excmg_op_rhs": ([_I32P, _D3, _P, _P, _P, _P], _I),
             "excmg_op_exp_finite": ([_I32P, _P, _P, _P, _P, _P], _I),
             "excmg_op_exp_true": ([_I32P, _P, _P, _P, _P], _I),
+            "excmg_op_initial_guess": ([ctypes.c_int32, _I32P, _P, _P, _P, _P, _P], _I),
         }
         for name, (args, res) in sig.items():
             fn = getattr(L, name)

@@ -93,12 +93,21 @@ int validate(const excmg_problem *p) {
   if (p->precision != EXCMG_FP64 && p->precision != EXCMG_FP32_IR) return EXCMG_ERR_ARG;
   if (p->inner_tol < 0.0 || !isfinite(p->inner_tol) || p->inner_tol >= 1.0) return EXCMG_ERR_ARG;
   if (p->max_iters < 0) return EXCMG_ERR_ARG;
-  if (p->flags & ~(EXCMG_WANT_HISTORY | EXCMG_WANT_TIMING | EXCMG_NO_GRAPHS)) return EXCMG_ERR_ARG;
+  if (p->flags & ~(EXCMG_WANT_HISTORY | EXCMG_WANT_TIMING | EXCMG_NO_GRAPHS | EXCMG_GUESS_QUADRATIC |
+                   EXCMG_GUESS_LINEAR))
+    return EXCMG_ERR_ARG;
+  if ((p->flags & EXCMG_GUESS_QUADRATIC) && (p->flags & EXCMG_GUESS_LINEAR)) return EXCMG_ERR_ARG;
   return EXCMG_OK;
 }
 
 // z planes per workgroup of the residual sweeps on large grids
 constexpr int kResidChunk = 64;
+
+int guess_kind(uint32_t flags) {
+  if (flags & EXCMG_GUESS_QUADRATIC) return kGuessQuadratic;
+  if (flags & EXCMG_GUESS_LINEAR) return kGuessLinear;
+  return kGuessQuartic;
+}
 
 // Events that only take timestamps: no system-scope fence at record (the cache write-back and invalidation it
 // costs would sit between the timed kernels).  Results are read on the host only after a stream synchronization.
@@ -642,8 +651,8 @@ int cascade(excmg_handle *h, int mode, const double *f, const double *g, excmg_s
     } else {
       {
         Tick t(h, EXCMG_K_EXP_FINITE, l);
-        launch_exp_finite(lo.lev[l - 1].g, lo.lev[l - 1].u, lo.lev[l - 2].g, lo.lev[l - 2].u, lo.gdense,
-                          mode == 0 ? g : nullptr, lv.stride, lv.g, lv.u, s);
+        launch_initial_guess(guess_kind(h->p.flags), lo.lev[l - 1].g, lo.lev[l - 1].u, lo.lev[l - 2].g,
+                             lo.lev[l - 2].u, lo.gdense, mode == 0 ? g : nullptr, lv.stride, lv.g, lv.u, s);
       }
       e = last_error();
       if (e) return e;
@@ -1347,7 +1356,23 @@ int excmg_op_exp_finite(const int32_t n[3], const double *u2h, const double *u4h
   const Grid gw = dense_grid(n[0], n[1], n[2]);
   const Grid g2 = dense_grid(n[0] / 2, n[1] / 2, n[2] / 2);
   const Grid g4 = dense_grid(n[0] / 4, n[1] / 4, n[2] / 4);
-  launch_exp_finite(g2, u2h, g4, u4h, gw, g, 1, gw, w, s);
+  launch_initial_guess(kGuessQuartic, g2, u2h, g4, u4h, gw, g, 1, gw, w, s);
+  int e = last_error();
+  if (e) return e;
+  HIPCHECK(hipStreamSynchronize(s));
+  return EXCMG_OK;
+}
+
+int excmg_op_initial_guess(int32_t kind, const int32_t n[3], const double *u2h, const double *u4h, const double *g,
+                           double *w, void *hip_stream) {
+  if (kind != kGuessQuartic && kind != kGuessQuadratic && kind != kGuessLinear) return EXCMG_ERR_ARG;
+  if (!n || !u2h || (kind != kGuessLinear && !u4h) || !g || !w) return EXCMG_ERR_ARG;
+  if (check_n(n, kind == kGuessLinear ? 2 : 8)) return EXCMG_ERR_SHAPE;
+  const hipStream_t s = (hipStream_t)hip_stream;
+  const Grid gw = dense_grid(n[0], n[1], n[2]);
+  const Grid g2 = dense_grid(n[0] / 2, n[1] / 2, n[2] / 2);
+  const Grid g4 = dense_grid(n[0] / 4, n[1] / 4, n[2] / 4);
+  launch_initial_guess(kind, g2, u2h, g4, u4h, gw, g, 1, gw, w, s);
   int e = last_error();
   if (e) return e;
   HIPCHECK(hipStreamSynchronize(s));
@@ -1419,7 +1444,9 @@ int excmg_solve_batched(excmg_handle *const *hs, int32_t count, const double *co
                         double *ms_per_problem) {
   if (!hs || count <= 0 || !f || !g || !u) return EXCMG_ERR_ARG;
   for (int b = 0; b < count; ++b)
-    if (!hs[b] || !f[b] || !g[b] || !u[b] || hs[b]->device != hs[0]->device) return EXCMG_ERR_ARG;
+    if (!hs[b] || !f[b] || !g[b] || !u[b] || hs[b]->device != hs[0]->device ||
+        guess_kind(hs[b]->p.flags) != kGuessQuartic)
+      return EXCMG_ERR_ARG;
   if (!batch_ws || ((uintptr_t)batch_ws & 255) || batch_bytes < batch_ws_bytes(count)) return EXCMG_ERR_WORKSPACE;
   DeviceGuard dg(hs[0]->device);
   return batched_solve(hs, count, f, g, u, (char *)batch_ws, stats, ms_per_problem);

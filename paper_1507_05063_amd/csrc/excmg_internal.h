@@ -237,8 +237,11 @@ void launch_rhs(const RhsSrc &rs, const Grid &gb, double *b, hipStream_t st);
 void launch_set_boundary(const Grid &gg, const double *g, int stride, const Grid &gu, double *u, int zero_interior,
                          hipStream_t st);
 // w on grid gw from u2 (grid g2, n/2) and u4 (grid g4, n/4); boundary from dense finest g at stride s
-void launch_exp_finite(const Grid &g2, const double *u2, const Grid &g4, const double *u4, const Grid &gg,
-                       const double *g, int stride, const Grid &gw, double *w, hipStream_t st);
+// Initial guess of a grid from the two coarser solutions: kGuessQuartic = EXP_finite (the paper's), kGuessQuadratic =
+// the same extrapolation with tri-quadratic interpolation, kGuessLinear = trilinear interpolation of u2 alone.
+enum GuessKind { kGuessQuartic = 0, kGuessQuadratic = 1, kGuessLinear = 2 };
+void launch_initial_guess(int kind, const Grid &g2, const double *u2, const Grid &g4, const double *u4,
+                          const Grid &gg, const double *g, int stride, const Grid &gw, double *w, hipStream_t st);
 // ut (grid gt) = EXP_true(uh (grid gh), u2 (grid g2))
 void launch_exp_true(const Grid &gh, const double *uh, const Grid &g2, const double *u2, const Grid &gt, double *ut,
                      double *ucopy, hipStream_t st);

@@ -91,6 +91,35 @@ __device__ __forceinline__ double quartic(const double (*q)[5], int t, double a0
   return q[t][0] * a0 + q[t][1] * a1 + q[t][2] * a2 + q[t][3] * a3 + q[t][4] * a4;
 }
 
+// Quadratic Lagrange weights on the nodes 0, 1, 2 at 1/2 (T = 0) and 3/2 (T = 1): the odd fine offsets of a cell of
+// two 2h elements (the tri-quadratic initial guess the paper compares its own with).
+template <int T>
+__device__ __forceinline__ double quadratic(double a0, double a1, double a2) {
+  return T == 0 ? 0.375 * a0 + 0.75 * a1 - 0.125 * a2 : -0.125 * a0 + 0.75 * a1 + 0.375 * a2;
+}
+
+// The nine values at fine offsets 0..8 along one axis of a staged block, from the five known values at the even
+// offsets: one tri-quartic cell (the paper's), or two tri-quadratic cells of two 2h elements each.
+template <bool QUAD>
+__device__ __forceinline__ void axis9(double a0, double a1, double a2, double a3, double a4, double (&o)[9]) {
+  o[0] = a0;
+  o[2] = a1;
+  o[4] = a2;
+  o[6] = a3;
+  o[8] = a4;
+  if constexpr (QUAD) {
+    o[1] = quadratic<0>(a0, a1, a2);
+    o[3] = quadratic<1>(a0, a1, a2);
+    o[5] = quadratic<0>(a2, a3, a4);
+    o[7] = quadratic<1>(a2, a3, a4);
+  } else {
+    o[1] = quartic<0>(a0, a1, a2, a3, a4);
+    o[3] = quartic<1>(a0, a1, a2, a3, a4);
+    o[5] = quartic<2>(a0, a1, a2, a3, a4);
+    o[7] = quartic<3>(a0, a1, a2, a3, a4);
+  }
+}
+
 // One workgroup per CXN x 1 x 1 interpolation cells.
 //  1. stage u_2h on the 5x5x(4CXN+1) 2h nodes and delta = u_2h - u_4h on the 3x3x(2CXN+1) 4h nodes in LDS;
 //  2. W = u_2h + delta_avg / 16 at every 2h node, where delta_avg is the mean of delta over the corners of the 4h
@@ -102,6 +131,9 @@ __device__ __forceinline__ double quartic(const double (*q)[5], int t, double a0
 //     that the four odd offsets have constant weights), then one thread per (x, y) column that interpolates its five
 //     z layers in y from the x-pass values and then produces its nine z outputs;
 //  4. boundary nodes get g.
+// QUAD: the tri-quadratic variant of step 3 (cells of 2x2x2 elements of the 2h grid, two per axis of the block), the
+// initial guess of the earlier EXCMG that the remark after eq. (inter) compares with; steps 1, 2 and 4 are the same.
+template <bool QUAD>
 __device__ void exp_finite_block(const Grid &g2, const double *__restrict__ u2, const Grid &g4,
                                  const double *__restrict__ u4, const Grid &gg, const double *__restrict__ gdat, int s,
                                  const Grid &gw, double *__restrict__ w, int bx, int cj, int ck, bool nt) {
@@ -144,17 +176,12 @@ __device__ void exp_finite_block(const Grid &g2, const double *__restrict__ u2, 
     const int cx = tid % CXN, bc = tid / CXN, b = bc % 5, c = bc / 5;
     if (cx < nc) {
       const double *wr = &W[c][b][4 * cx];
-      const double a0 = wr[0], a1 = wr[1], a2 = wr[2], a3 = wr[3], a4 = wr[4];
+      double v9[9];
+      axis9<QUAD>(wr[0], wr[1], wr[2], wr[3], wr[4], v9);
       double *o = &Wx[c][b][8 * cx];
-      o[0] = a0;
-      o[1] = quartic<0>(a0, a1, a2, a3, a4);
-      o[2] = a1;
-      o[3] = quartic<1>(a0, a1, a2, a3, a4);
-      o[4] = a2;
-      o[5] = quartic<2>(a0, a1, a2, a3, a4);
-      o[6] = a3;
-      o[7] = quartic<3>(a0, a1, a2, a3, a4);
-      if (cx == nc - 1) o[8] = a4;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) o[q] = v9[q];
+      if (cx == nc - 1) o[8] = v9[8];
     }
   }
   __syncthreads();
@@ -171,14 +198,23 @@ __device__ void exp_finite_block(const Grid &g2, const double *__restrict__ u2, 
     const int gi = gi0 + xf, gj = gj0 + yf;
     // y: the five z layers of this column, from the x-interpolated values (known at even yf, quartic at odd yf)
     double a[5];
+    if constexpr (QUAD) {
+      const int q2 = 2 * (yf >> 2);  // first 2h node of the y cell
+      const bool hi = (yf >> 1) & 1;  // offset 3/2 rather than 1/2
+      const double w0 = hi ? -0.125 : 0.375, w2 = hi ? 0.375 : -0.125;
 #pragma unroll
-    for (int c = 0; c < 5; ++c)
-      a[c] = (yf & 1) ? quartic(Q, yf >> 1, Wx[c][0][xf], Wx[c][1][xf], Wx[c][2][xf], Wx[c][3][xf], Wx[c][4][xf])
-                      : Wx[c][yf >> 1][xf];
-    const double a0 = a[0], a1 = a[1], a2 = a[2], a3 = a[3], a4 = a[4];
+      for (int c = 0; c < 5; ++c)
+        a[c] = (yf & 1) ? w0 * Wx[c][q2][xf] + 0.75 * Wx[c][q2 + 1][xf] + w2 * Wx[c][q2 + 2][xf]
+                        : Wx[c][yf >> 1][xf];
+    } else {
+#pragma unroll
+      for (int c = 0; c < 5; ++c)
+        a[c] = (yf & 1) ? quartic(Q, yf >> 1, Wx[c][0][xf], Wx[c][1][xf], Wx[c][2][xf], Wx[c][3][xf], Wx[c][4][xf])
+                        : Wx[c][yf >> 1][xf];
+    }
     const bool side = (gi == 0 || gj == 0 || gi == gw.nx || gj == gw.ny);
-    const double zv[9] = {a0, quartic<0>(a0, a1, a2, a3, a4), a1, quartic<1>(a0, a1, a2, a3, a4), a2,
-                          quartic<2>(a0, a1, a2, a3, a4), a3, quartic<3>(a0, a1, a2, a3, a4), a4};
+    double zv[9];
+    axis9<QUAD>(a[0], a[1], a[2], a[3], a[4], zv);
 #pragma unroll
     for (int zf = 0; zf < 9; ++zf) {
       if (zf < oz) {
@@ -198,13 +234,35 @@ __device__ void exp_finite_block(const Grid &g2, const double *__restrict__ u2, 
     for (int yf = tid; yf < oy; yf += ET) column(0, yf);
 }
 
+template <bool QUAD>
 __global__ __launch_bounds__(ET) void exp_finite_kernel(Grid g2, const double *__restrict__ u2, Grid g4,
                                                         const double *__restrict__ u4, Grid gg,
                                                         const double *__restrict__ gdat, int s, Grid gw,
                                                         double *__restrict__ w) {
   // w is read again right away by the residual sweep: streaming stores only where it cannot stay in the caches
-  exp_finite_block(g2, u2, g4, u4, gg, gdat, s, gw, w, blockIdx.x, blockIdx.y, blockIdx.z,
-                   gw.interior() >= (1LL << 23));
+  exp_finite_block<QUAD>(g2, u2, g4, u4, gg, gdat, s, gw, w, blockIdx.x, blockIdx.y, blockIdx.z,
+                         gw.interior() >= (1LL << 23));
+}
+
+// The CMG initial guess the paper compares with (Section 3): u_2h interpolated trilinearly, without extrapolation
+// (the mean of the 1, 2, 4 or 8 nearest 2h nodes), and g on the boundary.  One thread per node.
+__global__ __launch_bounds__(256) void prolong_linear_kernel(Grid g2, const double *__restrict__ u2, Grid gg,
+                                                             const double *__restrict__ gdat, int s, Grid gw,
+                                                             double *__restrict__ w) {
+  const int i = blockIdx.x * 256 + threadIdx.x, j = blockIdx.y, k = blockIdx.z;
+  if (i > gw.nx) return;
+  double v;
+  if (on_boundary(i, j, k, gw.nx, gw.ny, gw.nz)) {
+    v = gdat ? gdat[gg.at(i * s, j * s, k * s)] : 0.0;
+  } else {
+    const int I = i >> 1, J = j >> 1, K = k >> 1, di = i & 1, dj = j & 1, dk = k & 1;
+    double acc = 0.0;
+    for (int c = 0; c <= dk; ++c)
+      for (int b = 0; b <= dj; ++b)
+        for (int a = 0; a <= di; ++a) acc += u2[g2.at(I + a, J + b, K + c)];
+    v = acc * (1.0 / (double)(1 << (di + dj + dk)));
+  }
+  w[gw.at(i, j, k)] = v;
 }
 
 // ------------------------------------------------------------------------------------------------------- exp_true
@@ -340,7 +398,7 @@ __global__ __launch_bounds__(ET) void b_exp_finite_kernel(BatchList L) {
   const int ncx = E.g.nx / 8, ncy = E.g.ny / 8;
   const int gx = (ncx + CXN - 1) / CXN;
   const int lb = blockIdx.x - L.pre[e];
-  exp_finite_block(E.g2, E.u2, E.g4, E.u4, E.gd, E.gb, E.rs.s, E.g, E.u, lb % gx, (lb / gx) % ncy, lb / (gx * ncy),
+  exp_finite_block<false>(E.g2, E.u2, E.g4, E.u4, E.gd, E.gb, E.rs.s, E.g, E.u, lb % gx, (lb / gx) % ncy, lb / (gx * ncy),
                    false);
 }
 
@@ -358,11 +416,16 @@ void launch_set_boundary(const Grid &gg, const double *g, int stride, const Grid
   set_boundary_kernel<<<node_grid(gu, 256), 256, 0, st>>>(gg, g, stride, gu, u, zero_interior);
 }
 
-void launch_exp_finite(const Grid &g2, const double *u2, const Grid &g4, const double *u4, const Grid &gg,
-                       const double *g, int stride, const Grid &gw, double *w, hipStream_t st) {
+void launch_initial_guess(int kind, const Grid &g2, const double *u2, const Grid &g4, const double *u4,
+                          const Grid &gg, const double *g, int stride, const Grid &gw, double *w, hipStream_t st) {
+  if (kind == kGuessLinear) {
+    prolong_linear_kernel<<<node_grid(gw, 256), 256, 0, st>>>(g2, u2, gg, g, stride, gw, w);
+    return;
+  }
   const int ncx = gw.nx / 8, ncy = gw.ny / 8, ncz = gw.nz / 8;
   dim3 grid((ncx + CXN - 1) / CXN, ncy, ncz);
-  exp_finite_kernel<<<grid, ET, 0, st>>>(g2, u2, g4, u4, gg, g, stride, gw, w);
+  if (kind == kGuessQuadratic) exp_finite_kernel<true><<<grid, ET, 0, st>>>(g2, u2, g4, u4, gg, g, stride, gw, w);
+  else exp_finite_kernel<false><<<grid, ET, 0, st>>>(g2, u2, g4, u4, gg, g, stride, gw, w);
 }
 
 void launch_exp_true(const Grid &gh, const double *uh, const Grid &g2, const double *u2, const Grid &gt, double *ut,

@@ -171,3 +171,23 @@ def test_bandwidth_probe_argument_errors(abi):
     assert L.excmg_bandwidth_probe(ctypes.c_void_p(16), 1 << 20, 1, None, None) == abi.ERR_ARG  # no output
     src = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
     assert int(re.search(r"EXCMG_PROBE_KINDS\s*=\s*(\d+)", src).group(1)) == len(ex.PROBE_KINDS)
+
+
+def test_initial_guess_argument_errors(abi):
+    """The guess operator and the guess flags are checked before any device call."""
+    L = abi.lib()
+    n = (ctypes.c_int32 * 3)(8, 8, 8)
+    p = ctypes.c_void_p(256)
+    assert L.excmg_op_initial_guess(3, n, p, p, p, p, None) == abi.ERR_ARG  # unknown kind
+    assert L.excmg_op_initial_guess(1, n, p, None, p, p, None) == abi.ERR_ARG  # the quadratic guess needs u4h
+    n6 = (ctypes.c_int32 * 3)(8, 6, 8)
+    assert L.excmg_op_initial_guess(1, n6, p, p, p, p, None) == abi.ERR_SHAPE  # not multiples of 8
+    prob = abi.Problem()
+    prob.box[:] = (1.0, 1.0, 1.0)
+    prob.n[:] = (32, 32, 32)
+    prob.tol = 1e-10
+    prob.flags = abi.GUESS_QUADRATIC | abi.GUESS_LINEAR  # at most one of the two
+    nbytes = ctypes.c_size_t(0)
+    assert L.excmg_workspace_bytes(ctypes.byref(prob), ctypes.byref(nbytes)) == abi.ERR_ARG
+    prob.flags = abi.GUESS_LINEAR
+    assert L.excmg_workspace_bytes(ctypes.byref(prob), ctypes.byref(nbytes)) == abi.OK
