@@ -731,9 +731,10 @@ static void sample_stride(int nx, int ny, int nz, const double *fine, int s, int
 }
 
 /* shared cascade; mode 0: b_l from (f, g); mode 1: b_l = G on the interior, zero Dirichlet data */
-static int cascade(int mode, int guess, int nx, int ny, int nz, double lx, double ly, double lz, int ncx, int ncy,
-                   int ncz, const double *f, const double *g, double tol, int max_iters, const int *fixed_iters,
-                   double *u, double *ut, double *w_out, int *iters, double *relres, double *seconds) {
+static int cascade(int mode, int guess, int stop_norm, int nx, int ny, int nz, double lx, double ly, double lz,
+                   int ncx, int ncy, int ncz, const double *f, const double *g, double tol, int max_iters,
+                   const int *fixed_iters, double *u, double *ut, double *w_out, int *iters, double *relres,
+                   double *seconds) {
   if (!f || !u || !iters || !relres) return ORC_ERR_ARG;
   if (mode == 0 && !g) return ORC_ERR_ARG;
   if (!(lx > 0) || !(ly > 0) || !(lz > 0) || !(tol > 0) || max_iters < 0) return ORC_ERR_ARG;
@@ -812,8 +813,31 @@ static int cascade(int mode, int guess, int nx, int ny, int nz, double lx, doubl
       }
       if (l == Lt && w_out) memcpy(w_out, ul, nl * sizeof(double));
       const int fi = fixed_iters ? fixed_iters[l] : -1;
+      /* the stopping test ||r|| <= tol ||f_h||: f_h = b (the eliminated right-hand side) or, with stop_norm 1, the
+       * vector of R f on the interior nodes and g on the boundary nodes; the CG's test is against ||b||, so the
+       * tolerance is rescaled by ||f_h|| / ||b|| */
+      double tol_l = tol;
+      if (stop_norm == 1) {
+        double *rf = (double *)malloc(nl * sizeof(double));
+        if (!rf) {
+          status = ORC_ERR_NOMEM;
+          goto done;
+        }
+        orc_apply_R(mx, my, mz, hx, hy, hz, fl, rf);
+        double fg2 = dot_interior(mx, my, mz, rf, rf);
+        for (int k = 0; k <= mz; ++k)
+          for (int j = 0; j <= my; ++j)
+            for (int i = 0; i <= mx; ++i)
+              if (is_bnd(mx, my, mz, i, j, k)) {
+                const double gv = gl[(((size_t)k) * (size_t)(my + 1) + (size_t)j) * (size_t)(mx + 1) + (size_t)i];
+                fg2 += gv * gv;
+              }
+        free(rf);
+        const double bn = sqrt(dot_interior(mx, my, mz, bl, bl));
+        tol_l = bn > 0.0 ? tol * sqrt(fg2) / bn : tol;
+      }
       const double tc = now_s();
-      e = orc_cg(mx, my, mz, hx, hy, hz, bl, ul, tol, max_iters, fi, &iters[l], &relres[l], NULL);
+      e = orc_cg(mx, my, mz, hx, hy, hz, bl, ul, tol_l, max_iters, fi, &iters[l], &relres[l], NULL);
       t_cg += now_s() - tc;
       if (e) status = e;
       if (e && e != ORC_ERR_NOCONV) goto done;
@@ -848,16 +872,17 @@ done:
 int orc_excmg(int nx, int ny, int nz, double lx, double ly, double lz, int ncx, int ncy, int ncz,
               const double *f, const double *g, double tol, int max_iters, const int *fixed_iters, double *u,
               double *ut, double *w_out, int *iters, double *relres, double *seconds) {
-  return cascade(0, ORC_GUESS_QUARTIC, nx, ny, nz, lx, ly, lz, ncx, ncy, ncz, f, g, tol, max_iters, fixed_iters, u,
-                 ut, w_out, iters, relres, seconds);
+  return cascade(0, ORC_GUESS_QUARTIC, 0, nx, ny, nz, lx, ly, lz, ncx, ncy, ncz, f, g, tol, max_iters, fixed_iters,
+                 u, ut, w_out, iters, relres, seconds);
 }
 
-int orc_excmg_guess(int guess, int nx, int ny, int nz, double lx, double ly, double lz, int ncx, int ncy, int ncz,
-                    const double *f, const double *g, double tol, int max_iters, const int *fixed_iters, double *u,
-                    double *w_out, int *iters, double *relres) {
+int orc_excmg_variant(int guess, int stop_norm, int nx, int ny, int nz, double lx, double ly, double lz, int ncx,
+                      int ncy, int ncz, const double *f, const double *g, double tol, int max_iters,
+                      const int *fixed_iters, double *u, double *ut, double *w_out, int *iters, double *relres) {
   if (guess != ORC_GUESS_QUARTIC && guess != ORC_GUESS_QUADRATIC && guess != ORC_GUESS_LINEAR) return ORC_ERR_ARG;
-  return cascade(0, guess, nx, ny, nz, lx, ly, lz, ncx, ncy, ncz, f, g, tol, max_iters, fixed_iters, u, NULL, w_out,
-                 iters, relres, NULL);
+  if (stop_norm != 0 && stop_norm != 1) return ORC_ERR_ARG;
+  return cascade(0, guess, stop_norm, nx, ny, nz, lx, ly, lz, ncx, ncy, ncz, f, g, tol, max_iters, fixed_iters, u, ut,
+                 w_out, iters, relres, NULL);
 }
 
 /* ------------------------------------------------------------------------------------------------------------ */
@@ -912,7 +937,7 @@ int orc_adjoint(int nx, int ny, int nz, double lx, double ly, double lz, int ncx
   const size_t n = node_count(nx, ny, nz);
   double *lam = (double *)calloc(n, sizeof(double));
   if (!lam) return ORC_ERR_NOMEM;
-  int status = cascade(1, ORC_GUESS_QUARTIC, nx, ny, nz, lx, ly, lz, ncx, ncy, ncz, G, NULL, tol, max_iters, fixed_iters, lam, NULL,
+  int status = cascade(1, ORC_GUESS_QUARTIC, 0, nx, ny, nz, lx, ly, lz, ncx, ncy, ncz, G, NULL, tol, max_iters, fixed_iters, lam, NULL,
                        NULL, iters, relres, NULL);
   if (status && status != ORC_ERR_NOCONV) {
     free(lam);

