@@ -190,6 +190,42 @@ def bench_guess(ex, synth, torch, args, f, g, u_ref):
     return res
 
 
+def bench_tolerance(ex, synth, torch, args, f, g, u_exact):
+    """Accuracy of the extrapolated solution u~_h against the tolerance, on the benchmark's workload: its L2 error at
+    N/2 and N (the N/2 problem is the finest data at stride 2), the order between them, the finest grid's CG
+    iterations and the solve time at N, for the benchmark's setting, a tolerance of 1e-15 under either stopping norm,
+    and the level-dependent tolerance (tol_order 6: every coarser grid 64 times looser)."""
+    N = args.n
+    p = synth.smooth(0)
+    ue_d = torch.from_numpy(u_exact).cuda()
+    cfgs = [("bench", args.tol, "b", 0.0), ("b_1e-15", 1e-15, "b", 0.0), ("fg_1e-15", 1e-15, "fg", 0.0),
+            ("fg_1e-15_p6", 1e-15, "fg", 6.0)]
+    res = {}
+    for name, tol, sn, po in cfgs:
+        errs = []
+        for m in (N // 2, N):
+            q = N // m
+            fm = f[::q, ::q, ::q].contiguous() if q > 1 else f
+            gm = g[::q, ::q, ::q].contiguous() if q > 1 else g
+            s = ex.Solver((m, m, m), p.box, tol, stop_norm=sn, tol_order=po, max_iters=5000)
+            if m == N:
+                s.autotune()
+            _, ue, st = s.solve(fm, gm, want_ext=True)
+            d = ue - (ue_d[::q, ::q, ::q] if q > 1 else ue_d)
+            errs.append(float(torch.sqrt(torch.mean(d * d))))
+            if m == N:
+                u = s.empty()
+                ms, (_, _, st) = _timed(torch, lambda: s.solve(fm, gm, u=u), 2)
+                res[name] = {"tol": tol, "stop_norm": sn, "tol_order": po, "solve_ms": round(ms, 2),
+                             "iters": st["iters"]}
+                del u
+            del s, ue, d
+        res[name]["ext_L2"] = errs
+        res[name]["ext_order"] = round(float(np.log2(errs[0] / errs[1])), 2)
+    res["grids"] = [N // 2, N]
+    return res
+
+
 PROBE_BYTES = 2 << 30  # buffer of the streaming probe: its copy kernel reads PROBE_BYTES/2 and writes PROBE_BYTES/2
 COUNTERS_FILE = os.path.join(ROOT, "profiles", "excmg_512_fp64_hbm_counters.txt")
 KERNEL_SOURCES = ["paper_1507_05063_amd/csrc/kernels_cg.hip", "paper_1507_05063_amd/csrc/excmg_internal.h"]
@@ -273,6 +309,8 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the 96-problem batched section")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the 256^3 adjoint section")
     ap.add_argument("--no-guess", action="store_true", help="skip the initial-guess ablation (three 512^3 solves)")
+    ap.add_argument("--no-tolerance", action="store_true",
+                    help="skip the accuracy of u~_h against the tolerance (eight solves at N/2 and N)")
     args = ap.parse_args()
     if args.trace_summary:
         trace_summary(args.trace_summary)
@@ -422,6 +460,9 @@ def main():
     if not args.no_guess:
         out["guess_ablation"] = bench_guess(ex, synth, torch, args, f, g, u)
         print(f"# guess ablation: {out['guess_ablation']}", file=sys.stderr, flush=True)
+    if not args.no_tolerance:
+        out["tolerance"] = bench_tolerance(ex, synth, torch, args, f, g, u_exact)
+        print(f"# tolerance: {out['tolerance']}", file=sys.stderr, flush=True)
 
     if not args.no_cpu_baseline:
         # the oracle timed on the same step (solve with EXP_true, then the gradient) of the same inputs, repeated

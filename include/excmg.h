@@ -57,6 +57,12 @@ extern "C" {
                                     interpolation on cells of 2x2x2 2h elements (the earlier EXCMG's interpolation,
                                     which the remark after eq. (inter) in Section 4.3 finds too weak here) */
 #define EXCMG_GUESS_LINEAR 16u   /* trilinear interpolation of u_2h, no extrapolation (the CMG method, Section 3) */
+/* The norm ||f_h|| of the stopping test (Algorithm 1).  Default: f_h is the right-hand side b of the eliminated
+ * system, the vector the CG's residual is measured against.  With this flag f_h is the vector of the discrete
+ * equations before elimination: R f at the interior nodes and the Dirichlet value g at the boundary nodes (the same
+ * test with a larger ||f_h|| on fine grids, so more CG iterations; the finer-grid errors the paper prints for its
+ * Tables 1-12 follow this reading, its iteration counts the default one). */
+#define EXCMG_STOP_F_G 32u
 
 #define EXCMG_MAX_LEVELS 16
 #define EXCMG_MAX_HISTORY 256
@@ -84,12 +90,20 @@ typedef struct {
   int32_t n[3];         /* Nx, Ny, Nz: cells per axis on the finest grid */
   int32_t n_coarse[3];  /* cells per axis on the coarsest grid H; {0,0,0} = automatic: halve the finest counts
                            while the halves are all even and >= 2 and the largest half is >= 4 */
-  double tol;           /* relative-residual tolerance epsilon of Algorithm 1, on every level, > 0 */
+  double tol;           /* relative-residual tolerance epsilon of Algorithm 1, on every level (see tol_order), > 0 */
   int32_t precision;    /* EXCMG_FP64 or EXCMG_FP32_IR */
   double inner_tol;     /* FP32_IR: largest residual reduction asked of one inner FP32 solve (0 = 1e-5); an inner
                            solve also stops once its residual is half the outer target tol*||f_h|| */
   int32_t max_iters;    /* CG iterations allowed per level (FP32_IR: inner iterations per outer step); 0 = 10000 */
   uint32_t flags;       /* EXCMG_WANT_* */
+  double tol_order;     /* level-dependent tolerance (not in the paper, which uses one tol on every grid and notes
+                           that the extrapolated solution then loses its sixth order on fine grids, Section 5.1):
+                           0 = tol on every grid; p > 0: grid l of L (coarsest 0) relaxes to
+                           tol * 2^(p (L-1-l)), at most max(tol, 1e-2), so tol holds on the finest grid and each
+                           coarser grid's algebraic error keeps the ratio to h^p of the finest's.  p = 6 with
+                           EXCMG_STOP_F_G (whose ||f_h|| / sqrt(unknowns) does not grow as h falls) keeps the
+                           algebraic error of every grid proportional to the sixth-order truncation error.  0 <= p
+                           <= 16 */
 } excmg_problem;
 
 /* Statistics of one call (host struct, filled by the library). */
@@ -157,8 +171,8 @@ int excmg_batch_workspace_bytes(int32_t count, size_t *bytes);
  * other streams must be complete.  The cascades run in step, grid s of every problem in step s: each kernel launch
  * covers every problem it concerns (the workgroups of one launch are split among the problems), so a batch costs
  * about as many launches as its largest problem.  Each problem keeps its own precision, tolerance and iteration
- * limits; the history and timing flags are ignored.  Handles set up with an EXCMG_GUESS_* flag are rejected
- * (EXCMG_ERR_ARG): batched solves start every grid from EXP_finite.
+ * limits; the history and timing flags are ignored.  Handles set up with an EXCMG_GUESS_* flag or EXCMG_STOP_F_G
+ * are rejected (EXCMG_ERR_ARG): batched solves start every grid from EXP_finite and take the default stopping norm.
  * batch_ws: device memory of at least excmg_batch_workspace_bytes(count), 256-byte aligned, owned by the caller.
  * stats (host, nullable): count entries (ms_total = the host time of the whole call).  ms_per_problem (host,
  * nullable): count entries, the device time from the start of the batch until problem b's finest grid converged.

@@ -62,8 +62,8 @@ def lib():
             ("orc_apply_RT", [_I, _I, _I, _P, _P]),
             ("orc_apply_LIBT", g6 + [_P, _P]),
             ("orc_initial_guess", [_I, _I, _I, _I, _P, _P, _P, _P]),
-            ("orc_excmg_variant", [_I, _I, _I, _I, _I, _D, _D, _D, _I, _I, _I, _P, _P, _D, _I, _P, _P, _P, _P, _P,
-                                   _P]),
+            ("orc_excmg_variant", [_I, _I, _I, _I, _I, _D, _D, _D, _I, _I, _I, _P, _P, _D, _D, _I, _P, _P, _P, _P,
+                                   _P, _P]),
         ]:
             fn = getattr(L, name)
             fn.argtypes = args
@@ -223,9 +223,11 @@ def initial_guess(kind, u2h, u4h, g):
 STOP_NORMS = {"b": 0, "fg": 1}
 
 
-def excmg_guess(kind, f, g, box, n_coarse, tol, max_iters=100000, fixed_iters=None, stop_norm="b", want_ext=False):
+def excmg_guess(kind, f, g, box, n_coarse, tol, max_iters=100000, fixed_iters=None, stop_norm="b", want_ext=False,
+                tol_order=0.0):
     """Algorithm 1 with the initial guess of the given kind on every level from 2 on, and the stopping test's norm
-    read as stop_norm says ("b": the eliminated right-hand side; "fg": R f inside and g on the boundary).
+    read as stop_norm says ("b": the eliminated right-hand side; "fg": R f inside and g on the boundary); tol_order
+    p > 0 relaxes level l of the finest Lt to tol * 2^(p (Lt - l)) (at most max(tol, 1e-2)).
     Returns dict(u, ut, w, iters, relres): w is the finest level's initial guess, ut EXP_true (want_ext)."""
     k = GUESS_KINDS[kind] if isinstance(kind, str) else int(kind)
     f, g = _c(f), _c(g)
@@ -240,7 +242,8 @@ def excmg_guess(kind, f, g, box, n_coarse, tol, max_iters=100000, fixed_iters=No
         assert fx.size == nl
     ut = np.empty_like(f) if want_ext else None
     code = lib().orc_excmg_variant(k, STOP_NORMS[stop_norm], *n, *(float(v) for v in box),
-                                   *(int(v) for v in n_coarse), _ptr(f), _ptr(g), float(tol), int(max_iters),
+                                   *(int(v) for v in n_coarse), _ptr(f), _ptr(g), float(tol), float(tol_order),
+                                   int(max_iters),
                                    None if fx is None else fx.ctypes.data, _ptr(u), _ptr(ut),
                                    _ptr(w) if nl >= 3 else None, iters.ctypes.data, relres.ctypes.data)
     _check(code, "excmg_guess")

@@ -732,9 +732,9 @@ static void sample_stride(int nx, int ny, int nz, const double *fine, int s, int
 
 /* shared cascade; mode 0: b_l from (f, g); mode 1: b_l = G on the interior, zero Dirichlet data */
 static int cascade(int mode, int guess, int stop_norm, int nx, int ny, int nz, double lx, double ly, double lz,
-                   int ncx, int ncy, int ncz, const double *f, const double *g, double tol, int max_iters,
-                   const int *fixed_iters, double *u, double *ut, double *w_out, int *iters, double *relres,
-                   double *seconds) {
+                   int ncx, int ncy, int ncz, const double *f, const double *g, double tol, double tol_order,
+                   int max_iters, const int *fixed_iters, double *u, double *ut, double *w_out, int *iters,
+                   double *relres, double *seconds) {
   if (!f || !u || !iters || !relres) return ORC_ERR_ARG;
   if (mode == 0 && !g) return ORC_ERR_ARG;
   if (!(lx > 0) || !(ly > 0) || !(lz > 0) || !(tol > 0) || max_iters < 0) return ORC_ERR_ARG;
@@ -816,7 +816,14 @@ static int cascade(int mode, int guess, int stop_norm, int nx, int ny, int nz, d
       /* the stopping test ||r|| <= tol ||f_h||: f_h = b (the eliminated right-hand side) or, with stop_norm 1, the
        * vector of R f on the interior nodes and g on the boundary nodes; the CG's test is against ||b||, so the
        * tolerance is rescaled by ||f_h|| / ||b|| */
+      /* the level's tolerance: tol on every level, or (a schedule the paper does not give, for its remark on the
+       * extrapolated solution in Section 5.1) tol * 2^(tol_order (Lt - l)), capped at max(tol, 1e-2) */
       double tol_l = tol;
+      if (tol_order > 0.0) {
+        const double cap = tol > 1e-2 ? tol : 1e-2;
+        tol_l = tol * pow(2.0, tol_order * (double)(Lt - l));
+        if (tol_l > cap) tol_l = cap;
+      }
       if (stop_norm == 1) {
         double *rf = (double *)malloc(nl * sizeof(double));
         if (!rf) {
@@ -834,7 +841,7 @@ static int cascade(int mode, int guess, int stop_norm, int nx, int ny, int nz, d
               }
         free(rf);
         const double bn = sqrt(dot_interior(mx, my, mz, bl, bl));
-        tol_l = bn > 0.0 ? tol * sqrt(fg2) / bn : tol;
+        tol_l = bn > 0.0 ? tol_l * sqrt(fg2) / bn : tol_l;
       }
       const double tc = now_s();
       e = orc_cg(mx, my, mz, hx, hy, hz, bl, ul, tol_l, max_iters, fi, &iters[l], &relres[l], NULL);
@@ -872,17 +879,19 @@ done:
 int orc_excmg(int nx, int ny, int nz, double lx, double ly, double lz, int ncx, int ncy, int ncz,
               const double *f, const double *g, double tol, int max_iters, const int *fixed_iters, double *u,
               double *ut, double *w_out, int *iters, double *relres, double *seconds) {
-  return cascade(0, ORC_GUESS_QUARTIC, 0, nx, ny, nz, lx, ly, lz, ncx, ncy, ncz, f, g, tol, max_iters, fixed_iters,
-                 u, ut, w_out, iters, relres, seconds);
+  return cascade(0, ORC_GUESS_QUARTIC, 0, nx, ny, nz, lx, ly, lz, ncx, ncy, ncz, f, g, tol, 0.0, max_iters,
+                 fixed_iters, u, ut, w_out, iters, relres, seconds);
 }
 
 int orc_excmg_variant(int guess, int stop_norm, int nx, int ny, int nz, double lx, double ly, double lz, int ncx,
-                      int ncy, int ncz, const double *f, const double *g, double tol, int max_iters,
-                      const int *fixed_iters, double *u, double *ut, double *w_out, int *iters, double *relres) {
+                      int ncy, int ncz, const double *f, const double *g, double tol, double tol_order,
+                      int max_iters, const int *fixed_iters, double *u, double *ut, double *w_out, int *iters,
+                      double *relres) {
   if (guess != ORC_GUESS_QUARTIC && guess != ORC_GUESS_QUADRATIC && guess != ORC_GUESS_LINEAR) return ORC_ERR_ARG;
   if (stop_norm != 0 && stop_norm != 1) return ORC_ERR_ARG;
-  return cascade(0, guess, stop_norm, nx, ny, nz, lx, ly, lz, ncx, ncy, ncz, f, g, tol, max_iters, fixed_iters, u, ut,
-                 w_out, iters, relres, NULL);
+  if (!(tol_order >= 0.0) || tol_order > 16.0) return ORC_ERR_ARG;
+  return cascade(0, guess, stop_norm, nx, ny, nz, lx, ly, lz, ncx, ncy, ncz, f, g, tol, tol_order, max_iters,
+                 fixed_iters, u, ut, w_out, iters, relres, NULL);
 }
 
 /* ------------------------------------------------------------------------------------------------------------ */
@@ -937,8 +946,8 @@ int orc_adjoint(int nx, int ny, int nz, double lx, double ly, double lz, int ncx
   const size_t n = node_count(nx, ny, nz);
   double *lam = (double *)calloc(n, sizeof(double));
   if (!lam) return ORC_ERR_NOMEM;
-  int status = cascade(1, ORC_GUESS_QUARTIC, 0, nx, ny, nz, lx, ly, lz, ncx, ncy, ncz, G, NULL, tol, max_iters, fixed_iters, lam, NULL,
-                       NULL, iters, relres, NULL);
+  int status = cascade(1, ORC_GUESS_QUARTIC, 0, nx, ny, nz, lx, ly, lz, ncx, ncy, ncz, G, NULL, tol, 0.0, max_iters,
+                       fixed_iters, lam, NULL, NULL, iters, relres, NULL);
   if (status && status != ORC_ERR_NOCONV) {
     free(lam);
     return status;

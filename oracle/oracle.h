@@ -114,10 +114,12 @@ int orc_excmg(int nx, int ny, int nz, double lx, double ly, double lz, int ncx, 
 /* orc_excmg with the initial guess of kind guess (ORC_GUESS_*) on every level from 2 on, and the norm of the
  * stopping test ||A_h u_h - f_h|| <= eps ||f_h|| (Algorithm 1) read as stop_norm says: 0 = f_h is the eliminated
  * right-hand side b (the reading of orc_excmg), 1 = f_h is R f on the interior nodes and g on the boundary nodes
- * (the boundary values kept as identity rows).  No timing. */
+ * (the boundary values kept as identity rows).  tol_order = p > 0: level l of the finest Lt relaxes to
+ * eps_l = tol * 2^(p (Lt - l)), capped at max(tol, 1e-2) (0: tol on every level).  No timing. */
 int orc_excmg_variant(int guess, int stop_norm, int nx, int ny, int nz, double lx, double ly, double lz, int ncx,
-                      int ncy, int ncz, const double *f, const double *g, double tol, int max_iters,
-                      const int *fixed_iters, double *u, double *ut, double *w_out, int *iters, double *relres);
+                      int ncy, int ncz, const double *f, const double *g, double tol, double tol_order,
+                      int max_iters, const int *fixed_iters, double *u, double *ut, double *w_out, int *iters,
+                      double *relres);
 
 /* Adjoint of the exact discrete map u = (interior: M^-1 b(f, g); boundary: g) for an upstream gradient G
  * (node array, dL/du).  lambda solves M lambda = G_I by the same cascade (level data: G sampled on the interior),

@@ -24,7 +24,8 @@ def _torch():
     return torch
 
 
-def _problem(n, box, tol, n_coarse=(0, 0, 0), precision=FP64, inner_tol=0.0, max_iters=0, flags=0):
+def _problem(n, box, tol, n_coarse=(0, 0, 0), precision=FP64, inner_tol=0.0, max_iters=0, flags=0,
+             tol_order=0.0):
     p = _lib.Problem()
     for d in range(3):
         p.box[d] = float(box[d])
@@ -35,6 +36,7 @@ def _problem(n, box, tol, n_coarse=(0, 0, 0), precision=FP64, inner_tol=0.0, max
     p.inner_tol = float(inner_tol)
     p.max_iters = int(max_iters)
     p.flags = int(flags)
+    p.tol_order = float(tol_order)
     return p
 
 
@@ -80,9 +82,14 @@ class Solver:
 
     def __init__(self, n: Sequence[int], box=(1.0, 1.0, 1.0), tol: float = 1e-10, n_coarse=(0, 0, 0),
                  precision: int = FP64, inner_tol: float = 0.0, max_iters: int = 0, history: bool = False,
-                 timing: bool = False, graphs: bool = True, guess: str = "quartic", stream=None):
+                 timing: bool = False, graphs: bool = True, guess: str = "quartic", stop_norm: str = "b",
+                 tol_order: float = 0.0, stream=None):
         """guess: the initial guess of every grid from the third on: "quartic" (EXP_finite, the paper's method),
-        "quadratic" (the same extrapolation, tri-quadratic interpolation) or "linear" (CMG: trilinear u_2h)."""
+        "quadratic" (the same extrapolation, tri-quadratic interpolation) or "linear" (CMG: trilinear u_2h).
+        stop_norm: the ||f_h|| of the stopping test: "b" (the eliminated right-hand side) or "fg" (R f inside, g on
+        the boundary).
+        tol_order: p >= 0; grid l of L relaxes to tol * 2^(p (L-1-l)) (at most max(tol, 1e-2)): tol on the finest grid,
+        looser on the coarser ones (0: tol everywhere, Algorithm 1)."""
         torch = _torch()
         self.n = tuple(int(v) for v in n)
         self.box = tuple(float(v) for v in box)
@@ -91,9 +98,13 @@ class Solver:
         if guess not in _lib.GUESS_FLAGS:
             raise ValueError(f"guess must be one of {sorted(_lib.GUESS_FLAGS)}, not {guess!r}")
         self.guess = guess
+        if stop_norm not in _lib.STOP_NORM_FLAGS:
+            raise ValueError(f"stop_norm must be one of {sorted(_lib.STOP_NORM_FLAGS)}, not {stop_norm!r}")
+        self.stop_norm = stop_norm
         flags = (WANT_HISTORY if history else 0) | (WANT_TIMING if timing else 0) | (0 if graphs else NO_GRAPHS)
-        flags |= _lib.GUESS_FLAGS[guess]
-        self._p = _problem(self.n, self.box, tol, n_coarse, precision, inner_tol, max_iters, flags)
+        flags |= _lib.GUESS_FLAGS[guess] | _lib.STOP_NORM_FLAGS[stop_norm]
+        self.tol_order = float(tol_order)
+        self._p = _problem(self.n, self.box, tol, n_coarse, precision, inner_tol, max_iters, flags, tol_order)
         nbytes = ctypes.c_size_t(0)
         _lib.check(_lib.lib().excmg_workspace_bytes(ctypes.byref(self._p), ctypes.byref(nbytes)),
                    "excmg_workspace_bytes")

@@ -14,9 +14,10 @@ LIB_PATH = os.path.join(HERE, "libexcmg.so")
 OK = 0
 ERR_ARG, ERR_SHAPE, ERR_NONFINITE, ERR_NOCONV, ERR_BREAKDOWN, ERR_HIP, ERR_WORKSPACE = -1, -2, -3, -4, -5, -6, -7
 FP64, FP32_IR = 0, 1
-WANT_HISTORY, WANT_TIMING, NO_GRAPHS, GUESS_QUADRATIC, GUESS_LINEAR = 1, 2, 4, 8, 16
+WANT_HISTORY, WANT_TIMING, NO_GRAPHS, GUESS_QUADRATIC, GUESS_LINEAR, STOP_F_G = 1, 2, 4, 8, 16, 32
 GUESS_KINDS = {"quartic": 0, "quadratic": 1, "linear": 2}
 GUESS_FLAGS = {"quartic": 0, "quadratic": GUESS_QUADRATIC, "linear": GUESS_LINEAR}
+STOP_NORM_FLAGS = {"b": 0, "fg": STOP_F_G}
 MAX_LEVELS, MAX_HISTORY = 16, 256
 
 K_CLASSES = ["cg_a", "cg_b", "cg_a32", "cg_b32", "resid", "finalize", "rhs", "exp_finite", "exp_true", "dsolve",
@@ -33,6 +34,7 @@ class Problem(ctypes.Structure):
         ("inner_tol", ctypes.c_double),
         ("max_iters", ctypes.c_int32),
         ("flags", ctypes.c_uint32),
+        ("tol_order", ctypes.c_double),
     ]
 
 

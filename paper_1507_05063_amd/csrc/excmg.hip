@@ -94,14 +94,24 @@ int validate(const excmg_problem *p) {
   if (p->inner_tol < 0.0 || !isfinite(p->inner_tol) || p->inner_tol >= 1.0) return EXCMG_ERR_ARG;
   if (p->max_iters < 0) return EXCMG_ERR_ARG;
   if (p->flags & ~(EXCMG_WANT_HISTORY | EXCMG_WANT_TIMING | EXCMG_NO_GRAPHS | EXCMG_GUESS_QUADRATIC |
-                   EXCMG_GUESS_LINEAR))
+                   EXCMG_GUESS_LINEAR | EXCMG_STOP_F_G))
     return EXCMG_ERR_ARG;
   if ((p->flags & EXCMG_GUESS_QUADRATIC) && (p->flags & EXCMG_GUESS_LINEAR)) return EXCMG_ERR_ARG;
+  if (!(p->tol_order >= 0.0) || p->tol_order > 16.0) return EXCMG_ERR_ARG;
   return EXCMG_OK;
 }
 
 // z planes per workgroup of the residual sweeps on large grids
 constexpr int kResidChunk = 64;
+
+// The relative-residual tolerance of grid l: tol on every grid, or with tol_order = p > 0, tol * 2^(p (L-1-l)) capped
+// at max(tol, 1e-2) (tol on the finest grid, looser on each coarser one).
+double level_tol(const excmg_problem &p, int l, int L) {
+  if (!(p.tol_order > 0.0)) return p.tol;
+  const double cap = p.tol > 1e-2 ? p.tol : 1e-2;
+  const double t = p.tol * exp2(p.tol_order * (double)(L - 1 - l));
+  return t < cap ? t : cap;
+}
 
 int guess_kind(uint32_t flags) {
   if (flags & EXCMG_GUESS_QUADRATIC) return kGuessQuadratic;
@@ -352,12 +362,13 @@ bool self_finalizing(const Level &lv, bool fp32) {
 // launched: iteration index for the kernel timing.
 void launch_iteration(excmg_handle *h, int l, int fp32, bool first, hipStream_t s, int launched, int outer) {
   Level &lv = h->lo.lev[l];
+  const double tol = level_tol(h->p, l, h->lo.L);
   double *pa = h->partials, *pb = h->partials + h->lo.npart;
   if (fp32) {
     if (self_finalizing(lv, true)) {
       {
         Tick t(h, EXCMG_K_CG_A32, l, launched, outer);
-        launch_selfred_a<float>(lv.swA32, h->r32, h->p32a, h->p32b, h->cs2, pb, sweep_blocks(lv.swB32), h->p.tol,
+        launch_selfred_a<float>(lv.swA32, h->r32, h->p32a, h->p32b, h->cs2, pb, sweep_blocks(lv.swB32), tol,
                                 pa, s);
       }
       Tick t(h, EXCMG_K_CG_B32, l, launched, outer);
@@ -376,7 +387,7 @@ void launch_iteration(excmg_handle *h, int l, int fp32, bool first, hipStream_t 
     {
       Tick t(h, EXCMG_K_CG_A, l, launched);
       launch_selfred_a<double>(lv.swA, h->r, h->p0, h->p1, h->cs, pb,
-                               first ? sweep_blocks(lv.sw) : sweep_blocks(lv.swB), h->p.tol, pa, s);
+                               first ? sweep_blocks(lv.sw) : sweep_blocks(lv.swB), tol, pa, s);
     }
     Tick t(h, EXCMG_K_CG_B, l, launched);
     launch_selfred_b<double>(lv.swB, lv.u, h->r, h->p0, h->p1, h->cs, pa, sweep_blocks(lv.swA), pb, s);
@@ -452,7 +463,7 @@ int cg64(excmg_handle *h, int l, const RhsSrc &rs, bool finest, int *iters, doub
       launch_residual_partials(lv.sw, lv.u, rs, h->r, partsB, s);
       launch_selfred_init(h->cs, maxit, hist_on, 0, s);
     } else {
-      launch_residual(lv.sw, lv.u, rs, h->r, h->cs, h->partials, h->p.tol, maxit, hist_on, s);
+      launch_residual(lv.sw, lv.u, rs, h->r, h->cs, h->partials, level_tol(h->p, l, h->lo.L), maxit, hist_on, s);
     }
   }
   int e = last_error();
@@ -489,6 +500,7 @@ int cg_ir(excmg_handle *h, int l, const RhsSrc &rs, bool finest, int *iters, int
   Level &lv = h->lo.lev[l];
   const hipStream_t s = h->stream;
   const double eta = h->p.inner_tol > 0.0 ? h->p.inner_tol : 1e-5;
+  const double tol = level_tol(h->p, l, h->lo.L);
   const int maxit = h->p.max_iters > 0 ? h->p.max_iters : 10000;
   const int max_outer = 30;
   int total = 0;
@@ -498,7 +510,7 @@ int cg_ir(excmg_handle *h, int l, const RhsSrc &rs, bool finest, int *iters, int
   for (;; ++outer) {
     {
       Tick t(h, EXCMG_K_RESID, l);
-      launch_residual_cast(lv.sw, lv.u, rs, h->r, lv.g32, h->r32, h->d32, h->cs, h->cs2, h->partials, h->p.tol, eta,
+      launch_residual_cast(lv.sw, lv.u, rs, h->r, lv.g32, h->r32, h->d32, h->cs, h->cs2, h->partials, tol, eta,
                            outer, max_outer, maxit, s);
     }
     int e = last_error();
@@ -545,8 +557,8 @@ int small_cg(excmg_handle *h, int l, const RhsSrc &rs, bool exact, bool finest, 
   const int maxit = h->p.max_iters > 0 ? h->p.max_iters : 10000;
   {
     Tick t(h, EXCMG_K_DSOLVE, l);
-    launch_small_cg(lv.g, lv.u, rs, lv.g, h->r, h->p0, h->p1, lv.st, h->cs, h->p.tol, maxit, exact ? 1 : 0, hist_on,
-                    h->stream);
+    launch_small_cg(lv.g, lv.u, rs, lv.g, h->r, h->p0, h->p1, lv.st, h->cs, level_tol(h->p, l, h->lo.L), maxit,
+                    exact ? 1 : 0, hist_on, h->stream);
   }
   int e = last_error();
   if (e) return e;
@@ -638,6 +650,12 @@ int cascade(excmg_handle *h, int mode, const double *f, const double *g, excmg_s
     rs.a = 1.0 / (lv.h[0] * lv.h[0]);
     rs.b = 1.0 / (lv.h[1] * lv.h[1]);
     rs.c = 1.0 / (lv.h[2] * lv.h[2]);
+    rs.fg = (mode == 0 && (h->p.flags & EXCMG_STOP_F_G)) ? 1 : 0;
+    if (h->p.flags & EXCMG_STOP_F_G) {
+      // the boundary half of the stopping test's norm for this grid (0 for the adjoint, whose test stays on ||b||)
+      Tick t(h, EXCMG_K_OTHER, l);
+      launch_boundary_g2(rs, lv.g, h->cs, s);
+    }
     int e = EXCMG_OK;
     int it = 0, outer = 0;
     double rr = 0.0;
@@ -742,7 +760,7 @@ void batch_entry(excmg_handle *h, int problem, int l, const double *f, const dou
   E->level = l;
   E->cap = h->p.max_iters > 0 ? h->p.max_iters : 10000;
   E->max_outer = 30;
-  E->tol = h->p.tol;
+  E->tol = level_tol(h->p, l, h->lo.L);
   E->eta = h->p.inner_tol > 0.0 ? h->p.inner_tol : 1e-5;
   E->swA = lv.swA;
   E->swB = lv.swB;
@@ -760,6 +778,7 @@ void batch_entry(excmg_handle *h, int problem, int l, const double *f, const dou
   E->rs.g = g;
   E->rs.s = lv.stride;
   E->rs.mode = 0;
+  E->rs.fg = 0;
   E->rs.a = 1.0 / (lv.h[0] * lv.h[0]);
   E->rs.b = 1.0 / (lv.h[1] * lv.h[1]);
   E->rs.c = 1.0 / (lv.h[2] * lv.h[2]);
@@ -1118,7 +1137,8 @@ int excmg_setup(const excmg_problem *p, void *workspace, size_t bytes, void *hip
         return EXCMG_ERR_HIP;
       }
   }
-  if (hipStreamSynchronize(h->stream) != hipSuccess) {
+  launch_clear_gbnd2(h->cs, h->cs2, h->stream);
+  if (hipGetLastError() != hipSuccess || hipStreamSynchronize(h->stream) != hipSuccess) {
     delete h;
     return EXCMG_ERR_HIP;
   }
@@ -1338,6 +1358,7 @@ int excmg_op_rhs(const int32_t n[3], const double box[3], const double *f, const
   rs.g = g;
   rs.s = 1;
   rs.mode = 0;
+  rs.fg = 0;
   rs.a = (n[0] / box[0]) * (n[0] / box[0]);
   rs.b = (n[1] / box[1]) * (n[1] / box[1]);
   rs.c = (n[2] / box[2]) * (n[2] / box[2]);
@@ -1445,7 +1466,7 @@ int excmg_solve_batched(excmg_handle *const *hs, int32_t count, const double *co
   if (!hs || count <= 0 || !f || !g || !u) return EXCMG_ERR_ARG;
   for (int b = 0; b < count; ++b)
     if (!hs[b] || !f[b] || !g[b] || !u[b] || hs[b]->device != hs[0]->device ||
-        guess_kind(hs[b]->p.flags) != kGuessQuartic)
+        guess_kind(hs[b]->p.flags) != kGuessQuartic || (hs[b]->p.flags & EXCMG_STOP_F_G))
       return EXCMG_ERR_ARG;
   if (!batch_ws || ((uintptr_t)batch_ws & 255) || batch_bytes < batch_ws_bytes(count)) return EXCMG_ERR_WORKSPACE;
   DeviceGuard dg(hs[0]->device);

@@ -84,6 +84,8 @@ struct RhsSrc {
   int s;            // stride into the finest arrays
   int mode;
   double a, b, c;   // 1/hx^2, 1/hy^2, 1/hz^2 of the level
+  int fg;           // 1 (mode 0 only): the stopping test's norm is that of (R f inside, g on the boundary), so the
+                    // residual sweeps sum (R f)^2 where they otherwise sum b^2 (EXCMG_STOP_F_G)
 };
 
 // A's couplings to the Dirichlet values of the boundary neighbours of (i,j,k) (only nodes next to the boundary have any)
@@ -115,20 +117,33 @@ __device__ __noinline__ inline double rhs_boundary_terms(const RhsSrc &rs, int n
   return rhs_boundary_terms_inl(rs, nx, ny, nz, i, j, k);
 }
 
+// b at an interior node; rf (out): R f there (mode 0; the adjoint's G in mode 1)
 template <bool kInline = false>
-__device__ __forceinline__ double rhs_at(const RhsSrc &rs, int nx, int ny, int nz, int i, int j, int k) {
+__device__ __forceinline__ double rhs_at(const RhsSrc &rs, int nx, int ny, int nz, int i, int j, int k, double &rf) {
   const int s = rs.s;
   auto F = [&](int di, int dj, int dk) { return rs.f[rs.gf.at((i + di) * s, (j + dj) * s, (k + dk) * s)]; };
-  if (rs.mode == 1) return F(0, 0, 0);
-  const double rf = 0.5 * (6.0 * F(0, 0, 0) + (F(1, 0, 0) + F(-1, 0, 0)) + (F(0, 1, 0) + F(0, -1, 0)) +
-                           (F(0, 0, 1) + F(0, 0, -1)));
+  if (rs.mode == 1) {
+    rf = F(0, 0, 0);
+    return rf;
+  }
+  rf = 0.5 * (6.0 * F(0, 0, 0) + (F(1, 0, 0) + F(-1, 0, 0)) + (F(0, 1, 0) + F(0, -1, 0)) + (F(0, 0, 1) + F(0, 0, -1)));
   double lg = 0.0;
   if (i == 1 || j == 1 || k == 1 || i == nx - 1 || j == ny - 1 || k == nz - 1)
     lg = kInline ? rhs_boundary_terms_inl(rs, nx, ny, nz, i, j, k) : rhs_boundary_terms(rs, nx, ny, nz, i, j, k);
   return -rf + lg;
 }
+template <bool kInline = false>
+__device__ __forceinline__ double rhs_at(const RhsSrc &rs, int nx, int ny, int nz, int i, int j, int k) {
+  double rf;
+  return rhs_at<kInline>(rs, nx, ny, nz, i, j, k, rf);
+}
+// the term a node adds to the squared norm of the stopping test: b^2, or (R f)^2 in the EXCMG_STOP_F_G reading
+__device__ __forceinline__ double stop_norm_term(const RhsSrc &rs, double bv, double rf) {
+  return rs.fg ? rf * rf : bv * bv;
+}
 
-// Device-resident CG state of one solve (one per problem in a batch).  Written only by the finalize kernels.
+// Device-resident CG state of one solve (one per problem in a batch).  Written only by the finalize kernels (and
+// gbnd2 by boundary_g2_kernel).
 struct CgState {
   double rho;      // r.r of the current residual
   double rho_old;  // r.r of the previous residual
@@ -149,6 +164,8 @@ struct CgState {
   int iterA, iterB;
   int preset;
   int pad_;
+  double gbnd2;    // added to the squared norm of the stopping test: the sum of g^2 over the grid's boundary nodes
+                   // under EXCMG_STOP_F_G, else 0 (set at setup and by boundary_g2_kernel)
   double rhoA[2];
   double hist[EXCMG_MAX_HISTORY];
 };
@@ -203,6 +220,10 @@ void launch_selfred_b(const Sweep &swB, T *u, T *r, const T *p0, const T *p1, Cg
 int selfred_max_blocks();
 // the CG state before the first self-finalizing iteration (iterA = 0, not done, preset as given)
 void launch_selfred_init(CgState *cs, int max_iters, int hist_on, int preset, hipStream_t st);
+// cs->gbnd2 = the sum of g^2 over the boundary nodes of grid g (0 if rs.fg is 0 or rs.mode is 1); one workgroup
+void launch_boundary_g2(const RhsSrc &rs, const Grid &g, CgState *cs, hipStream_t st);
+// cs->gbnd2 = 0 for each state (at setup)
+void launch_clear_gbnd2(CgState *a, CgState *b, hipStream_t st);
 // residual sweep writing [r.r | b.b] partials without a finalize (for the self-finalizing iterations)
 void launch_residual_partials(const Sweep &sw, const double *u, const RhsSrc &rs, double *r, double *parts,
                               hipStream_t st);

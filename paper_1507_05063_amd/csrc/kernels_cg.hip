@@ -545,7 +545,7 @@ __global__ __launch_bounds__(NT) void cg_selfred_a_kernel(Sweep sw, const T *__r
     stop2 = cs->stop2;
   } else if (k == 0) {
     rho = block_fixed_sum(partsB, nbB, shf);
-    bb = block_fixed_sum(partsB + nbB, nbB, shf);
+    bb = block_fixed_sum(partsB + nbB, nbB, shf) + cs->gbnd2;
     stop2 = tol * tol * bb;
   } else {
     rho = block_fixed_sum(partsB, nbB, shf);
@@ -650,7 +650,7 @@ struct PolResid {
     const double rn = bv - out;
     st1<NTP>(rn, &r[idx]);
     acc0 += rn * rn;
-    acc1 += bv * bv;
+    acc1 += stop_norm_term(rp.rs, bv, rf);
   }
 };
 
@@ -695,7 +695,7 @@ struct PolResidCast {
     st1<NTP>(rf32, &r32[q]);
     st1<NTP>(0.0f, &d32[q]);
     acc0 += rn * rn;
-    acc1 += bv * bv;
+    acc1 += stop_norm_term(rp.rs, bv, rf);
     acc2 += (double)rf32 * (double)rf32;
   }
 };
@@ -767,13 +767,57 @@ __global__ __launch_bounds__(256) void boundary_terms_kernel(RhsSrc rs, Grid g, 
   boundary_terms_block(rs, g, out, blockIdx.x, blockIdx.y, blockIdx.z);
 }
 
+// cs->gbnd2 = the sum of g^2 over the boundary nodes of grid g, the boundary half of the squared norm of the stopping
+// test under EXCMG_STOP_F_G (0 otherwise).  Node m of the enumeration: the planes k = 0 and k = nz whole, then per
+// inner plane the rows j = 0 and j = ny whole and the two end nodes i = 0, nx of every inner row.  One workgroup,
+// fixed order.
+__global__ __launch_bounds__(FT) void boundary_g2_kernel(RhsSrc rs, Grid g, CgState *cs) {
+  __shared__ double sh[FT / 64 + 1];
+  const long long px = g.nx + 1, py = g.ny + 1;
+  const long long full = 2 * px * py;               // the two end planes
+  const long long per = 2 * px + 2 * (g.ny - 1);     // boundary nodes of one inner plane
+  const long long total = rs.fg ? full + (long long)(g.nz - 1) * per : 0;
+  const int s = rs.s;
+  double acc = 0.0;
+  for (long long m = threadIdx.x; m < total; m += FT) {
+    int i, j, k;
+    if (m < full) {
+      const long long t = m % (px * py);
+      k = m < px * py ? 0 : g.nz;
+      i = (int)(t % px);
+      j = (int)(t / px);
+    } else {
+      const long long q = m - full;
+      k = 1 + (int)(q / per);
+      const long long t = q % per;
+      if (t < 2 * px) {
+        i = (int)(t % px);
+        j = t < px ? 0 : g.ny;
+      } else {
+        const long long e = t - 2 * px;
+        i = (e & 1) ? g.nx : 0;
+        j = 1 + (int)(e >> 1);
+      }
+    }
+    const double v = rs.g[rs.gf.at(i * s, j * s, k * s)];
+    acc += v * v;
+  }
+  const double t = block_sum<FT>(acc, sh);
+  if (threadIdx.x == 0) cs->gbnd2 = t;
+}
+
+__global__ void clear_gbnd2_kernel(CgState *a, CgState *b) {
+  a->gbnd2 = 0.0;
+  b->gbnd2 = 0.0;
+}
+
 // --------------------------------------------------------------------------------------------------------- finalize
 
 __global__ __launch_bounds__(FT) void finalize_init_kernel(CgState *cs, const double *partials, int nparts, double tol,
                                                            int max_iters, int hist_on) {
   __shared__ double sh[FT / 64 + 1];
   const double rho = fixed_sum(partials, nparts, sh);
-  const double bb = fixed_sum(partials + nparts, nparts, sh);
+  const double bb = fixed_sum(partials + nparts, nparts, sh) + cs->gbnd2;
   if (threadIdx.x == 0) state_init(cs, rho, bb, tol, max_iters, hist_on);
 }
 
@@ -782,7 +826,7 @@ __global__ __launch_bounds__(FT) void finalize_ir_kernel(CgState *outer, CgState
                                                          int max_outer, int max_inner) {
   __shared__ double sh[FT / 64 + 1];
   const double r64 = fixed_sum(partials, nparts, sh);
-  const double bb = fixed_sum(partials + nparts, nparts, sh);
+  const double bb = fixed_sum(partials + nparts, nparts, sh) + outer->gbnd2;
   const double r32 = fixed_sum(partials + 2 * nparts, nparts, sh);
   if (threadIdx.x == 0) state_ir(outer, inner, r64, bb, r32, tol, eta, outer_step, max_outer, max_inner);
 }
@@ -899,15 +943,16 @@ __device__ void small_cg_body(const Grid &gu, double *u, const RhsSrc &rs, const
   for (int m = threadIdx.x; m < n; m += DT) {
     int i, j, k;
     coords(m, i, j, k);
-    const double bv = rhs_at<true>(rs, gu.nx, gu.ny, gu.nz, i, j, k);
+    double rf;
+    const double bv = rhs_at<true>(rs, gu.nx, gu.ny, gu.nz, i, j, k, rf);
     const double rv = bv - stencil_direct(gu, u, i, j, k, st);
     r[gw.at(i, j, k)] = rv;
     p[gw.at(i, j, k)] = rv;
     rr += rv * rv;
-    bb += bv * bv;
+    bb += stop_norm_term(rs, bv, rf);
   }
   double rho = dsum(rr, sh);
-  const double bnorm2 = dsum(bb, sh);
+  const double bnorm2 = dsum(bb, sh) + cs->gbnd2;
   const double stop2 = (exact ? 1e-30 : tol * tol) * bnorm2;
   if (hist_on && threadIdx.x == 0) cs->hist[0] = bnorm2 > 0.0 ? sqrt(rho / bnorm2) : 0.0;
   int it = 0;
@@ -1010,14 +1055,15 @@ __device__ void small_cg_lds_body(const Grid &gu, double *u, const RhsSrc &rs, c
   for (int m = threadIdx.x; m < n; m += DT) {
     int i, j, k;
     coords(m, i, j, k);
-    const double bv = rhs_at<true>(rs, gu.nx, gu.ny, gu.nz, i, j, k);
+    double rf;
+    const double bv = rhs_at<true>(rs, gu.nx, gu.ny, gu.nz, i, j, k, rf);
     const double rv = bv - stencil_direct(gu, u, i, j, k, st);
     r[gw.at(i, j, k)] = rv;
     r2 += rv * rv;
-    b2 += bv * bv;
+    b2 += stop_norm_term(rs, bv, rf);
   }
   double rho = dsum(r2, sh);  // its barriers also make r visible to the whole workgroup
-  const double bnorm2 = dsum(b2, sh);
+  const double bnorm2 = dsum(b2, sh) + cs->gbnd2;
   const double rho_start = rho;
   // 2. own unknowns into registers, p = r into LDS (boundary nodes 0)
   for (int c = threadIdx.x; c < nodes; c += DT) P[c] = 0.0;
@@ -1138,9 +1184,10 @@ __device__ void dst_solve_body(const Grid &gu, double *u, const RhsSrc &rs, cons
   for (int m = threadIdx.x; m < n; m += DT) {
     int i, j, k;
     coords(m, i, j, k);
-    const double bv = rhs_at<true>(rs, gu.nx, gu.ny, gu.nz, i, j, k);
+    double rf;
+    const double bv = rhs_at<true>(rs, gu.nx, gu.ny, gu.nz, i, j, k, rf);
     A[gu.at(i, j, k)] = bv;
-    b2 += bv * bv;
+    b2 += stop_norm_term(rs, bv, rf);
   }
   for (int e = threadIdx.x; e < 3 * kDstMax; e += DT) {
     const int d = e / kDstMax, p = e % kDstMax;
@@ -1200,7 +1247,7 @@ __device__ void dst_solve_body(const Grid &gu, double *u, const RhsSrc &rs, cons
     r2 += rv * rv;
   }
   const double rho = dsum(r2, sh);
-  const double bnorm2 = dsum(b2, sh);
+  const double bnorm2 = dsum(b2, sh) + cs->gbnd2;
   if (threadIdx.x == 0) {
     cs->iter = 0;
     cs->rho = rho;
@@ -1506,6 +1553,12 @@ void launch_residual_partials(const Sweep &sw, const double *u, const RhsSrc &rs
   launch_boundary_terms(rs, sw.g, r, st);
   launch_resid(sw, u, rs, r, parts, st);
 }
+
+void launch_boundary_g2(const RhsSrc &rs, const Grid &g, CgState *cs, hipStream_t st) {
+  boundary_g2_kernel<<<1, FT, 0, st>>>(rs, g, cs);
+}
+
+void launch_clear_gbnd2(CgState *a, CgState *b, hipStream_t st) { clear_gbnd2_kernel<<<1, 1, 0, st>>>(a, b); }
 
 void launch_selfred_init(CgState *cs, int max_iters, int hist_on, int preset, hipStream_t st) {
   selfred_init_kernel<<<1, 1, 0, st>>>(cs, max_iters, hist_on, preset);

@@ -90,6 +90,22 @@ def test_bad_arguments(abi):
     assert L.excmg_plan(None, None, None) == abi.ERR_ARG
 
 
+@pytest.mark.parametrize("flags,tol_order,ok", [(0, 0.0, True), (0, 6.0, True), (0, 16.0, True), (0, -1.0, False),
+                                                (0, 16.5, False), (0, float("nan"), False), (32, 6.0, True),
+                                                (64, 0.0, False), (8 | 16, 0.0, False)])
+def test_problem_validation(abi, flags, tol_order, ok):
+    """Flags (EXCMG_STOP_F_G = 32 accepted, unknown bits and both compared guesses rejected) and the level-dependent
+    tolerance's order (0 <= p <= 16)."""
+    import paper_1507_05063_amd as ex
+
+    p = ex._problem((16, 16, 16), (1.0, 1.0, 1.0), 1e-10, flags=flags, tol_order=tol_order)
+    b = ctypes.c_size_t(0)
+    code = abi.lib().excmg_workspace_bytes(ctypes.byref(p), ctypes.byref(b))
+    assert (code == abi.OK) == ok, code
+    if not ok:
+        assert code == abi.ERR_ARG
+
+
 def test_workspace_bytes_scale(abi):
     import paper_1507_05063_amd as ex
 

@@ -5,7 +5,9 @@ for EXCMG in its comparison with V- and W-cycles (CG smoother).
 Tolerances are those of the oracle's pins of the same rows (tests/test_oracle.py): max-norm columns to 2% (u, grad)
 and 6% (ext, w); L2 columns of u, grad, ext to 2% with the L2 norm read as the RMS over all nodes; the L2 column of
 w_h - u_h within 30% (it follows no convention found); entries the uniform CG tolerance limits are listed but not
-pinned.  w_h is the finest grid's initial guess: EXP_finite of the solutions on the grids n/2 and n/4, which are the
+pinned.  Entries marked '~' are set by the algebraic error the solves stop with and are pinned with the stopping test's
+norm read as that of (R f inside, g on the boundary) (EXCMG_STOP_F_G); those marked '?' are matched by neither reading
+and are listed only.  w_h is the finest grid's initial guess: EXP_finite of the solutions on the grids n/2 and n/4, which are the
 cascade's own grids (the level data are the finest data sampled at strides 2 and 4), solved here as problems of their
 own.
 """
@@ -45,9 +47,9 @@ def table_rows():
         if not line.strip() or line.startswith("#"):
             continue
         e, mesh, tol, norm, qty, val = line.split()
-        mark = "*" if val.endswith("*") else ("~" if val.endswith("~") else "")
+        mark = val[-1] if val[-1] in "*~?" else ""
         rows.append((int(e), tuple(int(v) for v in mesh.split(",")), float(tol), norm, qty,
-                     float(val.rstrip("*~")), mark))
+                     float(val.rstrip("*~?")), mark))
     return rows
 
 
@@ -58,20 +60,20 @@ def coarsest(e):
 _CACHE = {}
 
 
-def run_case(ex, e, n, tol):
-    key = (e, n, tol)
+def run_case(ex, e, n, tol, stop_norm="b"):
+    key = (e, n, tol, stop_norm)
     if key in _CACHE:
         return _CACHE[key]
     p = synth.example(e)
     f, g, u = synth.sample(p, n)
-    s = ex.Solver(n, p.box, tol, n_coarse=coarsest(e))
+    s = ex.Solver(n, p.box, tol, n_coarse=coarsest(e), stop_norm=stop_norm)
     fd, gd = dev(f), dev(g)
     ug, ueg, st = s.solve(fd, gd, want_ext=True)
     grads = [host(t) for t in s.gradient(ug)]
     sub = {}
     for q in (2, 4):
         m = tuple(v // q for v in n)
-        sq = ex.Solver(m, p.box, tol, n_coarse=coarsest(e))
+        sq = ex.Solver(m, p.box, tol, n_coarse=coarsest(e), stop_norm=stop_norm)
         sub[q], _, _ = sq.solve(fd[::q, ::q, ::q].contiguous(), gd[::q, ::q, ::q].contiguous())
         del sq
     w = host(ex.op_initial_guess("quartic", sub[2], sub[4], gd, n))
@@ -98,11 +100,11 @@ def run_case(ex, e, n, tol):
 @pytest.mark.parametrize("row", table_rows(), ids=lambda r: f"ex{r[0]}-{'x'.join(map(str, r[1]))}-{r[3]}-{r[4]}")
 def test_paper_tables_on_gpu(ex, row):
     e, n, tol, norm, qty, val, limited = row
-    got = run_case(ex, e, n, tol)[(norm, qty)]
+    if limited == "?":
+        pytest.skip("entry set by the algebraic error and reproduced by neither reading of the stopping norm")
+    got = run_case(ex, e, n, tol, "fg" if limited == "~" else "b")[(norm, qty)]
     if limited == "*":
         pytest.skip("entry limited by the uniform CG tolerance (the paper's own remark in Section 5.1)")
-    if limited == "~":
-        pytest.skip("entry set by the algebraic error: depends on the reading of the stopping norm (golden header)")
     if norm == "l2" and qty == "w":
         assert 0.7 * val < got < 1.3 * val, (got, val)
         return

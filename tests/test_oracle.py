@@ -478,11 +478,11 @@ def _table_rows(max_cells=64 ** 3):
         if not line.strip() or line.startswith("#"):
             continue
         ex, mesh, tol, norm, qty, val = line.split()
-        limited = "*" if val.endswith("*") else ("~" if val.endswith("~") else "")
+        limited = val[-1] if val[-1] in "*~?" else ""
         n = tuple(int(v) for v in mesh.split(","))
         if n[0] * n[1] * n[2] > max_cells:
             continue
-        rows.append((int(ex), n, float(tol), norm, qty, float(val.rstrip("*~")), limited))
+        rows.append((int(ex), n, float(tol), norm, qty, float(val.rstrip("*~?")), limited))
     return rows
 
 
@@ -522,7 +522,7 @@ def test_paper_tables(orc, row):
     got = _run(orc, ex, n, tol)[(norm, qty)]
     if limited == "*":
         pytest.skip("entry limited by the uniform CG tolerance (paper's own remark)")
-    if limited == "~":
+    if limited in "~?" and limited:
         pytest.skip("entry set by the algebraic error: depends on the reading of the stopping norm (golden header)")
     if norm == "l2" and qty == "w":
         assert 0.7 * val < got < 1.3 * val
@@ -546,6 +546,70 @@ def test_stopping_norm_reading_at_128(orc):
     assert abs(rms(fg["ut"] - u) - 6.22e-15) <= 0.06 * 6.22e-15
     assert rms(b["ut"] - u) > 5 * 6.22e-15
     assert fg["iters"][-1] > 3 * b["iters"][-1]
+
+
+_FG_CACHE = {}
+
+
+@pytest.mark.parametrize("row", [r for r in _table_rows(128 ** 3) if r[6] == "~"],
+                         ids=lambda r: f"ex{r[0]}-{'x'.join(map(str, r[1]))}-{r[3]}-{r[4]}")
+def test_paper_tables_second_stopping_norm(orc, row):
+    """The entries the algebraic error sets (marked '~', meshes up to 128^3): reproduced, to the tolerances of
+    test_paper_tables, with the stopping test's norm read as that of (R f inside, g on the boundary)."""
+    ex, n, tol, norm, qty, val, _ = row
+    key = (ex, n, tol)
+    if key not in _FG_CACHE:
+        p = synth.example(ex)
+        f, g, u = synth.sample(p, n)
+        nc = (8, 4, 2) if ex == 4 else (4, 4, 4)
+        r = orc.excmg_guess("quartic", f, g, p.box, nc, tol, stop_norm="fg", want_ext=True)
+        grad = orc.gradient(r["u"], p.box)
+        gex = synth.exact_gradient(p, n)
+        rms = lambda e: float(np.sqrt(np.mean(e * e)))
+        _FG_CACHE.clear()
+        _FG_CACHE[key] = {
+            ("inf", "u"): np.max(np.abs(r["u"] - u)),
+            ("inf", "grad"): max(np.max(np.abs(a - b)) for a, b in zip(grad, gex)),
+            ("inf", "ext"): np.max(np.abs(r["ut"] - u)),
+            ("l2", "u"): rms(r["u"] - u),
+            ("l2", "grad"): float(np.sqrt(sum(rms(a - b) ** 2 for a, b in zip(grad, gex)))),
+            ("l2", "ext"): rms(r["ut"] - u),
+        }
+    got = _FG_CACHE[key][(norm, qty)]
+    rel = 0.02 if qty in ("u", "grad") else 0.06
+    assert abs(got - val) <= rel * val, (got, val)
+
+
+def test_level_tolerance_schedule(orc):
+    """The level-dependent tolerance (tol_order p: level l of the finest Lt relaxes to tol * 2^(p (Lt - l))), a
+    schedule the paper does not give, for its remark that a uniform tolerance costs the extrapolated solution its sixth
+    order on fine grids (Section 5.1).  On Example 1 with the (R f, g) stopping norm, eps 1e-14 on the finest grid:
+    p = 0 is the uniform cascade bit for bit; p = 6 keeps the finest grid's tolerance, so u~_h is unchanged to 1% and
+    sixth order from 64^3 to 128^3, while every relaxed coarser grid needs fewer CG iterations."""
+    p = synth.example(1)
+    rms = lambda d: float(np.sqrt(np.mean(d * d)))
+    ext = {}
+    for N in (64, 128):
+        f, g, u = synth.sample(p, (N, N, N))
+        a = orc.excmg_guess("quartic", f, g, p.box, (4, 4, 4), 1e-14, stop_norm="fg", want_ext=True)
+        b = orc.excmg_guess("quartic", f, g, p.box, (4, 4, 4), 1e-14, stop_norm="fg", want_ext=True, tol_order=6.0)
+        if N == 64:
+            z = orc.excmg_guess("quartic", f, g, p.box, (4, 4, 4), 1e-14, stop_norm="fg", want_ext=True,
+                                tol_order=0.0)
+            assert np.array_equal(z["u"], a["u"]) and np.array_equal(z["iters"], a["iters"])
+        ea, eb = rms(a["ut"] - u), rms(b["ut"] - u)
+        assert abs(eb - ea) <= 0.01 * ea, (ea, eb)
+        assert b["iters"][-1] == a["iters"][-1]
+        assert np.all(b["iters"][2:-1] < a["iters"][2:-1]), (a["iters"], b["iters"])
+        ext[N] = eb
+    assert 5.8 < np.log2(ext[64] / ext[128]) < 6.2
+
+
+def test_level_tolerance_schedule_arguments(orc):
+    f, g, _ = synth.sample(synth.example(1), (16, 16, 16))
+    for bad in (-1.0, 17.0, float("nan")):
+        with pytest.raises(Exception):
+            orc.excmg_guess("quartic", f, g, (1.0, 1.0, 1.0), (4, 4, 4), 1e-10, tol_order=bad)
 
 
 def test_paper_iteration_count_256(orc):
