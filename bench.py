@@ -58,10 +58,26 @@ def trace_summary(db, top=30):
         print(f"kernel trace: {len(rows)} dispatches, {tot / 1e6:.3f} ms of kernel time")
         print(f"{'kernel':44s} {'grid':>9s} {'wg':>5s} {'calls':>6s} {'total_ms':>9s} {'avg_us':>9s} "
               f"{'working':>7s} {'work_avg_us':>11s}")
-        for (nm, gx, wx), ds in sorted(groups.items(), key=lambda kv: -sum(kv[1]))[:top]:
+        def line(nm, gx, wx, ds):
             w = [d for d in ds if d >= 0.5 * max(ds)]
             print(f"{nm:44s} {gx:9d} {wx:5d} {len(ds):6d} {sum(ds) / 1e6:9.3f} {sum(ds) / len(ds) / 1e3:9.2f} "
                   f"{len(w):7d} {sum(w) / len(w) / 1e3:11.2f}")
+            return sum(w) / len(w)
+
+        for (nm, gx, wx), ds in sorted(groups.items(), key=lambda kv: -sum(kv[1]))[:top]:
+            line(nm, gx, wx, ds)
+        print()
+        print("The other kernels of a step (not the CG passes, the autotuner's or the runtime's; working average at "
+              "least 50 us):")
+        print(f"{'kernel':44s} {'grid':>9s} {'wg':>5s} {'calls':>6s} {'total_ms':>9s} {'avg_us':>9s} "
+              f"{'working':>7s} {'work_avg_us':>11s}")
+        skip = ("cg_pass_", "cg_selfred_", "tune_state", "__amd", "finalize_")
+        for (nm, gx, wx), ds in sorted(groups.items(), key=lambda kv: -sum(kv[1])):
+            if nm.startswith(skip):
+                continue
+            w = [d for d in ds if d >= 0.5 * max(ds)]
+            if sum(w) / len(w) >= 50e3:
+                line(nm, gx, wx, ds)
     pm = c.execute("select kernel_name, grid_size, counter_name, value from counters_collection").fetchall()
     if pm:
         groups = {}
