@@ -169,6 +169,42 @@ def bench_adjoint(ex, synth, torch, args):
             "adjoint_iters": st["iters"]}
 
 
+def bench_slab(ex, synth, torch, args):
+    """One GPU's share of the z-slab decomposition of the benchmark's grid over G GPUs: the finest-grid CG sweeps on an
+    N x N x N/G slab (h as in the cube), timed per launch with HIP events.  The halo exchange and the all-reduces of a
+    real multi-GPU run are not in these figures."""
+    N = args.n
+    res = {}
+    for G in (2, 4, 8):
+        n = (N, N, N // G)
+        box = (1.0, 1.0, 1.0 / G)
+        p = synth.smooth(0, box)
+        f_np, g_np, _ = synth.sample(p, n)
+        f, g = torch.from_numpy(f_np).cuda(), torch.from_numpy(g_np).cuda()
+        s = ex.Solver(n, box, args.tol, timing=True)
+        s.autotune()
+        u = s.empty()
+        s.solve(f, g, u=u)
+        tot = {"cg_a": 0.0, "cg_b": 0.0}
+        calls = {"cg_a": 0, "cg_b": 0}
+        for _ in range(3):
+            _, _, st = s.solve(f, g, u=u)
+            for k in tot:
+                tot[k] += st["kernel_ms_finest"][k]
+                calls[k] += st["kernel_calls_finest"][k]
+        unknowns = (n[0] - 1) * (n[1] - 1) * (n[2] - 1)
+        out = {"cells": list(n), "finest_iters": st["iters"][-1]}
+        for k, b in (("cg_a", 24), ("cg_b", 40)):
+            if calls[k]:
+                ms = tot[k] / calls[k]
+                out[k + "_ms"] = round(ms, 4)
+                out[k + "_GBs"] = round(b * unknowns / (ms * 1e-3) / 1e9, 1)
+        out["vector_MB"] = round(8 * (n[0] + 1) * (n[1] + 1) * (n[2] + 1) / 1e6, 1)
+        res[f"G{G}"] = out
+        del s, u, f, g
+    return res
+
+
 def bench_guess(ex, synth, torch, args, f, g, u_ref):
     """The paper's initial guess against the two it compares with (tri-quadratic after the same extrapolation; CMG's
     trilinear interpolation of u_2h), FP64 on the benchmark's workload: finest-grid CG iterations and solve time per
@@ -325,6 +361,8 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the 96-problem batched section")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the 256^3 adjoint section")
     ap.add_argument("--no-guess", action="store_true", help="skip the initial-guess ablation (three 512^3 solves)")
+    ap.add_argument("--no-slab", action="store_true",
+                    help="skip one GPU's z-slab share of the grid for 2, 4 and 8 GPUs (three solves)")
     ap.add_argument("--no-tolerance", action="store_true",
                     help="skip the accuracy of u~_h against the tolerance (eight solves at N/2 and N)")
     args = ap.parse_args()
@@ -476,6 +514,9 @@ def main():
     if not args.no_guess:
         out["guess_ablation"] = bench_guess(ex, synth, torch, args, f, g, u)
         print(f"# guess ablation: {out['guess_ablation']}", file=sys.stderr, flush=True)
+    if not args.no_slab:
+        out["slab"] = bench_slab(ex, synth, torch, args)
+        print(f"# slab: {out['slab']}", file=sys.stderr, flush=True)
     if not args.no_tolerance:
         out["tolerance"] = bench_tolerance(ex, synth, torch, args, f, g, u_exact)
         print(f"# tolerance: {out['tolerance']}", file=sys.stderr, flush=True)
