@@ -169,6 +169,33 @@ def bench_adjoint(ex, synth, torch, args):
             "adjoint_iters": st["iters"]}
 
 
+# Table 13: EXCMG on the paper's examples at their finest grids (example: cells, eps, total CPU seconds of the paper's
+# serial FP64 Fortran code on an Intel Core i7-4790K at 4.0 GHz, finest-grid CG iterations).  Context only.
+PAPER_TABLE13 = {1: ((256, 256, 256), 1e-14, 12.9, 8), 2: ((256, 256, 256), 1e-14, 12.6, 9),
+                 3: ((256, 256, 256), 1e-11, 11.8, 8), 4: ((512, 256, 128), 1e-9, 10.8, 8),
+                 5: ((256, 256, 256), 1e-12, 13.8, 9), 6: ((256, 256, 256), 1e-13, 13.3, 9)}
+
+
+def bench_paper(ex, synth, torch, args):
+    """The paper's six examples at the grids and tolerances of its timing table (Table 13), FP64 on this GPU: the EXCMG
+    solve with EXP_true (median of 3 after a warm-up) and the finest grid's CG iterations, beside the paper's CPU
+    time and iteration count (its hardware, context only)."""
+    res = {}
+    for e, (n, tol, paper_s, paper_it) in PAPER_TABLE13.items():
+        p = synth.example(e)
+        f_np, g_np, _ = synth.sample(p, n)
+        f, g = torch.from_numpy(f_np).cuda(), torch.from_numpy(g_np).cuda()
+        s = ex.Solver(n, p.box, tol, n_coarse=(8, 4, 2) if e == 4 else (4, 4, 4))
+        s.autotune()
+        u, ue = s.empty(), s.empty()
+        ms, (_, _, st) = _timed(torch, lambda: s.solve(f, g, u=u, want_ext=True), 3)
+        res[f"ex{e}"] = {"cells": list(n), "tol": tol, "solve_ms": round(ms, 2), "finest_iters": st["iters"][-1],
+                         "paper_cpu_s": paper_s, "paper_finest_iters": paper_it}
+        del s, u, ue, f, g
+    res["paper_hardware"] = "Intel Core i7-4790K 4.0 GHz, serial FP64 Fortran (the paper's Table 13)"
+    return res
+
+
 def bench_slab(ex, synth, torch, args):
     """One GPU's share of the z-slab decomposition of the benchmark's grid over G GPUs: the finest-grid CG sweeps on an
     N x N x N/G slab (h as in the cube), timed per launch with HIP events.  The halo exchange and the all-reduces of a
@@ -361,6 +388,8 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the 96-problem batched section")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the 256^3 adjoint section")
     ap.add_argument("--no-guess", action="store_true", help="skip the initial-guess ablation (three 512^3 solves)")
+    ap.add_argument("--no-paper", action="store_true",
+                    help="skip the paper's six examples at the grids of its timing table (six solves)")
     ap.add_argument("--no-slab", action="store_true",
                     help="skip one GPU's z-slab share of the grid for 2, 4 and 8 GPUs (three solves)")
     ap.add_argument("--no-tolerance", action="store_true",
@@ -514,6 +543,9 @@ def main():
     if not args.no_guess:
         out["guess_ablation"] = bench_guess(ex, synth, torch, args, f, g, u)
         print(f"# guess ablation: {out['guess_ablation']}", file=sys.stderr, flush=True)
+    if not args.no_paper:
+        out["paper_examples"] = bench_paper(ex, synth, torch, args)
+        print(f"# paper examples: {out['paper_examples']}", file=sys.stderr, flush=True)
     if not args.no_slab:
         out["slab"] = bench_slab(ex, synth, torch, args)
         print(f"# slab: {out['slab']}", file=sys.stderr, flush=True)
