@@ -224,3 +224,23 @@ def test_extrapolated_solution_keeps_sixth_order(ex):
     assert abs(e["fg6", 256][0] - e["fg", 256][0]) <= 0.02 * e["fg", 256][0]
     it_u, it_s = e["fg", 256][1], e["fg6", 256][1]
     assert all(a < b for a, b in zip(it_s[2:-1], it_u[2:-1])), (it_u, it_s)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_ir"])
+def test_schedule_graphs_match_direct_launches(ex, precision):
+    """The graphs of CG iteration batches (every grid below the finest) are captured with their grid's own tolerance:
+    replaying them gives what direct launches give, bit for bit, over repeated solves."""
+    p = synth.example(5)
+    n = (128, 128, 128)
+    f, g, _ = synth.sample(p, n)
+    fd, gd = dev(f), dev(g)
+    prec = ex.FP64 if precision == "fp64" else ex.FP32_IR
+    kw = dict(n_coarse=(4, 4, 4), precision=prec, stop_norm="fg", tol_order=6.0)
+    sg = ex.Solver(n, p.box, 1e-12, graphs=True, **kw)
+    sd = ex.Solver(n, p.box, 1e-12, graphs=False, **kw)
+    ud, _, std = sd.solve(fd, gd)
+    ud = ud.clone()
+    for _ in range(3):
+        ug, _, stg = sg.solve(fd, gd)
+        assert torch.equal(ug, ud)
+        assert stg["iters"] == std["iters"]
