@@ -242,23 +242,32 @@ def test_nonfinite_and_noconv(ex):
 
 @pytest.mark.timeout(1000)
 def test_config2_512_fp64_full_oracle(ex, orc):
-    """512^3 cells, 8 grids from 4^3, tol 1e-10, FP64: the whole oracle cascade at full size with the GPU's
-    iteration counts, compared on every node."""
+    """512^3 cells, 8 grids from 4^3, tol 1e-10, FP64, in the benchmark's launch configuration (autotuned z chunks,
+    prefetch depths and cache policies; kernel timing on): the benchmark's step (the solve with EXP_true, then the
+    gradient) against the whole oracle cascade and the oracle's gradient at full size, with the GPU's iteration
+    counts, compared on every node."""
     p = synth.smooth(0)
     n = (512, 512, 512)
     f, g, u = synth.sample(p, n)
-    s = ex.Solver(n, p.box, 1e-10)
+    s = ex.Solver(n, p.box, 1e-10, timing=True)
+    s.autotune(with_depth=True)
     fd, gd = dev(f), dev(g)
-    ug, _, st = s.solve(fd, gd)
+    ug_d, ueg, st = s.solve(fd, gd, want_ext=True)
+    grads = [host(t) for t in s.gradient(ug_d)]
     del fd, gd
-    ug = host(ug)
+    ug, ueg = host(ug_d), host(ueg)
+    del ug_d
     orc.set_threads(max(1, min(16, len(__import__("os").sched_getaffinity(0)))))
     orc.set_progress(True)
     try:
-        ref = orc.excmg(f, g, p.box, (4, 4, 4), 1e-10, fixed_iters=np.array(st["iters"], dtype=np.int32))
+        ref = orc.excmg(f, g, p.box, (4, 4, 4), 1e-10, fixed_iters=np.array(st["iters"], dtype=np.int32),
+                        want_ext=True)
     finally:
         orc.set_progress(False)
     assert rel2(ug, ref["u"]) <= 1e-12
+    assert rel2(ueg, ref["ut"]) <= 1e-12
+    for a, b in zip(grads, orc.gradient(ug, p.box)):  # the gradient of the same u_h
+        assert rel2(a, b) <= 1e-12
     assert ref["relres"][-1] <= 1e-10 * 1.5
     # At this size the uniform tolerance limits the accuracy (the paper's remark on uniform epsilon, Section 5): the
     # algebraic error left by a 1e-10 residual reduction (about 1.7e-9 here) is far above the O(h^4) discretisation
