@@ -27,6 +27,10 @@ METRIC = "stencil-CG Gunknown-iters/s (%HBM peak); EXCMG solve time 512³ FP64 v
 HBM_PEAK_GBS = 8000.0
 # algorithmic bytes per interior unknown of one launch (FP64; halve for FP32)
 BYTES_PER_UNKNOWN = {"cg_a": 24, "cg_b": 40, "cg_a32": 12, "cg_b32": 20}
+# algorithmic bytes of the other finest-grid steps: per interior unknown (residual: reads u, f; writes r) or per node
+# (EXP_finite: writes w, reads u_2h and u_4h; EXP_true: reads u_h and u_2h, writes u~ and the caller's copy of u_h;
+# gradient: per axis reads u and writes one component)
+BYTES_PER_NODE = {"exp_finite": 8 * (1 + 1 / 8 + 1 / 64), "exp_true": 8 * (2 + 1 + 1 / 8), "gradient": 48}
 
 
 def unknown_iters(st):
@@ -432,9 +436,15 @@ def main():
     ue = s.empty()
     grads = (s.empty(), s.empty(), s.empty())
 
+    grad_events = []
+
     def one():
         uu, uext, st = s.solve(f, g, u=u, want_ext=True)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s.stream)
         s.gradient(uu, out=grads)
+        e1.record(s.stream)
+        grad_events.append((e0, e1))
         return st, uext
 
     for _ in range(args.warmup):
@@ -471,6 +481,25 @@ def main():
                     st["kernel_ms_finest"]["finalize"] for st in stats) / args.steps
     guis_fin_sweeps = nI * fin_iters / (cg_ms_fin * 1e-3) / 1e9 if cg_ms_fin > 0 else None
 
+    # every finest-grid step against the HBM peak: HIP-event time per launch (per call for the residual, which is the
+    # boundary-term kernel, the sweep and its reduction), algorithmic bytes as above
+    nodes = (N + 1) ** 3
+    kernels = {}
+    for k, b in [("cg_a", BYTES_PER_UNKNOWN["cg_a"] * nI), ("cg_b", BYTES_PER_UNKNOWN["cg_b"] * nI),
+                 ("resid", 24 * nI), ("exp_finite", BYTES_PER_NODE["exp_finite"] * nodes),
+                 ("exp_true", BYTES_PER_NODE["exp_true"] * nodes)]:
+        c = sum(st["kernel_calls_finest"][k] for st in stats)
+        if c:
+            ms_k = sum(st["kernel_ms_finest"][k] for st in stats) / c
+            kernels[k] = {"ms": round(ms_k, 4), "calls_per_step": c / args.steps, "GB": round(b / 1e9, 3),
+                          "GBs": round(b / (ms_k * 1e-3) / 1e9, 1),
+                          "frac": round(b / (ms_k * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    ms_g = float(np.mean([a.elapsed_time(b) for a, b in grad_events[-args.steps:]]))
+    bg = BYTES_PER_NODE["gradient"] * nodes
+    kernels["gradient"] = {"ms": round(ms_g, 4), "calls_per_step": 1, "GB": round(bg / 1e9, 3),
+                           "GBs": round(bg / (ms_g * 1e-3) / 1e9, 1),
+                           "frac": round(bg / (ms_g * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+
     u_np = u.cpu().numpy()
     err_fp64 = float(np.max(np.abs(u_np - u_exact)))
 
@@ -497,6 +526,7 @@ def main():
                      "avg_launch_ms": round(avg_ms, 4), "bytes_per_launch": BYTES_PER_UNKNOWN[dom] * nI,
                      "probe_GBs": {k: round(v, 1) for k, v in probe.items()},
                      "frac_of_probe_mix_nt": round(achieved / probe["mix_nt"], 4)},
+        "finest_grid_kernels": kernels,
         "iters_per_grid": stats[-1]["iters"],
         "autotuned_z_chunks": [list(z[:2]) for z in zc64],
         "autotuned_depths": [list(d[:2]) for d in dp64],
