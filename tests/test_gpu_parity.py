@@ -139,6 +139,49 @@ def test_solve_parity(ex, orc, case):
         assert st["relres"][l] <= tol
 
 
+@pytest.mark.parametrize("n", [(2, 2, 2), (2, 4, 2), (4, 2, 6)])
+def test_solve_smallest_grids(ex, orc, n):
+    """Grids with one to a few interior nodes (a single grid, solved directly) against the oracle."""
+    p = synth.smooth(4, (1.0, 0.5, 1.5))
+    f, g, _ = synth.sample(p, n)
+    s = ex.Solver(n, p.box, 1e-12)
+    assert s.levels == 1
+    ug, _, st = s.solve(dev(f), dev(g))
+    ref = orc.excmg(f, g, p.box, s.n_coarse, 1e-12)
+    assert rel2(host(ug), ref["u"]) <= 1e-12
+    assert st["iters"] == [0]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_ir"])
+def test_zero_and_constant_data(ex, precision):
+    """f = 0 with g = 0 gives u = 0 with no CG iteration on any grid (||b|| = 0 meets the test at once); f = 0 with
+    g = c gives u = c on every node: the compact scheme and the tri-quartic guess reproduce constants, so every
+    relaxed grid starts at rounding level."""
+    n = (128, 128, 128)  # 2^20 interior unknowns and more: the finest grid refines in FP32 under FP32_IR
+    prec = ex.FP64 if precision == "fp64" else ex.FP32_IR
+    s = ex.Solver(n, (1.0, 1.0, 0.5), 1e-10, n_coarse=(8, 8, 8), precision=prec)
+    z = torch.zeros((n[2] + 1, n[1] + 1, n[0] + 1), dtype=torch.float64, device="cuda")
+    u, ue, st = s.solve(z, z, want_ext=True)
+    assert torch.count_nonzero(u) == 0 and torch.count_nonzero(ue) == 0
+    assert all(i == 0 for i in st["iters"])
+    c = 2.5
+    u, ue, st = s.solve(z, torch.full_like(z, c), want_ext=True)
+    assert float(torch.max(torch.abs(u - c))) <= 1e-12 * c
+    assert float(torch.max(torch.abs(ue - c))) <= 1e-12 * c
+    gx, gy, gz = s.gradient(u)
+    for t in (gx, gy, gz):
+        assert float(torch.max(torch.abs(t))) <= 1e-9
+
+
+def test_gradient_needs_four_cells(ex):
+    s = ex.Solver((2, 4, 4), (1.0, 1.0, 1.0), 1e-10)
+    u = s.empty()
+    u.zero_()
+    with pytest.raises(ex.ExcmgError) as e:
+        s.gradient(u)
+    assert e.value.code == -2  # EXCMG_ERR_SHAPE
+
+
 def s_levels_ok(n, nc):
     return any(a != b for a, b in zip(n, nc))
 
