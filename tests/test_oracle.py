@@ -250,6 +250,19 @@ def test_quartic_weights_match_printed_rows(orc):
         assert abs(sum(orc.lagrange4(a, t) for a in range(5)) - 1.0) < 1e-14
 
 
+def test_quartic_remainder_constants(orc):
+    """Section 4.4, eqs. (si1)-(si4): the remainder of quartic interpolation on the nodes 0, 1/2, 1, 3/2, 2 (units of
+    h0) at the quarter points 1/4, 3/4, 5/4, 7/4 is (7, -3, 3, -7) h0^5 e^(5) / 8192.  For e = s^5 the remainder has no
+    higher-order term (e^(5) = 120 everywhere), so the oracle's quartic interpolation must leave exactly those values,
+    and a shifted, scaled quintic scales them by the cell width to the fifth power."""
+    for h0, s0 in ((1.0, 0.0), (0.25, 3.0), (1.0 / 64, -0.7)):
+        for pos, k in ((0.25, 7), (0.75, -3), (1.25, 3), (1.75, -7)):
+            x = s0 + pos * h0
+            e = lambda y: (y - s0) ** 5 + 2.0 * (y - s0) ** 3 - y  # degree 5 with e^(5) = 120
+            interp = sum(orc.lagrange4(a, 2.0 * pos) * e(s0 + 0.5 * a * h0) for a in range(5))
+            assert abs((e(x) - interp) - k * 120.0 * h0 ** 5 / 8192.0) <= 1e-12 * max(1.0, abs(e(x)))
+
+
 def _triquartic(rng, box):
     c = {}
     for a in range(5):
