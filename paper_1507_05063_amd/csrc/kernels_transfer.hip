@@ -150,14 +150,37 @@ __device__ void exp_finite_block(const Grid &g2, const double *__restrict__ u2, 
   const int I0 = 4 * cx0, J0 = 4 * cj, K0 = 4 * ck;  // 2h-grid origin of the slab
   // Index decompositions use the full-slab extents (compile-time divisors); entries past a short slab are skipped.
   // 1. stage
-  for (int e = tid; e < 25 * EX2; e += ET) {
-    const int a = e % EX2, bc = e / EX2, b = bc % 5, c = bc / 5;
-    if (a < n2x) W[c][b][a] = u2[g2.at(I0 + a, J0 + b, K0 + c)];
-  }
-  __syncthreads();
-  for (int e = tid; e < 9 * EX4; e += ET) {
-    const int a = e % EX4, bc = e / EX4, b = bc % 3, c = bc / 3;
-    if (a < n4x) D[c][b][a] = W[2 * c][2 * b][2 * a] - u4[g4.at(I0 / 2 + a, J0 / 2 + b, K0 / 2 + c)];
+  // Every staging load of the thread is issued before any is waited for (a load per loop trip, stored to LDS in the
+  // same trip, made the trips wait one memory latency each): addresses are clamped into the slab's 2h and 4h nodes,
+  // and only the entries of the slab are stored.
+  {
+    constexpr int NW = (25 * EX2 + ET - 1) / ET, ND = (9 * EX4 + ET - 1) / ET;
+    double wv[NW], dv[ND];
+#pragma unroll
+    for (int m = 0; m < NW; ++m) {
+      const int e = min(tid + m * ET, 25 * EX2 - 1);
+      const int a = min(e % EX2, n2x - 1), bc = e / EX2, b = bc % 5, c = bc / 5;
+      wv[m] = u2[g2.at(I0 + a, J0 + b, K0 + c)];
+    }
+#pragma unroll
+    for (int m = 0; m < ND; ++m) {
+      const int e = min(tid + m * ET, 9 * EX4 - 1);
+      const int a = min(e % EX4, n4x - 1), bc = e / EX4, b = bc % 3, c = bc / 3;
+      dv[m] = u4[g4.at(I0 / 2 + a, J0 / 2 + b, K0 / 2 + c)];
+    }
+#pragma unroll
+    for (int m = 0; m < NW; ++m) {
+      const int e = tid + m * ET;
+      const int a = e % EX2, bc = e / EX2, b = bc % 5, c = bc / 5;
+      if (e < 25 * EX2 && a < n2x) W[c][b][a] = wv[m];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < ND; ++m) {
+      const int e = tid + m * ET;
+      const int a = e % EX4, bc = e / EX4, b = bc % 3, c = bc / 3;
+      if (e < 9 * EX4 && a < n4x) D[c][b][a] = W[2 * c][2 * b][2 * a] - dv[m];
+    }
   }
   __syncthreads();
   // 2. extrapolate at the 2h nodes
