@@ -138,8 +138,11 @@ __device__ void exp_finite_block(const Grid &g2, const double *__restrict__ u2, 
                                  const double *__restrict__ u4, const Grid &gg, const double *__restrict__ gdat, int s,
                                  const Grid &gw, double *__restrict__ w, int bx, int cj, int ck, bool nt) {
   __shared__ double W[5][5][EX2];
-  __shared__ double D[3][3][EX4];
   __shared__ double Wx[5][5][EXF];
+  // D lives in Wx's space: it is dead (after the extrapolation) before the x pass writes Wx.  That keeps the
+  // workgroup under 20 KB of LDS, so the LDS does not cap the occupancy below what the registers allow.
+  static_assert(9 * EX4 <= 25 * EXF, "D fits in Wx");
+  double(*D)[3][EX4] = reinterpret_cast<double(*)[3][EX4]>(&Wx[0][0][0]);
   __shared__ double Q[4][5];
   if (threadIdx.x < 20) Q[threadIdx.x / 5][threadIdx.x % 5] = kQw[threadIdx.x / 5][threadIdx.x % 5];
   const int ncx = gw.nx / 8, ncy = gw.ny / 8, ncz = gw.nz / 8;
@@ -257,8 +260,10 @@ __device__ void exp_finite_block(const Grid &g2, const double *__restrict__ u2, 
     for (int yf = tid; yf < oy; yf += ET) column(0, yf);
 }
 
+// 7 waves per SIMD: the compiler's own choice (6, at 78 VGPRs) left too few workgroups in flight to cover the
+// staging loads (0.455 -> 0.42 ms at 512^3; 8 waves spills registers and is slower)
 template <bool QUAD>
-__global__ __launch_bounds__(ET) void exp_finite_kernel(Grid g2, const double *__restrict__ u2, Grid g4,
+__global__ __launch_bounds__(ET) __attribute__((amdgpu_waves_per_eu(7, 7))) void exp_finite_kernel(Grid g2, const double *__restrict__ u2, Grid g4,
                                                         const double *__restrict__ u4, Grid gg,
                                                         const double *__restrict__ gdat, int s, Grid gw,
                                                         double *__restrict__ w) {
