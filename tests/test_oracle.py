@@ -719,3 +719,28 @@ def test_adjoint_against_central_differences(orc):
         fd = (Lp - Lm) / (2 * eps)
         an = np.sum(adj["dLdf"] * df) + np.sum(adj["dLdg"] * dg)
         assert abs(fd - an) <= 1e-8 * max(abs(fd), 1e-12)
+
+
+def test_oracle_under_sanitizers(tmp_path):
+    """Every oracle entry point on small grids, built with AddressSanitizer and UndefinedBehaviorSanitizer (and leak
+    detection): no invalid access, undefined operation or leak (tests/oracle_sanitize_main.c)."""
+    import shutil
+    import subprocess
+
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("gcc not found")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    exe = str(tmp_path / "oracle_san")
+    cmd = [gcc, "-O1", "-g", "-std=c11", "-D_POSIX_C_SOURCE=199309L", "-fopenmp", "-fsanitize=address,undefined",
+           "-fno-sanitize-recover=all", "-fno-omit-frame-pointer", os.path.join(root, "tests", "oracle_sanitize_main.c"),
+           os.path.join(root, "oracle", "oracle.c"), "-lm", "-o", exe]
+    built = subprocess.run(cmd, capture_output=True, text=True)
+    if built.returncode != 0:
+        pytest.skip("no sanitizer runtime: " + built.stderr[-300:])
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1", OMP_NUM_THREADS="2")
+    run = subprocess.run([exe], capture_output=True, text=True, timeout=600, env=env)
+    if run.returncode != 0 and "does not come first in initial library list" in run.stderr:
+        pytest.skip("the sanitizer runtime cannot come first in this process environment")
+    assert run.returncode == 0, run.stderr[-3000:]
+    assert "all checks passed" in run.stdout
