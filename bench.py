@@ -26,7 +26,8 @@ sys.path.insert(0, ROOT)
 METRIC = "stencil-CG Gunknown-iters/s (%HBM peak); EXCMG solve time 512³ FP64 vs mixed"
 HBM_PEAK_GBS = 8000.0
 # algorithmic bytes per interior unknown of one launch (FP64; halve for FP32)
-BYTES_PER_UNKNOWN = {"cg_a": 24, "cg_b": 40, "cg_a32": 12, "cg_b32": 20}
+# a grid's first CG iteration (p = r): pass A reads r only, pass B reads r once for both of its operands
+BYTES_PER_UNKNOWN = {"cg_a": 24, "cg_b": 40, "cg_a0": 8, "cg_b0": 32, "cg_a32": 12, "cg_b32": 20}
 # algorithmic bytes of the other finest-grid steps: per interior unknown (residual: reads u, f; writes r) or per node
 # (EXP_finite: writes w, reads u_2h and u_4h; EXP_true: reads u_h and u_2h, writes u~ and the caller's copy of u_h;
 # gradient: per axis reads u and writes one component)
@@ -43,7 +44,9 @@ def unknown_iters(st):
 def trace_summary(db, top=30):
     """Per-kernel summary of a rocprofv3 database (kernel trace and/or counters), grouped by kernel and grid size.
     A CG launch made after its grid converged returns at once; launches shorter than half the longest of their group
-    (early exits, or a coarser grid's launches of the same shape) are left out of the 'working' average."""
+    (early exits, or a coarser grid's launches of the same shape) are left out of the 'working' average, and for the
+    CG passes those shorter than 0.9 of it (also a grid's first iteration, whose passes move 8 and 32 B per unknown
+    instead of 24 and 40)."""
     import re
     import sqlite3
 
@@ -63,7 +66,7 @@ def trace_summary(db, top=30):
         print(f"{'kernel':44s} {'grid':>9s} {'wg':>5s} {'calls':>6s} {'total_ms':>9s} {'avg_us':>9s} "
               f"{'working':>7s} {'work_avg_us':>11s}")
         def line(nm, gx, wx, ds):
-            w = [d for d in ds if d >= 0.5 * max(ds)]
+            w = [d for d in ds if d >= (0.9 if nm.startswith("cg_pass") else 0.5) * max(ds)]
             print(f"{nm:44s} {gx:9d} {wx:5d} {len(ds):6d} {sum(ds) / 1e6:9.3f} {sum(ds) / len(ds) / 1e3:9.2f} "
                   f"{len(w):7d} {sum(w) / len(w) / 1e3:11.2f}")
             return sum(w) / len(w)
@@ -327,8 +330,9 @@ def kernel_source_hash():
 def counter_summary(fetch_db, write_db, min_bytes=512 << 20):
     """HBM bytes per dispatch from a FETCH_SIZE run and a WRITE_SIZE run (KiB per dispatch), each scaled so that the
     probe's copy kernel (PROBE_BYTES/2 read, PROBE_BYTES/2 written) reads its known size.  One JSON line per
-    (kernel, grid size) that moves at least min_bytes, for the working dispatches (at least half of the group's
-    largest value: this drops launches that return at once and a coarser grid's launches of the same shape)."""
+    (kernel, grid size) that moves at least min_bytes, for the working dispatches (at least 0.9 of the group's
+    largest value: this drops launches that return at once, a coarser grid's launches of the same shape, and a grid's
+    first CG iteration, whose passes move 8 and 32 B per unknown instead of 24 and 40)."""
     import re
     import sqlite3
 
@@ -340,7 +344,7 @@ def counter_summary(fetch_db, write_db, min_bytes=512 << 20):
                 continue
             nm = re.sub(r"\(.*", "", nm.replace("excmg::(anonymous namespace)::", "").replace("void ", ""))
             g.setdefault((nm, gx), []).append(v)
-        return {k: [x for x in v if x >= 0.5 * max(v)] for k, v in g.items() if max(v) > 0}
+        return {k: [x for x in v if x >= 0.9 * max(v)] for k, v in g.items() if max(v) > 0}
 
     fetch, write = load(fetch_db, "FETCH_SIZE"), load(write_db, "WRITE_SIZE")
     probe = [k for k in fetch if k[0] == "probe_copy_kernel"]
@@ -477,15 +481,16 @@ def main():
     traffic = measured_traffic(kname, grid_threads)
     # stencil-CG sweeps of the finest grid alone: unknown-iterations per second of pass A + pass B kernel time
     fin_iters = stats[-1]["iters"][-1]
-    cg_ms_fin = sum(st["kernel_ms_finest"]["cg_a"] + st["kernel_ms_finest"]["cg_b"] +
-                    st["kernel_ms_finest"]["finalize"] for st in stats) / args.steps
+    cg_ms_fin = sum(sum(st["kernel_ms_finest"][k] for k in ("cg_a0", "cg_b0", "cg_a", "cg_b", "finalize"))
+                    for st in stats) / args.steps
     guis_fin_sweeps = nI * fin_iters / (cg_ms_fin * 1e-3) / 1e9 if cg_ms_fin > 0 else None
 
     # every finest-grid step against the HBM peak: HIP-event time per launch (per call for the residual, which is the
     # boundary-term kernel, the sweep and its reduction), algorithmic bytes as above
     nodes = (N + 1) ** 3
     kernels = {}
-    for k, b in [("cg_a", BYTES_PER_UNKNOWN["cg_a"] * nI), ("cg_b", BYTES_PER_UNKNOWN["cg_b"] * nI),
+    for k, b in [("cg_a0", BYTES_PER_UNKNOWN["cg_a0"] * nI), ("cg_b0", BYTES_PER_UNKNOWN["cg_b0"] * nI),
+                 ("cg_a", BYTES_PER_UNKNOWN["cg_a"] * nI), ("cg_b", BYTES_PER_UNKNOWN["cg_b"] * nI),
                  ("resid", 24 * nI), ("exp_finite", BYTES_PER_NODE["exp_finite"] * nodes),
                  ("exp_true", BYTES_PER_NODE["exp_true"] * nodes)]:
         c = sum(st["kernel_calls_finest"][k] for st in stats)

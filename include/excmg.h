@@ -80,7 +80,9 @@ extern "C" {
 #define EXCMG_K_DSOLVE 9     /* single-workgroup kernels: the direct solves, and the CG of grids <= 8000 unknowns */
 #define EXCMG_K_GRADIENT 10
 #define EXCMG_K_OTHER 11
-#define EXCMG_K_CLASSES 12
+#define EXCMG_K_CG_A0 12     /* the FP64 passes of a grid's first CG iteration, where p = r: pass A reads r and */
+#define EXCMG_K_CG_B0 13     /* writes no p, pass B reads r once for both operands (EXCMG_K_CG_A/B: the others) */
+#define EXCMG_K_CLASSES 14
 
 typedef struct excmg_handle excmg_handle;
 

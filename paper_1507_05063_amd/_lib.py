@@ -21,7 +21,7 @@ STOP_NORM_FLAGS = {"b": 0, "fg": STOP_F_G}
 MAX_LEVELS, MAX_HISTORY = 16, 256
 
 K_CLASSES = ["cg_a", "cg_b", "cg_a32", "cg_b32", "resid", "finalize", "rhs", "exp_finite", "exp_true", "dsolve",
-             "gradient", "other"]
+             "gradient", "other", "cg_a0", "cg_b0"]
 
 
 class Problem(ctypes.Structure):

@@ -211,10 +211,10 @@ void launch_probe_mix_nt(const double *a, double *b, double *c, long long n, hip
 // (the residual's [r.r | b.b] before iteration 0, pass B's r.r afterwards) and writes partsA; pass B reads nbA from
 // partsA and writes partsB
 template <typename T>
-void launch_selfred_a(const Sweep &swA, const T *r, T *p0, T *p1, CgState *cs, const double *partsB, int nb_prev,
+void launch_selfred_a(const Sweep &swA, T *r, T *p0, T *p1, CgState *cs, const double *partsB, int nb_prev,
                       double tol, double *partsA, hipStream_t st);
 template <typename T>
-void launch_selfred_b(const Sweep &swB, T *u, T *r, const T *p0, const T *p1, CgState *cs, const double *partsA,
+void launch_selfred_b(const Sweep &swB, T *u, T *r, T *p0, T *p1, CgState *cs, const double *partsA,
                       int nbA, double *partsB, hipStream_t st);
 // largest sweep (workgroups) that finalizes its own reductions
 int selfred_max_blocks();
@@ -230,9 +230,9 @@ void launch_residual_partials(const Sweep &sw, const double *u, const RhsSrc &rs
 
 // one CG pass and its finalize kernel (a second, single-workgroup launch)
 template <typename T>
-void launch_cg_pass_a(const Sweep &sw, const T *r, T *p0, T *p1, CgState *cs, double *partials, hipStream_t st);
+void launch_cg_pass_a(const Sweep &sw, T *r, T *p0, T *p1, CgState *cs, double *partials, hipStream_t st);
 template <typename T>
-void launch_cg_pass_b(const Sweep &sw, T *u, T *r, const T *p0, const T *p1, CgState *cs, double *partials,
+void launch_cg_pass_b(const Sweep &sw, T *u, T *r, T *p0, T *p1, CgState *cs, double *partials,
                       hipStream_t st);
 
 // CG state for timing sweeps in isolation: iteration 0, alpha = beta = 0, never done

@@ -4,8 +4,10 @@
 //   pass A:  p = r + beta p_old (beta = 0 on the first iteration), partial sums of p.Mp       reads r, p_old; writes p
 //   pass B:  u += alpha p, r -= alpha Mp, partial sums of r.r                                 reads p, r, u;  writes r, u
 // Mp is evaluated in both passes from p staged in LDS, so no q vector is stored: 64 B per unknown and iteration in
-// FP64 (32 B in FP32) instead of the 80 B of the textbook q-storing form.  The direction vector is double-buffered
-// (p_k lives in buffer k mod 2) because pass A reads p_old with halos while it writes p.
+// FP64 (32 B in FP32) instead of the 80 B of the textbook q-storing form.  The direction vector is double-buffered,
+// because pass A reads p_old with halos while it writes p.  On the first iteration p = r is not written out: pass A
+// reads r only (8 B) and pass B takes both operands from r's buffer and writes the new r into another (32 B); the
+// buffers then rotate as cg_bufs describes.
 //
 // Stencil sweep ("z-march"): a workgroup owns a TX x TY column tile and a chunk of z planes.  For each plane it loads
 // the (TX+2) x (TY+2) tile with its halo into LDS (double-buffered, one barrier per plane) and every thread forms the
@@ -387,6 +389,29 @@ __device__ void state_ir(CgState *outer, CgState *inner, double r64, double bb, 
 
 // ---------------------------------------------------------------------------------------------------------- passes
 
+// Buffers of CG iteration k, given r's buffer R and two more, P0 and P1.  Iteration 0 has p = r (beta = 0): pass A
+// writes no p (it only forms p.Mp from r), and pass B takes p from R and writes the new residual into P0, which holds
+// r from then on.  Later directions alternate between P1 (odd k) and R (even k), so pass A of iteration k reads
+// p_{k-1} from the buffer it does not write.  The iterates are those of p_0 = r_0 written out; one vector write and
+// one vector read less on every grid.
+template <typename T>
+struct CgBufs {
+  T *r_in;   // r_k (read by both passes)
+  T *r_out;  // r_{k+1} (written by pass B)
+  T *p_old;  // p_{k-1} (pass A; R at k = 0, where it is not used)
+  T *p;      // p_k (written by pass A unless k = 0, read by pass B)
+};
+
+template <typename T>
+__device__ __forceinline__ CgBufs<T> cg_bufs(int k, T *R, T *P0, T *P1) {
+  CgBufs<T> b;
+  b.r_in = (k == 0) ? R : P0;
+  b.r_out = P0;
+  b.p_old = (k == 0 || (k & 1)) ? R : P1;
+  b.p = (k == 0) ? R : ((k & 1) ? P1 : R);
+  return b;
+}
+
 template <typename T, bool NTP = false>
 struct PolA {
   static constexpr bool kRhs = false;
@@ -394,7 +419,7 @@ struct PolA {
   const T *pold;
   T *pnew;
   T beta;
-  bool first;  // p = r; pold then points at r (a cache hit, and no branch around the load)
+  bool first;  // p = r; pold then points at r (a cache hit, and no branch around the load), and p is not stored
   struct Raw {
     T r, p;
   };
@@ -413,23 +438,24 @@ struct PolA {
   template <int S>
   __device__ __forceinline__ void consume(int, int, int, long long idx, T c, T out, double, double, double &acc0,
                                           double &) {
-    st1<NTP>(c, &pnew[idx]);
+    if (!first) st1<NTP>(c, &pnew[idx]);
     acc0 += (double)c * (double)out;
   }
 };
 
 template <typename T, int D, bool NTP>
-__global__ __launch_bounds__(NT) void cg_pass_a_kernel(Sweep sw, const T *__restrict__ r, T *p0, T *p1,
+__global__ __launch_bounds__(NT) void cg_pass_a_kernel(Sweep sw, T *r, T *p0, T *p1,
                                                        const CgState *cs, double *partials) {
   __shared__ T tile[2][kTileRows][TX + 2];
   __shared__ double sh[NT / 64];
   if (cs->done) return;
   const int it = cs->iter;
+  const CgBufs<T> bf = cg_bufs(it, r, p0, p1);
   PolA<T, NTP> pol;
-  pol.r = r;
-  pol.pnew = (it & 1) ? p1 : p0;
+  pol.r = bf.r_in;
+  pol.pnew = bf.p;
   pol.first = (it == 0);
-  pol.pold = pol.first ? r : ((it & 1) ? p0 : p1);
+  pol.pold = bf.p_old;
   pol.beta = (T)cs->beta;
   double a0 = 0.0, a1 = 0.0;
   zmarch<T, D>(sw, pol, a0, a1, tile, nullptr, blockIdx.x, gridDim.x, true);
@@ -442,7 +468,8 @@ struct PolB {
   static constexpr bool kRhs = false;
   const T *p;
   T *u;
-  T *r;
+  const T *rin;
+  T *rout;
   T alpha;
   T pr[kMaxDepth], pu[kMaxDepth];
   using Raw = T;
@@ -454,30 +481,32 @@ struct PolB {
   template <int S>
   __device__ __forceinline__ void center(int, int, int, long long idx) {
     static_assert(S < kMaxDepth, "centre slot");
-    pr[S] = ld1<NTP>(&r[idx]);
+    pr[S] = ld1<NTP>(&rin[idx]);
     pu[S] = ld1<NTP>(&u[idx]);
   }
   template <int S>
   __device__ __forceinline__ void consume(int, int, int, long long idx, T c, T out, double, double, double &acc0,
                                           double &) {
     const T rn = pr[S] - alpha * out;
-    st1<NTP>(rn, &r[idx]);
+    st1<NTP>(rn, &rout[idx]);
     st1<NTP>(pu[S] + alpha * c, &u[idx]);
     acc0 += (double)rn * (double)rn;
   }
 };
 
 template <typename T, int D, bool NTP>
-__global__ __launch_bounds__(NT) void cg_pass_b_kernel(Sweep sw, T *u, T *r, const T *p0, const T *p1,
+__global__ __launch_bounds__(NT) void cg_pass_b_kernel(Sweep sw, T *u, T *r, T *p0, T *p1,
                                                        const CgState *cs, double *partials) {
   __shared__ T tile[2][kTileRows][TX + 2];
   __shared__ double sh[NT / 64];
   if (cs->done) return;
   const int it = cs->iter;
+  const CgBufs<T> bf = cg_bufs(it, r, p0, p1);
   PolB<T, NTP> pol;
-  pol.p = (it & 1) ? p1 : p0;
+  pol.p = bf.p;
   pol.u = u;
-  pol.r = r;
+  pol.rin = bf.r_in;
+  pol.rout = bf.r_out;
   pol.alpha = (T)cs->alpha;
   for (int q = 0; q < kMaxDepth; ++q) pol.pr[q] = pol.pu[q] = 0;
   double a0 = 0.0, a1 = 0.0;
@@ -530,7 +559,7 @@ __device__ double block_fixed_sum(const double *a, int n, double *sh) {
 // Pass A of iteration k = iterA: the stopping test on rho_k (Algorithm 1, the while condition), then
 // p = r + beta p with beta = rho_k / rho_{k-1}, partial sums of p.Mp into partsA.
 template <typename T, int D, bool NTP>
-__global__ __launch_bounds__(NT) void cg_selfred_a_kernel(Sweep sw, const T *__restrict__ r, T *p0, T *p1,
+__global__ __launch_bounds__(NT) void cg_selfred_a_kernel(Sweep sw, T *r, T *p0, T *p1,
                                                           CgState *cs, const double *partsB, int nbB, double tol,
                                                           double *partsA) {
   __shared__ T tile[2][kTileRows][TX + 2];
@@ -571,11 +600,12 @@ __global__ __launch_bounds__(NT) void cg_selfred_a_kernel(Sweep sw, const T *__r
     if (!finite || conv || cap) cs->done = 1;
   }
   if (!finite || conv || cap) return;
+  const CgBufs<T> bf = cg_bufs(k, r, p0, p1);
   PolA<T, NTP> pol;
-  pol.r = r;
-  pol.pnew = (k & 1) ? p1 : p0;
+  pol.r = bf.r_in;
+  pol.pnew = bf.p;
   pol.first = (k == 0);
-  pol.pold = pol.first ? r : ((k & 1) ? p0 : p1);
+  pol.pold = bf.p_old;
   pol.beta = (k == 0) ? T(0) : (T)(rho / cs->rhoA[(k - 1) & 1]);
   double a0 = 0.0, a1 = 0.0;
   zmarch<T, D>(sw, pol, a0, a1, tile, nullptr, blockIdx.x, gridDim.x, true);
@@ -586,7 +616,7 @@ __global__ __launch_bounds__(NT) void cg_selfred_a_kernel(Sweep sw, const T *__r
 // Pass B of iteration k = iterB: alpha = rho_k / p.Mp (from partsA), u += alpha p, r -= alpha Mp, partial sums of
 // r.r into partsB.
 template <typename T, int D, bool NTP>
-__global__ __launch_bounds__(NT) void cg_selfred_b_kernel(Sweep sw, T *u, T *r, const T *p0, const T *p1,
+__global__ __launch_bounds__(NT) void cg_selfred_b_kernel(Sweep sw, T *u, T *r, T *p0, T *p1,
                                                           CgState *cs, const double *partsA, int nbA,
                                                           double *partsB) {
   __shared__ T tile[2][kTileRows][TX + 2];
@@ -605,10 +635,12 @@ __global__ __launch_bounds__(NT) void cg_selfred_b_kernel(Sweep sw, T *u, T *r, 
     cs->iterA = k + 1;
   }
   if (bad) return;
+  const CgBufs<T> bf = cg_bufs(k, r, p0, p1);
   PolB<T, NTP> pol;
-  pol.p = (k & 1) ? p1 : p0;
+  pol.p = bf.p;
   pol.u = u;
-  pol.r = r;
+  pol.rin = bf.r_in;
+  pol.rout = bf.r_out;
   pol.alpha = (T)(cs->rhoA[k & 1] / pq);
   for (int q = 0; q < kMaxDepth; ++q) pol.pr[q] = pol.pu[q] = 0;
   double a0 = 0.0, a1 = 0.0;
@@ -1409,18 +1441,18 @@ __global__ __launch_bounds__(NT) void b_pass_a_kernel(BatchList L) {
   if (cs->done) return;
   const int bid = blockIdx.x - L.pre[e], nb = L.pre[e + 1] - L.pre[e];
   const int it = cs->iter;
-  T *p0, *p1;
-  const T *r;
+  T *p0, *p1, *r;
   if constexpr (F) {
     r = E.r32; p0 = E.p32a; p1 = E.p32b;
   } else {
     r = E.r; p0 = E.p0; p1 = E.p1;
   }
+  const CgBufs<T> bf = cg_bufs(it, r, p0, p1);
   PolA<T, true> pol;  // the batch's working set is far larger than the caches: streaming policy
-  pol.r = r;
-  pol.pnew = (it & 1) ? p1 : p0;
+  pol.r = bf.r_in;
+  pol.pnew = bf.p;
   pol.first = (it == 0);
-  pol.pold = pol.first ? r : ((it & 1) ? p0 : p1);
+  pol.pold = bf.p_old;
   pol.beta = (T)cs->beta;
   const Sweep sw = F ? E.swA32 : E.swA;
   double a0 = 0.0, a1 = 0.0;
@@ -1441,15 +1473,18 @@ __global__ __launch_bounds__(NT) void b_pass_b_kernel(BatchList L) {
   const int bid = blockIdx.x - L.pre[e], nb = L.pre[e + 1] - L.pre[e];
   const int it = cs->iter;
   PolB<T, true> pol;
+  T *p0, *p1, *r;
   if constexpr (F) {
-    pol.p = (it & 1) ? E.p32b : E.p32a;
+    r = E.r32; p0 = E.p32a; p1 = E.p32b;
     pol.u = E.d32;
-    pol.r = E.r32;
   } else {
-    pol.p = (it & 1) ? E.p1 : E.p0;
+    r = E.r; p0 = E.p0; p1 = E.p1;
     pol.u = E.u;
-    pol.r = E.r;
   }
+  const CgBufs<T> bf = cg_bufs(it, r, p0, p1);
+  pol.p = bf.p;
+  pol.rin = bf.r_in;
+  pol.rout = bf.r_out;
   pol.alpha = (T)cs->alpha;
   for (int q = 0; q < kMaxDepth; ++q) pol.pr[q] = pol.pu[q] = 0;
   const Sweep sw = F ? E.swB32 : E.swB;
@@ -1565,7 +1600,7 @@ void launch_selfred_init(CgState *cs, int max_iters, int hist_on, int preset, hi
 }
 
 template <typename T>
-void launch_selfred_a(const Sweep &swA, const T *r, T *p0, T *p1, CgState *cs, const double *partsB, int nb_prev,
+void launch_selfred_a(const Sweep &swA, T *r, T *p0, T *p1, CgState *cs, const double *partsB, int nb_prev,
                       double tol, double *partsA, hipStream_t st) {
   with_depth_policy(swA, [&](auto d, auto n) {
     cg_selfred_a_kernel<T, decltype(d)::value, decltype(n)::value>
@@ -1574,7 +1609,7 @@ void launch_selfred_a(const Sweep &swA, const T *r, T *p0, T *p1, CgState *cs, c
 }
 
 template <typename T>
-void launch_selfred_b(const Sweep &swB, T *u, T *r, const T *p0, const T *p1, CgState *cs, const double *partsA,
+void launch_selfred_b(const Sweep &swB, T *u, T *r, T *p0, T *p1, CgState *cs, const double *partsA,
                       int nbA, double *partsB, hipStream_t st) {
   with_depth_policy(swB, [&](auto d, auto n) {
     cg_selfred_b_kernel<T, decltype(d)::value, decltype(n)::value>
@@ -1582,13 +1617,13 @@ void launch_selfred_b(const Sweep &swB, T *u, T *r, const T *p0, const T *p1, Cg
   });
 }
 
-template void launch_selfred_a<double>(const Sweep &, const double *, double *, double *, CgState *, const double *,
+template void launch_selfred_a<double>(const Sweep &, double *, double *, double *, CgState *, const double *,
                                        int, double, double *, hipStream_t);
-template void launch_selfred_a<float>(const Sweep &, const float *, float *, float *, CgState *, const double *, int,
+template void launch_selfred_a<float>(const Sweep &, float *, float *, float *, CgState *, const double *, int,
                                       double, double *, hipStream_t);
-template void launch_selfred_b<double>(const Sweep &, double *, double *, const double *, const double *, CgState *,
+template void launch_selfred_b<double>(const Sweep &, double *, double *, double *, double *, CgState *,
                                        const double *, int, double *, hipStream_t);
-template void launch_selfred_b<float>(const Sweep &, float *, float *, const float *, const float *, CgState *,
+template void launch_selfred_b<float>(const Sweep &, float *, float *, float *, float *, CgState *,
                                       const double *, int, double *, hipStream_t);
 
 int selfred_max_blocks() { return kSelfRedMaxBlocks; }
@@ -1615,7 +1650,7 @@ void launch_residual_cast(const Sweep &sw, const double *u, const RhsSrc &rs, do
 }
 
 template <typename T>
-void launch_cg_pass_a(const Sweep &sw, const T *r, T *p0, T *p1, CgState *cs, double *partials, hipStream_t st) {
+void launch_cg_pass_a(const Sweep &sw, T *r, T *p0, T *p1, CgState *cs, double *partials, hipStream_t st) {
   const int nb = sweep_blocks(sw);
   with_depth_policy(sw, [&](auto d, auto n) {
     cg_pass_a_kernel<T, decltype(d)::value, decltype(n)::value><<<nb, NT, 0, st>>>(sw, r, p0, p1, cs, partials);
@@ -1624,7 +1659,7 @@ void launch_cg_pass_a(const Sweep &sw, const T *r, T *p0, T *p1, CgState *cs, do
 }
 
 template <typename T>
-void launch_cg_pass_b(const Sweep &sw, T *u, T *r, const T *p0, const T *p1, CgState *cs, double *partials,
+void launch_cg_pass_b(const Sweep &sw, T *u, T *r, T *p0, T *p1, CgState *cs, double *partials,
                       hipStream_t st) {
   const int nb = sweep_blocks(sw);
   with_depth_policy(sw, [&](auto d, auto n) {
@@ -1633,13 +1668,13 @@ void launch_cg_pass_b(const Sweep &sw, T *u, T *r, const T *p0, const T *p1, CgS
   finalize_b_kernel<<<1, FT, 0, st>>>(cs, partials, nb);
 }
 
-template void launch_cg_pass_a<double>(const Sweep &, const double *, double *, double *, CgState *, double *,
+template void launch_cg_pass_a<double>(const Sweep &, double *, double *, double *, CgState *, double *,
                                        hipStream_t);
-template void launch_cg_pass_a<float>(const Sweep &, const float *, float *, float *, CgState *, double *,
+template void launch_cg_pass_a<float>(const Sweep &, float *, float *, float *, CgState *, double *,
                                       hipStream_t);
-template void launch_cg_pass_b<double>(const Sweep &, double *, double *, const double *, const double *, CgState *,
+template void launch_cg_pass_b<double>(const Sweep &, double *, double *, double *, double *, CgState *,
                                        double *, hipStream_t);
-template void launch_cg_pass_b<float>(const Sweep &, float *, float *, const float *, const float *, CgState *,
+template void launch_cg_pass_b<float>(const Sweep &, float *, float *, float *, float *, CgState *,
                                       double *, hipStream_t);
 
 void launch_tune_state(CgState *cs, hipStream_t st) { tune_state_kernel<<<1, 1, 0, st>>>(cs); }
