@@ -185,7 +185,7 @@ int excmg_solve_batched(excmg_handle *const *hs, int32_t count, const double *co
                         double *ms_per_problem);
 
 /* Autotuner (host call, device work on the handle's stream): times the two CG sweep kernels of every relaxed grid
- * (FP64, and FP32 where EXCMG_FP32_IR relaxes in FP32) for each z-chunk length in {2, 4, ..., 64} planes per
+ * (FP64, and FP32 where EXCMG_FP32_IR relaxes in FP32) for each z-chunk length in {2, 4, ..., 512} planes per
  * workgroup, each prefetch depth (2, 3, 4 or 6 planes of loads in flight per thread) and each cache policy
  * (ordinary or non-temporal loads and stores of the data a sweep touches once), on the handle's own work buffers (no caller array
  * is read or written), and keeps the fastest per grid and kernel for every later call on this handle.
@@ -193,6 +193,12 @@ int excmg_solve_batched(excmg_handle *const *hs, int32_t count, const double *co
  * where the grid is not relaxed that way): the chunk, and the depth plus 10 if the non-temporal policy won.
  * Optional: without it the handle uses a fixed default (16 planes, fewer on small grids; depth 2; ordinary). */
 int excmg_autotune(excmg_handle *h, int32_t *zc_out, int32_t *depth_out);
+
+/* Host call.  Turns the kernel timing of EXCMG_WANT_TIMING on (on != 0) or off for later calls on this handle, as
+ * if the flag had been given at setup (the timing events are created the first time it is turned on).  The solver's
+ * results do not depend on it; the timing only adds event records between the finest grid's launches.  Waits for the
+ * handle's stream first.  Errors: EXCMG_ERR_ARG for a null handle, EXCMG_ERR_HIP if the events cannot be created. */
+int excmg_set_timing(excmg_handle *h, int32_t on);
 
 void excmg_destroy(excmg_handle *h);
 const char *excmg_strerror(int code);

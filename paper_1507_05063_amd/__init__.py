@@ -167,6 +167,10 @@ class Solver:
             return z, [tuple(dp[4 * l: 4 * l + 4]) for l in range(self.levels)]
         return z
 
+    def set_timing(self, on: bool):
+        """Kernel timing (stats kernel_ms, kernel_calls) on or off for later calls."""
+        _lib.check(_lib.lib().excmg_set_timing(self._h, 1 if on else 0), "excmg_set_timing")
+
     def close(self):
         if self._h:
             _lib.lib().excmg_destroy(self._h)

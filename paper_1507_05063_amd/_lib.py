@@ -110,6 +110,7 @@ def lib():
                                      ctypes.POINTER(_P), _P, ctypes.c_size_t, ctypes.POINTER(Stats),
                                      ctypes.POINTER(ctypes.c_double)], _I),
             "excmg_destroy": ([_P], None),
+            "excmg_set_timing": ([_P, ctypes.c_int32], _I),
             "excmg_autotune": ([_P, _I32P, _I32P], _I),
             "excmg_bandwidth_probe": ([_P, ctypes.c_size_t, ctypes.c_int32, _P, ctypes.POINTER(ctypes.c_double)], _I),
             "excmg_strerror": ([_I], ctypes.c_char_p),

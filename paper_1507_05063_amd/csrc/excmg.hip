@@ -113,6 +113,9 @@ double level_tol(const excmg_problem &p, int l, int L) {
   return t < cap ? t : cap;
 }
 
+// Tolerance and iteration cap of grid l's CG: the direct solves (grids 0 and 1) iterate to rounding
+double grid_tol(const excmg_problem &p, int l, int L) { return l <= 1 ? kDsolveTol : level_tol(p, l, L); }
+
 int guess_kind(uint32_t flags) {
   if (flags & EXCMG_GUESS_QUADRATIC) return kGuessQuadratic;
   if (flags & EXCMG_GUESS_LINEAR) return kGuessLinear;
@@ -348,8 +351,14 @@ int next_batch(double rho, double rho0, int done, double stop2) {
 // halving their bytes saves nothing, while the extra outer steps of the refinement would cost launches.
 constexpr long long kIrMinUnknowns = 1LL << 20;
 
-// Grids with at most this many interior unknowns (16^3 cells and below) relax in one single-workgroup launch.
-constexpr long long kSmallCg = 8000;
+// Grids with at most kSmallCg interior unknowns (16^3 cells and below) relax in one single-workgroup launch, and so
+// are the direct solves that fit the sine transforms; every other grid runs the multi-workgroup CG sweeps (a direct
+// solve then iterates to the relative residual kDsolveTol).
+bool swept(const Layout &lo, int l) {
+  const Level &lv = lo.lev[l];
+  if (lv.g.interior() <= kSmallCg) return false;
+  return l >= 2 || !dst_fits(lv.g);
+}
 
 bool self_finalizing(const Level &lv, bool fp32) {
   const int m = selfred_max_blocks();
@@ -362,7 +371,7 @@ bool self_finalizing(const Level &lv, bool fp32) {
 // launched: iteration index for the kernel timing.
 void launch_iteration(excmg_handle *h, int l, int fp32, bool first, hipStream_t s, int launched, int outer) {
   Level &lv = h->lo.lev[l];
-  const double tol = level_tol(h->p, l, h->lo.L);
+  const double tol = grid_tol(h->p, l, h->lo.L);
   double *pa = h->partials, *pb = h->partials + h->lo.npart;
   if (fp32) {
     if (self_finalizing(lv, true)) {
@@ -448,13 +457,20 @@ int launch_iterations(excmg_handle *h, int l, int fp32, int nb, int launched, in
   return launched;
 }
 
-// FP64 CG on level l from the current u (Algorithm 1, the while loop; one iteration per pass).
+// CG iterations allowed on grid l (the direct solves: their own cap, from the grid's size)
+int grid_cap(const excmg_handle *h, int l) {
+  if (l <= 1) return dsolve_cap(h->lo.lev[l].g.interior());
+  return h->p.max_iters > 0 ? h->p.max_iters : 10000;
+}
+
+// FP64 CG on level l from the current u (Algorithm 1, the while loop; one iteration per pass; on grids 0 and 1 the
+// direct solve, to the relative residual kDsolveTol).
 
 int cg64(excmg_handle *h, int l, const RhsSrc &rs, bool finest, int *iters, double *relres, excmg_stats *st) {
   Level &lv = h->lo.lev[l];
   const hipStream_t s = h->stream;
   const int hist_on = (finest && st && (h->p.flags & EXCMG_WANT_HISTORY)) ? 1 : 0;
-  const int maxit = h->p.max_iters > 0 ? h->p.max_iters : 10000;
+  const int maxit = grid_cap(h, l);
   const bool selfred = self_finalizing(lv, false);
   double *partsB = h->partials + h->lo.npart;
   {
@@ -463,7 +479,7 @@ int cg64(excmg_handle *h, int l, const RhsSrc &rs, bool finest, int *iters, doub
       launch_residual_partials(lv.sw, lv.u, rs, h->r, partsB, s);
       launch_selfred_init(h->cs, maxit, hist_on, 0, s);
     } else {
-      launch_residual(lv.sw, lv.u, rs, h->r, h->cs, h->partials, level_tol(h->p, l, h->lo.L), maxit, hist_on, s);
+      launch_residual(lv.sw, lv.u, rs, h->r, h->cs, h->partials, grid_tol(h->p, l, h->lo.L), maxit, hist_on, s);
     }
   }
   int e = last_error();
@@ -554,10 +570,10 @@ int small_cg(excmg_handle *h, int l, const RhsSrc &rs, bool exact, bool finest, 
              excmg_stats *st) {
   Level &lv = h->lo.lev[l];
   const int hist_on = (!exact && finest && st && (h->p.flags & EXCMG_WANT_HISTORY)) ? 1 : 0;
-  const int maxit = h->p.max_iters > 0 ? h->p.max_iters : 10000;
+  const int maxit = grid_cap(h, l);
   {
     Tick t(h, EXCMG_K_DSOLVE, l);
-    launch_small_cg(lv.g, lv.u, rs, lv.g, h->r, h->p0, h->p1, lv.st, h->cs, level_tol(h->p, l, h->lo.L), maxit,
+    launch_small_cg(lv.g, lv.u, rs, lv.g, h->r, h->p0, h->p1, lv.st, h->cs, grid_tol(h->p, l, h->lo.L), maxit,
                     exact ? 1 : 0, hist_on, h->stream);
   }
   int e = last_error();
@@ -575,6 +591,19 @@ int small_cg(excmg_handle *h, int l, const RhsSrc &rs, bool exact, bool finest, 
   }
   if (!isfinite(hs.bnorm2)) return EXCMG_ERR_NONFINITE;
   return hs.status;
+}
+
+// Kernel timing on or off; the event pool is created the first time it is turned on.
+int set_timing(excmg_handle *h, bool on) {
+  if (on && h->pool.empty()) {
+    h->pool.assign(8192, nullptr);
+    for (auto &ev : h->pool)
+      if (hipEventCreateWithFlags(&ev, kTimingEvent) != hipSuccess) return EXCMG_ERR_HIP;
+  }
+  h->timing = on;
+  if (on) h->p.flags |= EXCMG_WANT_TIMING;
+  else h->p.flags &= ~EXCMG_WANT_TIMING;
+  return EXCMG_OK;
 }
 
 void reset_timing(excmg_handle *h) {
@@ -661,15 +690,24 @@ int cascade(excmg_handle *h, int mode, const double *f, const double *g, excmg_s
       launch_boundary_g2(rs, lv.g, h->cs, s);
     }
     int e = EXCMG_OK;
-    int it = 0, outer = 0;
+    int it = 0, outer = 0, dit = 0;
     double rr = 0.0;
     if (l <= 1) {
       {
         Tick t(h, EXCMG_K_OTHER, l);
         launch_set_boundary(lo.gdense, mode == 0 ? g : nullptr, lv.stride, lv.g, lv.u, 1, s);
       }
-      e = small_cg(h, l, rs, true, l == L - 1, &it, &rr, st);
-      if (e) return e;
+      // DSOLVE: the sine-transform solve or single-workgroup CG, or on larger grids the CG sweeps from u = 0
+      if (swept(lo, l)) {
+        e = cg64(h, l, rs, l == L - 1, &dit, &rr, st);
+        if (st) st->dsolve_iters[l] = dit;
+      } else {
+        e = small_cg(h, l, rs, true, l == L - 1, &it, &rr, st);
+      }
+      if (e == EXCMG_ERR_NOCONV)
+        final_status = EXCMG_ERR_NOCONV;
+      else if (e)
+        return e;
     } else {
       {
         Tick t(h, EXCMG_K_EXP_FINITE, l);
@@ -678,7 +716,7 @@ int cascade(excmg_handle *h, int mode, const double *f, const double *g, excmg_s
       }
       e = last_error();
       if (e) return e;
-      if (lv.g.interior() <= kSmallCg)
+      if (!swept(lo, l))
         e = small_cg(h, l, rs, false, l == L - 1, &it, &rr, st);
       else if (h->p.precision == EXCMG_FP64 || lv.g.interior() < kIrMinUnknowns)
         e = cg64(h, l, rs, l == L - 1, &it, &rr, st);
@@ -689,7 +727,7 @@ int cascade(excmg_handle *h, int mode, const double *f, const double *g, excmg_s
       else if (e)
         return e;
     }
-    if (li) li->iters[l] = it;
+    if (li) li->iters[l] = l <= 1 ? dit : it;
     if (st) {
       st->iters[l] = it;
       st->ir_outer[l] = outer;
@@ -745,8 +783,8 @@ size_t batch_ws_bytes(int count) {
 int batch_kind(const excmg_handle *h, int l) {
   if (l >= h->lo.L) return kBNone;
   const Level &lv = h->lo.lev[l];
-  if (l <= 1 || lv.g.interior() <= kSmallCg) return kBSmall;
-  if (h->p.precision == EXCMG_FP64 || lv.g.interior() < kIrMinUnknowns) return kBCg64;
+  if (!swept(h->lo, l)) return kBSmall;
+  if (l <= 1 || h->p.precision == EXCMG_FP64 || lv.g.interior() < kIrMinUnknowns) return kBCg64;
   return kBIr;
 }
 
@@ -762,9 +800,9 @@ void batch_entry(excmg_handle *h, int problem, int l, const double *f, const dou
   E->finest = (l == lo.L - 1);
   E->exact = (l <= 1);
   E->level = l;
-  E->cap = h->p.max_iters > 0 ? h->p.max_iters : 10000;
+  E->cap = grid_cap(h, l);
   E->max_outer = 30;
-  E->tol = level_tol(h->p, l, h->lo.L);
+  E->tol = grid_tol(h->p, l, h->lo.L);
   E->eta = h->p.inner_tol > 0.0 ? h->p.inner_tol : 1e-5;
   E->swA = lv.swA;
   E->swB = lv.swB;
@@ -1131,15 +1169,10 @@ int excmg_setup(const excmg_problem *p, void *workspace, size_t bytes, void *hip
     delete h;
     return EXCMG_ERR_HIP;
   }
-  h->timing = (p->flags & EXCMG_WANT_TIMING) != 0;
   h->pool_used = 0;
-  if (h->timing) {
-    h->pool.resize(8192);
-    for (auto &ev : h->pool)
-      if (hipEventCreateWithFlags(&ev, kTimingEvent) != hipSuccess) {
-        delete h;
-        return EXCMG_ERR_HIP;
-      }
+  if (set_timing(h, (p->flags & EXCMG_WANT_TIMING) != 0) != EXCMG_OK) {
+    delete h;
+    return EXCMG_ERR_HIP;
   }
   launch_clear_gbnd2(h->cs, h->cs2, h->stream);
   if (hipGetLastError() != hipSuccess || hipStreamSynchronize(h->stream) != hipSuccess) {
@@ -1225,17 +1258,17 @@ int excmg_autotune(excmg_handle *h, int32_t *zc_out, int32_t *depth_out) {
   h->drop_graphs();  // captured with the old sweep shapes
   const hipStream_t s = h->stream;
   Layout &lo = h->lo;
-  static const int cand[] = {2, 4, 8, 16, 32, 64};
+  static const int cand[] = {2, 4, 8, 16, 32, 64, 128, 256, 512};
   static const int depths[] = {2, 3, 4, 6};
   constexpr int kVar = 2 * (int)(sizeof(depths) / sizeof(depths[0]));  // depth x cache policy
   hipEvent_t ea, eb;
   HIPCHECK(hipEventCreateWithFlags(&ea, kTimingEvent));
   HIPCHECK(hipEventCreateWithFlags(&eb, kTimingEvent));
   int rc = EXCMG_OK;
-  for (int l = 2; l < lo.L && rc == EXCMG_OK; ++l) {
+  for (int l = 0; l < lo.L && rc == EXCMG_OK; ++l) {
     Level &lv = lo.lev[l];
-    if (lv.g.interior() <= kSmallCg) continue;  // relaxed by the single-workgroup kernel
-    const bool ir = (h->p.precision == EXCMG_FP32_IR) && lv.g.interior() >= kIrMinUnknowns;
+    if (!swept(lo, l)) continue;  // solved by the single-workgroup kernel
+    const bool ir = l >= 2 && (h->p.precision == EXCMG_FP32_IR) && lv.g.interior() >= kIrMinUnknowns;
     for (int prec = 0; prec < (ir ? 2 : 1) && rc == EXCMG_OK; ++prec) {
       const Grid &g = prec ? lv.g32 : lv.g;
       for (int pass = 0; pass < 2 && rc == EXCMG_OK; ++pass) {
@@ -1283,8 +1316,8 @@ int excmg_autotune(excmg_handle *h, int32_t *zc_out, int32_t *depth_out) {
   if (zc_out) {
     for (int l = 0; l < lo.L; ++l) {
       const Level &lv = lo.lev[l];
-      const bool relaxed = l >= 2 && lv.g.interior() > kSmallCg;
-      const bool ir = relaxed && (h->p.precision == EXCMG_FP32_IR) && lv.g.interior() >= kIrMinUnknowns;
+      const bool relaxed = swept(lo, l);
+      const bool ir = relaxed && l >= 2 && (h->p.precision == EXCMG_FP32_IR) && lv.g.interior() >= kIrMinUnknowns;
       zc_out[4 * l + 0] = relaxed ? lv.swA.zc : 0;
       zc_out[4 * l + 1] = relaxed ? lv.swB.zc : 0;
       zc_out[4 * l + 2] = ir ? lv.swA32.zc : 0;
@@ -1294,8 +1327,8 @@ int excmg_autotune(excmg_handle *h, int32_t *zc_out, int32_t *depth_out) {
   if (depth_out) {
     for (int l = 0; l < lo.L; ++l) {
       const Level &lv = lo.lev[l];
-      const bool relaxed = l >= 2 && lv.g.interior() > kSmallCg;
-      const bool ir = relaxed && (h->p.precision == EXCMG_FP32_IR) && lv.g.interior() >= kIrMinUnknowns;
+      const bool relaxed = swept(lo, l);
+      const bool ir = relaxed && l >= 2 && (h->p.precision == EXCMG_FP32_IR) && lv.g.interior() >= kIrMinUnknowns;
       depth_out[4 * l + 0] = relaxed ? lv.swA.depth + 10 * lv.swA.nt : 0;
       depth_out[4 * l + 1] = relaxed ? lv.swB.depth + 10 * lv.swB.nt : 0;
       depth_out[4 * l + 2] = ir ? lv.swA32.depth + 10 * lv.swA32.nt : 0;
@@ -1303,6 +1336,13 @@ int excmg_autotune(excmg_handle *h, int32_t *zc_out, int32_t *depth_out) {
     }
   }
   return EXCMG_OK;
+}
+
+int excmg_set_timing(excmg_handle *h, int32_t on) {
+  if (!h) return EXCMG_ERR_ARG;
+  DeviceGuard dg(h->device);
+  HIPCHECK(hipStreamSynchronize(h->stream));  // no timed launch of an earlier call is still pending
+  return set_timing(h, on != 0);
 }
 
 void excmg_destroy(excmg_handle *h) {

@@ -29,6 +29,24 @@ struct Grid {
   __host__ __device__ long long nodes() const { return (long long)(nx + 1) * (ny + 1) * (nz + 1); }
 };
 
+// DSOLVE (the exact solve of the two coarsest grids, Algorithm 1) by sine transforms in one workgroup: grids of at
+// most kDstMax cells per axis.  Larger direct-solve grids are solved by CG to a relative residual of kDsolveTol (one
+// workgroup up to kSmallCg unknowns, else the multi-workgroup sweeps), which reports EXCMG_ERR_NOCONV if its
+// iteration cap is reached first.
+constexpr int kDstMax = 64;
+constexpr double kDsolveTol = 1e-15;
+constexpr long long kSmallCg = 8000;
+
+__host__ __device__ inline bool dst_fits(const Grid &g) {
+  return g.nx <= kDstMax && g.ny <= kDstMax && g.nz <= kDstMax;
+}
+
+// Iteration cap of a direct solve by CG on a grid of n interior unknowns.
+inline int dsolve_cap(long long n) {
+  const long long c = 4 * n + 200;
+  return c > 20000 ? 20000 : (int)c;
+}
+
 inline Grid dense_grid(int nx, int ny, int nz) {
   Grid g;
   g.nx = nx; g.ny = ny; g.nz = nz;

@@ -962,17 +962,17 @@ __device__ double dsum(double v, double *sh) {
 __device__ void small_cg_body(const Grid &gu, double *u, const RhsSrc &rs, const Grid &gw, double *r, double *p,
                               double *q, const Stencil &st, CgState *cs, double tol, int cap, int exact, int hist_on) {
   __shared__ double sh[DT / 64];
-  const int nx1 = gu.nx - 1, ny1 = gu.ny - 1, nz1 = gu.nz - 1;
-  const int n = nx1 * ny1 * nz1;
-  auto coords = [&](int m, int &i, int &j, int &k) {
-    i = 1 + m % nx1;
-    const int t = m / nx1;
-    j = 1 + t % ny1;
-    k = 1 + t / ny1;
+  const long long nx1 = gu.nx - 1, ny1 = gu.ny - 1, nz1 = gu.nz - 1;
+  const long long n = nx1 * ny1 * nz1;
+  auto coords = [&](long long m, int &i, int &j, int &k) {
+    i = (int)(1 + m % nx1);
+    const long long t = m / nx1;
+    j = (int)(1 + t % ny1);
+    k = (int)(1 + t / ny1);
   };
   // r = b - M u (u's interior), p = r
   double rr = 0.0, bb = 0.0;
-  for (int m = threadIdx.x; m < n; m += DT) {
+  for (long long m = threadIdx.x; m < n; m += DT) {
     int i, j, k;
     coords(m, i, j, k);
     double rf;
@@ -991,13 +991,13 @@ __device__ void small_cg_body(const Grid &gu, double *u, const RhsSrc &rs, const
   int status = 0;
   if (!isfinite(rho) || !isfinite(bnorm2)) status = EXCMG_ERR_BREAKDOWN;
   while (status == 0 && rho > stop2) {
-    if (it >= cap) {
-      if (!exact) status = EXCMG_ERR_NOCONV;
+    if (it >= cap) {  // also a direct solve that has not reached rounding level: reported, never silent
+      status = EXCMG_ERR_NOCONV;
       break;
     }
     __syncthreads();  // p complete
     double pq = 0.0;
-    for (int m = threadIdx.x; m < n; m += DT) {
+    for (long long m = threadIdx.x; m < n; m += DT) {
       int i, j, k;
       coords(m, i, j, k);
       const double qv = stencil_direct(gw, p, i, j, k, st);
@@ -1011,7 +1011,7 @@ __device__ void small_cg_body(const Grid &gu, double *u, const RhsSrc &rs, const
     }
     const double alpha = rho / pq;
     double rn = 0.0;
-    for (int m = threadIdx.x; m < n; m += DT) {
+    for (long long m = threadIdx.x; m < n; m += DT) {
       int i, j, k;
       coords(m, i, j, k);
       const long long w = gw.at(i, j, k);
@@ -1030,7 +1030,7 @@ __device__ void small_cg_body(const Grid &gu, double *u, const RhsSrc &rs, const
       break;
     }
     __syncthreads();  // all reads of p (in q) are done before p is overwritten
-    for (int m = threadIdx.x; m < n; m += DT) {
+    for (long long m = threadIdx.x; m < n; m += DT) {
       int i, j, k;
       coords(m, i, j, k);
       const long long w = gw.at(i, j, k);
@@ -1122,8 +1122,8 @@ __device__ void small_cg_lds_body(const Grid &gu, double *u, const RhsSrc &rs, c
   int it = 0, status = 0;
   if (!isfinite(rho) || !isfinite(bnorm2)) status = EXCMG_ERR_BREAKDOWN;
   while (status == 0 && rho > stop2) {
-    if (it >= cap) {
-      if (!exact) status = EXCMG_ERR_NOCONV;
+    if (it >= cap) {  // also a direct solve that has not reached rounding level: reported, never silent
+      status = EXCMG_ERR_NOCONV;
       break;
     }
     __syncthreads();  // p complete in LDS
@@ -1191,11 +1191,6 @@ __device__ void small_cg_lds_body(const Grid &gu, double *u, const RhsSrc &rs, c
 // (to rounding), in one workgroup, for grids of at most kDstMax cells per axis; the transforms are dense
 // (N-1) x (N-1) products along each axis through the work arrays A and B (the grid's layout), with the sine table of
 // the current axis in LDS.
-constexpr int kDstMax = 64;
-
-__host__ __device__ inline bool dst_fits(const Grid &g) {
-  return g.nx <= kDstMax && g.ny <= kDstMax && g.nz <= kDstMax;
-}
 
 __device__ void dst_solve_body(const Grid &gu, double *u, const RhsSrc &rs, const Stencil &st, CgState *cs,
                                double *A, double *B) {
@@ -1348,12 +1343,7 @@ __global__ void b_init_kernel(BatchStatus *stat, int count, long long *t0) {
 __global__ __launch_bounds__(DT) void b_small_cg_kernel(BatchList L, BatchStatus *stat, int lds_nodes) {
   extern __shared__ double lds_p[];
   const BatchEntry &E = *L.ent[blockIdx.x];
-  int cap = E.cap;
-  if (E.exact) {
-    const long long n = E.g.interior();
-    cap = (int)(4 * n + 200);
-    if (cap > 20000) cap = 20000;
-  }
+  const int cap = E.cap;  // grids 0 and 1: the direct solve's cap
   if (E.exact && dst_fits(E.g))
     dst_solve_body(E.g, E.u, E.rs, E.st, E.cs, E.r, E.p0);
   else if (small_fits_lds(E.g) && small_lds_nodes(E.g) <= lds_nodes)
@@ -1687,12 +1677,7 @@ void launch_add_correction(const Grid &gu, double *u, const Grid &g32, const flo
 void launch_small_cg(const Grid &gu, double *u, const RhsSrc &rs, const Grid &gw, double *r, double *p, double *q,
                      const Stencil &s, CgState *cs, double tol, int max_iters, int exact, int hist_on,
                      hipStream_t st) {
-  int cap = max_iters;
-  if (exact) {
-    const long long n = gu.interior();
-    cap = (int)(4 * n + 200);
-    if (cap > 20000) cap = 20000;
-  }
+  const int cap = exact ? dsolve_cap(gu.interior()) : max_iters;
   const size_t lds = (!(exact && dst_fits(gu)) && small_fits_lds(gu)) ? (size_t)small_lds_nodes(gu) * sizeof(double)
                                                                         : 0;
   small_cg_kernel<<<1, DT, lds, st>>>(gu, u, rs, gw, r, p, q, s, cs, tol, cap, exact, hist_on);

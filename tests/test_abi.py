@@ -88,6 +88,7 @@ def test_bad_arguments(abi):
         assert e.value.code == abi.ERR_ARG
     L = abi.lib()
     assert L.excmg_plan(None, None, None) == abi.ERR_ARG
+    assert L.excmg_set_timing(None, 1) == abi.ERR_ARG
 
 
 @pytest.mark.parametrize("flags,tol_order,ok", [(0, 0.0, True), (0, 6.0, True), (0, 16.0, True), (0, -1.0, False),

@@ -152,6 +152,71 @@ def test_solve_smallest_grids(ex, orc, n):
     assert st["iters"] == [0]
 
 
+# DSOLVE (Algorithm 1, the two coarsest grids) on grids the one-workgroup sine-transform solve does not take (over 64
+# cells on an axis): by CG to a relative residual of 1e-15, in one workgroup up to 8000 unknowns and on the
+# multi-workgroup sweeps above that.  The oracle solves those grids by banded Cholesky (x is the short axis where the
+# grid is large, so the band stays narrow).
+@pytest.mark.parametrize("n,nc,box,swept", [
+    ((264, 8, 8), (66, 2, 2), (8.25, 0.25, 0.25), False),   # grids 0 and 1 over 64 cells in x: one workgroup
+    ((8, 8, 200), (8, 8, 200), (0.04, 0.04, 1.0), True),      # one grid of 9751 unknowns: the sweeps
+    ((32, 32, 800), (8, 8, 200), (0.04, 0.04, 1.0), True),    # three grids, both direct solves on the sweeps
+])
+def test_dsolve_above_sine_transform_size(ex, orc, n, nc, box, swept):
+    p = synth.smooth(6, box)
+    f, g, u = synth.sample(p, n)
+    tol = 1e-11
+    s = ex.Solver(n, box, tol, n_coarse=nc)
+    ug, _, st = s.solve(dev(f), dev(g))
+    L = st["levels"]
+    for l in range(min(L, 2)):
+        assert st["iters"][l] == 0 and st["dsolve_iters"][l] > 0  # iterated, not the sine transforms
+        assert st["relres"][l] <= 1e-13
+    if swept:
+        zc = s.autotune()  # the swept direct solves are tuned like any relaxed grid
+        assert zc[0][0] >= 2 and zc[0][1] >= 2
+        ug, _, st = s.solve(dev(f), dev(g))
+    gi = np.array(st["iters"], dtype=np.int32)
+    free = orc.excmg(f, g, box, nc, tol)
+    assert np.all(np.abs(gi - free["iters"]) <= 1), (gi, free["iters"])
+    ref = orc.excmg(f, g, box, nc, tol, fixed_iters=gi)
+    assert rel2(host(ug), ref["u"]) <= 1e-12
+    mask = synth.boundary_mask(n)
+    assert np.array_equal(host(ug)[mask], g[mask])
+
+
+def test_dsolve_sweeps_match_sine_transform_solution(ex):
+    """A 68^3 direct solve (the second grid of a 34^3 -> 68^3 cascade, on the sweeps) against the exact discrete
+    solution by scipy's DST-I with the closed-form eigenvalues of the scheme."""
+    from test_oracle import dst_solve
+
+    n, nc = (68, 68, 68), (34, 34, 34)
+    p = synth.smooth(7)
+    f, g, _ = synth.sample(p, n)
+    s = ex.Solver(n, p.box, 1e-10, n_coarse=nc)
+    ug, _, st = s.solve(dev(f), dev(g))
+    assert st["levels"] == 2 and st["dsolve_iters"][1] > 0
+    b = host(ex.op_rhs(dev(f), dev(g), n, p.box))
+    ref = dst_solve(b, n, p.box)
+    mask = synth.boundary_mask(n)
+    ref[mask] = g[mask]
+    assert rel2(host(ug), ref) <= 1e-12
+
+
+def test_automatic_plan_with_large_direct_grid(ex):
+    """136^3 cells: the automatic plan halves to 34^3, so the second direct solve is on 68^3 (the sweeps).  Every grid
+    meets its test and the solution has the scheme's accuracy against the exact field."""
+    p = synth.smooth(0)
+    n = (136, 136, 136)
+    f, g, u = synth.sample(p, n)
+    s = ex.Solver(n, p.box, 1e-11)
+    assert s.levels == 3 and s.n_coarse == (34, 34, 34)
+    ug, _, st = s.solve(dev(f), dev(g))
+    assert st["dsolve_iters"][1] > 0 and st["relres"][0] <= 1e-13 and st["relres"][1] <= 1e-13
+    assert st["relres"][2] <= 1e-11
+    # fourth-order accuracy: at 256^3 this field's maximum error is about 1.1e-8, so about 1.3e-7 here
+    assert float(np.max(np.abs(host(ug) - u))) < 5e-7
+
+
 @pytest.mark.parametrize("precision", ["fp64", "fp32_ir"])
 def test_zero_and_constant_data(ex, precision):
     """f = 0 with g = 0 gives u = 0 with no CG iteration on any grid (||b|| = 0 meets the test at once); f = 0 with
