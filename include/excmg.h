@@ -41,6 +41,8 @@ extern "C" {
 #define EXCMG_ERR_BREAKDOWN (-5) /* CG met p.Ap <= 0 or a non-finite scalar */
 #define EXCMG_ERR_HIP (-6)       /* a HIP runtime call failed */
 #define EXCMG_ERR_WORKSPACE (-7) /* workspace null, too small or misaligned (256-byte alignment required) */
+#define EXCMG_ERR_SCRATCH (-8)   /* excmg_solve_noalloc: the problem needs more than the library's fixed scratch
+                                    array (EXCMG_NOALLOC_MAX_BYTES) */
 
 #define EXCMG_FP64 0    /* CG in FP64 */
 #define EXCMG_FP32_IR 1 /* CG sweeps in FP32 inside FP64 iterative refinement on every grid with at least 2^20
@@ -148,6 +150,22 @@ int excmg_setup(const excmg_problem *p, void *workspace, size_t bytes, void *hip
  * (Algorithm 1, optional step; Sections 4.2.1 and 4.3); needs at least two grids.
  * stats (host, nullable). */
 int excmg_solve(excmg_handle *h, const double *f, const double *g, double *u, double *u_ext, excmg_stats *stats);
+
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc): excmg_solve for the problem p without a handle or a caller workspace.  Its workspace is a
+ * fixed device array inside the library, EXCMG_NOALLOC_MAX_BYTES bytes, one per GPU the library is loaded on, held
+ * until the process ends; problems whose excmg_workspace_bytes exceeds it are rejected with EXCMG_ERR_SCRATCH before
+ * any device work.  The call allocates no device or pinned host memory and creates no HIP event, stream or graph: it
+ * launches kernels on hip_stream (hipStream_t, may be NULL) of the current device and reads the CG states back with
+ * stream copies, waiting for the stream before it returns, as excmg_solve does.  f, g, u, u_ext, stats: as for
+ * excmg_solve (same kernels and results as a handle set up for p without autotuning; EXCMG_WANT_TIMING is ignored
+ * and every iteration is launched directly).  All calls on one GPU share the array, which keeps the last call's
+ * contents: calls that overlap on one GPU (other host threads, other streams) race and must be serialised by the
+ * caller.  Errors: as excmg_solve, plus EXCMG_ERR_ARG for a null p, f, g or u, EXCMG_ERR_SHAPE for a bad plan, and
+ * EXCMG_ERR_HIP if the array's device address cannot be looked up. */
+#define EXCMG_NOALLOC_MAX_BYTES ((size_t)128 << 20)
+int excmg_solve_noalloc(const excmg_problem *p, const double *f, const double *g, double *u, double *u_ext,
+                        void *hip_stream, excmg_stats *stats);
 
 /* Fourth-order compact gradient of a finest-grid node array u (Section 5.1): one-sided fourth-order formulas at both
  * ends of every grid line, tridiagonal (1,4,1)/6 systems inside solved by the Thomas algorithm.  ux, uy, uz (out):

@@ -13,6 +13,8 @@ LIB_PATH = os.path.join(HERE, "libexcmg.so")
 
 OK = 0
 ERR_ARG, ERR_SHAPE, ERR_NONFINITE, ERR_NOCONV, ERR_BREAKDOWN, ERR_HIP, ERR_WORKSPACE = -1, -2, -3, -4, -5, -6, -7
+ERR_SCRATCH = -8
+NOALLOC_MAX_BYTES = 128 << 20
 FP64, FP32_IR = 0, 1
 WANT_HISTORY, WANT_TIMING, NO_GRAPHS, GUESS_QUADRATIC, GUESS_LINEAR, STOP_F_G = 1, 2, 4, 8, 16, 32
 GUESS_KINDS = {"quartic": 0, "quadratic": 1, "linear": 2}
@@ -111,6 +113,7 @@ def lib():
                                      ctypes.POINTER(ctypes.c_double)], _I),
             "excmg_destroy": ([_P], None),
             "excmg_set_timing": ([_P, ctypes.c_int32], _I),
+            "excmg_solve_noalloc": ([ctypes.POINTER(Problem), _P, _P, _P, _P, _P, ctypes.POINTER(Stats)], _I),
             "excmg_autotune": ([_P, _I32P, _I32P], _I),
             "excmg_bandwidth_probe": ([_P, ctypes.c_size_t, ctypes.c_int32, _P, ctypes.POINTER(ctypes.c_double)], _I),
             "excmg_strerror": ([_I], ctypes.c_char_p),

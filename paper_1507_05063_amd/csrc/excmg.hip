@@ -16,6 +16,7 @@
 #include <string.h>
 
 #include <chrono>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -220,6 +221,9 @@ struct excmg_handle {
   // graphs of kBatch CG iterations per grid (FP64, FP32 inner), captured on first use on a private stream
   hipStream_t cap = nullptr;
   hipGraphExec_t gexec[EXCMG_MAX_LEVELS][2] = {};
+  // a handle of excmg_solve_noalloc: no events, graphs, capture stream or pinned memory; CG states are read back with
+  // plain stream copies
+  bool noalloc = false;
 
   void drop_graphs() {
     for (auto &row : gexec)
@@ -309,6 +313,11 @@ int ensure_pinned(excmg_handle *h, size_t bytes) {
 // Copy `bytes` of a device record to the host: a one-workgroup kernel writes it into the pinned buffer, then the host
 // waits for the stream and reads it there.
 int read_record(excmg_handle *h, void *dst, const void *src, size_t bytes) {
+  if (h->noalloc) {
+    HIPCHECK(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, h->stream));
+    HIPCHECK(hipStreamSynchronize(h->stream));
+    return EXCMG_OK;
+  }
   int e = ensure_pinned(h, bytes);
   if (e) return e;
   launch_publish(src, h->pin_dev, bytes, h->stream);
@@ -412,7 +421,9 @@ void launch_iteration(excmg_handle *h, int l, int fp32, bool first, hipStream_t 
 
 // Graphs replace the iteration launches on every grid but the finest (where launches are long and may be timed),
 // unless EXCMG_NO_GRAPHS is set.
-bool use_graphs(const excmg_handle *h, int l) { return !(h->p.flags & EXCMG_NO_GRAPHS) && l < h->lo.L - 1; }
+bool use_graphs(const excmg_handle *h, int l) {
+  return !h->noalloc && !(h->p.flags & EXCMG_NO_GRAPHS) && l < h->lo.L - 1;
+}
 
 // kBatch CG iterations of grid l (not the first of a self-finalizing FP64 solve) as one graph launch on the handle's
 // stream.  The graph holds kernel launches only; it is captured on first use and kept until the sweeps change.
@@ -673,7 +684,7 @@ int cascade(excmg_handle *h, int mode, const double *f, const double *g, excmg_s
   int final_status = EXCMG_OK;
   for (int l = 0; l < L; ++l) {
     Level &lv = lo.lev[l];
-    HIPCHECK(hipEventRecord(h->lev_ev[l], s));
+    if (h->lev_ev[l]) HIPCHECK(hipEventRecord(h->lev_ev[l], s));
     RhsSrc rs;
     rs.gf = lo.gdense;
     rs.f = f;
@@ -734,18 +745,19 @@ int cascade(excmg_handle *h, int mode, const double *f, const double *g, excmg_s
       st->relres[l] = rr;
     }
   }
-  HIPCHECK(hipEventRecord(h->lev_ev[L], s));
+  if (h->lev_ev[L]) HIPCHECK(hipEventRecord(h->lev_ev[L], s));
   return final_status;
 }
 
 void fill_level_stats(excmg_handle *h, excmg_stats *st) {
   if (!st) return;
-  (void)hipEventSynchronize(h->lev_ev[h->lo.L]);
+  const bool ev = h->lev_ev[h->lo.L] != nullptr;
+  if (ev) (void)hipEventSynchronize(h->lev_ev[h->lo.L]);
   st->levels = h->lo.L;
   for (int l = 0; l < h->lo.L; ++l) {
     for (int d = 0; d < 3; ++d) st->n[l][d] = h->lo.lev[l].n[d];
     float ms = 0.0f;
-    if (hipEventElapsedTime(&ms, h->lev_ev[l], h->lev_ev[l + 1]) == hipSuccess) st->ms_level[l] = ms;
+    if (ev && hipEventElapsedTime(&ms, h->lev_ev[l], h->lev_ev[l + 1]) == hipSuccess) st->ms_level[l] = ms;
   }
 }
 
@@ -1094,6 +1106,37 @@ int batched_solve(excmg_handle *const *hs, int count, const double *const *f, co
 
 }  // namespace
 
+// ------------------------------------------------------------------------------------ the solve without allocation
+//
+// excmg_solve_noalloc's workspace is this fixed device array of the library: each GPU the library is loaded on holds
+// its own copy until the process ends.  Host code never uses the array's name as an address: the device address is
+// looked up once per device (hipGetSymbolAddress, with that device current) and kept.  Every call on one GPU uses
+// the same array, so calls that overlap on one GPU race; each call clears what it needs cleared.
+constexpr size_t kScratchBytes = EXCMG_NOALLOC_MAX_BYTES;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+
+int solve_on(excmg_handle *h, const double *f, const double *g, double *u, double *u_ext, excmg_stats *st);
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices];
+
+int scratch_address(int dev, void **out) {
+  if (dev < 0 || dev >= kMaxDevices) return EXCMG_ERR_HIP;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return EXCMG_ERR_HIP;
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return EXCMG_OK;
+}
+
+}  // namespace
+
 // ---------------------------------------------------------------------------------------------------------- C ABI
 
 extern "C" {
@@ -1187,12 +1230,43 @@ int excmg_solve(excmg_handle *h, const double *f, const double *g, double *u, do
   if (!h || !f || !g || !u) return EXCMG_ERR_ARG;
   if (u_ext && h->lo.L < 2) return EXCMG_ERR_SHAPE;
   DeviceGuard dg(h->device);
+  return solve_on(h, f, g, u, u_ext, st);
+}
+
+int excmg_solve_noalloc(const excmg_problem *p, const double *f, const double *g, double *u, double *u_ext,
+                        void *hip_stream, excmg_stats *st) {
+  if (!p || !f || !g || !u) return EXCMG_ERR_ARG;
+  excmg_handle h{};  // host state only, on the stack
+  int e = make_layout(p, &h.lo);
+  if (e) return e;
+  if (h.lo.total > kScratchBytes) return EXCMG_ERR_SCRATCH;
+  if (u_ext && h.lo.L < 2) return EXCMG_ERR_SHAPE;
+  h.p = *p;
+  h.p.flags = (p->flags & ~EXCMG_WANT_TIMING) | EXCMG_NO_GRAPHS;
+  h.noalloc = true;
+  h.stream = (hipStream_t)hip_stream;
+  HIPCHECK(hipGetDevice(&h.device));
+  void *ws = nullptr;
+  if ((e = scratch_address(h.device, &ws))) return e;
+  h.ws = (char *)ws;
+  bind_workspace(&h);
+  launch_clear_gbnd2(h.cs, h.cs2, h.stream);  // what excmg_setup clears: the CG states' boundary norm terms
+  if ((e = last_error())) return e;
+  return solve_on(&h, f, g, u, u_ext, st);
+}
+
+}  // extern "C"
+
+namespace {
+
+// Algorithm 1 on a set-up handle (the device current): the cascade, then EXP_true or the copy of u_h to the caller.
+int solve_on(excmg_handle *h, const double *f, const double *g, double *u, double *u_ext, excmg_stats *st) {
   const auto t0 = std::chrono::steady_clock::now();
   clear_stats(st);
   reset_timing(h);
   LevelIters li;
   memset(li.iters, 0, sizeof(li.iters));
-  const int status = cascade(h, 0, f, g, st, &li);
+  const int status = cascade(h, 0, f, g, st, h->noalloc ? nullptr : &li);
   if (status != EXCMG_OK && status != EXCMG_ERR_NOCONV) return status;
   Layout &lo = h->lo;
   const Level &fin = lo.lev[lo.L - 1];
@@ -1212,6 +1286,10 @@ int excmg_solve(excmg_handle *h, const double *f, const double *g, double *u, do
   if (st) st->ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   return status;
 }
+
+}  // namespace
+
+extern "C" {
 
 int excmg_gradient(excmg_handle *h, const double *u, double *ux, double *uy, double *uz) {
   if (!h || !u || !ux || !uy || !uz) return EXCMG_ERR_ARG;
@@ -1362,6 +1440,7 @@ const char *excmg_strerror(int code) {
     case EXCMG_ERR_BREAKDOWN: return "CG breakdown (p.Ap <= 0 or non-finite scalar)";
     case EXCMG_ERR_HIP: return "HIP runtime error";
     case EXCMG_ERR_WORKSPACE: return "workspace missing, too small or not 256-byte aligned";
+    case EXCMG_ERR_SCRATCH: return "problem too large for the fixed scratch array of excmg_solve_noalloc";
     default: return "unknown error code";
   }
 }

@@ -136,7 +136,7 @@ def test_setup_rejects_bad_workspace(abi):
 
 def test_strerror(abi):
     L = abi.lib()
-    for code in [0, -1, -2, -3, -4, -5, -6, -7]:
+    for code in [0, -1, -2, -3, -4, -5, -6, -7, -8]:
         assert L.excmg_strerror(code)
     assert L.excmg_strerror(-99) == b"unknown error code"
 
@@ -149,6 +149,26 @@ def test_product_path_does_not_import_the_oracle():
             if fn.endswith((".py", ".hip", ".h", ".cpp")):
                 txt = open(os.path.join(dirpath, fn)).read()
                 assert "import oracle" not in txt and "from oracle" not in txt and "oracle.h" not in txt, fn
+
+
+def test_noalloc_argument_errors(abi):
+    """excmg_solve_noalloc checks its arguments and the problem's size against its fixed array before any device
+    call: null pointers, a bad plan, and a workspace over EXCMG_NOALLOC_MAX_BYTES."""
+    import paper_1507_05063_amd as ex
+
+    L = abi.lib()
+    dummy = ctypes.c_void_p(4096)  # never dereferenced: every case returns before device work
+    p = ex._problem((32, 32, 32), (1, 1, 1), 1e-10)
+    assert L.excmg_solve_noalloc(None, dummy, dummy, dummy, None, None, None) == abi.ERR_ARG
+    assert L.excmg_solve_noalloc(ctypes.byref(p), None, dummy, dummy, None, None, None) == abi.ERR_ARG
+    assert L.excmg_solve_noalloc(ctypes.byref(p), dummy, dummy, None, None, None, None) == abi.ERR_ARG
+    bad = ex._problem((30, 32, 32), (1, 1, 1), 1e-10, n_coarse=(4, 4, 4))
+    assert L.excmg_solve_noalloc(ctypes.byref(bad), dummy, dummy, dummy, None, None, None) == abi.ERR_SHAPE
+    big = ex._problem((256, 256, 256), (1, 1, 1), 1e-10)
+    assert ex.workspace_bytes((256, 256, 256)) > abi.NOALLOC_MAX_BYTES
+    assert L.excmg_solve_noalloc(ctypes.byref(big), dummy, dummy, dummy, None, None, None) == abi.ERR_SCRATCH
+    one = ex._problem((4, 4, 4), (1, 1, 1), 1e-10, n_coarse=(4, 4, 4))  # one grid: no extrapolated solution
+    assert L.excmg_solve_noalloc(ctypes.byref(one), dummy, dummy, dummy, dummy, None, None) == abi.ERR_SHAPE
 
 
 def test_batch_workspace_bytes(abi):
