@@ -65,6 +65,12 @@ extern "C" {
  * test with a larger ||f_h|| on fine grids, so more CG iterations; the finer-grid errors the paper prints for its
  * Tables 1-12 follow this reading, its iteration counts the default one). */
 #define EXCMG_STOP_F_G 32u
+/* A third reading of the same test: the norm of (R f inside, g on the boundary) on every grid below the finest, and of
+ * the eliminated right-hand side b on the finest grid (so the grids that feed the extrapolation are relaxed to the
+ * tighter test, and the finest grid stops after the few iterations the default reading needs).  With it, one cascade
+ * reproduces both the paper's printed finest-grid errors (Tables 1-12, read as the grids of one run) and its printed
+ * finest-grid iteration counts.  At most one of EXCMG_STOP_F_G and this flag. */
+#define EXCMG_STOP_F_G_BELOW_FINEST 64u
 
 #define EXCMG_MAX_LEVELS 16
 #define EXCMG_MAX_HISTORY 256
@@ -191,8 +197,9 @@ int excmg_batch_workspace_bytes(int32_t count, size_t *bytes);
  * other streams must be complete.  The cascades run in step, grid s of every problem in step s: each kernel launch
  * covers every problem it concerns (the workgroups of one launch are split among the problems), so a batch costs
  * about as many launches as its largest problem.  Each problem keeps its own precision, tolerance and iteration
- * limits; the history and timing flags are ignored.  Handles set up with an EXCMG_GUESS_* flag or EXCMG_STOP_F_G
- * are rejected (EXCMG_ERR_ARG): batched solves start every grid from EXP_finite and take the default stopping norm.
+ * limits; the history and timing flags are ignored.  Handles set up with an EXCMG_GUESS_* flag, EXCMG_STOP_F_G or
+ * EXCMG_STOP_F_G_BELOW_FINEST are rejected (EXCMG_ERR_ARG): batched solves start every grid from EXP_finite and take
+ * the default stopping norm.
  * batch_ws: device memory of at least excmg_batch_workspace_bytes(count), 256-byte aligned, owned by the caller.
  * stats (host, nullable): count entries (ms_total = the host time of the whole call).  ms_per_problem (host,
  * nullable): count entries, the device time from the start of the batch until problem b's finest grid converged.
@@ -201,6 +208,18 @@ int excmg_batch_workspace_bytes(int32_t count, size_t *bytes);
 int excmg_solve_batched(excmg_handle *const *hs, int32_t count, const double *const *f, const double *const *g,
                         double *const *u, void *batch_ws, size_t batch_bytes, excmg_stats *stats,
                         double *ms_per_problem);
+
+/* Autotuner of excmg_solve_batched for a batch of handles (host call, device work on the stream of hs[0]; the same
+ * conditions on the handles as excmg_solve_batched).  In a batched launch the workgroups of all the problems concerned
+ * run together, so the z chunk a problem prefers alone is not the one the batch prefers.  For each grid counted from
+ * the problems' finest (t = 0 each problem's finest grid, t = 1 the next coarser, ...) and each precision, every z
+ * chunk in {2, 4, ..., 128} planes is timed as one flattened launch of the two CG passes over all problems whose grid
+ * t relaxes in that precision, and the fastest is kept in those problems' handles (replacing what excmg_autotune
+ * chose there; results do not depend on it).  Trial launches touch only the handles' work buffers and CG states.
+ * batch_ws: as for excmg_solve_batched.  zc_out (host, nullable, 2 * EXCMG_MAX_LEVELS entries): zc_out[2 t + p] the
+ * chunk chosen for grid t in precision p (0 FP64, 1 FP32), 0 where no problem relaxes that grid that way. */
+int excmg_autotune_batched(excmg_handle *const *hs, int32_t count, void *batch_ws, size_t batch_bytes,
+                           int32_t *zc_out);
 
 /* Autotuner (host call, device work on the handle's stream): times the two CG sweep kernels of every relaxed grid
  * (FP64, and FP32 where EXCMG_FP32_IR relaxes in FP32) for each z-chunk length in {2, 4, ..., 512} planes per
@@ -228,14 +247,23 @@ enum {
   EXCMG_PROBE_COPY_NT = 2, /* the copy with non-temporal loads and stores */
   EXCMG_PROBE_READ_NT = 3, /* the read with non-temporal loads */
   EXCMG_PROBE_MIX_NT = 4,  /* buf as three arrays a, b, c: b += a/2, c -= a/2, non-temporal (pass B's 3 reads, 2 writes) */
-  EXCMG_PROBE_KINDS = 5
+  EXCMG_PROBE_MIX = 5,     /* the same mix with ordinary loads and stores */
+  EXCMG_PROBE_WRITE = 6,   /* all of buf written, ordinary stores */
+  EXCMG_PROBE_WRITE_NT = 7, /* the write with non-temporal stores */
+  EXCMG_PROBE_KINDS = 8
 };
 
-/* Same-run bandwidth ceilings for the roofline: each kind above reps times (after one warm-up pass), with streaming
- * kernels of 16-byte accesses; GBs[kind] = the best rate in GB/s (bytes read plus bytes written).  buf: device, at
- * least 4096 bytes, 16-byte aligned; its contents are overwritten.  GBs: host, EXCMG_PROBE_KINDS entries.
- * Errors: EXCMG_ERR_ARG for a null or misaligned pointer, too few bytes or reps <= 0. */
-int excmg_bandwidth_probe(void *buf, size_t bytes, int32_t reps, void *hip_stream, double *GBs);
+/* Same-run bandwidth ceilings for the roofline: for each kind above, the best rate over a sweep of launch shapes --
+ * 2 to 64 workgroups of 256 threads per compute unit, 2, 4 or 8 independent 16-byte accesses in flight per lane, and
+ * two patterns (grid-stride loops; or each workgroup streaming through one contiguous range, as a stencil sweep's
+ * workgroup does) -- each run reps times after one warm-up pass, plus, for kinds 0-4, one fixed-shape kernel (8 or 32
+ * workgroups per CU, 4 accesses per lane, grid-stride; the copy of this one calibrates the hardware traffic
+ * counters).  GBs[kind] = bytes read plus bytes written / the fastest launch, in GB/s.  buf: device, at least 4096
+ * bytes, 16-byte aligned; its contents are overwritten.  GBs: host, EXCMG_PROBE_KINDS entries.  shapes (host,
+ * nullable, 3 * EXCMG_PROBE_KINDS entries): per kind, the fastest launch's workgroups per CU, accesses in flight per
+ * lane and pattern (1 = contiguous ranges).  Errors: EXCMG_ERR_ARG for a null or misaligned pointer, too few bytes
+ * or reps <= 0. */
+int excmg_bandwidth_probe(void *buf, size_t bytes, int32_t reps, void *hip_stream, double *GBs, int32_t *shapes);
 
 /* ---- single steps of the path, on one grid of cells n = (Nx,Ny,Nz) and box (node arrays as above) ---- */
 

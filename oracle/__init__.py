@@ -220,13 +220,14 @@ def initial_guess(kind, u2h, u4h, g):
     return w
 
 
-STOP_NORMS = {"b": 0, "fg": 1}
+STOP_NORMS = {"b": 0, "fg": 1, "fg_coarse": 2}
 
 
 def excmg_guess(kind, f, g, box, n_coarse, tol, max_iters=100000, fixed_iters=None, stop_norm="b", want_ext=False,
                 tol_order=0.0):
     """Algorithm 1 with the initial guess of the given kind on every level from 2 on, and the stopping test's norm
-    read as stop_norm says ("b": the eliminated right-hand side; "fg": R f inside and g on the boundary); tol_order
+    read as stop_norm says ("b": the eliminated right-hand side; "fg": R f inside and g on the boundary; "fg_coarse":
+    "fg" on every level below the finest and "b" on the finest); tol_order
     p > 0 relaxes level l of the finest Lt to tol * 2^(p (Lt - l)) (at most max(tol, 1e-2)).
     Returns dict(u, ut, w, iters, relres): w is the finest level's initial guess, ut EXP_true (want_ext)."""
     k = GUESS_KINDS[kind] if isinstance(kind, str) else int(kind)

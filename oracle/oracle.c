@@ -814,8 +814,9 @@ static int cascade(int mode, int guess, int stop_norm, int nx, int ny, int nz, d
       if (l == Lt && w_out) memcpy(w_out, ul, nl * sizeof(double));
       const int fi = fixed_iters ? fixed_iters[l] : -1;
       /* the stopping test ||r|| <= tol ||f_h||: f_h = b (the eliminated right-hand side) or, with stop_norm 1, the
-       * vector of R f on the interior nodes and g on the boundary nodes; the CG's test is against ||b||, so the
-       * tolerance is rescaled by ||f_h|| / ||b|| */
+       * vector of R f on the interior nodes and g on the boundary nodes; with stop_norm 2, that vector on every level
+       * below the finest and b on the finest; the CG's test is against ||b||, so the tolerance is rescaled by
+       * ||f_h|| / ||b|| */
       /* the level's tolerance: tol on every level, or (a schedule the paper does not give, for its remark on the
        * extrapolated solution in Section 5.1) tol * 2^(tol_order (Lt - l)), capped at max(tol, 1e-2) */
       double tol_l = tol;
@@ -824,7 +825,7 @@ static int cascade(int mode, int guess, int stop_norm, int nx, int ny, int nz, d
         tol_l = tol * pow(2.0, tol_order * (double)(Lt - l));
         if (tol_l > cap) tol_l = cap;
       }
-      if (stop_norm == 1) {
+      if (stop_norm == 1 || (stop_norm == 2 && l < Lt)) {
         double *rf = (double *)malloc(nl * sizeof(double));
         if (!rf) {
           status = ORC_ERR_NOMEM;
@@ -888,7 +889,7 @@ int orc_excmg_variant(int guess, int stop_norm, int nx, int ny, int nz, double l
                       int max_iters, const int *fixed_iters, double *u, double *ut, double *w_out, int *iters,
                       double *relres) {
   if (guess != ORC_GUESS_QUARTIC && guess != ORC_GUESS_QUADRATIC && guess != ORC_GUESS_LINEAR) return ORC_ERR_ARG;
-  if (stop_norm != 0 && stop_norm != 1) return ORC_ERR_ARG;
+  if (stop_norm != 0 && stop_norm != 1 && stop_norm != 2) return ORC_ERR_ARG;
   if (!(tol_order >= 0.0) || tol_order > 16.0) return ORC_ERR_ARG;
   return cascade(0, guess, stop_norm, nx, ny, nz, lx, ly, lz, ncx, ncy, ncz, f, g, tol, tol_order, max_iters,
                  fixed_iters, u, ut, w_out, iters, relres, NULL);

@@ -114,7 +114,8 @@ int orc_excmg(int nx, int ny, int nz, double lx, double ly, double lz, int ncx, 
 /* orc_excmg with the initial guess of kind guess (ORC_GUESS_*) on every level from 2 on, and the norm of the
  * stopping test ||A_h u_h - f_h|| <= eps ||f_h|| (Algorithm 1) read as stop_norm says: 0 = f_h is the eliminated
  * right-hand side b (the reading of orc_excmg), 1 = f_h is R f on the interior nodes and g on the boundary nodes
- * (the boundary values kept as identity rows).  tol_order = p > 0: level l of the finest Lt relaxes to
+ * (the boundary values kept as identity rows), 2 = reading 1 on every level below the finest and reading 0 on the
+ * finest.  tol_order = p > 0: level l of the finest Lt relaxes to
  * eps_l = tol * 2^(p (Lt - l)), capped at max(tol, 1e-2) (0: tol on every level).  No timing. */
 int orc_excmg_variant(int guess, int stop_norm, int nx, int ny, int nz, double lx, double ly, double lz, int ncx,
                       int ncy, int ncz, const double *f, const double *g, double tol, double tol_order,

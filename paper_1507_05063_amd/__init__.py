@@ -14,7 +14,8 @@ from . import _lib
 from ._lib import ExcmgError, FP32_IR, FP64, K_CLASSES, LIB_PATH, NO_GRAPHS, WANT_HISTORY, WANT_TIMING
 
 __all__ = ["Solver", "ExcmgError", "FP64", "FP32_IR", "plan", "workspace_bytes", "op_apply", "op_rhs",
-           "op_exp_finite", "op_initial_guess", "op_exp_true", "solve_batched", "batch_workspace_bytes",
+           "op_exp_finite", "op_initial_guess", "op_exp_true", "solve_batched", "autotune_batched",
+           "batch_workspace_bytes",
            "bandwidth_probe", "PROBE_KINDS", "K_CLASSES", "LIB_PATH"]
 
 
@@ -86,8 +87,8 @@ class Solver:
                  tol_order: float = 0.0, stream=None):
         """guess: the initial guess of every grid from the third on: "quartic" (EXP_finite, the paper's method),
         "quadratic" (the same extrapolation, tri-quadratic interpolation) or "linear" (CMG: trilinear u_2h).
-        stop_norm: the ||f_h|| of the stopping test: "b" (the eliminated right-hand side) or "fg" (R f inside, g on
-        the boundary).
+        stop_norm: the ||f_h|| of the stopping test: "b" (the eliminated right-hand side), "fg" (R f inside, g on
+        the boundary) or "fg_coarse" ("fg" on every grid below the finest, "b" on the finest).
         tol_order: p >= 0; grid l of L relaxes to tol * 2^(p (L-1-l)) (at most max(tol, 1e-2)): tol on the finest grid,
         looser on the coarser ones (0: tol everywhere, Algorithm 1)."""
         torch = _torch()
@@ -189,6 +190,23 @@ def batch_workspace_bytes(count: int) -> int:
     return int(b.value)
 
 
+def autotune_batched(solvers, workspace=None):
+    """Tune the z chunks of the batched CG sweeps for this batch of solvers (kept in the solvers' handles for later
+    solve_batched calls).  Returns {grid t counted from the finest: (FP64 chunk, FP32 chunk)}, 0 where unused."""
+    torch = _torch()
+    count = len(solvers)
+    if count == 0:
+        raise ValueError("no solvers")
+    nbytes = batch_workspace_bytes(count)
+    if workspace is None or workspace.numel() < nbytes:
+        workspace = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    H = (ctypes.c_void_p * count)(*[s.handle.value for s in solvers])
+    zc = (ctypes.c_int32 * (2 * _lib.MAX_LEVELS))()
+    _lib.check(_lib.lib().excmg_autotune_batched(H, count, _ptr(workspace), ctypes.c_size_t(workspace.numel()), zc),
+               "excmg_autotune_batched")
+    return {t: (zc[2 * t], zc[2 * t + 1]) for t in range(_lib.MAX_LEVELS) if zc[2 * t] or zc[2 * t + 1]}
+
+
 def solve_batched(solvers, fs, gs, us=None, workspace=None, allow_noconv: bool = False):
     """Solve many problems (each bound to its own Solver) in one batched call on the stream of solvers[0].
     Returns (us, stats list, ms_per_problem list): ms_per_problem[b] is the device time from the start of the batch
@@ -218,19 +236,26 @@ def solve_batched(solvers, fs, gs, us=None, workspace=None, allow_noconv: bool =
     return us, [st[b].to_dict() for b in range(count)], [ms[b] for b in range(count)]
 
 
-PROBE_KINDS = ("copy", "read", "copy_nt", "read_nt", "mix_nt")
+PROBE_KINDS = ("copy", "read", "copy_nt", "read_nt", "mix_nt", "mix", "write", "write_nt")
 
 
-def bandwidth_probe(nbytes: int = 2 << 30, reps: int = 5):
-    """Achievable HBM bandwidth in this process: GB/s of streaming kernels over nbytes, by kind: copy and read with
-    ordinary and with non-temporal accesses, and pass B's mix (three arrays read, two written, non-temporal)."""
+def bandwidth_probe(nbytes: int = 2 << 30, reps: int = 5, with_shapes: bool = False):
+    """Achievable HBM bandwidth in this process: GB/s of streaming kernels over nbytes, by kind (copy, read, pass B's
+    mix of three arrays read and two written, write; each with ordinary and with non-temporal accesses), the best
+    over a sweep of launch shapes.  with_shapes: also, per kind, the fastest shape (workgroups per CU, 16-byte
+    accesses in flight per lane, contiguous ranges per workgroup)."""
     torch = _torch()
     buf = torch.empty(int(nbytes), dtype=torch.uint8, device="cuda")
     rates = (ctypes.c_double * len(PROBE_KINDS))()
-    _lib.check(_lib.lib().excmg_bandwidth_probe(_ptr(buf), int(nbytes), int(reps), _stream_ptr(), rates),
+    shapes = (ctypes.c_int32 * (3 * len(PROBE_KINDS)))()
+    _lib.check(_lib.lib().excmg_bandwidth_probe(_ptr(buf), int(nbytes), int(reps), _stream_ptr(), rates, shapes),
                "excmg_bandwidth_probe")
     del buf
-    return {k: rates[i] for i, k in enumerate(PROBE_KINDS)}
+    out = {k: rates[i] for i, k in enumerate(PROBE_KINDS)}
+    if with_shapes:
+        return out, {k: {"wg_per_cu": shapes[3 * i], "lanes_in_flight": shapes[3 * i + 1],
+                         "contiguous": bool(shapes[3 * i + 2])} for i, k in enumerate(PROBE_KINDS)}
+    return out
 
 
 def _n3(n):

@@ -19,7 +19,8 @@ FP64, FP32_IR = 0, 1
 WANT_HISTORY, WANT_TIMING, NO_GRAPHS, GUESS_QUADRATIC, GUESS_LINEAR, STOP_F_G = 1, 2, 4, 8, 16, 32
 GUESS_KINDS = {"quartic": 0, "quadratic": 1, "linear": 2}
 GUESS_FLAGS = {"quartic": 0, "quadratic": GUESS_QUADRATIC, "linear": GUESS_LINEAR}
-STOP_NORM_FLAGS = {"b": 0, "fg": STOP_F_G}
+STOP_F_G_BELOW_FINEST = 64
+STOP_NORM_FLAGS = {"b": 0, "fg": STOP_F_G, "fg_coarse": STOP_F_G_BELOW_FINEST}
 MAX_LEVELS, MAX_HISTORY = 16, 256
 
 K_CLASSES = ["cg_a", "cg_b", "cg_a32", "cg_b32", "resid", "finalize", "rhs", "exp_finite", "exp_true", "dsolve",
@@ -111,11 +112,13 @@ def lib():
             "excmg_solve_batched": ([ctypes.POINTER(_P), ctypes.c_int32, ctypes.POINTER(_P), ctypes.POINTER(_P),
                                      ctypes.POINTER(_P), _P, ctypes.c_size_t, ctypes.POINTER(Stats),
                                      ctypes.POINTER(ctypes.c_double)], _I),
+            "excmg_autotune_batched": ([ctypes.POINTER(_P), ctypes.c_int32, _P, ctypes.c_size_t, _I32P], _I),
             "excmg_destroy": ([_P], None),
             "excmg_set_timing": ([_P, ctypes.c_int32], _I),
             "excmg_solve_noalloc": ([ctypes.POINTER(Problem), _P, _P, _P, _P, _P, ctypes.POINTER(Stats)], _I),
             "excmg_autotune": ([_P, _I32P, _I32P], _I),
-            "excmg_bandwidth_probe": ([_P, ctypes.c_size_t, ctypes.c_int32, _P, ctypes.POINTER(ctypes.c_double)], _I),
+            "excmg_bandwidth_probe": ([_P, ctypes.c_size_t, ctypes.c_int32, _P, ctypes.POINTER(ctypes.c_double), _I32P],
+                                      _I),
             "excmg_strerror": ([_I], ctypes.c_char_p),
             "excmg_op_apply": ([_I32P, _D3, _P, _P, _P], _I),
             "excmg_op_rhs": ([_I32P, _D3, _P, _P, _P, _P], _I),

@@ -95,9 +95,10 @@ int validate(const excmg_problem *p) {
   if (p->inner_tol < 0.0 || !isfinite(p->inner_tol) || p->inner_tol >= 1.0) return EXCMG_ERR_ARG;
   if (p->max_iters < 0) return EXCMG_ERR_ARG;
   if (p->flags & ~(EXCMG_WANT_HISTORY | EXCMG_WANT_TIMING | EXCMG_NO_GRAPHS | EXCMG_GUESS_QUADRATIC |
-                   EXCMG_GUESS_LINEAR | EXCMG_STOP_F_G))
+                   EXCMG_GUESS_LINEAR | EXCMG_STOP_F_G | EXCMG_STOP_F_G_BELOW_FINEST))
     return EXCMG_ERR_ARG;
   if ((p->flags & EXCMG_GUESS_QUADRATIC) && (p->flags & EXCMG_GUESS_LINEAR)) return EXCMG_ERR_ARG;
+  if ((p->flags & EXCMG_STOP_F_G) && (p->flags & EXCMG_STOP_F_G_BELOW_FINEST)) return EXCMG_ERR_ARG;
   if (!(p->tol_order >= 0.0) || p->tol_order > 16.0) return EXCMG_ERR_ARG;
   return EXCMG_OK;
 }
@@ -694,8 +695,11 @@ int cascade(excmg_handle *h, int mode, const double *f, const double *g, excmg_s
     rs.a = 1.0 / (lv.h[0] * lv.h[0]);
     rs.b = 1.0 / (lv.h[1] * lv.h[1]);
     rs.c = 1.0 / (lv.h[2] * lv.h[2]);
-    rs.fg = (mode == 0 && (h->p.flags & EXCMG_STOP_F_G)) ? 1 : 0;
-    if (h->p.flags & EXCMG_STOP_F_G) {
+    // the stopping test's norm on this grid: (R f, g) under EXCMG_STOP_F_G, and under EXCMG_STOP_F_G_BELOW_FINEST
+    // on every grid but the finest; else b (and always b for the adjoint)
+    const bool fg_here = (h->p.flags & EXCMG_STOP_F_G) || ((h->p.flags & EXCMG_STOP_F_G_BELOW_FINEST) && l < L - 1);
+    rs.fg = (mode == 0 && fg_here) ? 1 : 0;
+    if (h->p.flags & (EXCMG_STOP_F_G | EXCMG_STOP_F_G_BELOW_FINEST)) {
       // the boundary half of the stopping test's norm for this grid (0 for the adjoint, whose test stays on ||b||)
       Tick t(h, EXCMG_K_OTHER, l);
       launch_boundary_g2(rs, lv.g, h->cs, s);
@@ -1102,6 +1106,106 @@ int batched_solve(excmg_handle *const *hs, int count, const double *const *f, co
     if (stats) stats[b].ms_total = host_ms;
   }
   return final_status;
+}
+
+// Autotuner of the batched sweeps.  In a batched launch the workgroups of every problem concerned run together, so the
+// z chunk that suits one problem alone (small chunks, to give a small grid enough workgroups to fill the GPU) is not
+// the one that suits the batch.  Per grid counted from each problem's finest (t = 0 the finest, 1 the next coarser,
+// ...) and per precision, every candidate chunk is timed as one flattened launch of pass A and one of pass B over all
+// the problems whose grid t relaxes in that precision (the batched kernels' prefetch depth 2 and streaming policy),
+// and the fastest is kept in each of those problems' sweeps.  zc_out[2 t + prec] (nullable): the chunk chosen, 0
+// where no problem relaxes that grid in that precision.
+int batched_autotune(excmg_handle *const *hs, int count, char *ws, int32_t *zc_out) {
+  const hipStream_t s = hs[0]->stream;
+  int S = 0;
+  for (int b = 0; b < count; ++b) S = hs[b]->lo.L > S ? hs[b]->lo.L : S;
+  static const int cand[] = {2, 4, 8, 16, 32, 64, 128};
+  const size_t stat_bytes = align256(sizeof(BatchStatus) * (size_t)count);
+  char *table_dev = ws + stat_bytes + 256;
+  char *list_dev = table_dev + (size_t)EXCMG_MAX_LEVELS * batch_table_bytes(count);
+  const int n1 = count + 1;
+  std::vector<BatchEntry> ent(count);
+  std::vector<char> list_host(batch_list_bytes(count));
+  const BatchEntry **lent = (const BatchEntry **)list_host.data();
+  int *preA = (int *)(list_host.data() + sizeof(void *) * (size_t)count), *preB = preA + n1;
+  hipEvent_t ea, eb;
+  HIPCHECK(hipEventCreateWithFlags(&ea, kTimingEvent));
+  HIPCHECK(hipEventCreateWithFlags(&eb, kTimingEvent));
+  int rc = EXCMG_OK;
+  if (zc_out)
+    for (int q = 0; q < 2 * EXCMG_MAX_LEVELS; ++q) zc_out[q] = 0;
+  for (int t = 0; t < S && rc == EXCMG_OK; ++t) {
+    for (int prec = 0; prec < 2 && rc == EXCMG_OK; ++prec) {
+      std::vector<int> probs;  // the problems whose grid L-1-t relaxes in this precision
+      for (int b = 0; b < count; ++b) {
+        const int l = hs[b]->lo.L - 1 - t;
+        if (l < 0) continue;
+        const int kind = batch_kind(hs[b], l);
+        if ((prec == 0 && kind == kBCg64) || (prec == 1 && kind == kBIr)) probs.push_back(b);
+      }
+      if (probs.empty()) continue;
+      float best = 1e30f;
+      int best_zc = 0;
+      for (int zc : cand) {
+        const int n = (int)probs.size();
+        preA[0] = preB[0] = 0;
+        for (int q = 0; q < n; ++q) {
+          excmg_handle *h = hs[probs[q]];
+          const int l = h->lo.L - 1 - t;
+          const Level &lv = h->lo.lev[l];
+          int blocks[kLaunchKinds];
+          batch_entry(h, probs[q], l, nullptr, nullptr, nullptr, &ent[q], blocks);
+          const Sweep sw = make_sweep(prec ? lv.g32 : lv.g, lv.st, zc, 2, 1);
+          if (prec) ent[q].swA32 = ent[q].swB32 = sw;
+          else ent[q].swA = ent[q].swB = sw;
+          lent[q] = (const BatchEntry *)table_dev + q;
+          preA[q + 1] = preA[q] + sweep_blocks(sw);
+          preB[q + 1] = preB[q] + sweep_blocks(sw);
+        }
+        if (hipMemcpyAsync(table_dev, ent.data(), sizeof(BatchEntry) * (size_t)n, hipMemcpyHostToDevice, s) !=
+                hipSuccess ||
+            hipMemcpyAsync(list_dev, list_host.data(), list_host.size(), hipMemcpyHostToDevice, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess) {
+          rc = EXCMG_ERR_HIP;
+          break;
+        }
+        BatchList A, B;
+        A.ent = B.ent = (const BatchEntry *const *)list_dev;
+        A.pre = A.aux = (const int *)(list_dev + sizeof(void *) * (size_t)count);
+        B.pre = B.aux = A.pre + n1;
+        A.n = B.n = n;
+        A.total = preA[n];
+        B.total = preB[n];
+        launch_b_tune_state(A, s);
+        float tmin = 1e30f;
+        for (int rep = 0; rep < 4 && rc == EXCMG_OK; ++rep) {
+          float ms = 0.0f;
+          if (hipEventRecord(ea, s) != hipSuccess) rc = EXCMG_ERR_HIP;
+          launch_b_passes(prec, A, B, s);
+          if (hipEventRecord(eb, s) != hipSuccess || hipEventSynchronize(eb) != hipSuccess ||
+              hipEventElapsedTime(&ms, ea, eb) != hipSuccess || last_error() != EXCMG_OK)
+            rc = EXCMG_ERR_HIP;
+          if (rep > 0 && ms < tmin) tmin = ms;  // the first launch warms caches and code
+        }
+        if (tmin < best) {
+          best = tmin;
+          best_zc = zc;
+        }
+      }
+      if (rc) break;
+      for (int b : probs) {
+        Level &lv = hs[b]->lo.lev[hs[b]->lo.L - 1 - t];
+        const Sweep sw = make_sweep(prec ? lv.g32 : lv.g, lv.st, best_zc, 2, 1);
+        if (prec) lv.swA32 = lv.swB32 = sw;
+        else lv.swA = lv.swB = sw;
+      }
+      if (zc_out) zc_out[2 * t + prec] = best_zc;
+    }
+  }
+  (void)hipEventDestroy(ea);
+  (void)hipEventDestroy(eb);
+  for (int b = 0; b < count; ++b) hs[b]->drop_graphs();  // captured with the old sweep shapes
+  return rc;
 }
 
 }  // namespace
@@ -1538,44 +1642,91 @@ int excmg_op_exp_true(const int32_t n[3], const double *uh, const double *u2h, d
   return EXCMG_OK;
 }
 
-int excmg_bandwidth_probe(void *buf, size_t bytes, int32_t reps, void *hip_stream, double *GBs) {
+int excmg_bandwidth_probe(void *buf, size_t bytes, int32_t reps, void *hip_stream, double *GBs, int32_t *shapes) {
   if (!buf || bytes < 4096 || reps <= 0 || ((uintptr_t)buf & 15) || !GBs) return EXCMG_ERR_ARG;
   const hipStream_t s = (hipStream_t)hip_stream;
   const long long n = (long long)(bytes / sizeof(double)) & ~7LL;  // doubles, a multiple of 8
-  const long long m = (n / 3) & ~1LL;                              // doubles per array of the mix, even
+  const long long h = (n / 2) & ~1LL;                              // doubles per half (copy), even
+  const long long m = (n / 3) & ~1LL;                              // doubles per third (mix), even
   double *a = (double *)buf;
   hipEvent_t e0, e1;
   HIPCHECK(hipEventCreateWithFlags(&e0, kTimingEvent));
   HIPCHECK(hipEventCreateWithFlags(&e1, kTimingEvent));
   HIPCHECK(hipMemsetAsync(buf, 0, (size_t)n * sizeof(double), s));
-  // bytes each kind moves (read plus written)
-  const double moved[EXCMG_PROBE_KINDS] = {(double)n * 8, (double)n * 8, (double)n * 8, (double)n * 8,
-                                           5.0 * (double)m * 8};
+  // per kind: the sweep kernel's mode, cache policy, and the bytes it moves (read plus written)
+  struct Kind {
+    int mode;
+    bool nt;
+    double moved;
+  };
+  const Kind kinds[EXCMG_PROBE_KINDS] = {
+      {0, false, 16.0 * h}, {1, false, 8.0 * n}, {0, true, 16.0 * h}, {1, true, 8.0 * n},
+      {2, true, 40.0 * m},  {2, false, 40.0 * m}, {3, false, 8.0 * n}, {3, true, 8.0 * n}};
+  // launch shapes: the first kernels of each kind are the fixed-shape originals (kinds 0-4), then the sweep
+  static const int wgpc[] = {2, 4, 8, 16, 32, 64};
+  static const int lanes[] = {2, 4, 8};
+  struct Shape {
+    int wg, u, chunk, legacy;
+  };
+  std::vector<Shape> sh;
+  sh.push_back({0, 0, 0, 1});
+  for (int w : wgpc)
+    for (int u : lanes)
+      for (int c = 0; c < 2; ++c) sh.push_back({w, u, c, 0});
   float best[EXCMG_PROBE_KINDS];
-  for (float &v : best) v = 1e30f;
+  Shape win[EXCMG_PROBE_KINDS];
+  for (int k = 0; k < EXCMG_PROBE_KINDS; ++k) {
+    best[k] = 1e30f;
+    win[k] = {0, 0, 0, 0};
+  }
   int rc = EXCMG_OK;
   for (int rep = 0; rep <= reps && rc == EXCMG_OK; ++rep) {
     for (int kind = 0; kind < EXCMG_PROBE_KINDS && rc == EXCMG_OK; ++kind) {
-      if (hipEventRecord(e0, s) != hipSuccess) rc = EXCMG_ERR_HIP;
-      switch (kind) {
-        case EXCMG_PROBE_COPY: launch_probe_copy(a, a + n / 2, n / 2, s); break;
-        case EXCMG_PROBE_READ: launch_probe_read(a, n, a, s); break;
-        case EXCMG_PROBE_COPY_NT: launch_probe_copy_nt(a, a + n / 2, n / 2, s); break;
-        case EXCMG_PROBE_READ_NT: launch_probe_read_nt(a, n, a, s); break;
-        default: launch_probe_mix_nt(a, a + m, a + 2 * m, m, s); break;
+      const Kind &K = kinds[kind];
+      for (const Shape &q : sh) {
+        if (q.legacy && kind > EXCMG_PROBE_MIX_NT) continue;  // no fixed-shape original for these kinds
+        if (hipEventRecord(e0, s) != hipSuccess) rc = EXCMG_ERR_HIP;
+        if (q.legacy) {
+          switch (kind) {
+            case EXCMG_PROBE_COPY: launch_probe_copy(a, a + h, h, s); break;
+            case EXCMG_PROBE_READ: launch_probe_read(a, n, a, s); break;
+            case EXCMG_PROBE_COPY_NT: launch_probe_copy_nt(a, a + h, h, s); break;
+            case EXCMG_PROBE_READ_NT: launch_probe_read_nt(a, n, a, s); break;
+            default: launch_probe_mix_nt(a, a + m, a + 2 * m, m, s); break;
+          }
+        } else if (K.mode == 0) {
+          launch_probe_sweep(0, q.u, K.nt, q.chunk != 0, q.wg, a, a + h, nullptr, h, a, s);
+        } else if (K.mode == 2) {
+          launch_probe_sweep(2, q.u, K.nt, q.chunk != 0, q.wg, a, a + m, a + 2 * m, m, a, s);
+        } else {
+          launch_probe_sweep(K.mode, q.u, K.nt, q.chunk != 0, q.wg, a, a, nullptr, n, a, s);
+        }
+        float ms = 0.0f;
+        if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+          rc = EXCMG_ERR_HIP;
+        if (last_error() != EXCMG_OK) rc = EXCMG_ERR_HIP;
+        if (rc) break;
+        if (rep > 0 && ms < best[kind]) {  // the first pass warms up
+          best[kind] = ms;
+          win[kind] = q;
+        }
       }
-      float ms = 0.0f;
-      if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
-          hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
-        rc = EXCMG_ERR_HIP;
-      if (last_error() != EXCMG_OK) rc = EXCMG_ERR_HIP;
-      if (rep > 0 && ms < best[kind]) best[kind] = ms;  // the first pass warms up
     }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (rc) return rc;
-  for (int kind = 0; kind < EXCMG_PROBE_KINDS; ++kind) GBs[kind] = moved[kind] / (best[kind] * 1e-3) / 1e9;
+  for (int kind = 0; kind < EXCMG_PROBE_KINDS; ++kind) {
+    GBs[kind] = kinds[kind].moved / (best[kind] * 1e-3) / 1e9;
+    if (shapes) {
+      const Shape &q = win[kind];
+      // the fixed-shape originals run 8 (ordinary) or 32 (non-temporal) workgroups per CU, 4 accesses in flight
+      shapes[3 * kind + 0] = q.legacy ? (kinds[kind].nt ? 32 : 8) : q.wg;
+      shapes[3 * kind + 1] = q.legacy ? 4 : q.u;
+      shapes[3 * kind + 2] = q.legacy ? 0 : q.chunk;
+    }
+  }
   return EXCMG_OK;
 }
 
@@ -1585,13 +1736,24 @@ int excmg_batch_workspace_bytes(int32_t count, size_t *bytes) {
   return EXCMG_OK;
 }
 
+int excmg_autotune_batched(excmg_handle *const *hs, int32_t count, void *batch_ws, size_t batch_bytes,
+                           int32_t *zc_out) {
+  if (!hs || count <= 0) return EXCMG_ERR_ARG;
+  for (int b = 0; b < count; ++b)
+    if (!hs[b] || hs[b]->device != hs[0]->device) return EXCMG_ERR_ARG;
+  if (!batch_ws || ((uintptr_t)batch_ws & 255) || batch_bytes < batch_ws_bytes(count)) return EXCMG_ERR_WORKSPACE;
+  DeviceGuard dg(hs[0]->device);
+  return batched_autotune(hs, count, (char *)batch_ws, zc_out);
+}
+
 int excmg_solve_batched(excmg_handle *const *hs, int32_t count, const double *const *f, const double *const *g,
                         double *const *u, void *batch_ws, size_t batch_bytes, excmg_stats *stats,
                         double *ms_per_problem) {
   if (!hs || count <= 0 || !f || !g || !u) return EXCMG_ERR_ARG;
   for (int b = 0; b < count; ++b)
     if (!hs[b] || !f[b] || !g[b] || !u[b] || hs[b]->device != hs[0]->device ||
-        guess_kind(hs[b]->p.flags) != kGuessQuartic || (hs[b]->p.flags & EXCMG_STOP_F_G))
+        guess_kind(hs[b]->p.flags) != kGuessQuartic ||
+        (hs[b]->p.flags & (EXCMG_STOP_F_G | EXCMG_STOP_F_G_BELOW_FINEST)))
       return EXCMG_ERR_ARG;
   if (!batch_ws || ((uintptr_t)batch_ws & 255) || batch_bytes < batch_ws_bytes(count)) return EXCMG_ERR_WORKSPACE;
   DeviceGuard dg(hs[0]->device);

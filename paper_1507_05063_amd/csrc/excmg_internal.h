@@ -224,6 +224,9 @@ void launch_probe_read(const double *src, long long n, double *sink, hipStream_t
 void launch_probe_copy_nt(const double *src, double *dst, long long n, hipStream_t st);
 void launch_probe_read_nt(const double *src, long long n, double *sink, hipStream_t st);
 void launch_probe_mix_nt(const double *a, double *b, double *c, long long n, hipStream_t st);
+// the swept streaming kernels: mode 0 copy a -> b, 1 read a, 2 b += a/2 and c -= a/2, 3 write b; arrays of n doubles
+void launch_probe_sweep(int mode, int u, bool nt, bool chunk, int wg_per_cu, const double *a, double *b, double *c,
+                        long long n, double *sink, hipStream_t st);
 
 // one CG iteration with the reductions finalized inside the sweeps: pass A reads nb_prev partial sums from partsB
 // (the residual's [r.r | b.b] before iteration 0, pass B's r.r afterwards) and writes partsA; pass B reads nbA from
@@ -366,6 +369,9 @@ void launch_b_residual_cast(const BatchList &L, BatchStatus *stat, hipStream_t s
 // workgroup prefixes of pass A and pass B); fp32: the inner FP32 solves of the refinement
 void launch_b_iteration(int fp32, const BatchList &A, const BatchList &B, BatchStatus *stat, hipStream_t st);
 void launch_b_add_correction(const BatchList &L, hipStream_t st);
+// the autotuner's trial CG state in every entry of L, and the two passes alone (timed by the batched autotuner)
+void launch_b_tune_state(const BatchList &L, hipStream_t st);
+void launch_b_passes(int fp32, const BatchList &A, const BatchList &B, hipStream_t st);
 void launch_b_copy(const BatchList &L, hipStream_t st);
 // workgroup counts of the flattened launches for one grid
 int b_blocks_exp_finite(const Grid &gw);

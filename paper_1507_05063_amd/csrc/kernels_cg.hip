@@ -879,12 +879,10 @@ __global__ __launch_bounds__(FT) void finalize_b_kernel(CgState *cs, const doubl
 
 // ------------------------------------------------------------------------------------------------------ small kernels
 
-// A CG state in which the sweeps do their full work but change nothing that matters: iteration 0 (pass A reads only
-// r), alpha = 0 (pass B leaves u and r as they are), and a stopping test that never fires.
 // CG state for the autotuner's trial launches: a later iteration (pass A then reads r and p_old, as it does in
 // every iteration but the first), never converged, alpha = beta = 0.  The trials' results are discarded: a solve
 // writes these work buffers before it reads them.
-__global__ void tune_state_kernel(CgState *cs) {
+__device__ void tune_state(CgState *cs) {
   cs->rho = 1.0;
   cs->rho_old = 1.0;
   cs->pq = 1.0;
@@ -898,6 +896,8 @@ __global__ void tune_state_kernel(CgState *cs) {
   cs->max_iters = 1 << 30;
   cs->hist_on = 0;
 }
+
+__global__ void tune_state_kernel(CgState *cs) { tune_state(cs); }
 
 // copy of a small device record (n 8-byte words) into host memory the device can write (the host reads it after a
 // stream synchronisation; no staged copy)
@@ -1500,6 +1500,14 @@ __global__ __launch_bounds__(FT) void b_finalize_pass_kernel(BatchList L, BatchS
   }
 }
 
+// the trial state of the autotuner in both CG states of every entry of L (one thread per entry)
+__global__ void b_tune_state_kernel(BatchList L) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= L.n) return;
+  tune_state(L.ent[q]->cs);
+  tune_state(L.ent[q]->cs2);
+}
+
 __global__ __launch_bounds__(256) void b_add_correction_kernel(BatchList L) {
   const int e = find_entry(L.pre, L.n, blockIdx.x);
   const BatchEntry &E = *L.ent[e];
@@ -1736,6 +1744,21 @@ void launch_b_iteration(int fp32, const BatchList &A, const BatchList &B, BatchS
     b_finalize_pass_kernel<0, 0><<<A.n, FT, 0, st>>>(A, stat);
     b_pass_b_kernel<double><<<B.total, NT, 0, st>>>(B);
     b_finalize_pass_kernel<1, 0><<<B.n, FT, 0, st>>>(B, stat);
+  }
+}
+
+void launch_b_tune_state(const BatchList &L, hipStream_t st) {
+  if (L.n > 0) b_tune_state_kernel<<<(L.n + 255) / 256, 256, 0, st>>>(L);
+}
+
+void launch_b_passes(int fp32, const BatchList &A, const BatchList &B, hipStream_t st) {
+  if (A.total <= 0 || B.total <= 0) return;
+  if (fp32) {
+    b_pass_a_kernel<float><<<A.total, NT, 0, st>>>(A);
+    b_pass_b_kernel<float><<<B.total, NT, 0, st>>>(B);
+  } else {
+    b_pass_a_kernel<double><<<A.total, NT, 0, st>>>(A);
+    b_pass_b_kernel<double><<<B.total, NT, 0, st>>>(B);
   }
 }
 

@@ -3,6 +3,8 @@
 // of the CG's pass B (three reads, two writes).  16-byte accesses, several independent accesses in flight per lane,
 // grid-stride loops.  Used as the same-run ceilings beside the solver's sweeps; the ordinary copy also scales the
 // hardware traffic counters.
+#include <type_traits>
+
 #include "excmg_internal.h"
 
 namespace excmg {
@@ -101,6 +103,76 @@ __global__ __launch_bounds__(PT) void probe_mix_nt_kernel(const pv2 *__restrict_
   for (; q < m; q += stride) one(q, a[q], b[q], c[q]);
 }
 
+// The sweep of launch shapes: one kernel per (access mix, 16-byte accesses in flight per lane, cache policy, pattern).
+// MODE 0: copy a -> b; 1: read a; 2: pass B's mix, b += a/2 and c -= a/2 (three arrays read, two written); 3: write b.
+// CHUNK: each workgroup streams through one contiguous range of the arrays (the way a stencil sweep's workgroup
+// marches through its tile) instead of striding over the whole grid.
+template <bool NTP>
+__device__ __forceinline__ pv2 pld(const pv2 *p) {
+  if constexpr (NTP) return __builtin_nontemporal_load(p);
+  else return *p;
+}
+template <bool NTP>
+__device__ __forceinline__ void pst(pv2 v, pv2 *p) {
+  if constexpr (NTP) __builtin_nontemporal_store(v, p);
+  else *p = v;
+}
+
+template <int MODE, int U, bool NTP, bool CHUNK>
+__global__ __launch_bounds__(PT) void probe_sweep_kernel(const pv2 *__restrict__ a, pv2 *__restrict__ b,
+                                                         pv2 *__restrict__ c, long long m, double *sink) {
+  long long q, end, step;  // this thread's first element, the end of its range, and the distance between its rounds
+  long long lane_stride;   // distance between its U accesses of one round
+  if constexpr (CHUNK) {
+    const long long per = ((m + gridDim.x - 1) / gridDim.x + PT - 1) / PT * PT;
+    const long long s0 = (long long)blockIdx.x * per;
+    end = s0 + per < m ? s0 + per : m;
+    q = s0 + threadIdx.x;
+    lane_stride = PT;
+  } else {
+    end = m;
+    q = (long long)blockIdx.x * PT + threadIdx.x;
+    lane_stride = (long long)gridDim.x * PT;
+  }
+  step = U * lane_stride;
+  double acc = 0.0;
+  const pv2 fill = {1.0, 2.0};
+  auto one = [&](long long i, pv2 x, pv2 y, pv2 z) {
+    if constexpr (MODE == 0) pst<NTP>(x, &b[i]);
+    if constexpr (MODE == 1) acc += x.x + x.y;
+    if constexpr (MODE == 2) {
+      pst<NTP>(y + 0.5 * x, &b[i]);
+      pst<NTP>(z - 0.5 * x, &c[i]);
+    }
+    if constexpr (MODE == 3) pst<NTP>(fill, &b[i]);
+  };
+  for (; q + (U - 1) * lane_stride < end; q += step) {
+    pv2 x[U], y[U], z[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const long long i = q + u * lane_stride;
+      if constexpr (MODE != 3) x[u] = pld<NTP>(&a[i]);
+      if constexpr (MODE == 2) {
+        y[u] = pld<NTP>(&b[i]);
+        z[u] = pld<NTP>(&c[i]);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) one(q + u * lane_stride, x[u], y[u], z[u]);
+  }
+  for (; q < end; q += lane_stride) {
+    pv2 x = fill, y = fill, z = fill;
+    if constexpr (MODE != 3) x = pld<NTP>(&a[q]);
+    if constexpr (MODE == 2) {
+      y = pld<NTP>(&b[q]);
+      z = pld<NTP>(&c[q]);
+    }
+    one(q, x, y, z);
+  }
+  if constexpr (MODE == 1)
+    if (acc == 1.2345e300) sink[0] = acc;  // keeps the loads; never true for the probe's data
+}
+
 int probe_blocks() {
   int dev = 0, cus = 256;
   if (hipGetDevice(&dev) == hipSuccess) {
@@ -130,6 +202,40 @@ void launch_probe_read_nt(const double *src, long long n, double *sink, hipStrea
 
 void launch_probe_mix_nt(const double *a, double *b, double *c, long long n, hipStream_t st) {
   probe_mix_nt_kernel<<<4 * probe_blocks(), PT, 0, st>>>((const pv2 *)a, (pv2 *)b, (pv2 *)c, n / 2);
+}
+
+int probe_cus() { return probe_blocks() / 8; }
+
+// One launch of the sweep kernel of a shape: mode (0 copy, 1 read, 2 mix, 3 write), 16-byte accesses in flight per
+// lane (2, 4 or 8), cache policy, pattern; wg_per_cu workgroups per compute unit.  a, b, c: arrays of n doubles each
+// (n even; b and c unused where the mode does not need them; sink: a double the read mode may write).
+void launch_probe_sweep(int mode, int u, bool nt, bool chunk, int wg_per_cu, const double *a, double *b, double *c,
+                        long long n, double *sink, hipStream_t st) {
+  const int grid = wg_per_cu * probe_cus();
+  const long long m = n / 2;
+  auto go = [&](auto md, auto uu, auto ntp, auto ch) {
+    probe_sweep_kernel<decltype(md)::value, decltype(uu)::value, decltype(ntp)::value, decltype(ch)::value>
+        <<<grid, PT, 0, st>>>((const pv2 *)a, (pv2 *)b, (pv2 *)c, m, sink);
+  };
+  auto by_chunk = [&](auto md, auto uu, auto ntp) {
+    if (chunk) go(md, uu, ntp, std::true_type{});
+    else go(md, uu, ntp, std::false_type{});
+  };
+  auto by_nt = [&](auto md, auto uu) {
+    if (nt) by_chunk(md, uu, std::true_type{});
+    else by_chunk(md, uu, std::false_type{});
+  };
+  auto by_u = [&](auto md) {
+    if (u == 2) by_nt(md, std::integral_constant<int, 2>{});
+    else if (u == 4) by_nt(md, std::integral_constant<int, 4>{});
+    else by_nt(md, std::integral_constant<int, 8>{});
+  };
+  switch (mode) {
+    case 0: by_u(std::integral_constant<int, 0>{}); break;
+    case 1: by_u(std::integral_constant<int, 1>{}); break;
+    case 2: by_u(std::integral_constant<int, 2>{}); break;
+    default: by_u(std::integral_constant<int, 3>{}); break;
+  }
 }
 
 }  // namespace excmg

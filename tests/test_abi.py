@@ -93,7 +93,8 @@ def test_bad_arguments(abi):
 
 @pytest.mark.parametrize("flags,tol_order,ok", [(0, 0.0, True), (0, 6.0, True), (0, 16.0, True), (0, -1.0, False),
                                                 (0, 16.5, False), (0, float("nan"), False), (32, 6.0, True),
-                                                (64, 0.0, False), (8 | 16, 0.0, False)])
+                                                (64, 0.0, True), (32 | 64, 0.0, False), (128, 0.0, False),
+                                                (8 | 16, 0.0, False)])
 def test_problem_validation(abi, flags, tol_order, ok):
     """Flags (EXCMG_STOP_F_G = 32 accepted, unknown bits and both compared guesses rejected) and the level-dependent
     tolerance's order (0 <= p <= 16)."""
@@ -201,11 +202,11 @@ def test_bandwidth_probe_argument_errors(abi):
 
     L = abi.lib()
     rates = (ctypes.c_double * len(ex.PROBE_KINDS))()
-    assert L.excmg_bandwidth_probe(None, 1 << 20, 1, None, rates) == abi.ERR_ARG
-    assert L.excmg_bandwidth_probe(ctypes.c_void_p(16), 1024, 1, None, rates) == abi.ERR_ARG  # too few bytes
-    assert L.excmg_bandwidth_probe(ctypes.c_void_p(8), 1 << 20, 1, None, rates) == abi.ERR_ARG  # misaligned
-    assert L.excmg_bandwidth_probe(ctypes.c_void_p(16), 1 << 20, 0, None, rates) == abi.ERR_ARG  # no reps
-    assert L.excmg_bandwidth_probe(ctypes.c_void_p(16), 1 << 20, 1, None, None) == abi.ERR_ARG  # no output
+    assert L.excmg_bandwidth_probe(None, 1 << 20, 1, None, rates, None) == abi.ERR_ARG
+    assert L.excmg_bandwidth_probe(ctypes.c_void_p(16), 1024, 1, None, rates, None) == abi.ERR_ARG  # too few bytes
+    assert L.excmg_bandwidth_probe(ctypes.c_void_p(8), 1 << 20, 1, None, rates, None) == abi.ERR_ARG  # misaligned
+    assert L.excmg_bandwidth_probe(ctypes.c_void_p(16), 1 << 20, 0, None, rates, None) == abi.ERR_ARG  # no reps
+    assert L.excmg_bandwidth_probe(ctypes.c_void_p(16), 1 << 20, 1, None, None, None) == abi.ERR_ARG  # no output
     src = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
     assert int(re.search(r"EXCMG_PROBE_KINDS\s*=\s*(\d+)", src).group(1)) == len(ex.PROBE_KINDS)
 

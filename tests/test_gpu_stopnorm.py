@@ -59,6 +59,32 @@ def true_residual(ex, u, f, g, n, box):
     return float(torch.linalg.vector_norm(r))
 
 
+@pytest.mark.parametrize("case", ["ex3-64", "ex2-128", "ex4-aniso", "ex6-ragged"])
+def test_fg_below_finest_solve_parity(ex, orc, case):
+    """The third reading (EXCMG_STOP_F_G_BELOW_FINEST: (R f, g) below the finest grid, b on it) against the oracle's
+    stop_norm "fg_coarse" at matched iteration counts; the grids below the finest iterate as under the second
+    reading, and the finest stops on the default test."""
+    e, n, nc, tol = {
+        "ex3-64": (3, (64, 64, 64), (4, 4, 4), 1e-11),
+        "ex2-128": (2, (128, 128, 128), (4, 4, 4), 1e-14),
+        "ex4-aniso": (4, (128, 64, 32), (8, 4, 2), 1e-9),
+        "ex6-ragged": (6, (80, 48, 48), (10, 6, 6), 1e-13),
+    }[case]
+    p = synth.example(e)
+    f, g, _ = synth.sample(p, n)
+    s = ex.Solver(n, p.box, tol, n_coarse=nc, stop_norm="fg_coarse")
+    ug, _, st = s.solve(dev(f), dev(g))
+    ug = host(ug)
+    free = orc.excmg_guess("quartic", f, g, p.box, s.n_coarse, tol, stop_norm="fg_coarse")
+    gi = np.array(st["iters"], dtype=np.int32)
+    assert np.all(np.abs(gi - free["iters"]) <= 1), (gi, free["iters"])
+    ref = orc.excmg_guess("quartic", f, g, p.box, s.n_coarse, tol, fixed_iters=gi, stop_norm="fg_coarse")
+    assert rel2(ug, ref["u"]) <= 1e-12
+    fg = orc.excmg_guess("quartic", f, g, p.box, s.n_coarse, tol, stop_norm="fg")
+    assert np.all(np.abs(gi[:-1] - fg["iters"][:-1]) <= 1), (gi, fg["iters"])
+    assert st["relres"][-1] <= tol  # the default test on the finest grid
+
+
 @pytest.mark.parametrize("case", ["ex1-32", "ex1-64", "ex4-aniso", "ex5-ragged"])
 def test_fg_solve_parity(ex, orc, case):
     e, n, nc, tol = {

@@ -4,12 +4,13 @@ for EXCMG in its comparison with V- and W-cycles (CG smoother).
 
 Tolerances are those of the oracle's pins of the same rows (tests/test_oracle.py): max-norm columns to 2% (u, grad)
 and 6% (ext, w); L2 columns of u, grad, ext to 2% with the L2 norm read as the RMS over all nodes; the L2 column of
-w_h - u_h within 30% (it follows no convention found); entries the uniform CG tolerance limits are listed but not
-pinned.  Entries marked '~' are set by the algebraic error the solves stop with and are pinned with the stopping test's
-norm read as that of (R f inside, g on the boundary) (EXCMG_STOP_F_G); those marked '?' are matched by neither reading
-and are listed only.  w_h is the finest grid's initial guess: EXP_finite of the solutions on the grids n/2 and n/4, which are the
-cascade's own grids (the level data are the finest data sampled at strides 2 and 4), solved here as problems of their
-own.
+w_h - u_h within 30% (it follows no convention found).  Each example's table is read as the grids of one run to its
+finest mesh, with the stopping test's norm that of (R f inside, g on the boundary) on every grid below the finest and
+that of the eliminated right-hand side on the finest (EXCMG_STOP_F_G_BELOW_FINEST): rows at the finest mesh come
+from that run, rows below it from runs to their mesh with the (R f, g) norm on every grid (EXCMG_STOP_F_G), which
+is the same cascade stopped early.  Entries marked 'x' are not reproduced by this reading and are listed only.
+w_h is the finest grid's initial guess: EXP_finite of the solutions on the grids n/2 and n/4, which are the cascade's
+own grids (the level data are the finest data sampled at strides 2 and 4), solved here as problems of their own.
 """
 import os
 
@@ -47,10 +48,18 @@ def table_rows():
         if not line.strip() or line.startswith("#"):
             continue
         e, mesh, tol, norm, qty, val = line.split()
-        mark = val[-1] if val[-1] in "*~?" else ""
         rows.append((int(e), tuple(int(v) for v in mesh.split(",")), float(tol), norm, qty,
-                     float(val.rstrip("*~?")), mark))
+                     float(val.rstrip("x")), val.endswith("x")))
     return rows
+
+
+def finest_mesh(e, tol):
+    """The largest mesh of example e's table (the finest grid of the run the table lists)."""
+    return max((r[1] for r in table_rows() if r[0] == e and r[2] == tol), key=lambda n: n[0] * n[1] * n[2])
+
+
+def reading(e, n, tol):
+    return "fg_coarse" if n == finest_mesh(e, tol) else "fg"
 
 
 def coarsest(e):
@@ -71,9 +80,9 @@ def run_case(ex, e, n, tol, stop_norm="b"):
     ug, ueg, st = s.solve(fd, gd, want_ext=True)
     grads = [host(t) for t in s.gradient(ug)]
     sub = {}
-    for q in (2, 4):
+    for q in (2, 4):  # grids below the finest: the (R f, g) norm under either reading the table uses
         m = tuple(v // q for v in n)
-        sq = ex.Solver(m, p.box, tol, n_coarse=coarsest(e), stop_norm=stop_norm)
+        sq = ex.Solver(m, p.box, tol, n_coarse=coarsest(e), stop_norm="fg" if stop_norm != "b" else "b")
         sub[q], _, _ = sq.solve(fd[::q, ::q, ::q].contiguous(), gd[::q, ::q, ::q].contiguous())
         del sq
     w = host(ex.op_initial_guess("quartic", sub[2], sub[4], gd, n))
@@ -99,12 +108,10 @@ def run_case(ex, e, n, tol, stop_norm="b"):
 
 @pytest.mark.parametrize("row", table_rows(), ids=lambda r: f"ex{r[0]}-{'x'.join(map(str, r[1]))}-{r[3]}-{r[4]}")
 def test_paper_tables_on_gpu(ex, row):
-    e, n, tol, norm, qty, val, limited = row
-    if limited == "?":
-        pytest.skip("entry set by the algebraic error and reproduced by neither reading of the stopping norm")
-    got = run_case(ex, e, n, tol, "fg" if limited == "~" else "b")[(norm, qty)]
-    if limited == "*":
-        pytest.skip("entry limited by the uniform CG tolerance (the paper's own remark in Section 5.1)")
+    e, n, tol, norm, qty, val, unmatched = row
+    if unmatched:
+        pytest.skip("entry not reproduced by the reading (listed in the golden file)")
+    got = run_case(ex, e, n, tol, reading(e, n, tol))[(norm, qty)]
     if norm == "l2" and qty == "w":
         assert 0.7 * val < got < 1.3 * val, (got, val)
         return
@@ -126,10 +133,11 @@ def iteration_rows():
 @pytest.mark.parametrize("row", iteration_rows(), ids=lambda r: f"ex{r[0]}")
 def test_paper_finest_iterations(ex, row):
     """The finest grid's CG iterations, within one of the printed count (several iterates meet the stopping test
-    near the threshold, as in the parity tests).  Example 6, whose solution has low regularity, needs 16 here against
-    the printed 9; no reading of the stopping test found reproduces both that count and the other examples'."""
+    near the threshold, as in the parity tests), under the reading of the tables: the same counts as the default
+    reading for Examples 1-5.  Example 6, whose solution has low regularity, needs 13 here (16 under the default
+    reading) against the printed 9."""
     e, n, tol, its, unmatched = row
-    got = run_case(ex, e, n, tol)["iters"][-1]
+    got = run_case(ex, e, n, tol, "fg_coarse")["iters"][-1]
     if unmatched:
         pytest.skip(f"count not reproduced: {got} here against {its} printed")
     assert abs(got - its) <= 1, (got, its)
