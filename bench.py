@@ -205,6 +205,7 @@ def bench_batch(ex, synth, torch, args):
             "gunknown_iters_per_s": round(ui / (ms * 1e-3) / 1e9, 3),
             "one_at_a_time_ms": round(seq_ms, 3), "speedup_vs_one_at_a_time": round(seq_ms / ms, 2),
             "batch_ms_default_chunks": round(ms_default, 3), "autotune_s": round(tune_s, 2),
+            "round_graphs_replayed_captured": list(solvers[0].batch_graph_counts()),
             "autotuned_z_chunks_fp64_fp32_by_grid_from_finest": {str(k): list(v) for k, v in zc.items()}}
 
 

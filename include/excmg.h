@@ -209,6 +209,13 @@ int excmg_solve_batched(excmg_handle *const *hs, int32_t count, const double *co
                         double *const *u, void *batch_ws, size_t batch_bytes, excmg_stats *stats,
                         double *ms_per_problem);
 
+/* Host only.  Batched solves run the CG iterations of each round as a graph: replayed from a cache on the batch's
+ * first handle when a round has the launch shape of an earlier one (the same batch workspace, iteration counts and,
+ * per launch, numbers of problems and workgroups; which problems a launch covers is read from the workspace when it
+ * runs), else captured and instantiated (1024 are kept, the least recently used dropped first; EXCMG_NO_GRAPHS on
+ * that handle launches them directly).  replays, captures (host): the graphs replayed and captured on h so far. */
+int excmg_batch_graph_counts(const excmg_handle *h, int64_t *replays, int64_t *captures);
+
 /* Autotuner of excmg_solve_batched for a batch of handles (host call, device work on the stream of hs[0]; the same
  * conditions on the handles as excmg_solve_batched).  In a batched launch the workgroups of all the problems concerned
  * run together, so the z chunk a problem prefers alone is not the one the batch prefers.  For each grid counted from

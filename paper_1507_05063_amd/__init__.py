@@ -168,6 +168,13 @@ class Solver:
             return z, [tuple(dp[4 * l: 4 * l + 4]) for l in range(self.levels)]
         return z
 
+    def batch_graph_counts(self):
+        """(replays, captures) of the batched-round graphs cached on this solver's handle (batches it leads)."""
+        r, c = ctypes.c_int64(0), ctypes.c_int64(0)
+        _lib.check(_lib.lib().excmg_batch_graph_counts(self._h, ctypes.byref(r), ctypes.byref(c)),
+                   "excmg_batch_graph_counts")
+        return r.value, c.value
+
     def set_timing(self, on: bool):
         """Kernel timing (stats kernel_ms, kernel_calls) on or off for later calls."""
         _lib.check(_lib.lib().excmg_set_timing(self._h, 1 if on else 0), "excmg_set_timing")

@@ -113,6 +113,7 @@ def lib():
                                      ctypes.POINTER(_P), _P, ctypes.c_size_t, ctypes.POINTER(Stats),
                                      ctypes.POINTER(ctypes.c_double)], _I),
             "excmg_autotune_batched": ([ctypes.POINTER(_P), ctypes.c_int32, _P, ctypes.c_size_t, _I32P], _I),
+            "excmg_batch_graph_counts": ([_P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)], _I),
             "excmg_destroy": ([_P], None),
             "excmg_set_timing": ([_P, ctypes.c_int32], _I),
             "excmg_solve_noalloc": ([ctypes.POINTER(Problem), _P, _P, _P, _P, _P, ctypes.POINTER(Stats)], _I),

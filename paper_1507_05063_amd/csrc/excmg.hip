@@ -225,6 +225,14 @@ struct excmg_handle {
   // a handle of excmg_solve_noalloc: no events, graphs, capture stream or pinned memory; CG states are read back with
   // plain stream copies
   bool noalloc = false;
+  // graphs of a batched round's CG iterations (excmg_solve_batched, on the batch's first handle), by launch shape
+  struct BatchGraph {
+    std::vector<long long> key;
+    hipGraphExec_t ex;
+    long long used;  // the count of lookups when last used (the least recently used goes first)
+  };
+  std::vector<BatchGraph> bgraphs;
+  long long bgraph_hits = 0, bgraph_misses = 0;
 
   void drop_graphs() {
     for (auto &row : gexec)
@@ -233,6 +241,8 @@ struct excmg_handle {
           (void)hipGraphExecDestroy(ex);
           ex = nullptr;
         }
+    for (auto &bg : bgraphs) (void)hipGraphExecDestroy(bg.ex);
+    bgraphs.clear();
   }
 
   ~excmg_handle() {
@@ -875,6 +885,58 @@ void batch_entry(excmg_handle *h, int problem, int l, const double *f, const dou
 // a problem's place in its cascade
 enum BatchPhase { kPhStart, kPhSmall, kPhIter64, kPhIter32, kPhOuter, kPhCopy, kPhDone };
 
+// A round's CG iterations: it rounds of one iteration of the FP64 entries (the first nb64 rounds) and of the FP32 inner
+// solves (the first nb32), in a graph replayed from the first handle's cache when the round has the launch shape of
+// an earlier one (the same workspace, iteration counts and, per list, numbers of entries and workgroups; the lists
+// themselves are read from the batch workspace when the kernels run), else captured and instantiated; directly
+// launched under EXCMG_NO_GRAPHS or for a single iteration.
+constexpr size_t kBatchGraphCache = 1024;
+
+int batch_iterations(excmg_handle *h0, const char *ws, int it, int nb64, int nb32, const BatchList (&l64)[2],
+                     const BatchList (&l32)[2], BatchStatus *stat) {
+  const hipStream_t s = h0->stream;
+  auto launch_all = [&](hipStream_t st) {
+    for (int q = 0; q < it; ++q) {
+      if (q < nb64) launch_b_iteration(0, l64[0], l64[1], stat, st);
+      if (q < nb32) launch_b_iteration(1, l32[0], l32[1], stat, st);
+    }
+  };
+  if (it <= 1 || (h0->p.flags & EXCMG_NO_GRAPHS) || h0->noalloc) {
+    launch_all(s);
+    return last_error();
+  }
+  const std::vector<long long> key = {(long long)(uintptr_t)ws, it, nb64, nb32, l64[0].n, l64[0].total, l64[1].total,
+                                      l32[0].n, l32[0].total, l32[1].total};
+  const long long now = h0->bgraph_hits + h0->bgraph_misses;
+  for (auto &bg : h0->bgraphs)
+    if (bg.key == key) {
+      ++h0->bgraph_hits;
+      bg.used = now;
+      HIPCHECK(hipGraphLaunch(bg.ex, s));
+      return EXCMG_OK;
+    }
+  ++h0->bgraph_misses;
+  hipGraph_t gr = nullptr;
+  HIPCHECK(hipStreamBeginCapture(h0->cap, hipStreamCaptureModeThreadLocal));
+  launch_all(h0->cap);
+  const hipError_t ec = hipStreamEndCapture(h0->cap, &gr);
+  if (ec != hipSuccess) return EXCMG_ERR_HIP;
+  hipGraphExec_t ex = nullptr;
+  const hipError_t ei = hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(gr);
+  if (ei != hipSuccess) return EXCMG_ERR_HIP;
+  if (h0->bgraphs.size() >= kBatchGraphCache) {  // the least recently used goes
+    size_t lru = 0;
+    for (size_t q = 1; q < h0->bgraphs.size(); ++q)
+      if (h0->bgraphs[q].used < h0->bgraphs[lru].used) lru = q;
+    (void)hipGraphExecDestroy(h0->bgraphs[lru].ex);
+    h0->bgraphs.erase(h0->bgraphs.begin() + (long)lru);
+  }
+  h0->bgraphs.push_back({key, ex, now});
+  HIPCHECK(hipGraphLaunch(ex, s));
+  return EXCMG_OK;
+}
+
 int batched_solve(excmg_handle *const *hs, int count, const double *const *f, const double *const *g,
                   double *const *u, char *ws, excmg_stats *stats, double *ms_per_problem) {
   const hipStream_t s = hs[0]->stream;
@@ -1048,10 +1110,7 @@ int batched_solve(excmg_handle *const *hs, int count, const double *const *f, co
     launch_b_add_correction(dl[kListCorr][0], s);
     launch_b_residual_cast(dl[kListRC][0], stat, s);
     const int it = hl[kListI64].n || hl[kListI32].n ? (nb64 > nb32 ? nb64 : nb32) : 0;
-    for (int q = 0; q < it; ++q) {
-      if (q < nb64) launch_b_iteration(0, dl[kListI64][0], dl[kListI64][1], stat, s);
-      if (q < nb32) launch_b_iteration(1, dl[kListI32][0], dl[kListI32][1], stat, s);
-    }
+    if ((e = batch_iterations(hs[0], ws, it, nb64, nb32, dl[kListI64], dl[kListI32], stat))) return e;
     if ((e = last_error()) || (e = read_stat())) return e;
     // move every problem on, and size the next round's iteration batches from the residual decay seen so far
     nb64 = nb32 = 1;
@@ -1517,6 +1576,13 @@ int excmg_autotune(excmg_handle *h, int32_t *zc_out, int32_t *depth_out) {
       depth_out[4 * l + 3] = ir ? lv.swB32.depth + 10 * lv.swB32.nt : 0;
     }
   }
+  return EXCMG_OK;
+}
+
+int excmg_batch_graph_counts(const excmg_handle *h, int64_t *replays, int64_t *captures) {
+  if (!h || !replays || !captures) return EXCMG_ERR_ARG;
+  *replays = h->bgraph_hits;
+  *captures = h->bgraph_misses;
   return EXCMG_OK;
 }
 

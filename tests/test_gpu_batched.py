@@ -113,6 +113,34 @@ def test_batched_autotune_keeps_results(ex, orc):
         assert rel2(host(ub), ref["u"]) <= 1e-12, n
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32_ir"])
+def test_batched_graphs_match_direct_launches(ex, precision):
+    """The CG iterations of each batched round run as graphs cached on the first handle; the same batch with every
+    launch made directly (EXCMG_NO_GRAPHS on the first handle) must agree bit for bit, on every one of several calls
+    (later calls replay cached graphs) with other device work in between."""
+    prec = ex.FP64 if precision == "fp64" else ex.FP32_IR
+    cases = MIXED if precision == "fp64" else [((128, 128, 128), (4, 4, 4), synth.smooth(2)), MIXED[1], MIXED[6]]
+    fs, gs, graph, eager = [], [], [], []
+    for n, nc, p in cases:
+        f, g, _ = synth.sample(p, n)
+        fs.append(dev(f))
+        gs.append(dev(g))
+        graph.append(ex.Solver(n, p.box, 1e-10, n_coarse=nc, precision=prec))
+        eager.append(ex.Solver(n, p.box, 1e-10, n_coarse=nc, precision=prec, graphs=False))
+    ref, st_ref, _ = ex.solve_batched(eager, fs, gs)
+    assert eager[0].batch_graph_counts() == (0, 0)
+    x = dev(np.random.default_rng(1).standard_normal((17, 17, 17)))
+    for rep in range(3):
+        us, st, _ = ex.solve_batched(graph, fs, gs)
+        assert [a["iters"] for a in st] == [a["iters"] for a in st_ref], rep
+        for a, b in zip(us, ref):
+            assert torch.equal(a, b), rep
+        ex.op_apply(x, (16, 16, 16))  # unrelated eager work between the calls
+        torch.cuda.synchronize()
+    replays, captures = graph[0].batch_graph_counts()
+    assert captures >= 1 and replays >= 1, (replays, captures)
+
+
 def test_batched_rejects_bad_workspace(ex):
     solvers, fs, gs, data, us, stats, ms = _run(ex, MIXED[3:4], 1e-10, ex.FP64)
     small = torch.empty(64, dtype=torch.uint8, device="cuda")
