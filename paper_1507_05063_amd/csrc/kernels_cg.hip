@@ -412,24 +412,32 @@ __device__ __forceinline__ CgBufs<T> cg_bufs(int k, T *R, T *P0, T *P1) {
   return b;
 }
 
-template <typename T, bool NTP = false>
+// FIRST: iteration 0, where p = r: the operand is r alone (one load per node) and p is not stored.
+template <typename T, bool NTP = false, bool FIRST = false>
 struct PolA {
   static constexpr bool kRhs = false;
   const T *r;
   const T *pold;
   T *pnew;
   T beta;
-  bool first;  // p = r; pold then points at r (a cache hit, and no branch around the load), and p is not stored
-  struct Raw {
+  struct Pair {
     T r, p;
   };
+  using Raw = std::conditional_t<FIRST, T, Pair>;
   __device__ __forceinline__ Raw operand(long long idx) const {
-    Raw v;
-    v.r = r[idx];
-    v.p = pold[idx];
-    return v;
+    if constexpr (FIRST) {
+      return r[idx];
+    } else {
+      Pair v;
+      v.r = r[idx];
+      v.p = pold[idx];
+      return v;
+    }
   }
-  __device__ __forceinline__ T value(const Raw &v) const { return first ? v.r : v.r + beta * v.p; }
+  __device__ __forceinline__ T value(const Raw &v) const {
+    if constexpr (FIRST) return v;
+    else return v.r + beta * v.p;
+  }
   __device__ __forceinline__ long long fcol(int, int) const { return -1; }
   __device__ __forceinline__ long long fplane() const { return 0; }
   __device__ __forceinline__ double fval(long long) const { return 0.0; }
@@ -438,10 +446,32 @@ struct PolA {
   template <int S>
   __device__ __forceinline__ void consume(int, int, int, long long idx, T c, T out, double, double, double &acc0,
                                           double &) {
-    if (!first) st1<NTP>(c, &pnew[idx]);
+    if constexpr (!FIRST) st1<NTP>(c, &pnew[idx]);
     acc0 += (double)c * (double)out;
   }
 };
+
+// pass A's z-march of iteration it: the first iteration's form (r alone) or the general one
+template <typename T, int D, bool NTP>
+__device__ __forceinline__ void pass_a_march(const Sweep &sw, int it, const CgBufs<T> &bf, T beta, double &a0,
+                                             T (*tile)[kTileRows][TX + 2], int bid, int nb, bool remap) {
+  double a1 = 0.0;
+  if (it == 0) {
+    PolA<T, NTP, true> pol;
+    pol.r = bf.r_in;
+    pol.pold = bf.r_in;
+    pol.pnew = bf.p;
+    pol.beta = T(0);
+    zmarch<T, D>(sw, pol, a0, a1, tile, nullptr, bid, nb, remap);
+  } else {
+    PolA<T, NTP, false> pol;
+    pol.r = bf.r_in;
+    pol.pold = bf.p_old;
+    pol.pnew = bf.p;
+    pol.beta = beta;
+    zmarch<T, D>(sw, pol, a0, a1, tile, nullptr, bid, nb, remap);
+  }
+}
 
 template <typename T, int D, bool NTP>
 __global__ __launch_bounds__(NT) void cg_pass_a_kernel(Sweep sw, T *r, T *p0, T *p1,
@@ -451,19 +481,14 @@ __global__ __launch_bounds__(NT) void cg_pass_a_kernel(Sweep sw, T *r, T *p0, T 
   if (cs->done) return;
   const int it = cs->iter;
   const CgBufs<T> bf = cg_bufs(it, r, p0, p1);
-  PolA<T, NTP> pol;
-  pol.r = bf.r_in;
-  pol.pnew = bf.p;
-  pol.first = (it == 0);
-  pol.pold = bf.p_old;
-  pol.beta = (T)cs->beta;
-  double a0 = 0.0, a1 = 0.0;
-  zmarch<T, D>(sw, pol, a0, a1, tile, nullptr, blockIdx.x, gridDim.x, true);
+  double a0 = 0.0;
+  pass_a_march<T, D, NTP>(sw, it, bf, (T)cs->beta, a0, tile, blockIdx.x, gridDim.x, true);
   const double v[1] = {a0};
   write_partials<1>(v, partials, sh, blockIdx.x, gridDim.x);
 }
 
-template <typename T, bool NTP = false>
+// FIRST: iteration 0, where p and r are the same array: r at the node is the staged operand's centre, not loaded again.
+template <typename T, bool NTP = false, bool FIRST = false>
 struct PolB {
   static constexpr bool kRhs = false;
   const T *p;
@@ -481,18 +506,37 @@ struct PolB {
   template <int S>
   __device__ __forceinline__ void center(int, int, int, long long idx) {
     static_assert(S < kMaxDepth, "centre slot");
-    pr[S] = ld1<NTP>(&rin[idx]);
+    if constexpr (!FIRST) pr[S] = ld1<NTP>(&rin[idx]);
     pu[S] = ld1<NTP>(&u[idx]);
   }
   template <int S>
   __device__ __forceinline__ void consume(int, int, int, long long idx, T c, T out, double, double, double &acc0,
                                           double &) {
-    const T rn = pr[S] - alpha * out;
+    const T rn = (FIRST ? c : pr[S]) - alpha * out;
     st1<NTP>(rn, &rout[idx]);
     st1<NTP>(pu[S] + alpha * c, &u[idx]);
     acc0 += (double)rn * (double)rn;
   }
 };
+
+// pass B's z-march of iteration it (u: the solution, or the correction of an inner FP32 solve)
+template <typename T, int D, bool NTP>
+__device__ __forceinline__ void pass_b_march(const Sweep &sw, int it, const CgBufs<T> &bf, T *u, T alpha, double &a0,
+                                             T (*tile)[kTileRows][TX + 2], int bid, int nb, bool remap) {
+  double a1 = 0.0;
+  auto go = [&](auto first) {
+    PolB<T, NTP, decltype(first)::value> pol;
+    pol.p = bf.p;
+    pol.u = u;
+    pol.rin = bf.r_in;
+    pol.rout = bf.r_out;
+    pol.alpha = alpha;
+    for (int q = 0; q < kMaxDepth; ++q) pol.pr[q] = pol.pu[q] = 0;
+    zmarch<T, D>(sw, pol, a0, a1, tile, nullptr, bid, nb, remap);
+  };
+  if (it == 0) go(std::true_type{});
+  else go(std::false_type{});
+}
 
 template <typename T, int D, bool NTP>
 __global__ __launch_bounds__(NT) void cg_pass_b_kernel(Sweep sw, T *u, T *r, T *p0, T *p1,
@@ -502,15 +546,8 @@ __global__ __launch_bounds__(NT) void cg_pass_b_kernel(Sweep sw, T *u, T *r, T *
   if (cs->done) return;
   const int it = cs->iter;
   const CgBufs<T> bf = cg_bufs(it, r, p0, p1);
-  PolB<T, NTP> pol;
-  pol.p = bf.p;
-  pol.u = u;
-  pol.rin = bf.r_in;
-  pol.rout = bf.r_out;
-  pol.alpha = (T)cs->alpha;
-  for (int q = 0; q < kMaxDepth; ++q) pol.pr[q] = pol.pu[q] = 0;
-  double a0 = 0.0, a1 = 0.0;
-  zmarch<T, D>(sw, pol, a0, a1, tile, nullptr, blockIdx.x, gridDim.x, true);
+  double a0 = 0.0;
+  pass_b_march<T, D, NTP>(sw, it, bf, u, (T)cs->alpha, a0, tile, blockIdx.x, gridDim.x, true);
   const double v[1] = {a0};
   write_partials<1>(v, partials, sh, blockIdx.x, gridDim.x);
 }
@@ -601,14 +638,9 @@ __global__ __launch_bounds__(NT) void cg_selfred_a_kernel(Sweep sw, T *r, T *p0,
   }
   if (!finite || conv || cap) return;
   const CgBufs<T> bf = cg_bufs(k, r, p0, p1);
-  PolA<T, NTP> pol;
-  pol.r = bf.r_in;
-  pol.pnew = bf.p;
-  pol.first = (k == 0);
-  pol.pold = bf.p_old;
-  pol.beta = (k == 0) ? T(0) : (T)(rho / cs->rhoA[(k - 1) & 1]);
-  double a0 = 0.0, a1 = 0.0;
-  zmarch<T, D>(sw, pol, a0, a1, tile, nullptr, blockIdx.x, gridDim.x, true);
+  double a0 = 0.0;
+  pass_a_march<T, D, NTP>(sw, k, bf, (k == 0) ? T(0) : (T)(rho / cs->rhoA[(k - 1) & 1]), a0, tile, blockIdx.x,
+                          gridDim.x, true);
   const double v[1] = {a0};
   write_partials<1>(v, partsA, sh, blockIdx.x, gridDim.x);
 }
@@ -636,15 +668,8 @@ __global__ __launch_bounds__(NT) void cg_selfred_b_kernel(Sweep sw, T *u, T *r, 
   }
   if (bad) return;
   const CgBufs<T> bf = cg_bufs(k, r, p0, p1);
-  PolB<T, NTP> pol;
-  pol.p = bf.p;
-  pol.u = u;
-  pol.rin = bf.r_in;
-  pol.rout = bf.r_out;
-  pol.alpha = (T)(cs->rhoA[k & 1] / pq);
-  for (int q = 0; q < kMaxDepth; ++q) pol.pr[q] = pol.pu[q] = 0;
-  double a0 = 0.0, a1 = 0.0;
-  zmarch<T, D>(sw, pol, a0, a1, tile, nullptr, blockIdx.x, gridDim.x, true);
+  double a0 = 0.0;
+  pass_b_march<T, D, NTP>(sw, k, bf, u, (T)(cs->rhoA[k & 1] / pq), a0, tile, blockIdx.x, gridDim.x, true);
   const double v[1] = {a0};
   write_partials<1>(v, partsB, sh, blockIdx.x, gridDim.x);
 }
@@ -1438,15 +1463,10 @@ __global__ __launch_bounds__(NT) void b_pass_a_kernel(BatchList L) {
     r = E.r; p0 = E.p0; p1 = E.p1;
   }
   const CgBufs<T> bf = cg_bufs(it, r, p0, p1);
-  PolA<T, true> pol;  // the batch's working set is far larger than the caches: streaming policy
-  pol.r = bf.r_in;
-  pol.pnew = bf.p;
-  pol.first = (it == 0);
-  pol.pold = bf.p_old;
-  pol.beta = (T)cs->beta;
   const Sweep sw = F ? E.swA32 : E.swA;
-  double a0 = 0.0, a1 = 0.0;
-  zmarch<T>(sw, pol, a0, a1, tile, nullptr, bid, nb, false);
+  double a0 = 0.0;
+  // the batch's working set is far larger than the caches: streaming policy
+  pass_a_march<T, 2, true>(sw, it, bf, (T)cs->beta, a0, tile, bid, nb, false);
   const double v[1] = {a0};
   write_partials<1>(v, E.parts, sh, bid, nb);
 }
@@ -1462,24 +1482,18 @@ __global__ __launch_bounds__(NT) void b_pass_b_kernel(BatchList L) {
   if (cs->done) return;
   const int bid = blockIdx.x - L.pre[e], nb = L.pre[e + 1] - L.pre[e];
   const int it = cs->iter;
-  PolB<T, true> pol;
-  T *p0, *p1, *r;
+  T *p0, *p1, *r, *uu;
   if constexpr (F) {
     r = E.r32; p0 = E.p32a; p1 = E.p32b;
-    pol.u = E.d32;
+    uu = E.d32;
   } else {
     r = E.r; p0 = E.p0; p1 = E.p1;
-    pol.u = E.u;
+    uu = E.u;
   }
   const CgBufs<T> bf = cg_bufs(it, r, p0, p1);
-  pol.p = bf.p;
-  pol.rin = bf.r_in;
-  pol.rout = bf.r_out;
-  pol.alpha = (T)cs->alpha;
-  for (int q = 0; q < kMaxDepth; ++q) pol.pr[q] = pol.pu[q] = 0;
   const Sweep sw = F ? E.swB32 : E.swB;
-  double a0 = 0.0, a1 = 0.0;
-  zmarch<T>(sw, pol, a0, a1, tile, nullptr, bid, nb, false);
+  double a0 = 0.0;
+  pass_b_march<T, 2, true>(sw, it, bf, uu, (T)cs->alpha, a0, tile, bid, nb, false);
   const double v[1] = {a0};
   write_partials<1>(v, E.parts, sh, bid, nb);
 }
