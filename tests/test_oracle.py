@@ -502,14 +502,16 @@ def _table_rows(max_cells=64 ** 3, min_cells=0):
 _CACHE = {}
 
 
-def _run(orc, ex, n, tol, stop_norm):
-    """Errors of one cascade to mesh n: u_h, its compact gradient, u~_h and the finest grid's initial guess w_h."""
-    key = (ex, n, tol, stop_norm)
+def _run(orc, ex, n, tol, stop_norm, fixed_iters=None):
+    """Errors of one cascade to mesh n: u_h, its compact gradient, u~_h and the finest grid's initial guess w_h
+    (fixed_iters: CG iterations per grid instead of the stopping test)."""
+    key = (ex, n, tol, stop_norm, None if fixed_iters is None else tuple(fixed_iters))
     if key not in _CACHE:
         p = synth.example(ex)
         f, g, u = synth.sample(p, n)
         nc = (8, 4, 2) if ex == 4 else (4, 4, 4)
-        r = orc.excmg_guess("quartic", f, g, p.box, nc, tol, stop_norm=stop_norm, want_ext=True)
+        r = orc.excmg_guess("quartic", f, g, p.box, nc, tol, stop_norm=stop_norm, want_ext=True,
+                            fixed_iters=fixed_iters)
         grad = orc.gradient(r["u"], p.box)
         gex = synth.exact_gradient(p, n)
         rms = lambda e: float(np.sqrt(np.mean(e * e)))
@@ -523,6 +525,7 @@ def _run(orc, ex, n, tol, stop_norm):
             ("l2", "ext"): rms(r["ut"] - u),
             ("l2", "w"): rms(r["w"] - r["u"]),
             "iters": list(r["iters"]),
+            "relres": float(r["relres"][-1]),
         }
         _CACHE.clear()  # one case at a time (the rows are grouped by case)
         _CACHE[key] = out
@@ -564,6 +567,31 @@ def test_paper_tables_finest_grid_example3(orc):
         assert not unmatched
         _check_row(got[(norm, qty)], norm, qty, val)
     assert got["iters"][-1] == 8
+
+
+def test_paper_tables_example4_finest_meshes(orc):
+    """Example 4 (unequal meshsizes, coarsest 8x4x2, eps 1e-9) on its two finest meshes, 256x128x64 and 512x256x128,
+    whose u_h and u~_h entries the reading above misses: every printed entry of both meshes is reproduced by a
+    cascade whose grids below the finest stop at eps/100 on the default norm (the eliminated right-hand side) and
+    whose finest grid stops at eps on it, with the printed count of 8 finest-grid CG iterations.  The 256x128x64 rows
+    are the finest grid of that cascade run at eps/100.  The 512x256x128 run holds each coarser grid to the
+    iteration counts of that run (the same solves) and takes the finest grid's count k from its relative residual:
+    above eps after k - 1 iterations, at most eps after k."""
+    eps = 1e-9
+    rows = [r for r in _table_rows(512 * 256 * 128, 128 * 64 * 32) if r[0] == 4]
+    assert len(rows) == 16
+    mid = _run(orc, 4, (256, 128, 64), eps / 100, "b")
+    for _, n, _, norm, qty, val, _ in rows:
+        if n == (256, 128, 64):
+            _check_row(mid[(norm, qty)], norm, qty, val)
+    coarse = [int(v) for v in mid["iters"]]
+    fine = (512, 256, 128)
+    assert _run(orc, 4, fine, eps, "b", coarse + [7])["relres"] > eps
+    got = _run(orc, 4, fine, eps, "b", coarse + [8])
+    assert got["relres"] <= eps
+    for _, n, _, norm, qty, val, _ in rows:
+        if n == fine:
+            _check_row(got[(norm, qty)], norm, qty, val)
 
 
 def test_level_tolerance_schedule(orc):
