@@ -15,6 +15,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <chrono>
 #include <mutex>
 #include <new>
@@ -1452,6 +1453,11 @@ int solve_on(excmg_handle *h, const double *f, const double *g, double *u, doubl
 
 }  // namespace
 
+// launches per trial of a self-finalizing pass, and the delay they are queued behind (longer than it takes the host
+// to queue them)
+constexpr int kTuneBurst = 8;
+constexpr double kTuneDelayUs = 300.0;
+
 extern "C" {
 
 int excmg_gradient(excmg_handle *h, const double *u, double *ux, double *uy, double *uz) {
@@ -1506,38 +1512,63 @@ int excmg_autotune(excmg_handle *h, int32_t *zc_out, int32_t *depth_out) {
   HIPCHECK(hipEventCreateWithFlags(&ea, kTimingEvent));
   HIPCHECK(hipEventCreateWithFlags(&eb, kTimingEvent));
   int rc = EXCMG_OK;
+  double *pa = h->partials, *pb = h->partials + lo.npart;
   for (int l = 0; l < lo.L && rc == EXCMG_OK; ++l) {
     Level &lv = lo.lev[l];
     if (!swept(lo, l)) continue;  // solved by the single-workgroup kernel
     const bool ir = l >= 2 && (h->p.precision == EXCMG_FP32_IR) && lv.g.interior() >= kIrMinUnknowns;
+    // A grid whose iterations run as graphs of self-finalizing passes is tuned on those kernels, with the shapes that
+    // keep it self-finalizing; their launches are short, so each trial times a burst of them queued behind a delay
+    // (back to back, as in a graph) instead of one launch between two events, whose own cost would hide the kernel.
+    const bool burst = use_graphs(h, l) && sweep_blocks(lv.sw) <= selfred_max_blocks();
     for (int prec = 0; prec < (ir ? 2 : 1) && rc == EXCMG_OK; ++prec) {
       const Grid &g = prec ? lv.g32 : lv.g;
       for (int pass = 0; pass < 2 && rc == EXCMG_OK; ++pass) {
         float best = 1e30f;
         Sweep bsw = prec ? (pass ? lv.swB32 : lv.swA32) : (pass ? lv.swB : lv.swA);
+        // partial sums the trial pass reads: as many as the other pass's current shape writes (at most the
+        // self-finalizing limit; no sweep of a grid has more workgroups than its 2-plane chunks, which the
+        // partials' halves hold three times over)
+        const int nb_other = std::min(
+            sweep_blocks(prec ? (pass ? lv.swA32 : lv.swB32) : (pass ? lv.swA : lv.swB)), selfred_max_blocks());
         for (int ci = 0; ci < kVar * (int)(sizeof(cand) / sizeof(cand[0])); ++ci) {
           const int zc = cand[ci / kVar], depth = depths[(ci % kVar) / 2], nt = ci % 2;
           if (zc > 2 * (g.nz - 1) + 2) break;
           const Sweep sw = make_sweep(g, lv.st, zc, depth, nt);
           if (3LL * sweep_blocks(sw) > lo.npart) continue;
+          if (burst && sweep_blocks(sw) > selfred_max_blocks()) continue;
           float tmin = 1e30f;
           for (int rep = 0; rep < 4; ++rep) {
-            launch_tune_state(h->cs2, s);
-            if (hipEventRecord(ea, s) != hipSuccess) rc = EXCMG_ERR_HIP;
-            if (prec == 0) {
-              if (pass == 0) launch_cg_pass_a<double>(sw, h->r, h->p0, h->p1, h->cs2, h->partials, s);
-              // u: r's buffer, which iteration 1 does not use (r is in p0, p in p1), so that the trial reads
-              // three distinct arrays as a real pass B does
-              else launch_cg_pass_b<double>(sw, h->r, h->r, h->p0, h->p1, h->cs2, h->partials, s);
+            if (burst) {
+              launch_tune_selfred(h->cs2, pass ? pa : pb, nb_other, s);
+              launch_delay(kTuneDelayUs, s);
             } else {
-              if (pass == 0) launch_cg_pass_a<float>(sw, h->r32, h->p32a, h->p32b, h->cs2, h->partials, s);
-              else launch_cg_pass_b<float>(sw, h->d32, h->r32, h->p32a, h->p32b, h->cs2, h->partials, s);
+              launch_tune_state(h->cs2, s);
+            }
+            if (hipEventRecord(ea, s) != hipSuccess) rc = EXCMG_ERR_HIP;
+            for (int q = 0; q < (burst ? kTuneBurst : 1); ++q) {
+              if (burst && prec == 0) {
+                if (pass == 0) launch_selfred_a<double>(sw, h->r, h->p0, h->p1, h->cs2, pb, nb_other, 1.0, pa, s);
+                else launch_selfred_b<double>(sw, h->r, h->r, h->p0, h->p1, h->cs2, pa, nb_other, pb, s);
+              } else if (burst) {
+                if (pass == 0) launch_selfred_a<float>(sw, h->r32, h->p32a, h->p32b, h->cs2, pb, nb_other, 1.0, pa, s);
+                else launch_selfred_b<float>(sw, h->d32, h->r32, h->p32a, h->p32b, h->cs2, pa, nb_other, pb, s);
+              } else if (prec == 0) {
+                if (pass == 0) launch_cg_pass_a<double>(sw, h->r, h->p0, h->p1, h->cs2, h->partials, s);
+                // u: r's buffer, which iteration 1 does not use (r is in p0, p in p1), so that the trial reads
+                // three distinct arrays as a real pass B does
+                else launch_cg_pass_b<double>(sw, h->r, h->r, h->p0, h->p1, h->cs2, h->partials, s);
+              } else {
+                if (pass == 0) launch_cg_pass_a<float>(sw, h->r32, h->p32a, h->p32b, h->cs2, h->partials, s);
+                else launch_cg_pass_b<float>(sw, h->d32, h->r32, h->p32a, h->p32b, h->cs2, h->partials, s);
+              }
             }
             if (hipEventRecord(eb, s) != hipSuccess || hipEventSynchronize(eb) != hipSuccess) rc = EXCMG_ERR_HIP;
             if (last_error() != EXCMG_OK) rc = EXCMG_ERR_HIP;
             if (rc) break;
             float ms = 0.0f;
             if (hipEventElapsedTime(&ms, ea, eb) != hipSuccess) rc = EXCMG_ERR_HIP;
+            ms /= burst ? kTuneBurst : 1;
             if (rep > 0 && ms < tmin) tmin = ms;  // the first launch warms caches and code
           }
           if (rc) break;

@@ -258,6 +258,10 @@ void launch_cg_pass_b(const Sweep &sw, T *u, T *r, T *p0, T *p1, CgState *cs, do
 
 // CG state for timing sweeps in isolation: iteration 0, alpha = beta = 0, never done
 void launch_tune_state(CgState *cs, hipStream_t st);
+// the trial state of the self-finalizing passes in cs, and parts[0, n) = 1 (n <= the self-finalizing limit)
+void launch_tune_selfred(CgState *cs, double *parts, int n, hipStream_t st);
+// a single-wave kernel that returns after about `us` microseconds (bounded), to queue launches behind it
+void launch_delay(double us, hipStream_t st);
 // copy bytes (a multiple of 8) from device memory to host memory mapped for the device
 void launch_publish(const void *src, void *dst, size_t bytes, hipStream_t st);
 

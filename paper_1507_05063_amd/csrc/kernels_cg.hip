@@ -924,6 +924,27 @@ __device__ void tune_state(CgState *cs) {
 
 __global__ void tune_state_kernel(CgState *cs) { tune_state(cs); }
 
+// the trial state of a self-finalizing pass (iteration 1 of both passes, never converged) and n partial sums of 1 for
+// it to read, so that neither pass stops at its reduction
+__global__ void tune_selfred_kernel(CgState *cs, double *parts, int n) {
+  if (threadIdx.x == 0) {
+    tune_state(cs);
+    cs->iterA = 1;
+    cs->iterB = 1;
+    cs->preset = 0;
+    cs->rhoA[0] = 1.0;
+    cs->rhoA[1] = 1.0;
+  }
+  for (int q = threadIdx.x; q < n; q += blockDim.x) parts[q] = 1.0;
+}
+
+// Holds the stream for about `ticks` of the constant 100 MHz wall clock (at most 2^20 sleeps of ~0.3 us), so that
+// the launches queued behind it run back to back when it ends.
+__global__ void delay_kernel(long long ticks) {
+  const long long t0 = wall_clock64();
+  for (int q = 0; q < (1 << 20) && wall_clock64() - t0 < ticks; ++q) __builtin_amdgcn_s_sleep(10);
+}
+
 // copy of a small device record (n 8-byte words) into host memory the device can write (the host reads it after a
 // stream synchronisation; no staged copy)
 __global__ void publish_kernel(const unsigned long long *src, unsigned long long *dst, int n) {
@@ -1690,6 +1711,12 @@ template void launch_cg_pass_b<float>(const Sweep &, float *, float *, float *, 
                                       double *, hipStream_t);
 
 void launch_tune_state(CgState *cs, hipStream_t st) { tune_state_kernel<<<1, 1, 0, st>>>(cs); }
+
+void launch_tune_selfred(CgState *cs, double *parts, int n, hipStream_t st) {
+  tune_selfred_kernel<<<1, 256, 0, st>>>(cs, parts, n);
+}
+
+void launch_delay(double us, hipStream_t st) { delay_kernel<<<1, 64, 0, st>>>((long long)(us * 100.0)); }
 
 void launch_add_correction(const Grid &gu, double *u, const Grid &g32, const float *d32, hipStream_t st) {
   dim3 grid((gu.nx - 1 + 255) / 256, gu.ny - 1, gu.nz - 1);
