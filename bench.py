@@ -585,9 +585,11 @@ def main():
     achieved = BYTES_PER_UNKNOWN[dom] * nI / (avg_ms * 1e-3) / 1e9
     # measured HBM bytes of the same kernel and launch shape (z chunk) from the committed counter runs
     zc_dom = zc64[-1][0 if dom == "cg_a" else 1]
-    grid_threads = -(-(N - 1) // 64) * -(-(N - 1) // 4) * -(-(N - 1) // zc_dom) * 256
-    dvar = dp64[-1][0 if dom == "cg_a" else 1]  # prefetch depth, plus 10 for the non-temporal policy
-    kname = f"cg_pass_{dom[-1]}_kernel<double, {dvar % 10}, {'true' if dvar >= 10 else 'false'}>"
+    dvar = dp64[-1][0 if dom == "cg_a" else 1]  # prefetch depth + 10 (non-temporal policy) + 100 * tile height
+    ty = dvar // 100
+    grid_threads = -(-(N - 1) // 64) * -(-(N - 1) // ty) * -(-(N - 1) // zc_dom) * 64 * ty
+    kname = (f"cg_pass_{dom[-1]}_kernel<double, {dvar % 10}, {'true' if (dvar // 10) % 10 else 'false'}, "
+             f"{dvar // 100}>")
     traffic = measured_traffic(kname, grid_threads)
     # stencil-CG sweeps of the finest grid alone: unknown-iterations per second of pass A + pass B kernel time
     fin_iters = stats[-1]["iters"][-1]
@@ -647,7 +649,8 @@ def main():
         "finest_grid_kernels": kernels,
         "iters_per_grid": stats[-1]["iters"],
         "autotuned_z_chunks": [list(z[:2]) for z in zc64],
-        "autotuned_depths": [list(d[:2]) for d in dp64],
+        "autotuned_depths": [[x % 100 for x in d[:2]] for d in dp64],
+        "autotuned_tile_heights": [[x // 100 for x in d[:2]] for d in dp64],
         "ms_per_grid": [round(v, 3) for v in plain[-1]["ms_level"]],
         "solve_ms_fp64": round(float(np.median([st["ms_total"] for st in plain])), 3),  # median over the timed steps
         "ms_per_step_with_kernel_events": round(ms_step_timed, 3),

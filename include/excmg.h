@@ -230,12 +230,16 @@ int excmg_autotune_batched(excmg_handle *const *hs, int32_t count, void *batch_w
 
 /* Autotuner (host call, device work on the handle's stream): times the two CG sweep kernels of every relaxed grid
  * (FP64, and FP32 where EXCMG_FP32_IR relaxes in FP32) for each z-chunk length in {2, 4, ..., 512} planes per
- * workgroup, each prefetch depth (2, 3, 4 or 6 planes of loads in flight per thread) and each cache policy
- * (ordinary or non-temporal loads and stores of the data a sweep touches once), on the handle's own work buffers (no caller array
- * is read or written), and keeps the fastest per grid and kernel for every later call on this handle.
+ * workgroup, each tile height (4, 8 or 16 rows of 64 nodes per workgroup), each prefetch depth (2, 3, 4 or 6 planes
+ * of loads in flight per thread) and each cache policy (ordinary or non-temporal loads and stores of the data a
+ * sweep touches once), on the handle's own work buffers (no caller array is read or written), and keeps the fastest
+ * per grid and kernel for every later call on this handle.  Grids below the finest, whose iterations run as graphs
+ * of self-finalizing passes, are timed on those kernels, with the shapes that keep them self-finalizing.
  * zc_out, depth_out (host, nullable, 4 * levels entries each): per grid, pass A and pass B in FP64, then in FP32 (0
- * where the grid is not relaxed that way): the chunk, and the depth plus 10 if the non-temporal policy won.
- * Optional: without it the handle uses a fixed default (16 planes, fewer on small grids; depth 2; ordinary). */
+ * where the grid is not relaxed that way): the chunk, and depth + 10 (if the non-temporal policy won) + 100 * tile
+ * height.  Batched solves (excmg_solve_batched) keep the chunk and use 4-row tiles.
+ * Optional: without it the handle uses a fixed default (16 planes, fewer on small grids; 4 rows; depth 2;
+ * ordinary). */
 int excmg_autotune(excmg_handle *h, int32_t *zc_out, int32_t *depth_out);
 
 /* Host call.  Turns the kernel timing of EXCMG_WANT_TIMING on (on != 0) or off for later calls on this handle, as

@@ -831,11 +831,12 @@ void batch_entry(excmg_handle *h, int problem, int l, const double *f, const dou
   E->max_outer = 30;
   E->tol = grid_tol(h->p, l, h->lo.L);
   E->eta = h->p.inner_tol > 0.0 ? h->p.inner_tol : 1e-5;
-  E->swA = lv.swA;
-  E->swB = lv.swB;
-  E->swR = lv.sw;
-  E->swA32 = lv.swA32;
-  E->swB32 = lv.swB32;
+  // the batched kernels are built for 4-row tiles: a grid tuned alone to taller ones keeps its z chunk here
+  E->swA = default_height(lv.swA);
+  E->swB = default_height(lv.swB);
+  E->swR = default_height(lv.sw);
+  E->swA32 = default_height(lv.swA32);
+  E->swB32 = default_height(lv.swB32);
   E->g = lv.g;
   E->g32 = lv.g32;
   E->gd = lo.gdense;
@@ -867,14 +868,14 @@ void batch_entry(excmg_handle *h, int problem, int l, const double *f, const dou
   E->gb = g;
   E->out = u;
   if (E->kind == kBCg64) {
-    blocks[kLA64] = sweep_blocks(lv.swA);
-    blocks[kLB64] = sweep_blocks(lv.swB);
-    blocks[kLR64] = sweep_blocks(lv.sw);
+    blocks[kLA64] = sweep_blocks(E->swA);
+    blocks[kLB64] = sweep_blocks(E->swB);
+    blocks[kLR64] = sweep_blocks(E->swR);
   }
   if (E->kind == kBIr) {
-    blocks[kLA32] = sweep_blocks(lv.swA32);
-    blocks[kLB32] = sweep_blocks(lv.swB32);
-    blocks[kLRC] = sweep_blocks(lv.sw);
+    blocks[kLA32] = sweep_blocks(E->swA32);
+    blocks[kLB32] = sweep_blocks(E->swB32);
+    blocks[kLRC] = sweep_blocks(E->swR);
     blocks[kLCorr] = b_blocks_interior(lv.g);
   }
   if (E->kind == kBCg64 || E->kind == kBIr) blocks[kLBterm] = b_blocks_bterms(lv.g);
@@ -1507,7 +1508,9 @@ int excmg_autotune(excmg_handle *h, int32_t *zc_out, int32_t *depth_out) {
   Layout &lo = h->lo;
   static const int cand[] = {2, 4, 8, 16, 32, 64, 128, 256, 512};
   static const int depths[] = {2, 3, 4, 6};
-  constexpr int kVar = 2 * (int)(sizeof(depths) / sizeof(depths[0]));  // depth x cache policy
+  static const int heights[] = {4, 8, 16};
+  constexpr int kDp = 2 * (int)(sizeof(depths) / sizeof(depths[0]));  // depth x cache policy
+  constexpr int kVar = kDp * (int)(sizeof(heights) / sizeof(heights[0]));  // ... x tile height
   hipEvent_t ea, eb;
   HIPCHECK(hipEventCreateWithFlags(&ea, kTimingEvent));
   HIPCHECK(hipEventCreateWithFlags(&eb, kTimingEvent));
@@ -1532,9 +1535,11 @@ int excmg_autotune(excmg_handle *h, int32_t *zc_out, int32_t *depth_out) {
         const int nb_other = std::min(
             sweep_blocks(prec ? (pass ? lv.swA32 : lv.swB32) : (pass ? lv.swA : lv.swB)), selfred_max_blocks());
         for (int ci = 0; ci < kVar * (int)(sizeof(cand) / sizeof(cand[0])); ++ci) {
-          const int zc = cand[ci / kVar], depth = depths[(ci % kVar) / 2], nt = ci % 2;
+          const int zc = cand[ci / kVar], ty = heights[(ci % kVar) / kDp], depth = depths[(ci % kDp) / 2];
+          const int nt = ci % 2;
           if (zc > 2 * (g.nz - 1) + 2) break;
-          const Sweep sw = make_sweep(g, lv.st, zc, depth, nt);
+          if (ty > 4 && ty / 2 >= g.ny - 1) continue;  // a tile at least twice the grid's height
+          const Sweep sw = make_sweep(g, lv.st, zc, depth, nt, ty);
           if (3LL * sweep_blocks(sw) > lo.npart) continue;
           if (burst && sweep_blocks(sw) > selfred_max_blocks()) continue;
           float tmin = 1e30f;
@@ -1601,10 +1606,11 @@ int excmg_autotune(excmg_handle *h, int32_t *zc_out, int32_t *depth_out) {
       const Level &lv = lo.lev[l];
       const bool relaxed = swept(lo, l);
       const bool ir = relaxed && l >= 2 && (h->p.precision == EXCMG_FP32_IR) && lv.g.interior() >= kIrMinUnknowns;
-      depth_out[4 * l + 0] = relaxed ? lv.swA.depth + 10 * lv.swA.nt : 0;
-      depth_out[4 * l + 1] = relaxed ? lv.swB.depth + 10 * lv.swB.nt : 0;
-      depth_out[4 * l + 2] = ir ? lv.swA32.depth + 10 * lv.swA32.nt : 0;
-      depth_out[4 * l + 3] = ir ? lv.swB32.depth + 10 * lv.swB32.nt : 0;
+      auto code = [](const Sweep &sw) { return sw.depth + 10 * sw.nt + 100 * sw.ty; };
+      depth_out[4 * l + 0] = relaxed ? code(lv.swA) : 0;
+      depth_out[4 * l + 1] = relaxed ? code(lv.swB) : 0;
+      depth_out[4 * l + 2] = ir ? code(lv.swA32) : 0;
+      depth_out[4 * l + 3] = ir ? code(lv.swB32) : 0;
     }
   }
   return EXCMG_OK;

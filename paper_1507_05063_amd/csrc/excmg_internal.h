@@ -201,10 +201,14 @@ struct Sweep {
   int depth;  // planes of loads in flight per thread in the z-march (2, 3, 4 or 6 in the CG passes; 2 or 3 in
               // the residual sweeps)
   int nt;     // 1: data read or written once per sweep uses non-temporal (streaming) loads and stores
+  int ty;     // tile height in rows of 64 nodes (4, 8 or 16; only the CG passes of a single problem use 8 and 16)
 };
 
-Sweep make_sweep(const Grid &g, const Stencil &s, int zc, int depth = 2, int nt = 0);  // zc <= 0: default chunk
+// zc <= 0: default chunk; ty: 4 unless 8 or 16
+Sweep make_sweep(const Grid &g, const Stencil &s, int zc, int depth = 2, int nt = 0, int ty = 4);
 int sweep_blocks(const Sweep &sw);
+// the same sweep with 4-row tiles (what the residual sweeps and the batched launches are built for)
+Sweep default_height(const Sweep &sw);
 // partial-sum buffer length needed by the CG and residual kernels for a grid
 long long cg_partials_needed(const Grid &g);
 

@@ -9,7 +9,8 @@
 // reads r only (8 B) and pass B takes both operands from r's buffer and writes the new r into another (32 B); the
 // buffers then rotate as cg_bufs describes.
 //
-// Stencil sweep ("z-march"): a workgroup owns a TX x TY column tile and a chunk of z planes.  For each plane it loads
+// Stencil sweep ("z-march"): a workgroup owns a TX x TY column tile (64 x 4, 8 or 16 nodes, one thread per node; the
+// CG passes take the height per grid from the autotuner, the other sweeps use 4) and a chunk of z planes.  For each plane it loads
 // the (TX+2) x (TY+2) tile with its halo into LDS (double-buffered, one barrier per plane) and every thread forms the
 // plane sums of its column: centre C, x-pair X, y-pair Y, xy-diagonals D.  The 19-point result at plane k is
 //   c0 C_k + cx X_k + cy Y_k + cxy D_k + cz (C_{k-1} + C_{k+1}) + cxz (X_{k-1} + X_{k+1}) + cyz (Y_{k-1} + Y_{k+1}),
@@ -66,11 +67,21 @@ __device__ __forceinline__ double block_sum(double v, double *sh) {
 
 // Tile shape of the stencil sweeps (x is the fast axis: one wavefront covers one 64-node row segment).
 constexpr int TX = 64;
-constexpr int TY = 4;
-constexpr int NT = TX * TY;
-// Rows of one LDS plane buffer: the (TX+2) x (TY+2) tile with its halo, padded so that every fetch slot of the
-// workgroup (a whole number of slots per thread) has an entry and the staging stores need no bounds test.
-constexpr int kTileRows = ((TX + 2) * (TY + 2) + NT - 1) / NT * NT / (TX + 2) + 1;
+// Threads of a workgroup with tile height TY, and the rows of one LDS plane buffer: the (TX+2) x (TY+2) tile with its
+// halo, padded so that every fetch slot of the workgroup (a whole number of slots per thread) has an entry and the
+// staging stores need no bounds test.  A taller tile re-reads fewer halo rows per node (2 per TY rows); a shorter one
+// gives small grids more workgroups.
+template <int TY>
+struct Tile {
+  static constexpr int NT = TX * TY;
+  static constexpr int Rows = ((TX + 2) * (TY + 2) + NT - 1) / NT * NT / (TX + 2) + 1;
+};
+template <int TY>
+constexpr bool height_ok() { return TY == 4 || TY == 8 || TY == 16; }
+// the height of every sweep but the CG passes of a single problem (residuals, batched launches, operator apply)
+constexpr int kTy = 4;
+constexpr int NT = Tile<kTy>::NT;
+constexpr int kTileRows = Tile<kTy>::Rows;
 
 __device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
@@ -117,12 +128,15 @@ constexpr bool depth_ok() { return D == 2 || D == 3 || D == 4 || D == 6; }
 // bid, nb: this workgroup's index among the nb workgroups of the sweep (the grid of a single-problem launch, or one
 // problem's range of a batched launch); remap: number the tiles XCD by XCD (single-problem launches only, where the
 // hardware's round-robin dispatch over the XCDs follows bid).
-template <typename T, int D = 2, typename P>
-__device__ __forceinline__ void zmarch(const Sweep &sw, P &pol, double &acc0, double &acc1, T (*tile)[kTileRows][TX + 2],
-                                       double (*tileF)[kTileRows][TX + 2], int bid, int nb, bool remap) {
+template <typename T, int D = 2, int TY = kTy, typename P>
+__device__ __forceinline__ void zmarch(const Sweep &sw, P &pol, double &acc0, double &acc1,
+                                       T (*tile)[Tile<TY>::Rows][TX + 2], double (*tileF)[Tile<TY>::Rows][TX + 2],
+                                       int bid, int nb, bool remap) {
   static_assert(depth_ok<D>(), "prefetch depth");
+  static_assert(height_ok<TY>(), "tile height");
+  constexpr int NT = Tile<TY>::NT;
   constexpr int W = TX + 2, H = TY + 2, E = W * H, NL = (E + NT - 1) / NT;
-  static_assert(NL * NT <= kTileRows * W, "every fetch slot has an LDS entry");
+  static_assert(NL * NT <= Tile<TY>::Rows * W, "every fetch slot has an LDS entry");
   constexpr int U = D % 2 == 0 ? D : 2 * D;  // steps per unrolled round: a multiple of both 2 (LDS buffers) and D
   constexpr bool R = P::kRhs;
   const Grid &g = sw.g;
@@ -256,11 +270,11 @@ __device__ __forceinline__ void zmarch(const Sweep &sw, P &pol, double &acc0, do
 // runs next on the stream sums them in block order and updates the CG state.  The kernel boundary orders the two;
 // no workgroup of a sweep fences or synchronises with another (on this GPU an agent-scope fence writes back and
 // invalidates the XCD's L2, far too costly to issue from every workgroup).
-template <int K>
+template <int K, int NTB = NT>
 __device__ __forceinline__ void write_partials(const double (&v)[K], double *partials, double *sh, int bid, int nb) {
 #pragma unroll
   for (int k = 0; k < K; ++k) {
-    const double s = block_sum<NT>(v[k], sh);
+    const double s = block_sum<NTB>(v[k], sh);
     if (threadIdx.x == 0) partials[(long long)k * nb + bid] = s;
     __syncthreads();
   }
@@ -452,9 +466,9 @@ struct PolA {
 };
 
 // pass A's z-march of iteration it: the first iteration's form (r alone) or the general one
-template <typename T, int D, bool NTP>
+template <typename T, int D, bool NTP, int TY = kTy>
 __device__ __forceinline__ void pass_a_march(const Sweep &sw, int it, const CgBufs<T> &bf, T beta, double &a0,
-                                             T (*tile)[kTileRows][TX + 2], int bid, int nb, bool remap) {
+                                             T (*tile)[Tile<TY>::Rows][TX + 2], int bid, int nb, bool remap) {
   double a1 = 0.0;
   if (it == 0) {
     PolA<T, NTP, true> pol;
@@ -462,29 +476,29 @@ __device__ __forceinline__ void pass_a_march(const Sweep &sw, int it, const CgBu
     pol.pold = bf.r_in;
     pol.pnew = bf.p;
     pol.beta = T(0);
-    zmarch<T, D>(sw, pol, a0, a1, tile, nullptr, bid, nb, remap);
+    zmarch<T, D, TY>(sw, pol, a0, a1, tile, nullptr, bid, nb, remap);
   } else {
     PolA<T, NTP, false> pol;
     pol.r = bf.r_in;
     pol.pold = bf.p_old;
     pol.pnew = bf.p;
     pol.beta = beta;
-    zmarch<T, D>(sw, pol, a0, a1, tile, nullptr, bid, nb, remap);
+    zmarch<T, D, TY>(sw, pol, a0, a1, tile, nullptr, bid, nb, remap);
   }
 }
 
-template <typename T, int D, bool NTP>
-__global__ __launch_bounds__(NT) void cg_pass_a_kernel(Sweep sw, T *r, T *p0, T *p1,
-                                                       const CgState *cs, double *partials) {
-  __shared__ T tile[2][kTileRows][TX + 2];
-  __shared__ double sh[NT / 64];
+template <typename T, int D, bool NTP, int TY>
+__global__ __launch_bounds__(Tile<TY>::NT) void cg_pass_a_kernel(Sweep sw, T *r, T *p0, T *p1,
+                                                                 const CgState *cs, double *partials) {
+  __shared__ T tile[2][Tile<TY>::Rows][TX + 2];
+  __shared__ double sh[Tile<TY>::NT / 64];
   if (cs->done) return;
   const int it = cs->iter;
   const CgBufs<T> bf = cg_bufs(it, r, p0, p1);
   double a0 = 0.0;
-  pass_a_march<T, D, NTP>(sw, it, bf, (T)cs->beta, a0, tile, blockIdx.x, gridDim.x, true);
+  pass_a_march<T, D, NTP, TY>(sw, it, bf, (T)cs->beta, a0, tile, blockIdx.x, gridDim.x, true);
   const double v[1] = {a0};
-  write_partials<1>(v, partials, sh, blockIdx.x, gridDim.x);
+  write_partials<1, Tile<TY>::NT>(v, partials, sh, blockIdx.x, gridDim.x);
 }
 
 // FIRST: iteration 0, where p and r are the same array: r at the node is the staged operand's centre, not loaded again.
@@ -520,9 +534,9 @@ struct PolB {
 };
 
 // pass B's z-march of iteration it (u: the solution, or the correction of an inner FP32 solve)
-template <typename T, int D, bool NTP>
+template <typename T, int D, bool NTP, int TY = kTy>
 __device__ __forceinline__ void pass_b_march(const Sweep &sw, int it, const CgBufs<T> &bf, T *u, T alpha, double &a0,
-                                             T (*tile)[kTileRows][TX + 2], int bid, int nb, bool remap) {
+                                             T (*tile)[Tile<TY>::Rows][TX + 2], int bid, int nb, bool remap) {
   double a1 = 0.0;
   auto go = [&](auto first) {
     PolB<T, NTP, decltype(first)::value> pol;
@@ -532,24 +546,24 @@ __device__ __forceinline__ void pass_b_march(const Sweep &sw, int it, const CgBu
     pol.rout = bf.r_out;
     pol.alpha = alpha;
     for (int q = 0; q < kMaxDepth; ++q) pol.pr[q] = pol.pu[q] = 0;
-    zmarch<T, D>(sw, pol, a0, a1, tile, nullptr, bid, nb, remap);
+    zmarch<T, D, TY>(sw, pol, a0, a1, tile, nullptr, bid, nb, remap);
   };
   if (it == 0) go(std::true_type{});
   else go(std::false_type{});
 }
 
-template <typename T, int D, bool NTP>
-__global__ __launch_bounds__(NT) void cg_pass_b_kernel(Sweep sw, T *u, T *r, T *p0, T *p1,
-                                                       const CgState *cs, double *partials) {
-  __shared__ T tile[2][kTileRows][TX + 2];
-  __shared__ double sh[NT / 64];
+template <typename T, int D, bool NTP, int TY>
+__global__ __launch_bounds__(Tile<TY>::NT) void cg_pass_b_kernel(Sweep sw, T *u, T *r, T *p0, T *p1,
+                                                                 const CgState *cs, double *partials) {
+  __shared__ T tile[2][Tile<TY>::Rows][TX + 2];
+  __shared__ double sh[Tile<TY>::NT / 64];
   if (cs->done) return;
   const int it = cs->iter;
   const CgBufs<T> bf = cg_bufs(it, r, p0, p1);
   double a0 = 0.0;
-  pass_b_march<T, D, NTP>(sw, it, bf, u, (T)cs->alpha, a0, tile, blockIdx.x, gridDim.x, true);
+  pass_b_march<T, D, NTP, TY>(sw, it, bf, u, (T)cs->alpha, a0, tile, blockIdx.x, gridDim.x, true);
   const double v[1] = {a0};
-  write_partials<1>(v, partials, sh, blockIdx.x, gridDim.x);
+  write_partials<1, Tile<TY>::NT>(v, partials, sh, blockIdx.x, gridDim.x);
 }
 
 // The right-hand side inside the residual sweeps: f (or the adjoint's G) staged by the z-march (R f from LDS and
@@ -583,25 +597,27 @@ struct RhsPart {
 
 constexpr int kSelfRedMaxBlocks = 2048;
 
-// fixed-order sum by a whole workgroup of NT threads; valid in every thread
+// fixed-order sum by a whole workgroup of NTB threads; valid in every thread
+template <int NTB>
 __device__ double block_fixed_sum(const double *a, int n, double *sh) {
-  const double t = block_sum<NT>(strided_sum<NT>(a, n), sh);
-  if (threadIdx.x == 0) sh[NT / 64] = t;
+  const double t = block_sum<NTB>(strided_sum<NTB>(a, n), sh);
+  if (threadIdx.x == 0) sh[NTB / 64] = t;
   __syncthreads();
-  const double s = sh[NT / 64];
+  const double s = sh[NTB / 64];
   __syncthreads();
   return s;
 }
 
 // Pass A of iteration k = iterA: the stopping test on rho_k (Algorithm 1, the while condition), then
 // p = r + beta p with beta = rho_k / rho_{k-1}, partial sums of p.Mp into partsA.
-template <typename T, int D, bool NTP>
-__global__ __launch_bounds__(NT) void cg_selfred_a_kernel(Sweep sw, T *r, T *p0, T *p1,
-                                                          CgState *cs, const double *partsB, int nbB, double tol,
-                                                          double *partsA) {
-  __shared__ T tile[2][kTileRows][TX + 2];
-  __shared__ double sh[NT / 64];
-  __shared__ double shf[NT];
+template <typename T, int D, bool NTP, int TY>
+__global__ __launch_bounds__(Tile<TY>::NT) void cg_selfred_a_kernel(Sweep sw, T *r, T *p0, T *p1,
+                                                                    CgState *cs, const double *partsB, int nbB,
+                                                                    double tol, double *partsA) {
+  constexpr int NTB = Tile<TY>::NT;
+  __shared__ T tile[2][Tile<TY>::Rows][TX + 2];
+  __shared__ double sh[NTB / 64];
+  __shared__ double shf[NTB];
   if (cs->done) return;
   const int k = cs->iterA;
   double rho, bb, stop2;
@@ -610,11 +626,11 @@ __global__ __launch_bounds__(NT) void cg_selfred_a_kernel(Sweep sw, T *r, T *p0,
     bb = cs->bnorm2;
     stop2 = cs->stop2;
   } else if (k == 0) {
-    rho = block_fixed_sum(partsB, nbB, shf);
-    bb = block_fixed_sum(partsB + nbB, nbB, shf) + cs->gbnd2;
+    rho = block_fixed_sum<NTB>(partsB, nbB, shf);
+    bb = block_fixed_sum<NTB>(partsB + nbB, nbB, shf) + cs->gbnd2;
     stop2 = tol * tol * bb;
   } else {
-    rho = block_fixed_sum(partsB, nbB, shf);
+    rho = block_fixed_sum<NTB>(partsB, nbB, shf);
     bb = cs->bnorm2;
     stop2 = cs->stop2;
   }
@@ -639,24 +655,25 @@ __global__ __launch_bounds__(NT) void cg_selfred_a_kernel(Sweep sw, T *r, T *p0,
   if (!finite || conv || cap) return;
   const CgBufs<T> bf = cg_bufs(k, r, p0, p1);
   double a0 = 0.0;
-  pass_a_march<T, D, NTP>(sw, k, bf, (k == 0) ? T(0) : (T)(rho / cs->rhoA[(k - 1) & 1]), a0, tile, blockIdx.x,
-                          gridDim.x, true);
+  pass_a_march<T, D, NTP, TY>(sw, k, bf, (k == 0) ? T(0) : (T)(rho / cs->rhoA[(k - 1) & 1]), a0, tile, blockIdx.x,
+                              gridDim.x, true);
   const double v[1] = {a0};
-  write_partials<1>(v, partsA, sh, blockIdx.x, gridDim.x);
+  write_partials<1, NTB>(v, partsA, sh, blockIdx.x, gridDim.x);
 }
 
 // Pass B of iteration k = iterB: alpha = rho_k / p.Mp (from partsA), u += alpha p, r -= alpha Mp, partial sums of
 // r.r into partsB.
-template <typename T, int D, bool NTP>
-__global__ __launch_bounds__(NT) void cg_selfred_b_kernel(Sweep sw, T *u, T *r, T *p0, T *p1,
-                                                          CgState *cs, const double *partsA, int nbA,
-                                                          double *partsB) {
-  __shared__ T tile[2][kTileRows][TX + 2];
-  __shared__ double sh[NT / 64];
-  __shared__ double shf[NT];
+template <typename T, int D, bool NTP, int TY>
+__global__ __launch_bounds__(Tile<TY>::NT) void cg_selfred_b_kernel(Sweep sw, T *u, T *r, T *p0, T *p1,
+                                                                    CgState *cs, const double *partsA, int nbA,
+                                                                    double *partsB) {
+  constexpr int NTB = Tile<TY>::NT;
+  __shared__ T tile[2][Tile<TY>::Rows][TX + 2];
+  __shared__ double sh[NTB / 64];
+  __shared__ double shf[NTB];
   if (cs->done) return;
   const int k = cs->iterB;
-  const double pq = block_fixed_sum(partsA, nbA, shf);
+  const double pq = block_fixed_sum<NTB>(partsA, nbA, shf);
   const bool bad = !(pq > 0.0) || !isfinite(pq);
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     cs->pq = pq;
@@ -669,9 +686,9 @@ __global__ __launch_bounds__(NT) void cg_selfred_b_kernel(Sweep sw, T *u, T *r, 
   if (bad) return;
   const CgBufs<T> bf = cg_bufs(k, r, p0, p1);
   double a0 = 0.0;
-  pass_b_march<T, D, NTP>(sw, k, bf, u, (T)(cs->rhoA[k & 1] / pq), a0, tile, blockIdx.x, gridDim.x, true);
+  pass_b_march<T, D, NTP, TY>(sw, k, bf, u, (T)(cs->rhoA[k & 1] / pq), a0, tile, blockIdx.x, gridDim.x, true);
   const double v[1] = {a0};
-  write_partials<1>(v, partsB, sh, blockIdx.x, gridDim.x);
+  write_partials<1, NTB>(v, partsB, sh, blockIdx.x, gridDim.x);
 }
 
 __global__ void selfred_init_kernel(CgState *cs, int max_iters, int hist_on, int preset) {
@@ -1558,14 +1575,15 @@ __global__ __launch_bounds__(256) void b_add_correction_kernel(BatchList L) {
 
 // z chunk per workgroup (even, so that the first output plane of every workgroup is odd).  Default: 16 planes, or
 // fewer while the grid has under 2048 workgroups (8 per CU).  The autotuner replaces it per grid and pass.
-Sweep make_sweep(const Grid &g, const Stencil &s, int zc, int depth, int nt) {
+Sweep make_sweep(const Grid &g, const Stencil &s, int zc, int depth, int nt, int ty) {
   Sweep sw;
   sw.depth = (depth == 3 || depth == 4 || depth == 6) ? depth : 2;
   sw.nt = nt ? 1 : 0;
+  sw.ty = (ty == 8 || ty == 16) ? ty : kTy;
   sw.g = g;
   sw.st = s;
   sw.ntx = (g.nx - 1 + TX - 1) / TX;
-  sw.nty = (g.ny - 1 + TY - 1) / TY;
+  sw.nty = (g.ny - 1 + sw.ty - 1) / sw.ty;
   const long long tiles = (long long)sw.ntx * sw.nty;
   if (zc <= 0) {
     zc = 16;
@@ -1579,17 +1597,28 @@ Sweep make_sweep(const Grid &g, const Stencil &s, int zc, int depth, int nt) {
 
 int sweep_blocks(const Sweep &sw) { return sw.ntx * sw.nty * sw.nzc; }
 
+Sweep default_height(const Sweep &sw) {
+  return sw.ty == kTy ? sw : make_sweep(sw.g, sw.st, sw.zc, sw.depth, sw.nt, kTy);
+}
+
 long long cg_partials_needed(const Grid &g) {
-  const Sweep sw = make_sweep(g, Stencil{}, 2);  // the smallest chunk gives the most workgroups
+  const Sweep sw = make_sweep(g, Stencil{}, 2, 2, 0, 4);  // the smallest chunk and tile give the most workgroups
   return 3LL * sweep_blocks(sw) + 64;
 }
 
-// f(depth, policy) with the sweep's prefetch depth and cache policy as compile-time constants.
+// f(depth, policy, height) with the sweep's prefetch depth, cache policy and tile height as compile-time constants.
 template <typename F>
-static void with_depth_policy(const Sweep &sw, F &&f) {
+static void with_shape(const Sweep &sw, F &&f) {
+  auto height = [&](auto d, auto n) {
+    switch (sw.ty) {
+      case 8: f(d, n, std::integral_constant<int, 8>{}); break;
+      case 16: f(d, n, std::integral_constant<int, 16>{}); break;
+      default: f(d, n, std::integral_constant<int, kTy>{}); break;
+    }
+  };
   auto pol = [&](auto d) {
-    if (sw.nt) f(d, std::true_type{});
-    else f(d, std::false_type{});
+    if (sw.nt) height(d, std::true_type{});
+    else height(d, std::false_type{});
   };
   switch (sw.depth) {
     case 3: pol(std::integral_constant<int, 3>{}); break;
@@ -1606,8 +1635,9 @@ static void launch_boundary_terms(const RhsSrc &rs, const Grid &g, double *out, 
   boundary_terms_kernel<<<grid, 256, 0, st>>>(rs, g, out);
 }
 
-static void launch_resid(const Sweep &sw, const double *u, const RhsSrc &rs, double *r, double *parts,
+static void launch_resid(const Sweep &sw_in, const double *u, const RhsSrc &rs, double *r, double *parts,
                          hipStream_t st) {
+  const Sweep sw = default_height(sw_in);  // the residual kernels are built for 4-row tiles only
   const int nb = sweep_blocks(sw);
   const int v = (sw.depth == 3 ? 2 : 0) + sw.nt;
   if (v == 0) residual_kernel<2, false><<<nb, NT, 0, st>>>(sw, u, rs, r, parts);
@@ -1635,18 +1665,20 @@ void launch_selfred_init(CgState *cs, int max_iters, int hist_on, int preset, hi
 template <typename T>
 void launch_selfred_a(const Sweep &swA, T *r, T *p0, T *p1, CgState *cs, const double *partsB, int nb_prev,
                       double tol, double *partsA, hipStream_t st) {
-  with_depth_policy(swA, [&](auto d, auto n) {
-    cg_selfred_a_kernel<T, decltype(d)::value, decltype(n)::value>
-        <<<sweep_blocks(swA), NT, 0, st>>>(swA, r, p0, p1, cs, partsB, nb_prev, tol, partsA);
+  with_shape(swA, [&](auto d, auto n, auto ty) {
+    constexpr int TY = decltype(ty)::value;
+    cg_selfred_a_kernel<T, decltype(d)::value, decltype(n)::value, TY>
+        <<<sweep_blocks(swA), Tile<TY>::NT, 0, st>>>(swA, r, p0, p1, cs, partsB, nb_prev, tol, partsA);
   });
 }
 
 template <typename T>
 void launch_selfred_b(const Sweep &swB, T *u, T *r, T *p0, T *p1, CgState *cs, const double *partsA,
                       int nbA, double *partsB, hipStream_t st) {
-  with_depth_policy(swB, [&](auto d, auto n) {
-    cg_selfred_b_kernel<T, decltype(d)::value, decltype(n)::value>
-        <<<sweep_blocks(swB), NT, 0, st>>>(swB, u, r, p0, p1, cs, partsA, nbA, partsB);
+  with_shape(swB, [&](auto d, auto n, auto ty) {
+    constexpr int TY = decltype(ty)::value;
+    cg_selfred_b_kernel<T, decltype(d)::value, decltype(n)::value, TY>
+        <<<sweep_blocks(swB), Tile<TY>::NT, 0, st>>>(swB, u, r, p0, p1, cs, partsA, nbA, partsB);
   });
 }
 
@@ -1661,17 +1693,19 @@ template void launch_selfred_b<float>(const Sweep &, float *, float *, float *, 
 
 int selfred_max_blocks() { return kSelfRedMaxBlocks; }
 
-void launch_residual(const Sweep &sw, const double *u, const RhsSrc &rs, double *r, CgState *cs, double *partials,
+void launch_residual(const Sweep &sw_in, const double *u, const RhsSrc &rs, double *r, CgState *cs, double *partials,
                      double tol, int max_iters, int hist_on, hipStream_t st) {
+  const Sweep sw = default_height(sw_in);
   const int nb = sweep_blocks(sw);
   launch_boundary_terms(rs, sw.g, r, st);
   launch_resid(sw, u, rs, r, partials, st);
   finalize_init_kernel<<<1, FT, 0, st>>>(cs, partials, nb, tol, max_iters, hist_on);
 }
 
-void launch_residual_cast(const Sweep &sw, const double *u, const RhsSrc &rs, double *bterm, const Grid &g32,
+void launch_residual_cast(const Sweep &sw_in, const double *u, const RhsSrc &rs, double *bterm, const Grid &g32,
                           float *r32, float *d32, CgState *outer, CgState *inner, double *partials, double tol,
                           double eta, int outer_step, int max_outer, int max_inner, hipStream_t st) {
+  const Sweep sw = default_height(sw_in);
   const int nb = sweep_blocks(sw);
   launch_boundary_terms(rs, sw.g, bterm, st);
   const int v = (sw.depth == 3 ? 2 : 0) + sw.nt;
@@ -1685,8 +1719,10 @@ void launch_residual_cast(const Sweep &sw, const double *u, const RhsSrc &rs, do
 template <typename T>
 void launch_cg_pass_a(const Sweep &sw, T *r, T *p0, T *p1, CgState *cs, double *partials, hipStream_t st) {
   const int nb = sweep_blocks(sw);
-  with_depth_policy(sw, [&](auto d, auto n) {
-    cg_pass_a_kernel<T, decltype(d)::value, decltype(n)::value><<<nb, NT, 0, st>>>(sw, r, p0, p1, cs, partials);
+  with_shape(sw, [&](auto d, auto n, auto ty) {
+    constexpr int TY = decltype(ty)::value;
+    cg_pass_a_kernel<T, decltype(d)::value, decltype(n)::value, TY>
+        <<<nb, Tile<TY>::NT, 0, st>>>(sw, r, p0, p1, cs, partials);
   });
   finalize_a_kernel<<<1, FT, 0, st>>>(cs, partials, nb);
 }
@@ -1695,8 +1731,10 @@ template <typename T>
 void launch_cg_pass_b(const Sweep &sw, T *u, T *r, T *p0, T *p1, CgState *cs, double *partials,
                       hipStream_t st) {
   const int nb = sweep_blocks(sw);
-  with_depth_policy(sw, [&](auto d, auto n) {
-    cg_pass_b_kernel<T, decltype(d)::value, decltype(n)::value><<<nb, NT, 0, st>>>(sw, u, r, p0, p1, cs, partials);
+  with_shape(sw, [&](auto d, auto n, auto ty) {
+    constexpr int TY = decltype(ty)::value;
+    cg_pass_b_kernel<T, decltype(d)::value, decltype(n)::value, TY>
+        <<<nb, Tile<TY>::NT, 0, st>>>(sw, u, r, p0, p1, cs, partials);
   });
   finalize_b_kernel<<<1, FT, 0, st>>>(cs, partials, nb);
 }
