@@ -732,6 +732,23 @@ def main():
                                "sample": f"the whole step ({N}^3 cells, solve with EXP_true + gradient) on the same "
                                          f"inputs, {len(runs)} runs, median {secs:.2f} s; oracle iterations "
                                          f"{[int(v) for v in r['iters']]}"}
+        # and on one thread, the same step at half the cells per axis (one run)
+        n1 = (N // 2,) * 3
+        f1, g1, _ = synth.sample(p, n1)
+        oracle.set_threads(1)
+        t0 = time.perf_counter()
+        r1 = oracle.excmg(f1, g1, p.box, stats[-1]["n"][0], args.tol, want_ext=True)
+        oracle.gradient(r1["u"], p.box)
+        secs1 = time.perf_counter() - t0
+        oracle.set_threads(threads)
+        L1 = len(r1["iters"])
+        cells1 = [tuple(v // 2 ** (L1 - 1 - q) for v in n1) for q in range(L1)]
+        ui_1 = sum((a - 1) * (b - 1) * (c - 1) * int(it) for (a, b, c), it in zip(cells1, r1["iters"]))
+        out["cpu_baseline"]["one_thread"] = {
+            "value": round(ui_1 / secs1 / 1e9, 4), "unit": "Gunknown-iters/s", "cores": 1,
+            "sample": f"the whole step at {N // 2}^3 cells (solve with EXP_true + gradient), one run, {secs1:.2f} s; "
+                      f"oracle iterations {[int(v) for v in r1['iters']]}"}
+        print(f"# oracle on one thread at {N // 2}^3: {secs1:.2f} s", file=sys.stderr, flush=True)
 
     print(json.dumps(out), flush=True)
 
