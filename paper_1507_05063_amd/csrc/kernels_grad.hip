@@ -360,35 +360,37 @@ __global__ __launch_bounds__(64) void grad_x_short_kernel(Grid gu, const double 
 }
 
 // y and z lines: one thread per line, consecutive threads on consecutive x, so every step of the sweeps is a
-// coalesced row access.  A workgroup takes 64 lines of one plane (k for y lines, j for z lines).  The y-line
-// workgroups are numbered so that all x blocks of a plane run on the same XCD (the hardware deals consecutive
-// workgroups to the 8 XCDs in turn): the row segments they write meet inside cache lines of the caller's unpadded
-// rows, and a line written from two XCDs goes out to memory in pieces.  (The z lines write a different plane at
-// every step, and measured no better for it.)
+// coalesced row access.  The lines are numbered x fastest, then the other cross axis (k for y lines, j for z lines),
+// and a wavefront takes 64 consecutive numbers (at a row end the rest of the wavefront goes on with the next row), so
+// that no wavefront is left with the one or few lines past the last full 64 of a row: every wavefront runs a whole
+// line's length whatever its lines.  Wavefront numbers are dealt XCD by XCD (the hardware hands consecutive
+// workgroups to the 8 XCDs in turn), so that neighbouring wavefronts, whose row segments meet inside cache lines of
+// the caller's unpadded rows, write them from one XCD's L2.
 constexpr int kXcd = 8;
 constexpr int kLineWg = 64;
 
-__device__ __forceinline__ bool plane_block(int nbx, int nplanes, int &bx, int &plane) {
-  const int x = blockIdx.x % kXcd, rest = blockIdx.x / kXcd;
-  bx = rest % nbx;
-  plane = (rest / nbx) * kXcd + x;
-  return plane < nplanes;
+// logical wavefront of workgroup b of nb: consecutive logical numbers on one XCD
+__device__ __forceinline__ int xcd_wave(int b, int nb) {
+  const int per = nb / kXcd, rem = nb % kXcd;
+  const int x = b % kXcd, l = b / kXcd;
+  return ((x < rem) ? x * (per + 1) : rem * (per + 1) + (x - rem) * per) + l;
 }
 
 __global__ __launch_bounds__(kLineWg) void grad_y_kernel(Grid gu, const double *__restrict__ u, Grid gd, double *uy,
                                                          double hy, const double *__restrict__ inv_m) {
-  int bx, k;
-  if (!plane_block((gu.nx + kLineWg) / kLineWg, gu.nz + 1, bx, k)) return;
-  const int i = bx * kLineWg + threadIdx.x;
-  if (i > gu.nx) return;
+  const long long line = (long long)xcd_wave(blockIdx.x, gridDim.x) * kLineWg + threadIdx.x;
+  const int nxl = gu.nx + 1;
+  if (line >= (long long)nxl * (gu.nz + 1)) return;
+  const int i = (int)(line % nxl), k = (int)(line / nxl);
   line_solve(u, gu.at(i, 0, k), gu.sy, uy, gd.at(i, 0, k), gd.sy, gu.ny, hy, inv_m);
 }
 
 __global__ __launch_bounds__(kLineWg) void grad_z_kernel(Grid gu, const double *__restrict__ u, Grid gd, double *uz,
                                                          double hz, const double *__restrict__ inv_m) {
-  const int i = blockIdx.x * kLineWg + threadIdx.x;
-  const int j = blockIdx.y;
-  if (i > gu.nx) return;
+  const long long line = (long long)xcd_wave(blockIdx.x, gridDim.x) * kLineWg + threadIdx.x;
+  const int nxl = gu.nx + 1;
+  if (line >= (long long)nxl * (gu.ny + 1)) return;
+  const int i = (int)(line % nxl), j = (int)(line / nxl);
   line_solve(u, gu.at(i, j, 0), gu.sz, uz, gd.at(i, j, 0), gd.sz, gu.nz, hz, inv_m);
 }
 
@@ -403,9 +405,9 @@ void launch_gradient(const Grid &gu, const double *u, const Grid &gd, double *ux
     grad_x_short_kernel<<<std::min(nlines, 8192), 64, 0, st>>>(gu, u, gd, ux, hx, inv_m_x);
   else
     grad_x_scan_kernel<<<nlines, 64, (size_t)nseg * sizeof(double), st>>>(gu, u, gd, ux, hx, inv_m_x);
-  const int nbx = (gu.nx + kLineWg) / kLineWg;  // x blocks of nx + 1 nodes
-  grad_y_kernel<<<nbx * ((gu.nz + 1 + kXcd - 1) / kXcd) * kXcd, kLineWg, 0, st>>>(gu, u, gd, uy, hy, inv_m_y);
-  grad_z_kernel<<<dim3(nbx, gu.ny + 1), kLineWg, 0, st>>>(gu, u, gd, uz, hz, inv_m_z);
+  const long long ylines = (long long)(gu.nx + 1) * (gu.nz + 1), zlines = (long long)(gu.nx + 1) * (gu.ny + 1);
+  grad_y_kernel<<<(int)((ylines + kLineWg - 1) / kLineWg), kLineWg, 0, st>>>(gu, u, gd, uy, hy, inv_m_y);
+  grad_z_kernel<<<(int)((zlines + kLineWg - 1) / kLineWg), kLineWg, 0, st>>>(gu, u, gd, uz, hz, inv_m_z);
 }
 
 }  // namespace excmg

@@ -82,7 +82,8 @@ def test_exp_finite(ex, orc, n):
     assert relmax(w, ref) <= 1e-13
 
 
-@pytest.mark.parametrize("n", [(16, 8, 24), (70, 6, 10), (2, 2, 2)])
+@pytest.mark.parametrize("n", [(16, 8, 24), (70, 6, 10), (2, 2, 2),
+                               (18, 20, 70), (130, 10, 34)])  # z chunks of 32 planes with a ragged last one
 def test_exp_true(ex, orc, n):
     uh = rnd(n)
     u2 = rnd(tuple(v // 2 for v in n))
