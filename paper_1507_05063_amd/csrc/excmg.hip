@@ -36,6 +36,7 @@ struct Level {
   Stencil st;
   Sweep sw, sw32;  // stencil sweeps over g and g32 (residual kernels)
   Sweep swA, swB, swA32, swB32;  // CG passes A and B in FP64 and FP32 (z chunk chosen by the autotuner)
+  Sweep swA0, swB0;  // the FP64 passes of a grid's first iteration (p = r), on grids whose passes finalize apart
   double *u;   // this grid's solution, all nodes (boundary = g)
 };
 
@@ -152,6 +153,7 @@ int make_layout(const excmg_problem *p, Layout *Lo) {
     lv.sw = make_sweep(lv.g, lv.st, big ? kResidChunk : 0, 2, big ? 1 : 0);
     lv.sw32 = make_sweep(lv.g32, lv.st, 0);
     lv.swA = lv.swB = make_sweep(lv.g, lv.st, 0, 2, big ? 1 : 0);
+    lv.swA0 = lv.swB0 = lv.swA;
     lv.swA32 = lv.swB32 = lv.sw32;
     lv.u = nullptr;
     Lo->off_u[l] = off;
@@ -422,12 +424,15 @@ void launch_iteration(excmg_handle *h, int l, int fp32, bool first, hipStream_t 
     Tick t(h, EXCMG_K_CG_B, l, launched);
     launch_selfred_b<double>(lv.swB, lv.u, h->r, h->p0, h->p1, h->cs, pa, sweep_blocks(lv.swA), pb, s);
   } else {
+    // the first iteration (launched 0; launches past it always follow it) in its own tuned shapes: each pass's
+    // finalize kernel sums as many partials as that launch wrote
+    const bool it0 = launched == 0;
     {
       Tick t(h, EXCMG_K_CG_A, l, launched);
-      launch_cg_pass_a<double>(lv.swA, h->r, h->p0, h->p1, h->cs, h->partials, s);
+      launch_cg_pass_a<double>(it0 ? lv.swA0 : lv.swA, h->r, h->p0, h->p1, h->cs, h->partials, s);
     }
     Tick t(h, EXCMG_K_CG_B, l, launched);
-    launch_cg_pass_b<double>(lv.swB, lv.u, h->r, h->p0, h->p1, h->cs, h->partials, s);
+    launch_cg_pass_b<double>(it0 ? lv.swB0 : lv.swB, lv.u, h->r, h->p0, h->p1, h->cs, h->partials, s);
   }
 }
 
@@ -1524,11 +1529,18 @@ int excmg_autotune(excmg_handle *h, int32_t *zc_out, int32_t *depth_out) {
     // keep it self-finalizing; their launches are short, so each trial times a burst of them queued behind a delay
     // (back to back, as in a graph) instead of one launch between two events, whose own cost would hide the kernel.
     const bool burst = use_graphs(h, l) && sweep_blocks(lv.sw) <= selfred_max_blocks();
-    for (int prec = 0; prec < (ir ? 2 : 1) && rc == EXCMG_OK; ++prec) {
+    // kinds: FP64 passes, FP32 passes (refinement grids), and the FP64 passes of the first iteration (p = r: pass A
+    // reads r alone, pass B takes p from r's buffer) on grids whose passes finalize apart
+    for (int kind = 0; kind < 3 && rc == EXCMG_OK; ++kind) {
+      if ((kind == 1 && !ir) || (kind == 2 && burst)) continue;
+      const int prec = kind == 1;
+      const bool first = kind == 2;
       const Grid &g = prec ? lv.g32 : lv.g;
       for (int pass = 0; pass < 2 && rc == EXCMG_OK; ++pass) {
         float best = 1e30f;
-        Sweep bsw = prec ? (pass ? lv.swB32 : lv.swA32) : (pass ? lv.swB : lv.swA);
+        Sweep &dst = first ? (pass ? lv.swB0 : lv.swA0)
+                           : prec ? (pass ? lv.swB32 : lv.swA32) : (pass ? lv.swB : lv.swA);
+        Sweep bsw = dst;
         // partial sums the trial pass reads: as many as the other pass's current shape writes (at most the
         // self-finalizing limit; no sweep of a grid has more workgroups than its 2-plane chunks, which the
         // partials' halves hold three times over)
@@ -1548,7 +1560,7 @@ int excmg_autotune(excmg_handle *h, int32_t *zc_out, int32_t *depth_out) {
               launch_tune_selfred(h->cs2, pass ? pa : pb, nb_other, s);
               launch_delay(kTuneDelayUs, s);
             } else {
-              launch_tune_state(h->cs2, s);
+              launch_tune_state(h->cs2, first ? 0 : 1, s);
             }
             if (hipEventRecord(ea, s) != hipSuccess) rc = EXCMG_ERR_HIP;
             for (int q = 0; q < (burst ? kTuneBurst : 1); ++q) {
@@ -1560,9 +1572,10 @@ int excmg_autotune(excmg_handle *h, int32_t *zc_out, int32_t *depth_out) {
                 else launch_selfred_b<float>(sw, h->d32, h->r32, h->p32a, h->p32b, h->cs2, pa, nb_other, pb, s);
               } else if (prec == 0) {
                 if (pass == 0) launch_cg_pass_a<double>(sw, h->r, h->p0, h->p1, h->cs2, h->partials, s);
-                // u: r's buffer, which iteration 1 does not use (r is in p0, p in p1), so that the trial reads
-                // three distinct arrays as a real pass B does
-                else launch_cg_pass_b<double>(sw, h->r, h->r, h->p0, h->p1, h->cs2, h->partials, s);
+                // u: a buffer the iteration does not use (iteration 1: r's, with r in p0 and p in p1; iteration 0:
+                // p1, with r and p in r's buffer and the new r going to p0), so that the trial touches distinct
+                // arrays as a real pass B does
+                else launch_cg_pass_b<double>(sw, first ? h->p1 : h->r, h->r, h->p0, h->p1, h->cs2, h->partials, s);
               } else {
                 if (pass == 0) launch_cg_pass_a<float>(sw, h->r32, h->p32a, h->p32b, h->cs2, h->partials, s);
                 else launch_cg_pass_b<float>(sw, h->d32, h->r32, h->p32a, h->p32b, h->cs2, h->partials, s);
@@ -1582,8 +1595,7 @@ int excmg_autotune(excmg_handle *h, int32_t *zc_out, int32_t *depth_out) {
             bsw = sw;
           }
         }
-        if (prec == 0) (pass ? lv.swB : lv.swA) = bsw;
-        else (pass ? lv.swB32 : lv.swA32) = bsw;
+        dst = bsw;
       }
     }
   }

@@ -261,7 +261,7 @@ void launch_cg_pass_b(const Sweep &sw, T *u, T *r, T *p0, T *p1, CgState *cs, do
                       hipStream_t st);
 
 // CG state for timing sweeps in isolation: iteration 0, alpha = beta = 0, never done
-void launch_tune_state(CgState *cs, hipStream_t st);
+void launch_tune_state(CgState *cs, int iter, hipStream_t st);  // at iteration iter (0 or 1)
 // the trial state of the self-finalizing passes in cs, and parts[0, n) = 1 (n <= the self-finalizing limit)
 void launch_tune_selfred(CgState *cs, double *parts, int n, hipStream_t st);
 // a single-wave kernel that returns after about `us` microseconds (bounded), to queue launches behind it

@@ -939,7 +939,11 @@ __device__ void tune_state(CgState *cs) {
   cs->hist_on = 0;
 }
 
-__global__ void tune_state_kernel(CgState *cs) { tune_state(cs); }
+// the same at iteration iter: 0 for the trials of a first iteration's passes (p = r)
+__global__ void tune_state_kernel(CgState *cs, int iter) {
+  tune_state(cs);
+  cs->iter = iter;
+}
 
 // the trial state of a self-finalizing pass (iteration 1 of both passes, never converged) and n partial sums of 1 for
 // it to read, so that neither pass stops at its reduction
@@ -1748,7 +1752,7 @@ template void launch_cg_pass_b<double>(const Sweep &, double *, double *, double
 template void launch_cg_pass_b<float>(const Sweep &, float *, float *, float *, float *, CgState *,
                                       double *, hipStream_t);
 
-void launch_tune_state(CgState *cs, hipStream_t st) { tune_state_kernel<<<1, 1, 0, st>>>(cs); }
+void launch_tune_state(CgState *cs, int iter, hipStream_t st) { tune_state_kernel<<<1, 1, 0, st>>>(cs, iter); }
 
 void launch_tune_selfred(CgState *cs, double *parts, int n, hipStream_t st) {
   tune_selfred_kernel<<<1, 256, 0, st>>>(cs, parts, n);
