@@ -597,16 +597,21 @@ struct RhsPart {
 
 constexpr int kSelfRedMaxBlocks = 2048;
 
-// fixed-order sum by a whole workgroup of NTB threads; valid in every thread
+// fixed-order sum by a whole workgroup of NTB threads of the threads' strided parts v (strided_sum<NTB>); valid in
+// every thread
 template <int NTB>
-__device__ double block_fixed_sum(const double *a, int n, double *sh) {
-  const double t = block_sum<NTB>(strided_sum<NTB>(a, n), sh);
+__device__ double block_fixed_finish(double v, double *sh) {
+  const double t = block_sum<NTB>(v, sh);
   if (threadIdx.x == 0) sh[NTB / 64] = t;
   __syncthreads();
   const double s = sh[NTB / 64];
   __syncthreads();
   return s;
 }
+
+// Makes v be computed here, before what follows (an empty statement that takes it as an input), so that loads
+// feeding it are not moved past a branch that does not use it.
+__device__ __forceinline__ void keep(double v) { __asm__ volatile("" ::"v"(v)); }
 
 // Pass A of iteration k = iterA: the stopping test on rho_k (Algorithm 1, the while condition), then
 // p = r + beta p with beta = rho_k / rho_{k-1}, partial sums of p.Mp into partsA.
@@ -618,19 +623,25 @@ __global__ __launch_bounds__(Tile<TY>::NT) void cg_selfred_a_kernel(Sweep sw, T 
   __shared__ T tile[2][Tile<TY>::Rows][TX + 2];
   __shared__ double sh[NTB / 64];
   __shared__ double shf[NTB];
-  if (cs->done) return;
+  // The state and the partial sums are loaded together, so that they cost one memory latency: the second half of
+  // the partials (the residual sweep's b.b) is used at k = 0 only and read at every k (it lies inside the buffer).
+  const int done = cs->done;
   const int k = cs->iterA;
+  const double s1 = strided_sum<NTB>(partsB, nbB), s2 = strided_sum<NTB>(partsB + nbB, nbB);
+  keep(s1);
+  keep(s2);
+  if (done) return;
   double rho, bb, stop2;
   if (k == 0 && cs->preset) {
     rho = cs->rho;
     bb = cs->bnorm2;
     stop2 = cs->stop2;
   } else if (k == 0) {
-    rho = block_fixed_sum<NTB>(partsB, nbB, shf);
-    bb = block_fixed_sum<NTB>(partsB + nbB, nbB, shf) + cs->gbnd2;
+    rho = block_fixed_finish<NTB>(s1, shf);
+    bb = block_fixed_finish<NTB>(s2, shf) + cs->gbnd2;
     stop2 = tol * tol * bb;
   } else {
-    rho = block_fixed_sum<NTB>(partsB, nbB, shf);
+    rho = block_fixed_finish<NTB>(s1, shf);
     bb = cs->bnorm2;
     stop2 = cs->stop2;
   }
@@ -671,9 +682,12 @@ __global__ __launch_bounds__(Tile<TY>::NT) void cg_selfred_b_kernel(Sweep sw, T 
   __shared__ T tile[2][Tile<TY>::Rows][TX + 2];
   __shared__ double sh[NTB / 64];
   __shared__ double shf[NTB];
-  if (cs->done) return;
+  const int done = cs->done;  // loaded together with the partials, as in pass A
   const int k = cs->iterB;
-  const double pq = block_fixed_sum<NTB>(partsA, nbA, shf);
+  const double s1 = strided_sum<NTB>(partsA, nbA);
+  keep(s1);
+  if (done) return;
+  const double pq = block_fixed_finish<NTB>(s1, shf);
   const bool bad = !(pq > 0.0) || !isfinite(pq);
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     cs->pq = pq;
