@@ -74,11 +74,11 @@ def trace_summary(db, top=30):
         for (nm, gx, wx), ds in sorted(groups.items(), key=lambda kv: -sum(kv[1]))[:top]:
             line(nm, gx, wx, ds)
         print()
-        print("The other kernels of a step (not the CG passes, the autotuner's or the runtime's; working average at "
-              "least 50 us):")
+        print("The other kernels of a step (not the CG passes, the autotuner's, the bandwidth probe's or the runtime's; "
+              "working average at least 50 us):")
         print(f"{'kernel':44s} {'grid':>9s} {'wg':>5s} {'calls':>6s} {'total_ms':>9s} {'avg_us':>9s} "
               f"{'working':>7s} {'work_avg_us':>11s}")
-        skip = ("cg_pass_", "cg_selfred_", "tune_state", "__amd", "finalize_")
+        skip = ("cg_pass_", "cg_selfred_", "tune_", "delay_", "probe_", "__amd", "finalize_")
         for (nm, gx, wx), ds in sorted(groups.items(), key=lambda kv: -sum(kv[1])):
             if nm.startswith(skip):
                 continue

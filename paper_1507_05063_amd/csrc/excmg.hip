@@ -1460,9 +1460,9 @@ int solve_on(excmg_handle *h, const double *f, const double *g, double *u, doubl
 }  // namespace
 
 // launches per trial of a self-finalizing pass, and the delay they are queued behind (longer than it takes the host
-// to queue them)
+// to queue them: about 5 us per launch)
 constexpr int kTuneBurst = 8;
-constexpr double kTuneDelayUs = 300.0;
+constexpr double kTuneDelayUs = 120.0;
 
 extern "C" {
 
@@ -1555,7 +1555,7 @@ int excmg_autotune(excmg_handle *h, int32_t *zc_out, int32_t *depth_out) {
           if (3LL * sweep_blocks(sw) > lo.npart) continue;
           if (burst && sweep_blocks(sw) > selfred_max_blocks()) continue;
           float tmin = 1e30f;
-          for (int rep = 0; rep < 4; ++rep) {
+          for (int rep = 0; rep < 3; ++rep) {
             if (burst) {
               launch_tune_selfred(h->cs2, pass ? pa : pb, nb_other, s);
               launch_delay(kTuneDelayUs, s);
