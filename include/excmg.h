@@ -242,6 +242,25 @@ int excmg_autotune_batched(excmg_handle *const *hs, int32_t count, void *batch_w
  * ordinary). */
 int excmg_autotune(excmg_handle *h, int32_t *zc_out, int32_t *depth_out);
 
+/* Sweep shapes (host calls).  A sweep of grid `level` (0 = coarsest) of kind EXCMG_SWEEP_*: the CG passes A and B in
+ * FP64, in FP32 (EXCMG_FP32_IR), and the FP64 passes of a grid's first iteration (used on grids whose passes do not
+ * finalize their own reductions).  shape[4] (host) = {z chunk in planes (even, 2..4096), prefetch depth (2, 3, 4 or
+ * 6), non-temporal policy (0 or 1), tile height in rows of 64 nodes (4, 8 or 16)}.  excmg_get_sweep reads the shape
+ * in use (the setup's default or the autotuner's choice); excmg_set_sweep replaces it for every later call on this
+ * handle (so that a shape found by excmg_autotune can be saved and restored without tuning again, or a shape
+ * forced), after waiting for the handle's stream, and drops the handle's captured iteration graphs.  Results depend
+ * on the shape only through the order of the partial sums (rounding).  Errors: EXCMG_ERR_ARG for a null handle or
+ * shape, a level or kind out of range, a value outside the sets above, or a shape with more workgroups than the
+ * handle's partial-sum buffer holds (chunks of 2 planes at 4 rows always fit); EXCMG_ERR_HIP. */
+#define EXCMG_SWEEP_A 0
+#define EXCMG_SWEEP_B 1
+#define EXCMG_SWEEP_A32 2
+#define EXCMG_SWEEP_B32 3
+#define EXCMG_SWEEP_A_FIRST 4
+#define EXCMG_SWEEP_B_FIRST 5
+int excmg_get_sweep(excmg_handle *h, int32_t level, int32_t kind, int32_t shape[4]);
+int excmg_set_sweep(excmg_handle *h, int32_t level, int32_t kind, const int32_t shape[4]);
+
 /* Host call.  Turns the kernel timing of EXCMG_WANT_TIMING on (on != 0) or off for later calls on this handle, as
  * if the flag had been given at setup (the timing events are created the first time it is turned on).  The solver's
  * results do not depend on it; the timing only adds event records between the finest grid's launches.  Waits for the

@@ -175,6 +175,22 @@ class Solver:
                    "excmg_batch_graph_counts")
         return r.value, c.value
 
+    SWEEP_KINDS = {"a": 0, "b": 1, "a32": 2, "b32": 3, "a_first": 4, "b_first": 5}
+
+    def get_sweep(self, level: int, kind: str):
+        """(z chunk, prefetch depth, non-temporal policy, tile height) of a CG sweep of grid `level` (0 = coarsest);
+        kind: "a", "b" (FP64 passes), "a32", "b32" (FP32 refinement), "a_first", "b_first" (a grid's first
+        iteration)."""
+        sh = (ctypes.c_int32 * 4)()
+        _lib.check(_lib.lib().excmg_get_sweep(self._h, int(level), self.SWEEP_KINDS[kind], sh), "excmg_get_sweep")
+        return tuple(sh)
+
+    def set_sweep(self, level: int, kind: str, shape):
+        """Use shape = (z chunk, prefetch depth, non-temporal policy, tile height) for that sweep from now on (for
+        example one saved from get_sweep after autotune)."""
+        sh = (ctypes.c_int32 * 4)(*[int(v) for v in shape])
+        _lib.check(_lib.lib().excmg_set_sweep(self._h, int(level), self.SWEEP_KINDS[kind], sh), "excmg_set_sweep")
+
     def set_timing(self, on: bool):
         """Kernel timing (stats kernel_ms, kernel_calls) on or off for later calls."""
         _lib.check(_lib.lib().excmg_set_timing(self._h, 1 if on else 0), "excmg_set_timing")

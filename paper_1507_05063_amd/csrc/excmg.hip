@@ -1635,6 +1635,49 @@ int excmg_batch_graph_counts(const excmg_handle *h, int64_t *replays, int64_t *c
   return EXCMG_OK;
 }
 
+namespace {
+// the sweep of grid l that kind names (EXCMG_SWEEP_*), or null
+Sweep *sweep_of(excmg_handle *h, int l, int kind) {
+  if (!h || l < 0 || l >= h->lo.L) return nullptr;
+  Level &lv = h->lo.lev[l];
+  switch (kind) {
+    case EXCMG_SWEEP_A: return &lv.swA;
+    case EXCMG_SWEEP_B: return &lv.swB;
+    case EXCMG_SWEEP_A32: return &lv.swA32;
+    case EXCMG_SWEEP_B32: return &lv.swB32;
+    case EXCMG_SWEEP_A_FIRST: return &lv.swA0;
+    case EXCMG_SWEEP_B_FIRST: return &lv.swB0;
+    default: return nullptr;
+  }
+}
+}  // namespace
+
+int excmg_get_sweep(excmg_handle *h, int32_t level, int32_t kind, int32_t shape[4]) {
+  const Sweep *sw = sweep_of(h, level, kind);
+  if (!sw || !shape) return EXCMG_ERR_ARG;
+  shape[0] = sw->zc;
+  shape[1] = sw->depth;
+  shape[2] = sw->nt;
+  shape[3] = sw->ty;
+  return EXCMG_OK;
+}
+
+int excmg_set_sweep(excmg_handle *h, int32_t level, int32_t kind, const int32_t shape[4]) {
+  Sweep *sw = sweep_of(h, level, kind);
+  if (!sw || !shape) return EXCMG_ERR_ARG;
+  const int zc = shape[0], depth = shape[1], nt = shape[2], ty = shape[3];
+  if (zc < 2 || (zc & 1) || zc > 4096 || !(depth == 2 || depth == 3 || depth == 4 || depth == 6) ||
+      !(nt == 0 || nt == 1) || !(ty == 4 || ty == 8 || ty == 16))
+    return EXCMG_ERR_ARG;
+  const Sweep nw = make_sweep(sw->g, sw->st, zc, depth, nt, ty);
+  if (3LL * sweep_blocks(nw) > h->lo.npart) return EXCMG_ERR_ARG;  // more workgroups than the partial sums hold
+  DeviceGuard dg(h->device);
+  HIPCHECK(hipStreamSynchronize(h->stream));  // no launch of an earlier call still uses the old shape
+  *sw = nw;
+  h->drop_graphs();  // captured with the old sweep shapes
+  return EXCMG_OK;
+}
+
 int excmg_set_timing(excmg_handle *h, int32_t on) {
   if (!h) return EXCMG_ERR_ARG;
   DeviceGuard dg(h->device);

@@ -89,6 +89,9 @@ def test_bad_arguments(abi):
     L = abi.lib()
     assert L.excmg_plan(None, None, None) == abi.ERR_ARG
     assert L.excmg_set_timing(None, 1) == abi.ERR_ARG
+    sh = (ctypes.c_int32 * 4)(16, 2, 0, 4)
+    assert L.excmg_get_sweep(None, 0, 0, sh) == abi.ERR_ARG
+    assert L.excmg_set_sweep(None, 0, 0, sh) == abi.ERR_ARG
 
 
 @pytest.mark.parametrize("flags,tol_order,ok", [(0, 0.0, True), (0, 6.0, True), (0, 16.0, True), (0, -1.0, False),

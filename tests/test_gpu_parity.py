@@ -284,6 +284,46 @@ def test_history_and_timing(ex):
     assert st["kernel_ms"]["cg_b"] > 0
 
 
+# Every tile height, prefetch depth and cache policy of the CG sweeps, forced on every relaxed grid of a problem whose
+# grids leave ragged tiles in x, y and z (coarsest 10 x 6 x 14: interiors of 39 x 23 x 55 and 79 x 47 x 111 unknowns
+# on the two swept grids), with chunks of 2 planes and of 6 (a short last chunk), against the oracle.
+@pytest.mark.parametrize("ty", [4, 8, 16])
+@pytest.mark.parametrize("depth,nt,zc", [(2, 0, 2), (3, 1, 6), (6, 1, 6), (4, 0, 2)])
+def test_forced_sweep_shapes_match_oracle(ex, orc, ty, depth, nt, zc):
+    p = synth.smooth(5, (1.0, 0.6, 1.4))
+    n = (80, 48, 112)
+    f, g, _ = synth.sample(p, n)
+    tol = 1e-10
+    s = ex.Solver(n, p.box, tol, n_coarse=(10, 6, 14))
+    for l in range(2, s.levels):
+        for kind in ("a", "b", "a_first", "b_first"):
+            s.set_sweep(l, kind, (zc, depth, nt, ty))
+            assert s.get_sweep(l, kind) == (zc, depth, nt, ty)
+    ug, _, st = s.solve(dev(f), dev(g))
+    ref = orc.excmg(f, g, p.box, s.n_coarse, tol, fixed_iters=np.array(st["iters"], dtype=np.int32))
+    assert rel2(host(ug), ref["u"]) <= 1e-12
+    free = orc.excmg(f, g, p.box, s.n_coarse, tol)
+    assert np.all(np.abs(np.array(st["iters"]) - free["iters"]) <= 1), (st["iters"], free["iters"])
+
+
+def test_sweep_shape_roundtrip_and_errors(ex):
+    """The shapes the autotuner chose can be read back and set on another handle; bad shapes are refused."""
+    n = (64, 32, 32)
+    a = ex.Solver(n, (1.0, 0.8, 1.1), 1e-10)
+    a.autotune()
+    b = ex.Solver(n, (1.0, 0.8, 1.1), 1e-10)
+    for l in range(a.levels):
+        for kind in ("a", "b", "a_first", "b_first"):
+            b.set_sweep(l, kind, a.get_sweep(l, kind))
+            assert b.get_sweep(l, kind) == a.get_sweep(l, kind)
+    for bad in [(3, 2, 0, 4), (0, 2, 0, 4), (16, 5, 0, 4), (16, 2, 2, 4), (16, 2, 0, 12)]:
+        with pytest.raises(ex.ExcmgError) as e:
+            b.set_sweep(a.levels - 1, "a", bad)
+        assert e.value.code == ex._lib.ERR_ARG
+    with pytest.raises(ex.ExcmgError):
+        b.get_sweep(a.levels, "a")
+
+
 def test_autotuned_solve_matches_oracle(ex, orc):
     """After the autotuner picks other z chunks, the solve is still the oracle's (to the parity bar)."""
     p = synth.smooth(2, (1.0, 0.8, 1.1))
