@@ -434,3 +434,22 @@ def test_bandwidth_probe(ex):
     assert set(rates) == set(ex.PROBE_KINDS)
     for k, v in rates.items():
         assert 100.0 < v < 12000.0, (k, v)
+
+
+# The FP32 passes of the refinement (EXCMG_FP32_IR relaxes grids of 2^20 unknowns and more in FP32) at every tile
+# height on a grid with ragged tiles (127 x 95 x 111 unknowns), against the FP64 oracle at a tolerance where the
+# solution's error is the discretisation error: the mixed solve within 1% of that error from the oracle's solution.
+@pytest.mark.parametrize("ty", [4, 8, 16])
+def test_forced_fp32_sweep_shapes(ex, orc, ty):
+    p = synth.smooth(5, (1.0, 0.75, 0.875))
+    n = (128, 96, 112)
+    f, g, u = synth.sample(p, n)
+    tol = 1e-13
+    s = ex.Solver(n, p.box, tol, n_coarse=(16, 12, 14), precision=ex.FP32_IR)
+    for kind in ("a32", "b32"):
+        s.set_sweep(s.levels - 1, kind, (8, 4, 1, ty))
+    ug, _, st = s.solve(dev(f), dev(g))
+    assert st["ir_outer"][-1] >= 1  # the finest grid relaxed in FP32
+    ref = orc.excmg(f, g, p.box, s.n_coarse, tol)
+    rms = lambda a: float(np.sqrt(np.mean(np.square(a))))
+    assert rms(host(ug) - ref["u"]) <= 0.01 * rms(ref["u"] - u)
