@@ -206,7 +206,25 @@ def bench_batch(ex, synth, torch, args):
             "one_at_a_time_ms": round(seq_ms, 3), "speedup_vs_one_at_a_time": round(seq_ms / ms, 2),
             "batch_ms_default_chunks": round(ms_default, 3), "autotune_s": round(tune_s, 2),
             "round_graphs_replayed_captured": list(solvers[0].batch_graph_counts()),
-            "autotuned_z_chunks_fp64_fp32_by_grid_from_finest": {str(k): list(v) for k, v in zc.items()}}
+            "autotuned_z_chunks_fp64_fp32_by_grid_from_finest": {str(k): list(v) for k, v in zc.items()},
+            "autotuned_tile_heights": batch_heights(solvers)}
+
+
+def batch_heights(solvers):
+    """Tile heights of the batched CG passes after the batched autotuner, per precision: read from the grids that
+    relax in it (grids of more than 8000 interior unknowns; FP32 refinement from 2^20 on)."""
+    seen = {"fp64": set(), "fp32": set()}
+    for s in solvers:
+        for l in range(2, s.levels):
+            m = [c << l for c in s.n_coarse]
+            interior = (m[0] - 1) * (m[1] - 1) * (m[2] - 1)
+            if interior <= 8000:
+                continue
+            if interior >= 1 << 20:
+                seen["fp32"].add(s.get_sweep(l, "a32")[3])
+            else:
+                seen["fp64"].add(s.get_sweep(l, "a")[3])
+    return {k: sorted(v) for k, v in seen.items()}
 
 
 def bench_adjoint(ex, synth, torch, args):

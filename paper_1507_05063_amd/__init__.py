@@ -191,6 +191,17 @@ class Solver:
         sh = (ctypes.c_int32 * 4)(*[int(v) for v in shape])
         _lib.check(_lib.lib().excmg_set_sweep(self._h, int(level), self.SWEEP_KINDS[kind], sh), "excmg_set_sweep")
 
+    def get_batch_height(self):
+        """(FP64, FP32) tile heights of the batched CG passes of the batches this solver leads."""
+        ty = (ctypes.c_int32 * 2)()
+        _lib.check(_lib.lib().excmg_get_batch_height(self._h, ty), "excmg_get_batch_height")
+        return tuple(ty)
+
+    def set_batch_height(self, ty):
+        """Set the (FP64, FP32) tile heights (4, 8 or 16) of the batched CG passes of the batches this solver leads."""
+        t = (ctypes.c_int32 * 2)(*[int(v) for v in ty])
+        _lib.check(_lib.lib().excmg_set_batch_height(self._h, t), "excmg_set_batch_height")
+
     def set_timing(self, on: bool):
         """Kernel timing (stats kernel_ms, kernel_calls) on or off for later calls."""
         _lib.check(_lib.lib().excmg_set_timing(self._h, 1 if on else 0), "excmg_set_timing")

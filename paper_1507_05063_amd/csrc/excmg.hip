@@ -201,6 +201,8 @@ struct TimedLaunch {
 }  // namespace
 
 struct excmg_handle {
+  // tile height of the batched CG passes (FP64, FP32) when this handle leads a batch (excmg_autotune_batched)
+  int bty[2] = {4, 4};
   excmg_problem p;
   Layout lo;
   hipStream_t stream;
@@ -821,7 +823,7 @@ int batch_kind(const excmg_handle *h, int l) {
 }
 
 void batch_entry(excmg_handle *h, int problem, int l, const double *f, const double *g, double *u, BatchEntry *E,
-                 int blocks[kLaunchKinds]) {
+                 int blocks[kLaunchKinds], const int bty[2]) {
   memset(E, 0, sizeof(*E));
   for (int k = 0; k < kLaunchKinds; ++k) blocks[k] = 0;
   E->kind = batch_kind(h, l);
@@ -836,12 +838,13 @@ void batch_entry(excmg_handle *h, int problem, int l, const double *f, const dou
   E->max_outer = 30;
   E->tol = grid_tol(h->p, l, h->lo.L);
   E->eta = h->p.inner_tol > 0.0 ? h->p.inner_tol : 1e-5;
-  // the batched kernels are built for 4-row tiles: a grid tuned alone to taller ones keeps its z chunk here
-  E->swA = default_height(lv.swA);
-  E->swB = default_height(lv.swB);
+  // every entry of a batched launch has the launch's tile height (bty: the batch's, for the FP64 and the FP32
+  // passes); a grid tuned alone to another keeps its z chunk here
+  E->swA = with_height(lv.swA, bty[0]);
+  E->swB = with_height(lv.swB, bty[0]);
   E->swR = default_height(lv.sw);
-  E->swA32 = default_height(lv.swA32);
-  E->swB32 = default_height(lv.swB32);
+  E->swA32 = with_height(lv.swA32, bty[1]);
+  E->swB32 = with_height(lv.swB32, bty[1]);
   E->g = lv.g;
   E->g32 = lv.g32;
   E->gd = lo.gdense;
@@ -904,15 +907,16 @@ int batch_iterations(excmg_handle *h0, const char *ws, int it, int nb64, int nb3
   const hipStream_t s = h0->stream;
   auto launch_all = [&](hipStream_t st) {
     for (int q = 0; q < it; ++q) {
-      if (q < nb64) launch_b_iteration(0, l64[0], l64[1], stat, st);
-      if (q < nb32) launch_b_iteration(1, l32[0], l32[1], stat, st);
+      if (q < nb64) launch_b_iteration(0, h0->bty[0], l64[0], l64[1], stat, st);
+      if (q < nb32) launch_b_iteration(1, h0->bty[1], l32[0], l32[1], stat, st);
     }
   };
   if (it <= 1 || (h0->p.flags & EXCMG_NO_GRAPHS) || h0->noalloc) {
     launch_all(s);
     return last_error();
   }
-  const std::vector<long long> key = {(long long)(uintptr_t)ws, it, nb64, nb32, l64[0].n, l64[0].total, l64[1].total,
+  const std::vector<long long> key = {(long long)(uintptr_t)ws, h0->bty[0], h0->bty[1], it, nb64, nb32, l64[0].n,
+                                      l64[0].total, l64[1].total,
                                       l32[0].n, l32[0].total, l32[1].total};
   const long long now = h0->bgraph_hits + h0->bgraph_misses;
   for (auto &bg : h0->bgraphs)
@@ -965,7 +969,7 @@ int batched_solve(excmg_handle *const *hs, int count, const double *const *f, co
   for (int l = 0; l < S; ++l)
     for (int b = 0; b < count; ++b)
       batch_entry(hs[b], b, l, f[b], g[b], u[b], (BatchEntry *)(host.data() + l * tb) + b,
-                  &blocks[((size_t)l * count + b) * kLaunchKinds]);
+                  &blocks[((size_t)l * count + b) * kLaunchKinds], hs[0]->bty);
   int e;
   HIPCHECK(hipMemcpyAsync(tables, host.data(), host.size(), hipMemcpyHostToDevice, s));
   HIPCHECK(hipStreamSynchronize(s));  // the host tables may go out of scope on any early return below
@@ -1179,8 +1183,10 @@ int batched_solve(excmg_handle *const *hs, int count, const double *const *f, co
 // the one that suits the batch.  Per grid counted from each problem's finest (t = 0 the finest, 1 the next coarser,
 // ...) and per precision, every candidate chunk is timed as one flattened launch of pass A and one of pass B over all
 // the problems whose grid t relaxes in that precision (the batched kernels' prefetch depth 2 and streaming policy),
-// and the fastest is kept in each of those problems' sweeps.  zc_out[2 t + prec] (nullable): the chunk chosen, 0
-// where no problem relaxes that grid in that precision.
+// at each tile height; a batched launch holds every grid of the batch, so the height is one per precision: the one
+// whose fastest chunks sum to the least time over the grids.  The chunks and height are kept in those problems'
+// sweeps, and the height on every handle of the batch (for the batches it leads).  zc_out[2 t + prec] (nullable):
+// the chunk chosen, 0 where no problem relaxes that grid in that precision.
 int batched_autotune(excmg_handle *const *hs, int count, char *ws, int32_t *zc_out) {
   const hipStream_t s = hs[0]->stream;
   int S = 0;
@@ -1200,6 +1206,13 @@ int batched_autotune(excmg_handle *const *hs, int count, char *ws, int32_t *zc_o
   int rc = EXCMG_OK;
   if (zc_out)
     for (int q = 0; q < 2 * EXCMG_MAX_LEVELS; ++q) zc_out[q] = 0;
+  // best chunk per (precision, height, grid t) and the summed time of those bests per (precision, height): one
+  // launch covers every grid of the batch at once, so the height is chosen for the batch as a whole
+  static const int heights[] = {4, 8, 16};
+  constexpr int kH = (int)(sizeof(heights) / sizeof(heights[0]));
+  std::vector<int> bzc(2 * kH * (size_t)S, 0);
+  float total[2][kH] = {};
+  bool used[2] = {false, false};
   for (int t = 0; t < S && rc == EXCMG_OK; ++t) {
     for (int prec = 0; prec < 2 && rc == EXCMG_OK; ++prec) {
       std::vector<int> probs;  // the problems whose grid L-1-t relaxes in this precision
@@ -1210,62 +1223,86 @@ int batched_autotune(excmg_handle *const *hs, int count, char *ws, int32_t *zc_o
         if ((prec == 0 && kind == kBCg64) || (prec == 1 && kind == kBIr)) probs.push_back(b);
       }
       if (probs.empty()) continue;
-      float best = 1e30f;
-      int best_zc = 0;
-      for (int zc : cand) {
-        const int n = (int)probs.size();
-        preA[0] = preB[0] = 0;
-        for (int q = 0; q < n; ++q) {
-          excmg_handle *h = hs[probs[q]];
-          const int l = h->lo.L - 1 - t;
-          const Level &lv = h->lo.lev[l];
-          int blocks[kLaunchKinds];
-          batch_entry(h, probs[q], l, nullptr, nullptr, nullptr, &ent[q], blocks);
-          const Sweep sw = make_sweep(prec ? lv.g32 : lv.g, lv.st, zc, 2, 1);
-          if (prec) ent[q].swA32 = ent[q].swB32 = sw;
-          else ent[q].swA = ent[q].swB = sw;
-          lent[q] = (const BatchEntry *)table_dev + q;
-          preA[q + 1] = preA[q] + sweep_blocks(sw);
-          preB[q + 1] = preB[q] + sweep_blocks(sw);
-        }
-        if (hipMemcpyAsync(table_dev, ent.data(), sizeof(BatchEntry) * (size_t)n, hipMemcpyHostToDevice, s) !=
-                hipSuccess ||
-            hipMemcpyAsync(list_dev, list_host.data(), list_host.size(), hipMemcpyHostToDevice, s) != hipSuccess ||
-            hipStreamSynchronize(s) != hipSuccess) {
-          rc = EXCMG_ERR_HIP;
-          break;
-        }
-        BatchList A, B;
-        A.ent = B.ent = (const BatchEntry *const *)list_dev;
-        A.pre = A.aux = (const int *)(list_dev + sizeof(void *) * (size_t)count);
-        B.pre = B.aux = A.pre + n1;
-        A.n = B.n = n;
-        A.total = preA[n];
-        B.total = preB[n];
-        launch_b_tune_state(A, s);
-        float tmin = 1e30f;
-        for (int rep = 0; rep < 4 && rc == EXCMG_OK; ++rep) {
-          float ms = 0.0f;
-          if (hipEventRecord(ea, s) != hipSuccess) rc = EXCMG_ERR_HIP;
-          launch_b_passes(prec, A, B, s);
-          if (hipEventRecord(eb, s) != hipSuccess || hipEventSynchronize(eb) != hipSuccess ||
-              hipEventElapsedTime(&ms, ea, eb) != hipSuccess || last_error() != EXCMG_OK)
+      used[prec] = true;
+      for (int hi = 0; hi < kH && rc == EXCMG_OK; ++hi) {
+        const int ty = heights[hi];
+        const int bty[2] = {ty, ty};
+        float best = 1e30f;
+        int best_zc = 0;
+        for (int zc : cand) {
+          const int n = (int)probs.size();
+          preA[0] = preB[0] = 0;
+          for (int q = 0; q < n; ++q) {
+            excmg_handle *h = hs[probs[q]];
+            const int l = h->lo.L - 1 - t;
+            const Level &lv = h->lo.lev[l];
+            int blocks[kLaunchKinds];
+            batch_entry(h, probs[q], l, nullptr, nullptr, nullptr, &ent[q], blocks, bty);
+            const Sweep sw = make_sweep(prec ? lv.g32 : lv.g, lv.st, zc, 2, 1, ty);
+            if (prec) ent[q].swA32 = ent[q].swB32 = sw;
+            else ent[q].swA = ent[q].swB = sw;
+            lent[q] = (const BatchEntry *)table_dev + q;
+            preA[q + 1] = preA[q] + sweep_blocks(sw);
+            preB[q + 1] = preB[q] + sweep_blocks(sw);
+          }
+          if (hipMemcpyAsync(table_dev, ent.data(), sizeof(BatchEntry) * (size_t)n, hipMemcpyHostToDevice, s) !=
+                  hipSuccess ||
+              hipMemcpyAsync(list_dev, list_host.data(), list_host.size(), hipMemcpyHostToDevice, s) != hipSuccess ||
+              hipStreamSynchronize(s) != hipSuccess) {
             rc = EXCMG_ERR_HIP;
-          if (rep > 0 && ms < tmin) tmin = ms;  // the first launch warms caches and code
+            break;
+          }
+          BatchList A, B;
+          A.ent = B.ent = (const BatchEntry *const *)list_dev;
+          A.pre = A.aux = (const int *)(list_dev + sizeof(void *) * (size_t)count);
+          B.pre = B.aux = A.pre + n1;
+          A.n = B.n = n;
+          A.total = preA[n];
+          B.total = preB[n];
+          launch_b_tune_state(A, s);
+          float tmin = 1e30f;
+          for (int rep = 0; rep < 4 && rc == EXCMG_OK; ++rep) {
+            float ms = 0.0f;
+            if (hipEventRecord(ea, s) != hipSuccess) rc = EXCMG_ERR_HIP;
+            launch_b_passes(prec, ty, A, B, s);
+            if (hipEventRecord(eb, s) != hipSuccess || hipEventSynchronize(eb) != hipSuccess ||
+                hipEventElapsedTime(&ms, ea, eb) != hipSuccess || last_error() != EXCMG_OK)
+              rc = EXCMG_ERR_HIP;
+            if (rep > 0 && ms < tmin) tmin = ms;  // the first launch warms caches and code
+          }
+          if (tmin < best) {
+            best = tmin;
+            best_zc = zc;
+          }
         }
-        if (tmin < best) {
-          best = tmin;
-          best_zc = zc;
+        bzc[((size_t)prec * kH + hi) * S + t] = best_zc;
+        total[prec][hi] += best;
+      }
+    }
+  }
+  if (rc == EXCMG_OK) {
+    for (int prec = 0; prec < 2; ++prec) {
+      if (!used[prec]) continue;
+      int hb = 0;
+      for (int hi = 1; hi < kH; ++hi)
+        if (total[prec][hi] < total[prec][hb]) hb = hi;
+      const int ty = heights[hb];
+      for (int b = 0; b < count; ++b) hs[b]->bty[prec] = ty;
+      for (int t = 0; t < S; ++t) {
+        const int zc = bzc[((size_t)prec * kH + hb) * S + t];
+        if (zc == 0) continue;  // no problem relaxes grid t in this precision
+        for (int b = 0; b < count; ++b) {
+          const int l = hs[b]->lo.L - 1 - t;
+          if (l < 0) continue;
+          const int kind = batch_kind(hs[b], l);
+          if (!((prec == 0 && kind == kBCg64) || (prec == 1 && kind == kBIr))) continue;
+          Level &lv = hs[b]->lo.lev[l];
+          const Sweep sw = make_sweep(prec ? lv.g32 : lv.g, lv.st, zc, 2, 1, ty);
+          if (prec) lv.swA32 = lv.swB32 = sw;
+          else lv.swA = lv.swB = sw;
         }
+        if (zc_out) zc_out[2 * t + prec] = zc;
       }
-      if (rc) break;
-      for (int b : probs) {
-        Level &lv = hs[b]->lo.lev[hs[b]->lo.L - 1 - t];
-        const Sweep sw = make_sweep(prec ? lv.g32 : lv.g, lv.st, best_zc, 2, 1);
-        if (prec) lv.swA32 = lv.swB32 = sw;
-        else lv.swA = lv.swB = sw;
-      }
-      if (zc_out) zc_out[2 * t + prec] = best_zc;
     }
   }
   (void)hipEventDestroy(ea);
@@ -1675,6 +1712,25 @@ int excmg_set_sweep(excmg_handle *h, int32_t level, int32_t kind, const int32_t 
   HIPCHECK(hipStreamSynchronize(h->stream));  // no launch of an earlier call still uses the old shape
   *sw = nw;
   h->drop_graphs();  // captured with the old sweep shapes
+  return EXCMG_OK;
+}
+
+int excmg_get_batch_height(excmg_handle *h, int32_t ty[2]) {
+  if (!h || !ty) return EXCMG_ERR_ARG;
+  ty[0] = h->bty[0];
+  ty[1] = h->bty[1];
+  return EXCMG_OK;
+}
+
+int excmg_set_batch_height(excmg_handle *h, const int32_t ty[2]) {
+  if (!h || !ty) return EXCMG_ERR_ARG;
+  for (int q = 0; q < 2; ++q)
+    if (!(ty[q] == 4 || ty[q] == 8 || ty[q] == 16)) return EXCMG_ERR_ARG;
+  DeviceGuard dg(h->device);
+  HIPCHECK(hipStreamSynchronize(h->stream));
+  h->bty[0] = ty[0];
+  h->bty[1] = ty[1];
+  h->drop_graphs();
   return EXCMG_OK;
 }
 

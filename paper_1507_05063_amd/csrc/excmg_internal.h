@@ -201,13 +201,14 @@ struct Sweep {
   int depth;  // planes of loads in flight per thread in the z-march (2, 3, 4 or 6 in the CG passes; 2 or 3 in
               // the residual sweeps)
   int nt;     // 1: data read or written once per sweep uses non-temporal (streaming) loads and stores
-  int ty;     // tile height in rows of 64 nodes (4, 8 or 16; only the CG passes of a single problem use 8 and 16)
+  int ty;     // tile height in rows of 64 nodes (4, 8 or 16 in the CG passes; 4 in the residual sweeps)
 };
 
 // zc <= 0: default chunk; ty: 4 unless 8 or 16
 Sweep make_sweep(const Grid &g, const Stencil &s, int zc, int depth = 2, int nt = 0, int ty = 4);
 int sweep_blocks(const Sweep &sw);
-// the same sweep with 4-row tiles (what the residual sweeps and the batched launches are built for)
+// the same sweep with ty-row tiles, and with 4-row tiles (what the residual sweeps are built for)
+Sweep with_height(const Sweep &sw, int ty);
 Sweep default_height(const Sweep &sw);
 // partial-sum buffer length needed by the CG and residual kernels for a grid
 long long cg_partials_needed(const Grid &g);
@@ -374,12 +375,13 @@ void launch_b_boundary_terms(const BatchList &L, hipStream_t st);
 void launch_b_residual(const BatchList &L, BatchStatus *stat, hipStream_t st);       // + the reduction
 void launch_b_residual_cast(const BatchList &L, BatchStatus *stat, hipStream_t st);  // + the reduction
 // one CG iteration (pass A, its reduction, pass B, its reduction) of the entries of A and B (the same entries, with the
-// workgroup prefixes of pass A and pass B); fp32: the inner FP32 solves of the refinement
-void launch_b_iteration(int fp32, const BatchList &A, const BatchList &B, BatchStatus *stat, hipStream_t st);
+// workgroup prefixes of pass A and pass B); fp32: the inner FP32 solves of the refinement; ty: the tile height every
+// entry's pass sweeps use
+void launch_b_iteration(int fp32, int ty, const BatchList &A, const BatchList &B, BatchStatus *stat, hipStream_t st);
 void launch_b_add_correction(const BatchList &L, hipStream_t st);
 // the autotuner's trial CG state in every entry of L, and the two passes alone (timed by the batched autotuner)
 void launch_b_tune_state(const BatchList &L, hipStream_t st);
-void launch_b_passes(int fp32, const BatchList &A, const BatchList &B, hipStream_t st);
+void launch_b_passes(int fp32, int ty, const BatchList &A, const BatchList &B, hipStream_t st);
 void launch_b_copy(const BatchList &L, hipStream_t st);
 // workgroup counts of the flattened launches for one grid
 int b_blocks_exp_finite(const Grid &gw);

@@ -1501,11 +1501,11 @@ __global__ __launch_bounds__(FT) void b_finalize_ir_kernel(BatchList L, BatchSta
   }
 }
 
-template <typename T>
-__global__ __launch_bounds__(NT) void b_pass_a_kernel(BatchList L) {
+template <typename T, int TY>
+__global__ __launch_bounds__(Tile<TY>::NT) void b_pass_a_kernel(BatchList L) {
   constexpr bool F = sizeof(T) == 4;
-  __shared__ T tile[2][kTileRows][TX + 2];
-  __shared__ double sh[NT / 64];
+  __shared__ T tile[2][Tile<TY>::Rows][TX + 2];
+  __shared__ double sh[Tile<TY>::NT / 64];
   const int e = find_entry(L.pre, L.n, blockIdx.x);
   const BatchEntry &E = *L.ent[e];
   const CgState *cs = F ? E.cs2 : E.cs;
@@ -1522,16 +1522,16 @@ __global__ __launch_bounds__(NT) void b_pass_a_kernel(BatchList L) {
   const Sweep sw = F ? E.swA32 : E.swA;
   double a0 = 0.0;
   // the batch's working set is far larger than the caches: streaming policy
-  pass_a_march<T, 2, true>(sw, it, bf, (T)cs->beta, a0, tile, bid, nb, false);
+  pass_a_march<T, 2, true, TY>(sw, it, bf, (T)cs->beta, a0, tile, bid, nb, false);
   const double v[1] = {a0};
-  write_partials<1>(v, E.parts, sh, bid, nb);
+  write_partials<1, Tile<TY>::NT>(v, E.parts, sh, bid, nb);
 }
 
-template <typename T>
-__global__ __launch_bounds__(NT) void b_pass_b_kernel(BatchList L) {
+template <typename T, int TY>
+__global__ __launch_bounds__(Tile<TY>::NT) void b_pass_b_kernel(BatchList L) {
   constexpr bool F = sizeof(T) == 4;
-  __shared__ T tile[2][kTileRows][TX + 2];
-  __shared__ double sh[NT / 64];
+  __shared__ T tile[2][Tile<TY>::Rows][TX + 2];
+  __shared__ double sh[Tile<TY>::NT / 64];
   const int e = find_entry(L.pre, L.n, blockIdx.x);
   const BatchEntry &E = *L.ent[e];
   const CgState *cs = F ? E.cs2 : E.cs;
@@ -1549,9 +1549,9 @@ __global__ __launch_bounds__(NT) void b_pass_b_kernel(BatchList L) {
   const CgBufs<T> bf = cg_bufs(it, r, p0, p1);
   const Sweep sw = F ? E.swB32 : E.swB;
   double a0 = 0.0;
-  pass_b_march<T, 2, true>(sw, it, bf, uu, (T)cs->alpha, a0, tile, bid, nb, false);
+  pass_b_march<T, 2, true, TY>(sw, it, bf, uu, (T)cs->alpha, a0, tile, bid, nb, false);
   const double v[1] = {a0};
-  write_partials<1>(v, E.parts, sh, bid, nb);
+  write_partials<1, Tile<TY>::NT>(v, E.parts, sh, bid, nb);
 }
 
 // reduction after pass A (PASS 0) or pass B (PASS 1) of the FP64 CG (F = 0) or the FP32 inner CG (F = 1)
@@ -1615,9 +1615,11 @@ Sweep make_sweep(const Grid &g, const Stencil &s, int zc, int depth, int nt, int
 
 int sweep_blocks(const Sweep &sw) { return sw.ntx * sw.nty * sw.nzc; }
 
-Sweep default_height(const Sweep &sw) {
-  return sw.ty == kTy ? sw : make_sweep(sw.g, sw.st, sw.zc, sw.depth, sw.nt, kTy);
+Sweep with_height(const Sweep &sw, int ty) {
+  return sw.ty == ty ? sw : make_sweep(sw.g, sw.st, sw.zc, sw.depth, sw.nt, ty);
 }
+
+Sweep default_height(const Sweep &sw) { return with_height(sw, kTy); }
 
 long long cg_partials_needed(const Grid &g) {
   const Sweep sw = make_sweep(g, Stencil{}, 2, 2, 0, 4);  // the smallest chunk and tile give the most workgroups
@@ -1829,34 +1831,51 @@ void launch_b_residual_cast(const BatchList &L, BatchStatus *stat, hipStream_t s
   b_finalize_ir_kernel<<<L.n, FT, 0, st>>>(L, stat);
 }
 
-void launch_b_iteration(int fp32, const BatchList &A, const BatchList &B, BatchStatus *stat, hipStream_t st) {
-  if (A.total <= 0 || B.total <= 0) return;
-  if (fp32) {
-    b_pass_a_kernel<float><<<A.total, NT, 0, st>>>(A);
-    b_finalize_pass_kernel<0, 1><<<A.n, FT, 0, st>>>(A, stat);
-    b_pass_b_kernel<float><<<B.total, NT, 0, st>>>(B);
-    b_finalize_pass_kernel<1, 1><<<B.n, FT, 0, st>>>(B, stat);
-  } else {
-    b_pass_a_kernel<double><<<A.total, NT, 0, st>>>(A);
-    b_finalize_pass_kernel<0, 0><<<A.n, FT, 0, st>>>(A, stat);
-    b_pass_b_kernel<double><<<B.total, NT, 0, st>>>(B);
-    b_finalize_pass_kernel<1, 0><<<B.n, FT, 0, st>>>(B, stat);
+// f(integral_constant<int, ty>) for a tile height of 4, 8 or 16 rows (4 for anything else)
+template <typename F>
+static void with_height(int ty, F &&f) {
+  switch (ty) {
+    case 8: f(std::integral_constant<int, 8>{}); break;
+    case 16: f(std::integral_constant<int, 16>{}); break;
+    default: f(std::integral_constant<int, kTy>{}); break;
   }
+}
+
+void launch_b_iteration(int fp32, int ty, const BatchList &A, const BatchList &B, BatchStatus *stat,
+                        hipStream_t st) {
+  if (A.total <= 0 || B.total <= 0) return;
+  with_height(ty, [&](auto h) {
+    constexpr int TY = decltype(h)::value;
+    if (fp32) {
+      b_pass_a_kernel<float, TY><<<A.total, Tile<TY>::NT, 0, st>>>(A);
+      b_finalize_pass_kernel<0, 1><<<A.n, FT, 0, st>>>(A, stat);
+      b_pass_b_kernel<float, TY><<<B.total, Tile<TY>::NT, 0, st>>>(B);
+      b_finalize_pass_kernel<1, 1><<<B.n, FT, 0, st>>>(B, stat);
+    } else {
+      b_pass_a_kernel<double, TY><<<A.total, Tile<TY>::NT, 0, st>>>(A);
+      b_finalize_pass_kernel<0, 0><<<A.n, FT, 0, st>>>(A, stat);
+      b_pass_b_kernel<double, TY><<<B.total, Tile<TY>::NT, 0, st>>>(B);
+      b_finalize_pass_kernel<1, 0><<<B.n, FT, 0, st>>>(B, stat);
+    }
+  });
 }
 
 void launch_b_tune_state(const BatchList &L, hipStream_t st) {
   if (L.n > 0) b_tune_state_kernel<<<(L.n + 255) / 256, 256, 0, st>>>(L);
 }
 
-void launch_b_passes(int fp32, const BatchList &A, const BatchList &B, hipStream_t st) {
+void launch_b_passes(int fp32, int ty, const BatchList &A, const BatchList &B, hipStream_t st) {
   if (A.total <= 0 || B.total <= 0) return;
-  if (fp32) {
-    b_pass_a_kernel<float><<<A.total, NT, 0, st>>>(A);
-    b_pass_b_kernel<float><<<B.total, NT, 0, st>>>(B);
-  } else {
-    b_pass_a_kernel<double><<<A.total, NT, 0, st>>>(A);
-    b_pass_b_kernel<double><<<B.total, NT, 0, st>>>(B);
-  }
+  with_height(ty, [&](auto h) {
+    constexpr int TY = decltype(h)::value;
+    if (fp32) {
+      b_pass_a_kernel<float, TY><<<A.total, Tile<TY>::NT, 0, st>>>(A);
+      b_pass_b_kernel<float, TY><<<B.total, Tile<TY>::NT, 0, st>>>(B);
+    } else {
+      b_pass_a_kernel<double, TY><<<A.total, Tile<TY>::NT, 0, st>>>(A);
+      b_pass_b_kernel<double, TY><<<B.total, Tile<TY>::NT, 0, st>>>(B);
+    }
+  });
 }
 
 void launch_b_add_correction(const BatchList &L, hipStream_t st) {

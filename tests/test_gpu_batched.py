@@ -113,6 +113,54 @@ def test_batched_autotune_keeps_results(ex, orc):
         assert rel2(host(ub), ref["u"]) <= 1e-12, n
 
 
+@pytest.mark.parametrize("ty", [4, 8, 16])
+def test_batched_tile_heights_match_oracle(ex, orc, ty):
+    """The batched CG passes at each tile height (set on the batch's first solver), FP64, against the oracle with the
+    batch's per-grid iteration counts; a bad height is refused."""
+    tol = 1e-10
+    solvers, fs, gs, data, us, stats, ms = _run(ex, MIXED, tol, ex.FP64)
+    solvers[0].set_batch_height((ty, ty))
+    assert solvers[0].get_batch_height() == (ty, ty)
+    us, stats, ms = ex.solve_batched(solvers, fs, gs)
+    for (n, nc, p), s, (f, g, u, _), ub, st in zip(MIXED, solvers, data, us, stats):
+        ref = orc.excmg(f, g, p.box, s.n_coarse, tol, fixed_iters=np.array(st["iters"], dtype=np.int32))
+        assert rel2(host(ub), ref["u"]) <= 1e-12, n
+    with pytest.raises(ex.ExcmgError):
+        solvers[0].set_batch_height((12, 4))
+
+
+# two problems whose finest grids relax in FP32 (127 x 127 x 95 and 191 x 95 x 63 unknowns), and the oracle's solutions
+BIG32 = [
+    ((128, 128, 96), (8, 8, 6), synth.smooth(6, (1.0, 1.0, 0.75))),
+    ((192, 96, 64), (12, 6, 4), synth.smooth(7, (1.5, 0.75, 0.5))),
+]
+_REF32 = {}
+
+
+@pytest.mark.parametrize("ty", [4, 8, 16])
+def test_batched_fp32_tile_heights_against_oracle(ex, orc, ty):
+    """The batched FP32 refinement passes at each tile height, against the FP64 oracle where both are limited by the
+    discretisation error (tol 1e-13): the batch's solution within 1% of the oracle's own error against the exact field
+    (root mean square over all nodes)."""
+    tol = 1e-13
+    solvers, fs, gs, data = [], [], [], []
+    for n, nc, p in BIG32:
+        f, g, u = synth.sample(p, n)
+        solvers.append(ex.Solver(n, p.box, tol, n_coarse=nc, precision=ex.FP32_IR))
+        fs.append(dev(f))
+        gs.append(dev(g))
+        data.append((f, g, u))
+    solvers[0].set_batch_height((4, ty))
+    us, stats, ms = ex.solve_batched(solvers, fs, gs)
+    rms = lambda a: float(np.sqrt(np.mean(np.square(a))))
+    for q, ((n, nc, p), (f, g, u)) in enumerate(zip(BIG32, data)):
+        assert stats[q]["ir_outer"][-1] >= 1, stats[q]["ir_outer"]  # the finest grid relaxed in FP32
+        if q not in _REF32:
+            _REF32[q] = orc.excmg(f, g, p.box, nc, tol)["u"]
+        ref = _REF32[q]
+        assert rms(host(us[q]) - ref) <= 0.01 * rms(ref - u), n
+
+
 @pytest.mark.parametrize("precision", ["fp64", "fp32_ir"])
 def test_batched_graphs_match_direct_launches(ex, precision):
     """The CG iterations of each batched round run as graphs cached on the first handle; the same batch with every
