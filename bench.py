@@ -207,7 +207,10 @@ def bench_batch(ex, synth, torch, args):
             "batch_ms_default_chunks": round(ms_default, 3), "autotune_s": round(tune_s, 2),
             "round_graphs_replayed_captured": list(solvers[0].batch_graph_counts()),
             "autotuned_z_chunks_fp64_fp32_by_grid_from_finest": {str(k): list(v) for k, v in zc.items()},
-            "autotuned_tile_heights": batch_heights(solvers)}
+            "autotuned_tile_heights": batch_heights(solvers),
+            "autotuned_batch_shape_fp64_fp32": dict(zip(("tile_height", "depth"),
+                                                        [list(solvers[0].get_batch_shape()[:2]),
+                                                         list(solvers[0].get_batch_shape()[2:])]))}
 
 
 def batch_heights(solvers):

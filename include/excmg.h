@@ -221,10 +221,11 @@ int excmg_batch_graph_counts(const excmg_handle *h, int64_t *replays, int64_t *c
  * run together, so the z chunk a problem prefers alone is not the one the batch prefers.  For each grid counted from
  * the problems' finest (t = 0 each problem's finest grid, t = 1 the next coarser, ...) and each precision, every z
  * chunk in {2, 4, ..., 128} planes is timed as one flattened launch of the two CG passes over all problems whose grid
- * t relaxes in that precision, at each tile height (4, 8, 16 rows); a batched launch holds all the batch's grids, so
- * one height is chosen per precision (the one whose fastest chunks sum to the least time), and the chunks and height
- * are kept in those problems' handles (replacing what excmg_autotune chose there; results do not depend on them;
- * excmg_get_sweep reads them).  Trial launches touch only the handles' work buffers and CG states.
+ * t relaxes in that precision, at each tile height (4, 8, 16 rows) and prefetch depth (2, 3, 4, 6 planes); a batched
+ * launch holds all the batch's grids, so one height and depth are chosen per precision (those whose fastest chunks
+ * sum to the least time), and the chunks, height and depth are kept in those problems' handles (replacing what
+ * excmg_autotune chose there; results do not depend on them; excmg_get_sweep and excmg_get_batch_shape read them).
+ * Trial launches touch only the handles' work buffers and CG states.
  * batch_ws: as for excmg_solve_batched.  zc_out (host, nullable, 2 * EXCMG_MAX_LEVELS entries): zc_out[2 t + p] the
  * chunk chosen for grid t in precision p (0 FP64, 1 FP32), 0 where no problem relaxes that grid that way. */
 int excmg_autotune_batched(excmg_handle *const *hs, int32_t count, void *batch_ws, size_t batch_bytes,
@@ -263,12 +264,13 @@ int excmg_autotune(excmg_handle *h, int32_t *zc_out, int32_t *depth_out);
 int excmg_get_sweep(excmg_handle *h, int32_t level, int32_t kind, int32_t shape[4]);
 int excmg_set_sweep(excmg_handle *h, int32_t level, int32_t kind, const int32_t shape[4]);
 
-/* Tile height of the batched CG passes of the batches this handle leads (hs[0] of excmg_solve_batched), ty[2] (host)
- * = {FP64 passes, FP32 passes}, each 4, 8 or 16 rows (4 until excmg_autotune_batched chooses).  Every grid of a
- * batched launch uses it; a grid's z chunk comes from its own handle.  Set waits for the handle's stream and drops its
- * captured graphs.  Errors: EXCMG_ERR_ARG for a null handle or array or a height outside {4, 8, 16}. */
-int excmg_get_batch_height(excmg_handle *h, int32_t ty[2]);
-int excmg_set_batch_height(excmg_handle *h, const int32_t ty[2]);
+/* Shape of the batched CG passes of the batches this handle leads (hs[0] of excmg_solve_batched), shape[4] (host) =
+ * {tile height of the FP64 passes, of the FP32 passes (4, 8 or 16 rows), prefetch depth of the FP64 passes, of the
+ * FP32 passes (2, 3, 4 or 6 planes)}; {4, 4, 2, 2} until excmg_autotune_batched chooses.  Every grid of a batched launch
+ * uses it; a grid's z chunk comes from its own handle.  Set waits for the handle's stream and drops its captured
+ * graphs.  Errors: EXCMG_ERR_ARG for a null handle or array or a value outside those sets. */
+int excmg_get_batch_shape(excmg_handle *h, int32_t shape[4]);
+int excmg_set_batch_shape(excmg_handle *h, const int32_t shape[4]);
 
 /* Host call.  Turns the kernel timing of EXCMG_WANT_TIMING on (on != 0) or off for later calls on this handle, as
  * if the flag had been given at setup (the timing events are created the first time it is turned on).  The solver's

@@ -191,16 +191,18 @@ class Solver:
         sh = (ctypes.c_int32 * 4)(*[int(v) for v in shape])
         _lib.check(_lib.lib().excmg_set_sweep(self._h, int(level), self.SWEEP_KINDS[kind], sh), "excmg_set_sweep")
 
-    def get_batch_height(self):
-        """(FP64, FP32) tile heights of the batched CG passes of the batches this solver leads."""
-        ty = (ctypes.c_int32 * 2)()
-        _lib.check(_lib.lib().excmg_get_batch_height(self._h, ty), "excmg_get_batch_height")
-        return tuple(ty)
+    def get_batch_shape(self):
+        """(FP64 tile height, FP32 tile height, FP64 prefetch depth, FP32 prefetch depth) of the batched CG passes of
+        the batches this solver leads."""
+        sh = (ctypes.c_int32 * 4)()
+        _lib.check(_lib.lib().excmg_get_batch_shape(self._h, sh), "excmg_get_batch_shape")
+        return tuple(sh)
 
-    def set_batch_height(self, ty):
-        """Set the (FP64, FP32) tile heights (4, 8 or 16) of the batched CG passes of the batches this solver leads."""
-        t = (ctypes.c_int32 * 2)(*[int(v) for v in ty])
-        _lib.check(_lib.lib().excmg_set_batch_height(self._h, t), "excmg_set_batch_height")
+    def set_batch_shape(self, shape):
+        """Set (FP64 tile height, FP32 tile height, FP64 depth, FP32 depth) of the batched CG passes of the batches this
+        solver leads (heights 4, 8 or 16; depths 2, 3, 4 or 6)."""
+        sh = (ctypes.c_int32 * 4)(*[int(v) for v in shape])
+        _lib.check(_lib.lib().excmg_set_batch_shape(self._h, sh), "excmg_set_batch_shape")
 
     def set_timing(self, on: bool):
         """Kernel timing (stats kernel_ms, kernel_calls) on or off for later calls."""

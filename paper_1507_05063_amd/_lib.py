@@ -118,8 +118,8 @@ def lib():
             "excmg_set_timing": ([_P, ctypes.c_int32], _I),
             "excmg_get_sweep": ([_P, ctypes.c_int32, ctypes.c_int32, _I32P], _I),
             "excmg_set_sweep": ([_P, ctypes.c_int32, ctypes.c_int32, _I32P], _I),
-            "excmg_get_batch_height": ([_P, _I32P], _I),
-            "excmg_set_batch_height": ([_P, _I32P], _I),
+            "excmg_get_batch_shape": ([_P, _I32P], _I),
+            "excmg_set_batch_shape": ([_P, _I32P], _I),
             "excmg_solve_noalloc": ([ctypes.POINTER(Problem), _P, _P, _P, _P, _P, ctypes.POINTER(Stats)], _I),
             "excmg_autotune": ([_P, _I32P, _I32P], _I),
             "excmg_bandwidth_probe": ([_P, ctypes.c_size_t, ctypes.c_int32, _P, ctypes.POINTER(ctypes.c_double), _I32P],

@@ -201,8 +201,10 @@ struct TimedLaunch {
 }  // namespace
 
 struct excmg_handle {
-  // tile height of the batched CG passes (FP64, FP32) when this handle leads a batch (excmg_autotune_batched)
+  // tile height and prefetch depth of the batched CG passes (FP64, FP32) when this handle leads a batch
+  // (excmg_autotune_batched, excmg_set_batch_shape)
   int bty[2] = {4, 4};
+  int bdepth[2] = {2, 2};
   excmg_problem p;
   Layout lo;
   hipStream_t stream;
@@ -907,16 +909,16 @@ int batch_iterations(excmg_handle *h0, const char *ws, int it, int nb64, int nb3
   const hipStream_t s = h0->stream;
   auto launch_all = [&](hipStream_t st) {
     for (int q = 0; q < it; ++q) {
-      if (q < nb64) launch_b_iteration(0, h0->bty[0], l64[0], l64[1], stat, st);
-      if (q < nb32) launch_b_iteration(1, h0->bty[1], l32[0], l32[1], stat, st);
+      if (q < nb64) launch_b_iteration(0, h0->bty[0], h0->bdepth[0], l64[0], l64[1], stat, st);
+      if (q < nb32) launch_b_iteration(1, h0->bty[1], h0->bdepth[1], l32[0], l32[1], stat, st);
     }
   };
   if (it <= 1 || (h0->p.flags & EXCMG_NO_GRAPHS) || h0->noalloc) {
     launch_all(s);
     return last_error();
   }
-  const std::vector<long long> key = {(long long)(uintptr_t)ws, h0->bty[0], h0->bty[1], it, nb64, nb32, l64[0].n,
-                                      l64[0].total, l64[1].total,
+  const std::vector<long long> key = {(long long)(uintptr_t)ws, h0->bty[0], h0->bty[1], h0->bdepth[0], h0->bdepth[1],
+                                      it, nb64, nb32, l64[0].n, l64[0].total, l64[1].total,
                                       l32[0].n, l32[0].total, l32[1].total};
   const long long now = h0->bgraph_hits + h0->bgraph_misses;
   for (auto &bg : h0->bgraphs)
@@ -1206,10 +1208,13 @@ int batched_autotune(excmg_handle *const *hs, int count, char *ws, int32_t *zc_o
   int rc = EXCMG_OK;
   if (zc_out)
     for (int q = 0; q < 2 * EXCMG_MAX_LEVELS; ++q) zc_out[q] = 0;
-  // best chunk per (precision, height, grid t) and the summed time of those bests per (precision, height): one
-  // launch covers every grid of the batch at once, so the height is chosen for the batch as a whole
+  // best chunk per (precision, shape, grid t) and the summed time of those bests per (precision, shape), where a shape
+  // is a tile height and a prefetch depth: one launch covers every grid of the batch at once, so the shape is chosen
+  // for the batch as a whole
   static const int heights[] = {4, 8, 16};
-  constexpr int kH = (int)(sizeof(heights) / sizeof(heights[0]));
+  static const int bdepths[] = {2, 3, 4, 6};
+  constexpr int kD = (int)(sizeof(bdepths) / sizeof(bdepths[0]));
+  constexpr int kH = (int)(sizeof(heights) / sizeof(heights[0])) * kD;
   std::vector<int> bzc(2 * kH * (size_t)S, 0);
   float total[2][kH] = {};
   bool used[2] = {false, false};
@@ -1225,7 +1230,7 @@ int batched_autotune(excmg_handle *const *hs, int count, char *ws, int32_t *zc_o
       if (probs.empty()) continue;
       used[prec] = true;
       for (int hi = 0; hi < kH && rc == EXCMG_OK; ++hi) {
-        const int ty = heights[hi];
+        const int ty = heights[hi / kD], depth = bdepths[hi % kD];
         const int bty[2] = {ty, ty};
         float best = 1e30f;
         int best_zc = 0;
@@ -1238,7 +1243,7 @@ int batched_autotune(excmg_handle *const *hs, int count, char *ws, int32_t *zc_o
             const Level &lv = h->lo.lev[l];
             int blocks[kLaunchKinds];
             batch_entry(h, probs[q], l, nullptr, nullptr, nullptr, &ent[q], blocks, bty);
-            const Sweep sw = make_sweep(prec ? lv.g32 : lv.g, lv.st, zc, 2, 1, ty);
+            const Sweep sw = make_sweep(prec ? lv.g32 : lv.g, lv.st, zc, depth, 1, ty);
             if (prec) ent[q].swA32 = ent[q].swB32 = sw;
             else ent[q].swA = ent[q].swB = sw;
             lent[q] = (const BatchEntry *)table_dev + q;
@@ -1264,7 +1269,7 @@ int batched_autotune(excmg_handle *const *hs, int count, char *ws, int32_t *zc_o
           for (int rep = 0; rep < 4 && rc == EXCMG_OK; ++rep) {
             float ms = 0.0f;
             if (hipEventRecord(ea, s) != hipSuccess) rc = EXCMG_ERR_HIP;
-            launch_b_passes(prec, ty, A, B, s);
+            launch_b_passes(prec, ty, depth, A, B, s);
             if (hipEventRecord(eb, s) != hipSuccess || hipEventSynchronize(eb) != hipSuccess ||
                 hipEventElapsedTime(&ms, ea, eb) != hipSuccess || last_error() != EXCMG_OK)
               rc = EXCMG_ERR_HIP;
@@ -1286,8 +1291,11 @@ int batched_autotune(excmg_handle *const *hs, int count, char *ws, int32_t *zc_o
       int hb = 0;
       for (int hi = 1; hi < kH; ++hi)
         if (total[prec][hi] < total[prec][hb]) hb = hi;
-      const int ty = heights[hb];
-      for (int b = 0; b < count; ++b) hs[b]->bty[prec] = ty;
+      const int ty = heights[hb / kD], depth = bdepths[hb % kD];
+      for (int b = 0; b < count; ++b) {
+        hs[b]->bty[prec] = ty;
+        hs[b]->bdepth[prec] = depth;
+      }
       for (int t = 0; t < S; ++t) {
         const int zc = bzc[((size_t)prec * kH + hb) * S + t];
         if (zc == 0) continue;  // no problem relaxes grid t in this precision
@@ -1297,7 +1305,7 @@ int batched_autotune(excmg_handle *const *hs, int count, char *ws, int32_t *zc_o
           const int kind = batch_kind(hs[b], l);
           if (!((prec == 0 && kind == kBCg64) || (prec == 1 && kind == kBIr))) continue;
           Level &lv = hs[b]->lo.lev[l];
-          const Sweep sw = make_sweep(prec ? lv.g32 : lv.g, lv.st, zc, 2, 1, ty);
+          const Sweep sw = make_sweep(prec ? lv.g32 : lv.g, lv.st, zc, depth, 1, ty);
           if (prec) lv.swA32 = lv.swB32 = sw;
           else lv.swA = lv.swB = sw;
         }
@@ -1715,21 +1723,28 @@ int excmg_set_sweep(excmg_handle *h, int32_t level, int32_t kind, const int32_t 
   return EXCMG_OK;
 }
 
-int excmg_get_batch_height(excmg_handle *h, int32_t ty[2]) {
-  if (!h || !ty) return EXCMG_ERR_ARG;
-  ty[0] = h->bty[0];
-  ty[1] = h->bty[1];
+int excmg_get_batch_shape(excmg_handle *h, int32_t shape[4]) {
+  if (!h || !shape) return EXCMG_ERR_ARG;
+  shape[0] = h->bty[0];
+  shape[1] = h->bty[1];
+  shape[2] = h->bdepth[0];
+  shape[3] = h->bdepth[1];
   return EXCMG_OK;
 }
 
-int excmg_set_batch_height(excmg_handle *h, const int32_t ty[2]) {
-  if (!h || !ty) return EXCMG_ERR_ARG;
-  for (int q = 0; q < 2; ++q)
-    if (!(ty[q] == 4 || ty[q] == 8 || ty[q] == 16)) return EXCMG_ERR_ARG;
+int excmg_set_batch_shape(excmg_handle *h, const int32_t shape[4]) {
+  if (!h || !shape) return EXCMG_ERR_ARG;
+  for (int q = 0; q < 2; ++q) {
+    if (!(shape[q] == 4 || shape[q] == 8 || shape[q] == 16)) return EXCMG_ERR_ARG;
+    const int d = shape[2 + q];
+    if (!(d == 2 || d == 3 || d == 4 || d == 6)) return EXCMG_ERR_ARG;
+  }
   DeviceGuard dg(h->device);
   HIPCHECK(hipStreamSynchronize(h->stream));
-  h->bty[0] = ty[0];
-  h->bty[1] = ty[1];
+  for (int q = 0; q < 2; ++q) {
+    h->bty[q] = shape[q];
+    h->bdepth[q] = shape[2 + q];
+  }
   h->drop_graphs();
   return EXCMG_OK;
 }

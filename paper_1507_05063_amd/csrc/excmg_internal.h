@@ -376,12 +376,13 @@ void launch_b_residual(const BatchList &L, BatchStatus *stat, hipStream_t st);  
 void launch_b_residual_cast(const BatchList &L, BatchStatus *stat, hipStream_t st);  // + the reduction
 // one CG iteration (pass A, its reduction, pass B, its reduction) of the entries of A and B (the same entries, with the
 // workgroup prefixes of pass A and pass B); fp32: the inner FP32 solves of the refinement; ty: the tile height every
-// entry's pass sweeps use
-void launch_b_iteration(int fp32, int ty, const BatchList &A, const BatchList &B, BatchStatus *stat, hipStream_t st);
+// entry's pass sweeps use; depth: their prefetch depth (2, 3, 4 or 6)
+void launch_b_iteration(int fp32, int ty, int depth, const BatchList &A, const BatchList &B, BatchStatus *stat,
+                        hipStream_t st);
 void launch_b_add_correction(const BatchList &L, hipStream_t st);
 // the autotuner's trial CG state in every entry of L, and the two passes alone (timed by the batched autotuner)
 void launch_b_tune_state(const BatchList &L, hipStream_t st);
-void launch_b_passes(int fp32, int ty, const BatchList &A, const BatchList &B, hipStream_t st);
+void launch_b_passes(int fp32, int ty, int depth, const BatchList &A, const BatchList &B, hipStream_t st);
 void launch_b_copy(const BatchList &L, hipStream_t st);
 // workgroup counts of the flattened launches for one grid
 int b_blocks_exp_finite(const Grid &gw);

@@ -1501,7 +1501,7 @@ __global__ __launch_bounds__(FT) void b_finalize_ir_kernel(BatchList L, BatchSta
   }
 }
 
-template <typename T, int TY>
+template <typename T, int TY, int D>
 __global__ __launch_bounds__(Tile<TY>::NT) void b_pass_a_kernel(BatchList L) {
   constexpr bool F = sizeof(T) == 4;
   __shared__ T tile[2][Tile<TY>::Rows][TX + 2];
@@ -1522,12 +1522,12 @@ __global__ __launch_bounds__(Tile<TY>::NT) void b_pass_a_kernel(BatchList L) {
   const Sweep sw = F ? E.swA32 : E.swA;
   double a0 = 0.0;
   // the batch's working set is far larger than the caches: streaming policy
-  pass_a_march<T, 2, true, TY>(sw, it, bf, (T)cs->beta, a0, tile, bid, nb, false);
+  pass_a_march<T, D, true, TY>(sw, it, bf, (T)cs->beta, a0, tile, bid, nb, false);
   const double v[1] = {a0};
   write_partials<1, Tile<TY>::NT>(v, E.parts, sh, bid, nb);
 }
 
-template <typename T, int TY>
+template <typename T, int TY, int D>
 __global__ __launch_bounds__(Tile<TY>::NT) void b_pass_b_kernel(BatchList L) {
   constexpr bool F = sizeof(T) == 4;
   __shared__ T tile[2][Tile<TY>::Rows][TX + 2];
@@ -1549,7 +1549,7 @@ __global__ __launch_bounds__(Tile<TY>::NT) void b_pass_b_kernel(BatchList L) {
   const CgBufs<T> bf = cg_bufs(it, r, p0, p1);
   const Sweep sw = F ? E.swB32 : E.swB;
   double a0 = 0.0;
-  pass_b_march<T, 2, true, TY>(sw, it, bf, uu, (T)cs->alpha, a0, tile, bid, nb, false);
+  pass_b_march<T, D, true, TY>(sw, it, bf, uu, (T)cs->alpha, a0, tile, bid, nb, false);
   const double v[1] = {a0};
   write_partials<1, Tile<TY>::NT>(v, E.parts, sh, bid, nb);
 }
@@ -1831,30 +1831,39 @@ void launch_b_residual_cast(const BatchList &L, BatchStatus *stat, hipStream_t s
   b_finalize_ir_kernel<<<L.n, FT, 0, st>>>(L, stat);
 }
 
-// f(integral_constant<int, ty>) for a tile height of 4, 8 or 16 rows (4 for anything else)
+// f(integral_constant<int, ty>, integral_constant<int, depth>) for a batched pass shape: tile height 4, 8 or 16 rows
+// (4 for anything else) and prefetch depth 2, 3, 4 or 6 (2 for anything else)
 template <typename F>
-static void with_height(int ty, F &&f) {
+static void with_batch_shape(int ty, int depth, F &&f) {
+  auto dep = [&](auto h) {
+    switch (depth) {
+      case 3: f(h, std::integral_constant<int, 3>{}); break;
+      case 4: f(h, std::integral_constant<int, 4>{}); break;
+      case 6: f(h, std::integral_constant<int, 6>{}); break;
+      default: f(h, std::integral_constant<int, 2>{}); break;
+    }
+  };
   switch (ty) {
-    case 8: f(std::integral_constant<int, 8>{}); break;
-    case 16: f(std::integral_constant<int, 16>{}); break;
-    default: f(std::integral_constant<int, kTy>{}); break;
+    case 8: dep(std::integral_constant<int, 8>{}); break;
+    case 16: dep(std::integral_constant<int, 16>{}); break;
+    default: dep(std::integral_constant<int, kTy>{}); break;
   }
 }
 
-void launch_b_iteration(int fp32, int ty, const BatchList &A, const BatchList &B, BatchStatus *stat,
+void launch_b_iteration(int fp32, int ty, int depth, const BatchList &A, const BatchList &B, BatchStatus *stat,
                         hipStream_t st) {
   if (A.total <= 0 || B.total <= 0) return;
-  with_height(ty, [&](auto h) {
-    constexpr int TY = decltype(h)::value;
+  with_batch_shape(ty, depth, [&](auto h, auto d) {
+    constexpr int TY = decltype(h)::value, D = decltype(d)::value;
     if (fp32) {
-      b_pass_a_kernel<float, TY><<<A.total, Tile<TY>::NT, 0, st>>>(A);
+      b_pass_a_kernel<float, TY, D><<<A.total, Tile<TY>::NT, 0, st>>>(A);
       b_finalize_pass_kernel<0, 1><<<A.n, FT, 0, st>>>(A, stat);
-      b_pass_b_kernel<float, TY><<<B.total, Tile<TY>::NT, 0, st>>>(B);
+      b_pass_b_kernel<float, TY, D><<<B.total, Tile<TY>::NT, 0, st>>>(B);
       b_finalize_pass_kernel<1, 1><<<B.n, FT, 0, st>>>(B, stat);
     } else {
-      b_pass_a_kernel<double, TY><<<A.total, Tile<TY>::NT, 0, st>>>(A);
+      b_pass_a_kernel<double, TY, D><<<A.total, Tile<TY>::NT, 0, st>>>(A);
       b_finalize_pass_kernel<0, 0><<<A.n, FT, 0, st>>>(A, stat);
-      b_pass_b_kernel<double, TY><<<B.total, Tile<TY>::NT, 0, st>>>(B);
+      b_pass_b_kernel<double, TY, D><<<B.total, Tile<TY>::NT, 0, st>>>(B);
       b_finalize_pass_kernel<1, 0><<<B.n, FT, 0, st>>>(B, stat);
     }
   });
@@ -1864,16 +1873,16 @@ void launch_b_tune_state(const BatchList &L, hipStream_t st) {
   if (L.n > 0) b_tune_state_kernel<<<(L.n + 255) / 256, 256, 0, st>>>(L);
 }
 
-void launch_b_passes(int fp32, int ty, const BatchList &A, const BatchList &B, hipStream_t st) {
+void launch_b_passes(int fp32, int ty, int depth, const BatchList &A, const BatchList &B, hipStream_t st) {
   if (A.total <= 0 || B.total <= 0) return;
-  with_height(ty, [&](auto h) {
-    constexpr int TY = decltype(h)::value;
+  with_batch_shape(ty, depth, [&](auto h, auto d) {
+    constexpr int TY = decltype(h)::value, D = decltype(d)::value;
     if (fp32) {
-      b_pass_a_kernel<float, TY><<<A.total, Tile<TY>::NT, 0, st>>>(A);
-      b_pass_b_kernel<float, TY><<<B.total, Tile<TY>::NT, 0, st>>>(B);
+      b_pass_a_kernel<float, TY, D><<<A.total, Tile<TY>::NT, 0, st>>>(A);
+      b_pass_b_kernel<float, TY, D><<<B.total, Tile<TY>::NT, 0, st>>>(B);
     } else {
-      b_pass_a_kernel<double, TY><<<A.total, Tile<TY>::NT, 0, st>>>(A);
-      b_pass_b_kernel<double, TY><<<B.total, Tile<TY>::NT, 0, st>>>(B);
+      b_pass_a_kernel<double, TY, D><<<A.total, Tile<TY>::NT, 0, st>>>(A);
+      b_pass_b_kernel<double, TY, D><<<B.total, Tile<TY>::NT, 0, st>>>(B);
     }
   });
 }

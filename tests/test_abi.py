@@ -92,9 +92,9 @@ def test_bad_arguments(abi):
     sh = (ctypes.c_int32 * 4)(16, 2, 0, 4)
     assert L.excmg_get_sweep(None, 0, 0, sh) == abi.ERR_ARG
     assert L.excmg_set_sweep(None, 0, 0, sh) == abi.ERR_ARG
-    ty = (ctypes.c_int32 * 2)(4, 4)
-    assert L.excmg_get_batch_height(None, ty) == abi.ERR_ARG
-    assert L.excmg_set_batch_height(None, ty) == abi.ERR_ARG
+    bs = (ctypes.c_int32 * 4)(4, 4, 2, 2)
+    assert L.excmg_get_batch_shape(None, bs) == abi.ERR_ARG
+    assert L.excmg_set_batch_shape(None, bs) == abi.ERR_ARG
 
 
 @pytest.mark.parametrize("flags,tol_order,ok", [(0, 0.0, True), (0, 6.0, True), (0, 16.0, True), (0, -1.0, False),

@@ -113,20 +113,21 @@ def test_batched_autotune_keeps_results(ex, orc):
         assert rel2(host(ub), ref["u"]) <= 1e-12, n
 
 
-@pytest.mark.parametrize("ty", [4, 8, 16])
-def test_batched_tile_heights_match_oracle(ex, orc, ty):
-    """The batched CG passes at each tile height (set on the batch's first solver), FP64, against the oracle with the
-    batch's per-grid iteration counts; a bad height is refused."""
+@pytest.mark.parametrize("ty,depth", [(4, 2), (8, 3), (16, 4), (4, 6), (16, 6)])
+def test_batched_tile_heights_match_oracle(ex, orc, ty, depth):
+    """The batched CG passes at each tile height and prefetch depth (set on the batch's first solver), FP64, against
+    the oracle with the batch's per-grid iteration counts; bad shapes are refused."""
     tol = 1e-10
     solvers, fs, gs, data, us, stats, ms = _run(ex, MIXED, tol, ex.FP64)
-    solvers[0].set_batch_height((ty, ty))
-    assert solvers[0].get_batch_height() == (ty, ty)
+    solvers[0].set_batch_shape((ty, ty, depth, depth))
+    assert solvers[0].get_batch_shape() == (ty, ty, depth, depth)
     us, stats, ms = ex.solve_batched(solvers, fs, gs)
     for (n, nc, p), s, (f, g, u, _), ub, st in zip(MIXED, solvers, data, us, stats):
         ref = orc.excmg(f, g, p.box, s.n_coarse, tol, fixed_iters=np.array(st["iters"], dtype=np.int32))
         assert rel2(host(ub), ref["u"]) <= 1e-12, n
-    with pytest.raises(ex.ExcmgError):
-        solvers[0].set_batch_height((12, 4))
+    for bad in [(12, 4, 2, 2), (4, 4, 5, 2)]:
+        with pytest.raises(ex.ExcmgError):
+            solvers[0].set_batch_shape(bad)
 
 
 # two problems whose finest grids relax in FP32 (127 x 127 x 95 and 191 x 95 x 63 unknowns), and the oracle's solutions
@@ -137,8 +138,8 @@ BIG32 = [
 _REF32 = {}
 
 
-@pytest.mark.parametrize("ty", [4, 8, 16])
-def test_batched_fp32_tile_heights_against_oracle(ex, orc, ty):
+@pytest.mark.parametrize("ty,depth", [(4, 2), (8, 4), (16, 6)])
+def test_batched_fp32_tile_heights_against_oracle(ex, orc, ty, depth):
     """The batched FP32 refinement passes at each tile height, against the FP64 oracle where both are limited by the
     discretisation error (tol 1e-13): the batch's solution within 1% of the oracle's own error against the exact field
     (root mean square over all nodes)."""
@@ -150,7 +151,7 @@ def test_batched_fp32_tile_heights_against_oracle(ex, orc, ty):
         fs.append(dev(f))
         gs.append(dev(g))
         data.append((f, g, u))
-    solvers[0].set_batch_height((4, ty))
+    solvers[0].set_batch_shape((4, ty, 2, depth))
     us, stats, ms = ex.solve_batched(solvers, fs, gs)
     rms = lambda a: float(np.sqrt(np.mean(np.square(a))))
     for q, ((n, nc, p), (f, g, u)) in enumerate(zip(BIG32, data)):
