@@ -551,7 +551,9 @@ def main():
     print("# streaming probe (GB/s): " + ", ".join(f"{k} {v:.0f}" for k, v in probe.items()), file=sys.stderr,
           flush=True)
     s = ex.Solver(n, p.box, args.tol, timing=True)
+    t_tune = time.perf_counter()
     zc64, dp64 = s.autotune(with_depth=True)
+    tune_s = time.perf_counter() - t_tune
     print(f"# autotuned z chunks (A, B) per grid: {[z[:2] for z in zc64]}, depths {[d[:2] for d in dp64]}",
           file=sys.stderr, flush=True)
     u = s.empty()
@@ -672,6 +674,7 @@ def main():
         "autotuned_z_chunks": [list(z[:2]) for z in zc64],
         "autotuned_depths": [[x % 100 for x in d[:2]] for d in dp64],
         "autotuned_tile_heights": [[x // 100 for x in d[:2]] for d in dp64],
+        "autotune_s": round(tune_s, 2),
         "ms_per_grid": [round(v, 3) for v in plain[-1]["ms_level"]],
         "solve_ms_fp64": round(float(np.median([st["ms_total"] for st in plain])), 3),  # median over the timed steps
         "ms_per_step_with_kernel_events": round(ms_step_timed, 3),
