@@ -594,6 +594,31 @@ def test_paper_tables_example4_finest_meshes(orc):
             _check_row(got[(norm, qty)], norm, qty, val)
 
 
+def test_r25_orders_follow_regularity(orc):
+    """u = r^2.5 about the box centre (a node of every grid) lies in H^(4-e) only, so the errors converge at the orders
+    that regularity allows rather than the scheme's fourth order: L2 (RMS over all nodes) 3.5 and max norm 2.5 for u_h,
+    3 and 1.5 for its compact gradient, 3.5 and 2.5 for u~_h.  Measured from 32^3 to 64^3 at tol 1e-13 (the algebraic
+    error far below): 3.46 / 2.48, 2.96 / 1.50, 3.59 / 2.49 (they approach 3.5 / 2.5 / 3 / 1.5 from 64^3 to 128^3:
+    3.48 / 2.49, 2.98 / 1.50, 3.55 / 2.50)."""
+    p = synth.r25()
+    rms = lambda a: float(np.sqrt(np.mean(a * a)))
+    err = []
+    for N in (32, 64):
+        n = (N, N, N)
+        f, g, u = synth.sample(p, n)
+        r = orc.excmg(f, g, p.box, (4, 4, 4), 1e-13, want_ext=True)
+        gr = orc.gradient(r["u"], p.box)
+        gex = synth.exact_gradient(p, n)
+        err.append(dict(u2=rms(r["u"] - u), ui=np.max(np.abs(r["u"] - u)),
+                        g2=float(np.sqrt(sum(rms(a - b) ** 2 for a, b in zip(gr, gex)))),
+                        gi=max(np.max(np.abs(a - b)) for a, b in zip(gr, gex)),
+                        t2=rms(r["ut"] - u), ti=np.max(np.abs(r["ut"] - u))))
+    order = {k: np.log2(err[0][k] / err[1][k]) for k in err[0]}
+    windows = dict(u2=(3.35, 3.6), ui=(2.4, 2.6), g2=(2.85, 3.05), gi=(1.4, 1.6), t2=(3.4, 3.7), ti=(2.4, 2.6))
+    for k, (lo, hi) in windows.items():
+        assert lo <= order[k] <= hi, (k, order[k])
+
+
 def test_level_tolerance_schedule(orc):
     """The level-dependent tolerance (tol_order p: level l of the finest Lt relaxes to tol * 2^(p (Lt - l))), a
     schedule the paper does not give, for its remark that a uniform tolerance costs the extrapolated solution its sixth
