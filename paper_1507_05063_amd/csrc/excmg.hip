@@ -226,9 +226,9 @@ struct excmg_handle {
   // pinned host memory the device writes CG states (and batch status words) into; pin_dev is its device address
   void *pin_host = nullptr, *pin_dev = nullptr;
   size_t pin_bytes = 0;
-  // graphs of kBatch CG iterations per grid (FP64, FP32 inner), captured on first use on a private stream
+  // graphs of 8, 16 and 32 CG iterations per grid (FP64, FP32 inner), captured on first use on a private stream
   hipStream_t cap = nullptr;
-  hipGraphExec_t gexec[EXCMG_MAX_LEVELS][2] = {};
+  hipGraphExec_t gexec[EXCMG_MAX_LEVELS][2][3] = {};
   // a handle of excmg_solve_noalloc: no events, graphs, capture stream or pinned memory; CG states are read back with
   // plain stream copies
   bool noalloc = false;
@@ -243,11 +243,12 @@ struct excmg_handle {
 
   void drop_graphs() {
     for (auto &row : gexec)
-      for (auto &ex : row)
-        if (ex) {
-          (void)hipGraphExecDestroy(ex);
-          ex = nullptr;
-        }
+      for (auto &sizes : row)
+        for (auto &ex : sizes)
+          if (ex) {
+            (void)hipGraphExecDestroy(ex);
+            ex = nullptr;
+          }
     for (auto &bg : bgraphs) (void)hipGraphExecDestroy(bg.ex);
     bgraphs.clear();
   }
@@ -357,20 +358,24 @@ struct LevelIters {
   std::vector<int> inner[EXCMG_MAX_LEVELS];  // FP32_IR: inner iterations of each outer step
 };
 
-constexpr int kBatch = 4;
-constexpr int kBatchMax = 16;
+// Iterations launched before the first look at the CG state, and at most per look: in a single solve (launched as
+// graphs of kGraphSizes iterations), and in each round of a batched solve.
+constexpr int kSolveFirst = 8, kSolveMax = 32;
+constexpr int kBatch = 4, kBatchMax = 16;
+constexpr int kGraphSizes[3] = {8, 16, 32};
 
 // CG iterations to launch before the next look at the state: from the residual decay since the start (rho0 -> rho over
 // `done` iterations), the geometric rate predicts how many remain; a few more are launched than predicted, since
-// iterations launched after convergence cost a near-empty launch each while a look costs a round trip.
-int next_batch(double rho, double rho0, int done, double stop2) {
-  if (done <= 0 || !(rho > 0.0) || !(rho0 > rho) || !(stop2 > 0.0)) return kBatch;
+// iterations launched after convergence cost a near-empty launch each while a look costs a round trip.  first: the
+// count without a rate yet; cap: the most.
+int next_batch(double rho, double rho0, int done, double stop2, int first, int cap) {
+  if (done <= 0 || !(rho > 0.0) || !(rho0 > rho) || !(stop2 > 0.0)) return first;
   if (rho <= stop2) return 1;
   const double rate = log(rho / rho0) / done;  // < 0
   const double need = log(stop2 / rho) / rate;
   int n = (int)ceil(1.15 * need) + 1;
   if (n < 2) n = 2;
-  if (n > kBatchMax) n = kBatchMax;
+  if (n > cap) n = cap;
   return n;
 }
 
@@ -446,14 +451,14 @@ bool use_graphs(const excmg_handle *h, int l) {
   return !h->noalloc && !(h->p.flags & EXCMG_NO_GRAPHS) && l < h->lo.L - 1;
 }
 
-// kBatch CG iterations of grid l (not the first of a self-finalizing FP64 solve) as one graph launch on the handle's
-// stream.  The graph holds kernel launches only; it is captured on first use and kept until the sweeps change.
-int launch_iteration_graph(excmg_handle *h, int l, int fp32) {
-  hipGraphExec_t &ex = h->gexec[l][fp32];
+// kGraphSizes[si] CG iterations of grid l (not the first of a self-finalizing FP64 solve) as one graph launch on the
+// handle's stream.  The graph holds kernel launches only; it is captured on first use and kept until the sweeps change.
+int launch_iteration_graph(excmg_handle *h, int l, int fp32, int si) {
+  hipGraphExec_t &ex = h->gexec[l][fp32][si];
   if (!ex) {
     hipGraph_t g = nullptr;
     HIPCHECK(hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal));
-    for (int q = 0; q < kBatch; ++q) launch_iteration(h, l, fp32, false, h->cap, -1, -1);
+    for (int q = 0; q < kGraphSizes[si]; ++q) launch_iteration(h, l, fp32, false, h->cap, -1, -1);
     const hipError_t ec = hipStreamEndCapture(h->cap, &g);
     if (ec != hipSuccess) return EXCMG_ERR_HIP;
     const hipError_t ei = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
@@ -467,7 +472,9 @@ int launch_iteration_graph(excmg_handle *h, int l, int fp32) {
   return EXCMG_OK;
 }
 
-// Launch nb iterations (rounded up to whole graphs where graphs are used); returns the new launched count.
+// Launch nb iterations (where graphs are used: rounded up to a multiple of 8, which leaves the prediction of
+// next_batch some slack against another look, and launched as the fewest graphs of 32, 16 and 8 iterations); returns
+// the new launched count.
 int launch_iterations(excmg_handle *h, int l, int fp32, int nb, int launched, int outer, int *err) {
   *err = EXCMG_OK;
   const bool selfred64 = !fp32 && self_finalizing(h->lo.lev[l], false);
@@ -482,9 +489,14 @@ int launch_iterations(excmg_handle *h, int l, int fp32, int nb, int launched, in
     ++q;
     ++launched;
   }
-  for (; q < nb; q += kBatch, launched += kBatch) {
-    *err = launch_iteration_graph(h, l, fp32);
-    if (*err) return launched;
+  int rem = nb > q ? (nb - q + 7) / 8 * 8 : 0;
+  for (int si = 2; si >= 0; --si) {
+    while (rem >= kGraphSizes[si]) {
+      *err = launch_iteration_graph(h, l, fp32, si);
+      if (*err) return launched;
+      rem -= kGraphSizes[si];
+      launched += kGraphSizes[si];
+    }
   }
   return launched;
 }
@@ -518,7 +530,7 @@ int cg64(excmg_handle *h, int l, const RhsSrc &rs, bool finest, int *iters, doub
   if (e) return e;
   CgState hs;
   int launched = 0;
-  for (int nb = kBatch;;) {
+  for (int nb = kSolveFirst;;) {
     launched = launch_iterations(h, l, 0, nb, launched, -1, &e);
     if (e) return e;
     e = last_error();
@@ -526,7 +538,7 @@ int cg64(excmg_handle *h, int l, const RhsSrc &rs, bool finest, int *iters, doub
     e = read_state(h, &hs, h->cs);
     if (e) return e;
     if (hs.done) break;
-    nb = next_batch(hs.rho, hs.rho0, hs.iter, hs.stop2);
+    nb = next_batch(hs.rho, hs.rho0, hs.iter, hs.stop2, kSolveFirst, kSolveMax);
   }
   *iters = hs.iter;
   *relres = hs.bnorm2 > 0.0 ? sqrt(hs.rho / hs.bnorm2) : 0.0;
@@ -570,7 +582,7 @@ int cg_ir(excmg_handle *h, int l, const RhsSrc &rs, bool finest, int *iters, int
       break;
     }
     int launched = 0;
-    for (int nb = kBatch;;) {
+    for (int nb = kSolveFirst;;) {
       launched = launch_iterations(h, l, 1, nb, launched, outer, &e);
       if (e) return e;
       e = last_error();
@@ -578,7 +590,7 @@ int cg_ir(excmg_handle *h, int l, const RhsSrc &rs, bool finest, int *iters, int
       e = read_state(h, &hi, h->cs2);
       if (e) return e;
       if (hi.done) break;
-      nb = next_batch(hi.rho, hi.rho0, hi.iter, hi.stop2);
+      nb = next_batch(hi.rho, hi.rho0, hi.iter, hi.stop2, kSolveFirst, kSolveMax);
     }
     total += hi.iter;
     if (inner_counts) inner_counts->push_back(hi.iter);
@@ -1138,7 +1150,7 @@ int batched_solve(excmg_handle *const *hs, int count, const double *const *f, co
           if (m.done) {
             if ((e = finish_grid(b))) return e;
           } else {
-            const int want = fresh[b] ? kBatch : next_batch(m.rho, m.rho0, m.iter, m.stop2);
+            const int want = fresh[b] ? kBatch : next_batch(m.rho, m.rho0, m.iter, m.stop2, kBatch, kBatchMax);
             nb64 = want > nb64 ? want : nb64;
             any64 = true;
           }
@@ -1154,7 +1166,7 @@ int batched_solve(excmg_handle *const *hs, int count, const double *const *f, co
             ++outer[b];
             ph[b] = kPhOuter;
           } else {
-            const int want = fresh[b] ? kBatch : next_batch(mi.rho, mi.rho0, mi.iter, mi.stop2);
+            const int want = fresh[b] ? kBatch : next_batch(mi.rho, mi.rho0, mi.iter, mi.stop2, kBatch, kBatchMax);
             nb32 = want > nb32 ? want : nb32;
             any32 = true;
           }
