@@ -1520,6 +1520,9 @@ int solve_on(excmg_handle *h, const double *f, const double *g, double *u, doubl
 // to queue them: about 5 us per launch)
 constexpr int kTuneBurst = 8;
 constexpr double kTuneDelayUs = 120.0;
+// candidates timed again after the first round, and the timed launches each gets then
+constexpr int kTuneFinal = 4;
+constexpr int kTuneFinalReps = 7;
 
 extern "C" {
 
@@ -1603,16 +1606,10 @@ int excmg_autotune(excmg_handle *h, int32_t *zc_out, int32_t *depth_out) {
         // partials' halves hold three times over)
         const int nb_other = std::min(
             sweep_blocks(prec ? (pass ? lv.swA32 : lv.swB32) : (pass ? lv.swA : lv.swB)), selfred_max_blocks());
-        for (int ci = 0; ci < kVar * (int)(sizeof(cand) / sizeof(cand[0])); ++ci) {
-          const int zc = cand[ci / kVar], ty = heights[(ci % kVar) / kDp], depth = depths[(ci % kDp) / 2];
-          const int nt = ci % 2;
-          if (zc > 2 * (g.nz - 1) + 2) break;
-          if (ty > 4 && ty / 2 >= g.ny - 1) continue;  // a tile at least twice the grid's height
-          const Sweep sw = make_sweep(g, lv.st, zc, depth, nt, ty);
-          if (3LL * sweep_blocks(sw) > lo.npart) continue;
-          if (burst && sweep_blocks(sw) > selfred_max_blocks()) continue;
+        // the fastest launch of reps timed trials of shape sw (the first of them only warms caches and code)
+        auto trial = [&](const Sweep &sw, int reps) -> float {
           float tmin = 1e30f;
-          for (int rep = 0; rep < 3; ++rep) {
+          for (int rep = 0; rep < reps && rc == EXCMG_OK; ++rep) {
             if (burst) {
               launch_tune_selfred(h->cs2, pass ? pa : pb, nb_other, s);
               launch_delay(kTuneDelayUs, s);
@@ -1644,14 +1641,34 @@ int excmg_autotune(excmg_handle *h, int32_t *zc_out, int32_t *depth_out) {
             float ms = 0.0f;
             if (hipEventElapsedTime(&ms, ea, eb) != hipSuccess) rc = EXCMG_ERR_HIP;
             ms /= burst ? kTuneBurst : 1;
-            if (rep > 0 && ms < tmin) tmin = ms;  // the first launch warms caches and code
+            if (rep > 0 && ms < tmin) tmin = ms;
           }
-          if (rc) break;
-          if (tmin < best) {
-            best = tmin;
-            bsw = sw;
+          return tmin;
+        };
+        // every candidate timed twice; then the kTuneFinal fastest again, kTuneFinalReps times each, so that a shape
+        // is not kept for a difference within the timing noise of two launches
+        std::vector<std::pair<float, Sweep>> timed;
+        for (int ci = 0; ci < kVar * (int)(sizeof(cand) / sizeof(cand[0])) && rc == EXCMG_OK; ++ci) {
+          const int zc = cand[ci / kVar], ty = heights[(ci % kVar) / kDp], depth = depths[(ci % kDp) / 2];
+          const int nt = ci % 2;
+          if (zc > 2 * (g.nz - 1) + 2) break;
+          if (ty > 4 && ty / 2 >= g.ny - 1) continue;  // a tile at least twice the grid's height
+          const Sweep sw = make_sweep(g, lv.st, zc, depth, nt, ty);
+          if (3LL * sweep_blocks(sw) > lo.npart) continue;
+          if (burst && sweep_blocks(sw) > selfred_max_blocks()) continue;
+          timed.push_back({trial(sw, 3), sw});
+        }
+        if (rc) break;
+        std::sort(timed.begin(), timed.end(),
+                  [](const std::pair<float, Sweep> &a, const std::pair<float, Sweep> &b) { return a.first < b.first; });
+        for (size_t q = 0; q < timed.size() && q < (size_t)kTuneFinal && rc == EXCMG_OK; ++q) {
+          const float t = std::min(timed[q].first, trial(timed[q].second, kTuneFinalReps));
+          if (t < best) {
+            best = t;
+            bsw = timed[q].second;
           }
         }
+        if (rc) break;
         dst = bsw;
       }
     }
