@@ -114,6 +114,10 @@ typedef struct {
                            EXCMG_STOP_F_G (whose ||f_h|| / sqrt(unknowns) does not grow as h falls) keeps the
                            algebraic error of every grid proportional to the sixth-order truncation error.  0 <= p
                            <= 16 */
+  double tol_coarse;    /* 0 = as above; > 0 (and < 1, with tol_order 0): every grid below the finest relaxes to
+                           tol_coarse and the finest to tol (the paper gives one epsilon for all grids; this reading
+                           of Algorithm 1's stopping test, tol_coarse = tol / 100, reproduces the anisotropic example's
+                           two finest meshes in Section 5).  Errors: EXCMG_ERR_ARG outside that range */
 } excmg_problem;
 
 /* Statistics of one call (host struct, filled by the library). */

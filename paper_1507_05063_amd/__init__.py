@@ -26,7 +26,7 @@ def _torch():
 
 
 def _problem(n, box, tol, n_coarse=(0, 0, 0), precision=FP64, inner_tol=0.0, max_iters=0, flags=0,
-             tol_order=0.0):
+             tol_order=0.0, tol_coarse=0.0):
     p = _lib.Problem()
     for d in range(3):
         p.box[d] = float(box[d])
@@ -38,6 +38,7 @@ def _problem(n, box, tol, n_coarse=(0, 0, 0), precision=FP64, inner_tol=0.0, max
     p.max_iters = int(max_iters)
     p.flags = int(flags)
     p.tol_order = float(tol_order)
+    p.tol_coarse = float(tol_coarse)
     return p
 
 
@@ -84,13 +85,15 @@ class Solver:
     def __init__(self, n: Sequence[int], box=(1.0, 1.0, 1.0), tol: float = 1e-10, n_coarse=(0, 0, 0),
                  precision: int = FP64, inner_tol: float = 0.0, max_iters: int = 0, history: bool = False,
                  timing: bool = False, graphs: bool = True, guess: str = "quartic", stop_norm: str = "b",
-                 tol_order: float = 0.0, stream=None):
+                 tol_order: float = 0.0, tol_coarse: float = 0.0, stream=None):
         """guess: the initial guess of every grid from the third on: "quartic" (EXP_finite, the paper's method),
         "quadratic" (the same extrapolation, tri-quadratic interpolation) or "linear" (CMG: trilinear u_2h).
         stop_norm: the ||f_h|| of the stopping test: "b" (the eliminated right-hand side), "fg" (R f inside, g on
         the boundary) or "fg_coarse" ("fg" on every grid below the finest, "b" on the finest).
         tol_order: p >= 0; grid l of L relaxes to tol * 2^(p (L-1-l)) (at most max(tol, 1e-2)): tol on the finest grid,
-        looser on the coarser ones (0: tol everywhere, Algorithm 1)."""
+        looser on the coarser ones (0: tol everywhere, Algorithm 1).
+        tol_coarse: 0, or in (0, 1) with tol_order 0: every grid below the finest relaxes to tol_coarse, the finest
+        to tol."""
         torch = _torch()
         self.n = tuple(int(v) for v in n)
         self.box = tuple(float(v) for v in box)
@@ -105,7 +108,9 @@ class Solver:
         flags = (WANT_HISTORY if history else 0) | (WANT_TIMING if timing else 0) | (0 if graphs else NO_GRAPHS)
         flags |= _lib.GUESS_FLAGS[guess] | _lib.STOP_NORM_FLAGS[stop_norm]
         self.tol_order = float(tol_order)
-        self._p = _problem(self.n, self.box, tol, n_coarse, precision, inner_tol, max_iters, flags, tol_order)
+        self.tol_coarse = float(tol_coarse)
+        self._p = _problem(self.n, self.box, tol, n_coarse, precision, inner_tol, max_iters, flags, tol_order,
+                           tol_coarse)
         nbytes = ctypes.c_size_t(0)
         _lib.check(_lib.lib().excmg_workspace_bytes(ctypes.byref(self._p), ctypes.byref(nbytes)),
                    "excmg_workspace_bytes")

@@ -38,6 +38,7 @@ class Problem(ctypes.Structure):
         ("max_iters", ctypes.c_int32),
         ("flags", ctypes.c_uint32),
         ("tol_order", ctypes.c_double),
+        ("tol_coarse", ctypes.c_double),
     ]
 
 

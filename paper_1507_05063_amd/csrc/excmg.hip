@@ -102,15 +102,19 @@ int validate(const excmg_problem *p) {
   if ((p->flags & EXCMG_GUESS_QUADRATIC) && (p->flags & EXCMG_GUESS_LINEAR)) return EXCMG_ERR_ARG;
   if ((p->flags & EXCMG_STOP_F_G) && (p->flags & EXCMG_STOP_F_G_BELOW_FINEST)) return EXCMG_ERR_ARG;
   if (!(p->tol_order >= 0.0) || p->tol_order > 16.0) return EXCMG_ERR_ARG;
+  if (!(p->tol_coarse >= 0.0) || !(p->tol_coarse < 1.0) || (p->tol_coarse > 0.0 && p->tol_order > 0.0))
+    return EXCMG_ERR_ARG;
   return EXCMG_OK;
 }
 
 // z planes per workgroup of the residual sweeps on large grids
 constexpr int kResidChunk = 64;
 
-// The relative-residual tolerance of grid l: tol on every grid, or with tol_order = p > 0, tol * 2^(p (L-1-l)) capped
-// at max(tol, 1e-2) (tol on the finest grid, looser on each coarser one).
+// The relative-residual tolerance of grid l: tol on every grid; with tol_coarse > 0, tol_coarse on every grid below
+// the finest; or with tol_order = p > 0, tol * 2^(p (L-1-l)) capped at max(tol, 1e-2) (tol on the finest grid, looser
+// on each coarser one).
 double level_tol(const excmg_problem &p, int l, int L) {
+  if (p.tol_coarse > 0.0) return l < L - 1 ? p.tol_coarse : p.tol;
   if (!(p.tol_order > 0.0)) return p.tol;
   const double cap = p.tol > 1e-2 ? p.tol : 1e-2;
   const double t = p.tol * exp2(p.tol_order * (double)(L - 1 - l));

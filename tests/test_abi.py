@@ -114,6 +114,19 @@ def test_problem_validation(abi, flags, tol_order, ok):
         assert code == abi.ERR_ARG
 
 
+@pytest.mark.parametrize("tol_coarse,tol_order,ok", [(1e-11, 0.0, True), (0.5, 0.0, True), (0.0, 6.0, True),
+                                                     (1e-11, 6.0, False), (-1e-11, 0.0, False), (1.0, 0.0, False),
+                                                     (float("nan"), 0.0, False), (float("inf"), 0.0, False)])
+def test_coarse_tolerance_validation(abi, tol_coarse, tol_order, ok):
+    """The tolerance of the grids below the finest: 0 (off) or in (0, 1), and not together with tol_order."""
+    import paper_1507_05063_amd as ex
+
+    p = ex._problem((16, 16, 16), (1.0, 1.0, 1.0), 1e-9, tol_order=tol_order, tol_coarse=tol_coarse)
+    b = ctypes.c_size_t(0)
+    code = abi.lib().excmg_workspace_bytes(ctypes.byref(p), ctypes.byref(b))
+    assert code == (abi.OK if ok else abi.ERR_ARG), code
+
+
 def test_workspace_bytes_scale(abi):
     import paper_1507_05063_amd as ex
 

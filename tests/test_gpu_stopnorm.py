@@ -270,3 +270,38 @@ def test_schedule_graphs_match_direct_launches(ex, precision):
         ug, _, stg = sg.solve(fd, gd)
         assert torch.equal(ug, ud)
         assert stg["iters"] == std["iters"]
+
+
+@pytest.mark.parametrize("case", ["ex4-aniso", "ex2-ragged", "ex5-fp32"])
+def test_coarse_tolerance_solve_parity(ex, orc, case):
+    """tol_coarse: the grids below the finest stop at tol_coarse, the finest at tol (the reading that reproduces the
+    anisotropic example's finest meshes).  Those grids are the grids of a run to the mesh n/2 at tol_coarse, so their
+    counts are the oracle's for that run (within one); the finest count is within one of the oracle's free-running
+    count from there (FP64), and u is the oracle's with the counts of the HIP path (FP32 refinement, whose finest
+    count is of inner iterations: within 1% of the discretisation error, as in the mixed-precision parity tests)."""
+    e, n, nc, tol, tc, prec = {
+        "ex4-aniso": (4, (128, 64, 32), (8, 4, 2), 1e-9, 1e-11, ex.FP64),
+        "ex2-ragged": (2, (80, 48, 112), (10, 6, 14), 1e-11, 1e-13, ex.FP64),
+        # the finest grid in FP32 refinement to the discretisation error, the grids below at a looser tolerance
+        "ex5-fp32": (5, (128, 128, 128), (4, 4, 4), 1e-14, 1e-12, ex.FP32_IR),
+    }[case]
+    p = synth.example(e)
+    f, g, u = synth.sample(p, n)
+    s = ex.Solver(n, p.box, tol, n_coarse=nc, tol_coarse=tc, precision=prec)
+    ug, _, st = s.solve(dev(f), dev(g))
+    ug = host(ug)
+    gi = np.array(st["iters"], dtype=np.int32)
+    L = st["levels"]
+    half = orc.excmg(f[::2, ::2, ::2], g[::2, ::2, ::2], p.box, s.n_coarse, tc)
+    assert np.all(np.abs(gi[:-1] - half["iters"]) <= 1), (gi, half["iters"])
+    free = orc.excmg(f, g, p.box, s.n_coarse, tol, fixed_iters=np.r_[half["iters"], -1])
+    if prec == ex.FP64:  # (the FP32 refinement counts inner iterations)
+        assert abs(int(gi[-1]) - int(free["iters"][-1])) <= 1, (gi, free["iters"])
+    for l in range(2, L):
+        assert st["relres"][l] <= (tol if l == L - 1 else tc), (l, st["relres"])
+    if prec == ex.FP64:
+        ref = orc.excmg(f, g, p.box, s.n_coarse, tol, fixed_iters=gi)
+        assert rel2(ug, ref["u"]) <= 1e-12
+    else:
+        rms = lambda a: float(np.sqrt(np.mean(np.square(a))))
+        assert rms(ug - free["u"]) <= 0.01 * rms(free["u"] - u)

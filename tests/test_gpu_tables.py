@@ -8,7 +8,8 @@ w_h - u_h within 30% (it follows no convention found).  Each example's table is 
 finest mesh, with the stopping test's norm that of (R f inside, g on the boundary) on every grid below the finest and
 that of the eliminated right-hand side on the finest (EXCMG_STOP_F_G_BELOW_FINEST): rows at the finest mesh come
 from that run, rows below it from runs to their mesh with the (R f, g) norm on every grid (EXCMG_STOP_F_G), which
-is the same cascade stopped early.  Entries marked 'x' are not reproduced by this reading and are listed only.
+is the same cascade stopped early.  Entries marked 'x' are not reproduced by this reading; those of Example 4 are
+reproduced by another (grids below the finest at eps/100, tol_coarse), the other two are listed only.
 w_h is the finest grid's initial guess: EXP_finite of the solutions on the grids n/2 and n/4, which are the cascade's
 own grids (the level data are the finest data sampled at strides 2 and 4), solved here as problems of their own.
 """
@@ -69,20 +70,21 @@ def coarsest(e):
 _CACHE = {}
 
 
-def run_case(ex, e, n, tol, stop_norm="b"):
-    key = (e, n, tol, stop_norm)
+def run_case(ex, e, n, tol, stop_norm="b", tol_coarse=0.0):
+    key = (e, n, tol, stop_norm, tol_coarse)
     if key in _CACHE:
         return _CACHE[key]
     p = synth.example(e)
     f, g, u = synth.sample(p, n)
-    s = ex.Solver(n, p.box, tol, n_coarse=coarsest(e), stop_norm=stop_norm)
+    s = ex.Solver(n, p.box, tol, n_coarse=coarsest(e), stop_norm=stop_norm, tol_coarse=tol_coarse)
     fd, gd = dev(f), dev(g)
     ug, ueg, st = s.solve(fd, gd, want_ext=True)
     grads = [host(t) for t in s.gradient(ug)]
     sub = {}
     for q in (2, 4):  # grids below the finest: the (R f, g) norm under either reading the table uses
         m = tuple(v // q for v in n)
-        sq = ex.Solver(m, p.box, tol, n_coarse=coarsest(e), stop_norm="fg" if stop_norm != "b" else "b")
+        sq = ex.Solver(m, p.box, tol_coarse if tol_coarse > 0 else tol, n_coarse=coarsest(e),
+                       stop_norm="fg" if stop_norm != "b" else "b")
         sub[q], _, _ = sq.solve(fd[::q, ::q, ::q].contiguous(), gd[::q, ::q, ::q].contiguous())
         del sq
     w = host(ex.op_initial_guess("quartic", sub[2], sub[4], gd, n))
@@ -110,13 +112,36 @@ def run_case(ex, e, n, tol, stop_norm="b"):
 def test_paper_tables_on_gpu(ex, row):
     e, n, tol, norm, qty, val, unmatched = row
     if unmatched:
+        if e == 4:
+            pytest.skip("entry not reproduced by this reading; test_paper_tables_example4_finest_meshes_on_gpu "
+                        "reproduces it under another")
         pytest.skip("entry not reproduced by the reading (listed in the golden file)")
-    got = run_case(ex, e, n, tol, reading(e, n, tol))[(norm, qty)]
+    check_entry(run_case(ex, e, n, tol, reading(e, n, tol))[(norm, qty)], norm, qty, val)
+
+
+def check_entry(got, norm, qty, val):
     if norm == "l2" and qty == "w":
         assert 0.7 * val < got < 1.3 * val, (got, val)
         return
     rel = 0.02 if qty in ("u", "grad") else 0.06
     assert abs(got - val) <= rel * val, (got, val)
+
+
+def test_paper_tables_example4_finest_meshes_on_gpu(ex):
+    """Example 4 (coarsest 8x4x2, eps 1e-9) on its two finest meshes, 256x128x64 and 512x256x128, every printed entry
+    (the 'x' ones included), under the reading that reproduces them in the oracle: the grids below the finest stop at
+    eps/100 and the finest at eps, both on the eliminated right-hand side's norm (tol_coarse).  The 256x128x64 rows
+    are the finest grid of that cascade, a run to that mesh at eps/100; the 512x256x128 run takes the same counts on
+    those grids and the printed 8 iterations on the finest (within one)."""
+    eps = 1e-9
+    rows = [r for r in table_rows() if r[0] == 4 and r[1] in ((256, 128, 64), (512, 256, 128))]
+    assert len(rows) == 16
+    mid = run_case(ex, 4, (256, 128, 64), eps / 100)
+    fine = run_case(ex, 4, (512, 256, 128), eps, tol_coarse=eps / 100)
+    assert all(abs(a - b) <= 1 for a, b in zip(fine["iters"][:-1], mid["iters"])), (fine["iters"], mid["iters"])
+    assert abs(fine["iters"][-1] - 8) <= 1, fine["iters"]
+    for _, n, _, norm, qty, val, _ in rows:
+        check_entry((mid if n == (256, 128, 64) else fine)[(norm, qty)], norm, qty, val)
 
 
 def iteration_rows():
