@@ -71,6 +71,13 @@ extern "C" {
  * reproduces both the paper's printed finest-grid errors (Tables 1-12, read as the grids of one run) and its printed
  * finest-grid iteration counts.  At most one of EXCMG_STOP_F_G and this flag. */
 #define EXCMG_STOP_F_G_BELOW_FINEST 64u
+/* CG form on the small grids below the finest (at most 2^18 unknowns, from the third grid on) whose iterations
+ * finalize their own reductions.  Default:
+ * the single-reduction form of Chronopoulos and Gear, the same Krylov iterates as Algorithm 1's CG in exact
+ * arithmetic (so the same iteration counts up to rounding), with both inner products of an iteration from one
+ * reduction, which makes an iteration one kernel launch instead of two; it keeps s = M p and w = M r and moves 80
+ * bytes per unknown and iteration instead of 64.  With this flag every grid runs the two-pass CG as written. */
+#define EXCMG_TWO_PASS_CG 256u
 
 #define EXCMG_MAX_LEVELS 16
 #define EXCMG_MAX_HISTORY 256

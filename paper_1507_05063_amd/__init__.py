@@ -85,7 +85,7 @@ class Solver:
     def __init__(self, n: Sequence[int], box=(1.0, 1.0, 1.0), tol: float = 1e-10, n_coarse=(0, 0, 0),
                  precision: int = FP64, inner_tol: float = 0.0, max_iters: int = 0, history: bool = False,
                  timing: bool = False, graphs: bool = True, guess: str = "quartic", stop_norm: str = "b",
-                 tol_order: float = 0.0, tol_coarse: float = 0.0, stream=None):
+                 tol_order: float = 0.0, tol_coarse: float = 0.0, two_pass_cg: bool = False, stream=None):
         """guess: the initial guess of every grid from the third on: "quartic" (EXP_finite, the paper's method),
         "quadratic" (the same extrapolation, tri-quadratic interpolation) or "linear" (CMG: trilinear u_2h).
         stop_norm: the ||f_h|| of the stopping test: "b" (the eliminated right-hand side), "fg" (R f inside, g on
@@ -93,7 +93,9 @@ class Solver:
         tol_order: p >= 0; grid l of L relaxes to tol * 2^(p (L-1-l)) (at most max(tol, 1e-2)): tol on the finest grid,
         looser on the coarser ones (0: tol everywhere, Algorithm 1).
         tol_coarse: 0, or in (0, 1) with tol_order 0: every grid below the finest relaxes to tol_coarse, the finest
-        to tol."""
+        to tol.
+        two_pass_cg: run the two-pass CG as written on every grid (default: the single-reduction form on the
+        small grids below the finest, up to 2^18 unknowns, one launch per iteration)."""
         torch = _torch()
         self.n = tuple(int(v) for v in n)
         self.box = tuple(float(v) for v in box)
@@ -106,7 +108,7 @@ class Solver:
             raise ValueError(f"stop_norm must be one of {sorted(_lib.STOP_NORM_FLAGS)}, not {stop_norm!r}")
         self.stop_norm = stop_norm
         flags = (WANT_HISTORY if history else 0) | (WANT_TIMING if timing else 0) | (0 if graphs else NO_GRAPHS)
-        flags |= _lib.GUESS_FLAGS[guess] | _lib.STOP_NORM_FLAGS[stop_norm]
+        flags |= _lib.GUESS_FLAGS[guess] | _lib.STOP_NORM_FLAGS[stop_norm] | (_lib.TWO_PASS_CG if two_pass_cg else 0)
         self.tol_order = float(tol_order)
         self.tol_coarse = float(tol_coarse)
         self._p = _problem(self.n, self.box, tol, n_coarse, precision, inner_tol, max_iters, flags, tol_order,

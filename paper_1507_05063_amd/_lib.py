@@ -20,6 +20,7 @@ WANT_HISTORY, WANT_TIMING, NO_GRAPHS, GUESS_QUADRATIC, GUESS_LINEAR, STOP_F_G = 
 GUESS_KINDS = {"quartic": 0, "quadratic": 1, "linear": 2}
 GUESS_FLAGS = {"quartic": 0, "quadratic": GUESS_QUADRATIC, "linear": GUESS_LINEAR}
 STOP_F_G_BELOW_FINEST = 64
+TWO_PASS_CG = 256
 STOP_NORM_FLAGS = {"b": 0, "fg": STOP_F_G, "fg_coarse": STOP_F_G_BELOW_FINEST}
 MAX_LEVELS, MAX_HISTORY = 16, 256
 

@@ -97,7 +97,7 @@ int validate(const excmg_problem *p) {
   if (p->inner_tol < 0.0 || !isfinite(p->inner_tol) || p->inner_tol >= 1.0) return EXCMG_ERR_ARG;
   if (p->max_iters < 0) return EXCMG_ERR_ARG;
   if (p->flags & ~(EXCMG_WANT_HISTORY | EXCMG_WANT_TIMING | EXCMG_NO_GRAPHS | EXCMG_GUESS_QUADRATIC |
-                   EXCMG_GUESS_LINEAR | EXCMG_STOP_F_G | EXCMG_STOP_F_G_BELOW_FINEST))
+                   EXCMG_GUESS_LINEAR | EXCMG_STOP_F_G | EXCMG_STOP_F_G_BELOW_FINEST | EXCMG_TWO_PASS_CG))
     return EXCMG_ERR_ARG;
   if ((p->flags & EXCMG_GUESS_QUADRATIC) && (p->flags & EXCMG_GUESS_LINEAR)) return EXCMG_ERR_ARG;
   if ((p->flags & EXCMG_STOP_F_G) && (p->flags & EXCMG_STOP_F_G_BELOW_FINEST)) return EXCMG_ERR_ARG;
@@ -402,6 +402,42 @@ bool self_finalizing(const Level &lv, bool fp32) {
   return sweep_blocks(a) <= m && sweep_blocks(b) <= m && sweep_blocks(lv.sw) <= m;
 }
 
+// The single-reduction CG (launch_cg1_*) on grid l: FP64 self-finalizing grids of at most kCg1MaxUnknowns from the
+// third to the one below the finest (the direct solves keep the two-pass form), unless EXCMG_TWO_PASS_CG.  Its vectors: u; p in p1's buffer;
+// two sets of (r, w, s), one after the other in r's buffer (set 0, where the residual sweep leaves r) and in p0's
+// (set 1), which the iterations read and write alternately (each buffer holds the finest grid, three times a grid
+// below it).  Its partial sums: the iterations' alternately in the two halves of the partials buffer, the residual
+// sweep's in the second quarter, the init sweep's in the second half.
+constexpr long long kCg1Align = 32;  // doubles (256 bytes)
+// Grids up to this many unknowns, where an iteration's two launches cost more than their bytes: 512^3 step, grids
+// 32^3 / 64^3 / 128^3 / 256^3 0.476 / 0.585 / 1.06 / 1.72 ms in the two-pass form, 0.374 / 0.540 / 1.115 / 2.91 ms in
+// this one (which moves 80 bytes per unknown and iteration against 64, plus the sweep w = M r at the start)
+constexpr long long kCg1MaxUnknowns = 1LL << 18;
+long long cg1_stride(const Level &lv) { return (lv.g.elems + kCg1Align - 1) / kCg1Align * kCg1Align; }
+Sweep cg1_sweep(const Level &lv) { return lv.swB; }
+bool use_cg1(const excmg_handle *h, int l) {
+  const Layout &lo = h->lo;
+  const Level &lv = lo.lev[l];
+  if ((h->p.flags & EXCMG_TWO_PASS_CG) || l < 2 || l >= lo.L - 1 || lv.g.interior() > kCg1MaxUnknowns ||
+      !self_finalizing(lv, false))
+    return false;
+  const long long nb = sweep_blocks(cg1_sweep(lv)), nbR = sweep_blocks(lv.sw);
+  return 4 * nb <= lo.npart && 4 * nbR <= lo.npart && 2 * cg1_stride(lv) + lv.g.elems <= lo.gfin.elems;
+}
+double *cg1_resid_parts(const excmg_handle *h) { return h->partials + h->lo.npart / 2; }
+// vector j (0 r, 1 w, 2 s) of set q
+double *cg1_vec(excmg_handle *h, const Level &lv, int q, int j) { return (q ? h->p0 : h->r) + j * cg1_stride(lv); }
+
+// Iteration `launched` of the single-reduction CG on grid l (par: its parity): reads set par, writes set 1 - par
+void launch_cg1_step(excmg_handle *h, int l, hipStream_t s, int par) {
+  Level &lv = h->lo.lev[l];
+  double *pa = h->partials, *pb = h->partials + h->lo.npart;
+  launch_cg1_iteration(cg1_sweep(lv), lv.u, h->p1, cg1_vec(h, lv, par, 0), cg1_vec(h, lv, par, 1),
+                       cg1_vec(h, lv, par, 2), cg1_vec(h, lv, 1 - par, 0), cg1_vec(h, lv, 1 - par, 1),
+                       cg1_vec(h, lv, 1 - par, 2), h->cs, par, par ? pa : pb, cg1_resid_parts(h),
+                       sweep_blocks(lv.sw), grid_tol(h->p, l, h->lo.L), par ? pb : pa, s);
+}
+
 // One CG iteration of grid l on stream s: FP64 (fp32 = 0) on u, r, p, or the FP32 inner solve (fp32 = 1) on d32, r32,
 // p32.  first: the first FP64 iteration of a self-finalizing grid, whose pass A sums the residual sweep's partials.
 // launched: iteration index for the kernel timing.
@@ -426,6 +462,10 @@ void launch_iteration(excmg_handle *h, int l, int fp32, bool first, hipStream_t 
       Tick t(h, EXCMG_K_CG_B32, l, launched, outer);
       launch_cg_pass_b<float>(lv.swB32, h->d32, h->r32, h->p32a, h->p32b, h->cs2, h->partials, s);
     }
+    return;
+  }
+  if (use_cg1(h, l)) {  // (never the finest grid: no kernel timing)
+    launch_cg1_step(h, l, s, launched & 1);
     return;
   }
   if (self_finalizing(lv, false)) {
@@ -462,7 +502,12 @@ int launch_iteration_graph(excmg_handle *h, int l, int fp32, int si) {
   if (!ex) {
     hipGraph_t g = nullptr;
     HIPCHECK(hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal));
-    for (int q = 0; q < kGraphSizes[si]; ++q) launch_iteration(h, l, fp32, false, h->cap, -1, -1);
+    // (the single-reduction CG: graphs start at odd iterations, after the first one's direct launch)
+    const bool cg1 = !fp32 && use_cg1(h, l);
+    for (int q = 0; q < kGraphSizes[si]; ++q) {
+      if (cg1) launch_cg1_step(h, l, h->cap, (1 + q) & 1);
+      else launch_iteration(h, l, fp32, false, h->cap, -1, -1);
+    }
     const hipError_t ec = hipStreamEndCapture(h->cap, &g);
     if (ec != hipSuccess) return EXCMG_ERR_HIP;
     const hipError_t ei = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
@@ -523,7 +568,11 @@ int cg64(excmg_handle *h, int l, const RhsSrc &rs, bool finest, int *iters, doub
   double *partsB = h->partials + h->lo.npart;
   {
     Tick t(h, EXCMG_K_RESID, l);
-    if (selfred) {
+    if (use_cg1(h, l)) {  // r, then w = M r with the partials of the first iteration's two inner products
+      launch_residual_partials(lv.sw, lv.u, rs, h->r, cg1_resid_parts(h), s);
+      launch_selfred_init(h->cs, maxit, hist_on, 0, s);
+      launch_cg1_init(cg1_sweep(lv), cg1_vec(h, lv, 0, 0), cg1_vec(h, lv, 0, 1), partsB, s);
+    } else if (selfred) {
       launch_residual_partials(lv.sw, lv.u, rs, h->r, partsB, s);
       launch_selfred_init(h->cs, maxit, hist_on, 0, s);
     } else {

@@ -185,6 +185,7 @@ struct CgState {
   double gbnd2;    // added to the squared norm of the stopping test: the sum of g^2 over the grid's boundary nodes
                    // under EXCMG_STOP_F_G, else 0 (set at setup and by boundary_g2_kernel)
   double rhoA[2];
+  double alphaA[2];  // the single-reduction CG: alpha of iteration k in slot k mod 2
   double hist[EXCMG_MAX_HISTORY];
 };
 
@@ -251,6 +252,14 @@ void launch_boundary_g2(const RhsSrc &rs, const Grid &g, CgState *cs, hipStream_
 // cs->gbnd2 = 0 for each state (at setup)
 void launch_clear_gbnd2(CgState *a, CgState *b, hipStream_t st);
 // residual sweep writing [r.r | b.b] partials without a finalize (for the self-finalizing iterations)
+// The single-reduction CG of self-finalizing grids (kernels_cg.hip): the init sweep w = M r with the partial sums
+// of r.r and w.r into parts, and iteration k (launch parity par) from r, w, s into ro, wo, so (u, p in place), from
+// the partials of the previous launch (or the init's) and, at k = 0, the residual sweep's partsR (nbR workgroups);
+// both use sweep sw (depth 2 or 3).
+void launch_cg1_init(const Sweep &sw, const double *r, double *w, double *parts, hipStream_t st);
+void launch_cg1_iteration(const Sweep &sw, double *u, double *p, const double *r, const double *w, const double *s,
+                          double *ro, double *wo, double *so, CgState *cs, int par, const double *partsIn,
+                          const double *partsR, int nbR, double tol, double *partsOut, hipStream_t st);
 void launch_residual_partials(const Sweep &sw, const double *u, const RhsSrc &rs, double *r, double *parts,
                               hipStream_t st);
 

@@ -705,6 +705,163 @@ __global__ __launch_bounds__(Tile<TY>::NT) void cg_selfred_b_kernel(Sweep sw, T 
   write_partials<1, NTB>(v, partsB, sh, blockIdx.x, gridDim.x);
 }
 
+// ---------------------------------------------------------------- single-reduction CG on self-finalizing grids
+//
+// The Krylov iterates of Algorithm 1's CG (equal in exact arithmetic; the rounding differs), with both inner products
+// of an iteration taken in one reduction (Chronopoulos and Gear's form): with s = M p and w = M r kept as vectors,
+//   p = r + beta p,  s = w + beta s,  u += alpha p,  r -= alpha s,  w = M r,  gamma = r.r,  delta = w.r,
+//   beta = gamma / gamma_old,  alpha = gamma / (delta - beta gamma / alpha_old)   (p = r, s = w, alpha = gamma / delta
+// at k = 0).  An iteration is one launch: the new r is formed at staging on the tile and its halo (r - alpha (w +
+// beta s) from the three old vectors, the same bits in every workgroup that stages a node), so w = M r needs no
+// other pass, and each launch sums the previous launch's partials itself.
+
+// w = M r and the partial sums of r.r and w.r: the start of the single-reduction CG
+struct PolCg1Init {
+  static constexpr bool kRhs = false;
+  const double *r;
+  double *w;
+  using Raw = double;
+  __device__ __forceinline__ double operand(long long idx) const { return r[idx]; }
+  __device__ __forceinline__ double value(double v) const { return v; }
+  __device__ __forceinline__ long long fcol(int, int) const { return -1; }
+  __device__ __forceinline__ long long fplane() const { return 0; }
+  __device__ __forceinline__ double fval(long long) const { return 0.0; }
+  template <int S>
+  __device__ __forceinline__ void center(int, int, int, long long) {}
+  template <int S>
+  __device__ __forceinline__ void consume(int, int, int, long long idx, double rc, double out, double, double,
+                                          double &acc0, double &acc1) {
+    w[idx] = out;
+    acc0 += rc * rc;
+    acc1 += out * rc;
+  }
+};
+
+struct Cg1Raw {
+  double r, w, s;
+};
+
+// one iteration of the single-reduction CG (first: k = 0, where p and s start as r and w).  r, w and s are read
+// with halos, so the new ones go to another set of arrays (ro, wo, so); u and p are read and written at the node only.
+template <int D>
+struct PolCg1 {
+  static constexpr bool kRhs = false;
+  double *u, *p;
+  const double *r, *w, *s;
+  double *ro, *wo, *so;
+  double alpha, beta;
+  bool first;
+  double cu[D], cp[D], cr[D], cw[D], cs[D];  // centre data of the output planes in flight
+  using Raw = Cg1Raw;
+  __device__ __forceinline__ Cg1Raw operand(long long idx) const { return Cg1Raw{r[idx], w[idx], s[idx]}; }
+  __device__ __forceinline__ double dir(double a, double b) const { return first ? a : a + beta * b; }
+  // the new r at a staged node: r - alpha (w + beta s)
+  __device__ __forceinline__ double value(const Cg1Raw &v) const { return v.r - alpha * dir(v.w, v.s); }
+  __device__ __forceinline__ long long fcol(int, int) const { return -1; }
+  __device__ __forceinline__ long long fplane() const { return 0; }
+  __device__ __forceinline__ double fval(long long) const { return 0.0; }
+  template <int S>
+  __device__ __forceinline__ void center(int, int, int, long long idx) {
+    cu[S] = u[idx];
+    cp[S] = p[idx];
+    cr[S] = r[idx];
+    cw[S] = w[idx];
+    cs[S] = s[idx];
+  }
+  template <int S>
+  __device__ __forceinline__ void consume(int, int, int, long long idx, double rn, double out, double, double,
+                                          double &acc0, double &acc1) {
+    const double pn = dir(cr[S], cp[S]);
+    u[idx] = cu[S] + alpha * pn;
+    p[idx] = pn;
+    so[idx] = dir(cw[S], cs[S]);
+    ro[idx] = rn;
+    wo[idx] = out;
+    acc0 += rn * rn;
+    acc1 += out * rn;
+  }
+};
+
+template <int D, int TY>
+__global__ __launch_bounds__(Tile<TY>::NT) void cg1_init_kernel(Sweep sw, const double *r, double *w, double *parts) {
+  __shared__ double tile[2][Tile<TY>::Rows][TX + 2];
+  __shared__ double sh[Tile<TY>::NT / 64];
+  PolCg1Init pol{r, w};
+  double a0 = 0.0, a1 = 0.0;
+  zmarch<double, D, TY>(sw, pol, a0, a1, tile, nullptr, blockIdx.x, gridDim.x, true);
+  const double v[2] = {a0, a1};
+  write_partials<2, Tile<TY>::NT>(v, parts, sh, blockIdx.x, gridDim.x);
+}
+
+// Iteration k of the single-reduction CG: from r, w, s (read with halos) into ro, wo, so; u and p in place.  par (the
+// launch's parity, 0 for k = 0) picks the state's iteration counter to read (iterA, or iterB) and the one to write,
+// so that no launch writes what its own workgroups read (the host alternates the vector sets the same way); partsIn: the
+// previous launch's partial sums of gamma and delta (the init sweep's at k = 0), gridDim.x each; partsR: the residual
+// sweep's (r.r, b.b), nbR each, whose b.b is used at k = 0.  The stopping test on gamma = r_k.r_k comes first
+// (Algorithm 1), as in the two-pass CG.
+template <int D, int TY>
+__global__ __launch_bounds__(Tile<TY>::NT) void cg1_iter_kernel(Sweep sw, double *u, double *p, const double *r,
+                                                                const double *w, const double *s, double *ro,
+                                                                double *wo, double *so, CgState *cs, int par,
+                                                                const double *partsIn, const double *partsR, int nbR,
+                                                                double tol, double *partsOut) {
+  constexpr int NTB = Tile<TY>::NT;
+  __shared__ double tile[2][Tile<TY>::Rows][TX + 2];
+  __shared__ double sh[NTB / 64];
+  __shared__ double shf[NTB];
+  const int nb = gridDim.x;
+  const int done = cs->done;
+  const int k = par ? cs->iterB : cs->iterA;
+  const double g1 = strided_sum<NTB>(partsIn, nb), d1 = strided_sum<NTB>(partsIn + nb, nb);
+  const double b1 = strided_sum<NTB>(partsR + nbR, nbR);
+  keep(g1);
+  keep(d1);
+  keep(b1);
+  if (done) return;
+  const double gamma = block_fixed_finish<NTB>(g1, shf);
+  const double delta = block_fixed_finish<NTB>(d1, shf);
+  double bb, stop2, alpha, beta;
+  if (k == 0) {
+    bb = block_fixed_finish<NTB>(b1, shf) + cs->gbnd2;
+    stop2 = tol * tol * bb;
+    beta = 0.0;
+    alpha = gamma / delta;
+  } else {
+    bb = cs->bnorm2;
+    stop2 = cs->stop2;
+    beta = gamma / cs->rhoA[(k - 1) & 1];
+    alpha = gamma / (delta - beta * gamma / cs->alphaA[(k - 1) & 1]);
+  }
+  const bool finite = isfinite(gamma) && isfinite(bb);
+  const bool conv = finite && gamma <= stop2;
+  const bool cap = finite && !conv && k >= cs->max_iters;
+  const bool bad = finite && !conv && !cap && !(alpha > 0.0 && isfinite(alpha));
+  const bool stop = !finite || conv || cap || bad;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (k == 0) {
+      cs->bnorm2 = bb;
+      cs->stop2 = stop2;
+      cs->rho0 = gamma;
+    }
+    if (cs->hist_on && k < EXCMG_MAX_HISTORY) cs->hist[k] = bb > 0.0 ? sqrt(gamma / bb) : 0.0;
+    cs->rhoA[k & 1] = gamma;
+    cs->alphaA[k & 1] = alpha;
+    cs->rho = gamma;
+    cs->iter = k;
+    if (par) cs->iterA = k + 1;
+    else cs->iterB = k + 1;
+    if (!finite || bad) cs->status = EXCMG_ERR_BREAKDOWN;
+    if (cap) cs->status = EXCMG_ERR_NOCONV;
+    if (stop) cs->done = 1;
+  }
+  if (stop) return;
+  PolCg1<D> pol{u, p, r, w, s, ro, wo, so, alpha, beta, k == 0, {}, {}, {}, {}, {}};
+  double a0 = 0.0, a1 = 0.0;
+  zmarch<double, D, TY>(sw, pol, a0, a1, tile, nullptr, blockIdx.x, gridDim.x, true);
+  const double v[2] = {a0, a1};
+  write_partials<2, NTB>(v, partsOut, sh, blockIdx.x, gridDim.x);
+}
+
 __global__ void selfred_init_kernel(CgState *cs, int max_iters, int hist_on, int preset) {
   cs->iterA = 0;
   cs->iterB = 0;
@@ -1712,6 +1869,37 @@ template void launch_selfred_b<float>(const Sweep &, float *, float *, float *, 
                                       const double *, int, double *, hipStream_t);
 
 int selfred_max_blocks() { return kSelfRedMaxBlocks; }
+
+// f(depth, height) for the single-reduction CG sweeps, which prefetch 2 or 3 planes (a deeper depth runs as 3)
+template <typename F>
+static void with_cg1_shape(const Sweep &sw, F &&f) {
+  auto height = [&](auto d) {
+    switch (sw.ty) {
+      case 8: f(d, std::integral_constant<int, 8>{}); break;
+      case 16: f(d, std::integral_constant<int, 16>{}); break;
+      default: f(d, std::integral_constant<int, kTy>{}); break;
+    }
+  };
+  if (sw.depth >= 3) height(std::integral_constant<int, 3>{});
+  else height(std::integral_constant<int, 2>{});
+}
+
+void launch_cg1_init(const Sweep &sw, const double *r, double *w, double *parts, hipStream_t st) {
+  with_cg1_shape(sw, [&](auto d, auto ty) {
+    constexpr int TY = decltype(ty)::value;
+    cg1_init_kernel<decltype(d)::value, TY><<<sweep_blocks(sw), Tile<TY>::NT, 0, st>>>(sw, r, w, parts);
+  });
+}
+
+void launch_cg1_iteration(const Sweep &sw, double *u, double *p, const double *r, const double *w, const double *s,
+                          double *ro, double *wo, double *so, CgState *cs, int par, const double *partsIn,
+                          const double *partsR, int nbR, double tol, double *partsOut, hipStream_t st) {
+  with_cg1_shape(sw, [&](auto d, auto ty) {
+    constexpr int TY = decltype(ty)::value;
+    cg1_iter_kernel<decltype(d)::value, TY><<<sweep_blocks(sw), Tile<TY>::NT, 0, st>>>(
+        sw, u, p, r, w, s, ro, wo, so, cs, par, partsIn, partsR, nbR, tol, partsOut);
+  });
+}
 
 void launch_residual(const Sweep &sw_in, const double *u, const RhsSrc &rs, double *r, CgState *cs, double *partials,
                      double tol, int max_iters, int hist_on, hipStream_t st) {

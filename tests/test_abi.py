@@ -99,7 +99,7 @@ def test_bad_arguments(abi):
 
 @pytest.mark.parametrize("flags,tol_order,ok", [(0, 0.0, True), (0, 6.0, True), (0, 16.0, True), (0, -1.0, False),
                                                 (0, 16.5, False), (0, float("nan"), False), (32, 6.0, True),
-                                                (64, 0.0, True), (32 | 64, 0.0, False), (128, 0.0, False),
+                                                (64, 0.0, True), (32 | 64, 0.0, False), (128, 0.0, False), (256, 0.0, True),
                                                 (8 | 16, 0.0, False)])
 def test_problem_validation(abi, flags, tol_order, ok):
     """Flags (EXCMG_STOP_F_G = 32 accepted, unknown bits and both compared guesses rejected) and the level-dependent

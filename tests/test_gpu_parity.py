@@ -453,3 +453,29 @@ def test_forced_fp32_sweep_shapes(ex, orc, ty):
     ref = orc.excmg(f, g, p.box, s.n_coarse, tol)
     rms = lambda a: float(np.sqrt(np.mean(np.square(a))))
     assert rms(host(ug) - ref["u"]) <= 0.01 * rms(ref["u"] - u)
+
+
+@pytest.mark.parametrize("case", ["cube", "aniso-ragged"])
+def test_single_reduction_cg_matches_oracle(ex, orc, case):
+    """The single-reduction CG (the default on the small grids below the finest: here 32^3-size and 64^3-size ones)
+    and the two-pass CG (EXCMG_TWO_PASS_CG) both give the oracle's solution at its counts (1e-12), with free-running
+    counts within one of the oracle's; they differ in rounding only (so the forms really differ), and the
+    single-reduction CG in graphs and in direct launches gives the same bits."""
+    n, nc, box = {"cube": ((128, 128, 128), (4, 4, 4), (1.0, 1.0, 1.0)),
+                  "aniso-ragged": ((160, 96, 64), (10, 6, 4), (1.0, 0.6, 0.4))}[case]
+    p = synth.smooth(3, box)
+    f, g, _ = synth.sample(p, n)
+    tol = 1e-10
+    sols = {}
+    for name, kw in (("cg1", {}), ("two_pass", {"two_pass_cg": True}), ("cg1_direct", {"graphs": False})):
+        s = ex.Solver(n, p.box, tol, n_coarse=nc, **kw)
+        ug, _, st = s.solve(dev(f), dev(g))
+        sols[name] = (host(ug), np.array(st["iters"], dtype=np.int32))
+    free = orc.excmg(f, g, p.box, nc, tol)
+    for name in ("cg1", "two_pass"):
+        ug, gi = sols[name]
+        assert np.all(np.abs(gi - free["iters"]) <= 1), (name, gi, free["iters"])
+        ref = orc.excmg(f, g, p.box, nc, tol, fixed_iters=gi)
+        assert rel2(ug, ref["u"]) <= 1e-12, name
+    assert np.array_equal(sols["cg1"][0], sols["cg1_direct"][0])
+    assert not np.array_equal(sols["cg1"][0], sols["two_pass"][0])
