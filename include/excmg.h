@@ -251,7 +251,8 @@ int excmg_autotune_batched(excmg_handle *const *hs, int32_t count, void *batch_w
  * of self-finalizing passes, are timed on those kernels, with the shapes that keep them self-finalizing.
  * zc_out, depth_out (host, nullable, 4 * levels entries each): per grid, pass A and pass B in FP64, then in FP32 (0
  * where the grid is not relaxed that way): the chunk, and depth + 10 (if the non-temporal policy won) + 100 * tile
- * height.  Batched solves (excmg_solve_batched) keep the chunk and use 4-row tiles.
+ * height.  Batched solves (excmg_solve_batched) keep the chunk and use the handle's batch shape
+ * (excmg_get_batch_shape; excmg_autotune_batched chooses it).
  * Optional: without it the handle uses a fixed default (16 planes, fewer on small grids; 4 rows; depth 2;
  * ordinary). */
 int excmg_autotune(excmg_handle *h, int32_t *zc_out, int32_t *depth_out);
