@@ -248,7 +248,9 @@ int excmg_autotune_batched(excmg_handle *const *hs, int32_t count, void *batch_w
  * of loads in flight per thread) and each cache policy (ordinary or non-temporal loads and stores of the data a
  * sweep touches once), on the handle's own work buffers (no caller array is read or written), and keeps the fastest
  * per grid and kernel for every later call on this handle.  Grids below the finest, whose iterations run as graphs
- * of self-finalizing passes, are timed on those kernels, with the shapes that keep them self-finalizing.
+ * of self-finalizing passes, are timed on those kernels, with the shapes that keep them self-finalizing; on those
+ * that run the single-reduction CG (see EXCMG_TWO_PASS_CG) the pass-B shape, which that CG uses, is timed on its
+ * iterations.
  * zc_out, depth_out (host, nullable, 4 * levels entries each): per grid, pass A and pass B in FP64, then in FP32 (0
  * where the grid is not relaxed that way): the chunk, and depth + 10 (if the non-temporal policy won) + 100 * tile
  * height.  Batched solves (excmg_solve_batched) keep the chunk and use the handle's batch shape

@@ -415,14 +415,17 @@ constexpr long long kCg1Align = 32;  // doubles (256 bytes)
 constexpr long long kCg1MaxUnknowns = 1LL << 18;
 long long cg1_stride(const Level &lv) { return (lv.g.elems + kCg1Align - 1) / kCg1Align * kCg1Align; }
 Sweep cg1_sweep(const Level &lv) { return lv.swB; }
-bool use_cg1(const excmg_handle *h, int l) {
+// everything use_cg1 asks of grid l but that its passes finalize themselves with the sweep of at most 1/4 of the
+// partials buffer's half
+bool cg1_eligible(const excmg_handle *h, int l) {
   const Layout &lo = h->lo;
   const Level &lv = lo.lev[l];
-  if ((h->p.flags & EXCMG_TWO_PASS_CG) || l < 2 || l >= lo.L - 1 || lv.g.interior() > kCg1MaxUnknowns ||
-      !self_finalizing(lv, false))
-    return false;
-  const long long nb = sweep_blocks(cg1_sweep(lv)), nbR = sweep_blocks(lv.sw);
-  return 4 * nb <= lo.npart && 4 * nbR <= lo.npart && 2 * cg1_stride(lv) + lv.g.elems <= lo.gfin.elems;
+  if ((h->p.flags & EXCMG_TWO_PASS_CG) || l < 2 || l >= lo.L - 1 || lv.g.interior() > kCg1MaxUnknowns) return false;
+  return 4LL * sweep_blocks(lv.sw) <= lo.npart && 2 * cg1_stride(lv) + lv.g.elems <= lo.gfin.elems;
+}
+bool use_cg1(const excmg_handle *h, int l) {
+  const Level &lv = h->lo.lev[l];
+  return cg1_eligible(h, l) && self_finalizing(lv, false) && 4LL * sweep_blocks(cg1_sweep(lv)) <= h->lo.npart;
 }
 double *cg1_resid_parts(const excmg_handle *h) { return h->partials + h->lo.npart / 2; }
 // vector j (0 r, 1 w, 2 s) of set q
@@ -1642,6 +1645,9 @@ int excmg_autotune(excmg_handle *h, int32_t *zc_out, int32_t *depth_out) {
     // keep it self-finalizing; their launches are short, so each trial times a burst of them queued behind a delay
     // (back to back, as in a graph) instead of one launch between two events, whose own cost would hide the kernel.
     const bool burst = use_graphs(h, l) && sweep_blocks(lv.sw) <= selfred_max_blocks();
+    // a grid that will run the single-reduction CG has its pass-B shape (which that CG uses) timed on that CG's
+    // iterations (the trial state makes every launch of parity 1 run iteration 1 in full)
+    const bool cg1 = burst && cg1_eligible(h, l);
     // kinds: FP64 passes, FP32 passes (refinement grids), and the FP64 passes of the first iteration (p = r: pass A
     // reads r alone, pass B takes p from r's buffer) on grids whose passes finalize apart
     for (int kind = 0; kind < 3 && rc == EXCMG_OK; ++kind) {
@@ -1663,15 +1669,21 @@ int excmg_autotune(excmg_handle *h, int32_t *zc_out, int32_t *depth_out) {
         auto trial = [&](const Sweep &sw, int reps) -> float {
           float tmin = 1e30f;
           for (int rep = 0; rep < reps && rc == EXCMG_OK; ++rep) {
+            const bool cg1_trial = cg1 && prec == 0 && pass == 1;
             if (burst) {
-              launch_tune_selfred(h->cs2, pass ? pa : pb, nb_other, s);
+              launch_tune_selfred(h->cs2, pass ? pa : pb, cg1_trial ? 2 * sweep_blocks(sw) : nb_other, s);
               launch_delay(kTuneDelayUs, s);
             } else {
               launch_tune_state(h->cs2, first ? 0 : 1, s);
             }
             if (hipEventRecord(ea, s) != hipSuccess) rc = EXCMG_ERR_HIP;
             for (int q = 0; q < (burst ? kTuneBurst : 1); ++q) {
-              if (burst && prec == 0) {
+              if (cg1_trial) {  // u and p: the first two slots of p1's buffer (the grid's u may not be bound yet)
+                launch_cg1_iteration(sw, h->p1 + cg1_stride(lv), h->p1, cg1_vec(h, lv, 1, 0), cg1_vec(h, lv, 1, 1),
+                                     cg1_vec(h, lv, 1, 2), cg1_vec(h, lv, 0, 0), cg1_vec(h, lv, 0, 1),
+                                     cg1_vec(h, lv, 0, 2), h->cs2, 1, pa, cg1_resid_parts(h), sweep_blocks(lv.sw),
+                                     1.0, pb, s);
+              } else if (burst && prec == 0) {
                 if (pass == 0) launch_selfred_a<double>(sw, h->r, h->p0, h->p1, h->cs2, pb, nb_other, 1.0, pa, s);
                 else launch_selfred_b<double>(sw, h->r, h->r, h->p0, h->p1, h->cs2, pa, nb_other, pb, s);
               } else if (burst) {
@@ -1709,6 +1721,7 @@ int excmg_autotune(excmg_handle *h, int32_t *zc_out, int32_t *depth_out) {
           const Sweep sw = make_sweep(g, lv.st, zc, depth, nt, ty);
           if (3LL * sweep_blocks(sw) > lo.npart) continue;
           if (burst && sweep_blocks(sw) > selfred_max_blocks()) continue;
+          if (cg1 && prec == 0 && pass == 1 && 4LL * sweep_blocks(sw) > lo.npart) continue;
           timed.push_back({trial(sw, 3), sw});
         }
         if (rc) break;

@@ -1118,14 +1118,18 @@ __global__ void tune_state_kernel(CgState *cs, int iter) {
 
 // the trial state of a self-finalizing pass (iteration 1 of both passes, never converged) and n partial sums of 1 for
 // it to read, so that neither pass stops at its reduction
+// (also the trial state of the single-reduction CG, whose launches of parity 1 then all run iteration 1 with
+// beta ~ 1e-200 n and alpha = 1; the two-pass passes take beta from rhoA[0] and alpha from rhoA[1])
 __global__ void tune_selfred_kernel(CgState *cs, double *parts, int n) {
   if (threadIdx.x == 0) {
     tune_state(cs);
     cs->iterA = 1;
     cs->iterB = 1;
     cs->preset = 0;
-    cs->rhoA[0] = 1.0;
+    cs->rhoA[0] = 1e200;
     cs->rhoA[1] = 1.0;
+    cs->alphaA[0] = 1.0;
+    cs->alphaA[1] = 1.0;
   }
   for (int q = threadIdx.x; q < n; q += blockDim.x) parts[q] = 1.0;
 }
