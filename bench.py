@@ -97,6 +97,38 @@ def trace_summary(db, top=30):
             print(f"{nm:44s} {gx:9d} {cn:>12s} {len(vs):6d} {len(w):7d} {sum(w) / max(len(w), 1):14.1f}")
 
 
+def solve_trace_summary(db):
+    """The CG launches of the solves in a rocprofv3 kernel trace of the benchmark (the dispatches after the
+    autotuner's last trial), grouped by kernel and grid size (which tells the grids apart): calls, average duration
+    of the launches that did a sweep (at least half the group's longest: launches made after convergence return at
+    once), and the average idle time from the end of a launch to the start of the next dispatch."""
+    import re
+    import sqlite3
+
+    c = sqlite3.connect(db)
+
+    def clean(nm):
+        nm = nm.replace("excmg::(anonymous namespace)::", "").replace("void ", "")
+        return re.sub(r"\(.*", "", nm)[:44]
+
+    rows = c.execute("select name, grid_x, workgroup_x, start, end from kernels order by start").fetchall()
+    names = [clean(r[0]) for r in rows]
+    last = max((i for i, nm in enumerate(names) if nm.startswith(("tune_", "delay_"))), default=-1)
+    groups = {}
+    for i in range(last + 1, len(rows) - 1):
+        nm, (_, gx, wx, t0, t1) = names[i], rows[i]
+        if not nm.startswith(("cg1_", "cg_selfred_", "cg_pass_", "small_cg", "finalize_")):
+            continue
+        groups.setdefault((nm, gx, wx), []).append((t1 - t0, rows[i + 1][3] - t1))
+    print(f"solve launches after the autotuner: {len(rows) - last - 1} dispatches")
+    print(f"{'kernel':44s} {'grid':>9s} {'wg':>5s} {'calls':>6s} {'working':>7s} {'work_avg_us':>11s} {'gap_us':>7s}")
+    for (nm, gx, wx), v in sorted(groups.items(), key=lambda kv: kv[0][1]):
+        top = max(d for d, _ in v)
+        w = [d for d, _ in v if d >= 0.5 * top]
+        print(f"{nm:44s} {gx:9d} {wx:5d} {len(v):6d} {len(w):7d} {sum(w) / len(w) / 1e3:11.2f} "
+              f"{sum(g for _, g in v) / len(v) / 1e3:7.2f}")
+
+
 def _timed(torch, fn, reps):
     """Median wall time (ms) of reps calls of fn after one warm-up call."""
     fn()
@@ -505,6 +537,8 @@ def measured_traffic(kernel, grid):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--trace-summary", metavar="DB", help="print a summary of a rocprofv3 database and exit")
+    ap.add_argument("--solve-trace-summary", metavar="DB",
+                    help="print the solves' CG launches of a rocprofv3 kernel trace (durations, gaps) and exit")
     ap.add_argument("--counter-summary", nargs=2, metavar=("FETCH_DB", "WRITE_DB"),
                     help="print HBM bytes per dispatch from a FETCH_SIZE and a WRITE_SIZE rocprofv3 run and exit")
     ap.add_argument("--gpus", type=int, default=1)
@@ -528,6 +562,9 @@ def main():
     args = ap.parse_args()
     if args.trace_summary:
         trace_summary(args.trace_summary)
+        return
+    if args.solve_trace_summary:
+        solve_trace_summary(args.solve_trace_summary)
         return
     if args.counter_summary:
         counter_summary(*args.counter_summary)
