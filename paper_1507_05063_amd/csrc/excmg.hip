@@ -50,7 +50,7 @@ struct Layout {
   size_t off_u[EXCMG_MAX_LEVELS];
   size_t off_r, off_p0, off_p1;
   size_t off_r32, off_p32a, off_p32b, off_d32;
-  size_t off_part, off_cs, off_cs2, off_invm[3], off_flag;
+  size_t off_part, off_cs, off_cs2, off_defer, off_invm[3], off_flag;
   long long npart;
   size_t total;
 };
@@ -134,6 +134,9 @@ int guess_kind(uint32_t flags) {
 // costs would sit between the timed kernels).  Results are read on the host only after a stream synchronization.
 constexpr unsigned kTimingEvent = hipEventDisableSystemFence;
 
+// bytes of a CG state that the host reads after a solve (everything but the history)
+constexpr size_t kStateHead = offsetof(CgState, hist);
+
 int make_layout(const excmg_problem *p, Layout *Lo) {
   int e = validate(p);
   if (e) return e;
@@ -185,6 +188,7 @@ int make_layout(const excmg_problem *p, Layout *Lo) {
   Lo->off_part = off; off = align256(off + 2 * (size_t)Lo->npart * sizeof(double));  // two halves: A and B
   Lo->off_cs = off; off = align256(off + sizeof(CgState));
   Lo->off_cs2 = off; off = align256(off + sizeof(CgState));
+  Lo->off_defer = off; off = align256(off + EXCMG_MAX_LEVELS * kStateHead);
   for (int d = 0; d < 3; ++d) {
     Lo->off_invm[d] = off;
     off = align256(off + (size_t)(fin.n[d] + 1) * sizeof(double));
@@ -218,6 +222,7 @@ struct excmg_handle {
   float *r32, *p32a, *p32b, *d32;
   double *partials;
   CgState *cs, *cs2;
+  char *defer_dev;  // per grid, the CG state (without its history) of a one-launch solve, read after the cascade
   double *inv_m[3];
   int *flag;
   std::vector<double> inv_m_host[3];
@@ -666,8 +671,21 @@ int cg_ir(excmg_handle *h, int l, const RhsSrc &rs, bool finest, int *iters, int
 
 // Single-workgroup CG on a small grid: exact = 1 is DSOLVE (grids 0 and 1), exact = 0 the relaxation of a grid with
 // at most kSmallCg unknowns.
+// The outcome of a one-launch solve of grid l from its CG state hs: iterations and relative residual into the stats,
+// and its status.
+int small_cg_outcome(const CgState &hs, int l, bool exact, int *iters, double *relres, excmg_stats *st) {
+  if (exact && st && l < 2) st->dsolve_iters[l] = hs.iter;
+  *iters = exact ? 0 : hs.iter;
+  *relres = hs.bnorm2 > 0.0 ? sqrt(hs.rho / hs.bnorm2) : 0.0;
+  if (!isfinite(hs.bnorm2)) return EXCMG_ERR_NONFINITE;
+  return hs.status;
+}
+
+// defer: nothing on the host waits for this grid's outcome (it is not the finest): its state is copied on the device
+// to the grid's slot of defer_dev, which the cascade reads once at its end, so the stream runs on to the next grid
+// without a round trip to the host.
 int small_cg(excmg_handle *h, int l, const RhsSrc &rs, bool exact, bool finest, int *iters, double *relres,
-             excmg_stats *st) {
+             excmg_stats *st, bool defer = false) {
   Level &lv = h->lo.lev[l];
   const int hist_on = (!exact && finest && st && (h->p.flags & EXCMG_WANT_HISTORY)) ? 1 : 0;
   const int maxit = grid_cap(h, l);
@@ -678,6 +696,12 @@ int small_cg(excmg_handle *h, int l, const RhsSrc &rs, bool exact, bool finest, 
   }
   int e = last_error();
   if (e) return e;
+  if (defer && !hist_on) {
+    launch_publish(h->cs, h->defer_dev + (size_t)l * kStateHead, kStateHead, h->stream);
+    *iters = 0;
+    *relres = 0.0;
+    return last_error();
+  }
   CgState hs;
   e = hist_on ? read_hist(h, &hs, h->cs) : read_state(h, &hs, h->cs);
   if (e) return e;
@@ -761,6 +785,7 @@ void bind_workspace(excmg_handle *h) {
   h->partials = (double *)(w + lo.off_part);
   h->cs = (CgState *)(w + lo.off_cs);
   h->cs2 = (CgState *)(w + lo.off_cs2);
+  h->defer_dev = w + lo.off_defer;
   for (int d = 0; d < 3; ++d) h->inv_m[d] = (double *)(w + lo.off_invm[d]);
   h->flag = (int *)(w + lo.off_flag);
 }
@@ -771,6 +796,36 @@ int cascade(excmg_handle *h, int mode, const double *f, const double *g, excmg_s
   const int L = lo.L;
   const hipStream_t s = h->stream;
   int final_status = EXCMG_OK;
+  bool deferred[EXCMG_MAX_LEVELS] = {};  // grids solved in one launch whose outcome is read after the loop
+  // The outcomes of the deferred solves of the grids below `upto`, in one read: their stats, NOCONV into
+  // final_status, and the first other error (as it would have ended the cascade at that grid).
+  auto resolve = [&](int upto) -> int {
+    int nd = 0;
+    for (int l = 0; l < upto; ++l) nd = deferred[l] ? l + 1 : nd;
+    if (nd == 0) return EXCMG_OK;
+    std::vector<char> buf((size_t)nd * kStateHead);
+    int e = read_record(h, buf.data(), h->defer_dev, buf.size());
+    if (e) return e;
+    for (int l = 0; l < nd; ++l) {
+      if (!deferred[l]) continue;
+      CgState hs;
+      memcpy(&hs, buf.data() + (size_t)l * kStateHead, kStateHead);
+      const bool exact = l <= 1;
+      int it = 0;
+      double rr = 0.0;
+      e = small_cg_outcome(hs, l, exact, &it, &rr, st);
+      if (e == EXCMG_ERR_NOCONV)
+        final_status = EXCMG_ERR_NOCONV;
+      else if (e)
+        return e;
+      if (li) li->iters[l] = exact ? 0 : it;
+      if (st) {
+        st->iters[l] = it;
+        st->relres[l] = rr;
+      }
+    }
+    return EXCMG_OK;
+  };
   for (int l = 0; l < L; ++l) {
     Level &lv = lo.lev[l];
     if (h->lev_ev[l]) HIPCHECK(hipEventRecord(h->lev_ev[l], s));
@@ -805,12 +860,15 @@ int cascade(excmg_handle *h, int mode, const double *f, const double *g, excmg_s
         e = cg64(h, l, rs, l == L - 1, &dit, &rr, st);
         if (st) st->dsolve_iters[l] = dit;
       } else {
-        e = small_cg(h, l, rs, true, l == L - 1, &it, &rr, st);
+        deferred[l] = l < L - 1;
+        e = small_cg(h, l, rs, true, l == L - 1, &it, &rr, st, deferred[l]);
       }
-      if (e == EXCMG_ERR_NOCONV)
+      if (e == EXCMG_ERR_NOCONV) {
         final_status = EXCMG_ERR_NOCONV;
-      else if (e)
-        return e;
+      } else if (e) {
+        const int d = resolve(l);  // an error of an earlier grid comes first
+        return d ? d : e;
+      }
     } else {
       {
         Tick t(h, EXCMG_K_EXP_FINITE, l);
@@ -819,16 +877,20 @@ int cascade(excmg_handle *h, int mode, const double *f, const double *g, excmg_s
       }
       e = last_error();
       if (e) return e;
-      if (!swept(lo, l))
-        e = small_cg(h, l, rs, false, l == L - 1, &it, &rr, st);
+      if (!swept(lo, l)) {
+        deferred[l] = l < L - 1;
+        e = small_cg(h, l, rs, false, l == L - 1, &it, &rr, st, deferred[l]);
+      }
       else if (h->p.precision == EXCMG_FP64 || lv.g.interior() < kIrMinUnknowns)
         e = cg64(h, l, rs, l == L - 1, &it, &rr, st);
       else
         e = cg_ir(h, l, rs, l == L - 1, &it, &outer, &rr, st, li ? &li->inner[l] : nullptr);
-      if (e == EXCMG_ERR_NOCONV)
+      if (e == EXCMG_ERR_NOCONV) {
         final_status = EXCMG_ERR_NOCONV;
-      else if (e)
-        return e;
+      } else if (e) {
+        const int d = resolve(l);  // an error of an earlier grid comes first
+        return d ? d : e;
+      }
     }
     if (li) li->iters[l] = l <= 1 ? dit : it;
     if (st) {
@@ -838,7 +900,8 @@ int cascade(excmg_handle *h, int mode, const double *f, const double *g, excmg_s
     }
   }
   if (h->lev_ev[L]) HIPCHECK(hipEventRecord(h->lev_ev[L], s));
-  return final_status;
+  const int e = resolve(L);
+  return e ? e : final_status;
 }
 
 void fill_level_stats(excmg_handle *h, excmg_stats *st) {
